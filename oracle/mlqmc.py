@@ -1,0 +1,95 @@
+"""Level differences and the MLQMC estimator (section 4; Algorithm 2).
+
+For a level (n_fine=1/h_l, s_fine=s_l, n_coarse=1/H_l, s_coarse=S_l,
+n_prev=1/h_{l-1}, s_prev=s_{l-1}) and a parameter value y:
+
+* two-grid levels (n_coarse > 0): one coarse pair (lambda_{H_l,S_l}, u_{H_l,S_l})
+  feeds both two-grid updates, lambda^l on (h_l, s_l) and lambda^{l-1} on
+  (h_{l-1}, s_{l-1}) for the same point (Algorithm 2 reuses the coarse pair
+  for level l-1);
+* direct levels (n_coarse = 0): lambda^l = lambda_{h_l,s_l} by a direct
+  eigensolve, and lambda^{l-1} = lambda_{h_{l-1},s_{l-1}} likewise (the basic
+  estimator eq. mlqmc0; on level 0 of the two-grid estimator
+  lambda^0 = lambda_{h_0,s_0});
+* n_prev = 0 means lambda^{l-1} = 0 (lambda_{-1} = 0).
+
+Estimator (eq. mlqmc_R / eq. tg-mlqmc with eq. ml-var):
+  Q_l^(r) = (1/N_l) sum_{k<N_l} (lambda^l - lambda^{l-1})(y_{l,r,k}),
+  Qhat_l = (1/R) sum_r Q_l^(r),  V_l = eq. sample_var,
+  Q^ML = sum_l Qhat_l,  V = sum_l V_l.
+The loop over k runs over k = 0 .. N_l - 1 (eq. rqmc), and the level-(l-1)
+term is evaluated at the same point t_{l,k}.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import qmc, twogrid
+
+
+@dataclass
+class LevelValue:
+    Y: float          # lambda^l - lambda^{l-1}
+    lam: float        # lambda^l
+    lam_prev: float   # lambda^{l-1}
+    lam_coarse: float # lambda_{H_l,S_l}, NaN for direct levels
+
+
+def level_value(lv, y, fam) -> LevelValue:
+    y = np.asarray(y, dtype=np.float64)
+    if lv.n_coarse == 0:
+        lam, _ = twogrid.direct(lv.n_fine, lv.s_fine, y, fam)
+        lam_prev = 0.0
+        if lv.n_prev:
+            lam_prev, _ = twogrid.direct(lv.n_prev, lv.s_prev, y, fam)
+        return LevelValue(lam - lam_prev, lam, lam_prev, float("nan"))
+    lam_H, u_H = twogrid.coarse_pair(lv.n_coarse, lv.s_coarse, y, fam)
+    lam, _ = twogrid.two_grid_update(lv.n_fine, lv.s_fine, y, fam, lam_H, u_H, lv.n_coarse)
+    lam_prev = 0.0
+    if lv.n_prev:
+        if lv.n_prev == lv.n_coarse and lv.s_prev == lv.s_coarse:
+            # (A - lambda_H M) is exactly singular here; its two-grid value is lambda_H
+            lam_prev = lam_H
+        else:
+            lam_prev, _ = twogrid.two_grid_update(lv.n_prev, lv.s_prev, y, fam, lam_H, u_H,
+                                                  lv.n_coarse)
+    return LevelValue(lam - lam_prev, lam, lam_prev, lam_H)
+
+
+def level_samples(lv, z, N: int, shift, fam, ks=None):
+    """LevelValue for the points y_k (default k = 0..N-1) of one shift."""
+    pts = qmc.lattice_points(z, N, shift, ks)
+    return [level_value(lv, y, fam) for y in pts]
+
+
+@dataclass
+class Estimate:
+    Q_lr: np.ndarray   # [L+1, R]
+    Qhat: np.ndarray   # [L+1]
+    V: np.ndarray      # [L+1]
+    Q_ml: float
+    V_ml: float
+
+
+def combine(Q_lr) -> Estimate:
+    """Shift averages, sample variances and the multilevel sums from Q_l^(r)."""
+    Q_lr = np.asarray(Q_lr, dtype=np.float64)
+    Qhat = np.array([qmc.shift_average(row) for row in Q_lr])
+    V = np.array([qmc.sample_variance(row) for row in Q_lr])
+    return Estimate(Q_lr, Qhat, V, math.fsum(Qhat), math.fsum(V))
+
+
+def estimate(levels, zs, Ns, shifts, fam) -> Estimate:
+    """Algorithm 2: levels[l], zs[l] (int[s_l]), Ns[l], shifts[l] (float[R, s_l])."""
+    L1 = len(levels)
+    R = np.asarray(shifts[0]).shape[0]
+    Q_lr = np.empty((L1, R))
+    for l in range(L1):
+        for r in range(R):
+            vals = level_samples(levels[l], zs[l], Ns[l], shifts[l][r], fam)
+            Q_lr[l, r] = qmc.qmc_mean(v.Y for v in vals)
+    return combine(Q_lr)

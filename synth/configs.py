@@ -1,0 +1,121 @@
+"""Workload descriptions and seeded random shifts.
+
+Each workload is a list of levels; a level fixes the fine mesh h = 1/n_fine
+and truncation s, the coarse mesh H = 1/n_coarse and truncation S of the
+two-grid-truncation method (Algorithm 1; n_coarse = 0 means a direct
+eigensolve on the fine mesh), the previous-level mesh and truncation used for
+the level difference (Algorithm 2; n_prev = 0 means no previous level), and
+the number of lattice points N.  All levels share R random shifts.
+
+Shifts are independent per level and per replicate, drawn uniformly on
+[0, 1)^s from ``numpy.random.default_rng([210303407, cfg, level, r])``.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .cbc import lattice_vector
+from .family import coeff_family
+
+SEED_ROOT = 210303407
+
+
+@dataclass(frozen=True)
+class LevelSpec:
+    n_fine: int
+    s_fine: int
+    n_coarse: int
+    s_coarse: int
+    n_prev: int
+    s_prev: int
+    N: int
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    cfg_id: int
+    precision: str            # "fp64" or "mixed"
+    decay: float
+    levels: tuple
+    R: int
+    description: str = ""
+    a0: float = 1.0
+
+    @property
+    def s_max(self) -> int:
+        return max(lv.s_fine for lv in self.levels)
+
+    def family(self):
+        return coeff_family(self.s_max, decay=self.decay, a0=self.a0)
+
+    def z(self, level: int) -> np.ndarray:
+        lv = self.levels[level]
+        return lattice_vector(lv.N, lv.s_fine)
+
+    def shifts(self, level: int) -> np.ndarray:
+        lv = self.levels[level]
+        return shifts_for(self.cfg_id, level, self.R, lv.s_fine)
+
+    def n_samples(self) -> int:
+        return self.R * sum(lv.N for lv in self.levels)
+
+
+def shifts_for(cfg_id: int, level: int, R: int, s: int) -> np.ndarray:
+    """R independent uniform shifts in [0, 1)^s, float64 [R, s]."""
+    out = np.empty((R, s), dtype=np.float64)
+    for r in range(R):
+        out[r] = np.random.default_rng([SEED_ROOT, cfg_id, level, r]).random(s)
+    return out
+
+
+def coarse_rule(n_fine: int) -> int:
+    """H = sqrt(h) rounded to a power of two, ties to the finer mesh:
+    h = 2^-k  ->  H = 2^-ceil(k/2)."""
+    k = int(round(math.log2(n_fine)))
+    return 1 << ((k + 1) // 2)
+
+
+def coarse_trunc(s_fine: int, s0: int) -> int:
+    """S_l = max(ceil(s_l^(1/2)), s_0) (two-grid level rule, section 4.3)."""
+    return max(int(math.ceil(math.sqrt(s_fine) - 1e-12)), s0)
+
+
+def _cfg4_levels():
+    ns = [16, 32, 64, 128, 256]
+    ss = [16, 32, 64, 128, 256]
+    Ns = [1 << 14, 1 << 13, 1 << 11, 1 << 10, 1 << 8]
+    out = []
+    for l, (n, s, N) in enumerate(zip(ns, ss, Ns)):
+        if l == 0:
+            out.append(LevelSpec(n, s, 0, 0, 0, 0, N))
+        else:
+            out.append(LevelSpec(n, s, coarse_rule(n), coarse_trunc(s, ss[0]),
+                                 ns[l - 1], ss[l - 1], N))
+    return tuple(out)
+
+
+CONFIGS = {
+    1: Workload("cfg1-direct-h32-s16", 1, "fp64", 2.5,
+                (LevelSpec(32, 16, 0, 0, 0, 0, 256),), 4,
+                "single-level QMC, direct eigensolve on h=1/32, s=16, N=256 x R=4"),
+    2: Workload("cfg2-twogrid-H32-h128-s64", 2, "fp64", 2.5,
+                (LevelSpec(128, 64, 32, 8, 0, 0, 1024),), 8,
+                "single-level two-grid, H=1/32 -> h=1/128, s=64, S=8, N=1024 x R=8"),
+    3: Workload("cfg3-direct-h32-s16-mixed", 3, "mixed", 2.5,
+                (LevelSpec(32, 16, 0, 0, 0, 0, 256),), 4,
+                "cfg1 in mixed precision"),
+    4: Workload("cfg4-mlqmc-5level", 4, "fp64", 2.5, _cfg4_levels(), 8,
+                "five-level two-grid MLQMC, h=1/16..1/256, s=16..256"),
+    5: Workload("cfg5-twogrid-H64-h1024-s512", 5, "mixed", 2.0,
+                (LevelSpec(1024, 512, 64, 23, 0, 0, 1024),), 8,
+                "large fine level, H=1/64 -> h=1/1024, s=512, S=23, decay j^-2"),
+}
+
+
+def workload(cfg_id: int) -> Workload:
+    return CONFIGS[cfg_id]
