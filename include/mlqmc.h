@@ -1,0 +1,195 @@
+/*
+ * mlqmc.h -- C ABI of the MI355X two-grid MLQMC eigen-sample library.
+ *
+ * Problem (introduction, eq. evp, with b = 0, c = 1, D = (0,1)^2): the smallest
+ * eigenvalue of  -div(a(x,y) grad u) = lambda u,  u = 0 on the boundary, for
+ *     a(x,y) = a0 + sum_j y_j c_j sin(pi k1_j x1) sin(pi k2_j x2)      (eq. coeff)
+ * truncated to s terms (eq. coeff_s), discretised by P1 finite elements on the
+ * uniform "/"-diagonal triangulation with h = 1/n (section 2.3), the stiffness
+ * coefficient taken at element centroids and the mass matrix exact.
+ *
+ * Interior nodes (i,j), 1 <= i,j <= n-1, are stored row-major with x fastest:
+ * index (j-1)*(n-1) + (i-1).  Elements of square (i,j) are numbered 2*(j*n+i)
+ * (lower, vertices (i,j),(i+1,j),(i+1,j+1)) and 2*(j*n+i)+1 (upper, vertices
+ * (i,j),(i+1,j+1),(i,j+1)).  Multi-sample arrays are sample-major.
+ *
+ * Conventions for every call:
+ *  - returns mlqmc_status; nothing throws or aborts across the ABI;
+ *  - the caller owns every buffer; inputs are only read during the call;
+ *  - io_on_device (in mlqmc_opts, or the argument of the component calls)
+ *    selects device pointers (1; work is enqueued on the context's stream and
+ *    the call returns after that stream has finished it) or host pointers (0);
+ *  - on MLQMC_EINVAL nothing is written and mlqmc_last_error() says why;
+ *  - a context is bound to one device and one stream and is not reentrant:
+ *    use one context per host thread.
+ */
+#ifndef MLQMC_H
+#define MLQMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MLQMC_OK = 0,
+  MLQMC_EINVAL = -1,   /* invalid argument; nothing written */
+  MLQMC_ENOMEM = -2,   /* device allocation failed or exceeds opts.device_mem_cap */
+  MLQMC_EDEVICE = -3,  /* HIP runtime error (text in mlqmc_last_error) */
+  MLQMC_ENOCONV = -4   /* >= 1 sample flagged; every output is still written */
+} mlqmc_status;
+
+typedef enum { MLQMC_FP64 = 0, MLQMC_MIXED = 1 } mlqmc_precision;
+
+/* per-sample flag bits */
+#define MLQMC_FLAG_RQ_NOCONV   1u  /* Rayleigh-quotient iteration hit max_rq_iter */
+#define MLQMC_FLAG_LIN_NOCONV  2u  /* a linear solve hit max_lin_iter */
+#define MLQMC_FLAG_BREAKDOWN   4u  /* non-positive curvature in the projected solve */
+#define MLQMC_FLAG_NONFINITE   8u  /* NaN/Inf produced */
+#define MLQMC_FLAG_WRONG_PAIR 16u  /* converged vector has M-overlap < 1/2 with
+                                      sin(pi x1) sin(pi x2): not the first eigenpair */
+
+typedef struct mlqmc_ctx mlqmc_ctx;
+
+/* Coefficient family (eq. coeff): a0 + sum_{j<s} y_j c[j] sin(pi k1[j] x1) sin(pi k2[j] x2).
+ * Host arrays of length s_max, copied by mlqmc_create.  Requirements
+ * (Assumption A1.3 with |y_j| <= 1/2): a0 - 0.5 * sum_j |c[j]| > 0, k1, k2 >= 1. */
+typedef struct {
+  int32_t s_max;
+  double a0;
+  const double* c;
+  const int32_t* k1;
+  const int32_t* k2;
+} mlqmc_coeff;
+
+/* One level of the estimator (Algorithm 2).  n_* are 1/h; powers of two.
+ *  n_fine, s_fine   : fine mesh h_l and truncation s_l;
+ *  n_coarse, s_coarse: coarse mesh H_l and truncation S_l of the two-grid step
+ *                     (Algorithm 1); n_coarse == 0 means a direct eigensolve
+ *                     on the fine mesh (lambda_{h_l,s_l}, level 0 of Algorithm 2);
+ *  n_prev, s_prev   : mesh and truncation of the level-(l-1) term evaluated at
+ *                     the same point with the same coarse pair; 0 = no such term.
+ * Limits: 4 <= n_coarse <= 32 and n_coarse < n_fine <= 1024 for two-grid levels;
+ * 4 <= n_fine <= 32 for direct levels (the coarse eigensolve runs in LDS). */
+typedef struct {
+  int32_t n_fine, s_fine;
+  int32_t n_coarse, s_coarse;
+  int32_t n_prev, s_prev;
+} mlqmc_level;
+
+typedef struct {
+  int32_t prec;              /* mlqmc_precision */
+  double eig_rtol;           /* RQ iteration stops when |sigma_k - sigma_{k-1}| <= eig_rtol*sigma_k;
+                                the iteration converges cubically, so the returned
+                                sigma_k is accurate far below eig_rtol */
+  int32_t max_rq_iter;       /* cap on RQ iterations per coarse eigensolve */
+  double lin_rtol;           /* fine two-grid solve: projected PCG stops at sqrt(r.z / r0.z0) <= lin_rtol */
+  double rq_lin_rtol;        /* the same test for the inner solves of the RQ iteration */
+  int32_t max_lin_iter;      /* cap on PCG iterations per linear solve */
+  int32_t chain_len;         /* samples per warm-start chain (<=0: library default) */
+  int32_t batch;             /* samples per fine-solve batch (<=0: library default) */
+  int32_t io_on_device;      /* 1: device pointers, 0: host pointers */
+  int64_t device_mem_cap;    /* bytes; 0 = unlimited (a test hook for MLQMC_ENOMEM) */
+} mlqmc_opts;
+
+/* Fills *opt with the defaults (FP64, eig_rtol 1e-8, max_rq_iter 12,
+ * lin_rtol 1e-7, rq_lin_rtol 1e-4, max_lin_iter 60, io_on_device 0). */
+void mlqmc_default_opts(mlqmc_opts* opt);
+
+/* Creates a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  Validates and copies
+ * the coefficient family. */
+mlqmc_status mlqmc_create(mlqmc_ctx** out, const mlqmc_coeff* coeff, int device,
+                          void* hip_stream);
+/* Frees everything the context allocated.  NULL-safe. */
+void mlqmc_destroy(mlqmc_ctx* ctx);
+/* Text of the last error on this context (owned by ctx, valid until the next
+ * call on it).  Accepts NULL (returns the text of the last failed create). */
+const char* mlqmc_last_error(const mlqmc_ctx* ctx);
+
+/* ---- components of the hot path (one call per step, for parity checks) ---- */
+
+/* Randomly shifted rank-1 lattice points (eq. rqmc, eq. t_kl):
+ *   Y[i][j] = frac(((k0+i) * z[j] mod N) / N + shift[j]) - 1/2,  i < count, j < s.
+ * N a power of two; z[j] in [0, N); shift[j] in [0,1).  z, shift are host
+ * arrays; Y is [count x s] (device if io_on_device). */
+mlqmc_status mlqmc_lattice_points(mlqmc_ctx* ctx, int64_t N, int32_t s, const int64_t* z,
+                                  const double* shift, int64_t k0, int64_t count,
+                                  double* Y, int32_t io_on_device);
+
+/* Coefficient at the element centroids (eq. coeff_s, centroid rule):
+ *   aK[b][e] = a0 + sum_{j<s} Y[b][j] c_j sin(pi k1_j xc_e) sin(pi k2_j yc_e)
+ * Y is [B x s], aK is [B x 2n^2]. */
+mlqmc_status mlqmc_coefficient(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B,
+                               const double* Y, double* aK, int32_t io_on_device);
+
+/* Matrix-free P1 operator (section 2.3): out[b] = (A_h(y_b) - sigma[b] M_h) x[b],
+ * A from the centroid coefficient with s terms, M the consistent mass matrix.
+ * Y [B x s], sigma [B], x and out [B x (n-1)^2]. */
+mlqmc_status mlqmc_apply_operator(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B,
+                                  const double* Y, const double* sigma, const double* x,
+                                  double* out, int32_t io_on_device);
+
+/* P1 interpolation from mesh 1/nH to mesh 1/nh (nh a multiple of nH; section 3):
+ * uh[b] = values at the fine interior nodes of the coarse P1 function uH[b]. */
+mlqmc_status mlqmc_prolong(mlqmc_ctx* ctx, int32_t nH, int32_t nh, int64_t B, const double* uH,
+                           double* uh, int32_t io_on_device);
+
+/* ---- the hot path ---- */
+
+/* Eigen-samples of one level for an explicit point batch Y [n x s_fine]:
+ *   direct level:   lam[i] = lambda_{h,s}(y_i) (smallest FE eigenvalue), and
+ *                   lam_prev[i] = lambda_{h_prev,s_prev}(y_i) if n_prev > 0;
+ *   two-grid level: coarse pair by warm-started RQ iteration on (H,S), then
+ *                   lam[i] = lambda^{h,s}(y_i) (Algorithm 1) and, if n_prev > 0,
+ *                   lam_prev[i] = the same update on (h_prev, s_prev) from the
+ *                   same coarse pair (Algorithm 2).
+ * warm_chain = 1: sample i starts its RQ iteration from the eigenvector of
+ * sample i-1 of the same chain (the nearby-QMC-point start of section 4.3),
+ * chains being runs of opt->chain_len consecutive samples; 0: every sample
+ * starts from the eigenvector of the coefficient a = a0.
+ * lam_prev, lam_coarse, rq_iters, lin_iters may be NULL.  lam_coarse[i] =
+ * lambda_{H,S}(y_i) (NaN on direct levels); rq_iters[i] = RQ iterations of the
+ * coarse eigensolve; lin_iters[i] = PCG iterations of the fine solve(s);
+ * flags[i] = MLQMC_FLAG_* bits.  Returns MLQMC_ENOCONV if any flag is set. */
+mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* lvl, const mlqmc_opts* opt,
+                             int64_t n, const double* Y, int32_t warm_chain, double* lam,
+                             double* lam_prev, double* lam_coarse, int32_t* rq_iters,
+                             int32_t* lin_iters, uint8_t* flags);
+
+/* Two-grid MLQMC estimator (Algorithm 2; eq. tg-mlqmc, eq. sample_var, eq. ml-var).
+ * Levels l = 0..n_levels-1 with N[l] points (powers of two), R shifts, z the
+ * concatenated generating vectors ([s_fine of level l] each) and shifts the
+ * concatenated [R x s_fine] blocks per level, values in [0,1).  All of z, N,
+ * shifts and lvls are host arrays.  Outputs (host unless opt->io_on_device):
+ *   Q_lr [n_levels x R] = Q_l^(r), Qhat [n_levels], V [n_levels] (NaN if R == 1),
+ *   est[0] = Q^ML = sum_l Qhat_l, est[1] = sum_l V_l. */
+mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t n_levels, const mlqmc_level* lvls,
+                            const int64_t* N, int32_t R, const int64_t* z, const double* shifts,
+                            const mlqmc_opts* opt, double* Q_lr, double* Qhat, double* V,
+                            double* est);
+
+/* ---- instrumentation ---- */
+
+/* Kernel classes that can be timed with HIP events around each launch. */
+enum {
+  MLQMC_K_NONE = 0,
+  MLQMC_K_COEFF = 1,     /* coefficient expansion on the fine mesh */
+  MLQMC_K_APPLY = 2,     /* fine operator apply inside the projected PCG */
+  MLQMC_K_SMOOTH = 3,    /* fine-level Jacobi smoothing sweeps */
+  MLQMC_K_COARSE = 4     /* coarse eigensolve (persistent chain kernel) */
+};
+/* Selects the kernel class whose launches are bracketed by HIP events on the
+ * context's stream (MLQMC_K_NONE disables) and clears the totals. */
+mlqmc_status mlqmc_set_timing(mlqmc_ctx* ctx, int32_t kernel_class);
+/* Number of timed launches, their summed duration in ms and the summed
+ * algorithmic bytes those launches move (the model in the library's notes). */
+mlqmc_status mlqmc_get_timing(mlqmc_ctx* ctx, int64_t* launches, double* total_ms,
+                              double* model_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLQMC_H */

@@ -1,0 +1,304 @@
+"""ctypes binding of libmlqmc.so (the C ABI in include/mlqmc.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Functions carry the C names; arrays may be numpy (host memory,
+io_on_device = 0) or torch CUDA tensors (device memory, io_on_device = 1;
+the context then runs on torch's current stream).  A missing or unloadable
+library raises immediately: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlqmc.so")
+
+MLQMC_OK, MLQMC_EINVAL, MLQMC_ENOMEM, MLQMC_EDEVICE, MLQMC_ENOCONV = 0, -1, -2, -3, -4
+MLQMC_FP64, MLQMC_MIXED = 0, 1
+FLAG_RQ_NOCONV, FLAG_LIN_NOCONV, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_WRONG_PAIR = 1, 2, 4, 8, 16
+K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE = 0, 1, 2, 3, 4
+
+# every symbol include/mlqmc.h declares
+EXPORTS = [
+    "mlqmc_default_opts", "mlqmc_create", "mlqmc_destroy", "mlqmc_last_error",
+    "mlqmc_lattice_points", "mlqmc_coefficient", "mlqmc_apply_operator", "mlqmc_prolong",
+    "mlqmc_eig_level", "mlqmc_estimate", "mlqmc_set_timing", "mlqmc_get_timing",
+]
+
+
+class MlqmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mlqmc status {code}: {msg}")
+        self.code = code
+
+
+class Coeff(C.Structure):
+    _fields_ = [("s_max", C.c_int32), ("a0", C.c_double), ("c", C.POINTER(C.c_double)),
+                ("k1", C.POINTER(C.c_int32)), ("k2", C.POINTER(C.c_int32))]
+
+
+class Level(C.Structure):
+    _fields_ = [("n_fine", C.c_int32), ("s_fine", C.c_int32), ("n_coarse", C.c_int32),
+                ("s_coarse", C.c_int32), ("n_prev", C.c_int32), ("s_prev", C.c_int32)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("eig_rtol", C.c_double), ("max_rq_iter", C.c_int32),
+                ("lin_rtol", C.c_double), ("rq_lin_rtol", C.c_double),
+                ("max_lin_iter", C.c_int32), ("chain_len", C.c_int32), ("batch", C.c_int32),
+                ("io_on_device", C.c_int32), ("device_mem_cap", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Loads the library (once).  Raises if it is missing or incomplete."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2103_03407_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    for name in EXPORTS:
+        getattr(lib, name)  # AttributeError if absent
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.mlqmc_default_opts.argtypes = [C.POINTER(Opts)]
+    lib.mlqmc_default_opts.restype = None
+    lib.mlqmc_create.argtypes = [C.POINTER(P), C.POINTER(Coeff), C.c_int, P]
+    lib.mlqmc_destroy.argtypes = [P]
+    lib.mlqmc_destroy.restype = None
+    lib.mlqmc_last_error.argtypes = [P]
+    lib.mlqmc_last_error.restype = C.c_char_p
+    lib.mlqmc_lattice_points.argtypes = [P, I64, I32, P, P, I64, I64, P, I32]
+    lib.mlqmc_coefficient.argtypes = [P, I32, I32, I64, P, P, I32]
+    lib.mlqmc_apply_operator.argtypes = [P, I32, I32, I64, P, P, P, P, I32]
+    lib.mlqmc_prolong.argtypes = [P, I32, I32, I64, P, P, I32]
+    lib.mlqmc_eig_level.argtypes = [P, C.POINTER(Level), C.POINTER(Opts), I64, P, I32, P, P, P,
+                                    P, P, P]
+    lib.mlqmc_estimate.argtypes = [P, I32, C.POINTER(Level), P, I32, P, P, C.POINTER(Opts), P,
+                                   P, P, P]
+    lib.mlqmc_set_timing.argtypes = [P, I32]
+    lib.mlqmc_get_timing.argtypes = [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
+    for name in ("mlqmc_create", "mlqmc_lattice_points", "mlqmc_coefficient",
+                 "mlqmc_apply_operator", "mlqmc_prolong", "mlqmc_eig_level", "mlqmc_estimate",
+                 "mlqmc_set_timing", "mlqmc_get_timing"):
+        getattr(lib, name).restype = C.c_int
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    load().mlqmc_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype):
+    """(pointer, on_device) for a numpy array or torch CUDA tensor (or None)."""
+    if x is None:
+        return None, None
+    if _is_torch(x):
+        import torch
+        want = {np.float64: torch.float64, np.int64: torch.int64, np.int32: torch.int32,
+                np.uint8: torch.uint8}[dtype]
+        if x.dtype != want or not x.is_contiguous() or not x.is_cuda:
+            raise TypeError(f"expected a contiguous CUDA tensor of {want}")
+        return C.c_void_p(x.data_ptr()), True
+    if not isinstance(x, np.ndarray) or x.dtype != np.dtype(dtype) or not x.flags.c_contiguous:
+        raise TypeError(f"expected a C-contiguous numpy array of {np.dtype(dtype)}")
+    return C.c_void_p(x.ctypes.data), False
+
+
+def _one_side(*flags):
+    s = {f for f in flags if f is not None}
+    if len(s) > 1:
+        raise TypeError("mix of host arrays and device tensors")
+    return int(s.pop()) if s else 0
+
+
+class Context:
+    """An mlqmc_ctx bound to one device and stream."""
+
+    def __init__(self, family, device: int = 0, stream=None):
+        lib = load()
+        c = np.ascontiguousarray(family["c"], dtype=np.float64)
+        k1 = np.ascontiguousarray(family["k1"], dtype=np.int32)
+        k2 = np.ascontiguousarray(family["k2"], dtype=np.int32)
+        cf = Coeff(int(c.size), float(family["a0"]), c.ctypes.data_as(C.POINTER(C.c_double)),
+                   k1.ctypes.data_as(C.POINTER(C.c_int32)), k2.ctypes.data_as(C.POINTER(C.c_int32)))
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except ImportError:
+                stream = None
+        h = C.c_void_p()
+        st = lib.mlqmc_create(C.byref(h), C.byref(cf), int(device), C.c_void_p(stream or 0))
+        if st != MLQMC_OK:
+            raise MlqmcError(st, lib.mlqmc_last_error(None).decode())
+        self._lib, self._h = lib, h
+        self.s_max = int(c.size)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mlqmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow_noconv=False):
+        if st == MLQMC_OK or (allow_noconv and st == MLQMC_ENOCONV):
+            return st
+        raise MlqmcError(st, self._lib.mlqmc_last_error(self._h).decode())
+
+    # ---- components ----
+    def lattice_points(self, N, z, shift, k0, count, Y):
+        z = np.ascontiguousarray(z, dtype=np.int64)
+        shift = np.ascontiguousarray(shift, dtype=np.float64)
+        py, dy = _ptr(Y, np.float64)
+        return self._check(self._lib.mlqmc_lattice_points(
+            self._h, int(N), int(z.size), C.c_void_p(z.ctypes.data),
+            C.c_void_p(shift.ctypes.data), int(k0), int(count), py, int(bool(dy))))
+
+    def coefficient(self, n, s, Y, aK):
+        py, dy = _ptr(Y, np.float64)
+        pa, da = _ptr(aK, np.float64)
+        B = Y.shape[0]
+        return self._check(self._lib.mlqmc_coefficient(self._h, int(n), int(s), int(B), py, pa,
+                                                       _one_side(dy, da)))
+
+    def apply_operator(self, n, s, Y, sigma, x, out):
+        py, dy = _ptr(Y, np.float64)
+        ps, ds = _ptr(sigma, np.float64)
+        px, dx = _ptr(x, np.float64)
+        po, do = _ptr(out, np.float64)
+        B = x.shape[0]
+        return self._check(self._lib.mlqmc_apply_operator(
+            self._h, int(n), int(s), int(B), py, ps, px, po, _one_side(dy, ds, dx, do)))
+
+    def prolong(self, nH, nh, uH, uh):
+        pu, du = _ptr(uH, np.float64)
+        pv, dv = _ptr(uh, np.float64)
+        return self._check(self._lib.mlqmc_prolong(self._h, int(nH), int(nh), int(uH.shape[0]),
+                                                   pu, pv, _one_side(du, dv)))
+
+    # ---- hot path ----
+    def eig_level(self, level, Y, lam, flags, lam_prev=None, lam_coarse=None, rq_iters=None,
+                  lin_iters=None, warm_chain=1, opts=None):
+        o = opts if opts is not None else default_opts()
+        lv = Level(*[int(x) for x in level])
+        py, d0 = _ptr(Y, np.float64)
+        pl, d1 = _ptr(lam, np.float64)
+        pf, d2 = _ptr(flags, np.uint8)
+        pp, d3 = _ptr(lam_prev, np.float64)
+        pc, d4 = _ptr(lam_coarse, np.float64)
+        pr, d5 = _ptr(rq_iters, np.int32)
+        pi, d6 = _ptr(lin_iters, np.int32)
+        o.io_on_device = _one_side(d0, d1, d2, d3, d4, d5, d6)
+        n = Y.shape[0]
+        return self._check(self._lib.mlqmc_eig_level(
+            self._h, C.byref(lv), C.byref(o), int(n), py, int(warm_chain), pl, pp, pc, pr, pi,
+            pf), allow_noconv=True)
+
+    def estimate(self, levels, N, R, z, shifts, opts=None):
+        """levels: list of 6-tuples; z, shifts: per-level arrays.  Returns
+        (status, Q_lr [L,R], Qhat [L], V [L], est [2]) as host arrays."""
+        o = opts if opts is not None else default_opts()
+        o.io_on_device = 0
+        L = len(levels)
+        lv = (Level * L)(*[Level(*[int(x) for x in l]) for l in levels])
+        Nn = np.ascontiguousarray(N, dtype=np.int64)
+        zc = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.int64) for a in z]))
+        sc = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64).ravel()
+                                                  for a in shifts]))
+        Q = np.zeros((L, R))
+        Qh = np.zeros(L)
+        V = np.zeros(L)
+        est = np.zeros(2)
+        st = self._check(self._lib.mlqmc_estimate(
+            self._h, L, lv, C.c_void_p(Nn.ctypes.data), int(R), C.c_void_p(zc.ctypes.data),
+            C.c_void_p(sc.ctypes.data), C.byref(o), C.c_void_p(Q.ctypes.data),
+            C.c_void_p(Qh.ctypes.data), C.c_void_p(V.ctypes.data), C.c_void_p(est.ctypes.data)),
+            allow_noconv=True)
+        return st, Q, Qh, V, est
+
+    # ---- instrumentation ----
+    def set_timing(self, kernel_class):
+        return self._check(self._lib.mlqmc_set_timing(self._h, int(kernel_class)))
+
+    def get_timing(self):
+        n = C.c_int64()
+        ms = C.c_double()
+        by = C.c_double()
+        self._check(self._lib.mlqmc_get_timing(self._h, C.byref(n), C.byref(ms), C.byref(by)))
+        return int(n.value), float(ms.value), float(by.value)
+
+
+# module-level functions with the C names
+def mlqmc_create(family, device=0, stream=None) -> Context:
+    return Context(family, device, stream)
+
+
+def mlqmc_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def mlqmc_last_error(ctx: Context | None = None) -> str:
+    lib = load()
+    return lib.mlqmc_last_error(ctx._h if ctx is not None else None).decode()
+
+
+def mlqmc_default_opts(**kw) -> Opts:
+    return default_opts(**kw)
+
+
+def mlqmc_lattice_points(ctx, *a, **k):
+    return ctx.lattice_points(*a, **k)
+
+
+def mlqmc_coefficient(ctx, *a, **k):
+    return ctx.coefficient(*a, **k)
+
+
+def mlqmc_apply_operator(ctx, *a, **k):
+    return ctx.apply_operator(*a, **k)
+
+
+def mlqmc_prolong(ctx, *a, **k):
+    return ctx.prolong(*a, **k)
+
+
+def mlqmc_eig_level(ctx, *a, **k):
+    return ctx.eig_level(*a, **k)
+
+
+def mlqmc_estimate(ctx, *a, **k):
+    return ctx.estimate(*a, **k)
+
+
+def mlqmc_set_timing(ctx, *a, **k):
+    return ctx.set_timing(*a, **k)
+
+
+def mlqmc_get_timing(ctx):
+    return ctx.get_timing()

@@ -1,0 +1,892 @@
+// C ABI of the two-grid MLQMC eigen-sample library: argument validation,
+// device buffers, and the orchestration of the kernels for one level
+// (coarse eigensolve -> two-grid updates) and for the estimator (Algorithm 2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mlqmc.h"
+#include "kernels.h"
+
+using namespace mlqmc;
+
+namespace {
+
+std::string g_create_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Table {
+  int s = 0;
+  double* el = nullptr;    // [s][2n^2]
+  double* edge = nullptr;  // [s][2(n-1)n]
+};
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+struct Status {
+  mlqmc_status code = MLQMC_OK;
+};
+
+}  // namespace
+
+struct mlqmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int s_max = 0;
+  double a0 = 0.0;
+  double* d_c = nullptr;
+  int* d_k1 = nullptr;
+  int* d_k2 = nullptr;
+  std::map<std::string, DevBuf> bufs;
+  std::map<int, Table> tables;
+  int64_t bytes_alloc = 0;
+  int64_t mem_cap = 0;
+  std::string err;
+  // timing
+  int timing_class = MLQMC_K_NONE;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  size_t ev_used = 0;
+  int64_t t_launches = 0;
+  double t_ms = 0.0;
+  double t_bytes = 0.0;
+
+  mlqmc_status fail(mlqmc_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+  mlqmc_status hip_fail(hipError_t e, const char* what) {
+    return fail(MLQMC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  }
+
+  // growable named device buffer
+  mlqmc_status get(const char* name, size_t bytes, void** out) {
+    DevBuf& b = bufs[name];
+    if (b.bytes >= bytes && b.p) {
+      *out = b.p;
+      return MLQMC_OK;
+    }
+    if (b.p) {
+      hipFree(b.p);
+      bytes_alloc -= (int64_t)b.bytes;
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    if (bytes == 0) bytes = 8;
+    if (mem_cap > 0 && bytes_alloc + (int64_t)bytes > mem_cap)
+      return fail(MLQMC_ENOMEM, "buffer %s: %zu bytes exceed the device memory cap", name, bytes);
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+      b.p = nullptr;
+      return fail(MLQMC_ENOMEM, "hipMalloc(%zu) for %s: %s", bytes, name, hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    bytes_alloc += (int64_t)bytes;
+    *out = b.p;
+    return MLQMC_OK;
+  }
+  template <typename T>
+  mlqmc_status getT(const char* name, size_t count, T** out) {
+    void* p = nullptr;
+    mlqmc_status s = get(name, count * sizeof(T), &p);
+    *out = static_cast<T*>(p);
+    return s;
+  }
+
+  // coefficient tables for mesh n with at least s rows
+  mlqmc_status table(int n, int s, Table** out) {
+    Table& t = tables[n];
+    if (t.s < s || !t.el) {
+      if (t.el) hipFree(t.el);
+      if (t.edge) hipFree(t.edge);
+      bytes_alloc -= (int64_t)(t.s) * (2 * n * n + 2 * (n - 1) * n) * 8;
+      t.el = t.edge = nullptr;
+      t.s = 0;
+      const int srows = std::max(s, 1);
+      const size_t be = (size_t)srows * 2 * n * n * 8, bw = (size_t)srows * 2 * (n - 1) * n * 8;
+      if (mem_cap > 0 && bytes_alloc + (int64_t)(be + bw) > mem_cap)
+        return fail(MLQMC_ENOMEM, "coefficient table for n=%d exceeds the device memory cap", n);
+      hipError_t e = hipMalloc(&t.el, be);
+      if (e == hipSuccess) e = hipMalloc(&t.edge, bw);
+      if (e != hipSuccess) return fail(MLQMC_ENOMEM, "table allocation: %s", hipGetErrorString(e));
+      bytes_alloc += (int64_t)(be + bw);
+      t.s = srows;
+      e = launch_phi_elements(n, srows, d_c, d_k1, d_k2, t.el, stream);
+      if (e == hipSuccess) e = launch_phi_edges(n, srows, t.el, t.edge, stream);
+      if (e != hipSuccess) return hip_fail(e, "coefficient tables");
+    }
+    *out = &t;
+    return MLQMC_OK;
+  }
+
+  // timing around launches of the selected class
+  bool timed(int cls) const { return timing_class != MLQMC_K_NONE && timing_class == cls; }
+  void t_begin(int cls) {
+    if (!timed(cls)) return;
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t a, b;
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      ev_pool.push_back({a, b});
+    }
+    hipEventRecord(ev_pool[ev_used].first, stream);
+  }
+  void t_end(int cls, double bytes) {
+    if (!timed(cls)) return;
+    hipEventRecord(ev_pool[ev_used].second, stream);
+    ++ev_used;
+    ++t_launches;
+    t_bytes += bytes;
+  }
+  void t_collect() {
+    for (size_t k = 0; k < ev_used; ++k) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ev_pool[k].first, ev_pool[k].second);
+      t_ms += ms;
+    }
+    ev_used = 0;
+  }
+  mlqmc_status sync(const char* what) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, what);
+    t_collect();
+    return MLQMC_OK;
+  }
+};
+
+namespace {
+
+#define CK(expr, what)                        \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return ctx->hip_fail(e_, what); \
+  } while (0)
+#define CS(expr)                      \
+  do {                                \
+    mlqmc_status s_ = (expr);         \
+    if (s_ != MLQMC_OK) return s_;    \
+  } while (0)
+
+// copy n elements in from caller memory to a named device buffer (or alias)
+template <typename T>
+mlqmc_status stage_in(mlqmc_ctx* ctx, const char* name, const T* src, size_t n, int on_dev,
+                      const T** out) {
+  if (on_dev) {
+    *out = src;
+    return MLQMC_OK;
+  }
+  T* d = nullptr;
+  CS(ctx->getT(name, n, &d));
+  if (n) CK(hipMemcpyAsync(d, src, n * sizeof(T), hipMemcpyHostToDevice, ctx->stream), "copy in");
+  *out = d;
+  return MLQMC_OK;
+}
+
+template <typename T>
+mlqmc_status out_buf(mlqmc_ctx* ctx, const char* name, T* dst, size_t n, int on_dev, T** out) {
+  if (on_dev) {
+    *out = dst;
+    return MLQMC_OK;
+  }
+  return ctx->getT(name, n, out);
+}
+
+template <typename T>
+mlqmc_status stage_out(mlqmc_ctx* ctx, T* dst, const T* dev, size_t n, int on_dev) {
+  if (on_dev || !dst || n == 0) return MLQMC_OK;
+  CK(hipMemcpyAsync(dst, dev, n * sizeof(T), hipMemcpyDeviceToHost, ctx->stream), "copy out");
+  return MLQMC_OK;
+}
+
+mlqmc_status check_opts(mlqmc_ctx* ctx, const mlqmc_opts* o) {
+  if (!o) return ctx->fail(MLQMC_EINVAL, "opts is NULL");
+  if (o->prec != MLQMC_FP64 && o->prec != MLQMC_MIXED)
+    return ctx->fail(MLQMC_EINVAL, "unknown precision %d", o->prec);
+  if (o->prec == MLQMC_MIXED)
+    return ctx->fail(MLQMC_EINVAL, "mixed precision is not available in this build");
+  if (!(o->eig_rtol > 0) || !(o->lin_rtol > 0) || !(o->rq_lin_rtol > 0))
+    return ctx->fail(MLQMC_EINVAL, "tolerances must be positive");
+  if (o->max_rq_iter < 1 || o->max_lin_iter < 1)
+    return ctx->fail(MLQMC_EINVAL, "iteration caps must be >= 1");
+  if (o->device_mem_cap < 0) return ctx->fail(MLQMC_EINVAL, "device_mem_cap must be >= 0");
+  return MLQMC_OK;
+}
+
+mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
+  if (!l) return ctx->fail(MLQMC_EINVAL, "level is NULL");
+  if (!is_pow2(l->n_fine)) return ctx->fail(MLQMC_EINVAL, "n_fine=%d is not a power of two", l->n_fine);
+  if (l->s_fine < 0 || l->s_fine > ctx->s_max)
+    return ctx->fail(MLQMC_EINVAL, "s_fine=%d outside [0, s_max=%d]", l->s_fine, ctx->s_max);
+  if (l->s_fine > 512) return ctx->fail(MLQMC_EINVAL, "s_fine=%d exceeds 512", l->s_fine);
+  if (l->n_coarse == 0) {
+    if (l->n_fine < 4 || l->n_fine > 32)
+      return ctx->fail(MLQMC_EINVAL, "direct levels need 4 <= n_fine <= 32 (got %d)", l->n_fine);
+  } else {
+    if (!is_pow2(l->n_coarse) || l->n_coarse < 4 || l->n_coarse > 32)
+      return ctx->fail(MLQMC_EINVAL, "n_coarse=%d must be a power of two in [4, 32]", l->n_coarse);
+    if (l->n_fine <= l->n_coarse || l->n_fine > 1024)
+      return ctx->fail(MLQMC_EINVAL, "need n_coarse < n_fine <= 1024 (got %d, %d)", l->n_coarse,
+                       l->n_fine);
+    if (l->s_coarse < 0 || l->s_coarse > l->s_fine)
+      return ctx->fail(MLQMC_EINVAL, "s_coarse=%d outside [0, s_fine]", l->s_coarse);
+  }
+  if (l->n_prev != 0) {
+    if (!is_pow2(l->n_prev)) return ctx->fail(MLQMC_EINVAL, "n_prev=%d is not a power of two", l->n_prev);
+    if (l->s_prev < 0 || l->s_prev > l->s_fine)
+      return ctx->fail(MLQMC_EINVAL, "s_prev=%d outside [0, s_fine]", l->s_prev);
+    if (l->n_coarse == 0) {
+      if (l->n_prev < 4 || l->n_prev > 32)
+        return ctx->fail(MLQMC_EINVAL, "direct previous level needs 4 <= n_prev <= 32");
+    } else if (l->n_prev < l->n_coarse || l->n_prev > 1024) {
+      return ctx->fail(MLQMC_EINVAL, "need n_coarse <= n_prev <= 1024 (got %d)", l->n_prev);
+    }
+  }
+  return MLQMC_OK;
+}
+
+int default_chain(int64_t n, int warm, int chain_len) {
+  if (!warm) return 1;
+  if (chain_len > 0) return chain_len;
+  const int64_t target = 512;  // chains in flight: 2 workgroups on each of 256 CUs
+  int64_t c = (n + target - 1) / target;
+  return (int)std::max<int64_t>(1, c);
+}
+
+struct FineBufs {
+  int nh, nb;  // fine mesh, bottom mesh (<= 32)
+  std::vector<int> lv_n;  // batched levels: nh, nh/2, ..., > 32
+};
+
+// Two-grid update on mesh nh (>= 64) for n samples, batched.
+mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, const double* Y,
+                          int64_t ldY, const double* uH, const double* lamH, int nH, int64_t n,
+                          double* lam, int* lin_iters, uint8_t* flags, const char* tag) {
+  Table* tb = nullptr;
+  CS(ctx->table(nh, s, &tb));
+  // levels
+  std::vector<int> lv;
+  for (int m = nh; m > 32; m /= 2) lv.push_back(m);
+  const int nb = 32;
+  auto D = [](int m) { return (int64_t)(m - 1) * (m - 1); };
+  auto EW = [](int m) { return (int64_t)2 * (m - 1) * m; };
+  int64_t per_sample = 8 * (EW(nh) + 7 * D(nh));
+  for (size_t k = 1; k < lv.size(); ++k) per_sample += 8 * (EW(lv[k]) + 3 * D(lv[k]));
+  per_sample += 8 * (EW(nb) + 2 * D(nb));
+  int64_t batch = o->batch > 0 ? o->batch : std::max<int64_t>(1, (int64_t)16e9 / per_sample);
+  batch = std::min<int64_t>(batch, n);
+  batch = std::min<int64_t>(batch, 65535);
+  const int nblk0 = fine_blocks((int)D(nh));
+
+  std::string p = tag;
+  auto nm = [&](const char* x) { return p + x; };
+  double *w0, *v, *t, *r, *z, *zb, *pp, *q, *part;
+  CS(ctx->getT(nm("w0").c_str(), batch * EW(nh), &w0));
+  CS(ctx->getT(nm("v").c_str(), batch * D(nh), &v));
+  CS(ctx->getT(nm("t").c_str(), batch * D(nh), &t));
+  CS(ctx->getT(nm("r").c_str(), batch * D(nh), &r));
+  CS(ctx->getT(nm("z").c_str(), batch * D(nh), &z));
+  CS(ctx->getT(nm("zb").c_str(), batch * D(nh), &zb));
+  CS(ctx->getT(nm("p").c_str(), batch * D(nh), &pp));
+  CS(ctx->getT(nm("q").c_str(), batch * D(nh), &q));
+  CS(ctx->getT(nm("part").c_str(), batch * nblk0 * 3, &part));
+  std::vector<double*> W(lv.size() + 1), X(lv.size() + 1), Xb(lv.size() + 1), Bv(lv.size() + 1);
+  W[0] = w0;
+  for (size_t k = 1; k <= lv.size(); ++k) {
+    const int m = (k < lv.size()) ? lv[k] : nb;
+    char b1[64];
+    snprintf(b1, sizeof b1, "w%zu", k);
+    CS(ctx->getT(nm(b1).c_str(), batch * EW(m), &W[k]));
+    snprintf(b1, sizeof b1, "X%zu", k);
+    CS(ctx->getT(nm(b1).c_str(), batch * D(m), &X[k]));
+    snprintf(b1, sizeof b1, "B%zu", k);
+    CS(ctx->getT(nm(b1).c_str(), batch * D(m), &Bv[k]));
+    if (k < lv.size()) {
+      snprintf(b1, sizeof b1, "Xb%zu", k);
+      CS(ctx->getT(nm(b1).c_str(), batch * D(m), &Xb[k]));
+    }
+  }
+  double* sc = nullptr;
+  CS(ctx->getT(nm("scal").c_str(), batch * 9, &sc));
+  int* its = nullptr;
+  CS(ctx->getT(nm("its").c_str(), batch, &its));
+  uint8_t* active = nullptr;
+  CS(ctx->getT(nm("active").c_str(), batch, &active));
+  std::vector<uint8_t> h_active(batch);
+
+  const size_t nL = lv.size();
+  for (int64_t b0 = 0; b0 < n; b0 += batch) {
+    const int64_t Bn = std::min<int64_t>(batch, n - b0);
+    FineState S{};
+    S.mu = const_cast<double*>(lamH) + b0;
+    S.vs = sc;
+    S.rho = sc + batch;
+    S.rz = sc + 2 * batch;
+    S.rz0 = sc + 3 * batch;
+    S.alpha = sc + 4 * batch;
+    S.c = sc + 5 * batch;
+    S.c2 = sc + 6 * batch;
+    S.beta = sc + 7 * batch;
+    S.lam = lam + b0;
+    S.its = its;
+    S.lin_acc = lin_iters ? lin_iters + b0 : nullptr;
+    S.active = active;
+    S.flags = flags + b0;
+    hipStream_t st = ctx->stream;
+
+    // coefficient expansion straight into edge weights, then the coarser levels
+    ctx->t_begin(MLQMC_K_COEFF);
+    CK(launch_expand(Bn, s, (int)EW(nh), Y + b0 * ldY, ldY, tb->edge, ctx->a0, w0, st), "expand");
+    ctx->t_end(MLQMC_K_COEFF, 8.0 * ((double)Bn * s + (double)s * EW(nh) + (double)Bn * EW(nh)));
+    for (size_t k = 0; k < nL; ++k) CK(launch_coarsen(lv[k], Bn, W[k], W[k + 1], st), "coarsen");
+
+    CK(launch_prolong(nH, nh, Bn, uH + b0 * D(nH), v, st), "prolong");
+    CK(launch_setup_dots(nh, Bn, v, w0, part, st), "setup dots");
+    CK(launch_scalar(PH_SETUP, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
+    CK(launch_setup_rhs(nh, Bn, v, w0, S, r, t, zb, st), "setup rhs");
+
+    // remainder of the V-cycle on level 0 (first sweep already in zb): z = K^{-1} r
+    auto vcycle_rest = [&]() -> mlqmc_status {
+      const uint8_t* act = active;
+      const double jb = 8.0 * (double)Bn * (3 * D(nh) + EW(nh));
+      ctx->t_begin(MLQMC_K_SMOOTH);
+      CK(launch_jacobi(nh, Bn, w0, r, zb, z, act, st), "jacobi");
+      ctx->t_end(MLQMC_K_SMOOTH, jb);
+      CK(launch_resid_restrict(nh, Bn, w0, r, z, Bv[1], act, st), "restrict");
+      for (size_t k = 1; k < nL; ++k) {
+        CK(launch_jacobi_first(lv[k], Bn, W[k], Bv[k], Xb[k], act, st), "jacobi0");
+        CK(launch_jacobi(lv[k], Bn, W[k], Bv[k], Xb[k], X[k], act, st), "jacobi");
+        CK(launch_resid_restrict(lv[k], Bn, W[k], Bv[k], X[k], Bv[k + 1], act, st), "restrict");
+      }
+      CK(launch_bottom_vcycle(nb, Bn, W[nL], Bv[nL], X[nL], act, st), "bottom");
+      for (size_t k = nL - 1; k >= 1; --k) {
+        CK(launch_prolong_add(lv[k], Bn, X[k + 1], X[k], act, st), "prolong add");
+        CK(launch_jacobi(lv[k], Bn, W[k], Bv[k], X[k], Xb[k], act, st), "jacobi");
+        CK(launch_jacobi(lv[k], Bn, W[k], Bv[k], Xb[k], X[k], act, st), "jacobi");
+      }
+      CK(launch_prolong_add(nh, Bn, X[1], z, act, st), "prolong add");
+      ctx->t_begin(MLQMC_K_SMOOTH);
+      CK(launch_jacobi(nh, Bn, w0, r, z, zb, act, st), "jacobi");
+      ctx->t_end(MLQMC_K_SMOOTH, jb);
+      ctx->t_begin(MLQMC_K_SMOOTH);
+      CK(launch_jacobi(nh, Bn, w0, r, zb, z, act, st), "jacobi");
+      ctx->t_end(MLQMC_K_SMOOTH, jb);
+      return MLQMC_OK;
+    };
+    CS(vcycle_rest());
+    CK(launch_dots3(nh, Bn, r, z, v, S, part, st), "dots3");
+    CK(launch_scalar(PH_FIRST_RZ, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
+    CK(launch_pupdate(nh, Bn, z, v, S, pp, st), "pupdate");
+    const double ab = 8.0 * (double)Bn * (3 * D(nh) + EW(nh));
+    for (int it = 0; it < o->max_lin_iter; ++it) {
+      ctx->t_begin(MLQMC_K_APPLY);
+      CK(launch_apply_dots(nh, Bn, pp, v, w0, S, q, part, st), "apply");
+      ctx->t_end(MLQMC_K_APPLY, ab);
+      CK(launch_scalar(PH_ALPHA, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
+      CK(launch_update(nh, Bn, pp, q, v, w0, S, t, r, zb, st), "update");
+      CS(vcycle_rest());
+      CK(launch_dots3(nh, Bn, r, z, v, S, part, st), "dots3");
+      CK(launch_scalar(PH_BETA, nh, Bn, nblk0, part, S, o->lin_rtol, o->max_lin_iter, st),
+         "scalar");
+      CK(launch_pupdate(nh, Bn, z, v, S, pp, st), "pupdate");
+      if (it % 3 == 2 || it + 1 == o->max_lin_iter) {
+        CK(hipMemcpyAsync(h_active.data(), active, Bn, hipMemcpyDeviceToHost, st), "active");
+        CS(ctx->sync("pcg"));
+        bool any = false;
+        for (int64_t k = 0; k < Bn; ++k) any |= h_active[k] != 0;
+        if (!any) break;
+      }
+    }
+    CK(launch_final_dots(nh, Bn, v, t, w0, S, part, st), "final dots");
+    CK(launch_scalar(PH_FINAL, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
+  }
+  return MLQMC_OK;
+}
+
+// Two-grid update on mesh nh from the coarse pairs (uH on mesh nH, lamH).
+mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, const double* Y,
+                         int64_t ldY, const double* uH, const double* lamH, int nH, int64_t n,
+                         double* lam, int* lin_iters, uint8_t* flags, const char* tag) {
+  if (nh <= 32) {
+    Table* tb = nullptr;
+    CS(ctx->table(nh, s, &tb));
+    TgSmallArgs a{};
+    a.Y = Y;
+    a.ldY = ldY;
+    a.s = s;
+    a.phi = tb->edge;
+    a.a0 = ctx->a0;
+    a.uH = uH;
+    a.lamH = lamH;
+    a.nH = nH;
+    a.n = n;
+    a.lin_rtol = o->lin_rtol;
+    a.max_lin = o->max_lin_iter;
+    a.lam = lam;
+    a.lin_iters = lin_iters;
+    a.flags = flags;
+    CK(launch_tg_small(nh, a, ctx->stream), "two-grid (LDS)");
+    return MLQMC_OK;
+  }
+  return fine_batched(ctx, o, nh, s, Y, ldY, uH, lamH, nH, n, lam, lin_iters, flags, tag);
+}
+
+// Whole level on device buffers (Y [n x ldY] on device); outputs on device.
+mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* o, int64_t n,
+                        const double* Y, int64_t ldY, int warm, double* lam, double* lam_prev,
+                        double* lam_coarse, int* rq_iters, int* lin_iters, uint8_t* flags) {
+  hipStream_t st = ctx->stream;
+  if (n == 0) return MLQMC_OK;
+  CK(hipMemsetAsync(flags, 0, n, st), "memset");
+  CK(hipMemsetAsync(lin_iters, 0, n * sizeof(int), st), "memset");
+  const int chain = default_chain(n, warm, o->chain_len);
+  RqiArgs a{};
+  a.Y = Y;
+  a.ldY = ldY;
+  a.a0 = ctx->a0;
+  a.n = n;
+  a.chain_len = chain;
+  a.warm = warm;
+  a.eig_rtol = o->eig_rtol;
+  a.max_rq = o->max_rq_iter;
+  a.lin_rtol = o->rq_lin_rtol;
+  a.max_lin = o->max_lin_iter;
+  a.rq_iters = rq_iters;
+  a.lin_iters = lin_iters;
+  a.flags = flags;
+  if (L->n_coarse == 0) {
+    Table* tb = nullptr;
+    CS(ctx->table(L->n_fine, L->s_fine, &tb));
+    a.S = L->s_fine;
+    a.phi = tb->edge;
+    a.lam = lam;
+    a.u_out = nullptr;
+    ctx->t_begin(MLQMC_K_COARSE);
+    CK(launch_rqi(L->n_fine, a, st), "eigensolve (LDS)");
+    ctx->t_end(MLQMC_K_COARSE, 0.0);
+    if (lam_coarse) {
+      std::vector<double> nans(n, NAN);
+      CK(hipMemcpyAsync(lam_coarse, nans.data(), n * sizeof(double), hipMemcpyHostToDevice, st),
+         "nan fill");
+      CS(ctx->sync("nan fill"));
+    }
+    if (L->n_prev && lam_prev) {
+      uint8_t* f2 = nullptr;
+      int* i2 = nullptr;
+      CS(ctx->getT("flags_prev", n, &f2));
+      CS(ctx->getT("rq_prev", n, &i2));
+      CS(ctx->table(L->n_prev, L->s_prev, &tb));
+      RqiArgs b = a;
+      b.S = L->s_prev;
+      b.phi = tb->edge;
+      b.lam = lam_prev;
+      b.rq_iters = i2;
+      b.lin_iters = nullptr;
+      b.flags = f2;
+      CK(launch_rqi(L->n_prev, b, st), "eigensolve (LDS)");
+      // merge the flags of the previous-level eigensolve on the host
+      std::vector<uint8_t> h1(n), h2(n);
+      CK(hipMemcpyAsync(h1.data(), flags, n, hipMemcpyDeviceToHost, st), "flags");
+      CK(hipMemcpyAsync(h2.data(), f2, n, hipMemcpyDeviceToHost, st), "flags");
+      CS(ctx->sync("flags"));
+      for (int64_t k = 0; k < n; ++k) h1[k] |= h2[k];
+      CK(hipMemcpyAsync(flags, h1.data(), n, hipMemcpyHostToDevice, st), "flags");
+      CS(ctx->sync("flags"));
+    }
+    return MLQMC_OK;
+  }
+  // coarse pairs
+  Table* tb = nullptr;
+  CS(ctx->table(L->n_coarse, L->s_coarse, &tb));
+  const int64_t DH = (int64_t)(L->n_coarse - 1) * (L->n_coarse - 1);
+  double *uH = nullptr, *lamH = lam_coarse;
+  CS(ctx->getT("uH", n * DH, &uH));
+  if (!lamH) CS(ctx->getT("lamH", n, &lamH));
+  a.S = L->s_coarse;
+  a.phi = tb->edge;
+  a.lam = lamH;
+  a.u_out = uH;
+  ctx->t_begin(MLQMC_K_COARSE);
+  CK(launch_rqi(L->n_coarse, a, st), "coarse eigensolve (LDS)");
+  ctx->t_end(MLQMC_K_COARSE, 0.0);
+  CS(fine_update(ctx, o, L->n_fine, L->s_fine, Y, ldY, uH, lamH, L->n_coarse, n, lam, lin_iters,
+                 flags, "f_"));
+  if (L->n_prev && lam_prev) {
+    if (L->n_prev == L->n_coarse && L->s_prev == L->s_coarse) {
+      // (A - lambda_H M) is singular on the coarse space itself: its update is lambda_H
+      CK(hipMemcpyAsync(lam_prev, lamH, n * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+    } else {
+      CS(fine_update(ctx, o, L->n_prev, L->s_prev, Y, ldY, uH, lamH, L->n_coarse, n, lam_prev,
+                     lin_iters, flags, "p_"));
+    }
+  }
+  return MLQMC_OK;
+}
+
+mlqmc_status any_flag(mlqmc_ctx* ctx, const uint8_t* flags_dev, int64_t n, bool* any) {
+  std::vector<uint8_t> h(n);
+  if (n) CK(hipMemcpyAsync(h.data(), flags_dev, n, hipMemcpyDeviceToHost, ctx->stream), "flags");
+  CS(ctx->sync("flags"));
+  *any = false;
+  for (int64_t k = 0; k < n; ++k) *any |= h[k] != 0;
+  return MLQMC_OK;
+}
+
+bool finite_host(const double* x, size_t n) {
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(x[k])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mlqmc_default_opts(mlqmc_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->prec = MLQMC_FP64;
+  o->eig_rtol = 1e-8;
+  o->max_rq_iter = 12;
+  o->lin_rtol = 1e-7;
+  o->rq_lin_rtol = 1e-4;
+  o->max_lin_iter = 60;
+  o->chain_len = 0;
+  o->batch = 0;
+  o->io_on_device = 0;
+  o->device_mem_cap = 0;
+}
+
+mlqmc_status mlqmc_create(mlqmc_ctx** out, const mlqmc_coeff* cf, int device, void* stream) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return MLQMC_EINVAL;
+  }
+  *out = nullptr;
+  if (!cf || cf->s_max < 0 || (cf->s_max > 0 && (!cf->c || !cf->k1 || !cf->k2))) {
+    g_create_error = "invalid coefficient description";
+    return MLQMC_EINVAL;
+  }
+  if (!std::isfinite(cf->a0)) {
+    g_create_error = "a0 is not finite";
+    return MLQMC_EINVAL;
+  }
+  double half = 0.0;
+  for (int j = 0; j < cf->s_max; ++j) {
+    if (!std::isfinite(cf->c[j]) || cf->k1[j] < 1 || cf->k2[j] < 1) {
+      g_create_error = "coefficient term " + std::to_string(j) + " is invalid";
+      return MLQMC_EINVAL;
+    }
+    half += 0.5 * std::fabs(cf->c[j]);
+  }
+  if (!(cf->a0 - half > 0.0)) {
+    g_create_error = "a0 - 0.5 sum |c_j| <= 0: the coefficient is not uniformly positive";
+    return MLQMC_EINVAL;
+  }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || device < 0 || device >= ndev) {
+    g_create_error = std::string("no HIP device ") + std::to_string(device) +
+                     (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
+    return MLQMC_EDEVICE;
+  }
+  e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+    return MLQMC_EDEVICE;
+  }
+  mlqmc_ctx* ctx = new mlqmc_ctx();
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  ctx->s_max = cf->s_max;
+  ctx->a0 = cf->a0;
+  const int sm = std::max(cf->s_max, 1);
+  std::vector<double> c(sm, 0.0);
+  std::vector<int> k1(sm, 1), k2(sm, 1);
+  for (int j = 0; j < cf->s_max; ++j) {
+    c[j] = cf->c[j];
+    k1[j] = cf->k1[j];
+    k2[j] = cf->k2[j];
+  }
+  e = hipMalloc(&ctx->d_c, sm * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_k1, sm * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_k2, sm * sizeof(int));
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_c, c.data(), sm * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_k1, k1.data(), sm * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_k2, k2.data(), sm * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    g_create_error = std::string("device setup: ") + hipGetErrorString(e);
+    mlqmc_destroy(ctx);
+    return MLQMC_EDEVICE;
+  }
+  *out = ctx;
+  return MLQMC_OK;
+}
+
+void mlqmc_destroy(mlqmc_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->bufs)
+    if (kv.second.p) hipFree(kv.second.p);
+  for (auto& kv : ctx->tables) {
+    if (kv.second.el) hipFree(kv.second.el);
+    if (kv.second.edge) hipFree(kv.second.edge);
+  }
+  for (auto& ev : ctx->ev_pool) {
+    hipEventDestroy(ev.first);
+    hipEventDestroy(ev.second);
+  }
+  if (ctx->d_c) hipFree(ctx->d_c);
+  if (ctx->d_k1) hipFree(ctx->d_k1);
+  if (ctx->d_k2) hipFree(ctx->d_k2);
+  delete ctx;
+}
+
+const char* mlqmc_last_error(const mlqmc_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+mlqmc_status mlqmc_lattice_points(mlqmc_ctx* ctx, int64_t N, int32_t s, const int64_t* z,
+                                  const double* shift, int64_t k0, int64_t count, double* Y,
+                                  int32_t on_dev) {
+  if (!ctx) return MLQMC_EINVAL;
+  if (!is_pow2(N) || N > ((int64_t)1 << 30)) return ctx->fail(MLQMC_EINVAL, "N must be a power of two <= 2^30");
+  if (s < 0 || count < 0 || k0 < 0 || k0 + count > N)
+    return ctx->fail(MLQMC_EINVAL, "need s >= 0 and 0 <= k0 <= k0+count <= N");
+  if ((s > 0 && (!z || !shift)) || (count * s > 0 && !Y))
+    return ctx->fail(MLQMC_EINVAL, "NULL buffer");
+  for (int j = 0; j < s; ++j) {
+    if (z[j] < 0 || z[j] >= N) return ctx->fail(MLQMC_EINVAL, "z[%d] outside [0, N)", j);
+    if (!(shift[j] >= 0.0 && shift[j] < 1.0))
+      return ctx->fail(MLQMC_EINVAL, "shift[%d] outside [0, 1)", j);
+  }
+  hipSetDevice(ctx->device);
+  const int64_t* dz;
+  const double* dsh;
+  double* dY;
+  CS(stage_in(ctx, "in_z", z, s, 0, &dz));
+  CS(stage_in(ctx, "in_shift", shift, s, 0, &dsh));
+  CS(out_buf(ctx, "out_Y", Y, (size_t)(count * s), on_dev, &dY));
+  CK(launch_lattice(N, s, dz, dsh, k0, count, dY, s, ctx->stream), "lattice");
+  CS(stage_out(ctx, Y, dY, (size_t)(count * s), on_dev));
+  return ctx->sync("lattice");
+}
+
+mlqmc_status mlqmc_coefficient(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B, const double* Y,
+                               double* aK, int32_t on_dev) {
+  if (!ctx) return MLQMC_EINVAL;
+  if (!is_pow2(n) || n < 2 || n > 4096) return ctx->fail(MLQMC_EINVAL, "n must be a power of two in [2, 4096]");
+  if (s < 0 || s > ctx->s_max) return ctx->fail(MLQMC_EINVAL, "s outside [0, s_max]");
+  if (B < 0 || (B > 0 && (!aK || (s > 0 && !Y)))) return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
+  if (!on_dev && B * s > 0 && !finite_host(Y, (size_t)(B * s)))
+    return ctx->fail(MLQMC_EINVAL, "Y has non-finite entries");
+  hipSetDevice(ctx->device);
+  Table* tb = nullptr;
+  CS(ctx->table(n, s, &tb));
+  const double* dY;
+  double* dA;
+  const int E = 2 * n * n;
+  CS(stage_in(ctx, "in_Y", Y, (size_t)(B * s), on_dev, &dY));
+  CS(out_buf(ctx, "out_a", aK, (size_t)(B * E), on_dev, &dA));
+  CK(launch_expand(B, s, E, dY, s, tb->el, ctx->a0, dA, ctx->stream), "expand");
+  CS(stage_out(ctx, aK, dA, (size_t)(B * E), on_dev));
+  return ctx->sync("coefficient");
+}
+
+mlqmc_status mlqmc_apply_operator(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B,
+                                  const double* Y, const double* sigma, const double* x,
+                                  double* out, int32_t on_dev) {
+  if (!ctx) return MLQMC_EINVAL;
+  if (!is_pow2(n) || n < 2 || n > 4096) return ctx->fail(MLQMC_EINVAL, "n must be a power of two in [2, 4096]");
+  if (s < 0 || s > ctx->s_max) return ctx->fail(MLQMC_EINVAL, "s outside [0, s_max]");
+  if (B < 0 || (B > 0 && (!sigma || !x || !out || (s > 0 && !Y))))
+    return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
+  hipSetDevice(ctx->device);
+  Table* tb = nullptr;
+  CS(ctx->table(n, s, &tb));
+  const int64_t D = (int64_t)(n - 1) * (n - 1), EW = 2LL * (n - 1) * n;
+  const double *dY, *dsg, *dx;
+  double *dout, *w;
+  CS(stage_in(ctx, "in_Y", Y, (size_t)(B * s), on_dev, &dY));
+  CS(stage_in(ctx, "in_sigma", sigma, (size_t)B, on_dev, &dsg));
+  CS(stage_in(ctx, "in_x", x, (size_t)(B * D), on_dev, &dx));
+  CS(out_buf(ctx, "out_x", out, (size_t)(B * D), on_dev, &dout));
+  CS(ctx->getT("op_w", (size_t)(B * EW), &w));
+  CK(launch_expand(B, s, (int)EW, dY, s, tb->edge, ctx->a0, w, ctx->stream), "expand");
+  CK(launch_apply_plain(n, B, w, dsg, dx, dout, ctx->stream), "apply");
+  CS(stage_out(ctx, out, dout, (size_t)(B * D), on_dev));
+  return ctx->sync("apply");
+}
+
+mlqmc_status mlqmc_prolong(mlqmc_ctx* ctx, int32_t nH, int32_t nh, int64_t B, const double* uH,
+                           double* uh, int32_t on_dev) {
+  if (!ctx) return MLQMC_EINVAL;
+  if (!is_pow2(nH) || !is_pow2(nh) || nH < 2 || nh < nH || nh > 4096)
+    return ctx->fail(MLQMC_EINVAL, "need powers of two 2 <= nH <= nh <= 4096");
+  if (B < 0 || (B > 0 && (!uH || !uh))) return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
+  hipSetDevice(ctx->device);
+  const int64_t DH = (int64_t)(nH - 1) * (nH - 1), Dh = (int64_t)(nh - 1) * (nh - 1);
+  const double* du;
+  double* dv;
+  CS(stage_in(ctx, "in_uH", uH, (size_t)(B * DH), on_dev, &du));
+  CS(out_buf(ctx, "out_uh", uh, (size_t)(B * Dh), on_dev, &dv));
+  if (B > 0 && Dh > 0) CK(launch_prolong(nH, nh, B, du, dv, ctx->stream), "prolong");
+  CS(stage_out(ctx, uh, dv, (size_t)(B * Dh), on_dev));
+  return ctx->sync("prolong");
+}
+
+mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* o,
+                             int64_t n, const double* Y, int32_t warm, double* lam,
+                             double* lam_prev, double* lam_coarse, int32_t* rq_iters,
+                             int32_t* lin_iters, uint8_t* flags) {
+  if (!ctx) return MLQMC_EINVAL;
+  CS(check_opts(ctx, o));
+  CS(check_level(ctx, L));
+  if (n < 0) return ctx->fail(MLQMC_EINVAL, "n < 0");
+  if (n > 0 && (!Y || !lam || !flags)) return ctx->fail(MLQMC_EINVAL, "NULL buffer");
+  if (n > 0 && L->n_prev && !lam_prev) return ctx->fail(MLQMC_EINVAL, "lam_prev is NULL but n_prev > 0");
+  const int dev = o->io_on_device;
+  const int64_t s = L->s_fine;
+  if (!dev && n * s > 0 && !finite_host(Y, (size_t)(n * s)))
+    return ctx->fail(MLQMC_EINVAL, "Y has non-finite entries");
+  ctx->mem_cap = o->device_mem_cap;
+  hipSetDevice(ctx->device);
+  if (n == 0) return MLQMC_OK;
+  const double* dY;
+  double *dl, *dlp = nullptr, *dlc = nullptr;
+  int *dri = nullptr, *dli = nullptr;
+  uint8_t* dfl;
+  CS(stage_in(ctx, "in_Y", Y, (size_t)(n * s), dev, &dY));
+  CS(out_buf(ctx, "o_lam", lam, n, dev, &dl));
+  if (L->n_prev) CS(out_buf(ctx, "o_lamp", lam_prev, n, dev, &dlp));
+  if (lam_coarse) CS(out_buf(ctx, "o_lamc", lam_coarse, n, dev, &dlc));
+  if (rq_iters) CS(out_buf(ctx, "o_rq", rq_iters, n, dev, &dri));
+  CS(out_buf(ctx, "o_li", lin_iters, n, dev && lin_iters, &dli));
+  CS(out_buf(ctx, "o_fl", flags, n, dev, &dfl));
+  CS(level_core(ctx, L, o, n, dY, s, warm, dl, dlp, dlc, dri, dli, dfl));
+  CS(stage_out(ctx, lam, dl, n, dev));
+  if (dlp) CS(stage_out(ctx, lam_prev, dlp, n, dev));
+  if (dlc) CS(stage_out(ctx, lam_coarse, dlc, n, dev));
+  if (dri) CS(stage_out(ctx, rq_iters, dri, n, dev));
+  if (lin_iters) CS(stage_out(ctx, lin_iters, dli, n, dev));
+  CS(stage_out(ctx, flags, dfl, n, dev));
+  CS(ctx->sync("eig_level"));
+  bool any = false;
+  CS(any_flag(ctx, dfl, n, &any));
+  return any ? ctx->fail(MLQMC_ENOCONV, "at least one sample is flagged") : MLQMC_OK;
+}
+
+mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, const int64_t* N,
+                            int32_t R, const int64_t* z, const double* shifts,
+                            const mlqmc_opts* o, double* Q_lr, double* Qhat, double* V,
+                            double* est) {
+  if (!ctx) return MLQMC_EINVAL;
+  CS(check_opts(ctx, o));
+  if (nl < 1 || !lv || !N || !z || !shifts || R < 1)
+    return ctx->fail(MLQMC_EINVAL, "need n_levels >= 1, R >= 1 and non-NULL inputs");
+  if (!Q_lr || !Qhat || !V || !est) return ctx->fail(MLQMC_EINVAL, "NULL output");
+  int64_t zoff = 0, soff = 0;
+  for (int l = 0; l < nl; ++l) {
+    CS(check_level(ctx, &lv[l]));
+    if (!is_pow2(N[l]) || N[l] > ((int64_t)1 << 30))
+      return ctx->fail(MLQMC_EINVAL, "N[%d] must be a power of two <= 2^30", l);
+    const int s = lv[l].s_fine;
+    for (int j = 0; j < s; ++j)
+      if (z[zoff + j] < 0 || z[zoff + j] >= N[l])
+        return ctx->fail(MLQMC_EINVAL, "z of level %d outside [0, N)", l);
+    for (int64_t k = 0; k < (int64_t)R * s; ++k)
+      if (!(shifts[soff + k] >= 0.0 && shifts[soff + k] < 1.0))
+        return ctx->fail(MLQMC_EINVAL, "shift of level %d outside [0, 1)", l);
+    zoff += s;
+    soff += (int64_t)R * s;
+  }
+  ctx->mem_cap = o->device_mem_cap;
+  hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+  const int dev = o->io_on_device;
+  double *dQ, *dQh, *dV, *dest;
+  CS(out_buf(ctx, "e_Q", Q_lr, (size_t)nl * R, dev, &dQ));
+  CS(out_buf(ctx, "e_Qh", Qhat, nl, dev, &dQh));
+  CS(out_buf(ctx, "e_V", V, nl, dev, &dV));
+  CS(out_buf(ctx, "e_est", est, 2, dev, &dest));
+  bool flagged = false;
+  zoff = soff = 0;
+  for (int l = 0; l < nl; ++l) {
+    const mlqmc_level& L = lv[l];
+    const int s = L.s_fine;
+    const int64_t n = (int64_t)R * N[l];
+    const int64_t *dz;
+    const double* dsh;
+    CS(stage_in(ctx, "e_z", z + zoff, s, 0, &dz));
+    CS(stage_in(ctx, "e_sh", shifts + soff, (size_t)R * s, 0, &dsh));
+    double *Y, *lam, *lamp = nullptr;
+    int *rqi, *lini;
+    uint8_t* fl;
+    CS(ctx->getT("e_Y", (size_t)(n * std::max(s, 1)), &Y));
+    CS(ctx->getT("e_lam", n, &lam));
+    if (L.n_prev) CS(ctx->getT("e_lamp", n, &lamp));
+    CS(ctx->getT("e_rq", n, &rqi));
+    CS(ctx->getT("e_li", n, &lini));
+    CS(ctx->getT("e_fl", n, &fl));
+    CK(launch_lattice_multi(N[l], s, R, dz, dsh, N[l], Y, std::max(s, 1), st), "lattice");
+    mlqmc_opts oo = *o;
+    // chains never cross a shift: chain length divides N_l
+    int chain = default_chain(N[l] * R, 1, o->chain_len);
+    int c2 = 1;
+    while (c2 < chain) c2 *= 2;
+    oo.chain_len = (int)std::min<int64_t>(c2, N[l]);
+    CS(level_core(ctx, &L, &oo, n, Y, std::max(s, 1), 1, lam, lamp, nullptr, rqi, lini, fl));
+    CK(launch_level_sums(N[l], R, lam, lamp, dQ + (int64_t)l * R, st), "level sums");
+    bool any = false;
+    CS(any_flag(ctx, fl, n, &any));
+    flagged |= any;
+    zoff += s;
+    soff += (int64_t)R * s;
+  }
+  CK(launch_estimator_final(nl, R, dQ, dQh, dV, dest, st), "estimator");
+  CS(stage_out(ctx, Q_lr, dQ, (size_t)nl * R, dev));
+  CS(stage_out(ctx, Qhat, dQh, nl, dev));
+  CS(stage_out(ctx, V, dV, nl, dev));
+  CS(stage_out(ctx, est, dest, 2, dev));
+  CS(ctx->sync("estimate"));
+  return flagged ? ctx->fail(MLQMC_ENOCONV, "at least one sample is flagged") : MLQMC_OK;
+}
+
+mlqmc_status mlqmc_set_timing(mlqmc_ctx* ctx, int32_t cls) {
+  if (!ctx) return MLQMC_EINVAL;
+  if (cls < MLQMC_K_NONE || cls > MLQMC_K_COARSE) return ctx->fail(MLQMC_EINVAL, "unknown kernel class");
+  ctx->timing_class = cls;
+  ctx->t_launches = 0;
+  ctx->t_ms = 0.0;
+  ctx->t_bytes = 0.0;
+  ctx->ev_used = 0;
+  return MLQMC_OK;
+}
+
+mlqmc_status mlqmc_get_timing(mlqmc_ctx* ctx, int64_t* launches, double* total_ms,
+                              double* model_bytes) {
+  if (!ctx) return MLQMC_EINVAL;
+  hipSetDevice(ctx->device);
+  CS(ctx->sync("timing"));
+  if (launches) *launches = ctx->t_launches;
+  if (total_ms) *total_ms = ctx->t_ms;
+  if (model_bytes) *model_bytes = ctx->t_bytes;
+  return MLQMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+// Per-sample LDS kernels: the warm-started Rayleigh-quotient eigensolve on a
+// coarse (or direct-level) mesh, the two-grid update on small fine meshes, and
+// the bottom of the batched V-cycle.  One workgroup owns one sample (or one
+// warm-start chain of samples) and keeps every vector in LDS.
+#include "../../include/mlqmc.h"
+#include "kernels.h"
+#include "lds_mg.h"
+
+namespace mlqmc {
+namespace {
+
+constexpr int kMaxStagedS = 512;
+
+template <int N>
+constexpr int threads_for() {
+  return N >= 32 ? 256 : (N >= 16 ? 128 : 64);
+}
+
+// v = sin(pi x1) sin(pi x2) at the interior nodes
+template <int NT, int n>
+__device__ __forceinline__ void init_sine(double* v) {
+  constexpr int m = n - 1, D = m * m;
+  for (int id = threadIdx.x; id < D; id += NT) {
+    const int i = id % m + 1, j = id / m + 1;
+    v[id] = sinpi(double(i) / n) * sinpi(double(j) / n);
+  }
+  __syncthreads();
+}
+
+// M-overlap of the M-normalised v with the normalised sine mode
+template <int NT, int n>
+__device__ __forceinline__ double sine_overlap(const double* v, double* red) {
+  constexpr int m = n - 1, D = m * m;
+  double s[2] = {0.0, 0.0};
+  for (int id = threadIdx.x; id < D; id += NT) {
+    const int i = id % m + 1, j = id / m + 1;
+    auto ph = [&](int a, int b) -> double {
+      return (a >= 1 && a <= m && b >= 1 && b <= m) ? sinpi(double(a) / n) * sinpi(double(b) / n)
+                                                     : 0.0;
+    };
+    const double p0 = ph(i, j);
+    const double mp = 6.0 * p0 + ph(i - 1, j) + ph(i + 1, j) + ph(i, j - 1) + ph(i, j + 1) +
+                      ph(i + 1, j + 1) + ph(i - 1, j - 1);
+    s[0] += v[id] * mp;
+    s[1] += p0 * mp;
+  }
+  block_sums<NT, 2>(s, red);
+  const double hm = mass_scale(n);
+  return fabs(s[0] * hm) / sqrt(s[1] * hm);
+}
+
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_rqi(RqiArgs A) {
+  using Mh = lds::Mesh<N>;
+  constexpr int D = Mh::D;
+  __shared__ double s_w[Mh::EW];
+  __shared__ double s_v[D], s_t[D], s_r[D], s_z[D], s_p[D], s_q[D];
+  __shared__ double s_mg[lds::mg_scratch<N>() + 1];
+  __shared__ double s_red[3 * (NT / 64)];
+  __shared__ double s_y[kMaxStagedS];
+  const lds::PcgArrays a{s_w, s_w + Mh::EX, s_v, s_t, s_r, s_z, s_p, s_q, s_mg, s_red};
+
+  const int64_t i0 = (int64_t)blockIdx.x * A.chain_len;
+  const int64_t i1 = (i0 + A.chain_len < A.n) ? i0 + A.chain_len : A.n;
+  bool have_prev = false;
+  for (int64_t i = i0; i < i1; ++i) {
+    for (int j = threadIdx.x; j < A.S; j += NT) s_y[j] = A.Y[i * A.ldY + j];
+    __syncthreads();
+    lds::weights_from_table<NT, N>(A.phi, s_y, A.S, A.a0, s_w);
+    lds::coarsen_all<NT, N>(a.wx, a.wy, s_mg);
+    if (!(A.warm && have_prev)) init_sine<NT, N>(s_v);
+
+    double vMv, vAv;
+    lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);
+    lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
+    double sigma = vAv / vMv;  // sigma_0 = A(t_k; v0, v0) for the M-normalised start
+
+    int rq = 0, lin = 0;
+    bool conv = false;
+    uint8_t fl = 0;
+    while (rq < A.max_rq) {
+      ++rq;
+      bool c, b;
+      lin += lds::jd_pcg<NT, N>(a, sigma, sigma, A.lin_rtol, A.max_lin, &c, &b);
+      for (int id = threadIdx.x; id < D; id += NT) s_v[id] += s_t[id];
+      __syncthreads();
+      lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);
+      lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
+      const double sig_new = vAv / vMv;
+      const bool done = fabs(sig_new - sigma) <= A.eig_rtol * fabs(sig_new);
+      sigma = sig_new;
+      if (!isfinite(sigma)) break;
+      if (done) {
+        conv = true;
+        break;
+      }
+    }
+    if (!conv) fl |= MLQMC_FLAG_RQ_NOCONV;
+    if (!isfinite(sigma)) fl |= MLQMC_FLAG_NONFINITE;
+    const double ov = sine_overlap<NT, N>(s_v, s_red);
+    if (!(ov >= 0.5)) fl |= MLQMC_FLAG_WRONG_PAIR;
+    if (threadIdx.x == 0) {
+      A.lam[i] = sigma;
+      if (A.rq_iters) A.rq_iters[i] = rq;
+      if (A.lin_iters) A.lin_iters[i] = lin;
+      A.flags[i] = fl;
+    }
+    if (A.u_out)
+      for (int id = threadIdx.x; id < D; id += NT) A.u_out[i * D + id] = s_v[id];
+    have_prev = (fl == 0);
+    __syncthreads();
+  }
+}
+
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_tg_small(TgSmallArgs A) {
+  using Mh = lds::Mesh<N>;
+  constexpr int m = N - 1, D = Mh::D;
+  __shared__ double s_w[Mh::EW];
+  __shared__ double s_v[D], s_t[D], s_r[D], s_z[D], s_p[D], s_q[D];
+  __shared__ double s_mg[lds::mg_scratch<N>() + 1];
+  __shared__ double s_red[3 * (NT / 64)];
+  __shared__ double s_y[kMaxStagedS];
+  const lds::PcgArrays a{s_w, s_w + Mh::EX, s_v, s_t, s_r, s_z, s_p, s_q, s_mg, s_red};
+  const int64_t i = blockIdx.x;
+  for (int j = threadIdx.x; j < A.s; j += NT) s_y[j] = A.Y[i * A.ldY + j];
+  __syncthreads();
+  lds::weights_from_table<NT, N>(A.phi, s_y, A.s, A.a0, s_w);
+  lds::coarsen_all<NT, N>(a.wx, a.wy, s_mg);
+  const int mH = A.nH - 1, ratio = N / A.nH;
+  const double* uH = A.uH + i * (int64_t)(mH * mH);
+  for (int id = threadIdx.x; id < D; id += NT) {
+    const int ii = id % m + 1, jj = id / m + 1;
+    s_v[id] = interp_coarse(uH, A.nH, ratio, ii, jj);
+  }
+  __syncthreads();
+  double vMv, vAv;
+  lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);
+  lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
+  const double rho = vAv / vMv;
+  const double mu = A.lamH[i];
+  bool c, b;
+  const int its = lds::jd_pcg<NT, N>(a, mu, rho, A.lin_rtol, A.max_lin, &c, &b);
+  for (int id = threadIdx.x; id < D; id += NT) s_v[id] += s_t[id];
+  __syncthreads();
+  lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);
+  const double lam = vAv / vMv;
+  if (threadIdx.x == 0) {
+    A.lam[i] = lam;
+    if (A.lin_iters) A.lin_iters[i] += its;
+    uint8_t fl = 0;
+    if (!c) fl |= MLQMC_FLAG_LIN_NOCONV;
+    if (b) fl |= MLQMC_FLAG_BREAKDOWN;
+    if (!isfinite(lam)) fl |= MLQMC_FLAG_NONFINITE;
+    A.flags[i] |= fl;
+  }
+}
+
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_bottom(const double* __restrict__ w,
+                                               const double* __restrict__ rhs,
+                                               double* __restrict__ X,
+                                               const uint8_t* __restrict__ active) {
+  using Mh = lds::Mesh<N>;
+  constexpr int D = Mh::D;
+  const int64_t b = blockIdx.x;
+  if (active && !active[b]) return;
+  __shared__ double s_w[Mh::EW];
+  __shared__ double s_b[D], s_x[D], s_r[D];
+  __shared__ double s_mg[lds::mg_scratch<N>() + 1];
+  for (int e = threadIdx.x; e < Mh::EW; e += NT) s_w[e] = w[b * Mh::EW + e];
+  for (int id = threadIdx.x; id < D; id += NT) s_b[id] = rhs[b * D + id];
+  __syncthreads();
+  lds::coarsen_all<NT, N>(s_w, s_w + Mh::EX, s_mg);
+  lds::vcycle<NT, N>(s_w, s_w + Mh::EX, s_b, s_x, s_r, s_mg);
+  for (int id = threadIdx.x; id < D; id += NT) X[b * D + id] = s_x[id];
+}
+
+template <int N>
+hipError_t rqi_n(const RqiArgs& a, hipStream_t st) {
+  constexpr int NT = threads_for<N>();
+  const int64_t chains = (a.n + a.chain_len - 1) / a.chain_len;
+  if (chains <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_rqi<N, NT>), dim3((unsigned)chains), dim3(NT), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t tg_small_n(const TgSmallArgs& a, hipStream_t st) {
+  constexpr int NT = threads_for<N>();
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_tg_small<N, NT>), dim3((unsigned)a.n), dim3(NT), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t bottom_n(int64_t B, const double* w, const double* rhs, double* X,
+                    const uint8_t* active, hipStream_t st) {
+  constexpr int NT = threads_for<N>();
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_bottom<N, NT>), dim3((unsigned)B), dim3(NT), 0, st, w, rhs, X, active);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st) {
+  if (a.S > kMaxStagedS) return hipErrorInvalidValue;
+  switch (N) {
+    case 4: return rqi_n<4>(a, st);
+    case 8: return rqi_n<8>(a, st);
+    case 16: return rqi_n<16>(a, st);
+    case 32: return rqi_n<32>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st) {
+  if (a.s > kMaxStagedS) return hipErrorInvalidValue;
+  switch (N) {
+    case 4: return tg_small_n<4>(a, st);
+    case 8: return tg_small_n<8>(a, st);
+    case 16: return tg_small_n<16>(a, st);
+    case 32: return tg_small_n<32>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bottom_vcycle(int NB, int64_t B, const double* w, const double* rhs, double* X,
+                                const uint8_t* active, hipStream_t st) {
+  switch (NB) {
+    case 4: return bottom_n<4>(B, w, rhs, X, active, st);
+    case 8: return bottom_n<8>(B, w, rhs, X, active, st);
+    case 16: return bottom_n<16>(B, w, rhs, X, active, st);
+    case 32: return bottom_n<32>(B, w, rhs, X, active, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mlqmc

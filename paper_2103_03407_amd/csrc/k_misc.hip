@@ -1,0 +1,209 @@
+// Lattice points (eq. rqmc / eq. t_kl), coefficient tables and expansion
+// (eq. coeff_s at element centroids), and the estimator reductions
+// (Algorithm 2, eq. sample_var, eq. ml-var).
+#include <math.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace mlqmc {
+namespace {
+
+// y = frac(((k z) mod N) / N + shift) - 1/2.  N is a power of two, so the
+// product reduction and the scaling by 1/N are exact; the shift is one
+// rounded add and the final -1/2 one rounded subtract.
+__device__ __forceinline__ double lattice_coord(int64_t k, int64_t z, int64_t N, double invN,
+                                                double shift) {
+  const int64_t mk = (k * z) & (N - 1);
+  const double t = (double)mk * invN;
+  double u = t + shift;
+  if (u >= 1.0) u -= 1.0;
+  return u - 0.5;
+}
+
+__global__ __launch_bounds__(256) void k_lattice(int64_t N, double invN, int s, int R,
+                                                 const int64_t* __restrict__ z,
+                                                 const double* __restrict__ shifts, int64_t k0,
+                                                 int64_t count, double* __restrict__ Y,
+                                                 int64_t ldY) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)R * count * s;
+  if (idx >= total) return;
+  const int j = (int)(idx % s);
+  const int64_t row = idx / s;  // r * count + i
+  const int r = (int)(row / count);
+  const int64_t i = row - (int64_t)r * count;
+  Y[row * ldY + j] = lattice_coord(k0 + i, z[j], N, invN, shifts[(int64_t)r * s + j]);
+}
+
+__global__ __launch_bounds__(256) void k_phi_elements(int n, int s, const double* __restrict__ c,
+                                                      const int* __restrict__ k1,
+                                                      const int* __restrict__ k2,
+                                                      double* __restrict__ phi) {
+  const int E = 2 * n * n;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (e >= E || j >= s) return;
+  const int sq = e >> 1, tri = e & 1;
+  const int i = sq % n, jj = sq / n;
+  // centroid: lower ((i+2/3)h, (j+1/3)h), upper ((i+1/3)h, (j+2/3)h)
+  const double xc = (double)(3 * i + (tri ? 1 : 2)) / (3.0 * n);
+  const double yc = (double)(3 * jj + (tri ? 2 : 1)) / (3.0 * n);
+  phi[(int64_t)j * E + e] = c[j] * sinpi((double)k1[j] * xc) * sinpi((double)k2[j] * yc);
+}
+
+// edge table: horizontal edge (i,j)-(i+1,j) touches lower(i,j) and upper(i,j-1);
+// vertical edge (i,j)-(i,j+1) touches upper(i,j) and lower(i-1,j)
+__global__ __launch_bounds__(256) void k_phi_edges(int n, int s, const double* __restrict__ pe,
+                                                   double* __restrict__ pw) {
+  const int E = 2 * n * n, m = n - 1, EX = (n - 1) * n, EW = 2 * EX;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (e >= EW || j >= s) return;
+  const double* el = pe + (int64_t)j * E;
+  double v;
+  if (e < EX) {
+    const int jr = e / n + 1, i = e % n;
+    v = 0.5 * (el[2 * (jr * n + i)] + el[2 * ((jr - 1) * n + i) + 1]);
+  } else {
+    const int f = e - EX;
+    const int jr = f / m, i = f % m + 1;
+    v = 0.5 * (el[2 * (jr * n + i) + 1] + el[2 * (jr * n + i - 1)]);
+  }
+  pw[(int64_t)j * EW + e] = v;
+}
+
+// out[b][e] = a0 + sum_j Y[b][j] phi[j][e]: 256 columns x 32 samples per block,
+// Y staged through LDS in chunks of 64 terms, phi streamed once per block.
+constexpr int kExpBS = 32, kExpJC = 64;
+__global__ __launch_bounds__(256) void k_expand(int64_t B, int s, int E,
+                                                const double* __restrict__ Y, int64_t ldY,
+                                                const double* __restrict__ phi, double a0,
+                                                double* __restrict__ out) {
+  __shared__ double ys[kExpBS][kExpJC];
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.y * kExpBS;
+  double acc[kExpBS];
+#pragma unroll
+  for (int k = 0; k < kExpBS; ++k) acc[k] = a0;
+  for (int j0 = 0; j0 < s; j0 += kExpJC) {
+    const int jc = (s - j0 < kExpJC) ? s - j0 : kExpJC;
+    for (int t = threadIdx.x; t < kExpBS * kExpJC; t += 256) {
+      const int bb = t / kExpJC, jj = t % kExpJC;
+      ys[bb][jj] = (b0 + bb < B && jj < jc) ? Y[(b0 + bb) * ldY + j0 + jj] : 0.0;
+    }
+    __syncthreads();
+    if (e < E) {
+      for (int jj = 0; jj < jc; ++jj) {
+        const double ph = phi[(int64_t)(j0 + jj) * E + e];
+#pragma unroll
+        for (int k = 0; k < kExpBS; ++k) acc[k] += ys[k][jj] * ph;
+      }
+    }
+    __syncthreads();
+  }
+  if (e < E) {
+#pragma unroll
+    for (int k = 0; k < kExpBS; ++k)
+      if (b0 + k < B) out[(b0 + k) * (int64_t)E + e] = acc[k];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_level_sums(int64_t N, const double* __restrict__ lam,
+                                                    const double* __restrict__ lam_prev,
+                                                    double* __restrict__ Q) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  const double* a = lam + (int64_t)r * N;
+  const double* p = lam_prev ? lam_prev + (int64_t)r * N : nullptr;
+  double s[1] = {0.0};
+  for (int64_t k = threadIdx.x; k < N; k += 256) s[0] += a[k] - (p ? p[k] : 0.0);
+  block_sums<256, 1>(s, red);
+  if (threadIdx.x == 0) Q[r] = s[0] / (double)N;
+}
+
+__global__ void k_estimator_final(int L, int R, const double* __restrict__ Q,
+                                  double* __restrict__ Qhat, double* __restrict__ V,
+                                  double* __restrict__ est) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double qml = 0.0, vml = 0.0;
+  for (int l = 0; l < L; ++l) {
+    double s = 0.0;
+    for (int r = 0; r < R; ++r) s += Q[l * R + r];
+    const double qh = s / R;
+    double v = NAN;
+    if (R > 1) {
+      double d = 0.0;
+      for (int r = 0; r < R; ++r) d += (qh - Q[l * R + r]) * (qh - Q[l * R + r]);
+      v = d / ((double)R * (R - 1));
+    }
+    Qhat[l] = qh;
+    V[l] = v;
+    qml += qh;
+    vml += v;
+  }
+  est[0] = qml;
+  est[1] = vml;
+}
+
+}  // namespace
+
+hipError_t launch_lattice(int64_t N, int s, const int64_t* z_dev, const double* shift_dev,
+                          int64_t k0, int64_t count, double* Y, int64_t ldY, hipStream_t st) {
+  const int64_t total = count * s;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lattice, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, N,
+                     ldexp(1.0, -(int)log2((double)N)), s, 1, z_dev, shift_dev, k0, count, Y, ldY);
+  return hipGetLastError();
+}
+
+hipError_t launch_lattice_multi(int64_t N, int s, int R, const int64_t* z_dev,
+                                const double* shifts_dev, int64_t count, double* Y,
+                                int64_t ldY, hipStream_t st) {
+  const int64_t total = (int64_t)R * count * s;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lattice, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, N,
+                     ldexp(1.0, -(int)log2((double)N)), s, R, z_dev, shifts_dev, (int64_t)0,
+                     count, Y, ldY);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_elements(int n, int s, const double* c, const int* k1, const int* k2,
+                               double* phi, hipStream_t st) {
+  if (s <= 0) return hipSuccess;
+  const int E = 2 * n * n;
+  hipLaunchKernelGGL(k_phi_elements, dim3((E + 255) / 256, s), dim3(256), 0, st, n, s, c, k1, k2,
+                     phi);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_edges(int n, int s, const double* phi_el, double* phi_edge,
+                            hipStream_t st) {
+  if (s <= 0) return hipSuccess;
+  const int EW = 2 * (n - 1) * n;
+  hipLaunchKernelGGL(k_phi_edges, dim3((EW + 255) / 256, s), dim3(256), 0, st, n, s, phi_el,
+                     phi_edge);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(int64_t B, int s, int E, const double* Y, int64_t ldY,
+                         const double* phi, double a0, double* out, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand, dim3((E + 255) / 256, (unsigned)((B + kExpBS - 1) / kExpBS)),
+                     dim3(256), 0, st, B, s, E, Y, ldY, phi, a0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_sums(int64_t N, int R, const double* lam, const double* lam_prev,
+                             double* Q, hipStream_t st) {
+  hipLaunchKernelGGL(k_level_sums, dim3(R), dim3(256), 0, st, N, lam, lam_prev, Q);
+  return hipGetLastError();
+}
+
+hipError_t launch_estimator_final(int L, int R, const double* Q, double* Qhat, double* V,
+                                  double* est, hipStream_t st) {
+  hipLaunchKernelGGL(k_estimator_final, dim3(1), dim3(64), 0, st, L, R, Q, Qhat, V, est);
+  return hipGetLastError();
+}
+
+}  // namespace mlqmc

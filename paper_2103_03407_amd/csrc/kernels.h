@@ -1,0 +1,132 @@
+// Launch wrappers of the HIP kernels (host side).  Every wrapper enqueues on
+// `st` and returns the hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mlqmc {
+
+// ---------------- per-sample LDS kernels (meshes 1/4 .. 1/32) ----------------
+
+struct RqiArgs {
+  const double* Y;      // points [n x ldY]; the first S columns are used
+  int64_t ldY;
+  int S;
+  const double* phi;    // edge table [>=S][EW] of the mesh
+  double a0;
+  int64_t n;            // samples
+  int chain_len;        // samples per warm-start chain (one workgroup per chain)
+  int warm;             // 1: start from the previous sample's eigenvector
+  double eig_rtol;
+  int max_rq;
+  double lin_rtol;
+  int max_lin;
+  double* lam;          // [n] converged Rayleigh quotient
+  double* u_out;        // [n x D] M-normalised eigenvectors, or nullptr
+  int* rq_iters;        // [n] or nullptr
+  int* lin_iters;       // [n] or nullptr
+  uint8_t* flags;       // [n]
+};
+hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st);
+
+struct TgSmallArgs {
+  const double* Y;      // [n x ldY], first s columns
+  int64_t ldY;
+  int s;
+  const double* phi;    // edge table [>=s][EW] of the fine mesh
+  double a0;
+  const double* uH;     // [n x DH] coarse eigenvectors
+  const double* lamH;   // [n]
+  int nH;               // coarse mesh
+  int64_t n;
+  double lin_rtol;
+  int max_lin;
+  double* lam;          // [n] two-grid value
+  int* lin_iters;       // [n] added to, or nullptr
+  uint8_t* flags;       // [n] OR-ed
+};
+hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st);
+
+// One V-cycle X = K^{-1} B per active sample on mesh NB <= 32 (weights given).
+hipError_t launch_bottom_vcycle(int NB, int64_t B, const double* w, const double* rhs, double* X,
+                                const uint8_t* active, hipStream_t st);
+
+// ---------------- batched fine-mesh kernels (grid = blocks x samples) ----------------
+
+constexpr int kFineNT = 256;
+
+struct FineState {      // per-sample scalars of the projected PCG, arrays of length B
+  double *mu, *vs, *rho, *rz, *rz0, *alpha, *c, *c2, *beta, *lam;
+  int* its;
+  int* lin_acc;         // per-sample PCG iteration totals, added to at the end (or nullptr)
+  uint8_t* active;
+  uint8_t* flags;
+};
+
+inline int fine_blocks(int D) { return (D + kFineNT - 1) / kFineNT; }
+
+hipError_t launch_prolong(int nH, int nh, int64_t B, const double* uH, double* uh,
+                          hipStream_t st);
+hipError_t launch_coarsen(int n, int64_t B, const double* w, double* wc, hipStream_t st);
+hipError_t launch_setup_dots(int n, int64_t B, const double* v, const double* w, double* part,
+                             hipStream_t st);
+hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w,
+                            const FineState& S, double* r, double* t, double* zb,
+                            hipStream_t st);
+hipError_t launch_apply_dots(int n, int64_t B, const double* p, const double* v, const double* w,
+                             const FineState& S, double* q, double* part, hipStream_t st);
+hipError_t launch_update(int n, int64_t B, const double* p, const double* q, const double* v,
+                         const double* w, const FineState& S, double* t, double* r, double* zb,
+                         hipStream_t st);
+hipError_t launch_jacobi_first(int n, int64_t B, const double* w, const double* rhs, double* X,
+                               const uint8_t* active, hipStream_t st);
+hipError_t launch_jacobi(int n, int64_t B, const double* w, const double* rhs, const double* Xin,
+                         double* Xout, const uint8_t* active, hipStream_t st);
+hipError_t launch_resid_restrict(int n, int64_t B, const double* w, const double* rhs,
+                                 const double* X, double* rhs_c, const uint8_t* active,
+                                 hipStream_t st);
+hipError_t launch_prolong_add(int n, int64_t B, const double* Xc, double* X,
+                              const uint8_t* active, hipStream_t st);
+hipError_t launch_dots3(int n, int64_t B, const double* r, const double* z, const double* v,
+                        const FineState& S, double* part, hipStream_t st);
+hipError_t launch_pupdate(int n, int64_t B, const double* z, const double* v,
+                          const FineState& S, double* p, hipStream_t st);
+hipError_t launch_final_dots(int n, int64_t B, const double* v, const double* t,
+                             const double* w, const FineState& S, double* part, hipStream_t st);
+
+// scalar phases: one wavefront per sample sums that sample's block partials
+enum ScalarPhase { PH_SETUP = 0, PH_FIRST_RZ = 1, PH_ALPHA = 2, PH_BETA = 3, PH_FINAL = 4 };
+hipError_t launch_scalar(int phase, int n, int64_t B, int nblk, const double* part,
+                         const FineState& S, double rtol, int max_it, hipStream_t st);
+
+// plain operator apply out = (A - sigma M) x for the component entry point
+hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* sigma,
+                              const double* x, double* out, hipStream_t st);
+
+// ---------------- points, tables, coefficient expansion, estimator ----------------
+
+hipError_t launch_lattice(int64_t N, int s, const int64_t* z_dev, const double* shift_dev,
+                          int64_t k0, int64_t count, double* Y, int64_t ldY, hipStream_t st);
+// lattice points for R shifts at once: Y[(r*count + i) * ldY + j]
+hipError_t launch_lattice_multi(int64_t N, int s, int R, const int64_t* z_dev,
+                                const double* shifts_dev, int64_t count, double* Y,
+                                int64_t ldY, hipStream_t st);
+// element table phi[j][e] = c_j sin(pi k1_j xc_e) sin(pi k2_j yc_e), e < 2n^2
+hipError_t launch_phi_elements(int n, int s, const double* c, const int* k1, const int* k2,
+                               double* phi, hipStream_t st);
+// edge table: the mean of the element table over the two elements of each leg
+hipError_t launch_phi_edges(int n, int s, const double* phi_el, double* phi_edge,
+                            hipStream_t st);
+// out[b][e] = a0 + sum_{j<s} Y[b][j] phi[j][e], e < E
+hipError_t launch_expand(int64_t B, int s, int E, const double* Y, int64_t ldY,
+                         const double* phi, double a0, double* out, hipStream_t st);
+// Q[l*R + r] = (1/N) sum_k (lam[r*N + k] - lam_prev[r*N + k]) (fixed-order tree);
+// lam_prev may be nullptr (lambda^{-1} = 0)
+hipError_t launch_level_sums(int64_t N, int R, const double* lam, const double* lam_prev,
+                             double* Q, hipStream_t st);
+// Qhat, V, est from Q [L x R]
+hipError_t launch_estimator_final(int L, int R, const double* Q, double* Qhat, double* V,
+                                  double* est, hipStream_t st);
+
+}  // namespace mlqmc
