@@ -64,6 +64,13 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with "
                            "`python -m paper_2103_03407_amd.build` (no CPU fallback exists)")
+    # One HIP runtime per process: torch ships its own libamdhip64 (same
+    # SONAME); importing torch first makes this library bind to that copy
+    # instead of loading a second runtime that would not see the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name in EXPORTS:
         getattr(lib, name)  # AttributeError if absent
