@@ -37,6 +37,8 @@ def _parse():
                     choices=["smooth", "apply", "coeff"], help="kernel timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES bytes (counter calibration)")
     return ap.parse_args()
 
 
@@ -106,6 +108,16 @@ def main():
         return 2
     import numpy as np
     import torch
+    if a.copy_probe:
+        # plain copy kernel of known size: calibrates the HBM byte counters
+        n = a.copy_probe // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 8 * n, "copies": 3}), flush=True)
+        return 0
     import paper_2103_03407_amd as m
     from synth import CONFIGS
 
