@@ -35,6 +35,8 @@ def _parse():
     ap.add_argument("--cfg", type=int, default=2, help="workload id (2: two-grid 1/32->1/128)")
     ap.add_argument("--kernel-class", default="smooth",
                     choices=["smooth", "apply", "coeff"], help="kernel timed for the roofline")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"],
+                    help="fp64, or mixed (FP32 fine PCG/V-cycle, FP64 residual and RQ)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -130,7 +132,7 @@ def main():
     ctx = m.Context(fam, device=0)
     z, sh = w.z(0), w.shifts(0)
     level = (lv.n_fine, lv.s_fine, lv.n_coarse, lv.s_coarse, lv.n_prev, lv.s_prev)
-    opts = m.default_opts()
+    opts = m.default_opts(prec=m.MLQMC_MIXED if a.prec == "mixed" else m.MLQMC_FP64)
     n_samples = w.R * lv.N
 
     def step():
@@ -171,10 +173,11 @@ def main():
         cpu = cpu_baseline(a.cfg, a.cpu_seconds)
 
     out = {
-        "metric": "two-grid eigen-samples/sec per level (FP64 path); stencil HBM GB/s in roofline",
+        "metric": "two-grid eigen-samples/sec per level; stencil HBM GB/s in roofline",
         "value": round(value, 1), "unit": "samples/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if a.prec == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": w.name, "h": f"1/{lv.n_fine}", "H": f"1/{lv.n_coarse}",
                    "s": lv.s_fine, "S": lv.s_coarse, "N": lv.N, "R": w.R,
                    "samples_per_step": n_samples, "estimate": est[0]},

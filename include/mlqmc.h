@@ -94,7 +94,7 @@ typedef struct {
 } mlqmc_opts;
 
 /* Fills *opt with the defaults (FP64, eig_rtol 1e-8, max_rq_iter 12,
- * lin_rtol 1e-7, rq_lin_rtol 1e-4, max_lin_iter 60, io_on_device 0). */
+ * lin_rtol 1e-6, rq_lin_rtol 1e-4, max_lin_iter 60, io_on_device 0). */
 void mlqmc_default_opts(mlqmc_opts* opt);
 
 /* Creates a context on HIP device `device`, enqueueing on `hip_stream`

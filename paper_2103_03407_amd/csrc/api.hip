@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mlqmc.h"
@@ -29,7 +30,8 @@ struct DevBuf {
 struct Table {
   int s = 0;
   double* el = nullptr;    // [s][2n^2]
-  double* edge = nullptr;  // [s][2(n-1)n]
+  double* edge = nullptr;  // [s][2(n-1)n]   interior-layout edge weights (LDS kernels)
+  double* pad = nullptr;   // [s][2(n+2)n]   padded [WX | WY] edge weights (batched kernels)
 };
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
@@ -112,22 +114,27 @@ struct mlqmc_ctx {
   mlqmc_status table(int n, int s, Table** out) {
     Table& t = tables[n];
     if (t.s < s || !t.el) {
+      const int64_t per_row = (int64_t)2 * n * n + 2 * (n - 1) * n + 2 * padded_size(n);
       if (t.el) hipFree(t.el);
       if (t.edge) hipFree(t.edge);
-      bytes_alloc -= (int64_t)(t.s) * (2 * n * n + 2 * (n - 1) * n) * 8;
-      t.el = t.edge = nullptr;
+      if (t.pad) hipFree(t.pad);
+      bytes_alloc -= (int64_t)t.s * per_row * 8;
+      t.el = t.edge = t.pad = nullptr;
       t.s = 0;
       const int srows = std::max(s, 1);
-      const size_t be = (size_t)srows * 2 * n * n * 8, bw = (size_t)srows * 2 * (n - 1) * n * 8;
-      if (mem_cap > 0 && bytes_alloc + (int64_t)(be + bw) > mem_cap)
+      const size_t be = (size_t)srows * 2 * n * n * 8, bw = (size_t)srows * 2 * (n - 1) * n * 8,
+                   bp = (size_t)srows * 2 * padded_size(n) * 8;
+      if (mem_cap > 0 && bytes_alloc + (int64_t)(be + bw + bp) > mem_cap)
         return fail(MLQMC_ENOMEM, "coefficient table for n=%d exceeds the device memory cap", n);
       hipError_t e = hipMalloc(&t.el, be);
       if (e == hipSuccess) e = hipMalloc(&t.edge, bw);
+      if (e == hipSuccess) e = hipMalloc(&t.pad, bp);
       if (e != hipSuccess) return fail(MLQMC_ENOMEM, "table allocation: %s", hipGetErrorString(e));
-      bytes_alloc += (int64_t)(be + bw);
+      bytes_alloc += (int64_t)(be + bw + bp);
       t.s = srows;
       e = launch_phi_elements(n, srows, d_c, d_k1, d_k2, t.el, stream);
       if (e == hipSuccess) e = launch_phi_edges(n, srows, t.el, t.edge, stream);
+      if (e == hipSuccess) e = launch_phi_edges_padded(n, srows, t.el, t.pad, stream);
       if (e != hipSuccess) return hip_fail(e, "coefficient tables");
     }
     *out = &t;
@@ -217,8 +224,6 @@ mlqmc_status check_opts(mlqmc_ctx* ctx, const mlqmc_opts* o) {
   if (!o) return ctx->fail(MLQMC_EINVAL, "opts is NULL");
   if (o->prec != MLQMC_FP64 && o->prec != MLQMC_MIXED)
     return ctx->fail(MLQMC_EINVAL, "unknown precision %d", o->prec);
-  if (o->prec == MLQMC_MIXED)
-    return ctx->fail(MLQMC_EINVAL, "mixed precision is not available in this build");
   if (!(o->eig_rtol > 0) || !(o->lin_rtol > 0) || !(o->rq_lin_rtol > 0))
     return ctx->fail(MLQMC_EINVAL, "tolerances must be positive");
   if (o->max_rq_iter < 1 || o->max_lin_iter < 1)
@@ -267,57 +272,78 @@ int default_chain(int64_t n, int warm, int chain_len) {
   return (int)std::max<int64_t>(1, c);
 }
 
-struct FineBufs {
-  int nh, nb;  // fine mesh, bottom mesh (<= 32)
-  std::vector<int> lv_n;  // batched levels: nh, nh/2, ..., > 32
-};
-
-// Two-grid update on mesh nh (>= 64) for n samples, batched.
+// Two-grid update on mesh nh (>= 64) for n samples, batched.  T is the
+// storage type of the projected PCG and the V-cycle (double; float in mixed
+// precision); the right-hand side and the Rayleigh quotient are FP64.
+template <typename T>
 mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, const double* Y,
                           int64_t ldY, const double* uH, const double* lamH, int nH, int64_t n,
                           double* lam, int* lin_iters, uint8_t* flags, const char* tag) {
+  constexpr bool kMixed = std::is_same<T, float>::value;
   Table* tb = nullptr;
   CS(ctx->table(nh, s, &tb));
-  // levels
   std::vector<int> lv;
   for (int m = nh; m > 32; m /= 2) lv.push_back(m);
   const int nb = 32;
-  auto D = [](int m) { return (int64_t)(m - 1) * (m - 1); };
-  auto EW = [](int m) { return (int64_t)2 * (m - 1) * m; };
-  int64_t per_sample = 8 * (EW(nh) + 7 * D(nh));
-  for (size_t k = 1; k < lv.size(); ++k) per_sample += 8 * (EW(lv[k]) + 3 * D(lv[k]));
-  per_sample += 8 * (EW(nb) + 2 * D(nb));
+  const size_t nL = lv.size();
+  auto D = [](int m) { return (int64_t)(m - 1) * (m - 1); };  // interior nodes (coarse uH)
+  auto P = [](int m) { return padded_size(m); };                // padded vector
+  auto EW = [](int m) { return 2 * padded_size(m); };           // padded [WX | WY]
+  const int64_t sz = (int64_t)sizeof(T);
+  int64_t per_sample = 8 * (EW(nh) + 2 * P(nh)) + sz * (9 * P(nh)) + (kMixed ? 4 * EW(nh) : 0);
+  for (size_t k = 1; k < nL; ++k) per_sample += sz * (EW(lv[k]) + 3 * P(lv[k]));
+  per_sample += sz * (EW(nb) + 2 * P(nb));
   int64_t batch = o->batch > 0 ? o->batch : std::max<int64_t>(1, (int64_t)16e9 / per_sample);
   batch = std::min<int64_t>(batch, n);
-  batch = std::min<int64_t>(batch, 65535);
-  const int nblk0 = fine_blocks((int)D(nh));
+  const int nblk0 = march_blocks(nh);
 
   std::string p = tag;
   auto nm = [&](const char* x) { return p + x; };
-  double *w0, *v, *t, *r, *z, *zb, *pp, *q, *part;
-  CS(ctx->getT(nm("w0").c_str(), batch * EW(nh), &w0));
-  CS(ctx->getT(nm("v").c_str(), batch * D(nh), &v));
-  CS(ctx->getT(nm("t").c_str(), batch * D(nh), &t));
-  CS(ctx->getT(nm("r").c_str(), batch * D(nh), &r));
-  CS(ctx->getT(nm("z").c_str(), batch * D(nh), &z));
-  CS(ctx->getT(nm("zb").c_str(), batch * D(nh), &zb));
-  CS(ctx->getT(nm("p").c_str(), batch * D(nh), &pp));
-  CS(ctx->getT(nm("q").c_str(), batch * D(nh), &q));
+  double *w64, *v64, *part;
+  T *wT, *vn, *mvn, *t, *r, *z, *zb, *q, *pp[2];
+  CS(ctx->getT(nm("w64").c_str(), batch * EW(nh), &w64));
+  if constexpr (kMixed) {
+    CS(ctx->getT(nm("w32").c_str(), batch * EW(nh), &wT));
+  } else {
+    wT = w64;
+  }
+  CS(ctx->getT(nm("v64").c_str(), batch * P(nh), &v64));
   CS(ctx->getT(nm("part").c_str(), batch * nblk0 * 3, &part));
-  std::vector<double*> W(lv.size() + 1), X(lv.size() + 1), Xb(lv.size() + 1), Bv(lv.size() + 1);
-  W[0] = w0;
-  for (size_t k = 1; k <= lv.size(); ++k) {
-    const int m = (k < lv.size()) ? lv[k] : nb;
+  const char* vnames[] = {"vn", "t", "r", "z", "zb", "q", "p0", "p1", "mvn"};
+  T** vptr[] = {&vn, &t, &r, &z, &zb, &q, &pp[0], &pp[1], &mvn};
+  for (int k = 0; k < 9; ++k) {
+    std::string key = nm(vnames[k]) + (kMixed ? "_f" : "_d");
+    CS(ctx->getT(key.c_str(), batch * P(nh), vptr[k]));
+  }
+  std::vector<T*> W(nL + 1), X(nL + 1), Xb(nL + 1), Bv(nL + 1);
+  W[0] = wT;
+  for (size_t k = 1; k <= nL; ++k) {
+    const int m = (k < nL) ? lv[k] : nb;
     char b1[64];
-    snprintf(b1, sizeof b1, "w%zu", k);
+    const char* sfx = kMixed ? "f" : "d";
+    snprintf(b1, sizeof b1, "w%zu%s", k, sfx);
     CS(ctx->getT(nm(b1).c_str(), batch * EW(m), &W[k]));
-    snprintf(b1, sizeof b1, "X%zu", k);
-    CS(ctx->getT(nm(b1).c_str(), batch * D(m), &X[k]));
-    snprintf(b1, sizeof b1, "B%zu", k);
-    CS(ctx->getT(nm(b1).c_str(), batch * D(m), &Bv[k]));
-    if (k < lv.size()) {
-      snprintf(b1, sizeof b1, "Xb%zu", k);
-      CS(ctx->getT(nm(b1).c_str(), batch * D(m), &Xb[k]));
+    snprintf(b1, sizeof b1, "X%zu%s", k, sfx);
+    CS(ctx->getT(nm(b1).c_str(), batch * P(m), &X[k]));
+    snprintf(b1, sizeof b1, "B%zu%s", k, sfx);
+    CS(ctx->getT(nm(b1).c_str(), batch * P(m), &Bv[k]));
+    if (k < nL) {
+      snprintf(b1, sizeof b1, "Xb%zu%s", k, sfx);
+      CS(ctx->getT(nm(b1).c_str(), batch * P(m), &Xb[k]));
+    }
+  }
+  // Dirichlet positions of every padded vector are zero and stay zero: the
+  // kernels write interior positions only.
+  {
+    hipStream_t st = ctx->stream;
+    void* top[] = {vn, t, r, z, zb, q, pp[0], pp[1], mvn};
+    CK(launch_zero_boundary(nh, batch, top, 9, (int)sz, st), "zero boundary");
+    void* v64p[] = {v64};
+    CK(launch_zero_boundary(nh, batch, v64p, 1, 8, st), "zero boundary");
+    for (size_t k = 1; k <= nL; ++k) {
+      const int m = (k < nL) ? lv[k] : nb;
+      void* lp[] = {X[k], Bv[k], k < nL ? (void*)Xb[k] : (void*)X[k]};
+      CK(launch_zero_boundary(m, batch, lp, 3, (int)sz, st), "zero boundary");
     }
   }
   double* sc = nullptr;
@@ -328,7 +354,6 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   CS(ctx->getT(nm("active").c_str(), batch, &active));
   std::vector<uint8_t> h_active(batch);
 
-  const size_t nL = lv.size();
   for (int64_t b0 = 0; b0 < n; b0 += batch) {
     const int64_t Bn = std::min<int64_t>(batch, n - b0);
     FineState S{};
@@ -347,62 +372,60 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     S.active = active;
     S.flags = flags + b0;
     hipStream_t st = ctx->stream;
+    const uint8_t* act = active;
 
-    // coefficient expansion straight into edge weights, then the coarser levels
+    // coefficient expansion straight into FP64 edge weights, the storage copy, coarser levels
     ctx->t_begin(MLQMC_K_COEFF);
-    CK(launch_expand(Bn, s, (int)EW(nh), Y + b0 * ldY, ldY, tb->edge, ctx->a0, w0, st), "expand");
+    CK(launch_expand(Bn, s, (int)EW(nh), Y + b0 * ldY, ldY, tb->pad, ctx->a0, w64, st), "expand");
     ctx->t_end(MLQMC_K_COEFF, 8.0 * ((double)Bn * s + (double)s * EW(nh) + (double)Bn * EW(nh)));
-    for (size_t k = 0; k < nL; ++k) CK(launch_coarsen(lv[k], Bn, W[k], W[k + 1], st), "coarsen");
+    if constexpr (kMixed) CK(launch_to_float(Bn * EW(nh), w64, wT, st), "to float");
+    for (size_t k = 0; k < nL; ++k) CK(launch_coarsen<T>(lv[k], Bn, W[k], W[k + 1], st), "coarsen");
 
-    CK(launch_prolong(nH, nh, Bn, uH + b0 * D(nH), v, st), "prolong");
-    CK(launch_setup_dots(nh, Bn, v, w0, part, st), "setup dots");
+    CK(launch_prolong(nH, nh, Bn, uH + b0 * D(nH), v64, st), "prolong");
+    CK(launch_setup_dots(nh, Bn, v64, w64, part, st), "setup dots");
     CK(launch_scalar(PH_SETUP, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
-    CK(launch_setup_rhs(nh, Bn, v, w0, S, r, t, zb, st), "setup rhs");
+    CK(launch_setup_rhs<T>(nh, Bn, v64, w64, wT, S, r, t, zb, vn, mvn, st), "setup rhs");
 
-    // remainder of the V-cycle on level 0 (first sweep already in zb): z = K^{-1} r
-    auto vcycle_rest = [&]() -> mlqmc_status {
-      const uint8_t* act = active;
-      const double jb = 8.0 * (double)Bn * (3 * D(nh) + EW(nh));
+    // z = K^{-1} r: the first level-0 sweep is already in zb; the last one
+    // also forms the partial dot products r.z, M vn.z, r.vn
+    // algorithmic bytes: x, rhs, x out on the interior nodes, the 2 edge weights per node
+    const double jb = (double)sz * Bn * (5 * D(nh));
+    auto vcycle = [&]() -> mlqmc_status {
       ctx->t_begin(MLQMC_K_SMOOTH);
-      CK(launch_jacobi(nh, Bn, w0, r, zb, z, act, st), "jacobi");
+      CK(launch_jacobi<T>(nh, Bn, wT, r, zb, nullptr, z, act, st), "jacobi");
       ctx->t_end(MLQMC_K_SMOOTH, jb);
-      CK(launch_resid_restrict(nh, Bn, w0, r, z, Bv[1], act, st), "restrict");
+      CK(launch_resid_restrict<T>(nh, Bn, wT, r, z, Bv[1], act, st), "restrict");
       for (size_t k = 1; k < nL; ++k) {
-        CK(launch_jacobi_first(lv[k], Bn, W[k], Bv[k], Xb[k], act, st), "jacobi0");
-        CK(launch_jacobi(lv[k], Bn, W[k], Bv[k], Xb[k], X[k], act, st), "jacobi");
-        CK(launch_resid_restrict(lv[k], Bn, W[k], Bv[k], X[k], Bv[k + 1], act, st), "restrict");
+        CK(launch_jacobi_first<T>(lv[k], Bn, W[k], Bv[k], Xb[k], act, st), "jacobi0");
+        CK(launch_jacobi<T>(lv[k], Bn, W[k], Bv[k], Xb[k], nullptr, X[k], act, st), "jacobi");
+        CK(launch_resid_restrict<T>(lv[k], Bn, W[k], Bv[k], X[k], Bv[k + 1], act, st), "restrict");
       }
-      CK(launch_bottom_vcycle(nb, Bn, W[nL], Bv[nL], X[nL], act, st), "bottom");
+      CK(launch_bottom_vcycle<T>(nb, Bn, W[nL], Bv[nL], X[nL], act, st), "bottom");
       for (size_t k = nL - 1; k >= 1; --k) {
-        CK(launch_prolong_add(lv[k], Bn, X[k + 1], X[k], act, st), "prolong add");
-        CK(launch_jacobi(lv[k], Bn, W[k], Bv[k], X[k], Xb[k], act, st), "jacobi");
-        CK(launch_jacobi(lv[k], Bn, W[k], Bv[k], Xb[k], X[k], act, st), "jacobi");
+        CK(launch_jacobi<T>(lv[k], Bn, W[k], Bv[k], X[k], X[k + 1], Xb[k], act, st), "jacobi");
+        CK(launch_jacobi<T>(lv[k], Bn, W[k], Bv[k], Xb[k], nullptr, X[k], act, st), "jacobi");
       }
-      CK(launch_prolong_add(nh, Bn, X[1], z, act, st), "prolong add");
-      ctx->t_begin(MLQMC_K_SMOOTH);
-      CK(launch_jacobi(nh, Bn, w0, r, z, zb, act, st), "jacobi");
-      ctx->t_end(MLQMC_K_SMOOTH, jb);
-      ctx->t_begin(MLQMC_K_SMOOTH);
-      CK(launch_jacobi(nh, Bn, w0, r, zb, z, act, st), "jacobi");
-      ctx->t_end(MLQMC_K_SMOOTH, jb);
+      CK(launch_jacobi<T>(nh, Bn, wT, r, z, X[1], zb, act, st), "jacobi");
+      CK(launch_jacobi_dots<T>(nh, Bn, wT, r, zb, vn, mvn, S, z, part, st), "jacobi dots");
       return MLQMC_OK;
     };
-    CS(vcycle_rest());
-    CK(launch_dots3(nh, Bn, r, z, v, S, part, st), "dots3");
+    CS(vcycle());
+    all_active = false;
     CK(launch_scalar(PH_FIRST_RZ, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
-    CK(launch_pupdate(nh, Bn, z, v, S, pp, st), "pupdate");
-    const double ab = 8.0 * (double)Bn * (3 * D(nh) + EW(nh));
+    const double ab = (double)sz * Bn * (7 * D(nh));
+    int cur = 0;
     for (int it = 0; it < o->max_lin_iter; ++it) {
-      ctx->t_begin(MLQMC_K_APPLY);
-      CK(launch_apply_dots(nh, Bn, pp, v, w0, S, q, part, st), "apply");
-      ctx->t_end(MLQMC_K_APPLY, ab);
+      if (it == 0) ctx->t_begin(MLQMC_K_APPLY);
+      CK(launch_pupdate_apply<T>(nh, Bn, z, vn, pp[cur], mvn, wT, S, it == 0, pp[1 - cur], q, part,
+                                 st),
+         "apply");
+      if (it == 0) ctx->t_end(MLQMC_K_APPLY, ab);
+      cur = 1 - cur;
       CK(launch_scalar(PH_ALPHA, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
-      CK(launch_update(nh, Bn, pp, q, v, w0, S, t, r, zb, st), "update");
-      CS(vcycle_rest());
-      CK(launch_dots3(nh, Bn, r, z, v, S, part, st), "dots3");
+      CK(launch_update<T>(nh, Bn, pp[cur], q, mvn, wT, S, t, r, zb, st), "update");
+      CS(vcycle());
       CK(launch_scalar(PH_BETA, nh, Bn, nblk0, part, S, o->lin_rtol, o->max_lin_iter, st),
          "scalar");
-      CK(launch_pupdate(nh, Bn, z, v, S, pp, st), "pupdate");
       if (it % 3 == 2 || it + 1 == o->max_lin_iter) {
         CK(hipMemcpyAsync(h_active.data(), active, Bn, hipMemcpyDeviceToHost, st), "active");
         CS(ctx->sync("pcg"));
@@ -411,7 +434,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
         if (!any) break;
       }
     }
-    CK(launch_final_dots(nh, Bn, v, t, w0, S, part, st), "final dots");
+    CK(launch_final_dots<T>(nh, Bn, v64, t, w64, S, part, st), "final dots");
     CK(launch_scalar(PH_FINAL, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
   }
   return MLQMC_OK;
@@ -442,7 +465,9 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
     CK(launch_tg_small(nh, a, ctx->stream), "two-grid (LDS)");
     return MLQMC_OK;
   }
-  return fine_batched(ctx, o, nh, s, Y, ldY, uH, lamH, nH, n, lam, lin_iters, flags, tag);
+  if (o->prec == MLQMC_MIXED)
+    return fine_batched<float>(ctx, o, nh, s, Y, ldY, uH, lamH, nH, n, lam, lin_iters, flags, tag);
+  return fine_batched<double>(ctx, o, nh, s, Y, ldY, uH, lamH, nH, n, lam, lin_iters, flags, tag);
 }
 
 // Whole level on device buffers (Y [n x ldY] on device); outputs on device.
@@ -562,7 +587,7 @@ void mlqmc_default_opts(mlqmc_opts* o) {
   o->prec = MLQMC_FP64;
   o->eig_rtol = 1e-8;
   o->max_rq_iter = 12;
-  o->lin_rtol = 1e-7;
+  o->lin_rtol = 1e-6;
   o->rq_lin_rtol = 1e-4;
   o->max_lin_iter = 60;
   o->chain_len = 0;
@@ -646,6 +671,7 @@ void mlqmc_destroy(mlqmc_ctx* ctx) {
   for (auto& kv : ctx->tables) {
     if (kv.second.el) hipFree(kv.second.el);
     if (kv.second.edge) hipFree(kv.second.edge);
+    if (kv.second.pad) hipFree(kv.second.pad);
   }
   for (auto& ev : ctx->ev_pool) {
     hipEventDestroy(ev.first);
@@ -745,7 +771,7 @@ mlqmc_status mlqmc_prolong(mlqmc_ctx* ctx, int32_t nH, int32_t nh, int64_t B, co
   double* dv;
   CS(stage_in(ctx, "in_uH", uH, (size_t)(B * DH), on_dev, &du));
   CS(out_buf(ctx, "out_uh", uh, (size_t)(B * Dh), on_dev, &dv));
-  if (B > 0 && Dh > 0) CK(launch_prolong(nH, nh, B, du, dv, ctx->stream), "prolong");
+  if (B > 0 && Dh > 0) CK(launch_prolong_interior(nH, nh, B, du, dv, ctx->stream), "prolong");
   CS(stage_out(ctx, uh, dv, (size_t)(B * Dh), on_dev));
   return ctx->sync("prolong");
 }

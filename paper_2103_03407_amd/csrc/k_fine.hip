@@ -1,11 +1,30 @@
 // Batched fine-mesh kernels of the two-grid update (Algorithm 1 steps 2-4) for
-// meshes too large for LDS.  Grid: x = blocks of kFineNT interior nodes, y = sample.
-// Every sample carries its own coefficient, shift and prolongated coarse
-// eigenvector; per-sample scalars live in FineState.  Samples whose projected
-// PCG has finished are skipped (active[b] == 0).
+// meshes too large for LDS (h <= 1/64).
 //
-// The projected PCG (see lds_mg.h for the algebra) keeps v unnormalised and
-// carries vs = ||v||_M^{-1}, so v_n = vs * v below.
+// Padded layout (mesh h = 1/n, n a power of two): node (i, j), 0 <= i < n,
+// 0 <= j <= n+1, at k = j*n + i, (n+2) n positions per sample.  Column 0 and
+// rows 0, n and n+1 hold the homogeneous Dirichlet values (zeros); the right
+// boundary node (n, j) aliases the left boundary node (0, j+1), also zero (row
+// n+1 holds the alias of (n, n), the north-east neighbour of the last interior
+// node).  Hence every stencil below is branch-free:
+//   E/W = k+-1, N/S = k+-n, NE = k+n+1, SW = k-n-1.
+// Edge weights use the same indexing: WX[k] is the horizontal edge ending at
+// node k from the west ((i-1,j)-(i,j), so the east edge of k is WX[k+1]), and
+// WY[k] the vertical edge ending at k from the south ((i,j-1)-(i,j), north edge
+// WY[k+n]).  A sample's weights are [WX | WY], 2 (n+2) n values.  Entries that
+// are not edges of an interior node are never read.  Weights use the same
+// (n+2) n positions per half.
+//
+// Work mapping: a launch covers B samples x nblk blocks of kNodesPerBlock
+// positions of rows 1..n-1.  Hardware block L runs on XCD L mod 8; sample b is
+// mapped to XCD b mod 8 and its blocks to consecutive slots of that XCD, so
+// the halo rows a block shares with its neighbours stay in one L2.
+//
+// Storage type T (double, or float in mixed precision) holds the projected-PCG
+// vectors and the smoother's weights; dot products accumulate in FP64, and the
+// right-hand side and the Rayleigh quotient are formed in FP64 from FP64 weights
+// and the FP64 prolongated vector (lds_mg.h describes the projected solve).
+// Samples whose solve has finished are skipped (active[b] == 0).
 #include "../../include/mlqmc.h"
 #include "common.h"
 #include "kernels.h"
@@ -14,299 +33,513 @@ namespace mlqmc {
 namespace {
 
 constexpr int NT = kFineNT;
+constexpr int PT = kNodesPerBlock / kFineNT;  // positions per thread
 
 struct Geo {
-  int n, m, D;
-  __device__ __forceinline__ void ij(int id, int& i, int& j) const {
-    j = id / m + 1;
-    i = id - (j - 1) * m + 1;
-  }
+  int n, lg;     // n = 2^lg
+  int P;         // padded size (n+2) n
+  int nblk;      // blocks per sample
+  int64_t B;
 };
 
-// Block reduction of K partial sums; thread 0 writes part[(b*nblk + blk)*K + k].
+__device__ __forceinline__ bool map_block(const Geo& g, int64_t& b, int& blk) {
+  const int64_t L = blockIdx.x;
+  const int xcd = (int)(L & 7);
+  const int64_t j = L >> 3;
+  b = ((j / g.nblk) << 3) + xcd;
+  blk = (int)(j % g.nblk);
+  return b < g.B;
+}
+
+// Interior positions of rows 1..n-1 owned by this thread.
+#define FOR_NODES(g, blk)                                                              \
+  _Pragma("unroll") for (int k_ = 0; k_ < PT; ++k_)                                    \
+    if (const int k = (g).n + (blk) * kNodesPerBlock + k_ * NT + threadIdx.x;          \
+        k < (g).n * (g).n && (k & ((g).n - 1)) != 0)
+
 template <int K>
-__device__ __forceinline__ void write_partials(double (&s)[K], double* part) {
+__device__ __forceinline__ void write_partials(double (&s)[K], double* part, int64_t b, int blk,
+                                               int nblk) {
   __shared__ double red[K * (NT / 64)];
   block_sums<NT, K>(s, red);
   if (threadIdx.x == 0) {
-    const int64_t base = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * K;
+    const int64_t base = (b * nblk + blk) * K;
 #pragma unroll
     for (int k = 0; k < K; ++k) part[base + k] = s[k];
   }
 }
 
-__global__ __launch_bounds__(NT) void k_prolong(int nH, int nh, const double* __restrict__ uH,
-                                                double* __restrict__ uh) {
-  const int mH = nH - 1, mh = nh - 1, Dh = mh * mh;
-  const int id = blockIdx.x * NT + threadIdx.x;
-  if (id >= Dh) return;
+template <typename T>
+__device__ __forceinline__ T diagW(const T* wx, const T* wy, int k, int n) {
+  return wx[k] + wx[k + 1] + wy[k] + wy[k + n];
+}
+
+// (A x)_k and the diagonal
+template <typename T>
+__device__ __forceinline__ T applyA(const T* x, const T* wx, const T* wy, int k, int n, T& d) {
+  const T c = x[k];
+  const T ww = wx[k], we = wx[k + 1], ws = wy[k], wn = wy[k + n];
+  d = ww + we + ws + wn;
+  return ww * (c - x[k - 1]) + we * (c - x[k + 1]) + ws * (c - x[k - n]) + wn * (c - x[k + n]);
+}
+
+// 6 x_k + E + W + N + S + NE + SW  (the mass stencil without h^2/12)
+template <typename T>
+__device__ __forceinline__ T applyM12(const T* x, int k, int n) {
+  return T(6) * x[k] + x[k - 1] + x[k + 1] + x[k - n] + x[k + n] + x[k + n + 1] + x[k - n - 1];
+}
+
+// 2:1 P1 prolongation at fine (i, j) from a padded coarse field (nc = n/2):
+// the mean of the coarse values at ((i>>1), (j>>1)) and ((i+1)>>1, (j+1)>>1)
+// (equal points at coarse nodes; the two ends of the horizontal, vertical or
+// "/" coarse edge otherwise).
+template <typename T>
+__device__ __forceinline__ T prolong2(const T* xc, int nc, int i, int j) {
+  return T(0.5) * (xc[(j >> 1) * nc + (i >> 1)] + xc[((j + 1) >> 1) * nc + ((i + 1) >> 1)]);
+}
+
+// ---------------------------------------------------------------- row marching
+//
+// Stencil kernels march a block of NTC threads (one per column of a column
+// block [c0, c0 + NTC)) up a strip of rows [j0, j1).  The stencil's source
+// field is computed once per position into a 4-row LDS ring (with one halo
+// column on each side), so every neighbour comes from LDS and every input is
+// read from global memory once per strip; one barrier per row.
+
+struct MGeo {
+  int n, lg, P;
+  int cb;      // column blocks per row (n / NTC)
+  int R;       // rows per strip
+  int nblk;    // column blocks x strips per sample
+  int64_t B;
+};
+
+template <int NTC>
+inline MGeo mgeo(int n, int64_t B) {
+  MGeo g;
+  g.n = n;
+  g.lg = 0;
+  while ((1 << g.lg) < n) ++g.lg;
+  g.P = (n + 2) * n;
+  g.cb = n / NTC;
+  g.R = n >= 512 ? 8 : 16;
+  const int strips = (n - 1 + g.R - 1) / g.R;
+  g.nblk = g.cb * strips;
+  g.B = B;
+  return g;
+}
+
+template <int NTC>
+__device__ __forceinline__ bool map_march(const MGeo& g, int64_t& b, int& c0, int& j0, int& j1,
+                                          int& blk) {
+  const int64_t L = blockIdx.x;
+  const int xcd = (int)(L & 7);
+  const int64_t q = L >> 3;
+  b = ((q / g.nblk) << 3) + xcd;
+  blk = (int)(q % g.nblk);
+  if (b >= g.B) return false;
+  c0 = (blk % g.cb) * NTC;
+  j0 = 1 + (blk / g.cb) * g.R;
+  j1 = min(j0 + g.R, g.n);
+  return true;
+}
+
+// ring row j holds src at columns c0-1 .. c0+NTC of row j (0 outside the interior)
+template <typename T, int NTC, class Src>
+__device__ __forceinline__ void ring_fill(T (*ring)[NTC + 2], const MGeo& g, int c0, int j,
+                                          Src& src) {
+  const int t = threadIdx.x, c = c0 + t, n = g.n;
+  T* row = ring[j & 3];
+  const bool rowok = (j >= 1 && j <= n - 1);
+  row[t + 1] = (rowok && c >= 1) ? src(j * n + c) : T(0);
+  if (t == 0) row[0] = (rowok && c0 >= 2) ? src(j * n + c0 - 1) : T(0);
+  if (t == NTC - 1) row[NTC + 1] = (rowok && c0 + NTC <= n - 1) ? src(j * n + c0 + NTC) : T(0);
+}
+
+// body(j, c, k, south row, centre row, north row, index of column c in the rows)
+template <typename T, int NTC, class Src, class Body>
+__device__ __forceinline__ void march(T (*ring)[NTC + 2], const MGeo& g, int c0, int j0, int j1,
+                                      Src src, Body body) {
+  const int c = c0 + threadIdx.x, ci = threadIdx.x + 1;
+  ring_fill<T, NTC>(ring, g, c0, j0 - 1, src);
+  ring_fill<T, NTC>(ring, g, c0, j0, src);
+  for (int j = j0; j < j1; ++j) {
+    ring_fill<T, NTC>(ring, g, c0, j + 1, src);
+    __syncthreads();
+    if (c >= 1) body(j, c, j * g.n + c, ring[(j - 1) & 3], ring[j & 3], ring[(j + 1) & 3], ci);
+  }
+}
+
+template <int NTC, int K>
+__device__ __forceinline__ void write_partials_m(double (&s)[K], double* part, int64_t b,
+                                                 int blk, int nblk) {
+  __shared__ double red[K * (NTC / 64)];
+  block_sums<NTC, K>(s, red);
+  if (threadIdx.x == 0) {
+    const int64_t base = (b * nblk + blk) * K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) part[base + k] = s[k];
+  }
+}
+
+// A applied at column ci of the centre row from ring rows, weights at k
+template <typename T, typename W>
+__device__ __forceinline__ T ring_A(const T* rs, const T* rc, const T* rn, int ci, const W* wx,
+                                    const W* wy, int k, int n, T& d) {
+  const T c = rc[ci];
+  const T ww = (T)wx[k], we = (T)wx[k + 1], ws = (T)wy[k], wn = (T)wy[k + n];
+  d = ww + we + ws + wn;
+  return ww * (c - rc[ci - 1]) + we * (c - rc[ci + 1]) + ws * (c - rs[ci]) + wn * (c - rn[ci]);
+}
+
+template <typename T>
+__device__ __forceinline__ T ring_M12(const T* rs, const T* rc, const T* rn, int ci) {
+  return T(6) * rc[ci] + rc[ci - 1] + rc[ci + 1] + rs[ci] + rn[ci] + rn[ci + 1] + rs[ci - 1];
+}
+
+// ---------------------------------------------------------------- setup
+
+// zero the Dirichlet rows/column of `cnt` padded arrays of B samples (mesh n)
+struct ZeroArgs {
+  void* p[10];
+  int cnt;
+  int elem;  // bytes per element
+};
+__global__ __launch_bounds__(256) void k_zero_boundary(int n, int64_t B, ZeroArgs za) {
   const int64_t b = blockIdx.y;
+  const int a = blockIdx.z;
+  if (b >= B || a >= za.cnt) return;
+  const int P = (n + 2) * n;
+  // positions: row 0 (n), rows n and n+1 (2n), column 0 of rows 1..n-1 (n-1)
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < 4 * n - 1; t += gridDim.x * 256) {
+    const int k = t < n ? t : (t < 3 * n ? n * n + (t - n) : (t - 3 * n + 1) * n);
+    if (za.elem == 8)
+      static_cast<double*>(za.p[a])[b * P + k] = 0.0;
+    else
+      static_cast<float*>(za.p[a])[b * P + k] = 0.f;
+  }
+}
+
+// interior-layout coarse field (mesh nH) -> padded fine field (mesh n), P1 interpolation
+__global__ __launch_bounds__(NT) void k_prolong(Geo g, int nH, const double* __restrict__ uH,
+                                                double* __restrict__ uh) {
+  int64_t b;
+  int blk;
+  if (!map_block(g, b, blk)) return;
+  const int mH = nH - 1;
+  FOR_NODES(g, blk) {
+    const int i = k & (g.n - 1), j = k >> g.lg;
+    uh[b * g.P + k] = interp_coarse(uH + b * (int64_t)(mH * mH), nH, g.n / nH, i, j);
+  }
+}
+
+// interior-layout prolongation for the component entry point
+__global__ __launch_bounds__(256) void k_prolong_interior(int nH, int nh, int64_t B,
+                                                          const double* __restrict__ uH,
+                                                          double* __restrict__ uh) {
+  const int mH = nH - 1, mh = nh - 1, Dh = mh * mh;
+  const int id = blockIdx.x * 256 + threadIdx.x;
+  const int64_t b = blockIdx.y;
+  if (id >= Dh || b >= B) return;
   const int j = id / mh + 1, i = id - (j - 1) * mh + 1;
   uh[b * Dh + id] = interp_coarse(uH + b * (int64_t)(mH * mH), nH, nh / nH, i, j);
 }
 
-__global__ __launch_bounds__(NT) void k_coarsen(int n, const double* __restrict__ w,
-                                                double* __restrict__ wc) {
-  const int nc = n / 2, mc = nc - 1;
-  const int EX = (n - 1) * n, EW = 2 * EX;
-  const int EXc = (nc - 1) * nc, EWc = 2 * EXc;
-  const int e = blockIdx.x * NT + threadIdx.x;
-  if (e >= EWc) return;
+// padded weights of mesh n/2 from those of mesh n (means of collinear fine edges)
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarsen(int n, int64_t B, const T* __restrict__ w,
+                                                 T* __restrict__ wc) {
+  const int nc = n / 2;
+  const int P = (n + 2) * n, Pc = (nc + 2) * nc;
+  const int e = blockIdx.x * 256 + threadIdx.x;
   const int64_t b = blockIdx.y;
-  const double* wx = w + b * EW;
-  const double* wy = wx + EX;
-  double val;
-  if (e < EXc) {
-    const int J = e / nc + 1, I = e % nc;
-    val = coarsen_wx(wx, n, I, J);
-  } else {
-    const int f = e - EXc;
-    const int J = f / mc, I = f % mc + 1;
-    val = coarsen_wy(wy, n, I, J);
+  if (e >= 2 * Pc || b >= B) return;
+  const T* wx = w + b * 2 * P;
+  const T* wy = wx + P;
+  T val = T(0);
+  if (e < Pc) {  // WXc(J, I) = edge (I-1,J)-(I,J), I in [1, nc], stored at J*nc + I
+    const int J = e / nc, I = e % nc;
+    const int Ie = (I == 0) ? nc : I, Je = (I == 0) ? J - 1 : J;
+    if (Je >= 1 && Je <= nc - 1)
+      val = T(0.5) * (wx[2 * Je * n + 2 * Ie - 1] + wx[2 * Je * n + 2 * Ie]);
+  } else {       // WYc(J, I) = edge (I,J-1)-(I,J), stored at J*nc + I
+    const int f = e - Pc;
+    const int J = f / nc, I = f % nc;
+    if (J >= 1 && J <= nc && I >= 1)
+      val = T(0.5) * (wy[(2 * J - 1) * n + 2 * I] + wy[2 * J * n + 2 * I]);
   }
-  wc[b * EWc + e] = val;
+  wc[b * 2 * Pc + e] = val;
 }
 
-// partials: v.M12 v, v.A v  (raw v)
-__global__ __launch_bounds__(NT) void k_setup_dots(Geo g, const double* __restrict__ v,
-                                                   const double* __restrict__ w,
-                                                   double* __restrict__ part) {
-  const int64_t b = blockIdx.y;
-  const int id = blockIdx.x * NT + threadIdx.x;
-  const int EX = (g.n - 1) * g.n;
+__global__ __launch_bounds__(256) void k_to_float(int64_t count, const double* __restrict__ x,
+                                                  float* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) y[i] = (float)x[i];
+}
+
+// partials: v.M12 v, v.A v  (raw FP64 v, FP64 weights)
+template <int NTC>
+__global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, const double* __restrict__ v,
+                                                    const double* __restrict__ w,
+                                                    double* __restrict__ part) {
+  __shared__ double ring[4][NTC + 2];
+  int64_t b;
+  int c0, j0, j1, blk;
+  if (!map_march<NTC>(g, b, c0, j0, j1, blk)) return;
+  const double* vb = v + b * g.P;
+  const double* wx = w + b * 2 * g.P;
+  const double* wy = wx + g.P;
   double s[2] = {0.0, 0.0};
-  if (id < g.D) {
-    int i, j;
-    g.ij(id, i, j);
-    const double* vb = v + b * g.D;
-    const double* wx = w + b * (2 * EX);
-    double d;
-    const double av = stencil_A(vb, wx, wx + EX, g.n, i, j, id, d);
-    s[0] = vb[id] * stencil_M12(vb, g.n, i, j, id);
-    s[1] = vb[id] * av;
-  }
-  write_partials<2>(s, part);
+  march<double, NTC>(ring, g, c0, j0, j1, [&](int k) { return vb[k]; },
+                     [&](int, int, int k, const double* rs, const double* rc, const double* rn,
+                         int ci) {
+                       double d;
+                       const double av = ring_A(rs, rc, rn, ci, wx, wy, k, g.n, d);
+                       s[0] += rc[ci] * ring_M12(rs, rc, rn, ci);
+                       s[1] += rc[ci] * av;
+                     });
+  write_partials_m<NTC, 2>(s, part, b, blk, g.nblk);
 }
 
-// r = -(A v_n - rho M v_n), t = 0, zb = omega r / diag (first smoothing sweep)
-__global__ __launch_bounds__(NT) void k_setup_rhs(Geo g, const double* __restrict__ v,
-                                                  const double* __restrict__ w, FineState S,
-                                                  double* __restrict__ r, double* __restrict__ t,
-                                                  double* __restrict__ zb) {
-  const int64_t b = blockIdx.y;
-  const int id = blockIdx.x * NT + threadIdx.x;
-  if (id >= g.D) return;
-  const int EX = (g.n - 1) * g.n;
-  int i, j;
-  g.ij(id, i, j);
-  const double* vb = v + b * g.D;
-  const double* wx = w + b * (2 * EX);
-  double d;
-  const double av = stencil_A(vb, wx, wx + EX, g.n, i, j, id, d);
-  const double mv = mass_scale(g.n) * stencil_M12(vb, g.n, i, j, id);
-  const double vs = S.vs[b];
-  const double rv = -vs * (av - S.rho[b] * mv);
-  r[b * g.D + id] = rv;
-  t[b * g.D + id] = 0.0;
-  zb[b * g.D + id] = kOmega * rv / d;
+// r = -(A v_n - rho M v_n) (FP64), t = 0, zb = omega r / diag, vn = v_n, mvn = M v_n
+template <typename T, int NTC>
+__global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, const double* __restrict__ v,
+                                                   const double* __restrict__ w64,
+                                                   const T* __restrict__ wT, FineState S,
+                                                   T* __restrict__ r, T* __restrict__ t,
+                                                   T* __restrict__ zb, T* __restrict__ vn,
+                                                   T* __restrict__ mvn) {
+  __shared__ double ring[4][NTC + 2];
+  int64_t b;
+  int c0, j0, j1, blk;
+  if (!map_march<NTC>(g, b, c0, j0, j1, blk)) return;
+  const double* vb = v + b * g.P;
+  const double* wx = w64 + b * 2 * g.P;
+  const double* wy = wx + g.P;
+  const T* tx = wT + b * 2 * g.P;
+  const T* ty = tx + g.P;
+  const double vs = S.vs[b], rho = S.rho[b], hm = mass_scale(g.n);
+  march<double, NTC>(ring, g, c0, j0, j1, [&](int k) { return vb[k]; },
+                     [&](int, int, int k, const double* rs, const double* rc, const double* rn,
+                         int ci) {
+                       double d;
+                       const double av = ring_A(rs, rc, rn, ci, wx, wy, k, g.n, d);
+                       const double mv = hm * ring_M12(rs, rc, rn, ci);
+                       const double rv = -vs * (av - rho * mv);
+                       const T rT = (T)rv;
+                       const int64_t o = b * g.P + k;
+                       r[o] = rT;
+                       t[o] = T(0);
+                       zb[o] = T(kOmega) * rT / diagW(tx, ty, k, g.n);
+                       vn[o] = (T)(vs * rc[ci]);
+                       mvn[o] = (T)(vs * mv);
+                     });
 }
 
-// q = (A - mu M) p; partials p.q, v_n.q, p.M v_n
-__global__ __launch_bounds__(NT) void k_apply_dots(Geo g, const double* __restrict__ p,
-                                                   const double* __restrict__ v,
-                                                   const double* __restrict__ w, FineState S,
-                                                   double* __restrict__ q,
-                                                   double* __restrict__ part) {
-  const int64_t b = blockIdx.y;
-  if (!S.active[b]) return;
-  const int id = blockIdx.x * NT + threadIdx.x;
-  const int EX = (g.n - 1) * g.n;
+// ---------------------------------------------------------------- PCG
+
+// p = z - c2 vn + beta p_in (first: beta = 0), q = (A - mu M) p;
+// partials p.q, vn.q, p.M vn
+template <typename T, int NTC>
+__global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restrict__ z,
+                                                       const T* __restrict__ vn,
+                                                       const T* __restrict__ pin,
+                                                       const T* __restrict__ mvn,
+                                                       const T* __restrict__ w, FineState S,
+                                                       int first, T* __restrict__ pout,
+                                                       T* __restrict__ q,
+                                                       double* __restrict__ part) {
+  __shared__ T ring[4][NTC + 2];
+  int64_t b;
+  int c0, j0, j1, blk;
+  if (!map_march<NTC>(g, b, c0, j0, j1, blk) || !S.active[b]) return;
+  const T* zz = z + b * g.P;
+  const T* vb = vn + b * g.P;
+  const T* pb = pin + b * g.P;
+  const T* mb = mvn + b * g.P;
+  const T* wx = w + b * 2 * g.P;
+  const T* wy = wx + g.P;
+  const T c2 = (T)S.c2[b], beta = first ? T(0) : (T)S.beta[b], mu = (T)S.mu[b];
+  const T hm = (T)mass_scale(g.n);
   double s[3] = {0.0, 0.0, 0.0};
-  if (id < g.D) {
-    int i, j;
-    g.ij(id, i, j);
-    const double* pb = p + b * g.D;
-    const double* vb = v + b * g.D;
-    const double* wx = w + b * (2 * EX);
-    const double hm = mass_scale(g.n), vs = S.vs[b];
-    double d;
-    const double ap = stencil_A(pb, wx, wx + EX, g.n, i, j, id, d);
-    const double qv = ap - S.mu[b] * hm * stencil_M12(pb, g.n, i, j, id);
-    q[b * g.D + id] = qv;
-    s[0] = pb[id] * qv;
-    s[1] = vs * vb[id] * qv;
-    s[2] = pb[id] * vs * hm * stencil_M12(vb, g.n, i, j, id);
+  march<T, NTC>(ring, g, c0, j0, j1,
+                [&](int k) { return zz[k] - c2 * vb[k] + (first ? T(0) : beta * pb[k]); },
+                [&](int, int, int k, const T* rs, const T* rc, const T* rn, int ci) {
+                  T d;
+                  const T ap = ring_A(rs, rc, rn, ci, wx, wy, k, g.n, d);
+                  const T pc = rc[ci];
+                  const T qv = ap - mu * hm * ring_M12(rs, rc, rn, ci);
+                  const int64_t o = b * g.P + k;
+                  pout[o] = pc;
+                  q[o] = qv;
+                  s[0] += (double)pc * (double)qv;
+                  s[1] += (double)vb[k] * (double)qv;
+                  s[2] += (double)pc * (double)mb[k];
+                });
+  write_partials_m<NTC, 3>(s, part, b, blk, g.nblk);
+}
+
+// t += alpha p; r -= alpha (q - c M vn); zb = omega r / diag
+template <typename T>
+__global__ __launch_bounds__(NT) void k_update(Geo g, const T* __restrict__ p,
+                                               const T* __restrict__ q, const T* __restrict__ mvn,
+                                               const T* __restrict__ w, FineState S,
+                                               T* __restrict__ t, T* __restrict__ r,
+                                               T* __restrict__ zb) {
+  int64_t b;
+  int blk;
+  if (!map_block(g, b, blk) || !S.active[b]) return;
+  const T* mb = mvn + b * g.P;
+  const T* wx = w + b * 2 * g.P;
+  const T* wy = wx + g.P;
+  const T alpha = (T)S.alpha[b], c = (T)S.c[b];
+  FOR_NODES(g, blk) {
+    const int64_t o = b * g.P + k;
+    t[o] += alpha * p[o];
+    const T rn = r[o] - alpha * (q[o] - c * mb[k]);
+    r[o] = rn;
+    zb[o] = T(kOmega) * rn / diagW(wx, wy, k, g.n);
   }
-  write_partials<3>(s, part);
 }
 
-// t += alpha p; r -= alpha (q - c M v_n); zb = omega r / diag
-__global__ __launch_bounds__(NT) void k_update(Geo g, const double* __restrict__ p,
-                                               const double* __restrict__ q,
-                                               const double* __restrict__ v,
-                                               const double* __restrict__ w, FineState S,
-                                               double* __restrict__ t, double* __restrict__ r,
-                                               double* __restrict__ zb) {
-  const int64_t b = blockIdx.y;
-  if (!S.active[b]) return;
-  const int id = blockIdx.x * NT + threadIdx.x;
-  if (id >= g.D) return;
-  const int EX = (g.n - 1) * g.n;
-  int i, j;
-  g.ij(id, i, j);
-  const int64_t o = b * g.D + id;
-  const double* vb = v + b * g.D;
-  const double* wx = w + b * (2 * EX);
-  const double alpha = S.alpha[b];
-  const double mv = S.vs[b] * mass_scale(g.n) * stencil_M12(vb, g.n, i, j, id);
-  t[o] += alpha * p[o];
-  const double rn = r[o] - alpha * (q[o] - S.c[b] * mv);
-  r[o] = rn;
-  zb[o] = kOmega * rn / stencil_diag(wx, wx + EX, g.n, i, j);
-}
+// ---------------------------------------------------------------- V-cycle
 
-__global__ __launch_bounds__(NT) void k_jacobi_first(Geo g, const double* __restrict__ w,
-                                                     const double* __restrict__ rhs,
-                                                     double* __restrict__ X,
+template <typename T>
+__global__ __launch_bounds__(NT) void k_jacobi_first(Geo g, const T* __restrict__ w,
+                                                     const T* __restrict__ rhs,
+                                                     T* __restrict__ X,
                                                      const uint8_t* __restrict__ active) {
-  const int64_t b = blockIdx.y;
-  if (active && !active[b]) return;
-  const int id = blockIdx.x * NT + threadIdx.x;
-  if (id >= g.D) return;
-  const int EX = (g.n - 1) * g.n;
-  int i, j;
-  g.ij(id, i, j);
-  const double* wx = w + b * (2 * EX);
-  X[b * g.D + id] = kOmega * rhs[b * g.D + id] / stencil_diag(wx, wx + EX, g.n, i, j);
+  int64_t b;
+  int blk;
+  if (!map_block(g, b, blk) || !active[b]) return;
+  const T* wx = w + b * 2 * g.P;
+  const T* wy = wx + g.P;
+  FOR_NODES(g, blk) {
+    X[b * g.P + k] = T(kOmega) * rhs[b * g.P + k] / diagW(wx, wy, k, g.n);
+  }
 }
 
-__global__ __launch_bounds__(NT) void k_jacobi(Geo g, const double* __restrict__ w,
-                                               const double* __restrict__ rhs,
-                                               const double* __restrict__ Xin,
-                                               double* __restrict__ Xout,
-                                               const uint8_t* __restrict__ active) {
-  const int64_t b = blockIdx.y;
-  if (active && !active[b]) return;
-  const int id = blockIdx.x * NT + threadIdx.x;
-  if (id >= g.D) return;
-  const int EX = (g.n - 1) * g.n;
-  int i, j;
-  g.ij(id, i, j);
-  const double* xb = Xin + b * g.D;
-  const double* wx = w + b * (2 * EX);
-  double d;
-  const double ax = stencil_A(xb, wx, wx + EX, g.n, i, j, id, d);
-  Xout[b * g.D + id] = xb[id] + kOmega * (rhs[b * g.D + id] - ax) / d;
+// Xout = Xin + omega (rhs - A Xin) / diag; with kAddCoarse the input is
+// Xin + P Xc (the coarse-grid correction, prolongated on the fly).
+template <typename T, int NTC, bool kAddCoarse>
+__global__ __launch_bounds__(NTC) void k_jacobi(MGeo g, const T* __restrict__ w,
+                                                const T* __restrict__ rhs,
+                                                const T* __restrict__ Xin,
+                                                const T* __restrict__ Xc, T* __restrict__ Xout,
+                                                const uint8_t* __restrict__ active) {
+  __shared__ T ring[4][NTC + 2];
+  int64_t b;
+  int c0, j0, j1, blk;
+  if (!map_march<NTC>(g, b, c0, j0, j1, blk) || !active[b]) return;
+  const int n = g.n, nc = n / 2;
+  const T* xb = Xin + b * g.P;
+  const T* xc = kAddCoarse ? Xc + b * (int64_t)((nc + 2) * nc) : nullptr;
+  const T* rb = rhs + b * g.P;
+  const T* wx = w + b * 2 * g.P;
+  const T* wy = wx + g.P;
+  march<T, NTC>(ring, g, c0, j0, j1,
+                [&](int k) {
+                  T v = xb[k];
+                  if constexpr (kAddCoarse) v += prolong2(xc, nc, k & (n - 1), k >> g.lg);
+                  return v;
+                },
+                [&](int, int, int k, const T* rs, const T* rc, const T* rn, int ci) {
+                  T d;
+                  const T ax = ring_A(rs, rc, rn, ci, wx, wy, k, n, d);
+                  Xout[b * g.P + k] = rc[ci] + T(kOmega) * (rb[k] - ax) / d;
+                });
 }
 
-// rhs_c = P^T (rhs - A X) on the next coarser mesh (7 fine residuals per coarse node)
-__global__ __launch_bounds__(NT) void k_resid_restrict(Geo g, const double* __restrict__ w,
-                                                       const double* __restrict__ rhs,
-                                                       const double* __restrict__ X,
-                                                       double* __restrict__ rhs_c,
-                                                       const uint8_t* __restrict__ active) {
-  const int64_t b = blockIdx.y;
-  if (active && !active[b]) return;
-  const int nc = g.n / 2, mc = nc - 1, Dc = mc * mc;
-  const int idc = blockIdx.x * NT + threadIdx.x;
-  if (idc >= Dc) return;
-  const int J = idc / mc + 1, I = idc - (J - 1) * mc + 1;
-  const int EX = (g.n - 1) * g.n;
-  const double* xb = X + b * g.D;
-  const double* rb = rhs + b * g.D;
-  const double* wx = w + b * (2 * EX);
-  const double* wy = wx + EX;
-  auto res = [&](int i, int j) -> double {
-    const int id = (j - 1) * g.m + (i - 1);
-    double d;
-    return rb[id] - stencil_A(xb, wx, wy, g.n, i, j, id, d);
-  };
-  const int i0 = 2 * I, j0 = 2 * J;
-  const double v = res(i0, j0) + 0.5 * (res(i0 - 1, j0) + res(i0 + 1, j0) + res(i0, j0 - 1) +
-                                        res(i0, j0 + 1) + res(i0 + 1, j0 + 1) +
-                                        res(i0 - 1, j0 - 1));
-  rhs_c[b * Dc + idc] = v;
-}
-
-__global__ __launch_bounds__(NT) void k_prolong_add(Geo g, const double* __restrict__ Xc,
-                                                    double* __restrict__ X,
-                                                    const uint8_t* __restrict__ active) {
-  const int64_t b = blockIdx.y;
-  if (active && !active[b]) return;
-  const int id = blockIdx.x * NT + threadIdx.x;
-  if (id >= g.D) return;
-  int i, j;
-  g.ij(id, i, j);
-  const int nc = g.n / 2, Dc = (nc - 1) * (nc - 1);
-  X[b * g.D + id] += prolong2_at(Xc + b * Dc, nc, i, j);
-}
-
-// partials r.z, M v_n . z, r . v_n
-__global__ __launch_bounds__(NT) void k_dots3(Geo g, const double* __restrict__ r,
-                                              const double* __restrict__ z,
-                                              const double* __restrict__ v, FineState S,
-                                              double* __restrict__ part) {
-  const int64_t b = blockIdx.y;
-  if (!S.active[b]) return;
-  const int id = blockIdx.x * NT + threadIdx.x;
+// The last post-smoothing sweep of level 0 fused with the dot products of the
+// preconditioned residual: z = sweep(zin); partials r.z, M vn.z, r.vn.
+template <typename T, int NTC>
+__global__ __launch_bounds__(NTC) void k_jacobi_dots(MGeo g, const T* __restrict__ w,
+                                                     const T* __restrict__ r,
+                                                     const T* __restrict__ zin,
+                                                     const T* __restrict__ vn,
+                                                     const T* __restrict__ mvn, FineState S,
+                                                     T* __restrict__ z,
+                                                     double* __restrict__ part) {
+  __shared__ T ring[4][NTC + 2];
+  int64_t b;
+  int c0, j0, j1, blk;
+  if (!map_march<NTC>(g, b, c0, j0, j1, blk) || !S.active[b]) return;
+  const T* xb = zin + b * g.P;
+  const T* vb = vn + b * g.P;
+  const T* mb = mvn + b * g.P;
+  const T* rb = r + b * g.P;
+  const T* wx = w + b * 2 * g.P;
+  const T* wy = wx + g.P;
   double s[3] = {0.0, 0.0, 0.0};
-  if (id < g.D) {
-    int i, j;
-    g.ij(id, i, j);
-    const int64_t o = b * g.D + id;
-    const double* vb = v + b * g.D;
-    const double vs = S.vs[b];
-    const double zz = z[o], rr = r[o];
-    s[0] = rr * zz;
-    s[1] = vs * mass_scale(g.n) * stencil_M12(vb, g.n, i, j, id) * zz;
-    s[2] = rr * vs * vb[id];
+  march<T, NTC>(ring, g, c0, j0, j1, [&](int k) { return xb[k]; },
+                [&](int, int, int k, const T* rs, const T* rc, const T* rn, int ci) {
+                  T d;
+                  const T ax = ring_A(rs, rc, rn, ci, wx, wy, k, g.n, d);
+                  const T rr = rb[k];
+                  const T zz = rc[ci] + T(kOmega) * (rr - ax) / d;
+                  z[b * g.P + k] = zz;
+                  s[0] += (double)rr * (double)zz;
+                  s[1] += (double)mb[k] * (double)zz;
+                  s[2] += (double)rr * (double)vb[k];
+                });
+  write_partials_m<NTC, 3>(s, part, b, blk, g.nblk);
+}
+
+// rhs_c = P^T (rhs - A X) on mesh n/2: fine node (2I, 2J) with weight 1, its
+// E, W, N, S, NE, SW neighbours with weight 1/2 (all interior).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_resid_restrict(Geo gc, const T* __restrict__ w,
+                                                       const T* __restrict__ rhs,
+                                                       const T* __restrict__ X,
+                                                       T* __restrict__ rhs_c,
+                                                       const uint8_t* __restrict__ active) {
+  int64_t b;
+  int blk;
+  if (!map_block(gc, b, blk) || !active[b]) return;
+  const int n = 2 * gc.n, P = (n + 2) * n;
+  const T* xb = X + b * P;
+  const T* rb = rhs + b * P;
+  const T* wx = w + b * 2 * P;
+  const T* wy = wx + P;
+  FOR_NODES(gc, blk) {
+    const int I = k & (gc.n - 1), J = k >> gc.lg;
+    const int kf = 2 * J * n + 2 * I;
+    auto res = [&](int kk) -> T {
+      T d;
+      return rb[kk] - applyA(xb, wx, wy, kk, n, d);
+    };
+    rhs_c[b * gc.P + k] = res(kf) + T(0.5) * (res(kf - 1) + res(kf + 1) + res(kf - n) +
+                                              res(kf + n) + res(kf + n + 1) + res(kf - n - 1));
   }
-  write_partials<3>(s, part);
 }
 
-// p = z - c2 v_n + beta p
-__global__ __launch_bounds__(NT) void k_pupdate(Geo g, const double* __restrict__ z,
-                                                const double* __restrict__ v, FineState S,
-                                                double* __restrict__ p) {
-  const int64_t b = blockIdx.y;
-  if (!S.active[b]) return;
-  const int id = blockIdx.x * NT + threadIdx.x;
-  if (id >= g.D) return;
-  const int64_t o = b * g.D + id;
-  p[o] = z[o] - S.c2[b] * S.vs[b] * v[o] + S.beta[b] * p[o];
-}
+// ---------------------------------------------------------------- final
 
-// w = v_n + t: partials w.A w, w.M12 w
-__global__ __launch_bounds__(NT) void k_final_dots(Geo g, const double* __restrict__ v,
-                                                   const double* __restrict__ t,
-                                                   const double* __restrict__ w, FineState S,
-                                                   double* __restrict__ part) {
-  const int64_t b = blockIdx.y;
-  const int id = blockIdx.x * NT + threadIdx.x;
-  const int EX = (g.n - 1) * g.n;
+// w = vs v + t (FP64): partials w.A w, w.M12 w with FP64 weights
+template <typename T, int NTC>
+__global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, const double* __restrict__ v,
+                                                    const T* __restrict__ t,
+                                                    const double* __restrict__ w, FineState S,
+                                                    double* __restrict__ part) {
+  __shared__ double ring[4][NTC + 2];
+  int64_t b;
+  int c0, j0, j1, blk;
+  if (!map_march<NTC>(g, b, c0, j0, j1, blk)) return;
+  const double* vb = v + b * g.P;
+  const T* tb = t + b * g.P;
+  const double vs = S.vs[b];
+  const double* wx = w + b * 2 * g.P;
+  const double* wy = wx + g.P;
   double s[2] = {0.0, 0.0};
-  if (id < g.D) {
-    int i, j;
-    g.ij(id, i, j);
-    const int m = g.m, n = g.n;
-    const double* vb = v + b * g.D;
-    const double* tb = t + b * g.D;
-    const double vs = S.vs[b];
-    auto W = [&](int k) -> double { return vs * vb[k] + tb[k]; };
-    const double wc = W(id);
-    const double ww = (i > 1) ? W(id - 1) : 0.0, we = (i < m) ? W(id + 1) : 0.0;
-    const double ws = (j > 1) ? W(id - m) : 0.0, wn = (j < m) ? W(id + m) : 0.0;
-    const double wne = (i < m && j < m) ? W(id + m + 1) : 0.0;
-    const double wsw = (i > 1 && j > 1) ? W(id - m - 1) : 0.0;
-    const double* wx = w + b * (2 * EX);
-    const double* wy = wx + EX;
-    const double aw = wx[(j - 1) * n + (i - 1)] * (wc - ww) + wx[(j - 1) * n + i] * (wc - we) +
-                      wy[(j - 1) * m + (i - 1)] * (wc - ws) + wy[j * m + (i - 1)] * (wc - wn);
-    const double mw = 6.0 * wc + ww + we + ws + wn + wne + wsw;
-    s[0] = wc * aw;
-    s[1] = wc * mw;
-  }
-  write_partials<2>(s, part);
+  march<double, NTC>(ring, g, c0, j0, j1, [&](int k) { return vs * vb[k] + (double)tb[k]; },
+                     [&](int, int, int k, const double* rs, const double* rc, const double* rn,
+                         int ci) {
+                       double d;
+                       const double aw = ring_A(rs, rc, rn, ci, wx, wy, k, g.n, d);
+                       s[0] += rc[ci] * aw;
+                       s[1] += rc[ci] * ring_M12(rs, rc, rn, ci);
+                     });
+  write_partials_m<NTC, 2>(s, part, b, blk, g.nblk);
 }
 
 // one wavefront per sample: sum the sample's block partials in fixed order
@@ -318,7 +551,7 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
   if (b >= B) return;
   int K = 3;
   if (phase == PH_SETUP || phase == PH_FINAL) K = 2;
-  if (phase != PH_SETUP && phase != PH_FINAL && phase != PH_FIRST_RZ && !S.active[b]) return;
+  if ((phase == PH_ALPHA || phase == PH_BETA) && !S.active[b]) return;
   double s[3] = {0.0, 0.0, 0.0};
   for (int k = lane; k < nblk; k += 64)
     for (int c = 0; c < K; ++c) s[c] += part[((int64_t)b * nblk + k) * K + c];
@@ -383,119 +616,208 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
   }
 }
 
-__global__ __launch_bounds__(NT) void k_apply_plain(Geo g, const double* __restrict__ w,
-                                                    const double* __restrict__ sigma,
-                                                    const double* __restrict__ x,
-                                                    double* __restrict__ out) {
+// interior-layout operator apply for the component entry point
+__global__ __launch_bounds__(256) void k_apply_plain(int n, int64_t B,
+                                                     const double* __restrict__ w,
+                                                     const double* __restrict__ sigma,
+                                                     const double* __restrict__ x,
+                                                     double* __restrict__ out) {
+  const int m = n - 1, D = m * m, EX = (n - 1) * n;
+  const int id = blockIdx.x * 256 + threadIdx.x;
   const int64_t b = blockIdx.y;
-  const int id = blockIdx.x * NT + threadIdx.x;
-  if (id >= g.D) return;
-  const int EX = (g.n - 1) * g.n;
-  int i, j;
-  g.ij(id, i, j);
-  const double* xb = x + b * g.D;
+  if (id >= D || b >= B) return;
+  const int j = id / m + 1, i = id - (j - 1) * m + 1;
+  const double* xb = x + b * D;
   const double* wx = w + b * (2 * EX);
   double d;
-  const double ax = stencil_A(xb, wx, wx + EX, g.n, i, j, id, d);
-  out[b * g.D + id] = ax - sigma[b] * mass_scale(g.n) * stencil_M12(xb, g.n, i, j, id);
+  const double ax = stencil_A(xb, wx, wx + EX, n, i, j, id, d);
+  out[b * D + id] = ax - sigma[b] * mass_scale(n) * stencil_M12(xb, n, i, j, id);
 }
 
-inline Geo geo(int n) { return Geo{n, n - 1, (n - 1) * (n - 1)}; }
-inline dim3 grid_for(int D, int64_t B) { return dim3((unsigned)fine_blocks(D), (unsigned)B); }
+inline Geo geo(int n, int64_t B) {
+  Geo g;
+  g.n = n;
+  g.lg = 0;
+  while ((1 << g.lg) < n) ++g.lg;
+  g.P = (n + 2) * n;
+  g.nblk = fine_blocks(n);
+  g.B = B;
+  return g;
+}
+inline dim3 grid_of(const Geo& g) {
+  const int64_t Bp = (g.B + 7) / 8 * 8;
+  return dim3((unsigned)(Bp * g.nblk));
+}
 
 }  // namespace
 
-hipError_t launch_prolong(int nH, int nh, int64_t B, const double* uH, double* uh,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong, grid_for((nh - 1) * (nh - 1), B), dim3(NT), 0, st, nH, nh, uH, uh);
+hipError_t launch_zero_boundary(int n, int64_t B, void* const* ptrs, int cnt, int elem,
+                                hipStream_t st) {
+  if (B <= 0 || cnt <= 0) return hipSuccess;
+  if (cnt > 10) return hipErrorInvalidValue;
+  ZeroArgs za{};
+  for (int a = 0; a < cnt; ++a) za.p[a] = ptrs[a];
+  za.cnt = cnt;
+  za.elem = elem;
+  const int per = 4 * n - 1;
+  hipLaunchKernelGGL(k_zero_boundary, dim3((per + 255) / 256, (unsigned)B, cnt), dim3(256), 0, st,
+                     n, B, za);
   return hipGetLastError();
 }
 
-hipError_t launch_coarsen(int n, int64_t B, const double* w, double* wc, hipStream_t st) {
-  const int nc = n / 2;
-  hipLaunchKernelGGL(k_coarsen, grid_for(2 * (nc - 1) * nc, B), dim3(NT), 0, st, n, w, wc);
+hipError_t launch_prolong(int nH, int nh, int64_t B, const double* uH, double* uh,
+                          hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  const Geo g = geo(nh, B);
+  hipLaunchKernelGGL(k_prolong, grid_of(g), dim3(NT), 0, st, g, nH, uH, uh);
   return hipGetLastError();
+}
+
+hipError_t launch_prolong_interior(int nH, int nh, int64_t B, const double* uH, double* uh,
+                                  hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  const int Dh = (nh - 1) * (nh - 1);
+  hipLaunchKernelGGL(k_prolong_interior, dim3((Dh + 255) / 256, (unsigned)B), dim3(256), 0, st,
+                     nH, nh, B, uH, uh);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarsen(int n, int64_t B, const T* w, T* wc, hipStream_t st) {
+  const int nc = n / 2;
+  const int E = 2 * (nc + 2) * nc;
+  hipLaunchKernelGGL(k_coarsen<T>, dim3((E + 255) / 256, (unsigned)B), dim3(256), 0, st, n, B, w,
+                     wc);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_float(int64_t count, const double* x, float* y, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_float, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count,
+                     x, y);
+  return hipGetLastError();
+}
+
+// marching launches: NTC = 64 (n = 64), 128 (n = 128) or 256 (n >= 256)
+#define MARCH_DISPATCH(n, BODY)                \
+  do {                                         \
+    if ((n) <= 64) {                           \
+      constexpr int NTC = 64;                  \
+      BODY;                                    \
+    } else if ((n) == 128) {                   \
+      constexpr int NTC = 128;                 \
+      BODY;                                    \
+    } else {                                   \
+      constexpr int NTC = 256;                 \
+      BODY;                                    \
+    }                                          \
+  } while (0)
+
+template <int NTC>
+inline dim3 mgrid(const MGeo& g) {
+  const int64_t Bp = (g.B + 7) / 8 * 8;
+  return dim3((unsigned)(Bp * g.nblk));
 }
 
 hipError_t launch_setup_dots(int n, int64_t B, const double* v, const double* w, double* part,
                              hipStream_t st) {
-  const Geo g = geo(n);
-  hipLaunchKernelGGL(k_setup_dots, grid_for(g.D, B), dim3(NT), 0, st, g, v, w, part);
+  MARCH_DISPATCH(n, {
+    const MGeo g = mgeo<NTC>(n, B);
+    hipLaunchKernelGGL((k_setup_dots<NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, v, w, part);
+  });
   return hipGetLastError();
 }
 
-hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w,
-                            const FineState& S, double* r, double* t, double* zb,
+template <typename T>
+hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64, const T* wT,
+                            const FineState& S, T* r, T* t, T* zb, T* vn, T* mvn,
                             hipStream_t st) {
-  const Geo g = geo(n);
-  hipLaunchKernelGGL(k_setup_rhs, grid_for(g.D, B), dim3(NT), 0, st, g, v, w, S, r, t, zb);
+  MARCH_DISPATCH(n, {
+    const MGeo g = mgeo<NTC>(n, B);
+    hipLaunchKernelGGL((k_setup_rhs<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, v, w64, wT, S, r,
+                       t, zb, vn, mvn);
+  });
   return hipGetLastError();
 }
 
-hipError_t launch_apply_dots(int n, int64_t B, const double* p, const double* v, const double* w,
-                             const FineState& S, double* q, double* part, hipStream_t st) {
-  const Geo g = geo(n);
-  hipLaunchKernelGGL(k_apply_dots, grid_for(g.D, B), dim3(NT), 0, st, g, p, v, w, S, q, part);
+template <typename T>
+hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
+                                const T* mvn, const T* w, const FineState& S, int first, T* pout,
+                                T* q, double* part, hipStream_t st) {
+  MARCH_DISPATCH(n, {
+    const MGeo g = mgeo<NTC>(n, B);
+    hipLaunchKernelGGL((k_pupdate_apply<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, z, vn, pin,
+                       mvn, w, S, first, pout, q, part);
+  });
   return hipGetLastError();
 }
 
-hipError_t launch_update(int n, int64_t B, const double* p, const double* q, const double* v,
-                         const double* w, const FineState& S, double* t, double* r, double* zb,
-                         hipStream_t st) {
-  const Geo g = geo(n);
-  hipLaunchKernelGGL(k_update, grid_for(g.D, B), dim3(NT), 0, st, g, p, q, v, w, S, t, r, zb);
+template <typename T>
+hipError_t launch_update(int n, int64_t B, const T* p, const T* q, const T* mvn, const T* w,
+                         const FineState& S, T* t, T* r, T* zb, hipStream_t st) {
+  const Geo g = geo(n, B);
+  hipLaunchKernelGGL(k_update<T>, grid_of(g), dim3(NT), 0, st, g, p, q, mvn, w, S, t, r, zb);
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_first(int n, int64_t B, const double* w, const double* rhs, double* X,
+template <typename T>
+hipError_t launch_jacobi_first(int n, int64_t B, const T* w, const T* rhs, T* X,
                                const uint8_t* active, hipStream_t st) {
-  const Geo g = geo(n);
-  hipLaunchKernelGGL(k_jacobi_first, grid_for(g.D, B), dim3(NT), 0, st, g, w, rhs, X, active);
+  const Geo g = geo(n, B);
+  hipLaunchKernelGGL(k_jacobi_first<T>, grid_of(g), dim3(NT), 0, st, g, w, rhs, X, active);
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi(int n, int64_t B, const double* w, const double* rhs, const double* Xin,
-                         double* Xout, const uint8_t* active, hipStream_t st) {
-  const Geo g = geo(n);
-  hipLaunchKernelGGL(k_jacobi, grid_for(g.D, B), dim3(NT), 0, st, g, w, rhs, Xin, Xout, active);
+template <typename T>
+hipError_t launch_jacobi(int n, int64_t B, const T* w, const T* rhs, const T* Xin, const T* Xc,
+                         T* Xout, const uint8_t* active, hipStream_t st) {
+  MARCH_DISPATCH(n, {
+    const MGeo g = mgeo<NTC>(n, B);
+    if (Xc)
+      hipLaunchKernelGGL((k_jacobi<T, NTC, true>), mgrid<NTC>(g), dim3(NTC), 0, st, g, w, rhs, Xin,
+                         Xc, Xout, active);
+    else
+      hipLaunchKernelGGL((k_jacobi<T, NTC, false>), mgrid<NTC>(g), dim3(NTC), 0, st, g, w, rhs,
+                         Xin, Xc, Xout, active);
+  });
   return hipGetLastError();
 }
 
-hipError_t launch_resid_restrict(int n, int64_t B, const double* w, const double* rhs,
-                                 const double* X, double* rhs_c, const uint8_t* active,
-                                 hipStream_t st) {
-  const Geo g = geo(n);
-  const int mc = n / 2 - 1;
-  hipLaunchKernelGGL(k_resid_restrict, grid_for(mc * mc, B), dim3(NT), 0, st, g, w, rhs, X,
-                     rhs_c, active);
+template <typename T>
+hipError_t launch_jacobi_dots(int n, int64_t B, const T* w, const T* r, const T* zin,
+                              const T* vn, const T* mvn, const FineState& S, T* z, double* part,
+                              hipStream_t st) {
+  MARCH_DISPATCH(n, {
+    const MGeo g = mgeo<NTC>(n, B);
+    hipLaunchKernelGGL((k_jacobi_dots<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, w, r, zin, vn,
+                       mvn, S, z, part);
+  });
   return hipGetLastError();
 }
 
-hipError_t launch_prolong_add(int n, int64_t B, const double* Xc, double* X,
-                              const uint8_t* active, hipStream_t st) {
-  const Geo g = geo(n);
-  hipLaunchKernelGGL(k_prolong_add, grid_for(g.D, B), dim3(NT), 0, st, g, Xc, X, active);
+int march_blocks(int n) {
+  int nb = 0;
+  MARCH_DISPATCH(n, { nb = mgeo<NTC>(n, 1).nblk; });
+  return nb;
+}
+
+template <typename T>
+hipError_t launch_resid_restrict(int n, int64_t B, const T* w, const T* rhs, const T* X,
+                                 T* rhs_c, const uint8_t* active, hipStream_t st) {
+  const Geo gc = geo(n / 2, B);
+  hipLaunchKernelGGL(k_resid_restrict<T>, grid_of(gc), dim3(NT), 0, st, gc, w, rhs, X, rhs_c,
+                     active);
   return hipGetLastError();
 }
 
-hipError_t launch_dots3(int n, int64_t B, const double* r, const double* z, const double* v,
-                        const FineState& S, double* part, hipStream_t st) {
-  const Geo g = geo(n);
-  hipLaunchKernelGGL(k_dots3, grid_for(g.D, B), dim3(NT), 0, st, g, r, z, v, S, part);
-  return hipGetLastError();
-}
-
-hipError_t launch_pupdate(int n, int64_t B, const double* z, const double* v,
-                          const FineState& S, double* p, hipStream_t st) {
-  const Geo g = geo(n);
-  hipLaunchKernelGGL(k_pupdate, grid_for(g.D, B), dim3(NT), 0, st, g, z, v, S, p);
-  return hipGetLastError();
-}
-
-hipError_t launch_final_dots(int n, int64_t B, const double* v, const double* t,
-                             const double* w, const FineState& S, double* part, hipStream_t st) {
-  const Geo g = geo(n);
-  hipLaunchKernelGGL(k_final_dots, grid_for(g.D, B), dim3(NT), 0, st, g, v, t, w, S, part);
+template <typename T>
+hipError_t launch_final_dots(int n, int64_t B, const double* v, const T* t, const double* w,
+                             const FineState& S, double* part, hipStream_t st) {
+  MARCH_DISPATCH(n, {
+    const MGeo g = mgeo<NTC>(n, B);
+    hipLaunchKernelGGL((k_final_dots<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, v, t, w, S,
+                       part);
+  });
   return hipGetLastError();
 }
 
@@ -509,9 +831,36 @@ hipError_t launch_scalar(int phase, int n, int64_t B, int nblk, const double* pa
 
 hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* sigma,
                               const double* x, double* out, hipStream_t st) {
-  const Geo g = geo(n);
-  hipLaunchKernelGGL(k_apply_plain, grid_for(g.D, B), dim3(NT), 0, st, g, w, sigma, x, out);
+  if (B <= 0) return hipSuccess;
+  const int D = (n - 1) * (n - 1);
+  hipLaunchKernelGGL(k_apply_plain, dim3((D + 255) / 256, (unsigned)B), dim3(256), 0, st, n, B, w,
+                     sigma, x, out);
   return hipGetLastError();
 }
+
+#define INST(T)                                                                                 \
+  template hipError_t launch_coarsen<T>(int, int64_t, const T*, T*, hipStream_t);                \
+  template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, const double*, const T*, \
+                                          const FineState&, T*, T*, T*, T*, T*, hipStream_t);   \
+  template hipError_t launch_pupdate_apply<T>(int, int64_t, const T*, const T*, const T*,       \
+                                              const T*, const T*, const FineState&, int, T*,    \
+                                              T*, double*, hipStream_t);                        \
+  template hipError_t launch_update<T>(int, int64_t, const T*, const T*, const T*, const T*,    \
+                                       const FineState&, T*, T*, T*, hipStream_t);              \
+  template hipError_t launch_jacobi_first<T>(int, int64_t, const T*, const T*, T*,              \
+                                             const uint8_t*, hipStream_t);                      \
+  template hipError_t launch_jacobi<T>(int, int64_t, const T*, const T*, const T*, const T*,    \
+                                       T*, const uint8_t*, hipStream_t);                        \
+  template hipError_t launch_jacobi_dots<T>(int, int64_t, const T*, const T*, const T*,         \
+                                            const T*, const T*, const FineState&, T*, double*,  \
+                                            hipStream_t);                                       \
+  template hipError_t launch_resid_restrict<T>(int, int64_t, const T*, const T*, const T*, T*,  \
+                                               const uint8_t*, hipStream_t);                    \
+  template hipError_t launch_final_dots<T>(int, int64_t, const double*, const T*,               \
+                                           const double*, const FineState&, double*,            \
+                                           hipStream_t);
+INST(double)
+INST(float)
+#undef INST
 
 }  // namespace mlqmc

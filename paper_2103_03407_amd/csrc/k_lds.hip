@@ -156,24 +156,39 @@ __global__ __launch_bounds__(NT) void k_tg_small(TgSmallArgs A) {
   }
 }
 
-template <int N, int NT>
-__global__ __launch_bounds__(NT) void k_bottom(const double* __restrict__ w,
-                                               const double* __restrict__ rhs,
-                                               double* __restrict__ X,
+template <int N, int NT, typename T>
+__global__ __launch_bounds__(NT) void k_bottom(const T* __restrict__ w, const T* __restrict__ rhs,
+                                               T* __restrict__ X,
                                                const uint8_t* __restrict__ active) {
   using Mh = lds::Mesh<N>;
-  constexpr int D = Mh::D;
+  constexpr int m = N - 1, D = Mh::D, P = (N + 2) * N;
   const int64_t b = blockIdx.x;
   if (active && !active[b]) return;
   __shared__ double s_w[Mh::EW];
   __shared__ double s_b[D], s_x[D], s_r[D];
   __shared__ double s_mg[lds::mg_scratch<N>() + 1];
-  for (int e = threadIdx.x; e < Mh::EW; e += NT) s_w[e] = w[b * Mh::EW + e];
-  for (int id = threadIdx.x; id < D; id += NT) s_b[id] = rhs[b * D + id];
+  const T* WX = w + b * 2 * P;
+  const T* WY = WX + P;
+  // padded WX(j, i) = edge (i-1,j)-(i,j) at j*N + i; WY(j, i) = edge (i,j-1)-(i,j)
+  for (int e = threadIdx.x; e < Mh::EX; e += NT) {  // edge (i,j)-(i+1,j), j in [1,m], i in [0,m]
+    const int j = e / N + 1, i = e % N;
+    s_w[e] = (double)WX[j * N + i + 1];
+  }
+  for (int e = threadIdx.x; e < Mh::EY; e += NT) {  // edge (i,j)-(i,j+1), j in [0,m], i in [1,m]
+    const int j = e / m, i = e % m + 1;
+    s_w[Mh::EX + e] = (double)WY[(j + 1) * N + i];
+  }
+  for (int id = threadIdx.x; id < D; id += NT) {
+    const int i = id % m + 1, j = id / m + 1;
+    s_b[id] = (double)rhs[b * P + j * N + i];
+  }
   __syncthreads();
   lds::coarsen_all<NT, N>(s_w, s_w + Mh::EX, s_mg);
   lds::vcycle<NT, N>(s_w, s_w + Mh::EX, s_b, s_x, s_r, s_mg);
-  for (int id = threadIdx.x; id < D; id += NT) X[b * D + id] = s_x[id];
+  for (int id = threadIdx.x; id < D; id += NT) {
+    const int i = id % m + 1, j = id / m + 1;
+    X[b * P + j * N + i] = (T)s_x[id];
+  }
 }
 
 template <int N>
@@ -193,12 +208,12 @@ hipError_t tg_small_n(const TgSmallArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int N>
-hipError_t bottom_n(int64_t B, const double* w, const double* rhs, double* X,
-                    const uint8_t* active, hipStream_t st) {
+template <int N, typename T>
+hipError_t bottom_n(int64_t B, const T* w, const T* rhs, T* X, const uint8_t* active,
+                    hipStream_t st) {
   constexpr int NT = threads_for<N>();
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_bottom<N, NT>), dim3((unsigned)B), dim3(NT), 0, st, w, rhs, X, active);
+  hipLaunchKernelGGL((k_bottom<N, NT, T>), dim3((unsigned)B), dim3(NT), 0, st, w, rhs, X, active);
   return hipGetLastError();
 }
 
@@ -226,15 +241,20 @@ hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st) {
   }
 }
 
-hipError_t launch_bottom_vcycle(int NB, int64_t B, const double* w, const double* rhs, double* X,
+template <typename T>
+hipError_t launch_bottom_vcycle(int NB, int64_t B, const T* w, const T* rhs, T* X,
                                 const uint8_t* active, hipStream_t st) {
   switch (NB) {
-    case 4: return bottom_n<4>(B, w, rhs, X, active, st);
-    case 8: return bottom_n<8>(B, w, rhs, X, active, st);
-    case 16: return bottom_n<16>(B, w, rhs, X, active, st);
-    case 32: return bottom_n<32>(B, w, rhs, X, active, st);
+    case 4: return bottom_n<4, T>(B, w, rhs, X, active, st);
+    case 8: return bottom_n<8, T>(B, w, rhs, X, active, st);
+    case 16: return bottom_n<16, T>(B, w, rhs, X, active, st);
+    case 32: return bottom_n<32, T>(B, w, rhs, X, active, st);
     default: return hipErrorInvalidValue;
   }
 }
+template hipError_t launch_bottom_vcycle<double>(int, int64_t, const double*, const double*,
+                                                 double*, const uint8_t*, hipStream_t);
+template hipError_t launch_bottom_vcycle<float>(int, int64_t, const float*, const float*, float*,
+                                                const uint8_t*, hipStream_t);
 
 }  // namespace mlqmc

@@ -73,6 +73,36 @@ __global__ __launch_bounds__(256) void k_phi_edges(int n, int s, const double* _
   pw[(int64_t)j * EW + e] = v;
 }
 
+// padded [WX | WY] edge table: WX(j, i) = edge (i-1,j)-(i,j) (lower element of
+// square (i-1, j), upper of square (i-1, j-1)) at j*n + i, i in [1, n] (i = n at
+// (j+1)*n), j in [1, n-1]; WY(j, i) = edge (i,j-1)-(i,j) (upper of square
+// (i, j-1), lower of square (i-1, j-1)) at P + j*n + i, j in [1, n], i in [1, n-1];
+// P = (n+2) n.  Other positions are 0.
+__global__ __launch_bounds__(256) void k_phi_edges_padded(int n, int s,
+                                                          const double* __restrict__ pe,
+                                                          double* __restrict__ pw) {
+  const int E = 2 * n * n, P = (n + 2) * n;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int jt = blockIdx.y;
+  if (e >= 2 * P || jt >= s) return;
+  const double* el = pe + (int64_t)jt * E;
+  double v = 0.0;
+  if (e < P) {
+    int j = e / n, i = e % n;
+    if (i == 0) {
+      i = n;
+      j -= 1;
+    }
+    if (j >= 1 && j <= n - 1) v = 0.5 * (el[2 * (j * n + i - 1)] + el[2 * ((j - 1) * n + i - 1) + 1]);
+  } else {
+    const int f = e - P;
+    const int j = f / n, i = f % n;
+    if (j >= 1 && j <= n && i >= 1)
+      v = 0.5 * (el[2 * ((j - 1) * n + i) + 1] + el[2 * ((j - 1) * n + i - 1)]);
+  }
+  pw[(int64_t)jt * 2 * P + e] = v;
+}
+
 // out[b][e] = a0 + sum_j Y[b][j] phi[j][e]: 256 columns x 32 samples per block,
 // Y staged through LDS in chunks of 64 terms, phi streamed once per block.
 constexpr int kExpBS = 32, kExpJC = 64;
@@ -183,6 +213,15 @@ hipError_t launch_phi_edges(int n, int s, const double* phi_el, double* phi_edge
   const int EW = 2 * (n - 1) * n;
   hipLaunchKernelGGL(k_phi_edges, dim3((EW + 255) / 256, s), dim3(256), 0, st, n, s, phi_el,
                      phi_edge);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_edges_padded(int n, int s, const double* phi_el, double* phi_pad,
+                                   hipStream_t st) {
+  if (s <= 0) return hipSuccess;
+  const int E = 2 * (n + 2) * n;
+  hipLaunchKernelGGL(k_phi_edges_padded, dim3((E + 255) / 256, s), dim3(256), 0, st, n, s,
+                     phi_el, phi_pad);
   return hipGetLastError();
 }
 

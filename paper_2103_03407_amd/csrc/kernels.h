@@ -48,13 +48,17 @@ struct TgSmallArgs {
 };
 hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st);
 
-// One V-cycle X = K^{-1} B per active sample on mesh NB <= 32 (weights given).
-hipError_t launch_bottom_vcycle(int NB, int64_t B, const double* w, const double* rhs, double* X,
+// One V-cycle X = K^{-1} B per active sample on mesh NB <= 32 from padded global
+// arrays (weights [WX | WY], rhs, X; see k_fine.hip), computed in FP64 in LDS
+// whatever the storage type T of the global arrays.
+template <typename T>
+hipError_t launch_bottom_vcycle(int NB, int64_t B, const T* w, const T* rhs, T* X,
                                 const uint8_t* active, hipStream_t st);
 
-// ---------------- batched fine-mesh kernels (grid = blocks x samples) ----------------
+// ---------------- batched fine-mesh kernels (XCD-aware 1-D grid over samples x blocks) ----------------
 
 constexpr int kFineNT = 256;
+constexpr int kNodesPerBlock = 1024;
 
 struct FineState {      // per-sample scalars of the projected PCG, arrays of length B
   double *mu, *vs, *rho, *rz, *rz0, *alpha, *c, *c2, *beta, *lam;
@@ -64,36 +68,55 @@ struct FineState {      // per-sample scalars of the projected PCG, arrays of le
   uint8_t* flags;
 };
 
-inline int fine_blocks(int D) { return (D + kFineNT - 1) / kFineNT; }
+// blocks per sample covering the positions of rows 1..n-1 of the padded layout
+inline int fine_blocks(int n) { return (n * n - n + kNodesPerBlock - 1) / kNodesPerBlock; }
+inline int64_t padded_size(int n) { return (int64_t)(n + 2) * n; }
 
+// zero the Dirichlet positions (rows 0, n, n+1 and column 0) of cnt padded arrays
+hipError_t launch_zero_boundary(int n, int64_t B, void* const* ptrs, int cnt, int elem,
+                                hipStream_t st);
+
+// interior-layout coarse field (mesh nH) -> padded fine field (mesh nh)
 hipError_t launch_prolong(int nH, int nh, int64_t B, const double* uH, double* uh,
                           hipStream_t st);
-hipError_t launch_coarsen(int n, int64_t B, const double* w, double* wc, hipStream_t st);
+// interior layout -> interior layout (component entry point)
+hipError_t launch_prolong_interior(int nH, int nh, int64_t B, const double* uH, double* uh,
+                                   hipStream_t st);
+template <typename T>
+hipError_t launch_coarsen(int n, int64_t B, const T* w, T* wc, hipStream_t st);
+hipError_t launch_to_float(int64_t count, const double* x, float* y, hipStream_t st);
 hipError_t launch_setup_dots(int n, int64_t B, const double* v, const double* w, double* part,
                              hipStream_t st);
-hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w,
-                            const FineState& S, double* r, double* t, double* zb,
+template <typename T>
+hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64, const T* wT,
+                            const FineState& S, T* r, T* t, T* zb, T* vn, T* mvn,
                             hipStream_t st);
-hipError_t launch_apply_dots(int n, int64_t B, const double* p, const double* v, const double* w,
-                             const FineState& S, double* q, double* part, hipStream_t st);
-hipError_t launch_update(int n, int64_t B, const double* p, const double* q, const double* v,
-                         const double* w, const FineState& S, double* t, double* r, double* zb,
-                         hipStream_t st);
-hipError_t launch_jacobi_first(int n, int64_t B, const double* w, const double* rhs, double* X,
+template <typename T>
+hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
+                                const T* mvn, const T* w, const FineState& S, int first, T* pout,
+                                T* q, double* part, hipStream_t st);
+template <typename T>
+hipError_t launch_update(int n, int64_t B, const T* p, const T* q, const T* mvn, const T* w,
+                         const FineState& S, T* t, T* r, T* zb, hipStream_t st);
+template <typename T>
+hipError_t launch_jacobi_first(int n, int64_t B, const T* w, const T* rhs, T* X,
                                const uint8_t* active, hipStream_t st);
-hipError_t launch_jacobi(int n, int64_t B, const double* w, const double* rhs, const double* Xin,
-                         double* Xout, const uint8_t* active, hipStream_t st);
-hipError_t launch_resid_restrict(int n, int64_t B, const double* w, const double* rhs,
-                                 const double* X, double* rhs_c, const uint8_t* active,
-                                 hipStream_t st);
-hipError_t launch_prolong_add(int n, int64_t B, const double* Xc, double* X,
-                              const uint8_t* active, hipStream_t st);
-hipError_t launch_dots3(int n, int64_t B, const double* r, const double* z, const double* v,
-                        const FineState& S, double* part, hipStream_t st);
-hipError_t launch_pupdate(int n, int64_t B, const double* z, const double* v,
-                          const FineState& S, double* p, hipStream_t st);
-hipError_t launch_final_dots(int n, int64_t B, const double* v, const double* t,
-                             const double* w, const FineState& S, double* part, hipStream_t st);
+// Xout = sweep(Xin + P Xc) (Xc may be nullptr: no coarse correction)
+template <typename T>
+hipError_t launch_jacobi(int n, int64_t B, const T* w, const T* rhs, const T* Xin, const T* Xc,
+                         T* Xout, const uint8_t* active, hipStream_t st);
+template <typename T>
+hipError_t launch_jacobi_dots(int n, int64_t B, const T* w, const T* r, const T* zin,
+                              const T* vn, const T* mvn, const FineState& S, T* z, double* part,
+                              hipStream_t st);
+// blocks per sample of the row-marching kernels (the partial-sum count per sample)
+int march_blocks(int n);
+template <typename T>
+hipError_t launch_resid_restrict(int n, int64_t B, const T* w, const T* rhs, const T* X,
+                                 T* rhs_c, const uint8_t* active, hipStream_t st);
+template <typename T>
+hipError_t launch_final_dots(int n, int64_t B, const double* v, const T* t, const double* w,
+                             const FineState& S, double* part, hipStream_t st);
 
 // scalar phases: one wavefront per sample sums that sample's block partials
 enum ScalarPhase { PH_SETUP = 0, PH_FIRST_RZ = 1, PH_ALPHA = 2, PH_BETA = 3, PH_FINAL = 4 };
@@ -118,6 +141,9 @@ hipError_t launch_phi_elements(int n, int s, const double* c, const int* k1, con
 // edge table: the mean of the element table over the two elements of each leg
 hipError_t launch_phi_edges(int n, int s, const double* phi_el, double* phi_edge,
                             hipStream_t st);
+// the same edge table in the padded [WX | WY] layout of the batched kernels
+hipError_t launch_phi_edges_padded(int n, int s, const double* phi_el, double* phi_pad,
+                                   hipStream_t st);
 // out[b][e] = a0 + sum_{j<s} Y[b][j] phi[j][e], e < E
 hipError_t launch_expand(int64_t B, int s, int E, const double* Y, int64_t ldY,
                          const double* phi, double a0, double* out, hipStream_t st);

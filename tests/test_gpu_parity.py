@@ -347,3 +347,47 @@ def test_repeat_runs_bitwise_identical(ctx):
     ctx.eig_level((128, 64, 32, 8, 0, 0), Y, a, np.zeros(40, np.uint8))
     ctx.eig_level((128, 64, 32, 8, 0, 0), Y, b, np.zeros(40, np.uint8))
     assert np.array_equal(a, b)
+
+
+# ---------------- mixed precision (FP32 PCG/V-cycle, FP64 right-hand side and RQ) ----------------
+
+MIXED_RTOL = 1e-8
+
+
+def test_mixed_two_grid_cfg2_shape(ctx, fam):
+    cnt = 9
+    Y = np.ascontiguousarray(_points(1024, 64, 2, 0, 4, range(300, 300 + cnt)))
+    lam = np.empty(cnt)
+    fl = np.zeros(cnt, np.uint8)
+    ctx.eig_level((128, 64, 32, 8, 0, 0), Y, lam, fl, opts=m.default_opts(prec=m.MLQMC_MIXED))
+    assert not fl.any(), fl
+    for k in range(cnt):
+        tg = twogrid.two_grid(128, 64, 32, 8, Y[k], fam)[0]
+        assert abs(lam[k] - tg) <= MIXED_RTOL * tg
+
+
+def test_mixed_matches_fp64_full_batch(ctx):
+    w = CONFIGS[2]
+    lv = w.levels[0]
+    Y = np.ascontiguousarray(np.concatenate(
+        [qmc.lattice_points(w.z(0), lv.N, w.shifts(0)[r]) for r in range(w.R)]))
+    n = Y.shape[0]
+    l64, l32 = np.empty(n), np.empty(n)
+    f64, f32 = np.zeros(n, np.uint8), np.zeros(n, np.uint8)
+    ctx.eig_level(_lv6(lv), Y, l64, f64)
+    ctx.eig_level(_lv6(lv), Y, l32, f32, opts=m.default_opts(prec=m.MLQMC_MIXED))
+    assert not f64.any() and not f32.any()
+    assert _rel(l32, l64) <= MIXED_RTOL
+
+
+def test_mixed_multilevel_top_level(ctx, fam):
+    lv = LevelSpec(256, 256, 16, 16, 128, 128, 0)
+    Y = np.ascontiguousarray(_points(256, 256, 4, 4, 1, range(3)))
+    lam, lamp = np.empty(3), np.empty(3)
+    fl = np.zeros(3, np.uint8)
+    ctx.eig_level(_lv6(lv), Y, lam, fl, lam_prev=lamp, opts=m.default_opts(prec=m.MLQMC_MIXED))
+    assert not fl.any()
+    for k in range(3):
+        v = mlqmc.level_value(lv, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= MIXED_RTOL * v.lam
+        assert abs(lamp[k] - v.lam_prev) <= MIXED_RTOL * v.lam_prev
