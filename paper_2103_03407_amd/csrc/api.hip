@@ -387,13 +387,16 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     CK(launch_setup_rhs<T>(nh, Bn, v64, w64, wT, S, r, t, zb, vn, mvn, st), "setup rhs");
 
     // z = K^{-1} r: the first level-0 sweep is already in zb; the last one
-    // also forms the partial dot products r.z, M vn.z, r.vn
-    // algorithmic bytes: x, rhs, x out on the interior nodes, the 2 edge weights per node
+    // also forms the partial dot products r.z, M vn.z, r.vn.  Timed launches
+    // are those in which every sample is active (the set-up V-cycle, the first
+    // PCG step), so the byte model counts exactly the work done: x, rhs, x out
+    // and the 2 edge weights per interior node.
     const double jb = (double)sz * Bn * (5 * D(nh));
+    bool all_active = true;
     auto vcycle = [&]() -> mlqmc_status {
-      ctx->t_begin(MLQMC_K_SMOOTH);
+      if (all_active) ctx->t_begin(MLQMC_K_SMOOTH);
       CK(launch_jacobi<T>(nh, Bn, wT, r, zb, nullptr, z, act, st), "jacobi");
-      ctx->t_end(MLQMC_K_SMOOTH, jb);
+      if (all_active) ctx->t_end(MLQMC_K_SMOOTH, jb);
       CK(launch_resid_restrict<T>(nh, Bn, wT, r, z, Bv[1], act, st), "restrict");
       for (size_t k = 1; k < nL; ++k) {
         CK(launch_jacobi_first<T>(lv[k], Bn, W[k], Bv[k], Xb[k], act, st), "jacobi0");
