@@ -33,8 +33,9 @@ def _parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cfg", type=int, default=2, help="workload id (2: two-grid 1/32->1/128)")
-    ap.add_argument("--kernel-class", default="smooth",
-                    choices=["smooth", "apply", "coeff"], help="kernel timed for the roofline")
+    ap.add_argument("--kernel-class", default="post",
+                    choices=["post", "pre", "apply", "coeff"],
+                    help="kernel timed for the roofline (post: the dominant kernel)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"],
                     help="fp64, or mixed (FP32 fine PCG/V-cycle, FP64 residual and RQ)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -143,7 +144,8 @@ def main():
 
     for _ in range(a.warmup):
         step()
-    kcls = {"smooth": m.K_SMOOTH, "apply": m.K_APPLY, "coeff": m.K_COEFF}[a.kernel_class]
+    kcls = {"post": m.K_SMOOTH, "pre": m.K_PRE, "apply": m.K_APPLY,
+            "coeff": m.K_COEFF}[a.kernel_class]
     ctx.set_timing(kcls)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -157,7 +159,8 @@ def main():
     ms_per_step = 1e3 * dt / a.steps
     value = n_samples * a.steps / dt
 
-    kname = {"smooth": "k_jacobi", "apply": "k_apply_dots", "coeff": "k_expand"}[a.kernel_class]
+    kname = {"post": "k_post", "pre": "k_pre", "apply": "k_pupdate_apply",
+             "coeff": "k_expand"}[a.kernel_class]
     roof = None
     if launches > 0 and kms > 0:
         avg_ms = kms / launches

@@ -177,8 +177,9 @@ enum {
   MLQMC_K_NONE = 0,
   MLQMC_K_COEFF = 1,     /* coefficient expansion on the fine mesh */
   MLQMC_K_APPLY = 2,     /* fine operator apply inside the projected PCG */
-  MLQMC_K_SMOOTH = 3,    /* fine-level Jacobi smoothing sweeps */
-  MLQMC_K_COARSE = 4     /* coarse eigensolve (persistent chain kernel) */
+  MLQMC_K_SMOOTH = 3,    /* finest-level coarse correction + post-smoothing + PCG dots */
+  MLQMC_K_COARSE = 4,    /* coarse eigensolve (persistent chain kernel) */
+  MLQMC_K_PRE = 5        /* finest-level pre-smoothing + residual restriction */
 };
 /* Selects the kernel class whose launches are bracketed by HIP events on the
  * context's stream (MLQMC_K_NONE disables) and clears the totals. */

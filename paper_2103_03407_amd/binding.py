@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmlqmc.so")
 MLQMC_OK, MLQMC_EINVAL, MLQMC_ENOMEM, MLQMC_EDEVICE, MLQMC_ENOCONV = 0, -1, -2, -3, -4
 MLQMC_FP64, MLQMC_MIXED = 0, 1
 FLAG_RQ_NOCONV, FLAG_LIN_NOCONV, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_WRONG_PAIR = 1, 2, 4, 8, 16
-K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE = 0, 1, 2, 3, 4
+K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE, K_PRE = 0, 1, 2, 3, 4, 5
 
 # every symbol include/mlqmc.h declares
 EXPORTS = [

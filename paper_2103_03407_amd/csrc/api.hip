@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <utility>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -295,7 +296,8 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   per_sample += sz * (EW(nb) + 2 * P(nb));
   int64_t batch = o->batch > 0 ? o->batch : std::max<int64_t>(1, (int64_t)16e9 / per_sample);
   batch = std::min<int64_t>(batch, n);
-  const int nblk0 = march_blocks(nh);
+  // partial-sum counts depend on the batch size through the strip choice;
+  // the partial buffer is sized for the largest (smallest batch)
 
   std::string p = tag;
   auto nm = [&](const char* x) { return p + x; };
@@ -308,7 +310,9 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     wT = w64;
   }
   CS(ctx->getT(nm("v64").c_str(), batch * P(nh), &v64));
-  CS(ctx->getT(nm("part").c_str(), batch * nblk0 * 3, &part));
+  // blocks per sample <= (rows + 7) / 8 strips x (column blocks <= 4): bound the
+  // partial-sum buffer by the most strips any batch size can take, 3 partials each
+  CS(ctx->getT(nm("part").c_str(), batch * (4 * ((nh + 6) / 8) + 4) * 3, &part));
   const char* vnames[] = {"vn", "t", "r", "z", "zb", "q", "p0", "p1", "mvn"};
   T** vptr[] = {&vn, &t, &r, &z, &zb, &q, &pp[0], &pp[1], &mvn};
   for (int k = 0; k < 9; ++k) {
@@ -356,6 +360,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
 
   for (int64_t b0 = 0; b0 < n; b0 += batch) {
     const int64_t Bn = std::min<int64_t>(batch, n - b0);
+    const int nblk0 = march_blocks(nh, Bn);
     FineState S{};
     S.mu = const_cast<double*>(lamH) + b0;
     S.vs = sc;
@@ -384,50 +389,58 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     CK(launch_prolong(nH, nh, Bn, uH + b0 * D(nH), v64, st), "prolong");
     CK(launch_setup_dots(nh, Bn, v64, w64, part, st), "setup dots");
     CK(launch_scalar(PH_SETUP, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
-    CK(launch_setup_rhs<T>(nh, Bn, v64, w64, wT, S, r, t, zb, vn, mvn, st), "setup rhs");
+    CK(launch_setup_rhs<T>(nh, Bn, v64, w64, S, r, t, vn, mvn, st), "setup rhs");
 
-    // z = K^{-1} r: the first level-0 sweep is already in zb; the last one
-    // also forms the partial dot products r.z, M vn.z, r.vn.  Timed launches
-    // are those in which every sample is active (the set-up V-cycle, the first
-    // PCG step), so the byte model counts exactly the work done: x, rhs, x out
-    // and the 2 edge weights per interior node.
-    const double jb = (double)sz * Bn * (5 * D(nh));
+    // z = K^{-1} r by one V-cycle: fused pre-smoothing + restriction per level,
+    // the LDS bottom solve, fused coarse correction + post-smoothing per level;
+    // the level-0 post-smoothing also forms the partials r.z, M vn.z, r.vn.
+    // The result alternates between the two level-0 buffers (the post kernel
+    // cannot write in place).  Timed launches are those in which every sample is
+    // active (the set-up V-cycle, the first PCG step), so the byte model counts
+    // exactly the work done: rhs, 2 edge weights per node in; X and rhs_c out.
+    const double pre_b = (double)sz * Bn * (4.25 * D(nh));
+    // post: Xin, rhs, vn, mvn, 2 weights per node and 1/4 of a coarse vector in; Xout out
+    const double post_b = (double)sz * Bn * (7.25 * D(nh));
     bool all_active = true;
+    T* zc = z;   // current preconditioned residual
+    T* zo = zb;  // the other buffer
     auto vcycle = [&]() -> mlqmc_status {
-      if (all_active) ctx->t_begin(MLQMC_K_SMOOTH);
-      CK(launch_jacobi<T>(nh, Bn, wT, r, zb, nullptr, z, act, st), "jacobi");
-      if (all_active) ctx->t_end(MLQMC_K_SMOOTH, jb);
-      CK(launch_resid_restrict<T>(nh, Bn, wT, r, z, Bv[1], act, st), "restrict");
-      for (size_t k = 1; k < nL; ++k) {
-        CK(launch_jacobi_first<T>(lv[k], Bn, W[k], Bv[k], Xb[k], act, st), "jacobi0");
-        CK(launch_jacobi<T>(lv[k], Bn, W[k], Bv[k], Xb[k], nullptr, X[k], act, st), "jacobi");
-        CK(launch_resid_restrict<T>(lv[k], Bn, W[k], Bv[k], X[k], Bv[k + 1], act, st), "restrict");
-      }
+      if (all_active) ctx->t_begin(MLQMC_K_PRE);
+      CK(launch_pre<T>(nh, Bn, wT, r, zc, Bv[1], act, st), "pre");
+      if (all_active) ctx->t_end(MLQMC_K_PRE, pre_b);
+      for (size_t k = 1; k < nL; ++k)
+        CK(launch_pre<T>(lv[k], Bn, W[k], Bv[k], X[k], Bv[k + 1], act, st), "pre");
       CK(launch_bottom_vcycle<T>(nb, Bn, W[nL], Bv[nL], X[nL], act, st), "bottom");
+      const T* xc = X[nL];
       for (size_t k = nL - 1; k >= 1; --k) {
-        CK(launch_jacobi<T>(lv[k], Bn, W[k], Bv[k], X[k], X[k + 1], Xb[k], act, st), "jacobi");
-        CK(launch_jacobi<T>(lv[k], Bn, W[k], Bv[k], Xb[k], nullptr, X[k], act, st), "jacobi");
+        CK(launch_post<T>(lv[k], Bn, W[k], Bv[k], X[k], xc, Xb[k], nullptr, nullptr, act, nullptr,
+                          st),
+           "post");
+        xc = Xb[k];
       }
-      CK(launch_jacobi<T>(nh, Bn, wT, r, z, X[1], zb, act, st), "jacobi");
-      CK(launch_jacobi_dots<T>(nh, Bn, wT, r, zb, vn, mvn, S, z, part, st), "jacobi dots");
+      if (all_active) ctx->t_begin(MLQMC_K_SMOOTH);
+      CK(launch_post<T>(nh, Bn, wT, r, zc, xc, zo, vn, mvn, act, part, st), "post");
+      if (all_active) ctx->t_end(MLQMC_K_SMOOTH, post_b);
+      std::swap(zc, zo);
       return MLQMC_OK;
     };
     CS(vcycle());
     all_active = false;
-    CK(launch_scalar(PH_FIRST_RZ, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
+    const int nblk_post = post_strips(nh, Bn);
+    CK(launch_scalar(PH_FIRST_RZ, nh, Bn, nblk_post, part, S, 0.0, 0, st), "scalar");
     const double ab = (double)sz * Bn * (7 * D(nh));
     int cur = 0;
     for (int it = 0; it < o->max_lin_iter; ++it) {
       if (it == 0) ctx->t_begin(MLQMC_K_APPLY);
-      CK(launch_pupdate_apply<T>(nh, Bn, z, vn, pp[cur], mvn, wT, S, it == 0, pp[1 - cur], q, part,
-                                 st),
+      CK(launch_pupdate_apply<T>(nh, Bn, zc, vn, pp[cur], mvn, wT, S, it == 0, pp[1 - cur], q,
+                                 part, st),
          "apply");
       if (it == 0) ctx->t_end(MLQMC_K_APPLY, ab);
       cur = 1 - cur;
       CK(launch_scalar(PH_ALPHA, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
-      CK(launch_update<T>(nh, Bn, pp[cur], q, mvn, wT, S, t, r, zb, st), "update");
+      CK(launch_update<T>(nh, Bn, pp[cur], q, mvn, S, t, r, st), "update");
       CS(vcycle());
-      CK(launch_scalar(PH_BETA, nh, Bn, nblk0, part, S, o->lin_rtol, o->max_lin_iter, st),
+      CK(launch_scalar(PH_BETA, nh, Bn, nblk_post, part, S, o->lin_rtol, o->max_lin_iter, st),
          "scalar");
       if (it % 3 == 2 || it + 1 == o->max_lin_iter) {
         CK(hipMemcpyAsync(h_active.data(), active, Bn, hipMemcpyDeviceToHost, st), "active");
@@ -898,7 +911,7 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
 
 mlqmc_status mlqmc_set_timing(mlqmc_ctx* ctx, int32_t cls) {
   if (!ctx) return MLQMC_EINVAL;
-  if (cls < MLQMC_K_NONE || cls > MLQMC_K_COARSE) return ctx->fail(MLQMC_EINVAL, "unknown kernel class");
+  if (cls < MLQMC_K_NONE || cls > MLQMC_K_PRE) return ctx->fail(MLQMC_EINVAL, "unknown kernel class");
   ctx->timing_class = cls;
   ctx->t_launches = 0;
   ctx->t_ms = 0.0;

@@ -25,6 +25,9 @@
 // right-hand side and the Rayleigh quotient are formed in FP64 from FP64 weights
 // and the FP64 prolongated vector (lds_mg.h describes the projected solve).
 // Samples whose solve has finished are skipped (active[b] == 0).
+#include <algorithm>
+#include <cstdlib>
+
 #include "../../include/mlqmc.h"
 #include "common.h"
 #include "kernels.h"
@@ -114,6 +117,25 @@ struct MGeo {
   int64_t B;
 };
 
+// Strips per sample: as few as keep ~kTargetBlocks blocks in flight (one strip
+// per sample for large batches, so no halo row is read twice); with several
+// strips, odd strips march downwards so two neighbours read their shared halo
+// rows at the same time and the second read hits in L2.
+inline int64_t target_blocks() {
+  static int64_t v = [] {
+    const char* e = std::getenv("MLQMC_TARGET_BLOCKS");
+    const long long x = e ? std::atoll(e) : 0;
+    return (int64_t)(x > 0 ? x : 65536);
+  }();
+  return v;
+}
+inline int strips_for(int rows, int64_t units) {
+  const int64_t tb = target_blocks();
+  int s = (int)((tb + units - 1) / std::max<int64_t>(units, 1));
+  s = std::max(1, std::min(s, (rows + 7) / 8));
+  return s;
+}
+
 template <int NTC>
 inline MGeo mgeo(int n, int64_t B) {
   MGeo g;
@@ -122,16 +144,16 @@ inline MGeo mgeo(int n, int64_t B) {
   while ((1 << g.lg) < n) ++g.lg;
   g.P = (n + 2) * n;
   g.cb = n / NTC;
-  g.R = n >= 512 ? 8 : 16;
-  const int strips = (n - 1 + g.R - 1) / g.R;
-  g.nblk = g.cb * strips;
+  const int strips = strips_for(n - 1, B * g.cb);
+  g.R = (n - 1 + strips - 1) / strips;
+  g.nblk = g.cb * ((n - 1 + g.R - 1) / g.R);
   g.B = B;
   return g;
 }
 
 template <int NTC>
 __device__ __forceinline__ bool map_march(const MGeo& g, int64_t& b, int& c0, int& j0, int& j1,
-                                          int& blk) {
+                                          int& blk, int& dir) {
   const int64_t L = blockIdx.x;
   const int xcd = (int)(L & 7);
   const int64_t q = L >> 3;
@@ -139,8 +161,10 @@ __device__ __forceinline__ bool map_march(const MGeo& g, int64_t& b, int& c0, in
   blk = (int)(q % g.nblk);
   if (b >= g.B) return false;
   c0 = (blk % g.cb) * NTC;
-  j0 = 1 + (blk / g.cb) * g.R;
+  const int strip = blk / g.cb;
+  j0 = 1 + strip * g.R;
   j1 = min(j0 + g.R, g.n);
+  dir = (strip & 1) ? -1 : 1;
   return true;
 }
 
@@ -156,15 +180,19 @@ __device__ __forceinline__ void ring_fill(T (*ring)[NTC + 2], const MGeo& g, int
   if (t == NTC - 1) row[NTC + 1] = (rowok && c0 + NTC <= n - 1) ? src(j * n + c0 + NTC) : T(0);
 }
 
-// body(j, c, k, south row, centre row, north row, index of column c in the rows)
+// body(j, c, k, south row, centre row, north row, index of column c in the rows);
+// rows j0 .. j1-1 upwards (dir = 1) or downwards (dir = -1)
 template <typename T, int NTC, class Src, class Body>
 __device__ __forceinline__ void march(T (*ring)[NTC + 2], const MGeo& g, int c0, int j0, int j1,
-                                      Src src, Body body) {
+                                      int dir, Src src, Body body) {
   const int c = c0 + threadIdx.x, ci = threadIdx.x + 1;
-  ring_fill<T, NTC>(ring, g, c0, j0 - 1, src);
-  ring_fill<T, NTC>(ring, g, c0, j0, src);
-  for (int j = j0; j < j1; ++j) {
-    ring_fill<T, NTC>(ring, g, c0, j + 1, src);
+  const int first = dir > 0 ? j0 : j1 - 1;
+  const int count = j1 - j0;
+  ring_fill<T, NTC>(ring, g, c0, first - dir, src);
+  ring_fill<T, NTC>(ring, g, c0, first, src);
+  for (int i = 0; i < count; ++i) {
+    const int j = first + i * dir;
+    ring_fill<T, NTC>(ring, g, c0, j + dir, src);
     __syncthreads();
     if (c >= 1) body(j, c, j * g.n + c, ring[(j - 1) & 3], ring[j & 3], ring[(j + 1) & 3], ci);
   }
@@ -284,13 +312,13 @@ __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, const double* __rest
                                                     double* __restrict__ part) {
   __shared__ double ring[4][NTC + 2];
   int64_t b;
-  int c0, j0, j1, blk;
-  if (!map_march<NTC>(g, b, c0, j0, j1, blk)) return;
+  int c0, j0, j1, blk, dir;
+  if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir)) return;
   const double* vb = v + b * g.P;
   const double* wx = w + b * 2 * g.P;
   const double* wy = wx + g.P;
   double s[2] = {0.0, 0.0};
-  march<double, NTC>(ring, g, c0, j0, j1, [&](int k) { return vb[k]; },
+  march<double, NTC>(ring, g, c0, j0, j1, dir, [&](int k) { return vb[k]; },
                      [&](int, int, int k, const double* rs, const double* rc, const double* rn,
                          int ci) {
                        double d;
@@ -301,25 +329,21 @@ __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, const double* __rest
   write_partials_m<NTC, 2>(s, part, b, blk, g.nblk);
 }
 
-// r = -(A v_n - rho M v_n) (FP64), t = 0, zb = omega r / diag, vn = v_n, mvn = M v_n
+// r = -(A v_n - rho M v_n) (FP64), t = 0, vn = v_n, mvn = M v_n
 template <typename T, int NTC>
 __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, const double* __restrict__ v,
-                                                   const double* __restrict__ w64,
-                                                   const T* __restrict__ wT, FineState S,
+                                                   const double* __restrict__ w64, FineState S,
                                                    T* __restrict__ r, T* __restrict__ t,
-                                                   T* __restrict__ zb, T* __restrict__ vn,
-                                                   T* __restrict__ mvn) {
+                                                   T* __restrict__ vn, T* __restrict__ mvn) {
   __shared__ double ring[4][NTC + 2];
   int64_t b;
-  int c0, j0, j1, blk;
-  if (!map_march<NTC>(g, b, c0, j0, j1, blk)) return;
+  int c0, j0, j1, blk, dir;
+  if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir)) return;
   const double* vb = v + b * g.P;
   const double* wx = w64 + b * 2 * g.P;
   const double* wy = wx + g.P;
-  const T* tx = wT + b * 2 * g.P;
-  const T* ty = tx + g.P;
   const double vs = S.vs[b], rho = S.rho[b], hm = mass_scale(g.n);
-  march<double, NTC>(ring, g, c0, j0, j1, [&](int k) { return vb[k]; },
+  march<double, NTC>(ring, g, c0, j0, j1, dir, [&](int k) { return vb[k]; },
                      [&](int, int, int k, const double* rs, const double* rc, const double* rn,
                          int ci) {
                        double d;
@@ -330,7 +354,6 @@ __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, const double* __restr
                        const int64_t o = b * g.P + k;
                        r[o] = rT;
                        t[o] = T(0);
-                       zb[o] = T(kOmega) * rT / diagW(tx, ty, k, g.n);
                        vn[o] = (T)(vs * rc[ci]);
                        mvn[o] = (T)(vs * mv);
                      });
@@ -351,8 +374,8 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
                                                        double* __restrict__ part) {
   __shared__ T ring[4][NTC + 2];
   int64_t b;
-  int c0, j0, j1, blk;
-  if (!map_march<NTC>(g, b, c0, j0, j1, blk) || !S.active[b]) return;
+  int c0, j0, j1, blk, dir;
+  if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir) || !S.active[b]) return;
   const T* zz = z + b * g.P;
   const T* vb = vn + b * g.P;
   const T* pb = pin + b * g.P;
@@ -362,7 +385,7 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
   const T c2 = (T)S.c2[b], beta = first ? T(0) : (T)S.beta[b], mu = (T)S.mu[b];
   const T hm = (T)mass_scale(g.n);
   double s[3] = {0.0, 0.0, 0.0};
-  march<T, NTC>(ring, g, c0, j0, j1,
+  march<T, NTC>(ring, g, c0, j0, j1, dir,
                 [&](int k) { return zz[k] - c2 * vb[k] + (first ? T(0) : beta * pb[k]); },
                 [&](int, int, int k, const T* rs, const T* rc, const T* rn, int ci) {
                   T d;
@@ -379,137 +402,290 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
   write_partials_m<NTC, 3>(s, part, b, blk, g.nblk);
 }
 
-// t += alpha p; r -= alpha (q - c M vn); zb = omega r / diag
+// t += alpha p; r -= alpha (q - c M vn)
 template <typename T>
 __global__ __launch_bounds__(NT) void k_update(Geo g, const T* __restrict__ p,
                                                const T* __restrict__ q, const T* __restrict__ mvn,
-                                               const T* __restrict__ w, FineState S,
-                                               T* __restrict__ t, T* __restrict__ r,
-                                               T* __restrict__ zb) {
+                                               FineState S, T* __restrict__ t,
+                                               T* __restrict__ r) {
   int64_t b;
   int blk;
   if (!map_block(g, b, blk) || !S.active[b]) return;
   const T* mb = mvn + b * g.P;
-  const T* wx = w + b * 2 * g.P;
-  const T* wy = wx + g.P;
   const T alpha = (T)S.alpha[b], c = (T)S.c[b];
   FOR_NODES(g, blk) {
     const int64_t o = b * g.P + k;
     t[o] += alpha * p[o];
-    const T rn = r[o] - alpha * (q[o] - c * mb[k]);
-    r[o] = rn;
-    zb[o] = T(kOmega) * rn / diagW(wx, wy, k, g.n);
+    r[o] -= alpha * (q[o] - c * mb[k]);
   }
 }
 
 // ---------------------------------------------------------------- V-cycle
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_jacobi_first(Geo g, const T* __restrict__ w,
-                                                     const T* __restrict__ rhs,
-                                                     T* __restrict__ X,
-                                                     const uint8_t* __restrict__ active) {
-  int64_t b;
-  int blk;
-  if (!map_block(g, b, blk) || !active[b]) return;
-  const T* wx = w + b * 2 * g.P;
-  const T* wy = wx + g.P;
-  FOR_NODES(g, blk) {
-    X[b * g.P + k] = T(kOmega) * rhs[b * g.P + k] / diagW(wx, wy, k, g.n);
-  }
+// ---------------------------------------------------------------- fused V-cycle levels
+//
+// One block of NTC threads covers full rows (thread t: columns t + q NTC,
+// q < CPT = n / NTC) and runs a row pipeline over a strip with LDS rings of
+// full rows (n + 1 entries; columns 0 and n are the zero boundary).
+
+struct VGeo {
+  int n, lg, P;
+  int strips;   // strips per sample
+  int Rs;       // rows (PRE: coarse rows) per strip
+  int64_t B;
+};
+
+template <int NTC, int CPT>
+__device__ __forceinline__ bool map_strip(const VGeo& g, int64_t& b, int& s) {
+  const int64_t L = blockIdx.x;
+  const int xcd = (int)(L & 7);
+  const int64_t q = L >> 3;
+  b = ((q / g.strips) << 3) + xcd;
+  s = (int)(q % g.strips);
+  return b < g.B;
 }
 
-// Xout = Xin + omega (rhs - A Xin) / diag; with kAddCoarse the input is
-// Xin + P Xc (the coarse-grid correction, prolongated on the fly).
-template <typename T, int NTC, bool kAddCoarse>
-__global__ __launch_bounds__(NTC) void k_jacobi(MGeo g, const T* __restrict__ w,
-                                                const T* __restrict__ rhs,
-                                                const T* __restrict__ Xin,
-                                                const T* __restrict__ Xc, T* __restrict__ Xout,
-                                                const uint8_t* __restrict__ active) {
-  __shared__ T ring[4][NTC + 2];
+// stencil of A at column c of the centre ring row
+template <typename T>
+__device__ __forceinline__ T rowA(const T* rs, const T* rc, const T* rn, int c, const T* wx,
+                                  const T* wy, int k, int n, T& d) {
+  const T x = rc[c];
+  const T ww = wx[k], we = wx[k + 1], ws = wy[k], wn = wy[k + n];
+  d = ww + we + ws + wn;
+  return ww * (x - rc[c - 1]) + we * (x - rc[c + 1]) + ws * (x - rs[c]) + wn * (x - rn[c]);
+}
+
+// Pre-smoothing and restriction of one level:
+//   zb = omega rhs / D;  X = zb + omega (rhs - A zb) / D;  rhs_c = P^T (rhs - A X)
+// Strip s owns coarse rows [J0, J1) and fine rows [2 J0 - 1, 2 J1 - 1) (the last
+// strip also row n-1).
+template <typename T, int NTC, int CPT>
+__global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
+                                             const T* __restrict__ rhs, T* __restrict__ X,
+                                             T* __restrict__ rhs_c,
+                                             const uint8_t* __restrict__ active) {
+  constexpr int NR = NTC * CPT + 1;
+  __shared__ T s_zb[4][NR], s_x[4][NR], s_res[4][NR];
   int64_t b;
-  int c0, j0, j1, blk;
-  if (!map_march<NTC>(g, b, c0, j0, j1, blk) || !active[b]) return;
-  const int n = g.n, nc = n / 2;
-  const T* xb = Xin + b * g.P;
-  const T* xc = kAddCoarse ? Xc + b * (int64_t)((nc + 2) * nc) : nullptr;
+  int s;
+  if (!map_strip<NTC, CPT>(g, b, s) || !active[b]) return;
+  const int n = g.n, nc = n / 2, t = threadIdx.x;
+  const int J0 = 1 + s * g.Rs, J1 = min(J0 + g.Rs, nc);
+  const int lo = 2 * J0 - 1, hi = 2 * J1 - 1;
+  const int own_hi = (J1 == nc) ? hi + 1 : hi;  // owned fine rows [lo, own_hi)
+  const int dir = (s & 1) ? -1 : 1;             // odd strips march downwards
   const T* rb = rhs + b * g.P;
   const T* wx = w + b * 2 * g.P;
   const T* wy = wx + g.P;
-  march<T, NTC>(ring, g, c0, j0, j1,
-                [&](int k) {
-                  T v = xb[k];
-                  if constexpr (kAddCoarse) v += prolong2(xc, nc, k & (n - 1), k >> g.lg);
-                  return v;
-                },
-                [&](int, int, int k, const T* rs, const T* rc, const T* rn, int ci) {
-                  T d;
-                  const T ax = ring_A(rs, rc, rn, ci, wx, wy, k, n, d);
-                  Xout[b * g.P + k] = rc[ci] + T(kOmega) * (rb[k] - ax) / d;
-                });
+  T* xb = X + b * g.P;
+  T* cb = rhs_c + b * (int64_t)((nc + 2) * nc);
+  if (t == 0)
+    for (int r = 0; r < 4; ++r) s_zb[r][n] = s_x[r][n] = s_res[r][n] = T(0);
+  // register window of the row inputs (rhs, the 4 edge weights) of the rows at
+  // stages 1, 2 and 3: each is loaded once, at stage 1
+  T in0[CPT][5], in1[CPT][5], in2[CPT][5];
+  const int jfirst = dir > 0 ? lo - 2 : hi + 2;
+  for (int i = 0; i <= hi - lo + 4; ++i) {
+    const int j = jfirst + i * dir;
+    // stage 1: zb(j)
+    {
+      T* row = s_zb[j & 3];
+      const bool ok = (j >= 1 && j <= n - 1);
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int c = t + q * NTC, k = j * n + c;
+        T v = T(0);
+        if (ok && c >= 1) {
+          in0[q][0] = rb[k];
+          in0[q][1] = wx[k];
+          in0[q][2] = wx[k + 1];
+          in0[q][3] = wy[k];
+          in0[q][4] = wy[k + n];
+          v = T(kOmega) * in0[q][0] / (in0[q][1] + in0[q][2] + in0[q][3] + in0[q][4]);
+        }
+        row[c] = v;
+      }
+    }
+    __syncthreads();
+    // stage 2: X at the row one behind
+    const int jz = j - dir;
+    if (jz >= lo - 1 && jz <= hi + 1) {
+      T* row = s_x[jz & 3];
+      const bool ok = (jz >= 1 && jz <= n - 1);
+      const T* zs = s_zb[(jz - 1) & 3];
+      const T* zc = s_zb[jz & 3];
+      const T* zn = s_zb[(jz + 1) & 3];
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int c = t + q * NTC, k = jz * n + c;
+        T v = T(0);
+        if (ok && c >= 1) {
+          const T* in = in1[q];
+          const T x = zc[c];
+          const T d = in[1] + in[2] + in[3] + in[4];
+          const T ax = in[1] * (x - zc[c - 1]) + in[2] * (x - zc[c + 1]) + in[3] * (x - zs[c]) +
+                       in[4] * (x - zn[c]);
+          v = x + T(kOmega) * (in[0] - ax) / d;
+          if (jz >= lo && jz < own_hi) xb[k] = v;
+        }
+        row[c] = v;
+      }
+    }
+    __syncthreads();
+    // stage 3: residual two rows behind
+    const int jr = j - 2 * dir;
+    if (jr >= lo && jr <= hi) {
+      T* row = s_res[jr & 3];
+      const T* xs = s_x[(jr - 1) & 3];
+      const T* xc = s_x[jr & 3];
+      const T* xn = s_x[(jr + 1) & 3];
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int c = t + q * NTC;
+        T v = T(0);
+        if (c >= 1) {
+          const T* in = in2[q];
+          const T x = xc[c];
+          v = in[0] - (in[1] * (x - xc[c - 1]) + in[2] * (x - xc[c + 1]) + in[3] * (x - xs[c]) +
+                       in[4] * (x - xn[c]));
+        }
+        row[c] = v;
+      }
+      __syncthreads();
+      // stage 4: restriction at the coarse row J whose residual rows 2J-1..2J+1
+      // are complete (jr = 2J+1 upwards, 2J-1 downwards)
+      if ((jr & 1) && (dir > 0 ? jr >= lo + 2 : jr <= hi - 2)) {
+        const int J = dir > 0 ? (jr - 1) >> 1 : (jr + 1) >> 1;
+        const T* rs = s_res[(2 * J - 1) & 3];
+        const T* rc = s_res[(2 * J) & 3];
+        const T* rn = s_res[(2 * J + 1) & 3];
+        for (int I = t + 1; I <= nc - 1; I += NTC) {
+          const int c = 2 * I;
+          cb[J * nc + I] = rc[c] + T(0.5) * (rc[c - 1] + rc[c + 1] + rs[c] + rn[c] + rn[c + 1] +
+                                             rs[c - 1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CPT; ++q)
+#pragma unroll
+      for (int e = 0; e < 5; ++e) {
+        in2[q][e] = in1[q][e];
+        in1[q][e] = in0[q][e];
+      }
+  }
 }
 
-// The last post-smoothing sweep of level 0 fused with the dot products of the
-// preconditioned residual: z = sweep(zin); partials r.z, M vn.z, r.vn.
-template <typename T, int NTC>
-__global__ __launch_bounds__(NTC) void k_jacobi_dots(MGeo g, const T* __restrict__ w,
-                                                     const T* __restrict__ r,
-                                                     const T* __restrict__ zin,
-                                                     const T* __restrict__ vn,
-                                                     const T* __restrict__ mvn, FineState S,
-                                                     T* __restrict__ z,
-                                                     double* __restrict__ part) {
-  __shared__ T ring[4][NTC + 2];
+// Post-smoothing of one level: U = Xin + P Xc; two sweeps; Xout.  On level 0
+// (kDots) the last sweep also forms the partials r.z, M vn.z, r.vn.  Strip s
+// owns fine rows [f0, f1).  Xout must differ from Xin (neighbour strips read
+// Xin rows across the strip boundary).
+template <typename T, int NTC, int CPT, bool kDots>
+__global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
+                                              const T* __restrict__ rhs,
+                                              const T* __restrict__ Xin,
+                                              const T* __restrict__ Xc, T* __restrict__ Xout,
+                                              const T* __restrict__ vn, const T* __restrict__ mvn,
+                                              const uint8_t* __restrict__ active,
+                                              double* __restrict__ part) {
+  constexpr int NR = NTC * CPT + 1;
+  __shared__ T s_u[4][NR], s_zb[4][NR];
   int64_t b;
-  int c0, j0, j1, blk;
-  if (!map_march<NTC>(g, b, c0, j0, j1, blk) || !S.active[b]) return;
-  const T* xb = zin + b * g.P;
-  const T* vb = vn + b * g.P;
-  const T* mb = mvn + b * g.P;
-  const T* rb = r + b * g.P;
+  int s;
+  if (!map_strip<NTC, CPT>(g, b, s) || !active[b]) return;
+  const int n = g.n, nc = n / 2, t = threadIdx.x;
+  const int f0 = 1 + s * g.Rs, f1 = min(f0 + g.Rs, n);
+  const int dir = (s & 1) ? -1 : 1;             // odd strips march downwards
+  const T* rb = rhs + b * g.P;
+  const T* xi = Xin + b * g.P;
+  const T* xc = Xc + b * (int64_t)((nc + 2) * nc);
   const T* wx = w + b * 2 * g.P;
   const T* wy = wx + g.P;
-  double s[3] = {0.0, 0.0, 0.0};
-  march<T, NTC>(ring, g, c0, j0, j1, [&](int k) { return xb[k]; },
-                [&](int, int, int k, const T* rs, const T* rc, const T* rn, int ci) {
-                  T d;
-                  const T ax = ring_A(rs, rc, rn, ci, wx, wy, k, g.n, d);
-                  const T rr = rb[k];
-                  const T zz = rc[ci] + T(kOmega) * (rr - ax) / d;
-                  z[b * g.P + k] = zz;
-                  s[0] += (double)rr * (double)zz;
-                  s[1] += (double)mb[k] * (double)zz;
-                  s[2] += (double)rr * (double)vb[k];
-                });
-  write_partials_m<NTC, 3>(s, part, b, blk, g.nblk);
-}
-
-// rhs_c = P^T (rhs - A X) on mesh n/2: fine node (2I, 2J) with weight 1, its
-// E, W, N, S, NE, SW neighbours with weight 1/2 (all interior).
-template <typename T>
-__global__ __launch_bounds__(NT) void k_resid_restrict(Geo gc, const T* __restrict__ w,
-                                                       const T* __restrict__ rhs,
-                                                       const T* __restrict__ X,
-                                                       T* __restrict__ rhs_c,
-                                                       const uint8_t* __restrict__ active) {
-  int64_t b;
-  int blk;
-  if (!map_block(gc, b, blk) || !active[b]) return;
-  const int n = 2 * gc.n, P = (n + 2) * n;
-  const T* xb = X + b * P;
-  const T* rb = rhs + b * P;
-  const T* wx = w + b * 2 * P;
-  const T* wy = wx + P;
-  FOR_NODES(gc, blk) {
-    const int I = k & (gc.n - 1), J = k >> gc.lg;
-    const int kf = 2 * J * n + 2 * I;
-    auto res = [&](int kk) -> T {
-      T d;
-      return rb[kk] - applyA(xb, wx, wy, kk, n, d);
-    };
-    rhs_c[b * gc.P + k] = res(kf) + T(0.5) * (res(kf - 1) + res(kf + 1) + res(kf - n) +
-                                              res(kf + n) + res(kf + n + 1) + res(kf - n - 1));
+  T* xo = Xout + b * g.P;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (t == 0)
+    for (int r = 0; r < 4; ++r) s_u[r][n] = s_zb[r][n] = T(0);
+  // row inputs (rhs, 4 edge weights) loaded at stage 2 and reused at stage 3
+  T in1[CPT][5], in2[CPT][5];
+  const int jfirst = dir > 0 ? f0 - 2 : f1 + 1;
+  for (int i = 0; i <= f1 - f0 + 3; ++i) {
+    const int j = jfirst + i * dir;
+    {
+      T* row = s_u[j & 3];
+      const bool ok = (j >= 1 && j <= n - 1);
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int c = t + q * NTC, k = j * n + c;
+        row[c] = (ok && c >= 1) ? xi[k] + prolong2(xc, nc, c, j) : T(0);
+      }
+    }
+    __syncthreads();
+    const int j1 = j - dir;
+    if (j1 >= f0 - 1 && j1 <= f1) {
+      T* row = s_zb[j1 & 3];
+      const bool ok = (j1 >= 1 && j1 <= n - 1);
+      const T* us = s_u[(j1 - 1) & 3];
+      const T* uc = s_u[j1 & 3];
+      const T* un = s_u[(j1 + 1) & 3];
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int c = t + q * NTC, k = j1 * n + c;
+        T v = T(0);
+        if (ok && c >= 1) {
+          T* in = in1[q];
+          in[0] = rb[k];
+          in[1] = wx[k];
+          in[2] = wx[k + 1];
+          in[3] = wy[k];
+          in[4] = wy[k + n];
+          const T x = uc[c];
+          const T d = in[1] + in[2] + in[3] + in[4];
+          const T ax = in[1] * (x - uc[c - 1]) + in[2] * (x - uc[c + 1]) + in[3] * (x - us[c]) +
+                       in[4] * (x - un[c]);
+          v = x + T(kOmega) * (in[0] - ax) / d;
+        }
+        row[c] = v;
+      }
+    }
+    __syncthreads();
+    const int j2 = j - 2 * dir;
+    if (j2 >= f0 && j2 < f1) {
+      const T* zs = s_zb[(j2 - 1) & 3];
+      const T* zc = s_zb[j2 & 3];
+      const T* zn = s_zb[(j2 + 1) & 3];
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int c = t + q * NTC, k = j2 * n + c;
+        if (c >= 1) {
+          const T* in = in2[q];
+          const T x = zc[c];
+          const T d = in[1] + in[2] + in[3] + in[4];
+          const T ax = in[1] * (x - zc[c - 1]) + in[2] * (x - zc[c + 1]) + in[3] * (x - zs[c]) +
+                       in[4] * (x - zn[c]);
+          const T zz = x + T(kOmega) * (in[0] - ax) / d;
+          xo[k] = zz;
+          if constexpr (kDots) {
+            acc[0] += (double)in[0] * (double)zz;
+            acc[1] += (double)mvn[b * g.P + k] * (double)zz;
+            acc[2] += (double)in[0] * (double)vn[b * g.P + k];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CPT; ++q)
+#pragma unroll
+      for (int e = 0; e < 5; ++e) in2[q][e] = in1[q][e];
+  }
+  if constexpr (kDots) {
+    __shared__ double red[3 * (NTC / 64)];
+    block_sums<NTC, 3>(acc, red);
+    if (threadIdx.x == 0) {
+      const int64_t base = (b * g.strips + s) * 3;
+      part[base] = acc[0];
+      part[base + 1] = acc[1];
+      part[base + 2] = acc[2];
+    }
   }
 }
 
@@ -523,15 +699,15 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, const double* __rest
                                                     double* __restrict__ part) {
   __shared__ double ring[4][NTC + 2];
   int64_t b;
-  int c0, j0, j1, blk;
-  if (!map_march<NTC>(g, b, c0, j0, j1, blk)) return;
+  int c0, j0, j1, blk, dir;
+  if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir)) return;
   const double* vb = v + b * g.P;
   const T* tb = t + b * g.P;
   const double vs = S.vs[b];
   const double* wx = w + b * 2 * g.P;
   const double* wy = wx + g.P;
   double s[2] = {0.0, 0.0};
-  march<double, NTC>(ring, g, c0, j0, j1, [&](int k) { return vs * vb[k] + (double)tb[k]; },
+  march<double, NTC>(ring, g, c0, j0, j1, dir, [&](int k) { return vs * vb[k] + (double)tb[k]; },
                      [&](int, int, int k, const double* rs, const double* rc, const double* rn,
                          int ci) {
                        double d;
@@ -729,13 +905,12 @@ hipError_t launch_setup_dots(int n, int64_t B, const double* v, const double* w,
 }
 
 template <typename T>
-hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64, const T* wT,
-                            const FineState& S, T* r, T* t, T* zb, T* vn, T* mvn,
-                            hipStream_t st) {
+hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64,
+                            const FineState& S, T* r, T* t, T* vn, T* mvn, hipStream_t st) {
   MARCH_DISPATCH(n, {
     const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_setup_rhs<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, v, w64, wT, S, r,
-                       t, zb, vn, mvn);
+    hipLaunchKernelGGL((k_setup_rhs<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, v, w64, S, r, t,
+                       vn, mvn);
   });
   return hipGetLastError();
 }
@@ -753,61 +928,96 @@ hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const
 }
 
 template <typename T>
-hipError_t launch_update(int n, int64_t B, const T* p, const T* q, const T* mvn, const T* w,
-                         const FineState& S, T* t, T* r, T* zb, hipStream_t st) {
+hipError_t launch_update(int n, int64_t B, const T* p, const T* q, const T* mvn,
+                         const FineState& S, T* t, T* r, hipStream_t st) {
   const Geo g = geo(n, B);
-  hipLaunchKernelGGL(k_update<T>, grid_of(g), dim3(NT), 0, st, g, p, q, mvn, w, S, t, r, zb);
+  hipLaunchKernelGGL(k_update<T>, grid_of(g), dim3(NT), 0, st, g, p, q, mvn, S, t, r);
+  return hipGetLastError();
+}
+
+// fused V-cycle launches: (NTC, CPT) = (64,1), (128,1), (256,1), (256,2), (256,4)
+#define ROW_DISPATCH(n, BODY)                               \
+  do {                                                      \
+    if ((n) <= 64) {                                        \
+      constexpr int NTC = 64, CPT = 1;                      \
+      BODY;                                                 \
+    } else if ((n) == 128) {                                \
+      constexpr int NTC = 128, CPT = 1;                     \
+      BODY;                                                 \
+    } else if ((n) == 256) {                                \
+      constexpr int NTC = 256, CPT = 1;                     \
+      BODY;                                                 \
+    } else if ((n) == 512) {                                \
+      constexpr int NTC = 256, CPT = 2;                     \
+      BODY;                                                 \
+    } else {                                                \
+      constexpr int NTC = 256, CPT = 4;                     \
+      BODY;                                                 \
+    }                                                       \
+  } while (0)
+
+
+inline VGeo vgeo_pre(int n, int64_t B) {
+  VGeo g;
+  g.n = n;
+  g.lg = 0;
+  while ((1 << g.lg) < n) ++g.lg;
+  g.P = (n + 2) * n;
+  const int rows = n / 2 - 1;  // coarse rows
+  const int st = strips_for(rows, B);
+  g.Rs = (rows + st - 1) / st;
+  g.strips = (rows + g.Rs - 1) / g.Rs;
+  g.B = B;
+  return g;
+}
+inline VGeo vgeo_post(int n, int64_t B) {
+  VGeo g = vgeo_pre(n, B);
+  const int rows = n - 1;
+  const int st = strips_for(rows, B);
+  g.Rs = (rows + st - 1) / st;
+  g.strips = (rows + g.Rs - 1) / g.Rs;
+  return g;
+}
+inline dim3 sgrid(const VGeo& g) {
+  const int64_t Bp = (g.B + 7) / 8 * 8;
+  return dim3((unsigned)(Bp * g.strips));
+}
+
+template <typename T>
+hipError_t launch_pre(int n, int64_t B, const T* w, const T* rhs, T* X, T* rhs_c,
+                      const uint8_t* active, hipStream_t st) {
+  const VGeo g = vgeo_pre(n, B);
+  ROW_DISPATCH(n, {
+    if (NTC * CPT != n) return hipErrorInvalidValue;  // a block covers one full row
+    hipLaunchKernelGGL((k_pre<T, NTC, CPT>), sgrid(g), dim3(NTC), 0, st, g, w, rhs, X, rhs_c,
+                       active);
+  });
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_jacobi_first(int n, int64_t B, const T* w, const T* rhs, T* X,
-                               const uint8_t* active, hipStream_t st) {
-  const Geo g = geo(n, B);
-  hipLaunchKernelGGL(k_jacobi_first<T>, grid_of(g), dim3(NT), 0, st, g, w, rhs, X, active);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_jacobi(int n, int64_t B, const T* w, const T* rhs, const T* Xin, const T* Xc,
-                         T* Xout, const uint8_t* active, hipStream_t st) {
-  MARCH_DISPATCH(n, {
-    const MGeo g = mgeo<NTC>(n, B);
-    if (Xc)
-      hipLaunchKernelGGL((k_jacobi<T, NTC, true>), mgrid<NTC>(g), dim3(NTC), 0, st, g, w, rhs, Xin,
-                         Xc, Xout, active);
+hipError_t launch_post(int n, int64_t B, const T* w, const T* rhs, const T* Xin, const T* Xc,
+                       T* Xout, const T* vn, const T* mvn, const uint8_t* active, double* part,
+                       hipStream_t st) {
+  const VGeo g = vgeo_post(n, B);
+  ROW_DISPATCH(n, {
+    if (NTC * CPT != n) return hipErrorInvalidValue;  // a block covers one full row
+    if (part)
+      hipLaunchKernelGGL((k_post<T, NTC, CPT, true>), sgrid(g), dim3(NTC), 0, st, g, w, rhs, Xin,
+                         Xc, Xout, vn, mvn, active, part);
     else
-      hipLaunchKernelGGL((k_jacobi<T, NTC, false>), mgrid<NTC>(g), dim3(NTC), 0, st, g, w, rhs,
-                         Xin, Xc, Xout, active);
+      hipLaunchKernelGGL((k_post<T, NTC, CPT, false>), sgrid(g), dim3(NTC), 0, st, g, w, rhs, Xin,
+                         Xc, Xout, vn, mvn, active, part);
   });
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_jacobi_dots(int n, int64_t B, const T* w, const T* r, const T* zin,
-                              const T* vn, const T* mvn, const FineState& S, T* z, double* part,
-                              hipStream_t st) {
-  MARCH_DISPATCH(n, {
-    const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_jacobi_dots<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, w, r, zin, vn,
-                       mvn, S, z, part);
-  });
-  return hipGetLastError();
-}
+int post_strips(int n, int64_t B) { return vgeo_post(n, B).strips; }
 
-int march_blocks(int n) {
+int march_blocks(int n, int64_t B) {
   int nb = 0;
-  MARCH_DISPATCH(n, { nb = mgeo<NTC>(n, 1).nblk; });
+  MARCH_DISPATCH(n, { nb = mgeo<NTC>(n, B).nblk; });
   return nb;
-}
-
-template <typename T>
-hipError_t launch_resid_restrict(int n, int64_t B, const T* w, const T* rhs, const T* X,
-                                 T* rhs_c, const uint8_t* active, hipStream_t st) {
-  const Geo gc = geo(n / 2, B);
-  hipLaunchKernelGGL(k_resid_restrict<T>, grid_of(gc), dim3(NT), 0, st, gc, w, rhs, X, rhs_c,
-                     active);
-  return hipGetLastError();
 }
 
 template <typename T>
@@ -840,25 +1050,24 @@ hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* s
 
 #define INST(T)                                                                                 \
   template hipError_t launch_coarsen<T>(int, int64_t, const T*, T*, hipStream_t);                \
-  template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, const double*, const T*, \
-                                          const FineState&, T*, T*, T*, T*, T*, hipStream_t);   \
+  template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, const double*,           \
+                                          const FineState&, T*, T*, T*, T*, hipStream_t);       \
   template hipError_t launch_pupdate_apply<T>(int, int64_t, const T*, const T*, const T*,       \
                                               const T*, const T*, const FineState&, int, T*,    \
                                               T*, double*, hipStream_t);                        \
-  template hipError_t launch_update<T>(int, int64_t, const T*, const T*, const T*, const T*,    \
-                                       const FineState&, T*, T*, T*, hipStream_t);              \
-  template hipError_t launch_jacobi_first<T>(int, int64_t, const T*, const T*, T*,              \
-                                             const uint8_t*, hipStream_t);                      \
-  template hipError_t launch_jacobi<T>(int, int64_t, const T*, const T*, const T*, const T*,    \
-                                       T*, const uint8_t*, hipStream_t);                        \
-  template hipError_t launch_jacobi_dots<T>(int, int64_t, const T*, const T*, const T*,         \
-                                            const T*, const T*, const FineState&, T*, double*,  \
-                                            hipStream_t);                                       \
-  template hipError_t launch_resid_restrict<T>(int, int64_t, const T*, const T*, const T*, T*,  \
-                                               const uint8_t*, hipStream_t);                    \
+  template hipError_t launch_update<T>(int, int64_t, const T*, const T*, const T*,              \
+                                       const FineState&, T*, T*, hipStream_t);                  \
   template hipError_t launch_final_dots<T>(int, int64_t, const double*, const T*,               \
                                            const double*, const FineState&, double*,            \
                                            hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+#define INST(T)                                                                                 \
+  template hipError_t launch_pre<T>(int, int64_t, const T*, const T*, T*, T*, const uint8_t*,   \
+                                    hipStream_t);                                               \
+  template hipError_t launch_post<T>(int, int64_t, const T*, const T*, const T*, const T*, T*,  \
+                                     const T*, const T*, const uint8_t*, double*, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

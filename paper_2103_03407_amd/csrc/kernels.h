@@ -88,32 +88,31 @@ hipError_t launch_to_float(int64_t count, const double* x, float* y, hipStream_t
 hipError_t launch_setup_dots(int n, int64_t B, const double* v, const double* w, double* part,
                              hipStream_t st);
 template <typename T>
-hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64, const T* wT,
-                            const FineState& S, T* r, T* t, T* zb, T* vn, T* mvn,
-                            hipStream_t st);
+hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64,
+                            const FineState& S, T* r, T* t, T* vn, T* mvn, hipStream_t st);
 template <typename T>
 hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
                                 const T* mvn, const T* w, const FineState& S, int first, T* pout,
                                 T* q, double* part, hipStream_t st);
 template <typename T>
-hipError_t launch_update(int n, int64_t B, const T* p, const T* q, const T* mvn, const T* w,
-                         const FineState& S, T* t, T* r, T* zb, hipStream_t st);
+hipError_t launch_update(int n, int64_t B, const T* p, const T* q, const T* mvn,
+                         const FineState& S, T* t, T* r, hipStream_t st);
+// fused V-cycle level, pre-smoothing from zero and restriction:
+//   X = two damped-Jacobi sweeps on A X = rhs from X = 0; rhs_c = P^T (rhs - A X)
 template <typename T>
-hipError_t launch_jacobi_first(int n, int64_t B, const T* w, const T* rhs, T* X,
-                               const uint8_t* active, hipStream_t st);
-// Xout = sweep(Xin + P Xc) (Xc may be nullptr: no coarse correction)
+hipError_t launch_pre(int n, int64_t B, const T* w, const T* rhs, T* X, T* rhs_c,
+                      const uint8_t* active, hipStream_t st);
+// fused V-cycle level, coarse correction and post-smoothing:
+//   Xout = two sweeps from Xin + P Xc; with part != nullptr also the partials
+//   rhs.Xout, mvn.Xout, rhs.vn per strip (level 0 of the projected PCG)
 template <typename T>
-hipError_t launch_jacobi(int n, int64_t B, const T* w, const T* rhs, const T* Xin, const T* Xc,
-                         T* Xout, const uint8_t* active, hipStream_t st);
-template <typename T>
-hipError_t launch_jacobi_dots(int n, int64_t B, const T* w, const T* r, const T* zin,
-                              const T* vn, const T* mvn, const FineState& S, T* z, double* part,
-                              hipStream_t st);
-// blocks per sample of the row-marching kernels (the partial-sum count per sample)
-int march_blocks(int n);
-template <typename T>
-hipError_t launch_resid_restrict(int n, int64_t B, const T* w, const T* rhs, const T* X,
-                                 T* rhs_c, const uint8_t* active, hipStream_t st);
+hipError_t launch_post(int n, int64_t B, const T* w, const T* rhs, const T* Xin, const T* Xc,
+                       T* Xout, const T* vn, const T* mvn, const uint8_t* active, double* part,
+                       hipStream_t st);
+// strips per sample of launch_post for a batch of B (its partial-sum count per sample)
+int post_strips(int n, int64_t B);
+// blocks per sample of the row-marching kernels for a batch of B (their partial-sum count)
+int march_blocks(int n, int64_t B);
 template <typename T>
 hipError_t launch_final_dots(int n, int64_t B, const double* v, const T* t, const double* w,
                              const FineState& S, double* part, hipStream_t st);
