@@ -80,10 +80,33 @@ def cpu_baseline(cfg_id: int, seconds: float):
         vals = pool.map(_oracle_worker, idx, chunksize=1)
     dt = time.perf_counter() - t0
     assert all(math.isfinite(v) for v in vals)
-    return {"value": count / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
+    base = {"value": count / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
             "sample": f"{count} of the {n_total} two-grid eigen-samples of the workload "
                       f"(strided lattice indices), scipy/SuperLU FP64, {cores} processes, "
                       f"{dt:.1f} s"}
+    return base, [i for _, i in idx], vals
+
+
+def accuracy(ctx, m, w, opts, idx, ref):
+    """Per-sample relative eigenvalue error of the GPU path against the
+    oracle values of the CPU-baseline sample (same lattice indices), from one
+    untimed eig_level call over the whole workload with the bench options."""
+    import numpy as np
+    lv = w.levels[0]
+    z, sh = w.z(0), w.shifts(0)
+    n = w.R * lv.N
+    Y = np.empty((n, lv.s_fine))
+    for r in range(w.R):
+        ctx.lattice_points(lv.N, z, sh[r], 0, lv.N, Y[r * lv.N:(r + 1) * lv.N])
+    lam = np.empty(n)
+    fl = np.zeros(n, np.uint8)
+    level = (lv.n_fine, lv.s_fine, lv.n_coarse, lv.s_coarse, lv.n_prev, lv.s_prev)
+    ctx.eig_level(level, Y, lam, fl, opts=opts)
+    ref = np.asarray(ref)
+    err = np.abs(lam[np.asarray(idx)] - ref) / np.abs(ref)
+    return {"max_rel_err": float(err.max()), "median_rel_err": float(np.median(err)),
+            "samples": int(err.size), "flagged": int((fl != 0).sum()),
+            "bound": 1e-10 if opts.prec == m.MLQMC_FP64 else 1e-8}
 
 
 def _traffic(kernel: str):
@@ -171,9 +194,10 @@ def main():
                 "traffic": _traffic(kname), "avg_launch_us": round(avg_ms * 1e3, 2),
                 "launches": launches, "algorithmic_bytes_per_launch": bytes_per_launch}
 
-    cpu = None
+    cpu = acc = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(a.cfg, a.cpu_seconds)
+        cpu, idx, ref = cpu_baseline(a.cfg, a.cpu_seconds)
+        acc = accuracy(ctx, m, w, opts, idx, ref)
 
     out = {
         "metric": "two-grid eigen-samples/sec per level; stencil HBM GB/s in roofline",
@@ -184,7 +208,7 @@ def main():
         "config": {"workload": w.name, "h": f"1/{lv.n_fine}", "H": f"1/{lv.n_coarse}",
                    "s": lv.s_fine, "S": lv.s_coarse, "N": lv.N, "R": w.R,
                    "samples_per_step": n_samples, "estimate": est[0]},
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "accuracy_vs_oracle": acc,
     }
     print(json.dumps(out), flush=True)
     return 0

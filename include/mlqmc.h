@@ -84,7 +84,12 @@ typedef struct {
                                 the iteration converges cubically, so the returned
                                 sigma_k is accurate far below eig_rtol */
   int32_t max_rq_iter;       /* cap on RQ iterations per coarse eigensolve */
-  double lin_rtol;           /* fine two-grid solve: projected PCG stops at sqrt(r.z / r0.z0) <= lin_rtol */
+  double lin_rtol;           /* fine two-grid solve: projected PCG stops at sqrt(r.z / r0.z0) <= lin_rtol
+                                (0 = the precision's default: FP64 1e-10, mixed 1e-7) ... */
+  double lam_rtol;           /* ... or when the estimated error of the Rayleigh quotient of the
+                                current iterate is <= lam_rtol * lambda (0 = default: FP64 5e-12,
+                                mixed 5e-10, a factor >= 10 inside the stated accuracies 1e-10
+                                and 1e-8) */
   double rq_lin_rtol;        /* the same test for the inner solves of the RQ iteration */
   int32_t max_lin_iter;      /* cap on PCG iterations per linear solve */
   int32_t chain_len;         /* samples per warm-start chain (<=0: library default) */
@@ -94,7 +99,8 @@ typedef struct {
 } mlqmc_opts;
 
 /* Fills *opt with the defaults (FP64, eig_rtol 1e-8, max_rq_iter 12,
- * lin_rtol 1e-6, rq_lin_rtol 1e-4, max_lin_iter 60, io_on_device 0). */
+ * lin_rtol 0 and lam_rtol 0 (per precision), rq_lin_rtol 1e-4, max_lin_iter 60,
+ * io_on_device 0). */
 void mlqmc_default_opts(mlqmc_opts* opt);
 
 /* Creates a context on HIP device `device`, enqueueing on `hip_stream`

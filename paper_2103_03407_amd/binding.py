@@ -48,7 +48,7 @@ class Level(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("eig_rtol", C.c_double), ("max_rq_iter", C.c_int32),
-                ("lin_rtol", C.c_double), ("rq_lin_rtol", C.c_double),
+                ("lin_rtol", C.c_double), ("lam_rtol", C.c_double), ("rq_lin_rtol", C.c_double),
                 ("max_lin_iter", C.c_int32), ("chain_len", C.c_int32), ("batch", C.c_int32),
                 ("io_on_device", C.c_int32), ("device_mem_cap", C.c_int64)]
 

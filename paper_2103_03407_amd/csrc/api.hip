@@ -221,12 +221,27 @@ mlqmc_status stage_out(mlqmc_ctx* ctx, T* dst, const T* dev, size_t n, int on_de
   return MLQMC_OK;
 }
 
+// Two-grid solve stopping tests; 0 selects the precision's default.
+// lin_rtol bounds the preconditioned residual, sqrt(r.z / r0.z0).  lam_rtol
+// bounds the estimated error of the Rayleigh quotient of v + t_k, which the
+// PCG tracks from its own dots: the solve stops as soon as the eigenvalue,
+// the quantity returned, is settled.  The defaults leave the eigenvalues a
+// factor of at least 10 inside the stated accuracies (FP64 1e-10, mixed 1e-8).
+double lin_tol(const mlqmc_opts* o) {
+  if (o->lin_rtol > 0) return o->lin_rtol;
+  return o->prec == MLQMC_MIXED ? 1e-7 : 1e-10;
+}
+double lam_tol(const mlqmc_opts* o) {
+  if (o->lam_rtol > 0) return o->lam_rtol;
+  return o->prec == MLQMC_MIXED ? 5e-10 : 5e-12;
+}
+
 mlqmc_status check_opts(mlqmc_ctx* ctx, const mlqmc_opts* o) {
   if (!o) return ctx->fail(MLQMC_EINVAL, "opts is NULL");
   if (o->prec != MLQMC_FP64 && o->prec != MLQMC_MIXED)
     return ctx->fail(MLQMC_EINVAL, "unknown precision %d", o->prec);
-  if (!(o->eig_rtol > 0) || !(o->lin_rtol > 0) || !(o->rq_lin_rtol > 0))
-    return ctx->fail(MLQMC_EINVAL, "tolerances must be positive");
+  if (!(o->eig_rtol > 0) || !(o->lin_rtol >= 0) || !(o->lam_rtol >= 0) || !(o->rq_lin_rtol > 0))
+    return ctx->fail(MLQMC_EINVAL, "tolerances must be positive (lin_rtol, lam_rtol: >= 0)");
   if (o->max_rq_iter < 1 || o->max_lin_iter < 1)
     return ctx->fail(MLQMC_EINVAL, "iteration caps must be >= 1");
   if (o->device_mem_cap < 0) return ctx->fail(MLQMC_EINVAL, "device_mem_cap must be >= 0");
@@ -312,7 +327,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   CS(ctx->getT(nm("v64").c_str(), batch * P(nh), &v64));
   // blocks per sample <= (rows + 7) / 8 strips x (column blocks <= 4): bound the
   // partial-sum buffer by the most strips any batch size can take, 3 partials each
-  CS(ctx->getT(nm("part").c_str(), batch * (4 * ((nh + 6) / 8) + 4) * 3, &part));
+  CS(ctx->getT(nm("part").c_str(), batch * (4 * ((nh + 6) / 8) + 4) * 6, &part));
   const char* vnames[] = {"vn", "t", "r", "z", "zb", "q", "p0", "p1", "mvn"};
   T** vptr[] = {&vn, &t, &r, &z, &zb, &q, &pp[0], &pp[1], &mvn};
   for (int k = 0; k < 9; ++k) {
@@ -351,11 +366,12 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     }
   }
   double* sc = nullptr;
-  CS(ctx->getT(nm("scal").c_str(), batch * 9, &sc));
+  CS(ctx->getT(nm("scal").c_str(), batch * 11, &sc));
   int* its = nullptr;
   CS(ctx->getT(nm("its").c_str(), batch, &its));
-  uint8_t* active = nullptr;
+  uint8_t *active = nullptr, *vact = nullptr;
   CS(ctx->getT(nm("active").c_str(), batch, &active));
+  CS(ctx->getT(nm("vact").c_str(), batch, &vact));
   std::vector<uint8_t> h_active(batch);
 
   for (int64_t b0 = 0; b0 < n; b0 += batch) {
@@ -371,13 +387,17 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     S.c = sc + 5 * batch;
     S.c2 = sc + 6 * batch;
     S.beta = sc + 7 * batch;
+    S.f = sc + 8 * batch;
+    S.m = sc + 9 * batch;
+    S.dl = sc + 10 * batch;
     S.lam = lam + b0;
     S.its = its;
     S.lin_acc = lin_iters ? lin_iters + b0 : nullptr;
     S.active = active;
+    S.vact = vact;
     S.flags = flags + b0;
     hipStream_t st = ctx->stream;
-    const uint8_t* act = active;
+    const uint8_t* act = vact;  // the V-cycle skips samples whose last step is taken
 
     // coefficient expansion straight into FP64 edge weights, the storage copy, coarser levels
     ctx->t_begin(MLQMC_K_COEFF);
@@ -428,19 +448,20 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     all_active = false;
     const int nblk_post = post_strips(nh, Bn);
     CK(launch_scalar(PH_FIRST_RZ, nh, Bn, nblk_post, part, S, 0.0, 0, st), "scalar");
-    const double ab = (double)sz * Bn * (7 * D(nh));
+    // first apply: z, vn, mvn, t, 2 weights per node in (no previous p); p, q out
+    const double ab = (double)sz * Bn * (8 * D(nh));
     int cur = 0;
     for (int it = 0; it < o->max_lin_iter; ++it) {
       if (it == 0) ctx->t_begin(MLQMC_K_APPLY);
-      CK(launch_pupdate_apply<T>(nh, Bn, zc, vn, pp[cur], mvn, wT, S, it == 0, pp[1 - cur], q,
-                                 part, st),
+      CK(launch_pupdate_apply<T>(nh, Bn, zc, vn, pp[cur], mvn, wT, t, S, it == 0, pp[1 - cur],
+                                 q, part, st),
          "apply");
       if (it == 0) ctx->t_end(MLQMC_K_APPLY, ab);
       cur = 1 - cur;
-      CK(launch_scalar(PH_ALPHA, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
+      CK(launch_scalar(PH_ALPHA, nh, Bn, nblk0, part, S, lam_tol(o), 0, st), "scalar");
       CK(launch_update<T>(nh, Bn, pp[cur], q, mvn, S, t, r, st), "update");
       CS(vcycle());
-      CK(launch_scalar(PH_BETA, nh, Bn, nblk_post, part, S, o->lin_rtol, o->max_lin_iter, st),
+      CK(launch_scalar(PH_BETA, nh, Bn, nblk_post, part, S, lin_tol(o), o->max_lin_iter, st),
          "scalar");
       if (it % 3 == 2 || it + 1 == o->max_lin_iter) {
         CK(hipMemcpyAsync(h_active.data(), active, Bn, hipMemcpyDeviceToHost, st), "active");
@@ -473,7 +494,7 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
     a.lamH = lamH;
     a.nH = nH;
     a.n = n;
-    a.lin_rtol = o->lin_rtol;
+    a.lin_rtol = lin_tol(o);
     a.max_lin = o->max_lin_iter;
     a.lam = lam;
     a.lin_iters = lin_iters;
@@ -603,7 +624,8 @@ void mlqmc_default_opts(mlqmc_opts* o) {
   o->prec = MLQMC_FP64;
   o->eig_rtol = 1e-8;
   o->max_rq_iter = 12;
-  o->lin_rtol = 1e-6;
+  o->lin_rtol = 0.0;
+  o->lam_rtol = 0.0;
   o->rq_lin_rtol = 1e-4;
   o->max_lin_iter = 60;
   o->chain_len = 0;

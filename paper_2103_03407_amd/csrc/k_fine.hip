@@ -368,7 +368,8 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
                                                        const T* __restrict__ vn,
                                                        const T* __restrict__ pin,
                                                        const T* __restrict__ mvn,
-                                                       const T* __restrict__ w, FineState S,
+                                                       const T* __restrict__ w,
+                                                       const T* __restrict__ t, FineState S,
                                                        int first, T* __restrict__ pout,
                                                        T* __restrict__ q,
                                                        double* __restrict__ part) {
@@ -382,24 +383,30 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
   const T* mb = mvn + b * g.P;
   const T* wx = w + b * 2 * g.P;
   const T* wy = wx + g.P;
+  const T* tb = t + b * g.P;
   const T c2 = (T)S.c2[b], beta = first ? T(0) : (T)S.beta[b], mu = (T)S.mu[b];
   const T hm = (T)mass_scale(g.n);
-  double s[3] = {0.0, 0.0, 0.0};
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   march<T, NTC>(ring, g, c0, j0, j1, dir,
                 [&](int k) { return zz[k] - c2 * vb[k] + (first ? T(0) : beta * pb[k]); },
                 [&](int, int, int k, const T* rs, const T* rc, const T* rn, int ci) {
                   T d;
                   const T ap = ring_A(rs, rc, rn, ci, wx, wy, k, g.n, d);
                   const T pc = rc[ci];
-                  const T qv = ap - mu * hm * ring_M12(rs, rc, rn, ci);
+                  const T m12 = ring_M12(rs, rc, rn, ci);
+                  const T qv = ap - mu * hm * m12;
                   const int64_t o = b * g.P + k;
                   pout[o] = pc;
                   q[o] = qv;
+                  const double tk = (double)tb[k];
                   s[0] += (double)pc * (double)qv;
                   s[1] += (double)vb[k] * (double)qv;
                   s[2] += (double)pc * (double)mb[k];
+                  s[3] += (double)pc * (double)m12;
+                  s[4] += tk * (double)m12;
+                  s[5] += tk * (double)qv;
                 });
-  write_partials_m<NTC, 3>(s, part, b, blk, g.nblk);
+  write_partials_m<NTC, 6>(s, part, b, blk, g.nblk);
 }
 
 // t += alpha p; r -= alpha (q - c M vn)
@@ -727,8 +734,9 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
   if (b >= B) return;
   int K = 3;
   if (phase == PH_SETUP || phase == PH_FINAL) K = 2;
+  if (phase == PH_ALPHA) K = 6;
   if ((phase == PH_ALPHA || phase == PH_BETA) && !S.active[b]) return;
-  double s[3] = {0.0, 0.0, 0.0};
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int k = lane; k < nblk; k += 64)
     for (int c = 0; c < K; ++c) s[c] += part[((int64_t)b * nblk + k) * K + c];
   for (int c = 0; c < K; ++c) s[c] = wave_sum(s[c]);
@@ -739,7 +747,11 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
       const double g = s[0] * hm;
       S.vs[b] = 1.0 / sqrt(g);
       S.rho[b] = s[1] / g;
+      S.f[b] = S.rho[b] - S.mu[b];  // w_0 = vn, M-normalised
+      S.m[b] = 1.0;
+      S.dl[b] = 0.0;
       S.active[b] = 1;
+      S.vact[b] = 1;
       S.its[b] = 0;
       break;
     }
@@ -749,32 +761,54 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
       S.rz0[b] = rz;
       S.c2[b] = s[1];
       S.beta[b] = 0.0;
-      if (!(rz > 0.0)) S.active[b] = 0;  // zero right-hand side: t = 0 is exact
+      if (!(rz > 0.0)) S.active[b] = S.vact[b] = 0;  // zero right-hand side: t = 0 is exact
       break;
     }
-    case PH_ALPHA: {  // s0 = p.q, s1 = v.q, s2 = p.Mv
+    case PH_ALPHA: {
+      // s0 = p.q, s1 = v.q, s2 = p.Mv, s3 = p.M12 p, s4 = t.M12 p, s5 = t.q
+      // (q = (A - mu M) p, t = t_k before this step)
       const double pq = s[0] - s[2] * s[1];
       if (!(pq > 0.0)) {
         S.flags[b] |= MLQMC_FLAG_BREAKDOWN;
-        S.active[b] = 0;
+        S.active[b] = S.vact[b] = 0;
         S.alpha[b] = 0.0;
         break;
       }
-      S.alpha[b] = S.rz[b] / pq;
+      const double a = S.rz[b] / pq;
+      S.alpha[b] = a;
       S.c[b] = s[1];
+      // Rayleigh quotient of w_{k+1} = w_k + a p: mu + f/m with
+      // f += 2a p^T (A - mu M) w_k + a^2 p^T (A - mu M) p, m += 2a p^T M w_k + a^2 p^T M p
+      const double f = S.f[b], m = S.m[b];
+      const double df = 2.0 * a * (s[1] + s[5]) + a * a * s[0];
+      const double dm = 2.0 * a * (s[2] + hm * s[4]) + a * a * hm * s[3];
+      const double dl = fabs((df * m - f * dm) / (m * (m + dm)));
+      S.f[b] = f + df;
+      S.m[b] = m + dm;
+      // the error left after this step is estimated by the change it made,
+      // scaled by the observed contraction (at most 1)
+      const double dprev = S.dl[b];
+      const double est = dprev > 0.0 ? dl * fmin(1.0, 2.0 * dl / dprev) : dl;
+      S.dl[b] = dl;
+      const double lam = S.mu[b] + (f + df) / (m + dm);
+      if (est <= rtol * fabs(lam)) S.vact[b] = 0;  // converged: this is the last step
       break;
     }
     case PH_BETA: {  // s0 = r.z, s1 = Mv.z, s2 = r.v
-      const double rzn = s[0] - s[2] * s[1];
       const int it = S.its[b] + 1;
       S.its[b] = it;
-      if (sqrt(fabs(rzn / S.rz0[b])) <= rtol) {
+      if (!S.vact[b]) {  // the eigenvalue test stopped the sample at its last step
         S.active[b] = 0;
+        break;
+      }
+      const double rzn = s[0] - s[2] * s[1];
+      if (sqrt(fabs(rzn / S.rz0[b])) <= rtol) {
+        S.active[b] = S.vact[b] = 0;
         break;
       }
       if (it >= max_it) {
         S.flags[b] |= MLQMC_FLAG_LIN_NOCONV;
-        S.active[b] = 0;
+        S.active[b] = S.vact[b] = 0;
         break;
       }
       S.beta[b] = rzn / S.rz[b];
@@ -917,12 +951,12 @@ hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64
 
 template <typename T>
 hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
-                                const T* mvn, const T* w, const FineState& S, int first, T* pout,
-                                T* q, double* part, hipStream_t st) {
+                                const T* mvn, const T* w, const T* t, const FineState& S,
+                                int first, T* pout, T* q, double* part, hipStream_t st) {
   MARCH_DISPATCH(n, {
     const MGeo g = mgeo<NTC>(n, B);
     hipLaunchKernelGGL((k_pupdate_apply<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, z, vn, pin,
-                       mvn, w, S, first, pout, q, part);
+                       mvn, w, t, S, first, pout, q, part);
   });
   return hipGetLastError();
 }
@@ -1053,8 +1087,8 @@ hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* s
   template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, const double*,           \
                                           const FineState&, T*, T*, T*, T*, hipStream_t);       \
   template hipError_t launch_pupdate_apply<T>(int, int64_t, const T*, const T*, const T*,       \
-                                              const T*, const T*, const FineState&, int, T*,    \
-                                              T*, double*, hipStream_t);                        \
+                                              const T*, const T*, const T*, const FineState&,   \
+                                              int, T*, T*, double*, hipStream_t);               \
   template hipError_t launch_update<T>(int, int64_t, const T*, const T*, const T*,              \
                                        const FineState&, T*, T*, hipStream_t);                  \
   template hipError_t launch_final_dots<T>(int, int64_t, const double*, const T*,               \

@@ -62,9 +62,13 @@ constexpr int kNodesPerBlock = 1024;
 
 struct FineState {      // per-sample scalars of the projected PCG, arrays of length B
   double *mu, *vs, *rho, *rz, *rz0, *alpha, *c, *c2, *beta, *lam;
+  // Rayleigh quotient of w_k = vn + t_k, tracked from the PCG dots:
+  // f = w^T (A - mu M) w, m = w^T M w, dl = |change of f/m| in the last step
+  double *f, *m, *dl;
   int* its;
   int* lin_acc;         // per-sample PCG iteration totals, added to at the end (or nullptr)
-  uint8_t* active;
+  uint8_t* active;      // the sample still takes PCG steps
+  uint8_t* vact;        // the sample still needs the preconditioner this step
   uint8_t* flags;
 };
 
@@ -92,8 +96,8 @@ hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64
                             const FineState& S, T* r, T* t, T* vn, T* mvn, hipStream_t st);
 template <typename T>
 hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
-                                const T* mvn, const T* w, const FineState& S, int first, T* pout,
-                                T* q, double* part, hipStream_t st);
+                                const T* mvn, const T* w, const T* t, const FineState& S,
+                                int first, T* pout, T* q, double* part, hipStream_t st);
 template <typename T>
 hipError_t launch_update(int n, int64_t B, const T* p, const T* q, const T* mvn,
                          const FineState& S, T* t, T* r, hipStream_t st);

@@ -297,6 +297,34 @@ def test_invalid_levels_rejected(ctx, lv):
     assert e.value.code == m.MLQMC_EINVAL
 
 
+@pytest.mark.parametrize("kw", [dict(lin_rtol=-1.0), dict(eig_rtol=0.0), dict(rq_lin_rtol=-1e-3),
+                                dict(max_lin_iter=0), dict(max_rq_iter=0), dict(prec=7)])
+def test_invalid_opts_rejected(ctx, kw):
+    Y = np.ascontiguousarray(_points(1024, 64, 2, 0, 0, range(2)))
+    with pytest.raises(m.MlqmcError) as e:
+        ctx.eig_level((128, 64, 32, 8, 0, 0), Y, np.empty(2), np.zeros(2, np.uint8),
+                      opts=m.default_opts(**kw))
+    assert e.value.code == m.MLQMC_EINVAL
+
+
+@pytest.mark.parametrize("lv", [(128, 64, 32, 8, 0, 0), (64, 64, 8, 16, 0, 0)])
+def test_eigenvalue_stopping_test(ctx, lv):
+    # lam_rtol = 0 selects the precision's default (5e-12 in FP64); the
+    # eigenvalue test stops the solve earlier than a residual test at 1e-10
+    # would, and still leaves the result within 1e-11 of a solve to round-off
+    Y = np.ascontiguousarray(_points(1024, lv[1], 2, 0, 4, range(24)))
+    a, b, c = np.empty(24), np.empty(24), np.empty(24)
+    ia, ic = np.zeros(24, np.int32), np.zeros(24, np.int32)
+    ctx.eig_level(lv, Y, a, np.zeros(24, np.uint8), lin_iters=ia)
+    ctx.eig_level(lv, Y, b, np.zeros(24, np.uint8), opts=m.default_opts(lam_rtol=5e-12))
+    fl = np.zeros(24, np.uint8)
+    ctx.eig_level(lv, Y, c, fl, lin_iters=ic,
+                  opts=m.default_opts(lam_rtol=1e-300, lin_rtol=1e-13, max_lin_iter=80))
+    assert np.array_equal(a, b)
+    assert _rel(a, c) <= 1e-11
+    assert np.all(ia <= ic) and ia.sum() < ic.sum()
+
+
 def test_nonfinite_points_rejected(ctx):
     Y = np.zeros((2, 16))
     Y[1, 3] = np.nan
