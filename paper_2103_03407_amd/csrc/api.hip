@@ -258,8 +258,8 @@ mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
     if (l->n_fine < 4 || l->n_fine > 32)
       return ctx->fail(MLQMC_EINVAL, "direct levels need 4 <= n_fine <= 32 (got %d)", l->n_fine);
   } else {
-    if (!is_pow2(l->n_coarse) || l->n_coarse < 4 || l->n_coarse > 32)
-      return ctx->fail(MLQMC_EINVAL, "n_coarse=%d must be a power of two in [4, 32]", l->n_coarse);
+    if (!is_pow2(l->n_coarse) || l->n_coarse < 4 || l->n_coarse > 64)
+      return ctx->fail(MLQMC_EINVAL, "n_coarse=%d must be a power of two in [4, 64]", l->n_coarse);
     if (l->n_fine <= l->n_coarse || l->n_fine > 1024)
       return ctx->fail(MLQMC_EINVAL, "need n_coarse < n_fine <= 1024 (got %d, %d)", l->n_coarse,
                        l->n_fine);
@@ -582,6 +582,10 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   a.phi = tb->edge;
   a.lam = lamH;
   a.u_out = uH;
+  if (const int64_t per = rqi_scratch_doubles(L->n_coarse)) {
+    a.scratch_doubles = per * ((n + chain - 1) / chain);
+    CS(ctx->getT("rqi_scratch", a.scratch_doubles, &a.scratch));
+  }
   ctx->t_begin(MLQMC_K_COARSE);
   CK(launch_rqi(L->n_coarse, a, st), "coarse eigensolve (LDS)");
   ctx->t_end(MLQMC_K_COARSE, 0.0);

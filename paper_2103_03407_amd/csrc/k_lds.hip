@@ -49,25 +49,21 @@ __device__ __forceinline__ double sine_overlap(const double* v, double* red) {
   return fabs(s[0] * hm) / sqrt(s[1] * hm);
 }
 
+// The chain of samples [blockIdx.x * chain_len, ...) on mesh N: arrays in `a`
+// (weights at a.wx), the staged point in s_y.
 template <int N, int NT>
-__global__ __launch_bounds__(NT) void k_rqi(RqiArgs A) {
+__device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays& a, double* s_y) {
   using Mh = lds::Mesh<N>;
   constexpr int D = Mh::D;
-  __shared__ double s_w[Mh::EW];
-  __shared__ double s_v[D], s_t[D], s_r[D], s_z[D], s_p[D], s_q[D];
-  __shared__ double s_mg[lds::mg_scratch<N>() + 1];
-  __shared__ double s_red[3 * (NT / 64)];
-  __shared__ double s_y[kMaxStagedS];
-  const lds::PcgArrays a{s_w, s_w + Mh::EX, s_v, s_t, s_r, s_z, s_p, s_q, s_mg, s_red};
-
+  double* const s_v = a.v;
   const int64_t i0 = (int64_t)blockIdx.x * A.chain_len;
   const int64_t i1 = (i0 + A.chain_len < A.n) ? i0 + A.chain_len : A.n;
   bool have_prev = false;
   for (int64_t i = i0; i < i1; ++i) {
     for (int j = threadIdx.x; j < A.S; j += NT) s_y[j] = A.Y[i * A.ldY + j];
     __syncthreads();
-    lds::weights_from_table<NT, N>(A.phi, s_y, A.S, A.a0, s_w);
-    lds::coarsen_all<NT, N>(a.wx, a.wy, s_mg);
+    lds::weights_from_table<NT, N>(A.phi, s_y, A.S, A.a0, a.wx);
+    lds::coarsen_all<NT, N>(a.wx, a.wy, a.mg);
     if (!(A.warm && have_prev)) init_sine<NT, N>(s_v);
 
     double vMv, vAv;
@@ -82,7 +78,7 @@ __global__ __launch_bounds__(NT) void k_rqi(RqiArgs A) {
       ++rq;
       bool c, b;
       lin += lds::jd_pcg<NT, N>(a, sigma, sigma, A.lin_rtol, A.max_lin, &c, &b);
-      for (int id = threadIdx.x; id < D; id += NT) s_v[id] += s_t[id];
+      for (int id = threadIdx.x; id < D; id += NT) s_v[id] += a.t[id];
       __syncthreads();
       lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);
       lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
@@ -97,7 +93,7 @@ __global__ __launch_bounds__(NT) void k_rqi(RqiArgs A) {
     }
     if (!conv) fl |= MLQMC_FLAG_RQ_NOCONV;
     if (!isfinite(sigma)) fl |= MLQMC_FLAG_NONFINITE;
-    const double ov = sine_overlap<NT, N>(s_v, s_red);
+    const double ov = sine_overlap<NT, N>(s_v, a.red);
     if (!(ov >= 0.5)) fl |= MLQMC_FLAG_WRONG_PAIR;
     if (threadIdx.x == 0) {
       A.lam[i] = sigma;
@@ -110,6 +106,42 @@ __global__ __launch_bounds__(NT) void k_rqi(RqiArgs A) {
     have_prev = (fl == 0);
     __syncthreads();
   }
+}
+
+// Every array in LDS (meshes up to 1/32).
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_rqi(RqiArgs A) {
+  using Mh = lds::Mesh<N>;
+  constexpr int D = Mh::D;
+  __shared__ double s_w[Mh::EW];
+  __shared__ double s_v[D], s_t[D], s_r[D], s_z[D], s_p[D], s_q[D];
+  __shared__ double s_mg[lds::mg_scratch<N>() + 1];
+  __shared__ double s_red[3 * (NT / 64)];
+  __shared__ double s_y[kMaxStagedS];
+  const lds::PcgArrays a{s_w, s_w + Mh::EX, s_v, s_t, s_r, s_z, s_p, s_q, s_mg, s_red};
+  rqi_chain<N, NT>(A, a, s_y);
+}
+
+// Meshes whose vectors exceed LDS (1/64): the top-level weights and the six
+// PCG vectors live in the chain's slice of a global scratch buffer (L2/MALL
+// resident while the chain runs); the V-cycle levels below stay in LDS.
+template <int N>
+constexpr int64_t rqi_global_doubles() {
+  return (int64_t)lds::Mesh<N>::EW + 6 * (int64_t)lds::Mesh<N>::D;
+}
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_rqi_global(RqiArgs A) {
+  using Mh = lds::Mesh<N>;
+  constexpr int D = Mh::D;
+  __shared__ double s_mg[lds::mg_scratch<N>() + 1];
+  __shared__ double s_red[3 * (NT / 64)];
+  __shared__ double s_y[kMaxStagedS];
+  double* g = A.scratch + (int64_t)blockIdx.x * rqi_global_doubles<N>();
+  double* w = g;
+  double* v = w + Mh::EW;
+  const lds::PcgArrays a{w, w + Mh::EX, v, v + D, v + 2 * D, v + 3 * D, v + 4 * D, v + 5 * D,
+                         s_mg, s_red};
+  rqi_chain<N, NT>(A, a, s_y);
 }
 
 template <int N, int NT>
@@ -193,10 +225,17 @@ __global__ __launch_bounds__(NT) void k_bottom(const T* __restrict__ w, const T*
 
 template <int N>
 hipError_t rqi_n(const RqiArgs& a, hipStream_t st) {
-  constexpr int NT = threads_for<N>();
   const int64_t chains = (a.n + a.chain_len - 1) / a.chain_len;
   if (chains <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_rqi<N, NT>), dim3((unsigned)chains), dim3(NT), 0, st, a);
+  if constexpr (N <= 32) {
+    constexpr int NT = threads_for<N>();
+    hipLaunchKernelGGL((k_rqi<N, NT>), dim3((unsigned)chains), dim3(NT), 0, st, a);
+  } else {
+    // the caller provides chains x rqi_scratch_doubles(N) doubles of scratch
+    if (!a.scratch || a.scratch_doubles < chains * rqi_global_doubles<N>())
+      return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_rqi_global<N, 512>), dim3((unsigned)chains), dim3(512), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -226,9 +265,12 @@ hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st) {
     case 8: return rqi_n<8>(a, st);
     case 16: return rqi_n<16>(a, st);
     case 32: return rqi_n<32>(a, st);
+    case 64: return rqi_n<64>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
+
+int64_t rqi_scratch_doubles(int N) { return N == 64 ? rqi_global_doubles<64>() : 0; }
 
 hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st) {
   if (a.s > kMaxStagedS) return hipErrorInvalidValue;

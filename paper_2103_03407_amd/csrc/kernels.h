@@ -27,8 +27,12 @@ struct RqiArgs {
   int* rq_iters;        // [n] or nullptr
   int* lin_iters;       // [n] or nullptr
   uint8_t* flags;       // [n]
+  double* scratch;      // meshes above 1/32: per-chain global scratch
+  int64_t scratch_doubles;
 };
 hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st);
+// doubles of global scratch one chain needs on mesh N (0: all in LDS)
+int64_t rqi_scratch_doubles(int N);
 
 struct TgSmallArgs {
   const double* Y;      // [n x ldY], first s columns

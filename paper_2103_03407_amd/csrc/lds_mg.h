@@ -133,6 +133,65 @@ MLQMC_DEV void vcycle(const double* wx, const double* wy, const double* B, doubl
   }
 }
 
+// Xout = Xin + omega (B - A Xin) / diag (two distinct arrays)
+template <int NT, int n>
+MLQMC_DEV void jacobi_to(const double* wx, const double* wy, const double* B, const double* Xin,
+                         double* Xout) {
+  constexpr int m = n - 1, D = m * m;
+  for (int id = threadIdx.x; id < D; id += NT) {
+    const int i = id % m + 1, j = id / m + 1;
+    double d;
+    const double ax = stencil_A(Xin, wx, wy, n, i, j, id, d);
+    Xout[id] = Xin[id] + kOmega * (B[id] - ax) / d;
+  }
+  __syncthreads();
+}
+
+// The same V-cycle for a top level whose arrays are too large for register
+// staging (mesh 1/64 and finer): the sweeps alternate between X and R, the
+// levels below run vcycle().
+template <int NT, int n>
+MLQMC_DEV void vcycle_pingpong(const double* wx, const double* wy, const double* B, double* X,
+                               double* R, double* nxt) {
+  constexpr int m = n - 1, D = m * m;
+  constexpr int nc = n / 2, mc = nc - 1, Dc = mc * mc;
+  const double* wxc = nxt;
+  const double* wyc = wxc + (nc - 1) * nc;
+  double* Bc = nxt + 2 * (nc - 1) * nc;
+  double* Xc = Bc + Dc;
+  double* Rc = Xc + Dc;
+  jacobi_first<NT, n>(wx, wy, B, R);
+  jacobi_to<NT, n>(wx, wy, B, R, X);
+  for (int id = threadIdx.x; id < D; id += NT) {
+    const int i = id % m + 1, j = id / m + 1;
+    double d;
+    R[id] = B[id] - stencil_A(X, wx, wy, n, i, j, id, d);
+  }
+  __syncthreads();
+  for (int id = threadIdx.x; id < Dc; id += NT) {
+    const int I = id % mc + 1, J = id / mc + 1;
+    Bc[id] = restrict_at(R, n, I, J);
+  }
+  __syncthreads();
+  vcycle<NT, nc>(wxc, wyc, Bc, Xc, Rc, Rc + Dc);
+  for (int id = threadIdx.x; id < D; id += NT) {
+    const int i = id % m + 1, j = id / m + 1;
+    X[id] += prolong2_at(Xc, nc, i, j);
+  }
+  __syncthreads();
+  jacobi_to<NT, n>(wx, wy, B, X, R);
+  jacobi_to<NT, n>(wx, wy, B, R, X);
+}
+
+template <int NT, int n>
+MLQMC_DEV void vcycle_top(const double* wx, const double* wy, const double* B, double* X,
+                          double* R, double* nxt) {
+  if constexpr (n > 32)
+    vcycle_pingpong<NT, n>(wx, wy, B, X, R, nxt);
+  else
+    vcycle<NT, n>(wx, wy, B, X, R, nxt);
+}
+
 // Arrays of one projected-PCG solve on mesh N (all LDS, D doubles each except
 // the weights and the multigrid scratch).
 struct PcgArrays {
@@ -185,7 +244,7 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
     t[id] = 0.0;
   }
   __syncthreads();
-  vcycle<NT, n>(a.wx, a.wy, r, z, q, a.mg);
+  vcycle_top<NT, n>(a.wx, a.wy, r, z, q, a.mg);
   // rz = r.(P^T z) = r.z - (r.v)(Mv.z);  p = P^T z
   double s3[3] = {0.0, 0.0, 0.0};
   for (int id = threadIdx.x; id < D; id += NT) {
@@ -233,7 +292,7 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
       r[id] -= alpha * (q[id] - c * hm * stencil_M12(v, n, i, j, id));
     }
     __syncthreads();
-    vcycle<NT, n>(a.wx, a.wy, r, z, q, a.mg);
+    vcycle_top<NT, n>(a.wx, a.wy, r, z, q, a.mg);
     double u[3] = {0.0, 0.0, 0.0};
     for (int id = threadIdx.x; id < D; id += NT) {
       const int i = id % m + 1, j = id / m + 1;

@@ -154,6 +154,55 @@ def test_two_grid_cfg2_shape(ctx, fam):
     assert li.min() >= 1
 
 
+@pytest.mark.parametrize("warm", [0, 1])
+def test_two_grid_coarse_64(ctx, fam, warm):
+    # coarse mesh 1/64: the eigensolve keeps its top level in global scratch
+    cnt = 5
+    Y = np.ascontiguousarray(_points(1024, 32, 5, 0, 1, range(40, 40 + cnt)))
+    lam, lamc = np.empty(cnt), np.empty(cnt)
+    fl = np.zeros(cnt, np.uint8)
+    rq = np.zeros(cnt, np.int32)
+    ctx.eig_level((128, 32, 64, 16, 0, 0), Y, lam, fl, lam_coarse=lamc, rq_iters=rq,
+                  warm_chain=warm)
+    assert not fl.any(), fl
+    for k in range(cnt):
+        tg, lamH, _ = twogrid.two_grid(128, 32, 64, 16, Y[k], fam)
+        assert abs(lam[k] - tg) <= LAM_RTOL * tg
+        assert abs(lamc[k] - lamH) <= LAM_RTOL * lamH
+    assert rq.min() >= 1
+
+
+def _large_golden():
+    import json
+    import os
+    p = os.path.join(os.path.dirname(__file__), "golden", "large_twogrid_samples.json")
+    return json.load(open(p))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", LAM_RTOL), ("mixed", 1e-8)])
+def test_large_two_grid_golden(ctx, prec, tol):
+    # H = 1/64 -> h = 1/1024, s = 512, S = 23 against stored oracle values
+    g = _large_golden()
+    w = CONFIGS[5]
+    lv = w.levels[0]
+    z, sh = w.z(0), w.shifts(0)
+    pts = g["samples"]
+    Y = np.ascontiguousarray(np.stack([qmc.lattice_point(z, lv.N, sh[p["r"]], p["k"]) for p in pts]))
+    n = len(pts)
+    lam, lamc = np.empty(n), np.empty(n)
+    fl = np.zeros(n, np.uint8)
+    o = m.default_opts(prec=m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED)
+    ctx_l = m.Context(w.family())
+    try:
+        ctx_l.eig_level(_lv6(lv), Y, lam, fl, lam_coarse=lamc, warm_chain=0, opts=o)
+    finally:
+        ctx_l.close()
+    assert not fl.any(), fl
+    for k, p in enumerate(pts):
+        assert abs(lamc[k] - p["lambda_H"]) <= LAM_RTOL * p["lambda_H"]
+        assert abs(lam[k] - p["lambda"]) <= tol * p["lambda"], (k, lam[k], p["lambda"])
+
+
 @pytest.mark.parametrize("lv", [LevelSpec(32, 32, 8, 16, 16, 16, 0), LevelSpec(64, 64, 8, 16, 32, 32, 0),
                                 LevelSpec(128, 128, 16, 16, 64, 64, 0), LevelSpec(16, 8, 4, 4, 8, 8, 0)])
 def test_level_with_previous_term(ctx, fam, lv):
@@ -288,6 +337,7 @@ def test_zero_truncation_is_constant_coefficient(ctx, fam):
 
 
 @pytest.mark.parametrize("lv", [(48, 16, 0, 0, 0, 0), (64, 16, 0, 0, 0, 0), (64, 16, 64, 8, 0, 0),
+                                (256, 16, 128, 8, 0, 0),
                                 (128, 16, 32, 32, 0, 0), (128, 600, 32, 8, 0, 0),
                                 (128, 16, 32, 8, 64, 32), (64, 16, 32, 8, 16, 8)])
 def test_invalid_levels_rejected(ctx, lv):
