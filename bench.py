@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+PEAK_FP64_MFMA_TFS = 78.6  # MI355X dense FP64 matrix, published
 
 
 def _parse():
@@ -183,9 +184,22 @@ def main():
     value = n_samples * a.steps / dt
 
     kname = {"post": "k_post", "pre": "k_pre", "apply": "k_pupdate_apply",
-             "coeff": "k_expand"}[a.kernel_class]
+             "coeff": "k_expand_mfma"}[a.kernel_class]
     roof = None
-    if launches > 0 and kms > 0:
+    if launches > 0 and kms > 0 and a.kernel_class == "coeff":
+        # the coefficient product on FP64 MFMA: 2 s E flops per sample, every
+        # sample expanded once per step (E = edge weights of the padded mesh)
+        avg_ms = kms / launches
+        ew = 2 * (lv.n_fine + 2) * lv.n_fine
+        flops_per_launch = 2.0 * lv.s_fine * ew * n_samples * a.steps / launches
+        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 2),
+                "peak": PEAK_FP64_MFMA_TFS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_MFMA_TFS, 4), "traffic": _traffic(kname),
+                "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
+                "algorithmic_flops_per_launch": flops_per_launch,
+                "hbm_GBs": round(kbytes / launches / (avg_ms * 1e-3) / 1e9, 1)}
+    elif launches > 0 and kms > 0:
         avg_ms = kms / launches
         bytes_per_launch = kbytes / launches
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9

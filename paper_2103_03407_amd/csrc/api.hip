@@ -309,7 +309,13 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   int64_t per_sample = 8 * (EW(nh) + 2 * P(nh)) + sz * (9 * P(nh)) + (kMixed ? 4 * EW(nh) : 0);
   for (size_t k = 1; k < nL; ++k) per_sample += sz * (EW(lv[k]) + 3 * P(lv[k]));
   per_sample += sz * (EW(nb) + 2 * P(nb));
-  int64_t batch = o->batch > 0 ? o->batch : std::max<int64_t>(1, (int64_t)16e9 / per_sample);
+  // default batch: up to 48 GB of working arrays (HBM holds 288 GB), in
+  // multiples of the 128-sample tile of the coefficient product when larger
+  int64_t batch = o->batch;
+  if (batch <= 0) {
+    batch = std::max<int64_t>(1, (int64_t)48e9 / per_sample);
+    if (batch > 128) batch -= batch % 128;
+  }
   batch = std::min<int64_t>(batch, n);
   // partial-sum counts depend on the batch size through the strip choice;
   // the partial buffer is sized for the largest (smallest batch)
@@ -401,9 +407,12 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
 
     // coefficient expansion straight into FP64 edge weights, the storage copy, coarser levels
     ctx->t_begin(MLQMC_K_COEFF);
-    CK(launch_expand(Bn, s, (int)EW(nh), Y + b0 * ldY, ldY, tb->pad, ctx->a0, w64, st), "expand");
-    ctx->t_end(MLQMC_K_COEFF, 8.0 * ((double)Bn * s + (double)s * EW(nh) + (double)Bn * EW(nh)));
-    if constexpr (kMixed) CK(launch_to_float(Bn * EW(nh), w64, wT, st), "to float");
+    float* w32 = nullptr;
+    if constexpr (kMixed) w32 = wT;
+    CK(launch_expand(Bn, s, EW(nh), Y + b0 * ldY, ldY, tb->pad, ctx->a0, w64, w32, st), "expand");
+    // Y and phi in, the weights out (FP64, plus the FP32 copy in mixed precision)
+    ctx->t_end(MLQMC_K_COEFF, 8.0 * ((double)Bn * s + (double)s * EW(nh)) +
+                                  (8.0 + (kMixed ? 4.0 : 0.0)) * (double)Bn * EW(nh));
     for (size_t k = 0; k < nL; ++k) CK(launch_coarsen<T>(lv[k], Bn, W[k], W[k + 1], st), "coarsen");
 
     CK(launch_prolong(nH, nh, Bn, uH + b0 * D(nH), v64, st), "prolong");
@@ -771,7 +780,7 @@ mlqmc_status mlqmc_coefficient(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B, 
   const int E = 2 * n * n;
   CS(stage_in(ctx, "in_Y", Y, (size_t)(B * s), on_dev, &dY));
   CS(out_buf(ctx, "out_a", aK, (size_t)(B * E), on_dev, &dA));
-  CK(launch_expand(B, s, E, dY, s, tb->el, ctx->a0, dA, ctx->stream), "expand");
+  CK(launch_expand(B, s, E, dY, s, tb->el, ctx->a0, dA, nullptr, ctx->stream), "expand");
   CS(stage_out(ctx, aK, dA, (size_t)(B * E), on_dev));
   return ctx->sync("coefficient");
 }
@@ -795,7 +804,7 @@ mlqmc_status mlqmc_apply_operator(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t 
   CS(stage_in(ctx, "in_x", x, (size_t)(B * D), on_dev, &dx));
   CS(out_buf(ctx, "out_x", out, (size_t)(B * D), on_dev, &dout));
   CS(ctx->getT("op_w", (size_t)(B * EW), &w));
-  CK(launch_expand(B, s, (int)EW, dY, s, tb->edge, ctx->a0, w, ctx->stream), "expand");
+  CK(launch_expand(B, s, EW, dY, s, tb->edge, ctx->a0, w, nullptr, ctx->stream), "expand");
   CK(launch_apply_plain(n, B, w, dsg, dx, dout, ctx->stream), "apply");
   CS(stage_out(ctx, out, dout, (size_t)(B * D), on_dev));
   return ctx->sync("apply");

@@ -299,12 +299,6 @@ __global__ __launch_bounds__(256) void k_coarsen(int n, int64_t B, const T* __re
   wc[b * 2 * Pc + e] = val;
 }
 
-__global__ __launch_bounds__(256) void k_to_float(int64_t count, const double* __restrict__ x,
-                                                  float* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < count) y[i] = (float)x[i];
-}
-
 // partials: v.M12 v, v.A v  (raw FP64 v, FP64 weights)
 template <int NTC>
 __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, const double* __restrict__ v,
@@ -898,13 +892,6 @@ hipError_t launch_coarsen(int n, int64_t B, const T* w, T* wc, hipStream_t st) {
   const int E = 2 * (nc + 2) * nc;
   hipLaunchKernelGGL(k_coarsen<T>, dim3((E + 255) / 256, (unsigned)B), dim3(256), 0, st, n, B, w,
                      wc);
-  return hipGetLastError();
-}
-
-hipError_t launch_to_float(int64_t count, const double* x, float* y, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_to_float, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count,
-                     x, y);
   return hipGetLastError();
 }
 

@@ -103,40 +103,113 @@ __global__ __launch_bounds__(256) void k_phi_edges_padded(int n, int s,
   pw[(int64_t)jt * 2 * P + e] = v;
 }
 
-// out[b][e] = a0 + sum_j Y[b][j] phi[j][e]: 256 columns x 32 samples per block,
-// Y staged through LDS in chunks of 64 terms, phi streamed once per block.
-constexpr int kExpBS = 32, kExpJC = 64;
-__global__ __launch_bounds__(256) void k_expand(int64_t B, int s, int E,
-                                                const double* __restrict__ Y, int64_t ldY,
-                                                const double* __restrict__ phi, double a0,
-                                                double* __restrict__ out) {
-  __shared__ double ys[kExpBS][kExpJC];
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  const int64_t b0 = (int64_t)blockIdx.y * kExpBS;
-  double acc[kExpBS];
+// out[b][e] = a0 + sum_j Y[b][j] phi[j][e] (eq. coeff at the quadrature points
+// of every sample, as one [B x s] x [s x E] product) on FP64 MFMA
+// (v_mfma_f64_16x16x4f64).  A block computes a 128-sample x 128-entry tile
+// with 4 waves in 2 x 2, each wave 4 x 4 MFMA tiles of 16 x 16; K runs in
+// chunks of 16 through double-buffered LDS, the next chunk's global loads in
+// flight while the current one is multiplied.  Tiles are ordered so that the
+// blocks sharing one entry tile of phi run together on one XCD (one L2).
+// out32, when given, receives the same values rounded to FP32.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kXM = 128, kXN = 128, kXK = 16, kXPad = 4;
+
+__global__ __launch_bounds__(256, 2) void k_expand_mfma(int64_t B, int s, int64_t E,
+                                                     const double* __restrict__ Y, int64_t ldY,
+                                                     const double* __restrict__ phi, double a0,
+                                                     double* __restrict__ out,
+                                                     float* __restrict__ out32, int nbm,
+                                                     int64_t per_xcd, int64_t ntiles) {
+  __shared__ double sY[2][kXK][kXM + kXPad];
+  __shared__ double sP[2][kXK][kXN + kXPad];
+  const int64_t L = blockIdx.x;
+  const int64_t T = (L & 7) * per_xcd + (L >> 3);
+  if (T >= ntiles) return;
+  const int tm = (int)(T % nbm);
+  const int64_t tn = T / nbm;
+  const int64_t m0 = (int64_t)tm * kXM, n0 = tn * kXN;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  // global -> register staging: Y rows t/2, 8 terms from (t&1)*8; phi row t/16,
+  // 8 entries from (t&15)*8
+  const int yr = t >> 1, yj = (t & 1) * 8;
+  const int pr = t >> 4, pc = (t & 15) * 8;
+  const int64_t yb = m0 + yr;
+  const int64_t pe = n0 + pc;  // E is even and pe is even: pairs are in or out together
+  double ry[8], rp[8];
+  auto load = [&](int j0) {
 #pragma unroll
-  for (int k = 0; k < kExpBS; ++k) acc[k] = a0;
-  for (int j0 = 0; j0 < s; j0 += kExpJC) {
-    const int jc = (s - j0 < kExpJC) ? s - j0 : kExpJC;
-    for (int t = threadIdx.x; t < kExpBS * kExpJC; t += 256) {
-      const int bb = t / kExpJC, jj = t % kExpJC;
-      ys[bb][jj] = (b0 + bb < B && jj < jc) ? Y[(b0 + bb) * ldY + j0 + jj] : 0.0;
+    for (int q = 0; q < 8; ++q) {
+      const int j = j0 + yj + q;
+      ry[q] = (yb < B && j < s) ? Y[yb * ldY + j] : 0.0;
     }
-    __syncthreads();
-    if (e < E) {
-      for (int jj = 0; jj < jc; ++jj) {
-        const double ph = phi[(int64_t)(j0 + jj) * E + e];
+    const int j = j0 + pr;
+    const double* src = phi + (int64_t)j * E + pe;
 #pragma unroll
-        for (int k = 0; k < kExpBS; ++k) acc[k] += ys[k][jj] * ph;
+    for (int q = 0; q < 8; q += 2) {
+      if (j < s && pe + q < E) {
+        const double2 v = *reinterpret_cast<const double2*>(src + q);
+        rp[q] = v.x;
+        rp[q + 1] = v.y;
+      } else {
+        rp[q] = rp[q + 1] = 0.0;
       }
     }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sY[buf][yj + q][yr] = ry[q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sP[buf][pr][pc + q] = rp[q];
+  };
+  v4d acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int nch = (s + kXK - 1) / kXK;
+  load(0);
+  store(0);
+  __syncthreads();
+  const int fr = lane & 15, fk = lane >> 4;
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) load((c + 1) * kXK);
+#pragma unroll
+    for (int kk = 0; kk < kXK; kk += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = sY[buf][kk + fk][wm * 64 + i * 16 + fr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = sP[buf][kk + fk][wn * 64 + j * 16 + fr];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (c + 1 < nch) store(buf ^ 1);
     __syncthreads();
   }
-  if (e < E) {
+  // D[row][col] of a 16 x 16 tile: lane holds col = lane & 15 and, in its
+  // r-th value, row 4 r + (lane >> 4) (A[row][k] sits in lane row + 16 k,
+  // B[k][col] in lane col + 16 k)
 #pragma unroll
-    for (int k = 0; k < kExpBS; ++k)
-      if (b0 + k < B) out[(b0 + k) * (int64_t)E + e] = acc[k];
-  }
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t e = n0 + wn * 64 + j * 16 + fr;
+      if (e >= E) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t b = m0 + wm * 64 + i * 16 + 4 * r + fk;
+        if (b < B) {
+          const double v = a0 + acc[i][j][r];
+          out[b * E + e] = v;
+          if (out32) out32[b * E + e] = (float)v;
+        }
+      }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_level_sums(int64_t N, const double* __restrict__ lam,
@@ -225,11 +298,17 @@ hipError_t launch_phi_edges_padded(int n, int s, const double* phi_el, double* p
   return hipGetLastError();
 }
 
-hipError_t launch_expand(int64_t B, int s, int E, const double* Y, int64_t ldY,
-                         const double* phi, double a0, double* out, hipStream_t st) {
-  if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_expand, dim3((E + 255) / 256, (unsigned)((B + kExpBS - 1) / kExpBS)),
-                     dim3(256), 0, st, B, s, E, Y, ldY, phi, a0, out);
+hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t ldY,
+                         const double* phi, double a0, double* out, float* out32,
+                         hipStream_t st) {
+  if (B <= 0 || E <= 0) return hipSuccess;
+  if (E & 1) return hipErrorInvalidValue;  // rows of phi are read in aligned pairs
+  const int nbm = (int)((B + kXM - 1) / kXM);
+  const int64_t nbn = (E + kXN - 1) / kXN;
+  const int64_t ntiles = (int64_t)nbm * nbn;
+  const int64_t per_xcd = (ntiles + 7) / 8;
+  hipLaunchKernelGGL(k_expand_mfma, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, st, B, s, E, Y,
+                     ldY, phi, a0, out, out32, nbm, per_xcd, ntiles);
   return hipGetLastError();
 }
 

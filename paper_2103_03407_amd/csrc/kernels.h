@@ -92,7 +92,6 @@ hipError_t launch_prolong_interior(int nH, int nh, int64_t B, const double* uH, 
                                    hipStream_t st);
 template <typename T>
 hipError_t launch_coarsen(int n, int64_t B, const T* w, T* wc, hipStream_t st);
-hipError_t launch_to_float(int64_t count, const double* x, float* y, hipStream_t st);
 hipError_t launch_setup_dots(int n, int64_t B, const double* v, const double* w, double* part,
                              hipStream_t st);
 template <typename T>
@@ -152,8 +151,9 @@ hipError_t launch_phi_edges(int n, int s, const double* phi_el, double* phi_edge
 hipError_t launch_phi_edges_padded(int n, int s, const double* phi_el, double* phi_pad,
                                    hipStream_t st);
 // out[b][e] = a0 + sum_{j<s} Y[b][j] phi[j][e], e < E
-hipError_t launch_expand(int64_t B, int s, int E, const double* Y, int64_t ldY,
-                         const double* phi, double a0, double* out, hipStream_t st);
+hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t ldY,
+                         const double* phi, double a0, double* out, float* out32,
+                         hipStream_t st);
 // Q[l*R + r] = (1/N) sum_k (lam[r*N + k] - lam_prev[r*N + k]) (fixed-order tree);
 // lam_prev may be nullptr (lambda^{-1} = 0)
 hipError_t launch_level_sums(int64_t N, int R, const double* lam, const double* lam_prev,
