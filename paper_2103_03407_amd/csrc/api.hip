@@ -306,7 +306,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   auto P = [](int m) { return padded_size(m); };                // padded vector
   auto EW = [](int m) { return 2 * padded_size(m); };           // padded [WX | WY]
   const int64_t sz = (int64_t)sizeof(T);
-  int64_t per_sample = 8 * (EW(nh) + 2 * P(nh)) + sz * (9 * P(nh)) + (kMixed ? 4 * EW(nh) : 0);
+  int64_t per_sample = 8 * (EW(nh) + 2 * P(nh)) + sz * (10 * P(nh)) + (kMixed ? 4 * EW(nh) : 0);
   for (size_t k = 1; k < nL; ++k) per_sample += sz * (EW(lv[k]) + 3 * P(lv[k]));
   per_sample += sz * (EW(nb) + 2 * P(nb));
   // default batch: up to 48 GB of working arrays (HBM holds 288 GB), in
@@ -323,7 +323,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   std::string p = tag;
   auto nm = [&](const char* x) { return p + x; };
   double *w64, *v64, *part;
-  T *wT, *vn, *mvn, *t, *r, *z, *zb, *q, *pp[2];
+  T *wT, *vn, *mvn, *t, *r, *r2, *z, *zb, *q, *pp[2];
   CS(ctx->getT(nm("w64").c_str(), batch * EW(nh), &w64));
   if constexpr (kMixed) {
     CS(ctx->getT(nm("w32").c_str(), batch * EW(nh), &wT));
@@ -334,9 +334,9 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   // blocks per sample <= (rows + 7) / 8 strips x (column blocks <= 4): bound the
   // partial-sum buffer by the most strips any batch size can take, 3 partials each
   CS(ctx->getT(nm("part").c_str(), batch * (4 * ((nh + 6) / 8) + 4) * 6, &part));
-  const char* vnames[] = {"vn", "t", "r", "z", "zb", "q", "p0", "p1", "mvn"};
-  T** vptr[] = {&vn, &t, &r, &z, &zb, &q, &pp[0], &pp[1], &mvn};
-  for (int k = 0; k < 9; ++k) {
+  const char* vnames[] = {"vn", "t", "r", "z", "zb", "q", "p0", "p1", "mvn", "r2"};
+  T** vptr[] = {&vn, &t, &r, &z, &zb, &q, &pp[0], &pp[1], &mvn, &r2};
+  for (int k = 0; k < 10; ++k) {
     std::string key = nm(vnames[k]) + (kMixed ? "_f" : "_d");
     CS(ctx->getT(key.c_str(), batch * P(nh), vptr[k]));
   }
@@ -361,8 +361,8 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   // kernels write interior positions only.
   {
     hipStream_t st = ctx->stream;
-    void* top[] = {vn, t, r, z, zb, q, pp[0], pp[1], mvn};
-    CK(launch_zero_boundary(nh, batch, top, 9, (int)sz, st), "zero boundary");
+    void* top[] = {vn, t, r, z, zb, q, pp[0], pp[1], mvn, r2};
+    CK(launch_zero_boundary(nh, batch, top, 10, (int)sz, st), "zero boundary");
     void* v64p[] = {v64};
     CK(launch_zero_boundary(nh, batch, v64p, 1, 8, st), "zero boundary");
     for (size_t k = 1; k <= nL; ++k) {
@@ -433,12 +433,24 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     bool all_active = true;
     T* zc = z;   // current preconditioned residual
     T* zo = zb;  // the other buffer
-    auto vcycle = [&]() -> mlqmc_status {
+    T* rc = r;   // current residual
+    T* ro = r2;  // the other buffer
+    // upd: bring the residual up to date first, r <- r - alpha (q - c M vn),
+    // inside the finest pre-smoothing kernel (the result lands in ro)
+    auto vcycle = [&](bool upd) -> mlqmc_status {
       if (all_active) ctx->t_begin(MLQMC_K_PRE);
-      CK(launch_pre<T>(nh, Bn, wT, r, zc, Bv[1], act, st), "pre");
+      if (upd) {
+        CK(launch_pre<T>(nh, Bn, wT, rc, zc, Bv[1], act, q, mvn, &S, ro, st), "pre");
+        std::swap(rc, ro);
+      } else {
+        CK(launch_pre<T>(nh, Bn, wT, rc, zc, Bv[1], act, nullptr, nullptr, nullptr, nullptr, st),
+           "pre");
+      }
       if (all_active) ctx->t_end(MLQMC_K_PRE, pre_b);
       for (size_t k = 1; k < nL; ++k)
-        CK(launch_pre<T>(lv[k], Bn, W[k], Bv[k], X[k], Bv[k + 1], act, st), "pre");
+        CK(launch_pre<T>(lv[k], Bn, W[k], Bv[k], X[k], Bv[k + 1], act, nullptr, nullptr, nullptr,
+                         nullptr, st),
+           "pre");
       CK(launch_bottom_vcycle<T>(nb, Bn, W[nL], Bv[nL], X[nL], act, st), "bottom");
       const T* xc = X[nL];
       for (size_t k = nL - 1; k >= 1; --k) {
@@ -448,12 +460,12 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
         xc = Xb[k];
       }
       if (all_active) ctx->t_begin(MLQMC_K_SMOOTH);
-      CK(launch_post<T>(nh, Bn, wT, r, zc, xc, zo, vn, mvn, act, part, st), "post");
+      CK(launch_post<T>(nh, Bn, wT, rc, zc, xc, zo, vn, mvn, act, part, st), "post");
       if (all_active) ctx->t_end(MLQMC_K_SMOOTH, post_b);
       std::swap(zc, zo);
       return MLQMC_OK;
     };
-    CS(vcycle());
+    CS(vcycle(false));
     all_active = false;
     const int nblk_post = post_strips(nh, Bn);
     CK(launch_scalar(PH_FIRST_RZ, nh, Bn, nblk_post, part, S, 0.0, 0, st), "scalar");
@@ -468,8 +480,8 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
       if (it == 0) ctx->t_end(MLQMC_K_APPLY, ab);
       cur = 1 - cur;
       CK(launch_scalar(PH_ALPHA, nh, Bn, nblk0, part, S, lam_tol(o), 0, st), "scalar");
-      CK(launch_update<T>(nh, Bn, pp[cur], q, mvn, S, t, r, st), "update");
-      CS(vcycle());
+      // t += alpha p happens in the next apply (or the final dots)
+      CS(vcycle(true));
       CK(launch_scalar(PH_BETA, nh, Bn, nblk_post, part, S, lin_tol(o), o->max_lin_iter, st),
          "scalar");
       if (it % 3 == 2 || it + 1 == o->max_lin_iter) {
@@ -480,7 +492,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
         if (!any) break;
       }
     }
-    CK(launch_final_dots<T>(nh, Bn, v64, t, w64, S, part, st), "final dots");
+    CK(launch_final_dots<T>(nh, Bn, v64, t, pp[0], pp[1], w64, S, part, st), "final dots");
     CK(launch_scalar(PH_FINAL, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
   }
   return MLQMC_OK;

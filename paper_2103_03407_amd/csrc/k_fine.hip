@@ -363,7 +363,7 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
                                                        const T* __restrict__ pin,
                                                        const T* __restrict__ mvn,
                                                        const T* __restrict__ w,
-                                                       const T* __restrict__ t, FineState S,
+                                                       T* __restrict__ t, FineState S,
                                                        int first, T* __restrict__ pout,
                                                        T* __restrict__ q,
                                                        double* __restrict__ part) {
@@ -377,8 +377,9 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
   const T* mb = mvn + b * g.P;
   const T* wx = w + b * 2 * g.P;
   const T* wy = wx + g.P;
-  const T* tb = t + b * g.P;
+  T* tb = t + b * g.P;
   const T c2 = (T)S.c2[b], beta = first ? T(0) : (T)S.beta[b], mu = (T)S.mu[b];
+  const T alpha = first ? T(0) : (T)S.alpha[b];  // the previous step, not yet applied to t
   const T hm = (T)mass_scale(g.n);
   double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   march<T, NTC>(ring, g, c0, j0, j1, dir,
@@ -392,7 +393,13 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
                   const int64_t o = b * g.P + k;
                   pout[o] = pc;
                   q[o] = qv;
-                  const double tk = (double)tb[k];
+                  // t_k = t_{k-1} + alpha_{k-1} p_{k-1}, the iterate this step starts from
+                  T tn = tb[k];
+                  if (!first) {
+                    tn += alpha * pb[k];
+                    tb[k] = tn;
+                  }
+                  const double tk = (double)tn;
                   s[0] += (double)pc * (double)qv;
                   s[1] += (double)vb[k] * (double)qv;
                   s[2] += (double)pc * (double)mb[k];
@@ -401,24 +408,6 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
                   s[5] += tk * (double)qv;
                 });
   write_partials_m<NTC, 6>(s, part, b, blk, g.nblk);
-}
-
-// t += alpha p; r -= alpha (q - c M vn)
-template <typename T>
-__global__ __launch_bounds__(NT) void k_update(Geo g, const T* __restrict__ p,
-                                               const T* __restrict__ q, const T* __restrict__ mvn,
-                                               FineState S, T* __restrict__ t,
-                                               T* __restrict__ r) {
-  int64_t b;
-  int blk;
-  if (!map_block(g, b, blk) || !S.active[b]) return;
-  const T* mb = mvn + b * g.P;
-  const T alpha = (T)S.alpha[b], c = (T)S.c[b];
-  FOR_NODES(g, blk) {
-    const int64_t o = b * g.P + k;
-    t[o] += alpha * p[o];
-    r[o] -= alpha * (q[o] - c * mb[k]);
-  }
 }
 
 // ---------------------------------------------------------------- V-cycle
@@ -460,11 +449,17 @@ __device__ __forceinline__ T rowA(const T* rs, const T* rc, const T* rn, int c, 
 //   zb = omega rhs / D;  X = zb + omega (rhs - A zb) / D;  rhs_c = P^T (rhs - A X)
 // Strip s owns coarse rows [J0, J1) and fine rows [2 J0 - 1, 2 J1 - 1) (the last
 // strip also row n-1).
-template <typename T, int NTC, int CPT>
+// With kUpd (the finest level inside the PCG loop) the right-hand side is
+// first brought up to date, r' = r - alpha (q - c M vn), and r' written to
+// rout on the rows the strip owns (a second buffer: neighbouring strips still
+// read r on their halo rows).
+template <typename T, int NTC, int CPT, bool kUpd>
 __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
                                              const T* __restrict__ rhs, T* __restrict__ X,
                                              T* __restrict__ rhs_c,
-                                             const uint8_t* __restrict__ active) {
+                                             const uint8_t* __restrict__ active,
+                                             const T* __restrict__ qd, const T* __restrict__ mvn,
+                                             FineState S, T* __restrict__ rout) {
   constexpr int NR = NTC * CPT + 1;
   __shared__ T s_zb[4][NR], s_x[4][NR], s_res[4][NR];
   int64_t b;
@@ -480,6 +475,11 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
   const T* wy = wx + g.P;
   T* xb = X + b * g.P;
   T* cb = rhs_c + b * (int64_t)((nc + 2) * nc);
+  T alpha = T(0), cc = T(0);
+  if constexpr (kUpd) {
+    alpha = (T)S.alpha[b];
+    cc = (T)S.c[b];
+  }
   if (t == 0)
     for (int r = 0; r < 4; ++r) s_zb[r][n] = s_x[r][n] = s_res[r][n] = T(0);
   // register window of the row inputs (rhs, the 4 edge weights) of the rows at
@@ -497,7 +497,14 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
         const int c = t + q * NTC, k = j * n + c;
         T v = T(0);
         if (ok && c >= 1) {
-          in0[q][0] = rb[k];
+          if constexpr (kUpd) {
+            const int64_t o = b * g.P + k;
+            const T rn = rb[k] - alpha * (qd[o] - cc * mvn[o]);
+            if (j >= lo && j < own_hi) rout[o] = rn;
+            in0[q][0] = rn;
+          } else {
+            in0[q][0] = rb[k];
+          }
           in0[q][1] = wx[k];
           in0[q][2] = wx[k + 1];
           in0[q][3] = wy[k];
@@ -696,6 +703,8 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
 template <typename T, int NTC>
 __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, const double* __restrict__ v,
                                                     const T* __restrict__ t,
+                                                    const T* __restrict__ p0,
+                                                    const T* __restrict__ p1,
                                                     const double* __restrict__ w, FineState S,
                                                     double* __restrict__ part) {
   __shared__ double ring[4][NTC + 2];
@@ -704,11 +713,17 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, const double* __rest
   if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir)) return;
   const double* vb = v + b * g.P;
   const T* tb = t + b * g.P;
+  // the sample's last step alpha p is still to be added to t: its direction
+  // sits in the buffer that iteration its - 1 wrote
+  const int its = S.its[b];
+  const T* pl = ((its & 1) ? p1 : p0) + b * g.P;
+  const T al = its > 0 ? (T)S.alpha[b] : T(0);
   const double vs = S.vs[b];
   const double* wx = w + b * 2 * g.P;
   const double* wy = wx + g.P;
   double s[2] = {0.0, 0.0};
-  march<double, NTC>(ring, g, c0, j0, j1, dir, [&](int k) { return vs * vb[k] + (double)tb[k]; },
+  march<double, NTC>(ring, g, c0, j0, j1, dir,
+                     [&](int k) { return vs * vb[k] + (double)(T)(tb[k] + al * pl[k]); },
                      [&](int, int, int k, const double* rs, const double* rc, const double* rn,
                          int ci) {
                        double d;
@@ -938,21 +953,13 @@ hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64
 
 template <typename T>
 hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
-                                const T* mvn, const T* w, const T* t, const FineState& S,
+                                const T* mvn, const T* w, T* t, const FineState& S,
                                 int first, T* pout, T* q, double* part, hipStream_t st) {
   MARCH_DISPATCH(n, {
     const MGeo g = mgeo<NTC>(n, B);
     hipLaunchKernelGGL((k_pupdate_apply<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, z, vn, pin,
                        mvn, w, t, S, first, pout, q, part);
   });
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_update(int n, int64_t B, const T* p, const T* q, const T* mvn,
-                         const FineState& S, T* t, T* r, hipStream_t st) {
-  const Geo g = geo(n, B);
-  hipLaunchKernelGGL(k_update<T>, grid_of(g), dim3(NT), 0, st, g, p, q, mvn, S, t, r);
   return hipGetLastError();
 }
 
@@ -1006,12 +1013,20 @@ inline dim3 sgrid(const VGeo& g) {
 
 template <typename T>
 hipError_t launch_pre(int n, int64_t B, const T* w, const T* rhs, T* X, T* rhs_c,
-                      const uint8_t* active, hipStream_t st) {
+                      const uint8_t* active, const T* q, const T* mvn, const FineState* S,
+                      T* rout, hipStream_t st) {
   const VGeo g = vgeo_pre(n, B);
+  const bool upd = q != nullptr;
+  if (upd && (!mvn || !S || !rout || rout == rhs)) return hipErrorInvalidValue;
+  const FineState s0 = S ? *S : FineState{};
   ROW_DISPATCH(n, {
     if (NTC * CPT != n) return hipErrorInvalidValue;  // a block covers one full row
-    hipLaunchKernelGGL((k_pre<T, NTC, CPT>), sgrid(g), dim3(NTC), 0, st, g, w, rhs, X, rhs_c,
-                       active);
+    if (upd)
+      hipLaunchKernelGGL((k_pre<T, NTC, CPT, true>), sgrid(g), dim3(NTC), 0, st, g, w, rhs, X,
+                         rhs_c, active, q, mvn, s0, rout);
+    else
+      hipLaunchKernelGGL((k_pre<T, NTC, CPT, false>), sgrid(g), dim3(NTC), 0, st, g, w, rhs, X,
+                         rhs_c, active, q, mvn, s0, rout);
   });
   return hipGetLastError();
 }
@@ -1042,12 +1057,13 @@ int march_blocks(int n, int64_t B) {
 }
 
 template <typename T>
-hipError_t launch_final_dots(int n, int64_t B, const double* v, const T* t, const double* w,
-                             const FineState& S, double* part, hipStream_t st) {
+hipError_t launch_final_dots(int n, int64_t B, const double* v, const T* t, const T* p0,
+                             const T* p1, const double* w, const FineState& S, double* part,
+                             hipStream_t st) {
   MARCH_DISPATCH(n, {
     const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_final_dots<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, v, t, w, S,
-                       part);
+    hipLaunchKernelGGL((k_final_dots<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, v, t, p0, p1,
+                       w, S, part);
   });
   return hipGetLastError();
 }
@@ -1074,19 +1090,17 @@ hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* s
   template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, const double*,           \
                                           const FineState&, T*, T*, T*, T*, hipStream_t);       \
   template hipError_t launch_pupdate_apply<T>(int, int64_t, const T*, const T*, const T*,       \
-                                              const T*, const T*, const T*, const FineState&,   \
+                                              const T*, const T*, T*, const FineState&,         \
                                               int, T*, T*, double*, hipStream_t);               \
-  template hipError_t launch_update<T>(int, int64_t, const T*, const T*, const T*,              \
-                                       const FineState&, T*, T*, hipStream_t);                  \
-  template hipError_t launch_final_dots<T>(int, int64_t, const double*, const T*,               \
-                                           const double*, const FineState&, double*,            \
+  template hipError_t launch_final_dots<T>(int, int64_t, const double*, const T*, const T*,     \
+                                           const T*, const double*, const FineState&, double*,  \
                                            hipStream_t);
 INST(double)
 INST(float)
 #undef INST
 #define INST(T)                                                                                 \
   template hipError_t launch_pre<T>(int, int64_t, const T*, const T*, T*, T*, const uint8_t*,   \
-                                    hipStream_t);                                               \
+                                    const T*, const T*, const FineState*, T*, hipStream_t);     \
   template hipError_t launch_post<T>(int, int64_t, const T*, const T*, const T*, const T*, T*,  \
                                      const T*, const T*, const uint8_t*, double*, hipStream_t);
 INST(double)

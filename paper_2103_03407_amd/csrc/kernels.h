@@ -99,16 +99,15 @@ hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64
                             const FineState& S, T* r, T* t, T* vn, T* mvn, hipStream_t st);
 template <typename T>
 hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
-                                const T* mvn, const T* w, const T* t, const FineState& S,
+                                const T* mvn, const T* w, T* t, const FineState& S,
                                 int first, T* pout, T* q, double* part, hipStream_t st);
-template <typename T>
-hipError_t launch_update(int n, int64_t B, const T* p, const T* q, const T* mvn,
-                         const FineState& S, T* t, T* r, hipStream_t st);
 // fused V-cycle level, pre-smoothing from zero and restriction:
-//   X = two damped-Jacobi sweeps on A X = rhs from X = 0; rhs_c = P^T (rhs - A X)
+//   X = two damped-Jacobi sweeps on A X = rhs from X = 0; rhs_c = P^T (rhs - A X);
+//   with q != nullptr the rhs is first updated, rhs - alpha (q - c mvn) -> rout
 template <typename T>
 hipError_t launch_pre(int n, int64_t B, const T* w, const T* rhs, T* X, T* rhs_c,
-                      const uint8_t* active, hipStream_t st);
+                      const uint8_t* active, const T* q, const T* mvn, const FineState* S,
+                      T* rout, hipStream_t st);
 // fused V-cycle level, coarse correction and post-smoothing:
 //   Xout = two sweeps from Xin + P Xc; with part != nullptr also the partials
 //   rhs.Xout, mvn.Xout, rhs.vn per strip (level 0 of the projected PCG)
@@ -121,8 +120,9 @@ int post_strips(int n, int64_t B);
 // blocks per sample of the row-marching kernels for a batch of B (their partial-sum count)
 int march_blocks(int n, int64_t B);
 template <typename T>
-hipError_t launch_final_dots(int n, int64_t B, const double* v, const T* t, const double* w,
-                             const FineState& S, double* part, hipStream_t st);
+hipError_t launch_final_dots(int n, int64_t B, const double* v, const T* t, const T* p0,
+                             const T* p1, const double* w, const FineState& S, double* part,
+                             hipStream_t st);
 
 // scalar phases: one wavefront per sample sums that sample's block partials
 enum ScalarPhase { PH_SETUP = 0, PH_FIRST_RZ = 1, PH_ALPHA = 2, PH_BETA = 3, PH_FINAL = 4 };
