@@ -85,6 +85,7 @@ struct mlqmc_ctx {
       return MLQMC_OK;
     }
     if (b.p) {
+      zeroed.erase(b.p);
       hipFree(b.p);
       bytes_alloc -= (int64_t)b.bytes;
       b.p = nullptr;
@@ -103,6 +104,20 @@ struct mlqmc_ctx {
     *out = b.p;
     return MLQMC_OK;
   }
+  // Padded per-node buffers whose Dirichlet positions are known to be zero:
+  // pointer -> (mesh, element size, samples).  Kernels never write those
+  // positions, so a buffer is zeroed once per layout, not once per call.
+  struct ZeroKey {
+    int n, elem;
+    int64_t batch;
+  };
+  std::map<void*, ZeroKey> zeroed;
+  bool boundary_is_zero(void* p, int n, int elem, int64_t batch) const {
+    auto it = zeroed.find(p);
+    return it != zeroed.end() && it->second.n == n && it->second.elem == elem &&
+           it->second.batch >= batch;
+  }
+
   template <typename T>
   mlqmc_status getT(const char* name, size_t count, T** out) {
     void* p = nullptr;
@@ -361,14 +376,23 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   // kernels write interior positions only.
   {
     hipStream_t st = ctx->stream;
-    void* top[] = {vn, t, r, z, zb, q, pp[0], pp[1], mvn, r2};
-    CK(launch_zero_boundary(nh, batch, top, 10, (int)sz, st), "zero boundary");
-    void* v64p[] = {v64};
-    CK(launch_zero_boundary(nh, batch, v64p, 1, 8, st), "zero boundary");
+    auto zero = [&](int m, std::initializer_list<void*> ptrs, int elem) -> mlqmc_status {
+      std::vector<void*> todo;
+      for (void* q : ptrs)
+        if (!ctx->boundary_is_zero(q, m, elem, batch)) todo.push_back(q);
+      if (todo.empty()) return MLQMC_OK;
+      CK(launch_zero_boundary(m, batch, todo.data(), (int)todo.size(), elem, st), "zero boundary");
+      for (void* q : todo) ctx->zeroed[q] = mlqmc_ctx::ZeroKey{m, elem, batch};
+      return MLQMC_OK;
+    };
+    CS(zero(nh, {vn, t, r, z, zb, q, pp[0], pp[1], mvn, r2}, (int)sz));
+    CS(zero(nh, {v64}, 8));
     for (size_t k = 1; k <= nL; ++k) {
       const int m = (k < nL) ? lv[k] : nb;
-      void* lp[] = {X[k], Bv[k], k < nL ? (void*)Xb[k] : (void*)X[k]};
-      CK(launch_zero_boundary(m, batch, lp, 3, (int)sz, st), "zero boundary");
+      if (k < nL)
+        CS(zero(m, {X[k], Bv[k], Xb[k]}, (int)sz));
+      else
+        CS(zero(m, {X[k], Bv[k]}, (int)sz));
     }
   }
   double* sc = nullptr;

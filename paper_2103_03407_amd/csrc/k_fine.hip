@@ -233,13 +233,16 @@ struct ZeroArgs {
   int cnt;
   int elem;  // bytes per element
 };
-__global__ __launch_bounds__(256) void k_zero_boundary(int n, int64_t B, ZeroArgs za) {
-  const int64_t b = blockIdx.y;
-  const int a = blockIdx.z;
+// grid: x = (blocks per sample) x samples, y = arrays
+__global__ __launch_bounds__(256) void k_zero_boundary(int n, int64_t B, int per_blocks,
+                                                       ZeroArgs za) {
+  const int64_t b = blockIdx.x / per_blocks;
+  const int xb = (int)(blockIdx.x - b * per_blocks);
+  const int a = blockIdx.y;
   if (b >= B || a >= za.cnt) return;
   const int P = (n + 2) * n;
   // positions: row 0 (n), rows n and n+1 (2n), column 0 of rows 1..n-1 (n-1)
-  for (int t = blockIdx.x * 256 + threadIdx.x; t < 4 * n - 1; t += gridDim.x * 256) {
+  for (int t = xb * 256 + threadIdx.x; t < 4 * n - 1; t += per_blocks * 256) {
     const int k = t < n ? t : (t < 3 * n ? n * n + (t - n) : (t - 3 * n + 1) * n);
     if (za.elem == 8)
       static_cast<double*>(za.p[a])[b * P + k] = 0.0;
@@ -262,12 +265,12 @@ __global__ __launch_bounds__(NT) void k_prolong(Geo g, int nH, const double* __r
 }
 
 // interior-layout prolongation for the component entry point
-__global__ __launch_bounds__(256) void k_prolong_interior(int nH, int nh, int64_t B,
+__global__ __launch_bounds__(256) void k_prolong_interior(int xblk, int nH, int nh, int64_t B,
                                                           const double* __restrict__ uH,
                                                           double* __restrict__ uh) {
   const int mH = nH - 1, mh = nh - 1, Dh = mh * mh;
-  const int id = blockIdx.x * 256 + threadIdx.x;
-  const int64_t b = blockIdx.y;
+  const int64_t b = blockIdx.x / xblk;  // grid x = xblk blocks per sample x samples
+  const int id = (int)(blockIdx.x - b * xblk) * 256 + threadIdx.x;
   if (id >= Dh || b >= B) return;
   const int j = id / mh + 1, i = id - (j - 1) * mh + 1;
   uh[b * Dh + id] = interp_coarse(uH + b * (int64_t)(mH * mH), nH, nh / nH, i, j);
@@ -275,12 +278,12 @@ __global__ __launch_bounds__(256) void k_prolong_interior(int nH, int nh, int64_
 
 // padded weights of mesh n/2 from those of mesh n (means of collinear fine edges)
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarsen(int n, int64_t B, const T* __restrict__ w,
+__global__ __launch_bounds__(256) void k_coarsen(int xblk, int n, int64_t B, const T* __restrict__ w,
                                                  T* __restrict__ wc) {
   const int nc = n / 2;
   const int P = (n + 2) * n, Pc = (nc + 2) * nc;
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  const int64_t b = blockIdx.y;
+  const int64_t b = blockIdx.x / xblk;  // grid x = xblk blocks per sample x samples
+  const int e = (int)(blockIdx.x - b * xblk) * 256 + threadIdx.x;
   if (e >= 2 * Pc || b >= B) return;
   const T* wx = w + b * 2 * P;
   const T* wy = wx + P;
@@ -836,14 +839,14 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
 }
 
 // interior-layout operator apply for the component entry point
-__global__ __launch_bounds__(256) void k_apply_plain(int n, int64_t B,
+__global__ __launch_bounds__(256) void k_apply_plain(int xblk, int n, int64_t B,
                                                      const double* __restrict__ w,
                                                      const double* __restrict__ sigma,
                                                      const double* __restrict__ x,
                                                      double* __restrict__ out) {
   const int m = n - 1, D = m * m, EX = (n - 1) * n;
-  const int id = blockIdx.x * 256 + threadIdx.x;
-  const int64_t b = blockIdx.y;
+  const int64_t b = blockIdx.x / xblk;  // grid x = xblk blocks per sample x samples
+  const int id = (int)(blockIdx.x - b * xblk) * 256 + threadIdx.x;
   if (id >= D || b >= B) return;
   const int j = id / m + 1, i = id - (j - 1) * m + 1;
   const double* xb = x + b * D;
@@ -878,9 +881,9 @@ hipError_t launch_zero_boundary(int n, int64_t B, void* const* ptrs, int cnt, in
   for (int a = 0; a < cnt; ++a) za.p[a] = ptrs[a];
   za.cnt = cnt;
   za.elem = elem;
-  const int per = 4 * n - 1;
-  hipLaunchKernelGGL(k_zero_boundary, dim3((per + 255) / 256, (unsigned)B, cnt), dim3(256), 0, st,
-                     n, B, za);
+  const int per_blocks = (4 * n - 1 + 255) / 256;
+  hipLaunchKernelGGL(k_zero_boundary, dim3((unsigned)(per_blocks * B), cnt), dim3(256), 0, st, n,
+                     B, per_blocks, za);
   return hipGetLastError();
 }
 
@@ -896,7 +899,8 @@ hipError_t launch_prolong_interior(int nH, int nh, int64_t B, const double* uH, 
                                   hipStream_t st) {
   if (B <= 0) return hipSuccess;
   const int Dh = (nh - 1) * (nh - 1);
-  hipLaunchKernelGGL(k_prolong_interior, dim3((Dh + 255) / 256, (unsigned)B), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_prolong_interior, dim3((unsigned)((Dh + 255) / 256 * B)), dim3(256), 0, st,
+                     (Dh + 255) / 256,
                      nH, nh, B, uH, uh);
   return hipGetLastError();
 }
@@ -905,7 +909,8 @@ template <typename T>
 hipError_t launch_coarsen(int n, int64_t B, const T* w, T* wc, hipStream_t st) {
   const int nc = n / 2;
   const int E = 2 * (nc + 2) * nc;
-  hipLaunchKernelGGL(k_coarsen<T>, dim3((E + 255) / 256, (unsigned)B), dim3(256), 0, st, n, B, w,
+  hipLaunchKernelGGL(k_coarsen<T>, dim3((unsigned)((E + 255) / 256 * B)), dim3(256), 0, st,
+                     (E + 255) / 256, n, B, w,
                      wc);
   return hipGetLastError();
 }
@@ -1080,7 +1085,8 @@ hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* s
                               const double* x, double* out, hipStream_t st) {
   if (B <= 0) return hipSuccess;
   const int D = (n - 1) * (n - 1);
-  hipLaunchKernelGGL(k_apply_plain, dim3((D + 255) / 256, (unsigned)B), dim3(256), 0, st, n, B, w,
+  hipLaunchKernelGGL(k_apply_plain, dim3((unsigned)((D + 255) / 256 * B)), dim3(256), 0, st,
+                     (D + 255) / 256, n, B, w,
                      sigma, x, out);
   return hipGetLastError();
 }

@@ -37,6 +37,10 @@ def ctx(fam):
     c.close()
 
 
+def ctx_family(ctx):
+    return coeff_family(512, decay=2.5)
+
+
 def _lv6(lv):
     return (lv.n_fine, lv.s_fine, lv.n_coarse, lv.s_coarse, lv.n_prev, lv.s_prev)
 
@@ -417,6 +421,20 @@ def test_device_tensors_match_host(ctx):
     ctx.eig_level((128, 64, 32, 8, 0, 0), Yd, ld, fd)
     assert np.array_equal(ld.cpu().numpy(), lh)
     assert not fd.cpu().numpy().any()
+
+
+def test_buffer_reuse_across_meshes(ctx):
+    # the working arrays are reused between calls with different meshes and
+    # batch sizes; their zero Dirichlet padding must follow the layout
+    Y = np.ascontiguousarray(_points(1024, 128, 2, 0, 7, range(12)))
+    a, b, c = np.empty(12), np.empty(12), np.empty(5)
+    ctx.eig_level((128, 64, 32, 8, 0, 0), np.ascontiguousarray(Y[:, :64]), a, np.zeros(12, np.uint8))
+    ctx.eig_level((256, 128, 16, 16, 0, 0), np.ascontiguousarray(Y[:5]), c, np.zeros(5, np.uint8))
+    ctx.eig_level((128, 64, 32, 8, 0, 0), np.ascontiguousarray(Y[:, :64]), b, np.zeros(12, np.uint8))
+    assert np.array_equal(a, b)
+    for k in (0, 4):
+        tg = twogrid.two_grid(256, 128, 16, 16, Y[k], ctx_family(ctx))[0]
+        assert abs(c[k] - tg) <= LAM_RTOL * tg
 
 
 def test_repeat_runs_bitwise_identical(ctx):
