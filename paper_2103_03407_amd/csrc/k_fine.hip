@@ -486,10 +486,31 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
   if (t == 0)
     for (int r = 0; r < 4; ++r) s_zb[r][n] = s_x[r][n] = s_res[r][n] = T(0);
   // register window of the row inputs (rhs, the 4 edge weights) of the rows at
-  // stages 1, 2 and 3: each is loaded once, at stage 1
-  T in0[CPT][5], in1[CPT][5], in2[CPT][5];
+  // stages 1, 2 and 3: each is loaded once, one row ahead of stage 1 (nx;
+  // with kUpd also q and M vn), and carried through the stages
+  T nx[CPT][7], in0[CPT][5], in1[CPT][5], in2[CPT][5];
+  auto fetch = [&](int j) {
+    if (!(j >= 1 && j <= n - 1)) return;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = t + q * NTC, k = j * n + c;
+      if (c >= 1) {
+        nx[q][0] = rb[k];
+        nx[q][1] = wx[k];
+        nx[q][2] = wx[k + 1];
+        nx[q][3] = wy[k];
+        nx[q][4] = wy[k + n];
+        if constexpr (kUpd) {
+          nx[q][5] = qd[b * g.P + k];
+          nx[q][6] = mvn[b * g.P + k];
+        }
+      }
+    }
+  };
   const int jfirst = dir > 0 ? lo - 2 : hi + 2;
-  for (int i = 0; i <= hi - lo + 4; ++i) {
+  const int last = hi - lo + 4;
+  fetch(jfirst);
+  for (int i = 0; i <= last; ++i) {
     const int j = jfirst + i * dir;
     // stage 1: zb(j)
     {
@@ -497,21 +518,23 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
       const bool ok = (j >= 1 && j <= n - 1);
 #pragma unroll
       for (int q = 0; q < CPT; ++q) {
+#pragma unroll
+        for (int e = 0; e < 5; ++e) {
+          in2[q][e] = in1[q][e];
+          in1[q][e] = in0[q][e];
+          in0[q][e] = nx[q][e];
+        }
+        if constexpr (kUpd) in0[q][0] = nx[q][0] - alpha * (nx[q][5] - cc * nx[q][6]);
+      }
+      if (i < last) fetch(j + dir);
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
         const int c = t + q * NTC, k = j * n + c;
         T v = T(0);
         if (ok && c >= 1) {
           if constexpr (kUpd) {
-            const int64_t o = b * g.P + k;
-            const T rn = rb[k] - alpha * (qd[o] - cc * mvn[o]);
-            if (j >= lo && j < own_hi) rout[o] = rn;
-            in0[q][0] = rn;
-          } else {
-            in0[q][0] = rb[k];
+            if (j >= lo && j < own_hi) rout[b * g.P + k] = in0[q][0];
           }
-          in0[q][1] = wx[k];
-          in0[q][2] = wx[k + 1];
-          in0[q][3] = wy[k];
-          in0[q][4] = wy[k + n];
           v = T(kOmega) * in0[q][0] / (in0[q][1] + in0[q][2] + in0[q][3] + in0[q][4]);
         }
         row[c] = v;
@@ -577,13 +600,6 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
         }
       }
     }
-#pragma unroll
-    for (int q = 0; q < CPT; ++q)
-#pragma unroll
-      for (int e = 0; e < 5; ++e) {
-        in2[q][e] = in1[q][e];
-        in1[q][e] = in0[q][e];
-      }
   }
 }
 
@@ -612,23 +628,82 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
   const T* xc = Xc + b * (int64_t)((nc + 2) * nc);
   const T* wx = w + b * 2 * g.P;
   const T* wy = wx + g.P;
+  const T* vb = vn + b * g.P;
+  const T* mb = mvn + b * g.P;
   T* xo = Xout + b * g.P;
   double acc[3] = {0.0, 0.0, 0.0};
   if (t == 0)
     for (int r = 0; r < 4; ++r) s_u[r][n] = s_zb[r][n] = T(0);
-  // row inputs (rhs, 4 edge weights) loaded at stage 2 and reused at stage 3
-  T in1[CPT][5], in2[CPT][5];
+  // Every global input is requested one pipeline step before it is used:
+  // u-row sources (X_in and the two coarse values of the prolongation) one
+  // row ahead, the row inputs of the sweeps (rhs, 4 edge weights) as in0 one
+  // row ahead of stage 2, then kept through stage 3 (in1 -> in2).
+  T ux[CPT][3], in0[CPT][5], in1[CPT][5], in2[CPT][5];
+  auto fetch_u = [&](int j) {
+    const bool ok = (j >= 1 && j <= n - 1);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = t + q * NTC;
+      if (ok && c >= 1) {
+        ux[q][0] = xi[j * n + c];
+        ux[q][1] = xc[(j >> 1) * nc + (c >> 1)];
+        ux[q][2] = xc[((j + 1) >> 1) * nc + ((c + 1) >> 1)];
+      } else {
+        ux[q][0] = ux[q][1] = ux[q][2] = T(0);
+      }
+    }
+  };
+  auto fetch_in = [&](int j) {
+    if (!(j >= max(f0 - 1, 1) && j <= min(f1, n - 1))) return;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = t + q * NTC, k = j * n + c;
+      if (c >= 1) {
+        in0[q][0] = rb[k];
+        in0[q][1] = wx[k];
+        in0[q][2] = wx[k + 1];
+        in0[q][3] = wy[k];
+        in0[q][4] = wy[k + n];
+      }
+    }
+  };
   const int jfirst = dir > 0 ? f0 - 2 : f1 + 1;
-  for (int i = 0; i <= f1 - f0 + 3; ++i) {
+  const int last = f1 - f0 + 3;
+  fetch_u(jfirst);
+  for (int i = 0; i <= last; ++i) {
     const int j = jfirst + i * dir;
+    T uc[CPT][3];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) uc[q][e] = ux[q][e];
+#pragma unroll
+      for (int e = 0; e < 5; ++e) {
+        in2[q][e] = in1[q][e];
+        in1[q][e] = in0[q][e];
+      }
+    }
+    if (i < last) {
+      fetch_u(j + dir);
+      fetch_in(j);
+    }
+    const int j2 = j - 2 * dir;
+    T dv[CPT][2];
+    if constexpr (kDots) {
+      if (j2 >= f0 && j2 < f1) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          const int k = j2 * n + t + q * NTC;
+          dv[q][0] = mb[k];
+          dv[q][1] = vb[k];
+        }
+      }
+    }
     {
       T* row = s_u[j & 3];
-      const bool ok = (j >= 1 && j <= n - 1);
 #pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const int c = t + q * NTC, k = j * n + c;
-        row[c] = (ok && c >= 1) ? xi[k] + prolong2(xc, nc, c, j) : T(0);
-      }
+      for (int q = 0; q < CPT; ++q)
+        row[t + q * NTC] = uc[q][0] + T(0.5) * (uc[q][1] + uc[q][2]);
     }
     __syncthreads();
     const int j1 = j - dir;
@@ -636,22 +711,17 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
       T* row = s_zb[j1 & 3];
       const bool ok = (j1 >= 1 && j1 <= n - 1);
       const T* us = s_u[(j1 - 1) & 3];
-      const T* uc = s_u[j1 & 3];
+      const T* uc0 = s_u[j1 & 3];
       const T* un = s_u[(j1 + 1) & 3];
 #pragma unroll
       for (int q = 0; q < CPT; ++q) {
-        const int c = t + q * NTC, k = j1 * n + c;
+        const int c = t + q * NTC;
         T v = T(0);
         if (ok && c >= 1) {
-          T* in = in1[q];
-          in[0] = rb[k];
-          in[1] = wx[k];
-          in[2] = wx[k + 1];
-          in[3] = wy[k];
-          in[4] = wy[k + n];
-          const T x = uc[c];
+          const T* in = in1[q];
+          const T x = uc0[c];
           const T d = in[1] + in[2] + in[3] + in[4];
-          const T ax = in[1] * (x - uc[c - 1]) + in[2] * (x - uc[c + 1]) + in[3] * (x - us[c]) +
+          const T ax = in[1] * (x - uc0[c - 1]) + in[2] * (x - uc0[c + 1]) + in[3] * (x - us[c]) +
                        in[4] * (x - un[c]);
           v = x + T(kOmega) * (in[0] - ax) / d;
         }
@@ -659,7 +729,6 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
       }
     }
     __syncthreads();
-    const int j2 = j - 2 * dir;
     if (j2 >= f0 && j2 < f1) {
       const T* zs = s_zb[(j2 - 1) & 3];
       const T* zc = s_zb[j2 & 3];
@@ -677,16 +746,12 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
           xo[k] = zz;
           if constexpr (kDots) {
             acc[0] += (double)in[0] * (double)zz;
-            acc[1] += (double)mvn[b * g.P + k] * (double)zz;
-            acc[2] += (double)in[0] * (double)vn[b * g.P + k];
+            acc[1] += (double)dv[q][0] * (double)zz;
+            acc[2] += (double)in[0] * (double)dv[q][1];
           }
         }
       }
     }
-#pragma unroll
-    for (int q = 0; q < CPT; ++q)
-#pragma unroll
-      for (int e = 0; e < 5; ++e) in2[q][e] = in1[q][e];
   }
   if constexpr (kDots) {
     __shared__ double red[3 * (NTC / 64)];
