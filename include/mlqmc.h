@@ -90,7 +90,9 @@ typedef struct {
                                 current iterate is <= lam_rtol * lambda (0 = default: FP64 5e-12,
                                 mixed 5e-10, a factor >= 10 inside the stated accuracies 1e-10
                                 and 1e-8) */
-  double rq_lin_rtol;        /* the same test for the inner solves of the RQ iteration */
+  double rq_lin_rtol;        /* the same test for the inner solves of the RQ iteration; the
+                                iteration converges from inexact inner solves, so a loose
+                                value (default 1e-2) costs fewer inner steps in total */
   int32_t max_lin_iter;      /* cap on PCG iterations per linear solve */
   int32_t chain_len;         /* samples per warm-start chain (<=0: library default) */
   int32_t batch;             /* samples per fine-solve batch (<=0: library default) */
@@ -99,7 +101,7 @@ typedef struct {
 } mlqmc_opts;
 
 /* Fills *opt with the defaults (FP64, eig_rtol 1e-8, max_rq_iter 12,
- * lin_rtol 0 and lam_rtol 0 (per precision), rq_lin_rtol 1e-4, max_lin_iter 60,
+ * lin_rtol 0 and lam_rtol 0 (per precision), rq_lin_rtol 1e-2, max_lin_iter 60,
  * io_on_device 0). */
 void mlqmc_default_opts(mlqmc_opts* opt);
 

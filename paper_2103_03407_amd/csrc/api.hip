@@ -675,7 +675,7 @@ void mlqmc_default_opts(mlqmc_opts* o) {
   o->max_rq_iter = 12;
   o->lin_rtol = 0.0;
   o->lam_rtol = 0.0;
-  o->rq_lin_rtol = 1e-4;
+  o->rq_lin_rtol = 1e-2;
   o->max_lin_iter = 60;
   o->chain_len = 0;
   o->batch = 0;
