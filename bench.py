@@ -46,17 +46,31 @@ def _parse():
     return ap.parse_args()
 
 
+def _lv6(lv):
+    return (lv.n_fine, lv.s_fine, lv.n_coarse, lv.s_coarse, lv.n_prev, lv.s_prev)
+
+
+def _flat(w, i):
+    """The i-th sample of workload w in (level, shift r, lattice index k) order."""
+    for l, lv in enumerate(w.levels):
+        n = w.R * lv.N
+        if i < n:
+            r, k = divmod(i, lv.N)
+            return l, r, k
+        i -= n
+    raise IndexError(i)
+
+
 def _oracle_worker(args):
     # CPU baseline: the oracle as it stands, one sample per call
-    cfg_id, idx = args
+    cfg_id, l, r, k = args
     from oracle import mlqmc, qmc
     from synth import CONFIGS
     w = CONFIGS[cfg_id]
-    lv = w.levels[0]
-    fam = w.family()
-    r, k = divmod(int(idx), lv.N)
-    y = qmc.lattice_point(w.z(0), lv.N, w.shifts(0)[r], k)
-    return mlqmc.level_value(lv, y, fam).Y
+    lv = w.levels[l]
+    y = qmc.lattice_point(w.z(l), lv.N, w.shifts(l)[r], k)
+    v = mlqmc.level_value(lv, y, w.family())
+    return v.Y, v.lam
 
 
 def cpu_baseline(cfg_id: int, seconds: float):
@@ -67,47 +81,75 @@ def cpu_baseline(cfg_id: int, seconds: float):
     cores = len(os.sched_getaffinity(0))
     cores = min(cores, 16)
     w = CONFIGS[cfg_id]
-    n_total = w.R * w.levels[0].N
-    # calibrate: one sample on this process, then size the sample to ~`seconds`
-    t0 = time.perf_counter()
-    _oracle_worker((cfg_id, 0))
-    per = time.perf_counter() - t0
+    n_total = w.n_samples()
+    # calibrate: one sample of every level on this process, weighted by the
+    # level's share of the samples; then size the sample to ~`seconds`
+    per = 0.0
+    for l, lv in enumerate(w.levels):
+        t0 = time.perf_counter()
+        _oracle_worker((cfg_id, l, 0, 0))
+        per += (time.perf_counter() - t0) * w.R * lv.N / n_total
     count = max(cores, int(seconds * cores / max(per, 1e-3)))
     count = min(count, n_total)
-    idx = [(cfg_id, (i * 7919) % n_total) for i in range(count)]
+    flat = [(i * 7919) % n_total for i in range(count)]
+    idx = [(cfg_id, *_flat(w, i)) for i in flat]
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
         vals = pool.map(_oracle_worker, idx, chunksize=1)
     dt = time.perf_counter() - t0
-    assert all(math.isfinite(v) for v in vals)
+    assert all(math.isfinite(v[0]) for v in vals)
+    kind = "two-grid eigen-samples" if len(w.levels) == 1 else "level samples Y_l"
     base = {"value": count / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"{count} of the {n_total} two-grid eigen-samples of the workload "
-                      f"(strided lattice indices), scipy/SuperLU FP64, {cores} processes, "
-                      f"{dt:.1f} s"}
-    return base, [i for _, i in idx], vals
+            "sample": f"{count} of the {n_total} {kind} of the workload (strided indices), "
+                      f"scipy/SuperLU FP64, {cores} processes, {dt:.1f} s"}
+    return base, [i[1:] for i in idx], vals
 
 
-def accuracy(ctx, m, w, opts, idx, ref):
-    """Per-sample relative eigenvalue error of the GPU path against the
-    oracle values of the CPU-baseline sample (same lattice indices), from one
-    untimed eig_level call over the whole workload with the bench options."""
+def per_level(ctx, m, w, opts, idx=None, ref=None):
+    """Untimed pass over every level with mlqmc_eig_level and the bench
+    options: samples/s per level and, given oracle values of the CPU-baseline
+    sample, the per-sample error of Y_l (relative to lambda) against them."""
     import numpy as np
-    lv = w.levels[0]
-    z, sh = w.z(0), w.shifts(0)
-    n = w.R * lv.N
-    Y = np.empty((n, lv.s_fine))
-    for r in range(w.R):
-        ctx.lattice_points(lv.N, z, sh[r], 0, lv.N, Y[r * lv.N:(r + 1) * lv.N])
-    lam = np.empty(n)
-    fl = np.zeros(n, np.uint8)
-    level = (lv.n_fine, lv.s_fine, lv.n_coarse, lv.s_coarse, lv.n_prev, lv.s_prev)
-    ctx.eig_level(level, Y, lam, fl, opts=opts)
-    ref = np.asarray(ref)
-    err = np.abs(lam[np.asarray(idx)] - ref) / np.abs(ref)
-    return {"max_rel_err": float(err.max()), "median_rel_err": float(np.median(err)),
-            "samples": int(err.size), "flagged": int((fl != 0).sum()),
-            "bound": 1e-10 if opts.prec == m.MLQMC_FP64 else 1e-8}
+    import torch
+    out, errs = [], []
+    ys = {}
+    for l, lv in enumerate(w.levels):
+        n = w.R * lv.N
+        Y = np.empty((n, max(lv.s_fine, 1)))
+        for r in range(w.R):
+            ctx.lattice_points(lv.N, w.z(l), w.shifts(l)[r], 0, lv.N, Y[r * lv.N:(r + 1) * lv.N])
+        lam, lp = np.empty(n), np.empty(n)
+        fl = np.zeros(n, np.uint8)
+        prev = lp if lv.n_prev else None
+        ctx.eig_level(_lv6(lv), Y, lam, fl, lam_prev=prev, opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.eig_level(_lv6(lv), Y, lam, fl, lam_prev=prev, opts=opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out.append({"level": l, "h": f"1/{lv.n_fine}", "H": f"1/{lv.n_coarse}" if lv.n_coarse else None,
+                    "s": lv.s_fine, "samples": n, "samples_per_s": round(n / dt, 1),
+                    "flagged": int((fl != 0).sum())})
+        ys[l] = (lam - lp) if lv.n_prev else lam, lam
+    acc = None
+    if idx is not None:
+        lev_err = {}
+        for (l, r, k), (yref, lref) in zip(idx, ref):
+            yv = ys[l][0][r * w.levels[l].N + k]
+            errs.append(abs(yv - yref) / abs(lref))
+            lev_err.setdefault(l, []).append(errs[-1])
+        for x in out:
+            le = lev_err.get(x["level"])
+            x["max_rel_err"] = float(max(le)) if le else None
+            x["oracle_samples"] = len(le) if le else 0
+        e = np.asarray(errs)
+        acc = {"max_rel_err": float(e.max()), "median_rel_err": float(np.median(e)),
+               "samples": int(e.size), "flagged": int(sum(x["flagged"] for x in out)),
+               "bound": 1e-10 if opts.prec == m.MLQMC_FP64 else 1e-8,
+               "quantity": "Y_l = lambda^l - lambda^(l-1), error relative to lambda^l"
+               if len(w.levels) > 1 else "lambda"}
+    return out, acc
 
 
 def _traffic(kernel: str):
@@ -149,19 +191,18 @@ def main():
     from synth import CONFIGS
 
     w = CONFIGS[a.cfg]
-    if len(w.levels) != 1:
-        raise SystemExit("bench workload must be single-level")
-    lv = w.levels[0]
     fam = w.family()
     torch.cuda.init()
     ctx = m.Context(fam, device=0)
-    z, sh = w.z(0), w.shifts(0)
-    level = (lv.n_fine, lv.s_fine, lv.n_coarse, lv.s_coarse, lv.n_prev, lv.s_prev)
+    levels = [_lv6(lv) for lv in w.levels]
+    Ns = [lv.N for lv in w.levels]
+    zs = [w.z(l) for l in range(len(w.levels))]
+    shs = [w.shifts(l) for l in range(len(w.levels))]
     opts = m.default_opts(prec=m.MLQMC_MIXED if a.prec == "mixed" else m.MLQMC_FP64)
-    n_samples = w.R * lv.N
+    n_samples = w.n_samples()
 
     def step():
-        st, Q, Qh, V, est = ctx.estimate([level], [lv.N], w.R, [z], [sh], opts=opts)
+        st, Q, Qh, V, est = ctx.estimate(levels, Ns, w.R, zs, shs, opts=opts)
         if st != m.MLQMC_OK:
             raise RuntimeError(f"estimate flagged samples (status {st})")
         return est
@@ -190,8 +231,17 @@ def main():
         # the coefficient product on FP64 MFMA: 2 s E flops per sample, every
         # sample expanded once per step (E = edge weights of the padded mesh)
         avg_ms = kms / launches
-        ew = 2 * (lv.n_fine + 2) * lv.n_fine
-        flops_per_launch = 2.0 * lv.s_fine * ew * n_samples * a.steps / launches
+        flops_step = 0.0
+        for lv in w.levels:
+            if not lv.n_coarse:
+                continue
+            meshes = [(lv.n_fine, lv.s_fine)]
+            if lv.n_prev and not (lv.n_prev == lv.n_coarse and lv.s_prev == lv.s_coarse):
+                meshes.append((lv.n_prev, lv.s_prev))
+            for nm, sm in meshes:
+                if nm >= 64:  # meshes of the batched path (finer ones solve in LDS)
+                    flops_step += 2.0 * sm * 2 * (nm + 2) * nm * w.R * lv.N
+        flops_per_launch = flops_step * a.steps / launches
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 2),
                 "peak": PEAK_FP64_MFMA_TFS, "unit": "TFLOP/s",
@@ -208,10 +258,11 @@ def main():
                 "traffic": _traffic(kname), "avg_launch_us": round(avg_ms * 1e3, 2),
                 "launches": launches, "algorithmic_bytes_per_launch": bytes_per_launch}
 
-    cpu = acc = None
+    cpu = None
+    idx = ref = None
     if not a.no_cpu_baseline:
         cpu, idx, ref = cpu_baseline(a.cfg, a.cpu_seconds)
-        acc = accuracy(ctx, m, w, opts, idx, ref)
+    levels_out, acc = per_level(ctx, m, w, opts, idx, ref)
 
     out = {
         "metric": "two-grid eigen-samples/sec per level; stencil HBM GB/s in roofline",
@@ -219,10 +270,14 @@ def main():
         "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if a.prec == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"workload": w.name, "h": f"1/{lv.n_fine}", "H": f"1/{lv.n_coarse}",
-                   "s": lv.s_fine, "S": lv.s_coarse, "N": lv.N, "R": w.R,
-                   "samples_per_step": n_samples, "estimate": est[0]},
+        "config": {"workload": w.name, "levels": len(w.levels),
+                   "h": [f"1/{lv.n_fine}" for lv in w.levels],
+                   "H": [f"1/{lv.n_coarse}" if lv.n_coarse else None for lv in w.levels],
+                   "s": [lv.s_fine for lv in w.levels], "S": [lv.s_coarse for lv in w.levels],
+                   "N": Ns, "R": w.R, "samples_per_step": n_samples,
+                   "estimate": est[0], "variance": est[1]},
         "roofline": roof, "cpu_baseline": cpu, "accuracy_vs_oracle": acc,
+        "per_level": levels_out,
     }
     print(json.dumps(out), flush=True)
     return 0

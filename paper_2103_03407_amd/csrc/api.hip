@@ -396,7 +396,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     }
   }
   double* sc = nullptr;
-  CS(ctx->getT(nm("scal").c_str(), batch * 11, &sc));
+  CS(ctx->getT(nm("scal").c_str(), batch * 12, &sc));
   int* its = nullptr;
   CS(ctx->getT(nm("its").c_str(), batch, &its));
   uint8_t *active = nullptr, *vact = nullptr;
@@ -419,7 +419,8 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     S.beta = sc + 7 * batch;
     S.f = sc + 8 * batch;
     S.m = sc + 9 * batch;
-    S.dl = sc + 10 * batch;
+    S.dmp = sc + 10 * batch;
+    S.rzp = sc + 11 * batch;
     S.lam = lam + b0;
     S.its = its;
     S.lin_acc = lin_iters ? lin_iters + b0 : nullptr;

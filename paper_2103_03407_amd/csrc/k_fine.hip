@@ -826,7 +826,8 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
       S.rho[b] = s[1] / g;
       S.f[b] = S.rho[b] - S.mu[b];  // w_0 = vn, M-normalised
       S.m[b] = 1.0;
-      S.dl[b] = 0.0;
+      S.dmp[b] = 0.0;
+      S.rzp[b] = 0.0;
       S.active[b] = 1;
       S.vact[b] = 1;
       S.its[b] = 0;
@@ -856,18 +857,26 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
       S.c[b] = s[1];
       // Rayleigh quotient of w_{k+1} = w_k + a p: mu + f/m with
       // f += 2a p^T (A - mu M) w_k + a^2 p^T (A - mu M) p, m += 2a p^T M w_k + a^2 p^T M p
-      const double f = S.f[b], m = S.m[b];
-      const double df = 2.0 * a * (s[1] + s[5]) + a * a * s[0];
+      const double f1 = S.f[b] + 2.0 * a * (s[1] + s[5]) + a * a * s[0];
       const double dm = 2.0 * a * (s[2] + hm * s[4]) + a * a * hm * s[3];
-      const double dl = fabs((df * m - f * dm) / (m * (m + dm)));
-      S.f[b] = f + df;
-      S.m[b] = m + dm;
-      // the error left after this step is estimated by the change it made,
-      // scaled by the observed contraction (at most 1)
-      const double dprev = S.dl[b];
-      const double est = dprev > 0.0 ? dl * fmin(1.0, 2.0 * dl / dprev) : dl;
-      S.dl[b] = dl;
-      const double lam = S.mu[b] + (f + df) / (m + dm);
+      const double df = f1 - S.f[b];
+      const double m1 = S.m[b] + dm;
+      S.f[b] = f1;
+      S.m[b] = m1;
+      // Error left in mu + f/m after this step.  f (the energy) falls by
+      // |df| per step with a tail of about |df| c^2 / (1 - c^2); m changes at
+      // first order in the error, with a tail of about |dm| c / (1 - c), and
+      // enters the quotient scaled by |f/m| = |lambda - mu|.  c is the
+      // observed contraction of the preconditioned residual; |dm| is guarded
+      // by the previous step's change, since single increments can vanish.
+      const double rzp = S.rzp[b];
+      double c = rzp > 0.0 ? sqrt(S.rz[b] / rzp) : 0.5;
+      c = fmin(fmax(c, 0.05), 0.9);
+      const double dmg = fmax(fabs(dm), c * fabs(S.dmp[b]));
+      S.dmp[b] = dm;
+      const double est =
+          (fabs(df) * c * c / (1.0 - c * c) + fabs(f1 / m1) * dmg * c / (1.0 - c)) / m1;
+      const double lam = S.mu[b] + f1 / m1;
       if (est <= rtol * fabs(lam)) S.vact[b] = 0;  // converged: this is the last step
       break;
     }
@@ -889,6 +898,7 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
         break;
       }
       S.beta[b] = rzn / S.rz[b];
+      S.rzp[b] = S.rz[b];
       S.rz[b] = rzn;
       S.c2[b] = s[1];
       break;

@@ -67,8 +67,9 @@ constexpr int kNodesPerBlock = 1024;
 struct FineState {      // per-sample scalars of the projected PCG, arrays of length B
   double *mu, *vs, *rho, *rz, *rz0, *alpha, *c, *c2, *beta, *lam;
   // Rayleigh quotient of w_k = vn + t_k, tracked from the PCG dots:
-  // f = w^T (A - mu M) w, m = w^T M w, dl = |change of f/m| in the last step
-  double *f, *m, *dl;
+  // f = w^T (A - mu M) w, m = w^T M w; dmp = the previous step's change of m,
+  // rzp = the previous r.z (for the observed contraction)
+  double *f, *m, *dmp, *rzp;
   int* its;
   int* lin_acc;         // per-sample PCG iteration totals, added to at the end (or nullptr)
   uint8_t* active;      // the sample still takes PCG steps

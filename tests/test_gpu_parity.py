@@ -306,6 +306,28 @@ def test_cfg2_full_batch_sampled(ctx, fam):
     assert np.max(np.abs(Q[0] - per_r)) <= 1e-12 * np.max(per_r)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", LAM_RTOL), ("mixed", 1e-8)])
+def test_cfg4_coarse8_level_sampled(ctx, fam, prec, tol):
+    # level 2 of the multilevel workload, H = 1/8 -> h = 1/64 (previous 1/32):
+    # the largest coarse/fine eigenvalue gap of the workloads, where the
+    # two-grid solve's stopping test is hardest
+    w = CONFIGS[4]
+    lv = w.levels[2]
+    z, sh = w.z(2), w.shifts(2)
+    Y = np.concatenate([qmc.lattice_points(z, lv.N, sh[r]) for r in range(w.R)])
+    n = Y.shape[0]
+    lam, lamp = np.empty(n), np.empty(n)
+    fl = np.zeros(n, np.uint8)
+    o = m.default_opts(prec=m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED)
+    ctx.eig_level(_lv6(lv), np.ascontiguousarray(Y), lam, fl, lam_prev=lamp, opts=o)
+    assert not fl.any()
+    pick = np.random.default_rng(3).choice(n, 40, replace=False)
+    for k in pick:
+        v = mlqmc.level_value(lv, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= tol * v.lam, (k, lam[k], v.lam)
+        assert abs(lamp[k] - v.lam_prev) <= tol * v.lam_prev, (k, lamp[k], v.lam_prev)
+
+
 def test_cfg4_top_level_sampled(ctx, fam):
     w = CONFIGS[4]
     lv = w.levels[4]          # h = 1/256 from H = 1/16, previous 1/128
