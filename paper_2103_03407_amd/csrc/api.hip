@@ -295,11 +295,19 @@ mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
   return MLQMC_OK;
 }
 
-int default_chain(int64_t n, int warm, int chain_len) {
+// Samples per warm-start chain of the eigensolve on mesh N: as short as keeps
+// every workgroup slot of the device busy (one chain per workgroup).
+int default_chain(int64_t n, int warm, int chain_len, int N) {
   if (!warm) return 1;
   if (chain_len > 0) return chain_len;
-  const int64_t target = 512;  // chains in flight: 2 workgroups on each of 256 CUs
-  int64_t c = (n + target - 1) / target;
+  static std::map<int, int> slots;  // mesh -> chains in flight on this device type
+  auto it = slots.find(N);
+  if (it == slots.end()) {
+    const int c = rqi_chains_in_flight(N);
+    it = slots.emplace(N, c > 0 ? c : 512).first;
+  }
+  const int64_t target = it->second;
+  const int64_t c = (n + target - 1) / target;
   return (int)std::max<int64_t>(1, c);
 }
 
@@ -561,7 +569,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   if (n == 0) return MLQMC_OK;
   CK(hipMemsetAsync(flags, 0, n, st), "memset");
   CK(hipMemsetAsync(lin_iters, 0, n * sizeof(int), st), "memset");
-  const int chain = default_chain(n, warm, o->chain_len);
+  const int chain = default_chain(n, warm, o->chain_len, L->n_coarse ? L->n_coarse : L->n_fine);
   RqiArgs a{};
   a.Y = Y;
   a.ldY = ldY;
@@ -960,7 +968,7 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
     CK(launch_lattice_multi(N[l], s, R, dz, dsh, N[l], Y, std::max(s, 1), st), "lattice");
     mlqmc_opts oo = *o;
     // chains never cross a shift: chain length divides N_l
-    int chain = default_chain(N[l] * R, 1, o->chain_len);
+    int chain = default_chain(N[l] * R, 1, o->chain_len, L.n_coarse ? L.n_coarse : L.n_fine);
     int c2 = 1;
     while (c2 < chain) c2 *= 2;
     oo.chain_len = (int)std::min<int64_t>(c2, N[l]);

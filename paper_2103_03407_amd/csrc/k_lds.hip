@@ -272,6 +272,33 @@ hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st) {
 
 int64_t rqi_scratch_doubles(int N) { return N == 64 ? rqi_global_doubles<64>() : 0; }
 
+template <int N>
+hipError_t rqi_occupancy(int* per) {
+  constexpr int NT = threads_for<N>();
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_rqi<N, NT>, NT, 0);
+}
+
+// Workgroups of the eigensolve on mesh N that the current device holds at
+// once (compute units x resident workgroups per unit); 0 if unknown.
+int rqi_chains_in_flight(int N) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (N) {
+    case 4: e = rqi_occupancy<4>(&per); break;
+    case 8: e = rqi_occupancy<8>(&per); break;
+    case 16: e = rqi_occupancy<16>(&per); break;
+    case 32: e = rqi_occupancy<32>(&per); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rqi_global<64, 512>, 512, 0);
+             break;
+    default: break;
+  }
+  if (e != hipSuccess || per <= 0) return 0;
+  return cus * per;
+}
+
 hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st) {
   if (a.s > kMaxStagedS) return hipErrorInvalidValue;
   switch (N) {

@@ -33,6 +33,8 @@ struct RqiArgs {
 hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st);
 // doubles of global scratch one chain needs on mesh N (0: all in LDS)
 int64_t rqi_scratch_doubles(int N);
+// workgroups of the eigensolve on mesh N resident on the current device at once
+int rqi_chains_in_flight(int N);
 
 struct TgSmallArgs {
   const double* Y;      // [n x ldY], first s columns
