@@ -549,6 +549,7 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
     a.nH = nH;
     a.n = n;
     a.lin_rtol = lin_tol(o);
+    a.lam_rtol = lam_tol(o);
     a.max_lin = o->max_lin_iter;
     a.lam = lam;
     a.lin_iters = lin_iters;

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(NT) void k_tg_small(TgSmallArgs A) {
   const double rho = vAv / vMv;
   const double mu = A.lamH[i];
   bool c, b;
-  const int its = lds::jd_pcg<NT, N>(a, mu, rho, A.lin_rtol, A.max_lin, &c, &b);
+  const int its = lds::jd_pcg<NT, N, true>(a, mu, rho, A.lin_rtol, A.max_lin, &c, &b, A.lam_rtol);
   for (int id = threadIdx.x; id < D; id += NT) s_v[id] += s_t[id];
   __syncthreads();
   lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);

@@ -47,6 +47,7 @@ struct TgSmallArgs {
   int nH;               // coarse mesh
   int64_t n;
   double lin_rtol;
+  double lam_rtol;      // eigenvalue stopping test of the solve (0: residual test only)
   int max_lin;
   double* lam;          // [n] two-grid value
   int* lin_iters;       // [n] added to, or nullptr

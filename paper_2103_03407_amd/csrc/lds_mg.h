@@ -225,9 +225,16 @@ MLQMC_DEV void scale_vec(double* x, double f) {
 // Projected PCG for  P (A - mu M) P^T t = -(A v - rho M v), t = 0 initially.
 // Requires v^T M v = 1 and rho = v^T A v.  Returns the iteration count;
 // sets *conv (stop test met) and *brk (non-positive curvature).
-template <int NT, int n>
+// Stops when sqrt(r.z / r0.z0) <= rtol or, with lam_tol > 0, when the
+// estimated error of the Rayleigh quotient of v + t is <= lam_tol times it:
+// the quotient is tracked as mu + f/m, f = w^T (A - mu M) w, m = w^T M w,
+// w = v + t, from the step's dot products, and the error estimated from the
+// tails of f (energy, factor c^2) and m (first order, factor c, scaled by
+// |lambda - mu|), c the observed residual contraction.
+template <int NT, int n, bool kTrack = false>
 MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int maxit,
-                     bool* conv, bool* brk) {
+                     bool* conv, bool* brk, double lam_tol = 0.0) {
+  constexpr int K = kTrack ? 6 : 3;
   constexpr int m = n - 1, D = m * m;
   const double hm = mass_scale(n);
   double* const v = a.v;
@@ -265,33 +272,62 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
     return 0;
   }
   int it = 0;
+  double f = rho - mu, mm = 1.0, dmp = 0.0, rzp = 0.0;
   while (it < maxit) {
     ++it;
-    // q = (A - mu M) p;  pq = p.(P q) = p.q - (p.Mv)(v.q)
-    double s[3] = {0.0, 0.0, 0.0};
+    // q = (A - mu M) p;  pq = p.(P q) = p.q - (p.Mv)(v.q); with lam_tol also
+    // p.M p, t.M p, t.q for the Rayleigh-quotient tracking
+    double s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = 0.0;
     for (int id = threadIdx.x; id < D; id += NT) {
       const int i = id % m + 1, j = id / m + 1;
       double d;
       const double ap = stencil_A(p, a.wx, a.wy, n, i, j, id, d);
-      const double qv = ap - mu * hm * stencil_M12(p, n, i, j, id);
+      const double mp = hm * stencil_M12(p, n, i, j, id);
+      const double qv = ap - mu * mp;
       q[id] = qv;
       s[0] += p[id] * qv;
       s[1] += v[id] * qv;
       s[2] += p[id] * hm * stencil_M12(v, n, i, j, id);
+      if constexpr (kTrack) {
+        s[3] += p[id] * mp;
+        s[4] += t[id] * mp;
+        s[5] += t[id] * qv;
+      }
     }
-    block_sums<NT, 3>(s, a.red);
+    block_sums<NT, K>(s, a.red);
     const double pq = s[0] - s[2] * s[1];
     if (!(pq > 0.0)) {
       *brk = true;
       break;
     }
     const double alpha = rz / pq, c = s[1];
+    bool lam_done = false;
+    if constexpr (kTrack) {
+      const double f1 = f + 2.0 * alpha * (s[1] + s[5]) + alpha * alpha * s[0];
+      const double dm = 2.0 * alpha * (s[2] + s[4]) + alpha * alpha * s[3];
+      const double m1 = mm + dm;
+      double cr = rzp > 0.0 ? sqrt(rz / rzp) : 0.5;
+      cr = fmin(fmax(cr, 0.05), 0.9);
+      const double dmg = fmax(fabs(dm), cr * fabs(dmp));
+      const double est = (fabs(f1 - f) * cr * cr / (1.0 - cr * cr) +
+                          fabs(f1 / m1) * dmg * cr / (1.0 - cr)) / m1;
+      lam_done = est <= lam_tol * fabs(mu + f1 / m1);
+      f = f1;
+      mm = m1;
+      dmp = dm;
+    }
     for (int id = threadIdx.x; id < D; id += NT) {
       const int i = id % m + 1, j = id / m + 1;
       t[id] += alpha * p[id];
       r[id] -= alpha * (q[id] - c * hm * stencil_M12(v, n, i, j, id));
     }
     __syncthreads();
+    if (lam_done) {
+      *conv = true;
+      break;
+    }
     vcycle_top<NT, n>(a.wx, a.wy, r, z, q, a.mg);
     double u[3] = {0.0, 0.0, 0.0};
     for (int id = threadIdx.x; id < D; id += NT) {
@@ -307,6 +343,7 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
       break;
     }
     const double beta = rzn / rz;
+    rzp = rz;
     rz = rzn;
     for (int id = threadIdx.x; id < D; id += NT) p[id] = z[id] - u[1] * v[id] + beta * p[id];
     __syncthreads();
