@@ -542,7 +542,7 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
     a.Y = Y;
     a.ldY = ldY;
     a.s = s;
-    a.phi = tb->edge;
+    a.phi = tb->pad;
     a.a0 = ctx->a0;
     a.uH = uH;
     a.lamH = lamH;
@@ -589,7 +589,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
     Table* tb = nullptr;
     CS(ctx->table(L->n_fine, L->s_fine, &tb));
     a.S = L->s_fine;
-    a.phi = tb->edge;
+    a.phi = tb->pad;
     a.lam = lam;
     a.u_out = nullptr;
     ctx->t_begin(MLQMC_K_COARSE);
@@ -609,7 +609,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
       CS(ctx->table(L->n_prev, L->s_prev, &tb));
       RqiArgs b = a;
       b.S = L->s_prev;
-      b.phi = tb->edge;
+      b.phi = tb->pad;
       b.lam = lam_prev;
       b.rq_iters = i2;
       b.lin_iters = nullptr;
@@ -634,7 +634,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   CS(ctx->getT("uH", n * DH, &uH));
   if (!lamH) CS(ctx->getT("lamH", n, &lamH));
   a.S = L->s_coarse;
-  a.phi = tb->edge;
+  a.phi = tb->pad;
   a.lam = lamH;
   a.u_out = uH;
   if (const int64_t per = rqi_scratch_doubles(L->n_coarse)) {

@@ -19,10 +19,9 @@ constexpr int threads_for() {
 // v = sin(pi x1) sin(pi x2) at the interior nodes
 template <int NT, int n>
 __device__ __forceinline__ void init_sine(double* v) {
-  constexpr int m = n - 1, D = m * m;
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int i = id % m + 1, j = id / m + 1;
-    v[id] = sinpi(double(i) / n) * sinpi(double(j) / n);
+  LDS_FOR_NODES(NT, n, k) {
+    const int i = k & (n - 1), j = k >> lds::Mesh<n>::lg;
+    v[k] = sinpi(double(i) / n) * sinpi(double(j) / n);
   }
   __syncthreads();
 }
@@ -30,10 +29,10 @@ __device__ __forceinline__ void init_sine(double* v) {
 // M-overlap of the M-normalised v with the normalised sine mode
 template <int NT, int n>
 __device__ __forceinline__ double sine_overlap(const double* v, double* red) {
-  constexpr int m = n - 1, D = m * m;
+  constexpr int m = n - 1;
   double s[2] = {0.0, 0.0};
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int i = id % m + 1, j = id / m + 1;
+  LDS_FOR_NODES(NT, n, k) {
+    const int i = k & (n - 1), j = k >> lds::Mesh<n>::lg;
     auto ph = [&](int a, int b) -> double {
       return (a >= 1 && a <= m && b >= 1 && b <= m) ? sinpi(double(a) / n) * sinpi(double(b) / n)
                                                      : 0.0;
@@ -41,7 +40,7 @@ __device__ __forceinline__ double sine_overlap(const double* v, double* red) {
     const double p0 = ph(i, j);
     const double mp = 6.0 * p0 + ph(i - 1, j) + ph(i + 1, j) + ph(i, j - 1) + ph(i, j + 1) +
                       ph(i + 1, j + 1) + ph(i - 1, j - 1);
-    s[0] += v[id] * mp;
+    s[0] += v[k] * mp;
     s[1] += p0 * mp;
   }
   block_sums<NT, 2>(s, red);
@@ -50,11 +49,11 @@ __device__ __forceinline__ double sine_overlap(const double* v, double* red) {
 }
 
 // The chain of samples [blockIdx.x * chain_len, ...) on mesh N: arrays in `a`
-// (weights at a.wx), the staged point in s_y.
+// (zero padding), the staged point in s_y.
 template <int N, int NT>
 __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays& a, double* s_y) {
   using Mh = lds::Mesh<N>;
-  constexpr int D = Mh::D;
+  constexpr int m = N - 1;
   double* const s_v = a.v;
   const int64_t i0 = (int64_t)blockIdx.x * A.chain_len;
   const int64_t i1 = (i0 + A.chain_len < A.n) ? i0 + A.chain_len : A.n;
@@ -78,7 +77,7 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays& a, double* s_y
       ++rq;
       bool c, b;
       lin += lds::jd_pcg<NT, N>(a, sigma, sigma, A.lin_rtol, A.max_lin, &c, &b);
-      for (int id = threadIdx.x; id < D; id += NT) s_v[id] += a.t[id];
+      LDS_FOR_NODES(NT, N, k) s_v[k] += a.t[k];
       __syncthreads();
       lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);
       lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
@@ -101,69 +100,112 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays& a, double* s_y
       if (A.lin_iters) A.lin_iters[i] = lin;
       A.flags[i] = fl;
     }
-    if (A.u_out)
-      for (int id = threadIdx.x; id < D; id += NT) A.u_out[i * D + id] = s_v[id];
+    if (A.u_out) {  // interior layout, node (i, j) at (j - 1) m + i - 1
+      LDS_FOR_NODES(NT, N, k) {
+        const int ii = k & (N - 1), jj = k >> Mh::lg;
+        A.u_out[i * Mh::D + (jj - 1) * m + ii - 1] = s_v[k];
+      }
+    }
     have_prev = (fl == 0);
     __syncthreads();
   }
 }
 
-// Every array in LDS (meshes up to 1/32).
+// Every array in LDS (meshes up to 1/32).  The five vectors' padding is
+// zeroed once; the solvers write interior positions only.
 template <int N, int NT>
-__global__ __launch_bounds__(NT) void k_rqi(RqiArgs A) {
+__global__ __launch_bounds__(NT, N >= 32 ? 2 : 4) void k_rqi(RqiArgs A) {
   using Mh = lds::Mesh<N>;
-  constexpr int D = Mh::D;
+  constexpr int P = Mh::P;
   __shared__ double s_w[Mh::EW];
-  __shared__ double s_v[D], s_t[D], s_r[D], s_z[D], s_p[D], s_q[D];
+  __shared__ double s_vec[5 * P];
   __shared__ double s_mg[lds::mg_scratch<N>() + 1];
-  __shared__ double s_red[3 * (NT / 64)];
+  __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
-  const lds::PcgArrays a{s_w, s_w + Mh::EX, s_v, s_t, s_r, s_z, s_p, s_q, s_mg, s_red};
+  lds::PcgArrays a;
+  a.wx = s_w;
+  a.wy = s_w + P;
+  a.v = s_vec;
+  a.t = s_vec + P;
+  a.r = s_vec + 2 * P;
+  a.z = s_vec + 3 * P;
+  a.p = s_vec + 4 * P;
+  a.q = a.z;
+  a.mg = s_mg;
+  a.red = s_red;
+  a.xtmp = nullptr;
+  lds::zero<NT>(s_vec, 5 * P);
+  __syncthreads();
   rqi_chain<N, NT>(A, a, s_y);
 }
 
-// Meshes whose vectors exceed LDS (1/64): the top-level weights and the six
-// PCG vectors live in the chain's slice of a global scratch buffer (L2/MALL
-// resident while the chain runs); the V-cycle levels below stay in LDS.
+// Meshes whose vectors exceed LDS (1/64): the top-level weights, the five
+// PCG vectors and the smoother's second array live in the chain's slice of a
+// global scratch buffer (L2/MALL resident while the chain runs); the levels
+// below stay in LDS.
 template <int N>
 constexpr int64_t rqi_global_doubles() {
-  return (int64_t)lds::Mesh<N>::EW + 6 * (int64_t)lds::Mesh<N>::D;
+  return (int64_t)lds::Mesh<N>::EW + 6 * (int64_t)lds::Mesh<N>::P;
 }
 template <int N, int NT>
 __global__ __launch_bounds__(NT) void k_rqi_global(RqiArgs A) {
   using Mh = lds::Mesh<N>;
-  constexpr int D = Mh::D;
+  constexpr int P = Mh::P;
   __shared__ double s_mg[lds::mg_scratch<N>() + 1];
-  __shared__ double s_red[3 * (NT / 64)];
+  __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
   double* g = A.scratch + (int64_t)blockIdx.x * rqi_global_doubles<N>();
-  double* w = g;
-  double* v = w + Mh::EW;
-  const lds::PcgArrays a{w, w + Mh::EX, v, v + D, v + 2 * D, v + 3 * D, v + 4 * D, v + 5 * D,
-                         s_mg, s_red};
+  double* vec = g + Mh::EW;
+  lds::PcgArrays a;
+  a.wx = g;
+  a.wy = g + P;
+  a.v = vec;
+  a.t = vec + P;
+  a.r = vec + 2 * P;
+  a.z = vec + 3 * P;
+  a.p = vec + 4 * P;
+  a.q = a.z;
+  a.xtmp = vec + 5 * P;
+  a.mg = s_mg;
+  a.red = s_red;
+  lds::zero<NT>(vec, 6 * P);
+  __syncthreads();
   rqi_chain<N, NT>(A, a, s_y);
 }
 
 template <int N, int NT>
-__global__ __launch_bounds__(NT) void k_tg_small(TgSmallArgs A) {
+__global__ __launch_bounds__(NT, N >= 32 ? 2 : 4) void k_tg_small(TgSmallArgs A) {
   using Mh = lds::Mesh<N>;
-  constexpr int m = N - 1, D = Mh::D;
+  constexpr int P = Mh::P;
   __shared__ double s_w[Mh::EW];
-  __shared__ double s_v[D], s_t[D], s_r[D], s_z[D], s_p[D], s_q[D];
+  __shared__ double s_vec[5 * P];
   __shared__ double s_mg[lds::mg_scratch<N>() + 1];
-  __shared__ double s_red[3 * (NT / 64)];
+  __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
-  const lds::PcgArrays a{s_w, s_w + Mh::EX, s_v, s_t, s_r, s_z, s_p, s_q, s_mg, s_red};
+  lds::PcgArrays a;
+  a.wx = s_w;
+  a.wy = s_w + P;
+  a.v = s_vec;
+  a.t = s_vec + P;
+  a.r = s_vec + 2 * P;
+  a.z = s_vec + 3 * P;
+  a.p = s_vec + 4 * P;
+  a.q = a.z;
+  a.mg = s_mg;
+  a.red = s_red;
+  a.xtmp = nullptr;
+  double* const s_v = a.v;
   const int64_t i = blockIdx.x;
+  lds::zero<NT>(s_vec, 5 * P);
   for (int j = threadIdx.x; j < A.s; j += NT) s_y[j] = A.Y[i * A.ldY + j];
   __syncthreads();
   lds::weights_from_table<NT, N>(A.phi, s_y, A.s, A.a0, s_w);
   lds::coarsen_all<NT, N>(a.wx, a.wy, s_mg);
   const int mH = A.nH - 1, ratio = N / A.nH;
   const double* uH = A.uH + i * (int64_t)(mH * mH);
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int ii = id % m + 1, jj = id / m + 1;
-    s_v[id] = interp_coarse(uH, A.nH, ratio, ii, jj);
+  LDS_FOR_NODES(NT, N, k) {
+    const int ii = k & (N - 1), jj = k >> Mh::lg;
+    s_v[k] = interp_coarse(uH, A.nH, ratio, ii, jj);
   }
   __syncthreads();
   double vMv, vAv;
@@ -173,7 +215,7 @@ __global__ __launch_bounds__(NT) void k_tg_small(TgSmallArgs A) {
   const double mu = A.lamH[i];
   bool c, b;
   const int its = lds::jd_pcg<NT, N, true>(a, mu, rho, A.lin_rtol, A.max_lin, &c, &b, A.lam_rtol);
-  for (int id = threadIdx.x; id < D; id += NT) s_v[id] += s_t[id];
+  LDS_FOR_NODES(NT, N, k) s_v[k] += a.t[k];
   __syncthreads();
   lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);
   const double lam = vAv / vMv;
@@ -188,39 +230,33 @@ __global__ __launch_bounds__(NT) void k_tg_small(TgSmallArgs A) {
   }
 }
 
+// The V-cycle below the batched levels: one workgroup per sample reads its
+// padded arrays of the batched layout ((N + 2) N per vector, same indexing)
+// into LDS, runs the cycle, writes the interior of X back.
 template <int N, int NT, typename T>
 __global__ __launch_bounds__(NT) void k_bottom(const T* __restrict__ w, const T* __restrict__ rhs,
                                                T* __restrict__ X,
                                                const uint8_t* __restrict__ active) {
   using Mh = lds::Mesh<N>;
-  constexpr int m = N - 1, D = Mh::D, P = (N + 2) * N;
+  constexpr int P = Mh::P, PG = (N + 2) * N;
   const int64_t b = blockIdx.x;
   if (active && !active[b]) return;
   __shared__ double s_w[Mh::EW];
-  __shared__ double s_b[D], s_x[D], s_r[D];
+  __shared__ double s_b[P], s_x[P];
   __shared__ double s_mg[lds::mg_scratch<N>() + 1];
-  const T* WX = w + b * 2 * P;
-  const T* WY = WX + P;
-  // padded WX(j, i) = edge (i-1,j)-(i,j) at j*N + i; WY(j, i) = edge (i,j-1)-(i,j)
-  for (int e = threadIdx.x; e < Mh::EX; e += NT) {  // edge (i,j)-(i+1,j), j in [1,m], i in [0,m]
-    const int j = e / N + 1, i = e % N;
-    s_w[e] = (double)WX[j * N + i + 1];
-  }
-  for (int e = threadIdx.x; e < Mh::EY; e += NT) {  // edge (i,j)-(i,j+1), j in [0,m], i in [1,m]
-    const int j = e / m, i = e % m + 1;
-    s_w[Mh::EX + e] = (double)WY[(j + 1) * N + i];
-  }
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int i = id % m + 1, j = id / m + 1;
-    s_b[id] = (double)rhs[b * P + j * N + i];
+  const T* WX = w + b * 2 * PG;
+  const T* WY = WX + PG;
+  const T* rb = rhs + b * PG;
+  for (int e = threadIdx.x; e < P; e += NT) {
+    s_w[e] = (double)WX[e];
+    s_w[P + e] = (double)WY[e];
+    s_b[e] = (double)rb[e];
+    s_x[e] = 0.0;
   }
   __syncthreads();
-  lds::coarsen_all<NT, N>(s_w, s_w + Mh::EX, s_mg);
-  lds::vcycle<NT, N>(s_w, s_w + Mh::EX, s_b, s_x, s_r, s_mg);
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int i = id % m + 1, j = id / m + 1;
-    X[b * P + j * N + i] = (T)s_x[id];
-  }
+  lds::coarsen_all<NT, N>(s_w, s_w + P, s_mg);
+  lds::vcycle<NT, N>(s_w, s_w + P, s_b, s_x, s_mg);
+  LDS_FOR_NODES(NT, N, k) X[b * PG + k] = (T)s_x[k];
 }
 
 template <int N>

@@ -1,4 +1,5 @@
-// LDS-resident solvers for one sample per workgroup on meshes h = 1/N, N <= 32.
+// Per-workgroup solvers for one sample on meshes h = 1/N (N <= 32 in LDS;
+// the top level of N = 64 in global scratch):
 //
 // * a geometric V-cycle for the SPD stiffness matrix A(a) (damped Jacobi,
 //   2 pre- and 2 post-sweeps, rediscretised coarse levels whose edge weights
@@ -13,6 +14,16 @@
 //   eigenvalue of the pencil restricted there, so CG applies, and the
 //   nearly-singular direction of (A - mu M) never enters the iteration.
 //   The preconditioner is P^T K^{-1} P with K^{-1} one V-cycle of A.
+//
+// Padded layout of a level n (the batched kernels use the same indexing):
+// node (i, j), 1 <= i, j <= n-1, at k = j n + i in an array of
+// P(n) = (n+1) n + 1 entries; row 0, row n, column 0 and the last entry are
+// zero and are never written, and the right neighbour of column n-1 aliases
+// column 0 of the next row, so every stencil is branch-free.  Edge weights:
+// WX[k] is the edge arriving at node k from the west, WY[k] from the south
+// (so the east and north edges of node k are WX[k + 1] and WY[k + n]), two
+// arrays of P(n) entries.  Loops run over the positions n .. n n - 1 and skip
+// column 0.
 #pragma once
 
 #include "common.h"
@@ -23,192 +34,202 @@ namespace lds {
 template <int n>
 struct Mesh {
   static constexpr int m = n - 1;
-  static constexpr int D = m * m;        // interior nodes
-  static constexpr int EX = (n - 1) * n; // horizontal edges
-  static constexpr int EY = n * (n - 1); // vertical edges
-  static constexpr int EW = EX + EY;
+  static constexpr int D = m * m;            // interior nodes
+  static constexpr int P = (n + 1) * n + 1;  // padded length of a vector
+  static constexpr int EW = 2 * P;           // [WX | WY]
+  static constexpr int lg = n == 2 ? 1 : n == 4 ? 2 : n == 8 ? 3 : n == 16 ? 4 : n == 32 ? 5 : 6;
 };
 
-// LDS doubles used by the V-cycle levels strictly below mesh n:
-// per level nc: weights (EW) + B, X, R (3 D).
+// Loop over the interior positions owned by this thread: k = n + t, n + t +
+// NT, ... < n n, skipping column 0.
+#define LDS_FOR_NODES(NT, n, k)                                  \
+  for (int k = (n) + (int)threadIdx.x; k < (n) * (n); k += (NT)) \
+    if ((k & ((n) - 1)) != 0)
+
+// (A x)_k with the diagonal in d
+template <int n>
+MLQMC_DEV double pA(const double* x, const double* wx, const double* wy, int k, double& d) {
+  const double ww = wx[k], we = wx[k + 1], ws = wy[k], wn = wy[k + n];
+  d = ww + we + ws + wn;
+  const double xc = x[k];
+  return ww * (xc - x[k - 1]) + we * (xc - x[k + 1]) + ws * (xc - x[k - n]) +
+         wn * (xc - x[k + n]);
+}
+template <int n>
+MLQMC_DEV double pdiag(const double* wx, const double* wy, int k) {
+  return wx[k] + wx[k + 1] + wy[k] + wy[k + n];
+}
+// (M x)_k without the h^2/12 factor
+template <int n>
+MLQMC_DEV double pM12(const double* x, int k) {
+  return 6.0 * x[k] + x[k - 1] + x[k + 1] + x[k - n] + x[k + n] + x[k + n + 1] + x[k - n - 1];
+}
+
+// Doubles of the V-cycle levels strictly below mesh n: per level nc, the
+// weights (2 P) and B, X (2 P).
 template <int n>
 constexpr int mg_scratch() {
   int s = 0;
-  for (int c = n / 2; c >= 2; c /= 2) s += 2 * (c - 1) * c + 3 * (c - 1) * (c - 1);
+  for (int c = n / 2; c >= 2; c /= 2) s += 4 * ((c + 1) * c + 1);
   return s;
 }
 
+// zero `count` doubles
+template <int NT>
+MLQMC_DEV void zero(double* x, int count) {
+  for (int e = threadIdx.x; e < count; e += NT) x[e] = 0.0;
+}
+
+// Weights of every level below n, each the mean of the two collinear fine
+// edges it covers; the B and X arrays of every level are zeroed.
 template <int NT, int n>
 MLQMC_DEV void coarsen_all(const double* wx, const double* wy, double* nxt) {
   if constexpr (n > 2) {
-    constexpr int nc = n / 2, mc = nc - 1;
+    constexpr int nc = n / 2, Pc = Mesh<nc>::P;
     double* wxc = nxt;
-    double* wyc = wxc + (nc - 1) * nc;
-    for (int e = threadIdx.x; e < (nc - 1) * nc; e += NT) {
-      const int J = e / nc + 1, I = e % nc;
-      wxc[e] = coarsen_wx(wx, n, I, J);
+    double* wyc = wxc + Pc;
+    for (int e = threadIdx.x; e < Pc; e += NT) {
+      const int J = e / nc, I = e % nc;
+      const int Ie = (I == 0) ? nc : I, Je = (I == 0) ? J - 1 : J;
+      wxc[e] = (Je >= 1 && Je <= nc - 1)
+                   ? 0.5 * (wx[2 * Je * n + 2 * Ie - 1] + wx[2 * Je * n + 2 * Ie])
+                   : 0.0;
+      wyc[e] = (J >= 1 && J <= nc && I >= 1)
+                   ? 0.5 * (wy[(2 * J - 1) * n + 2 * I] + wy[2 * J * n + 2 * I])
+                   : 0.0;
     }
-    for (int e = threadIdx.x; e < nc * (nc - 1); e += NT) {
-      const int J = e / mc, I = e % mc + 1;
-      wyc[e] = coarsen_wy(wy, n, I, J);
-    }
+    zero<NT>(wyc + Pc, 2 * Pc);
     __syncthreads();
-    constexpr int Dc = mc * mc;
-    coarsen_all<NT, nc>(wxc, wyc, wyc + nc * (nc - 1) + 3 * Dc);
+    coarsen_all<NT, nc>(wxc, wyc, wyc + 3 * Pc);
   }
 }
 
 // X = omega * B / diag  (first sweep from a zero start)
 template <int NT, int n>
 MLQMC_DEV void jacobi_first(const double* wx, const double* wy, const double* B, double* X) {
-  constexpr int m = n - 1, D = m * m;
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int i = id % m + 1, j = id / m + 1;
-    X[id] = kOmega * B[id] / stencil_diag(wx, wy, n, i, j);
-  }
+  LDS_FOR_NODES(NT, n, k) X[k] = kOmega * B[k] / pdiag<n>(wx, wy, k);
   __syncthreads();
 }
 
 // X <- X + omega (B - A X) / diag, new values staged in registers
 template <int NT, int n>
 MLQMC_DEV void jacobi_sweep(const double* wx, const double* wy, const double* B, double* X) {
-  constexpr int m = n - 1, D = m * m, PT = (D + NT - 1) / NT;
+  constexpr int PT = (n * n - n + NT - 1) / NT;
   double nv[PT];
 #pragma unroll
-  for (int k = 0; k < PT; ++k) {
-    const int id = threadIdx.x + k * NT;
-    if (id < D) {
-      const int i = id % m + 1, j = id / m + 1;
+  for (int q = 0; q < PT; ++q) {
+    const int k = n + (int)threadIdx.x + q * NT;
+    if (k < n * n && (k & (n - 1)) != 0) {
       double d;
-      const double ax = stencil_A(X, wx, wy, n, i, j, id, d);
-      nv[k] = X[id] + kOmega * (B[id] - ax) / d;
+      const double ax = pA<n>(X, wx, wy, k, d);
+      nv[q] = X[k] + kOmega * (B[k] - ax) / d;
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < PT; ++k) {
-    const int id = threadIdx.x + k * NT;
-    if (id < D) X[id] = nv[k];
+  for (int q = 0; q < PT; ++q) {
+    const int k = n + (int)threadIdx.x + q * NT;
+    if (k < n * n && (k & (n - 1)) != 0) X[k] = nv[q];
   }
   __syncthreads();
 }
 
-// One V-cycle X = K^{-1} B on mesh n; R is a residual scratch of D doubles,
-// `nxt` the scratch of the coarser levels (weights already built there).
-template <int NT, int n>
-MLQMC_DEV void vcycle(const double* wx, const double* wy, const double* B, double* X,
-                      double* R, double* nxt) {
-  constexpr int m = n - 1, D = m * m;
-  if constexpr (n == 2) {
-    if (threadIdx.x == 0) X[0] = B[0] / stencil_diag(wx, wy, 2, 1, 1);
-    __syncthreads();
-  } else {
-    constexpr int nc = n / 2, mc = nc - 1, Dc = mc * mc;
-    const double* wxc = nxt;
-    const double* wyc = wxc + (nc - 1) * nc;
-    double* Bc = nxt + 2 * (nc - 1) * nc;
-    double* Xc = Bc + Dc;
-    double* Rc = Xc + Dc;
-    jacobi_first<NT, n>(wx, wy, B, X);
-    jacobi_sweep<NT, n>(wx, wy, B, X);
-    for (int id = threadIdx.x; id < D; id += NT) {
-      const int i = id % m + 1, j = id / m + 1;
-      double d;
-      R[id] = B[id] - stencil_A(X, wx, wy, n, i, j, id, d);
-    }
-    __syncthreads();
-    for (int id = threadIdx.x; id < Dc; id += NT) {
-      const int I = id % mc + 1, J = id / mc + 1;
-      Bc[id] = restrict_at(R, n, I, J);
-    }
-    __syncthreads();
-    vcycle<NT, nc>(wxc, wyc, Bc, Xc, Rc, Rc + Dc);
-    for (int id = threadIdx.x; id < D; id += NT) {
-      const int i = id % m + 1, j = id / m + 1;
-      X[id] += prolong2_at(Xc, nc, i, j);
-    }
-    __syncthreads();
-    jacobi_sweep<NT, n>(wx, wy, B, X);
-    jacobi_sweep<NT, n>(wx, wy, B, X);
-  }
-}
-
-// Xout = Xin + omega (B - A Xin) / diag (two distinct arrays)
+// Xout = Xin + omega (B - A Xin) / diag (two distinct arrays; for top levels
+// too large for register staging)
 template <int NT, int n>
 MLQMC_DEV void jacobi_to(const double* wx, const double* wy, const double* B, const double* Xin,
                          double* Xout) {
-  constexpr int m = n - 1, D = m * m;
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int i = id % m + 1, j = id / m + 1;
+  LDS_FOR_NODES(NT, n, k) {
     double d;
-    const double ax = stencil_A(Xin, wx, wy, n, i, j, id, d);
-    Xout[id] = Xin[id] + kOmega * (B[id] - ax) / d;
+    const double ax = pA<n>(Xin, wx, wy, k, d);
+    Xout[k] = Xin[k] + kOmega * (B[k] - ax) / d;
   }
   __syncthreads();
 }
 
-// The same V-cycle for a top level whose arrays are too large for register
-// staging (mesh 1/64 and finer): the sweeps alternate between X and R, the
-// levels below run vcycle().
+// Bc = P^T (B - A X): the residual at the seven fine nodes each coarse node's
+// hat function covers (weight 1 at the node, 1/2 at E, W, N, S, NE, SW, all
+// interior), formed on the fly, so no residual array is stored.
 template <int NT, int n>
-MLQMC_DEV void vcycle_pingpong(const double* wx, const double* wy, const double* B, double* X,
-                               double* R, double* nxt) {
-  constexpr int m = n - 1, D = m * m;
-  constexpr int nc = n / 2, mc = nc - 1, Dc = mc * mc;
-  const double* wxc = nxt;
-  const double* wyc = wxc + (nc - 1) * nc;
-  double* Bc = nxt + 2 * (nc - 1) * nc;
-  double* Xc = Bc + Dc;
-  double* Rc = Xc + Dc;
-  jacobi_first<NT, n>(wx, wy, B, R);
-  jacobi_to<NT, n>(wx, wy, B, R, X);
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int i = id % m + 1, j = id / m + 1;
+MLQMC_DEV void restrict_residual(const double* wx, const double* wy, const double* B,
+                                 const double* X, double* Bc) {
+  constexpr int nc = n / 2;
+  auto res = [&](int k) {
     double d;
-    R[id] = B[id] - stencil_A(X, wx, wy, n, i, j, id, d);
+    return B[k] - pA<n>(X, wx, wy, k, d);
+  };
+  LDS_FOR_NODES(NT, nc, kc) {
+    const int I = kc & (nc - 1), J = kc >> Mesh<nc>::lg;
+    const int f = 2 * J * n + 2 * I;
+    Bc[kc] = res(f) + 0.5 * (res(f - 1) + res(f + 1) + res(f - n) + res(f + n) +
+                             res(f + n + 1) + res(f - n - 1));
   }
   __syncthreads();
-  for (int id = threadIdx.x; id < Dc; id += NT) {
-    const int I = id % mc + 1, J = id / mc + 1;
-    Bc[id] = restrict_at(R, n, I, J);
-  }
-  __syncthreads();
-  vcycle<NT, nc>(wxc, wyc, Bc, Xc, Rc, Rc + Dc);
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int i = id % m + 1, j = id / m + 1;
-    X[id] += prolong2_at(Xc, nc, i, j);
-  }
-  __syncthreads();
-  jacobi_to<NT, n>(wx, wy, B, X, R);
-  jacobi_to<NT, n>(wx, wy, B, R, X);
 }
 
+// X += P Xc (2:1 P1 interpolation: the mean of the coarse values at
+// (i>>1, j>>1) and ((i+1)>>1, (j+1)>>1))
 template <int NT, int n>
-MLQMC_DEV void vcycle_top(const double* wx, const double* wy, const double* B, double* X,
-                          double* R, double* nxt) {
-  if constexpr (n > 32)
-    vcycle_pingpong<NT, n>(wx, wy, B, X, R, nxt);
-  else
-    vcycle<NT, n>(wx, wy, B, X, R, nxt);
+MLQMC_DEV void prolong_add(const double* Xc, double* X) {
+  constexpr int nc = n / 2;
+  LDS_FOR_NODES(NT, n, k) {
+    const int i = k & (n - 1), j = k >> Mesh<n>::lg;
+    X[k] += 0.5 * (Xc[(j >> 1) * nc + (i >> 1)] + Xc[((j + 1) >> 1) * nc + ((i + 1) >> 1)]);
+  }
+  __syncthreads();
 }
 
-// Arrays of one projected-PCG solve on mesh N (all LDS, D doubles each except
-// the weights and the multigrid scratch).
+// One V-cycle X = K^{-1} B on mesh n; `nxt` holds the coarser levels (weights
+// built by coarsen_all).  kStage: register-staged sweeps (false: the sweeps
+// alternate between X and Xtmp, for top levels in global scratch).
+template <int NT, int n, bool kStage = true>
+MLQMC_DEV void vcycle(const double* wx, const double* wy, const double* B, double* X,
+                      double* nxt, double* Xtmp = nullptr) {
+  if constexpr (n == 2) {
+    if (threadIdx.x == 0) X[3] = B[3] / pdiag<2>(wx, wy, 3);
+    __syncthreads();
+  } else {
+    constexpr int nc = n / 2, Pc = Mesh<nc>::P;
+    const double* wxc = nxt;
+    const double* wyc = wxc + Pc;
+    double* Bc = nxt + 2 * Pc;
+    double* Xc = Bc + Pc;
+    if constexpr (kStage) {
+      jacobi_first<NT, n>(wx, wy, B, X);
+      jacobi_sweep<NT, n>(wx, wy, B, X);
+    } else {
+      jacobi_first<NT, n>(wx, wy, B, Xtmp);
+      jacobi_to<NT, n>(wx, wy, B, Xtmp, X);
+    }
+    restrict_residual<NT, n>(wx, wy, B, X, Bc);
+    vcycle<NT, nc>(wxc, wyc, Bc, Xc, Xc + Pc);
+    prolong_add<NT, n>(Xc, X);
+    if constexpr (kStage) {
+      jacobi_sweep<NT, n>(wx, wy, B, X);
+      jacobi_sweep<NT, n>(wx, wy, B, X);
+    } else {
+      jacobi_to<NT, n>(wx, wy, B, X, Xtmp);
+      jacobi_to<NT, n>(wx, wy, B, Xtmp, X);
+    }
+  }
+}
+
+// Arrays of one projected-PCG solve on mesh N, P(N) doubles each except the
+// weights [WX | WY] and the multigrid scratch.  q may share z's storage (z is
+// dead between forming p and the next V-cycle); xtmp is only used when the
+// top level sweeps without register staging.
 struct PcgArrays {
-  double *wx, *wy, *v, *t, *r, *z, *p, *q, *mg, *red;
+  double *wx, *wy, *v, *t, *r, *z, *p, *q, *mg, *red, *xtmp;
 };
 
-// ||v||_M^2 and v^T A v in one pass (all threads get both)
+// ||x||_M^2 and x^T A x in one pass (all threads get both)
 template <int NT, int n>
 MLQMC_DEV void rayleigh_parts(const PcgArrays& a, const double* x, double& xMx, double& xAx) {
-  constexpr int m = n - 1, D = m * m;
   double s[2] = {0.0, 0.0};
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int i = id % m + 1, j = id / m + 1;
+  LDS_FOR_NODES(NT, n, k) {
     double d;
-    const double ax = stencil_A(x, a.wx, a.wy, n, i, j, id, d);
-    s[0] += x[id] * stencil_M12(x, n, i, j, id);
-    s[1] += x[id] * ax;
+    s[0] += x[k] * pM12<n>(x, k);
+    s[1] += x[k] * pA<n>(x, a.wx, a.wy, k, d);
   }
   block_sums<NT, 2>(s, a.red);
   xMx = s[0] * mass_scale(n);
@@ -217,17 +238,24 @@ MLQMC_DEV void rayleigh_parts(const PcgArrays& a, const double* x, double& xMx, 
 
 template <int NT, int n>
 MLQMC_DEV void scale_vec(double* x, double f) {
-  constexpr int D = (n - 1) * (n - 1);
-  for (int id = threadIdx.x; id < D; id += NT) x[id] *= f;
+  LDS_FOR_NODES(NT, n, k) x[k] *= f;
   __syncthreads();
+}
+
+template <int NT, int n>
+MLQMC_DEV void precondition(const PcgArrays& a, const double* r, double* z) {
+  if constexpr (n > 32)
+    vcycle<NT, n, false>(a.wx, a.wy, r, z, a.mg, a.xtmp);
+  else
+    vcycle<NT, n>(a.wx, a.wy, r, z, a.mg);
 }
 
 // Projected PCG for  P (A - mu M) P^T t = -(A v - rho M v), t = 0 initially.
 // Requires v^T M v = 1 and rho = v^T A v.  Returns the iteration count;
 // sets *conv (stop test met) and *brk (non-positive curvature).
-// Stops when sqrt(r.z / r0.z0) <= rtol or, with lam_tol > 0, when the
-// estimated error of the Rayleigh quotient of v + t is <= lam_tol times it:
-// the quotient is tracked as mu + f/m, f = w^T (A - mu M) w, m = w^T M w,
+// Stops when sqrt(r.z / r0.z0) <= rtol or, with kTrack, when the estimated
+// error of the Rayleigh quotient of v + t is <= lam_tol times it: the
+// quotient is tracked as mu + f/m, f = w^T (A - mu M) w, m = w^T M w,
 // w = v + t, from the step's dot products, and the error estimated from the
 // tails of f (energy, factor c^2) and m (first order, factor c, scaled by
 // |lambda - mu|), c the observed residual contraction.
@@ -235,7 +263,6 @@ template <int NT, int n, bool kTrack = false>
 MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int maxit,
                      bool* conv, bool* brk, double lam_tol = 0.0) {
   constexpr int K = kTrack ? 6 : 3;
-  constexpr int m = n - 1, D = m * m;
   const double hm = mass_scale(n);
   double* const v = a.v;
   double* const t = a.t;
@@ -243,27 +270,25 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
   double* const z = a.z;
   double* const p = a.p;
   double* const q = a.q;
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int i = id % m + 1, j = id / m + 1;
+  LDS_FOR_NODES(NT, n, k) {
     double d;
-    const double av = stencil_A(v, a.wx, a.wy, n, i, j, id, d);
-    r[id] = -(av - rho * hm * stencil_M12(v, n, i, j, id));
-    t[id] = 0.0;
+    const double av = pA<n>(v, a.wx, a.wy, k, d);
+    r[k] = -(av - rho * hm * pM12<n>(v, k));
+    t[k] = 0.0;
   }
   __syncthreads();
-  vcycle_top<NT, n>(a.wx, a.wy, r, z, q, a.mg);
+  precondition<NT, n>(a, r, z);
   // rz = r.(P^T z) = r.z - (r.v)(Mv.z);  p = P^T z
   double s3[3] = {0.0, 0.0, 0.0};
-  for (int id = threadIdx.x; id < D; id += NT) {
-    const int i = id % m + 1, j = id / m + 1;
-    s3[0] += r[id] * z[id];
-    s3[1] += hm * stencil_M12(v, n, i, j, id) * z[id];
-    s3[2] += r[id] * v[id];
+  LDS_FOR_NODES(NT, n, k) {
+    s3[0] += r[k] * z[k];
+    s3[1] += hm * pM12<n>(v, k) * z[k];
+    s3[2] += r[k] * v[k];
   }
   block_sums<NT, 3>(s3, a.red);
   double rz = s3[0] - s3[2] * s3[1];
   const double rz0 = rz;
-  for (int id = threadIdx.x; id < D; id += NT) p[id] = z[id] - s3[1] * v[id];
+  LDS_FOR_NODES(NT, n, k) p[k] = z[k] - s3[1] * v[k];
   __syncthreads();
   *conv = false;
   *brk = false;
@@ -275,26 +300,25 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
   double f = rho - mu, mm = 1.0, dmp = 0.0, rzp = 0.0;
   while (it < maxit) {
     ++it;
-    // q = (A - mu M) p;  pq = p.(P q) = p.q - (p.Mv)(v.q); with lam_tol also
+    // q = (A - mu M) p;  pq = p.(P q) = p.q - (p.Mv)(v.q); with kTrack also
     // p.M p, t.M p, t.q for the Rayleigh-quotient tracking
     double s[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) s[k] = 0.0;
-    for (int id = threadIdx.x; id < D; id += NT) {
-      const int i = id % m + 1, j = id / m + 1;
+    for (int e = 0; e < K; ++e) s[e] = 0.0;
+    LDS_FOR_NODES(NT, n, k) {
       double d;
-      const double ap = stencil_A(p, a.wx, a.wy, n, i, j, id, d);
-      const double mp = hm * stencil_M12(p, n, i, j, id);
+      const double ap = pA<n>(p, a.wx, a.wy, k, d);
+      const double mp = hm * pM12<n>(p, k);
       const double qv = ap - mu * mp;
-      q[id] = qv;
-      s[0] += p[id] * qv;
-      s[1] += v[id] * qv;
-      s[2] += p[id] * hm * stencil_M12(v, n, i, j, id);
+      s[0] += p[k] * qv;
+      s[1] += v[k] * qv;
+      s[2] += p[k] * hm * pM12<n>(v, k);
       if constexpr (kTrack) {
-        s[3] += p[id] * mp;
-        s[4] += t[id] * mp;
-        s[5] += t[id] * qv;
+        s[3] += p[k] * mp;
+        s[4] += t[k] * mp;
+        s[5] += t[k] * qv;
       }
+      q[k] = qv;  // may overwrite z, which is dead here
     }
     block_sums<NT, K>(s, a.red);
     const double pq = s[0] - s[2] * s[1];
@@ -318,23 +342,21 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
       mm = m1;
       dmp = dm;
     }
-    for (int id = threadIdx.x; id < D; id += NT) {
-      const int i = id % m + 1, j = id / m + 1;
-      t[id] += alpha * p[id];
-      r[id] -= alpha * (q[id] - c * hm * stencil_M12(v, n, i, j, id));
+    LDS_FOR_NODES(NT, n, k) {
+      t[k] += alpha * p[k];
+      r[k] -= alpha * (q[k] - c * hm * pM12<n>(v, k));
     }
     __syncthreads();
     if (lam_done) {
       *conv = true;
       break;
     }
-    vcycle_top<NT, n>(a.wx, a.wy, r, z, q, a.mg);
+    precondition<NT, n>(a, r, z);
     double u[3] = {0.0, 0.0, 0.0};
-    for (int id = threadIdx.x; id < D; id += NT) {
-      const int i = id % m + 1, j = id / m + 1;
-      u[0] += r[id] * z[id];
-      u[1] += hm * stencil_M12(v, n, i, j, id) * z[id];
-      u[2] += r[id] * v[id];
+    LDS_FOR_NODES(NT, n, k) {
+      u[0] += r[k] * z[k];
+      u[1] += hm * pM12<n>(v, k) * z[k];
+      u[2] += r[k] * v[k];
     }
     block_sums<NT, 3>(u, a.red);
     const double rzn = u[0] - u[2] * u[1];
@@ -345,21 +367,26 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
     const double beta = rzn / rz;
     rzp = rz;
     rz = rzn;
-    for (int id = threadIdx.x; id < D; id += NT) p[id] = z[id] - u[1] * v[id] + beta * p[id];
+    LDS_FOR_NODES(NT, n, k) p[k] = z[k] - u[1] * v[k] + beta * p[k];
     __syncthreads();
   }
   return it;
 }
 
-// Edge weights of mesh n from an edge table: w_e = a0 + sum_{j<S} y_j Phi[j][e].
+// Padded edge weights of mesh n from the padded edge table of the batched
+// path (rows of [WX | WY] with (n + 2) n entries each):
+// w_e = a0 + sum_{j<S} y_j Phi[j][e].  Entries that no stencil reads are
+// finite and otherwise unused.
 template <int NT, int n>
 MLQMC_DEV void weights_from_table(const double* __restrict__ phi, const double* ys, int S,
-                                  double a0, double* wx) {
-  constexpr int EW = Mesh<n>::EW;
-  for (int e = threadIdx.x; e < EW; e += NT) {
+                                  double a0, double* w) {
+  constexpr int P = Mesh<n>::P, PG = (n + 2) * n;
+  for (int e = threadIdx.x; e < 2 * P; e += NT) {
+    const int half = e >= P, idx = e - half * P;
+    const double* src = phi + half * PG + idx;
     double acc = a0;
-    for (int j = 0; j < S; ++j) acc += ys[j] * phi[(int64_t)j * EW + e];
-    wx[e] = acc;  // wy follows wx contiguously
+    for (int j = 0; j < S; ++j) acc += ys[j] * src[(int64_t)j * 2 * PG];
+    w[e] = acc;  // WY follows WX contiguously
   }
   __syncthreads();
 }
