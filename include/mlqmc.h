@@ -96,13 +96,15 @@ typedef struct {
   int32_t max_lin_iter;      /* cap on PCG iterations per linear solve */
   int32_t chain_len;         /* samples per warm-start chain (<=0: library default) */
   int32_t batch;             /* samples per fine-solve batch (<=0: library default) */
+  int32_t pcg_graph;         /* 1: replay the batched PCG iterations from a captured HIP graph
+                                (cached per layout); 0: launch them one by one */
   int32_t io_on_device;      /* 1: device pointers, 0: host pointers */
   int64_t device_mem_cap;    /* bytes; 0 = unlimited (a test hook for MLQMC_ENOMEM) */
 } mlqmc_opts;
 
 /* Fills *opt with the defaults (FP64, eig_rtol 1e-8, max_rq_iter 12,
  * lin_rtol 0 and lam_rtol 0 (per precision), rq_lin_rtol 1e-2, max_lin_iter 60,
- * io_on_device 0). */
+ * pcg_graph 1, io_on_device 0). */
 void mlqmc_default_opts(mlqmc_opts* opt);
 
 /* Creates a context on HIP device `device`, enqueueing on `hip_stream`

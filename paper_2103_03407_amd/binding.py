@@ -50,7 +50,8 @@ class Opts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("eig_rtol", C.c_double), ("max_rq_iter", C.c_int32),
                 ("lin_rtol", C.c_double), ("lam_rtol", C.c_double), ("rq_lin_rtol", C.c_double),
                 ("max_lin_iter", C.c_int32), ("chain_len", C.c_int32), ("batch", C.c_int32),
-                ("io_on_device", C.c_int32), ("device_mem_cap", C.c_int64)]
+                ("pcg_graph", C.c_int32), ("io_on_device", C.c_int32),
+                ("device_mem_cap", C.c_int64)]
 
 
 _lib = None

@@ -46,6 +46,14 @@ struct Status {
 struct mlqmc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // captured PCG iterations (graph replay): one entry per fine-solve tag,
+  // valid while every argument baked into it (the key) is unchanged
+  struct PcgGraph {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::map<std::string, PcgGraph> graphs;
+  hipStream_t cap_stream = nullptr;  // private stream for capturing (default priority)
   int s_max = 0;
   double a0 = 0.0;
   double* d_c = nullptr;
@@ -311,6 +319,61 @@ int default_chain(int64_t n, int warm, int chain_len, int N) {
   return (int)std::max<int64_t>(1, c);
 }
 
+// Everything a captured PCG iteration bakes into its kernel arguments.
+template <typename T, typename V>
+std::vector<uint64_t> graph_key(int nh, int64_t Bn, const mlqmc_opts* o, const FineState& S,
+                                std::initializer_list<const void*> ptrs, const V& W, const V& X,
+                                const V& Xb, const V& Bv, int nblk0, int nblk_post) {
+  std::vector<uint64_t> k = {(uint64_t)nh, (uint64_t)Bn, sizeof(T), (uint64_t)nblk0,
+                             (uint64_t)nblk_post, (uint64_t)o->max_lin_iter};
+  double tl[2] = {lin_tol(o), lam_tol(o)};
+  uint64_t bits[2];
+  std::memcpy(bits, tl, sizeof bits);
+  k.push_back(bits[0]);
+  k.push_back(bits[1]);
+  for (const void* p : ptrs) k.push_back((uint64_t)(uintptr_t)p);
+  const void* sp[] = {S.mu, S.vs, S.rho, S.rz, S.rz0, S.alpha, S.c, S.c2, S.beta, S.lam, S.f,
+                      S.m, S.dmp, S.rzp, S.its, S.lin_acc, S.active, S.vact, S.flags};
+  for (const void* p : sp) k.push_back((uint64_t)(uintptr_t)p);
+  for (const V* v : {&W, &X, &Xb, &Bv})
+    for (auto* p : *v) k.push_back((uint64_t)(uintptr_t)p);
+  return k;
+}
+
+// The instantiated graph of `body` (launches on the stream it is given) for
+// this tag and key: reused while the key matches, captured on the context's
+// private stream otherwise.
+template <typename F>
+mlqmc_status pcg_graph(mlqmc_ctx* ctx, const char* tag, int64_t, F body,
+                       const std::vector<uint64_t>& key, hipGraphExec_t* out) {
+  mlqmc_ctx::PcgGraph& g = ctx->graphs[tag];
+  if (g.exec && g.key == key) {
+    *out = g.exec;
+    return MLQMC_OK;
+  }
+  if (g.exec) {
+    CK(hipGraphExecDestroy(g.exec), "graph destroy");
+    g.exec = nullptr;
+  }
+  if (!ctx->cap_stream) CK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking),
+                           "capture stream");
+  CK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  const mlqmc_status st = body(ctx->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+  if (st != MLQMC_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return st;
+  }
+  CK(e, "end capture");
+  const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  CK(ei, "graph instantiate");
+  g.key = key;
+  *out = g.exec;
+  return MLQMC_OK;
+}
+
 // Two-grid update on mesh nh (>= 64) for n samples, batched.  T is the
 // storage type of the projected PCG and the V-cycle (double; float in mixed
 // precision); the right-hand side and the Rayleigh quotient are FP64.
@@ -505,7 +568,9 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     // first apply: z, vn, mvn, t, 2 weights per node in (no previous p); p, q out
     const double ab = (double)sz * Bn * (8 * D(nh));
     int cur = 0;
-    for (int it = 0; it < o->max_lin_iter; ++it) {
+    // one PCG iteration: apply (with the previous step's t update), alpha and
+    // the eigenvalue test, the V-cycle (with the residual update), beta
+    auto iteration = [&](int it) -> mlqmc_status {
       if (it == 0) ctx->t_begin(MLQMC_K_APPLY);
       CK(launch_pupdate_apply<T>(nh, Bn, zc, vn, pp[cur], mvn, wT, t, S, it == 0, pp[1 - cur],
                                  q, part, st),
@@ -517,12 +582,48 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
       CS(vcycle(true));
       CK(launch_scalar(PH_BETA, nh, Bn, nblk_post, part, S, lin_tol(o), o->max_lin_iter, st),
          "scalar");
-      if (it % 3 == 2 || it + 1 == o->max_lin_iter) {
-        CK(hipMemcpyAsync(h_active.data(), active, Bn, hipMemcpyDeviceToHost, st), "active");
-        CS(ctx->sync("pcg"));
+      return MLQMC_OK;
+    };
+    auto any_active = [&](bool* any) -> mlqmc_status {
+      CK(hipMemcpyAsync(h_active.data(), active, Bn, hipMemcpyDeviceToHost, st), "active");
+      CS(ctx->sync("pcg"));
+      *any = false;
+      for (int64_t k = 0; k < Bn; ++k) *any |= h_active[k] != 0;
+      return MLQMC_OK;
+    };
+    CS(iteration(0));
+    int done_its = 1;
+    if (o->pcg_graph) {
+      // Iterations 1, 2, ... replayed two at a time from a captured graph: two
+      // iterations bring every alternating buffer back to its parity, so one
+      // graph serves every replay.  Samples that have converged exit at once.
+      hipGraphExec_t exec = nullptr;
+      const std::string gtag = std::string(tag) + std::to_string(b0);
+      CS(pcg_graph(ctx, gtag.c_str(), Bn, [&](hipStream_t cs) -> mlqmc_status {
+        const hipStream_t keep = st;
+        st = cs;
+        mlqmc_status r = iteration(1);
+        if (r == MLQMC_OK) r = iteration(2);
+        st = keep;
+        return r;
+      }, graph_key<T>(nh, Bn, o, S, {zc, zo, rc, ro, pp[0], pp[1], vn, mvn, wT, t, q, part, act,
+                                     active}, W, X, Xb, Bv, nblk0, nblk_post), &exec));
+      while (done_its < o->max_lin_iter) {
+        CK(hipGraphLaunch(exec, st), "graph launch");
+        done_its += 2;
         bool any = false;
-        for (int64_t k = 0; k < Bn; ++k) any |= h_active[k] != 0;
+        CS(any_active(&any));
         if (!any) break;
+      }
+    } else {
+      for (int it = 1; it < o->max_lin_iter; ++it) {
+        CS(iteration(it));
+        done_its = it + 1;
+        if (it % 3 == 2 || it + 1 == o->max_lin_iter) {
+          bool any = false;
+          CS(any_active(&any));
+          if (!any) break;
+        }
       }
     }
     CK(launch_final_dots<T>(nh, Bn, v64, t, pp[0], pp[1], w64, S, part, st), "final dots");
@@ -689,6 +790,7 @@ void mlqmc_default_opts(mlqmc_opts* o) {
   o->max_lin_iter = 60;
   o->chain_len = 0;
   o->batch = 0;
+  o->pcg_graph = 1;
   o->io_on_device = 0;
   o->device_mem_cap = 0;
 }
@@ -774,6 +876,9 @@ void mlqmc_destroy(mlqmc_ctx* ctx) {
     hipEventDestroy(ev.first);
     hipEventDestroy(ev.second);
   }
+  for (auto& kv : ctx->graphs)
+    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   if (ctx->d_c) hipFree(ctx->d_c);
   if (ctx->d_k1) hipFree(ctx->d_k1);
   if (ctx->d_k2) hipFree(ctx->d_k2);

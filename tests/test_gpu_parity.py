@@ -459,6 +459,32 @@ def test_buffer_reuse_across_meshes(ctx):
         assert abs(c[k] - tg) <= LAM_RTOL * tg
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pcg_graph_replays_match_eager(ctx, prec):
+    # the PCG iterations replayed from the cached HIP graph give the eager
+    # launches' results bit for bit, replay after replay, with other work
+    # (an eager solve, a different level) and synchronisations in between;
+    # batch=10 splits the 24 samples into three graphs
+    pr = m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED
+    Y = np.ascontiguousarray(_points(1024, 64, 2, 0, 8, range(24)))
+    lv = (128, 64, 32, 8, 0, 0)
+    ref, li_ref = np.empty(24), np.zeros(24, np.int32)
+    ctx.eig_level(lv, Y, ref, np.zeros(24, np.uint8), lin_iters=li_ref,
+                  opts=m.default_opts(prec=pr, pcg_graph=0, batch=10))
+    Yd = np.ascontiguousarray(_points(1024, 16, 2, 0, 9, range(8)))
+    for rep in range(4):
+        got, li = np.empty(24), np.zeros(24, np.int32)
+        fl = np.zeros(24, np.uint8)
+        ctx.eig_level(lv, Y, got, fl, lin_iters=li,
+                      opts=m.default_opts(prec=pr, pcg_graph=1, batch=10))
+        assert not fl.any()
+        assert np.array_equal(got, ref), rep
+        assert np.array_equal(li, li_ref), rep
+        other = np.empty(8)
+        ctx.eig_level((64, 16, 16, 16, 0, 0), Yd, other, np.zeros(8, np.uint8),
+                      opts=m.default_opts(prec=pr, pcg_graph=rep % 2))
+
+
 def test_repeat_runs_bitwise_identical(ctx):
     Y = np.ascontiguousarray(_points(1024, 64, 2, 0, 6, range(40)))
     a, b = np.empty(40), np.empty(40)
