@@ -194,6 +194,7 @@ def main():
     fam = w.family()
     torch.cuda.init()
     ctx = m.Context(fam, device=0)
+    tuned = ctx.apply_tuning()  # the autotuner's table for this device, if shipped
     levels = [_lv6(lv) for lv in w.levels]
     Ns = [lv.N for lv in w.levels]
     zs = [w.z(l) for l in range(len(w.levels))]
@@ -277,7 +278,7 @@ def main():
                    "N": Ns, "R": w.R, "samples_per_step": n_samples,
                    "estimate": est[0], "variance": est[1]},
         "roofline": roof, "cpu_baseline": cpu, "accuracy_vs_oracle": acc,
-        "per_level": levels_out,
+        "per_level": levels_out, "tuning_entries_applied": tuned,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -180,6 +180,19 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t n_levels, const mlqmc_level*
                             const mlqmc_opts* opt, double* Q_lr, double* Qhat, double* V,
                             double* est);
 
+/* ---- tuning ---- */
+
+/* Sets how many workgroups in flight the batched stencil kernels of the fine
+ * solve on mesh 1/n_fine (64..1024, a power of two) aim for in precision
+ * `prec`; the number of row strips per sample follows from it and the batch
+ * size.  0 restores the default (65536).  The package's autotuner measures
+ * the choices on a device and writes a table the Python binding applies.
+ * The strip count sets the order in which the solver's dot products are
+ * summed, so results agree to rounding, not bit for bit, across settings.
+ * Errors: MLQMC_EINVAL (mesh, precision or value out of range). */
+mlqmc_status mlqmc_set_tuning(mlqmc_ctx* ctx, int32_t n_fine, int32_t prec,
+                              int64_t target_blocks);
+
 /* ---- instrumentation ---- */
 
 /* Kernel classes that can be timed with HIP events around each launch. */

@@ -1,0 +1,111 @@
+"""Autotuner for the batched fine-solve kernels.
+
+For every fine mesh of a workload that the batched path solves (1/64 ..
+1/1024) and each precision, times one mlqmc_eig_level pass over the
+workload's points for each candidate number of workgroups in flight
+(mlqmc_set_tuning; the row strips per sample follow from it), checks that
+the eigenvalues agree with the default setting to rounding, and writes the
+fastest choice per (mesh, precision) into a JSON table keyed by the device
+architecture.  The binding's Context.apply_tuning() reads that table.
+
+    python -m paper_2103_03407_amd.autotune --cfg 2 --cfg 4 [--out PATH]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+CANDIDATES = (8192, 16384, 32768, 65536, 131072, 262144)
+
+
+def _levels_on_batched_path(w):
+    """(level index, mesh) pairs whose fine solve runs on the batched path."""
+    out = []
+    for l, lv in enumerate(w.levels):
+        if lv.n_coarse and lv.n_fine >= 64:
+            out.append((l, lv.n_fine))
+    return out
+
+
+def tune(cfg_ids, precs=("fp64", "mixed"), reps=3, log=print):
+    import numpy as np
+    import torch
+    from . import binding as B
+    from synth import CONFIGS
+
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    best = {}
+    for cfg in cfg_ids:
+        w = CONFIGS[cfg]
+        ctx = B.Context(w.family())
+        for l, n_fine in _levels_on_batched_path(w):
+            lv = w.levels[l]
+            n = w.R * lv.N
+            Y = np.empty((n, lv.s_fine))
+            for r in range(w.R):
+                ctx.lattice_points(lv.N, w.z(l), w.shifts(l)[r], 0, lv.N,
+                                   Y[r * lv.N:(r + 1) * lv.N])
+            Yd = torch.from_numpy(Y).cuda()
+            lam = torch.empty(n, dtype=torch.float64, device="cuda")
+            lp = torch.empty(n, dtype=torch.float64, device="cuda") if lv.n_prev else None
+            fl = torch.zeros(n, dtype=torch.uint8, device="cuda")
+            level = (lv.n_fine, lv.s_fine, lv.n_coarse, lv.s_coarse, lv.n_prev, lv.s_prev)
+            for prec in precs:
+                p = B.MLQMC_MIXED if prec == "mixed" else B.MLQMC_FP64
+                opts = B.default_opts(prec=p)
+                ctx.set_tuning(n_fine, p, 0)
+                ctx.eig_level(level, Yd, lam, fl, lam_prev=lp, opts=opts)
+                ref = lam.cpu().numpy().copy()
+                times = {}
+                for tb in CANDIDATES:
+                    ctx.set_tuning(n_fine, p, tb)
+                    ctx.eig_level(level, Yd, lam, fl, lam_prev=lp, opts=opts)  # warm-up, graph capture
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        ctx.eig_level(level, Yd, lam, fl, lam_prev=lp, opts=opts)
+                    torch.cuda.synchronize()
+                    dt = (time.perf_counter() - t0) / reps
+                    err = float(np.max(np.abs(lam.cpu().numpy() - ref) / np.abs(ref)))
+                    if err > (1e-11 if prec == "fp64" else 1e-9):
+                        raise RuntimeError(f"tuning changed the result by {err:.2e}")
+                    times[tb] = dt
+                    log(f"cfg{cfg} level {l} 1/{n_fine} {prec} target {tb:7d}: "
+                        f"{n / dt:10.0f} samples/s (max change {err:.1e})")
+                key = (n_fine, prec)
+                tb = min(times, key=times.get)
+                if key not in best or times[tb] < best[key][1]:
+                    best[key] = (tb, times[tb])
+                ctx.set_tuning(n_fine, p, 0)
+        ctx.close()
+    entries = [{"n_fine": k[0], "prec": k[1], "target_blocks": v[0]}
+               for k, v in sorted(best.items())]
+    return arch, entries
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--cfg", type=int, action="append", required=True)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--reps", type=int, default=3)
+    a = ap.parse_args(argv)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    from . import binding as B
+    arch, entries = tune(a.cfg, reps=a.reps, log=lambda s: print(s, flush=True))
+    out = a.out or B.TUNING_PATH
+    table = json.load(open(out)) if os.path.exists(out) else {}
+    table[arch] = entries
+    with open(out, "w") as f:
+        json.dump(table, f, indent=1)
+    print(json.dumps({"arch": arch, "entries": entries}))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

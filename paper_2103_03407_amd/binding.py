@@ -16,6 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmlqmc.so")
+TUNING_PATH = os.path.join(HERE, "tuning.json")
 
 MLQMC_OK, MLQMC_EINVAL, MLQMC_ENOMEM, MLQMC_EDEVICE, MLQMC_ENOCONV = 0, -1, -2, -3, -4
 MLQMC_FP64, MLQMC_MIXED = 0, 1
@@ -26,7 +27,8 @@ K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE, K_PRE = 0, 1, 2, 3, 4, 5
 EXPORTS = [
     "mlqmc_default_opts", "mlqmc_create", "mlqmc_destroy", "mlqmc_last_error",
     "mlqmc_lattice_points", "mlqmc_coefficient", "mlqmc_apply_operator", "mlqmc_prolong",
-    "mlqmc_eig_level", "mlqmc_estimate", "mlqmc_set_timing", "mlqmc_get_timing",
+    "mlqmc_eig_level", "mlqmc_estimate", "mlqmc_set_tuning", "mlqmc_set_timing",
+    "mlqmc_get_timing",
 ]
 
 
@@ -91,11 +93,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                     P, P, P]
     lib.mlqmc_estimate.argtypes = [P, I32, C.POINTER(Level), P, I32, P, P, C.POINTER(Opts), P,
                                    P, P, P]
+    lib.mlqmc_set_tuning.argtypes = [P, I32, I32, I64]
     lib.mlqmc_set_timing.argtypes = [P, I32]
     lib.mlqmc_get_timing.argtypes = [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
     for name in ("mlqmc_create", "mlqmc_lattice_points", "mlqmc_coefficient",
                  "mlqmc_apply_operator", "mlqmc_prolong", "mlqmc_eig_level", "mlqmc_estimate",
-                 "mlqmc_set_timing", "mlqmc_get_timing"):
+                 "mlqmc_set_tuning", "mlqmc_set_timing", "mlqmc_get_timing"):
         getattr(lib, name).restype = C.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -162,6 +165,33 @@ class Context:
             raise MlqmcError(st, lib.mlqmc_last_error(None).decode())
         self._lib, self._h = lib, h
         self.s_max = int(c.size)
+        self.device = int(device)
+
+    def set_tuning(self, n_fine, prec, target_blocks):
+        return self._check(self._lib.mlqmc_set_tuning(self._h, int(n_fine), int(prec),
+                                                      int(target_blocks)))
+
+    def apply_tuning(self, path=None, arch=None):
+        """Applies the autotuner's table (a JSON file; by default the one
+        shipped beside the library) for this device's architecture.  Returns
+        the number of entries applied."""
+        import json
+        path = path or TUNING_PATH
+        if not os.path.exists(path):
+            return 0
+        table = json.load(open(path))
+        if arch is None:
+            try:
+                import torch
+                arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+            except Exception:
+                return 0
+        count = 0
+        for e in table.get(arch, []):
+            prec = MLQMC_MIXED if e["prec"] == "mixed" else MLQMC_FP64
+            self.set_tuning(e["n_fine"], prec, e["target_blocks"])
+            count += 1
+        return count
 
     def close(self):
         if getattr(self, "_h", None):
@@ -302,6 +332,10 @@ def mlqmc_eig_level(ctx, *a, **k):
 
 def mlqmc_estimate(ctx, *a, **k):
     return ctx.estimate(*a, **k)
+
+
+def mlqmc_set_tuning(ctx, *a, **k):
+    return ctx.set_tuning(*a, **k)
 
 
 def mlqmc_set_timing(ctx, *a, **k):

@@ -54,6 +54,13 @@ struct mlqmc_ctx {
   };
   std::map<std::string, PcgGraph> graphs;
   hipStream_t cap_stream = nullptr;  // private stream for capturing (default priority)
+  // tuning: workgroups in flight for the batched stencil kernels, per
+  // (fine mesh, precision); absent = the library default
+  std::map<std::pair<int, int>, int64_t> target_blocks;
+  int64_t target_for(int n, int prec) const {
+    auto it = target_blocks.find({n, prec});
+    return it == target_blocks.end() ? 0 : it->second;
+  }
   int s_max = 0;
   double a0 = 0.0;
   double* d_c = nullptr;
@@ -475,6 +482,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   CS(ctx->getT(nm("vact").c_str(), batch, &vact));
   std::vector<uint8_t> h_active(batch);
 
+  set_target_blocks(ctx->target_for(nh, kMixed ? MLQMC_MIXED : MLQMC_FP64));
   for (int64_t b0 = 0; b0 < n; b0 += batch) {
     const int64_t Bn = std::min<int64_t>(batch, n - b0);
     const int nblk0 = march_blocks(nh, Bn);
@@ -1093,6 +1101,22 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
   CS(stage_out(ctx, est, dest, 2, dev));
   CS(ctx->sync("estimate"));
   return flagged ? ctx->fail(MLQMC_ENOCONV, "at least one sample is flagged") : MLQMC_OK;
+}
+
+mlqmc_status mlqmc_set_tuning(mlqmc_ctx* ctx, int32_t n_fine, int32_t prec,
+                              int64_t target_blocks) {
+  if (!ctx) return MLQMC_EINVAL;
+  if (!is_pow2(n_fine) || n_fine < 64 || n_fine > 1024)
+    return ctx->fail(MLQMC_EINVAL, "tuning applies to batched meshes 64..1024 (got %d)", n_fine);
+  if (prec != MLQMC_FP64 && prec != MLQMC_MIXED)
+    return ctx->fail(MLQMC_EINVAL, "unknown precision %d", prec);
+  if (target_blocks < 0 || target_blocks > (int64_t)1 << 30)
+    return ctx->fail(MLQMC_EINVAL, "target_blocks %lld out of range", (long long)target_blocks);
+  if (target_blocks == 0)
+    ctx->target_blocks.erase({n_fine, prec});
+  else
+    ctx->target_blocks[{n_fine, prec}] = target_blocks;
+  return MLQMC_OK;
 }
 
 mlqmc_status mlqmc_set_timing(mlqmc_ctx* ctx, int32_t cls) {

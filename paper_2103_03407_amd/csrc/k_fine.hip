@@ -117,20 +117,15 @@ struct MGeo {
   int64_t B;
 };
 
-// Strips per sample: as few as keep ~kTargetBlocks blocks in flight (one strip
-// per sample for large batches, so no halo row is read twice); with several
-// strips, odd strips march downwards so two neighbours read their shared halo
-// rows at the same time and the second read hits in L2.
-inline int64_t target_blocks() {
-  static int64_t v = [] {
-    const char* e = std::getenv("MLQMC_TARGET_BLOCKS");
-    const long long x = e ? std::atoll(e) : 0;
-    return (int64_t)(x > 0 ? x : 65536);
-  }();
-  return v;
-}
+// Strips per sample: as few as keep about `target` workgroups in flight
+// (one strip per sample for large batches, so no halo row is read twice);
+// with several strips, odd strips march downwards so two neighbours read
+// their shared halo rows at the same time and the second read hits in L2.
+// The target is a per-mesh tuning value set before each batch.
+constexpr int64_t kDefaultTargetBlocks = 65536;
+thread_local int64_t t_target_blocks = kDefaultTargetBlocks;
 inline int strips_for(int rows, int64_t units) {
-  const int64_t tb = target_blocks();
+  const int64_t tb = t_target_blocks;
   int s = (int)((tb + units - 1) / std::max<int64_t>(units, 1));
   s = std::max(1, std::min(s, (rows + 7) / 8));
   return s;
@@ -1129,6 +1124,8 @@ hipError_t launch_post(int n, int64_t B, const T* w, const T* rhs, const T* Xin,
 }
 
 int post_strips(int n, int64_t B) { return vgeo_post(n, B).strips; }
+
+void set_target_blocks(int64_t v) { t_target_blocks = v > 0 ? v : kDefaultTargetBlocks; }
 
 int march_blocks(int n, int64_t B) {
   int nb = 0;

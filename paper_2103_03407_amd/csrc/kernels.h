@@ -121,6 +121,9 @@ hipError_t launch_post(int n, int64_t B, const T* w, const T* rhs, const T* Xin,
                        hipStream_t st);
 // strips per sample of launch_post for a batch of B (its partial-sum count per sample)
 int post_strips(int n, int64_t B);
+// workgroups in flight the batched stencil kernels aim for (<= 0: default);
+// the strips per sample follow from it and the batch size
+void set_target_blocks(int64_t v);
 // blocks per sample of the row-marching kernels for a batch of B (their partial-sum count)
 int march_blocks(int n, int64_t B);
 template <typename T>

@@ -485,6 +485,32 @@ def test_pcg_graph_replays_match_eager(ctx, prec):
                       opts=m.default_opts(prec=pr, pcg_graph=rep % 2))
 
 
+def test_tuning_changes_speed_not_results(ctx, tmp_path):
+    Y = np.ascontiguousarray(_points(1024, 64, 2, 0, 10, range(40)))
+    lv = (128, 64, 32, 8, 0, 0)
+    ref = np.empty(40)
+    ctx.eig_level(lv, Y, ref, np.zeros(40, np.uint8))
+    for tb in (1, 4096, 1 << 20):
+        ctx.set_tuning(128, m.MLQMC_FP64, tb)
+        got = np.empty(40)
+        ctx.eig_level(lv, Y, got, np.zeros(40, np.uint8))
+        assert _rel(got, ref) <= 1e-12, tb
+    ctx.set_tuning(128, m.MLQMC_FP64, 0)
+    back = np.empty(40)
+    ctx.eig_level(lv, Y, back, np.zeros(40, np.uint8))
+    assert np.array_equal(back, ref)
+    for bad in ((100, m.MLQMC_FP64, 1), (32, m.MLQMC_FP64, 1), (128, 5, 1), (128, 0, -1)):
+        with pytest.raises(m.MlqmcError) as e:
+            ctx.set_tuning(*bad)
+        assert e.value.code == m.MLQMC_EINVAL
+    import json
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps({"gfx950": [{"n_fine": 128, "prec": "fp64", "target_blocks": 8192}]}))
+    assert ctx.apply_tuning(str(p), arch="gfx950") == 1
+    assert ctx.apply_tuning(str(p), arch="gfx000") == 0
+    ctx.set_tuning(128, m.MLQMC_FP64, 0)
+
+
 def test_repeat_runs_bitwise_identical(ctx):
     Y = np.ascontiguousarray(_points(1024, 64, 2, 0, 6, range(40)))
     a, b = np.empty(40), np.empty(40)
