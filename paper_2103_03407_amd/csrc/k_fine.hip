@@ -379,32 +379,107 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
   const T c2 = (T)S.c2[b], beta = first ? T(0) : (T)S.beta[b], mu = (T)S.mu[b];
   const T alpha = first ? T(0) : (T)S.alpha[b];  // the previous step, not yet applied to t
   const T hm = (T)mass_scale(g.n);
+  const int n = g.n, tx = threadIdx.x, c = c0 + tx, ci = tx + 1;
+  // the two threads at the block's edges also load one halo column
+  const bool hl = (tx == 0), hr = (tx == NTC - 1);
+  const int ch = hl ? c0 - 1 : c0 + NTC;
+  const bool hok = (hl && c0 >= 2) || (hr && c0 + NTC <= n - 1);
+  // Inputs are requested one row step before they are used: the sources of
+  // the ring row p = z - c2 vn + beta p_prev (z, vn, p_prev at the column and
+  // the halo column) one row ahead of the ring, the stencil row's weights,
+  // M vn and t one row ahead of the stencil; vn and p_prev of a row are kept
+  // from its ring fill for its stencil step.
+  struct Src {
+    T z, v, p, zh, vh, ph;
+  };
+  struct Row {
+    T ww, we, ws, wn, m, tt;
+  };
+  auto fetch_src = [&](int j, Src& f) {
+    const bool rowok = (j >= 1 && j <= n - 1);
+    f.z = f.v = f.p = f.zh = f.vh = f.ph = T(0);
+    if (rowok && c >= 1) {
+      const int k = j * n + c;
+      f.z = zz[k];
+      f.v = vb[k];
+      if (!first) f.p = pb[k];
+    }
+    if (rowok && hok) {
+      const int k = j * n + ch;
+      f.zh = zz[k];
+      f.vh = vb[k];
+      if (!first) f.ph = pb[k];
+    }
+  };
+  auto store = [&](int j, const Src& f) {
+    T* row = ring[j & 3];
+    row[ci] = f.z - c2 * f.v + beta * f.p;
+    if (hl) row[0] = f.zh - c2 * f.vh + beta * f.ph;
+    if (hr) row[NTC + 1] = f.zh - c2 * f.vh + beta * f.ph;
+  };
+  auto fetch_row = [&](int j, Row& r) {
+    if (c >= 1 && j >= j0 && j < j1) {
+      const int k = j * n + c;
+      r.ww = wx[k];
+      r.we = wx[k + 1];
+      r.ws = wy[k];
+      r.wn = wy[k + n];
+      r.m = mb[k];
+      r.tt = tb[k];
+    }
+  };
   double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  march<T, NTC>(ring, g, c0, j0, j1, dir,
-                [&](int k) { return zz[k] - c2 * vb[k] + (first ? T(0) : beta * pb[k]); },
-                [&](int, int, int k, const T* rs, const T* rc, const T* rn, int ci) {
-                  T d;
-                  const T ap = ring_A(rs, rc, rn, ci, wx, wy, k, g.n, d);
-                  const T pc = rc[ci];
-                  const T m12 = ring_M12(rs, rc, rn, ci);
-                  const T qv = ap - mu * hm * m12;
-                  const int64_t o = b * g.P + k;
-                  pout[o] = pc;
-                  q[o] = qv;
-                  // t_k = t_{k-1} + alpha_{k-1} p_{k-1}, the iterate this step starts from
-                  T tn = tb[k];
-                  if (!first) {
-                    tn += alpha * pb[k];
-                    tb[k] = tn;
-                  }
-                  const double tk = (double)tn;
-                  s[0] += (double)pc * (double)qv;
-                  s[1] += (double)vb[k] * (double)qv;
-                  s[2] += (double)pc * (double)mb[k];
-                  s[3] += (double)pc * (double)m12;
-                  s[4] += tk * (double)m12;
-                  s[5] += tk * (double)qv;
-                });
+  const int jf = dir > 0 ? j0 : j1 - 1;
+  const int count = j1 - j0;
+  Src f, fn;
+  fetch_src(jf - dir, f);
+  store(jf - dir, f);
+  fetch_src(jf, f);
+  store(jf, f);
+  T sv = f.v, sp = f.p;  // vn and p_prev of the row the next stencil step handles
+  fetch_src(jf + dir, fn);
+  Row rw;
+  fetch_row(jf, rw);
+  for (int i = 0; i < count; ++i) {
+    const int j = jf + i * dir;
+    store(j + dir, fn);
+    const T nv = fn.v, np = fn.p;
+    const Row rc = rw;
+    if (i + 1 < count) {
+      fetch_src(j + 2 * dir, fn);
+      fetch_row(j + dir, rw);
+    }
+    __syncthreads();
+    if (c >= 1) {
+      const T* xs = ring[(j - 1) & 3];
+      const T* xc = ring[j & 3];
+      const T* xn = ring[(j + 1) & 3];
+      const T pc = xc[ci];
+      const T ap = rc.ww * (pc - xc[ci - 1]) + rc.we * (pc - xc[ci + 1]) + rc.ws * (pc - xs[ci]) +
+                   rc.wn * (pc - xn[ci]);
+      const T m12 = T(6) * pc + xc[ci - 1] + xc[ci + 1] + xs[ci] + xn[ci] + xn[ci + 1] +
+                    xs[ci - 1];
+      const T qv = ap - mu * hm * m12;
+      const int64_t o = b * g.P + j * n + c;
+      pout[o] = pc;
+      q[o] = qv;
+      // t_k = t_{k-1} + alpha_{k-1} p_{k-1}, the iterate this step starts from
+      T tn = rc.tt;
+      if (!first) {
+        tn += alpha * sp;
+        t[o] = tn;
+      }
+      const double tk = (double)tn;
+      s[0] += (double)pc * (double)qv;
+      s[1] += (double)sv * (double)qv;
+      s[2] += (double)pc * (double)rc.m;
+      s[3] += (double)pc * (double)m12;
+      s[4] += tk * (double)m12;
+      s[5] += tk * (double)qv;
+    }
+    sv = nv;
+    sp = np;
+  }
   write_partials_m<NTC, 6>(s, part, b, blk, g.nblk);
 }
 
