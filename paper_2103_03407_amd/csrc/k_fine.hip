@@ -163,34 +163,84 @@ __device__ __forceinline__ bool map_march(const MGeo& g, int64_t& b, int& c0, in
   return true;
 }
 
-// ring row j holds src at columns c0-1 .. c0+NTC of row j (0 outside the interior)
-template <typename T, int NTC, class Src>
-__device__ __forceinline__ void ring_fill(T (*ring)[NTC + 2], const MGeo& g, int c0, int j,
-                                          Src& src) {
-  const int t = threadIdx.x, c = c0 + t, n = g.n;
-  T* row = ring[j & 3];
-  const bool rowok = (j >= 1 && j <= n - 1);
-  row[t + 1] = (rowok && c >= 1) ? src(j * n + c) : T(0);
-  if (t == 0) row[0] = (rowok && c0 >= 2) ? src(j * n + c0 - 1) : T(0);
-  if (t == NTC - 1) row[NTC + 1] = (rowok && c0 + NTC <= n - 1) ? src(j * n + c0 + NTC) : T(0);
+// March a block of NTC threads (columns c0 .. c0+NTC-1) through the rows
+// [j0, j1) of a strip, upwards (dir = 1) or downwards, with a ring of 4 rows
+// in LDS holding the stencil's source field (with one halo column each side)
+// and one barrier per row.  Every global input is requested one row step
+// before use: fetch(k) loads the raw sources of ring position k, value(f)
+// turns them into the ring entry (0 outside the interior); fetch_row(k) loads
+// the stencil row's own inputs; body(j, k, rs, rc, rn, ci, row inputs, ring
+// sources of (j, c)) with south, centre and north ring rows.
+template <typename T, int NTC, class Fetch, class Value, class FetchRow, class Body>
+__device__ __forceinline__ void march_pf(T (*ring)[NTC + 2], const MGeo& g, int c0, int j0,
+                                         int j1, int dir, Fetch fetch, Value value,
+                                         FetchRow fetch_row, Body body) {
+  using F = decltype(fetch(0));
+  using R = decltype(fetch_row(0));
+  const int n = g.n, tx = threadIdx.x, c = c0 + tx, ci = tx + 1;
+  const bool hl = (tx == 0), hr = (tx == NTC - 1);
+  const int ch = hl ? c0 - 1 : c0 + NTC;
+  const bool hok = (hl && c0 >= 2) || (hr && c0 + NTC <= n - 1);
+  struct Src {
+    F f, h;
+    bool ok, hk;
+  };
+  auto fsrc = [&](int j, Src& s) {
+    const bool rowok = (j >= 1 && j <= n - 1);
+    s.ok = rowok && c >= 1;
+    s.hk = rowok && hok;
+    if (s.ok) s.f = fetch(j * n + c);
+    if (s.hk) s.h = fetch(j * n + ch);
+  };
+  auto store = [&](int j, const Src& s) {
+    T* row = ring[j & 3];
+    row[ci] = s.ok ? value(s.f) : T(0);
+    if (hl) row[0] = s.hk ? value(s.h) : T(0);
+    if (hr) row[NTC + 1] = s.hk ? value(s.h) : T(0);
+  };
+  auto frow = [&](int j, R& r) {
+    if (c >= 1 && j >= j0 && j < j1) r = fetch_row(j * n + c);
+  };
+  const int jf = dir > 0 ? j0 : j1 - 1;
+  const int count = j1 - j0;
+  Src s, sn;
+  fsrc(jf - dir, s);
+  store(jf - dir, s);
+  fsrc(jf, s);
+  store(jf, s);
+  F cur = s.f;  // ring sources of the row the next stencil step handles
+  fsrc(jf + dir, sn);
+  R rw;
+  frow(jf, rw);
+  for (int i = 0; i < count; ++i) {
+    const int j = jf + i * dir;
+    store(j + dir, sn);
+    const F nxt = sn.f;
+    const R rc = rw;
+    if (i + 1 < count) {
+      fsrc(j + 2 * dir, sn);
+      frow(j + dir, rw);
+    }
+    __syncthreads();
+    if (c >= 1) body(j, j * n + c, ring[(j - 1) & 3], ring[j & 3], ring[(j + 1) & 3], ci, rc, cur);
+    cur = nxt;
+  }
 }
 
-// body(j, c, k, south row, centre row, north row, index of column c in the rows);
-// rows j0 .. j1-1 upwards (dir = 1) or downwards (dir = -1)
-template <typename T, int NTC, class Src, class Body>
-__device__ __forceinline__ void march(T (*ring)[NTC + 2], const MGeo& g, int c0, int j0, int j1,
-                                      int dir, Src src, Body body) {
-  const int c = c0 + threadIdx.x, ci = threadIdx.x + 1;
-  const int first = dir > 0 ? j0 : j1 - 1;
-  const int count = j1 - j0;
-  ring_fill<T, NTC>(ring, g, c0, first - dir, src);
-  ring_fill<T, NTC>(ring, g, c0, first, src);
-  for (int i = 0; i < count; ++i) {
-    const int j = first + i * dir;
-    ring_fill<T, NTC>(ring, g, c0, j + dir, src);
-    __syncthreads();
-    if (c >= 1) body(j, c, j * g.n + c, ring[(j - 1) & 3], ring[j & 3], ring[(j + 1) & 3], ci);
-  }
+// the four edge weights of node k
+template <typename W>
+struct Wts {
+  W ww, we, ws, wn;
+};
+template <typename W>
+__device__ __forceinline__ Wts<W> load_wts(const W* wx, const W* wy, int k, int n) {
+  return Wts<W>{wx[k], wx[k + 1], wy[k], wy[k + n]};
+}
+template <typename T, typename W>
+__device__ __forceinline__ T ring_Aw(const T* rs, const T* rc, const T* rn, int ci, const Wts<W>& w) {
+  const T c = rc[ci];
+  return (T)w.ww * (c - rc[ci - 1]) + (T)w.we * (c - rc[ci + 1]) + (T)w.ws * (c - rs[ci]) +
+         (T)w.wn * (c - rn[ci]);
 }
 
 template <int NTC, int K>
@@ -203,16 +253,6 @@ __device__ __forceinline__ void write_partials_m(double (&s)[K], double* part, i
 #pragma unroll
     for (int k = 0; k < K; ++k) part[base + k] = s[k];
   }
-}
-
-// A applied at column ci of the centre row from ring rows, weights at k
-template <typename T, typename W>
-__device__ __forceinline__ T ring_A(const T* rs, const T* rc, const T* rn, int ci, const W* wx,
-                                    const W* wy, int k, int n, T& d) {
-  const T c = rc[ci];
-  const T ww = (T)wx[k], we = (T)wx[k + 1], ws = (T)wy[k], wn = (T)wy[k + n];
-  d = ww + we + ws + wn;
-  return ww * (c - rc[ci - 1]) + we * (c - rc[ci + 1]) + ws * (c - rs[ci]) + wn * (c - rn[ci]);
 }
 
 template <typename T>
@@ -247,15 +287,39 @@ __global__ __launch_bounds__(256) void k_zero_boundary(int n, int64_t B, int per
 }
 
 // interior-layout coarse field (mesh nH) -> padded fine field (mesh n), P1 interpolation
+// P1 interpolation from the interior-layout coarse field at fine node (i, j)
+// for a power-of-two ratio 2^lr: barycentric on the coarse "/" triangle
+// holding the node (the same arithmetic as interp_coarse; 1/r is exact)
+__device__ __forceinline__ double interp_pow2(const double* __restrict__ uH, int nH, int lr,
+                                              double inv_r, int i, int j) {
+  const int mH = nH - 1, r = 1 << lr;
+  const int I = i >> lr, J = j >> lr, li = i & (r - 1), lj = j & (r - 1);
+  auto U = [&](int a, int b) -> double {
+    return (a >= 1 && a <= mH && b >= 1 && b <= mH) ? uH[(b - 1) * mH + (a - 1)] : 0.0;
+  };
+  const double xi = li * inv_r, eta = lj * inv_r;
+  const double u00 = U(I, J), u11 = U(I + 1, J + 1);
+  if (lj <= li) {  // lower triangle (I,J),(I+1,J),(I+1,J+1)
+    const double u10 = U(I + 1, J);
+    return u00 + xi * (u10 - u00) + eta * (u11 - u10);
+  }
+  const double u01 = U(I, J + 1);  // upper triangle (I,J),(I+1,J+1),(I,J+1)
+  return u00 + eta * (u01 - u00) + xi * (u11 - u01);
+}
+
 __global__ __launch_bounds__(NT) void k_prolong(Geo g, int nH, const double* __restrict__ uH,
                                                 double* __restrict__ uh) {
   int64_t b;
   int blk;
   if (!map_block(g, b, blk)) return;
   const int mH = nH - 1;
+  int lr = 0;
+  while ((nH << lr) < g.n) ++lr;
+  const double inv_r = 1.0 / (double)(1 << lr);
+  const double* ub = uH + b * (int64_t)(mH * mH);
   FOR_NODES(g, blk) {
     const int i = k & (g.n - 1), j = k >> g.lg;
-    uh[b * g.P + k] = interp_coarse(uH + b * (int64_t)(mH * mH), nH, g.n / nH, i, j);
+    uh[b * g.P + k] = interp_pow2(ub, nH, lr, inv_r, i, j);
   }
 }
 
@@ -310,14 +374,15 @@ __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, const double* __rest
   const double* wx = w + b * 2 * g.P;
   const double* wy = wx + g.P;
   double s[2] = {0.0, 0.0};
-  march<double, NTC>(ring, g, c0, j0, j1, dir, [&](int k) { return vb[k]; },
-                     [&](int, int, int k, const double* rs, const double* rc, const double* rn,
-                         int ci) {
-                       double d;
-                       const double av = ring_A(rs, rc, rn, ci, wx, wy, k, g.n, d);
-                       s[0] += rc[ci] * ring_M12(rs, rc, rn, ci);
-                       s[1] += rc[ci] * av;
-                     });
+  march_pf<double, NTC>(
+      ring, g, c0, j0, j1, dir, [&](int k) { return vb[k]; }, [](double f) { return f; },
+      [&](int k) { return load_wts(wx, wy, k, g.n); },
+      [&](int, int, const double* rs, const double* rc, const double* rn, int ci,
+          const Wts<double>& wt, double) {
+        const double av = ring_Aw(rs, rc, rn, ci, wt);
+        s[0] += rc[ci] * ring_M12(rs, rc, rn, ci);
+        s[1] += rc[ci] * av;
+      });
   write_partials_m<NTC, 2>(s, part, b, blk, g.nblk);
 }
 
@@ -335,11 +400,12 @@ __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, const double* __restr
   const double* wx = w64 + b * 2 * g.P;
   const double* wy = wx + g.P;
   const double vs = S.vs[b], rho = S.rho[b], hm = mass_scale(g.n);
-  march<double, NTC>(ring, g, c0, j0, j1, dir, [&](int k) { return vb[k]; },
-                     [&](int, int, int k, const double* rs, const double* rc, const double* rn,
-                         int ci) {
-                       double d;
-                       const double av = ring_A(rs, rc, rn, ci, wx, wy, k, g.n, d);
+  march_pf<double, NTC>(
+      ring, g, c0, j0, j1, dir, [&](int k) { return vb[k]; }, [](double f) { return f; },
+      [&](int k) { return load_wts(wx, wy, k, g.n); },
+      [&](int, int k, const double* rs, const double* rc, const double* rn, int ci,
+          const Wts<double>& wt, double) {
+                       const double av = ring_Aw(rs, rc, rn, ci, wt);
                        const double mv = hm * ring_M12(rs, rc, rn, ci);
                        const double rv = -vs * (av - rho * mv);
                        const T rT = (T)rv;
@@ -860,15 +926,20 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, const double* __rest
   const double* wx = w + b * 2 * g.P;
   const double* wy = wx + g.P;
   double s[2] = {0.0, 0.0};
-  march<double, NTC>(ring, g, c0, j0, j1, dir,
-                     [&](int k) { return vs * vb[k] + (double)(T)(tb[k] + al * pl[k]); },
-                     [&](int, int, int k, const double* rs, const double* rc, const double* rn,
-                         int ci) {
-                       double d;
-                       const double aw = ring_A(rs, rc, rn, ci, wx, wy, k, g.n, d);
-                       s[0] += rc[ci] * aw;
-                       s[1] += rc[ci] * ring_M12(rs, rc, rn, ci);
-                     });
+  struct Fin {
+    double v;
+    T t, p;
+  };
+  march_pf<double, NTC>(
+      ring, g, c0, j0, j1, dir, [&](int k) { return Fin{vb[k], tb[k], pl[k]}; },
+      [&](const Fin& f) { return vs * f.v + (double)(T)(f.t + al * f.p); },
+      [&](int k) { return load_wts(wx, wy, k, g.n); },
+      [&](int, int, const double* rs, const double* rc, const double* rn, int ci,
+          const Wts<double>& wt, const Fin&) {
+        const double aw = ring_Aw(rs, rc, rn, ci, wt);
+        s[0] += rc[ci] * aw;
+        s[1] += rc[ci] * ring_M12(rs, rc, rn, ci);
+      });
   write_partials_m<NTC, 2>(s, part, b, blk, g.nblk);
 }
 
