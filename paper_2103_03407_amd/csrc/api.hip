@@ -312,14 +312,14 @@ mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
 
 // Samples per warm-start chain of the eigensolve on mesh N: as short as keeps
 // every workgroup slot of the device busy (one chain per workgroup).
-int default_chain(int64_t n, int warm, int chain_len, int N) {
+int default_chain(int64_t n, int warm, int chain_len, int N, int mixed) {
   if (!warm) return 1;
   if (chain_len > 0) return chain_len;
-  static std::map<int, int> slots;  // mesh -> chains in flight on this device type
-  auto it = slots.find(N);
+  static std::map<std::pair<int, int>, int> slots;  // (mesh, precision) -> chains in flight
+  auto it = slots.find({N, mixed});
   if (it == slots.end()) {
-    const int c = rqi_chains_in_flight(N);
-    it = slots.emplace(N, c > 0 ? c : 512).first;
+    const int c = rqi_chains_in_flight(N, mixed);
+    it = slots.emplace(std::make_pair(N, mixed), c > 0 ? c : 512).first;
   }
   const int64_t target = it->second;
   const int64_t c = (n + target - 1) / target;
@@ -659,6 +659,7 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
     a.n = n;
     a.lin_rtol = lin_tol(o);
     a.lam_rtol = lam_tol(o);
+    a.mixed = o->prec == MLQMC_MIXED ? 1 : 0;
     a.max_lin = o->max_lin_iter;
     a.lam = lam;
     a.lin_iters = lin_iters;
@@ -679,7 +680,9 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   if (n == 0) return MLQMC_OK;
   CK(hipMemsetAsync(flags, 0, n, st), "memset");
   CK(hipMemsetAsync(lin_iters, 0, n * sizeof(int), st), "memset");
-  const int chain = default_chain(n, warm, o->chain_len, L->n_coarse ? L->n_coarse : L->n_fine);
+  const int mixed = o->prec == MLQMC_MIXED ? 1 : 0;
+  const int chain =
+      default_chain(n, warm, o->chain_len, L->n_coarse ? L->n_coarse : L->n_fine, mixed);
   RqiArgs a{};
   a.Y = Y;
   a.ldY = ldY;
@@ -694,6 +697,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   a.rq_iters = rq_iters;
   a.lin_iters = lin_iters;
   a.flags = flags;
+  a.mixed = mixed;
   if (L->n_coarse == 0) {
     Table* tb = nullptr;
     CS(ctx->table(L->n_fine, L->s_fine, &tb));
@@ -1082,7 +1086,8 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
     CK(launch_lattice_multi(N[l], s, R, dz, dsh, N[l], Y, std::max(s, 1), st), "lattice");
     mlqmc_opts oo = *o;
     // chains never cross a shift: chain length divides N_l
-    int chain = default_chain(N[l] * R, 1, o->chain_len, L.n_coarse ? L.n_coarse : L.n_fine);
+    int chain = default_chain(N[l] * R, 1, o->chain_len, L.n_coarse ? L.n_coarse : L.n_fine,
+                              o->prec == MLQMC_MIXED ? 1 : 0);
     int c2 = 1;
     while (c2 < chain) c2 *= 2;
     oo.chain_len = (int)std::min<int64_t>(c2, N[l]);

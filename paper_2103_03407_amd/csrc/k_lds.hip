@@ -17,18 +17,18 @@ constexpr int threads_for() {
 }
 
 // v = sin(pi x1) sin(pi x2) at the interior nodes
-template <int NT, int n>
-__device__ __forceinline__ void init_sine(double* v) {
+template <int NT, int n, typename T>
+__device__ __forceinline__ void init_sine(T* v) {
   LDS_FOR_NODES(NT, n, k) {
     const int i = k & (n - 1), j = k >> lds::Mesh<n>::lg;
-    v[k] = sinpi(double(i) / n) * sinpi(double(j) / n);
+    v[k] = (T)(sinpi(double(i) / n) * sinpi(double(j) / n));
   }
   __syncthreads();
 }
 
 // M-overlap of the M-normalised v with the normalised sine mode
-template <int NT, int n>
-__device__ __forceinline__ double sine_overlap(const double* v, double* red) {
+template <int NT, int n, typename T>
+__device__ __forceinline__ double sine_overlap(const T* v, double* red) {
   constexpr int m = n - 1;
   double s[2] = {0.0, 0.0};
   LDS_FOR_NODES(NT, n, k) {
@@ -40,7 +40,7 @@ __device__ __forceinline__ double sine_overlap(const double* v, double* red) {
     const double p0 = ph(i, j);
     const double mp = 6.0 * p0 + ph(i - 1, j) + ph(i + 1, j) + ph(i, j - 1) + ph(i, j + 1) +
                       ph(i + 1, j + 1) + ph(i - 1, j - 1);
-    s[0] += v[k] * mp;
+    s[0] += (double)v[k] * mp;
     s[1] += p0 * mp;
   }
   block_sums<NT, 2>(s, red);
@@ -50,11 +50,12 @@ __device__ __forceinline__ double sine_overlap(const double* v, double* red) {
 
 // The chain of samples [blockIdx.x * chain_len, ...) on mesh N: arrays in `a`
 // (zero padding), the staged point in s_y.
-template <int N, int NT>
-__device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays& a, double* s_y) {
+template <int N, int NT, typename T, class WF>
+__device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* s_y,
+                          const WF& wf) {
   using Mh = lds::Mesh<N>;
   constexpr int m = N - 1;
-  double* const s_v = a.v;
+  T* const s_v = a.v;
   const int64_t i0 = (int64_t)blockIdx.x * A.chain_len;
   const int64_t i1 = (i0 + A.chain_len < A.n) ? i0 + A.chain_len : A.n;
   bool have_prev = false;
@@ -66,7 +67,7 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays& a, double* s_y
     if (!(A.warm && have_prev)) init_sine<NT, N>(s_v);
 
     double vMv, vAv;
-    lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);
+    lds::rayleigh_parts<NT, N>(a, s_v, wf, vMv, vAv);
     lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
     double sigma = vAv / vMv;  // sigma_0 = A(t_k; v0, v0) for the M-normalised start
 
@@ -79,7 +80,7 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays& a, double* s_y
       lin += lds::jd_pcg<NT, N>(a, sigma, sigma, A.lin_rtol, A.max_lin, &c, &b);
       LDS_FOR_NODES(NT, N, k) s_v[k] += a.t[k];
       __syncthreads();
-      lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);
+      lds::rayleigh_parts<NT, N>(a, s_v, wf, vMv, vAv);
       lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
       const double sig_new = vAv / vMv;
       const bool done = fabs(sig_new - sigma) <= A.eig_rtol * fabs(sig_new);
@@ -103,7 +104,7 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays& a, double* s_y
     if (A.u_out) {  // interior layout, node (i, j) at (j - 1) m + i - 1
       LDS_FOR_NODES(NT, N, k) {
         const int ii = k & (N - 1), jj = k >> Mh::lg;
-        A.u_out[i * Mh::D + (jj - 1) * m + ii - 1] = s_v[k];
+        A.u_out[i * Mh::D + (jj - 1) * m + ii - 1] = (double)s_v[k];
       }
     }
     have_prev = (fl == 0);
@@ -112,17 +113,19 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays& a, double* s_y
 }
 
 // Every array in LDS (meshes up to 1/32).  The five vectors' padding is
-// zeroed once; the solvers write interior positions only.
-template <int N, int NT>
-__global__ __launch_bounds__(NT, N >= 32 ? 2 : 4) void k_rqi(RqiArgs A) {
+// zeroed once; the solvers write interior positions only.  T = float keeps
+// vectors, weights and V-cycle in FP32 (mixed precision); the Rayleigh
+// quotients then use FP64 weights recomputed from the edge table.
+template <int N, int NT, typename T>
+__global__ __launch_bounds__(NT, (N >= 32 && sizeof(T) == 8) ? 2 : 4) void k_rqi(RqiArgs A) {
   using Mh = lds::Mesh<N>;
   constexpr int P = Mh::P;
-  __shared__ double s_w[Mh::EW];
-  __shared__ double s_vec[5 * P];
-  __shared__ double s_mg[lds::mg_scratch<N>() + 1];
+  __shared__ T s_w[Mh::EW];
+  __shared__ T s_vec[5 * P];
+  __shared__ T s_mg[lds::mg_scratch<N>() + 1];
   __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
-  lds::PcgArrays a;
+  lds::PcgArrays<T> a;
   a.wx = s_w;
   a.wy = s_w + P;
   a.v = s_vec;
@@ -136,7 +139,11 @@ __global__ __launch_bounds__(NT, N >= 32 ? 2 : 4) void k_rqi(RqiArgs A) {
   a.xtmp = nullptr;
   lds::zero<NT>(s_vec, 5 * P);
   __syncthreads();
-  rqi_chain<N, NT>(A, a, s_y);
+  if constexpr (sizeof(T) == 8) {
+    rqi_chain<N, NT>(A, a, s_y, lds::WeightsFromArrays<N>{s_w, s_w + P});
+  } else {
+    rqi_chain<N, NT>(A, a, s_y, lds::WeightsFromTable<N>{A.phi, s_y, A.S, A.a0});
+  }
 }
 
 // Meshes whose vectors exceed LDS (1/64): the top-level weights, the five
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(NT) void k_rqi_global(RqiArgs A) {
   __shared__ double s_y[kMaxStagedS];
   double* g = A.scratch + (int64_t)blockIdx.x * rqi_global_doubles<N>();
   double* vec = g + Mh::EW;
-  lds::PcgArrays a;
+  lds::PcgArrays<double> a;
   a.wx = g;
   a.wy = g + P;
   a.v = vec;
@@ -170,19 +177,20 @@ __global__ __launch_bounds__(NT) void k_rqi_global(RqiArgs A) {
   a.red = s_red;
   lds::zero<NT>(vec, 6 * P);
   __syncthreads();
-  rqi_chain<N, NT>(A, a, s_y);
+  rqi_chain<N, NT>(A, a, s_y, lds::WeightsFromArrays<N>{g, g + P});
 }
 
-template <int N, int NT>
-__global__ __launch_bounds__(NT, N >= 32 ? 2 : 4) void k_tg_small(TgSmallArgs A) {
+template <int N, int NT, typename T>
+__global__ __launch_bounds__(NT, (N >= 32 && sizeof(T) == 8) ? 2 : 4) void k_tg_small(
+    TgSmallArgs A) {
   using Mh = lds::Mesh<N>;
   constexpr int P = Mh::P;
-  __shared__ double s_w[Mh::EW];
-  __shared__ double s_vec[5 * P];
-  __shared__ double s_mg[lds::mg_scratch<N>() + 1];
+  __shared__ T s_w[Mh::EW];
+  __shared__ T s_vec[5 * P];
+  __shared__ T s_mg[lds::mg_scratch<N>() + 1];
   __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
-  lds::PcgArrays a;
+  lds::PcgArrays<T> a;
   a.wx = s_w;
   a.wy = s_w + P;
   a.v = s_vec;
@@ -194,7 +202,7 @@ __global__ __launch_bounds__(NT, N >= 32 ? 2 : 4) void k_tg_small(TgSmallArgs A)
   a.mg = s_mg;
   a.red = s_red;
   a.xtmp = nullptr;
-  double* const s_v = a.v;
+  T* const s_v = a.v;
   const int64_t i = blockIdx.x;
   lds::zero<NT>(s_vec, 5 * P);
   for (int j = threadIdx.x; j < A.s; j += NT) s_y[j] = A.Y[i * A.ldY + j];
@@ -205,29 +213,36 @@ __global__ __launch_bounds__(NT, N >= 32 ? 2 : 4) void k_tg_small(TgSmallArgs A)
   const double* uH = A.uH + i * (int64_t)(mH * mH);
   LDS_FOR_NODES(NT, N, k) {
     const int ii = k & (N - 1), jj = k >> Mh::lg;
-    s_v[k] = interp_coarse(uH, A.nH, ratio, ii, jj);
+    s_v[k] = (T)interp_coarse(uH, A.nH, ratio, ii, jj);
   }
   __syncthreads();
-  double vMv, vAv;
-  lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);
-  lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
-  const double rho = vAv / vMv;
-  const double mu = A.lamH[i];
-  bool c, b;
-  const int its = lds::jd_pcg<NT, N, true>(a, mu, rho, A.lin_rtol, A.max_lin, &c, &b, A.lam_rtol);
-  LDS_FOR_NODES(NT, N, k) s_v[k] += a.t[k];
-  __syncthreads();
-  lds::rayleigh_parts<NT, N>(a, s_v, vMv, vAv);
-  const double lam = vAv / vMv;
-  if (threadIdx.x == 0) {
-    A.lam[i] = lam;
-    if (A.lin_iters) A.lin_iters[i] += its;
-    uint8_t fl = 0;
-    if (!c) fl |= MLQMC_FLAG_LIN_NOCONV;
-    if (b) fl |= MLQMC_FLAG_BREAKDOWN;
-    if (!isfinite(lam)) fl |= MLQMC_FLAG_NONFINITE;
-    A.flags[i] |= fl;
-  }
+  auto run = [&](const auto& wf) {
+    double vMv, vAv;
+    lds::rayleigh_parts<NT, N>(a, s_v, wf, vMv, vAv);
+    lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
+    const double rho = vAv / vMv;
+    const double mu = A.lamH[i];
+    bool c, b;
+    const int its =
+        lds::jd_pcg<NT, N, true>(a, mu, rho, A.lin_rtol, A.max_lin, &c, &b, A.lam_rtol);
+    LDS_FOR_NODES(NT, N, k) s_v[k] += a.t[k];
+    __syncthreads();
+    lds::rayleigh_parts<NT, N>(a, s_v, wf, vMv, vAv);
+    const double lam = vAv / vMv;
+    if (threadIdx.x == 0) {
+      A.lam[i] = lam;
+      if (A.lin_iters) A.lin_iters[i] += its;
+      uint8_t fl = 0;
+      if (!c) fl |= MLQMC_FLAG_LIN_NOCONV;
+      if (b) fl |= MLQMC_FLAG_BREAKDOWN;
+      if (!isfinite(lam)) fl |= MLQMC_FLAG_NONFINITE;
+      A.flags[i] |= fl;
+    }
+  };
+  if constexpr (sizeof(T) == 8)
+    run(lds::WeightsFromArrays<N>{s_w, s_w + P});
+  else
+    run(lds::WeightsFromTable<N>{A.phi, s_y, A.s, A.a0});
 }
 
 // The V-cycle below the batched levels: one workgroup per sample reads its
@@ -241,22 +256,22 @@ __global__ __launch_bounds__(NT) void k_bottom(const T* __restrict__ w, const T*
   constexpr int P = Mh::P, PG = (N + 2) * N;
   const int64_t b = blockIdx.x;
   if (active && !active[b]) return;
-  __shared__ double s_w[Mh::EW];
-  __shared__ double s_b[P], s_x[P];
-  __shared__ double s_mg[lds::mg_scratch<N>() + 1];
+  __shared__ T s_w[Mh::EW];
+  __shared__ T s_b[P], s_x[P];
+  __shared__ T s_mg[lds::mg_scratch<N>() + 1];
   const T* WX = w + b * 2 * PG;
   const T* WY = WX + PG;
   const T* rb = rhs + b * PG;
   for (int e = threadIdx.x; e < P; e += NT) {
-    s_w[e] = (double)WX[e];
-    s_w[P + e] = (double)WY[e];
-    s_b[e] = (double)rb[e];
-    s_x[e] = 0.0;
+    s_w[e] = WX[e];
+    s_w[P + e] = WY[e];
+    s_b[e] = rb[e];
+    s_x[e] = T(0);
   }
   __syncthreads();
   lds::coarsen_all<NT, N>(s_w, s_w + P, s_mg);
-  lds::vcycle<NT, N>(s_w, s_w + P, s_b, s_x, s_mg);
-  LDS_FOR_NODES(NT, N, k) X[b * PG + k] = (T)s_x[k];
+  lds::vcycle<NT, N, true, T>(s_w, s_w + P, s_b, s_x, s_mg);
+  LDS_FOR_NODES(NT, N, k) X[b * PG + k] = s_x[k];
 }
 
 template <int N>
@@ -265,7 +280,10 @@ hipError_t rqi_n(const RqiArgs& a, hipStream_t st) {
   if (chains <= 0) return hipSuccess;
   if constexpr (N <= 32) {
     constexpr int NT = threads_for<N>();
-    hipLaunchKernelGGL((k_rqi<N, NT>), dim3((unsigned)chains), dim3(NT), 0, st, a);
+    if (a.mixed)
+      hipLaunchKernelGGL((k_rqi<N, NT, float>), dim3((unsigned)chains), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_rqi<N, NT, double>), dim3((unsigned)chains), dim3(NT), 0, st, a);
   } else {
     // the caller provides chains x rqi_scratch_doubles(N) doubles of scratch
     if (!a.scratch || a.scratch_doubles < chains * rqi_global_doubles<N>())
@@ -279,7 +297,10 @@ template <int N>
 hipError_t tg_small_n(const TgSmallArgs& a, hipStream_t st) {
   constexpr int NT = threads_for<N>();
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_tg_small<N, NT>), dim3((unsigned)a.n), dim3(NT), 0, st, a);
+  if (a.mixed)
+    hipLaunchKernelGGL((k_tg_small<N, NT, float>), dim3((unsigned)a.n), dim3(NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_tg_small<N, NT, double>), dim3((unsigned)a.n), dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -309,24 +330,25 @@ hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st) {
 int64_t rqi_scratch_doubles(int N) { return N == 64 ? rqi_global_doubles<64>() : 0; }
 
 template <int N>
-hipError_t rqi_occupancy(int* per) {
+hipError_t rqi_occupancy(int* per, int mixed) {
   constexpr int NT = threads_for<N>();
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_rqi<N, NT>, NT, 0);
+  if (mixed) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_rqi<N, NT, float>, NT, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_rqi<N, NT, double>, NT, 0);
 }
 
 // Workgroups of the eigensolve on mesh N that the current device holds at
 // once (compute units x resident workgroups per unit); 0 if unknown.
-int rqi_chains_in_flight(int N) {
+int rqi_chains_in_flight(int N, int mixed) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   hipError_t e = hipErrorInvalidValue;
   switch (N) {
-    case 4: e = rqi_occupancy<4>(&per); break;
-    case 8: e = rqi_occupancy<8>(&per); break;
-    case 16: e = rqi_occupancy<16>(&per); break;
-    case 32: e = rqi_occupancy<32>(&per); break;
+    case 4: e = rqi_occupancy<4>(&per, mixed); break;
+    case 8: e = rqi_occupancy<8>(&per, mixed); break;
+    case 16: e = rqi_occupancy<16>(&per, mixed); break;
+    case 32: e = rqi_occupancy<32>(&per, mixed); break;
     case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rqi_global<64, 512>, 512, 0);
              break;
     default: break;

@@ -29,12 +29,13 @@ struct RqiArgs {
   uint8_t* flags;       // [n]
   double* scratch;      // meshes above 1/32: per-chain global scratch
   int64_t scratch_doubles;
+  int mixed;            // 1: FP32 vectors, weights and V-cycle (meshes up to 1/32)
 };
 hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st);
 // doubles of global scratch one chain needs on mesh N (0: all in LDS)
 int64_t rqi_scratch_doubles(int N);
 // workgroups of the eigensolve on mesh N resident on the current device at once
-int rqi_chains_in_flight(int N);
+int rqi_chains_in_flight(int N, int mixed);
 
 struct TgSmallArgs {
   const double* Y;      // [n x ldY], first s columns
@@ -48,6 +49,7 @@ struct TgSmallArgs {
   int64_t n;
   double lin_rtol;
   double lam_rtol;      // eigenvalue stopping test of the solve (0: residual test only)
+  int mixed;            // 1: FP32 vectors, weights and V-cycle
   int max_lin;
   double* lam;          // [n] two-grid value
   int* lin_iters;       // [n] added to, or nullptr

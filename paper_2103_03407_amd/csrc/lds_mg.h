@@ -23,7 +23,9 @@
 // WX[k] is the edge arriving at node k from the west, WY[k] from the south
 // (so the east and north edges of node k are WX[k + 1] and WY[k + n]), two
 // arrays of P(n) entries.  Loops run over the positions n .. n n - 1 and skip
-// column 0.
+// column 0.  T is the storage and arithmetic type of the vectors, weights and
+// V-cycle (double, or float in mixed precision); every dot product and every
+// Rayleigh quotient is accumulated in double, the quotients from FP64 weights.
 #pragma once
 
 #include "common.h"
@@ -47,25 +49,34 @@ struct Mesh {
     if ((k & ((n) - 1)) != 0)
 
 // (A x)_k with the diagonal in d
-template <int n>
-MLQMC_DEV double pA(const double* x, const double* wx, const double* wy, int k, double& d) {
-  const double ww = wx[k], we = wx[k + 1], ws = wy[k], wn = wy[k + n];
+template <int n, typename T>
+MLQMC_DEV T pA(const T* x, const T* wx, const T* wy, int k, T& d) {
+  const T ww = wx[k], we = wx[k + 1], ws = wy[k], wn = wy[k + n];
   d = ww + we + ws + wn;
-  const double xc = x[k];
+  const T xc = x[k];
   return ww * (xc - x[k - 1]) + we * (xc - x[k + 1]) + ws * (xc - x[k - n]) +
          wn * (xc - x[k + n]);
 }
-template <int n>
-MLQMC_DEV double pdiag(const double* wx, const double* wy, int k) {
+template <int n, typename T>
+MLQMC_DEV T pdiag(const T* wx, const T* wy, int k) {
   return wx[k] + wx[k + 1] + wy[k] + wy[k + n];
 }
 // (M x)_k without the h^2/12 factor
-template <int n>
-MLQMC_DEV double pM12(const double* x, int k) {
-  return 6.0 * x[k] + x[k - 1] + x[k + 1] + x[k - n] + x[k + n] + x[k + n + 1] + x[k - n - 1];
+template <int n, typename T>
+MLQMC_DEV T pM12(const T* x, int k) {
+  return T(6) * x[k] + x[k - 1] + x[k + 1] + x[k - n] + x[k + n] + x[k + n + 1] + x[k - n - 1];
 }
 
-// Doubles of the V-cycle levels strictly below mesh n: per level nc, the
+// the same in FP64 whatever T: with FP32 entries, (M x)_k rounded to FP32
+// would put a relative error of order 1e-8 into x^T M x and so into the
+// Rayleigh quotient
+template <int n, typename T>
+MLQMC_DEV double pM12d(const T* x, int k) {
+  return 6.0 * (double)x[k] + (double)x[k - 1] + (double)x[k + 1] + (double)x[k - n] +
+         (double)x[k + n] + (double)x[k + n + 1] + (double)x[k - n - 1];
+}
+
+// Entries of the V-cycle levels strictly below mesh n: per level nc, the
 // weights (2 P) and B, X (2 P).
 template <int n>
 constexpr int mg_scratch() {
@@ -74,29 +85,29 @@ constexpr int mg_scratch() {
   return s;
 }
 
-// zero `count` doubles
-template <int NT>
-MLQMC_DEV void zero(double* x, int count) {
-  for (int e = threadIdx.x; e < count; e += NT) x[e] = 0.0;
+// zero `count` entries
+template <int NT, typename T>
+MLQMC_DEV void zero(T* x, int count) {
+  for (int e = threadIdx.x; e < count; e += NT) x[e] = T(0);
 }
 
 // Weights of every level below n, each the mean of the two collinear fine
 // edges it covers; the B and X arrays of every level are zeroed.
-template <int NT, int n>
-MLQMC_DEV void coarsen_all(const double* wx, const double* wy, double* nxt) {
+template <int NT, int n, typename T>
+MLQMC_DEV void coarsen_all(const T* wx, const T* wy, T* nxt) {
   if constexpr (n > 2) {
     constexpr int nc = n / 2, Pc = Mesh<nc>::P;
-    double* wxc = nxt;
-    double* wyc = wxc + Pc;
+    T* wxc = nxt;
+    T* wyc = wxc + Pc;
     for (int e = threadIdx.x; e < Pc; e += NT) {
       const int J = e / nc, I = e % nc;
       const int Ie = (I == 0) ? nc : I, Je = (I == 0) ? J - 1 : J;
       wxc[e] = (Je >= 1 && Je <= nc - 1)
-                   ? 0.5 * (wx[2 * Je * n + 2 * Ie - 1] + wx[2 * Je * n + 2 * Ie])
-                   : 0.0;
+                   ? T(0.5) * (wx[2 * Je * n + 2 * Ie - 1] + wx[2 * Je * n + 2 * Ie])
+                   : T(0);
       wyc[e] = (J >= 1 && J <= nc && I >= 1)
-                   ? 0.5 * (wy[(2 * J - 1) * n + 2 * I] + wy[2 * J * n + 2 * I])
-                   : 0.0;
+                   ? T(0.5) * (wy[(2 * J - 1) * n + 2 * I] + wy[2 * J * n + 2 * I])
+                   : T(0);
     }
     zero<NT>(wyc + Pc, 2 * Pc);
     __syncthreads();
@@ -105,24 +116,24 @@ MLQMC_DEV void coarsen_all(const double* wx, const double* wy, double* nxt) {
 }
 
 // X = omega * B / diag  (first sweep from a zero start)
-template <int NT, int n>
-MLQMC_DEV void jacobi_first(const double* wx, const double* wy, const double* B, double* X) {
-  LDS_FOR_NODES(NT, n, k) X[k] = kOmega * B[k] / pdiag<n>(wx, wy, k);
+template <int NT, int n, typename T>
+MLQMC_DEV void jacobi_first(const T* wx, const T* wy, const T* B, T* X) {
+  LDS_FOR_NODES(NT, n, k) X[k] = T(kOmega) * B[k] / pdiag<n>(wx, wy, k);
   __syncthreads();
 }
 
 // X <- X + omega (B - A X) / diag, new values staged in registers
-template <int NT, int n>
-MLQMC_DEV void jacobi_sweep(const double* wx, const double* wy, const double* B, double* X) {
+template <int NT, int n, typename T>
+MLQMC_DEV void jacobi_sweep(const T* wx, const T* wy, const T* B, T* X) {
   constexpr int PT = (n * n - n + NT - 1) / NT;
-  double nv[PT];
+  T nv[PT];
 #pragma unroll
   for (int q = 0; q < PT; ++q) {
     const int k = n + (int)threadIdx.x + q * NT;
     if (k < n * n && (k & (n - 1)) != 0) {
-      double d;
-      const double ax = pA<n>(X, wx, wy, k, d);
-      nv[q] = X[k] + kOmega * (B[k] - ax) / d;
+      T d;
+      const T ax = pA<n>(X, wx, wy, k, d);
+      nv[q] = X[k] + T(kOmega) * (B[k] - ax) / d;
     }
   }
   __syncthreads();
@@ -136,13 +147,12 @@ MLQMC_DEV void jacobi_sweep(const double* wx, const double* wy, const double* B,
 
 // Xout = Xin + omega (B - A Xin) / diag (two distinct arrays; for top levels
 // too large for register staging)
-template <int NT, int n>
-MLQMC_DEV void jacobi_to(const double* wx, const double* wy, const double* B, const double* Xin,
-                         double* Xout) {
+template <int NT, int n, typename T>
+MLQMC_DEV void jacobi_to(const T* wx, const T* wy, const T* B, const T* Xin, T* Xout) {
   LDS_FOR_NODES(NT, n, k) {
-    double d;
-    const double ax = pA<n>(Xin, wx, wy, k, d);
-    Xout[k] = Xin[k] + kOmega * (B[k] - ax) / d;
+    T d;
+    const T ax = pA<n>(Xin, wx, wy, k, d);
+    Xout[k] = Xin[k] + T(kOmega) * (B[k] - ax) / d;
   }
   __syncthreads();
 }
@@ -150,31 +160,30 @@ MLQMC_DEV void jacobi_to(const double* wx, const double* wy, const double* B, co
 // Bc = P^T (B - A X): the residual at the seven fine nodes each coarse node's
 // hat function covers (weight 1 at the node, 1/2 at E, W, N, S, NE, SW, all
 // interior), formed on the fly, so no residual array is stored.
-template <int NT, int n>
-MLQMC_DEV void restrict_residual(const double* wx, const double* wy, const double* B,
-                                 const double* X, double* Bc) {
+template <int NT, int n, typename T>
+MLQMC_DEV void restrict_residual(const T* wx, const T* wy, const T* B, const T* X, T* Bc) {
   constexpr int nc = n / 2;
   auto res = [&](int k) {
-    double d;
+    T d;
     return B[k] - pA<n>(X, wx, wy, k, d);
   };
   LDS_FOR_NODES(NT, nc, kc) {
     const int I = kc & (nc - 1), J = kc >> Mesh<nc>::lg;
     const int f = 2 * J * n + 2 * I;
-    Bc[kc] = res(f) + 0.5 * (res(f - 1) + res(f + 1) + res(f - n) + res(f + n) +
-                             res(f + n + 1) + res(f - n - 1));
+    Bc[kc] = res(f) + T(0.5) * (res(f - 1) + res(f + 1) + res(f - n) + res(f + n) +
+                                res(f + n + 1) + res(f - n - 1));
   }
   __syncthreads();
 }
 
 // X += P Xc (2:1 P1 interpolation: the mean of the coarse values at
 // (i>>1, j>>1) and ((i+1)>>1, (j+1)>>1))
-template <int NT, int n>
-MLQMC_DEV void prolong_add(const double* Xc, double* X) {
+template <int NT, int n, typename T>
+MLQMC_DEV void prolong_add(const T* Xc, T* X) {
   constexpr int nc = n / 2;
   LDS_FOR_NODES(NT, n, k) {
     const int i = k & (n - 1), j = k >> Mesh<n>::lg;
-    X[k] += 0.5 * (Xc[(j >> 1) * nc + (i >> 1)] + Xc[((j + 1) >> 1) * nc + ((i + 1) >> 1)]);
+    X[k] += T(0.5) * (Xc[(j >> 1) * nc + (i >> 1)] + Xc[((j + 1) >> 1) * nc + ((i + 1) >> 1)]);
   }
   __syncthreads();
 }
@@ -182,18 +191,17 @@ MLQMC_DEV void prolong_add(const double* Xc, double* X) {
 // One V-cycle X = K^{-1} B on mesh n; `nxt` holds the coarser levels (weights
 // built by coarsen_all).  kStage: register-staged sweeps (false: the sweeps
 // alternate between X and Xtmp, for top levels in global scratch).
-template <int NT, int n, bool kStage = true>
-MLQMC_DEV void vcycle(const double* wx, const double* wy, const double* B, double* X,
-                      double* nxt, double* Xtmp = nullptr) {
+template <int NT, int n, bool kStage = true, typename T>
+MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtmp = nullptr) {
   if constexpr (n == 2) {
     if (threadIdx.x == 0) X[3] = B[3] / pdiag<2>(wx, wy, 3);
     __syncthreads();
   } else {
     constexpr int nc = n / 2, Pc = Mesh<nc>::P;
-    const double* wxc = nxt;
-    const double* wyc = wxc + Pc;
-    double* Bc = nxt + 2 * Pc;
-    double* Xc = Bc + Pc;
+    const T* wxc = nxt;
+    const T* wyc = wxc + Pc;
+    T* Bc = nxt + 2 * Pc;
+    T* Xc = Bc + Pc;
     if constexpr (kStage) {
       jacobi_first<NT, n>(wx, wy, B, X);
       jacobi_sweep<NT, n>(wx, wy, B, X);
@@ -202,7 +210,7 @@ MLQMC_DEV void vcycle(const double* wx, const double* wy, const double* B, doubl
       jacobi_to<NT, n>(wx, wy, B, Xtmp, X);
     }
     restrict_residual<NT, n>(wx, wy, B, X, Bc);
-    vcycle<NT, nc>(wxc, wyc, Bc, Xc, Xc + Pc);
+    vcycle<NT, nc, true, T>(wxc, wyc, Bc, Xc, Xc + Pc);
     prolong_add<NT, n>(Xc, X);
     if constexpr (kStage) {
       jacobi_sweep<NT, n>(wx, wy, B, X);
@@ -218,36 +226,73 @@ MLQMC_DEV void vcycle(const double* wx, const double* wy, const double* B, doubl
 // weights [WX | WY] and the multigrid scratch.  q may share z's storage (z is
 // dead between forming p and the next V-cycle); xtmp is only used when the
 // top level sweeps without register staging.
+template <typename T>
 struct PcgArrays {
-  double *wx, *wy, *v, *t, *r, *z, *p, *q, *mg, *red, *xtmp;
+  T *wx, *wy, *v, *t, *r, *z, *p, *q, *mg, *xtmp;
+  double* red;
 };
 
-// ||x||_M^2 and x^T A x in one pass (all threads get both)
-template <int NT, int n>
-MLQMC_DEV void rayleigh_parts(const PcgArrays& a, const double* x, double& xMx, double& xAx) {
+// The four FP64 edge weights of node k, from the arrays (double storage) or
+// recomputed from the padded edge table (float storage): w = a0 + sum_j y_j Phi[j]
+struct Wd {
+  double ww, we, ws, wn;
+};
+template <int n>
+struct WeightsFromArrays {
+  const double *wx, *wy;
+  MLQMC_DEV Wd operator()(int k) const { return Wd{wx[k], wx[k + 1], wy[k], wy[k + n]}; }
+};
+template <int n>
+struct WeightsFromTable {
+  const double* phi;  // rows of [WX | WY], (n + 2) n entries each
+  const double* ys;
+  int S;
+  double a0;
+  MLQMC_DEV Wd operator()(int k) const {
+    constexpr int PG = (n + 2) * n;
+    double a[4] = {a0, a0, a0, a0};
+    const int e[4] = {k, k + 1, PG + k, PG + k + n};
+    for (int j = 0; j < S; ++j) {
+      const double y = ys[j];
+      const double* row = phi + (int64_t)j * 2 * PG;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] += y * row[e[q]];
+    }
+    return Wd{a[0], a[1], a[2], a[3]};
+  }
+};
+
+// ||x||_M^2 and x^T A x in one pass in FP64 with FP64 weights from wf (all
+// threads get both)
+template <int NT, int n, typename T, class WF>
+MLQMC_DEV void rayleigh_parts(const PcgArrays<T>& a, const T* x, const WF& wf, double& xMx,
+                              double& xAx) {
   double s[2] = {0.0, 0.0};
   LDS_FOR_NODES(NT, n, k) {
-    double d;
-    s[0] += x[k] * pM12<n>(x, k);
-    s[1] += x[k] * pA<n>(x, a.wx, a.wy, k, d);
+    const Wd w = wf(k);
+    const double xc = (double)x[k];
+    const double ax = w.ww * (xc - (double)x[k - 1]) + w.we * (xc - (double)x[k + 1]) +
+                      w.ws * (xc - (double)x[k - n]) + w.wn * (xc - (double)x[k + n]);
+    s[0] += xc * pM12d<n>(x, k);
+    s[1] += xc * ax;
   }
   block_sums<NT, 2>(s, a.red);
   xMx = s[0] * mass_scale(n);
   xAx = s[1];
 }
 
-template <int NT, int n>
-MLQMC_DEV void scale_vec(double* x, double f) {
-  LDS_FOR_NODES(NT, n, k) x[k] *= f;
+template <int NT, int n, typename T>
+MLQMC_DEV void scale_vec(T* x, double f) {
+  LDS_FOR_NODES(NT, n, k) x[k] = (T)((double)x[k] * f);
   __syncthreads();
 }
 
-template <int NT, int n>
-MLQMC_DEV void precondition(const PcgArrays& a, const double* r, double* z) {
+template <int NT, int n, typename T>
+MLQMC_DEV void precondition(const PcgArrays<T>& a, const T* r, T* z) {
   if constexpr (n > 32)
-    vcycle<NT, n, false>(a.wx, a.wy, r, z, a.mg, a.xtmp);
+    vcycle<NT, n, false, T>(a.wx, a.wy, r, z, a.mg, a.xtmp);
   else
-    vcycle<NT, n>(a.wx, a.wy, r, z, a.mg);
+    vcycle<NT, n, true, T>(a.wx, a.wy, r, z, a.mg);
 }
 
 // Projected PCG for  P (A - mu M) P^T t = -(A v - rho M v), t = 0 initially.
@@ -259,36 +304,36 @@ MLQMC_DEV void precondition(const PcgArrays& a, const double* r, double* z) {
 // w = v + t, from the step's dot products, and the error estimated from the
 // tails of f (energy, factor c^2) and m (first order, factor c, scaled by
 // |lambda - mu|), c the observed residual contraction.
-template <int NT, int n, bool kTrack = false>
-MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int maxit,
+template <int NT, int n, bool kTrack = false, typename T>
+MLQMC_DEV int jd_pcg(const PcgArrays<T>& a, double mu, double rho, double rtol, int maxit,
                      bool* conv, bool* brk, double lam_tol = 0.0) {
   constexpr int K = kTrack ? 6 : 3;
-  const double hm = mass_scale(n);
-  double* const v = a.v;
-  double* const t = a.t;
-  double* const r = a.r;
-  double* const z = a.z;
-  double* const p = a.p;
-  double* const q = a.q;
+  const T hm = (T)mass_scale(n), muT = (T)mu;
+  T* const v = a.v;
+  T* const t = a.t;
+  T* const r = a.r;
+  T* const z = a.z;
+  T* const p = a.p;
+  T* const q = a.q;
   LDS_FOR_NODES(NT, n, k) {
-    double d;
-    const double av = pA<n>(v, a.wx, a.wy, k, d);
-    r[k] = -(av - rho * hm * pM12<n>(v, k));
-    t[k] = 0.0;
+    T d;
+    const T av = pA<n>(v, a.wx, a.wy, k, d);
+    r[k] = -(av - (T)rho * hm * pM12<n>(v, k));
+    t[k] = T(0);
   }
   __syncthreads();
   precondition<NT, n>(a, r, z);
   // rz = r.(P^T z) = r.z - (r.v)(Mv.z);  p = P^T z
   double s3[3] = {0.0, 0.0, 0.0};
   LDS_FOR_NODES(NT, n, k) {
-    s3[0] += r[k] * z[k];
-    s3[1] += hm * pM12<n>(v, k) * z[k];
-    s3[2] += r[k] * v[k];
+    s3[0] += (double)r[k] * (double)z[k];
+    s3[1] += (double)(hm * pM12<n>(v, k)) * (double)z[k];
+    s3[2] += (double)r[k] * (double)v[k];
   }
   block_sums<NT, 3>(s3, a.red);
   double rz = s3[0] - s3[2] * s3[1];
   const double rz0 = rz;
-  LDS_FOR_NODES(NT, n, k) p[k] = z[k] - s3[1] * v[k];
+  LDS_FOR_NODES(NT, n, k) p[k] = z[k] - (T)s3[1] * v[k];
   __syncthreads();
   *conv = false;
   *brk = false;
@@ -306,17 +351,18 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
 #pragma unroll
     for (int e = 0; e < K; ++e) s[e] = 0.0;
     LDS_FOR_NODES(NT, n, k) {
-      double d;
-      const double ap = pA<n>(p, a.wx, a.wy, k, d);
-      const double mp = hm * pM12<n>(p, k);
-      const double qv = ap - mu * mp;
-      s[0] += p[k] * qv;
-      s[1] += v[k] * qv;
-      s[2] += p[k] * hm * pM12<n>(v, k);
+      T d;
+      const T ap = pA<n>(p, a.wx, a.wy, k, d);
+      const T mp = hm * pM12<n>(p, k);
+      const T qv = ap - muT * mp;
+      const double pk = (double)p[k], qd = (double)qv;
+      s[0] += pk * qd;
+      s[1] += (double)v[k] * qd;
+      s[2] += pk * (double)(hm * pM12<n>(v, k));
       if constexpr (kTrack) {
-        s[3] += p[k] * mp;
-        s[4] += t[k] * mp;
-        s[5] += t[k] * qv;
+        s[3] += pk * (double)mp;
+        s[4] += (double)t[k] * (double)mp;
+        s[5] += (double)t[k] * qd;
       }
       q[k] = qv;  // may overwrite z, which is dead here
     }
@@ -342,9 +388,10 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
       mm = m1;
       dmp = dm;
     }
+    const T aT = (T)alpha, cT = (T)c;
     LDS_FOR_NODES(NT, n, k) {
-      t[k] += alpha * p[k];
-      r[k] -= alpha * (q[k] - c * hm * pM12<n>(v, k));
+      t[k] += aT * p[k];
+      r[k] -= aT * (q[k] - cT * hm * pM12<n>(v, k));
     }
     __syncthreads();
     if (lam_done) {
@@ -354,9 +401,10 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
     precondition<NT, n>(a, r, z);
     double u[3] = {0.0, 0.0, 0.0};
     LDS_FOR_NODES(NT, n, k) {
-      u[0] += r[k] * z[k];
-      u[1] += hm * pM12<n>(v, k) * z[k];
-      u[2] += r[k] * v[k];
+      const double zk = (double)z[k];
+      u[0] += (double)r[k] * zk;
+      u[1] += (double)(hm * pM12<n>(v, k)) * zk;
+      u[2] += (double)r[k] * (double)v[k];
     }
     block_sums<NT, 3>(u, a.red);
     const double rzn = u[0] - u[2] * u[1];
@@ -367,7 +415,8 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
     const double beta = rzn / rz;
     rzp = rz;
     rz = rzn;
-    LDS_FOR_NODES(NT, n, k) p[k] = z[k] - u[1] * v[k] + beta * p[k];
+    const T u1 = (T)u[1], bT = (T)beta;
+    LDS_FOR_NODES(NT, n, k) p[k] = z[k] - u1 * v[k] + bT * p[k];
     __syncthreads();
   }
   return it;
@@ -377,16 +426,16 @@ MLQMC_DEV int jd_pcg(const PcgArrays& a, double mu, double rho, double rtol, int
 // path (rows of [WX | WY] with (n + 2) n entries each):
 // w_e = a0 + sum_{j<S} y_j Phi[j][e].  Entries that no stencil reads are
 // finite and otherwise unused.
-template <int NT, int n>
+template <int NT, int n, typename T>
 MLQMC_DEV void weights_from_table(const double* __restrict__ phi, const double* ys, int S,
-                                  double a0, double* w) {
+                                  double a0, T* w) {
   constexpr int P = Mesh<n>::P, PG = (n + 2) * n;
   for (int e = threadIdx.x; e < 2 * P; e += NT) {
     const int half = e >= P, idx = e - half * P;
     const double* src = phi + half * PG + idx;
     double acc = a0;
     for (int j = 0; j < S; ++j) acc += ys[j] * src[(int64_t)j * 2 * PG];
-    w[e] = acc;  // WY follows WX contiguously
+    w[e] = (T)acc;  // WY follows WX contiguously
   }
   __syncthreads();
 }
