@@ -19,6 +19,16 @@ Estimator (eq. mlqmc_R / eq. tg-mlqmc with eq. ml-var):
   Q^ML = sum_l Qhat_l,  V = sum_l V_l.
 The loop over k runs over k = 0 .. N_l - 1 (eq. rqmc), and the level-(l-1)
 term is evaluated at the same point t_{l,k}.
+
+Shared shifts with nested rules (end of section 4.3): one set of R shifts
+and one embedded rule serve every level, so t_{l,k} = t_{0,k} (the first N_l
+points of the rule, N_0 >= N_1 >= ...).  Then H_l = h_0 (and S_l = s_0): the
+coarse pair of every level is the level-0 direct pair at the same point, and
+lambda^{l-1} at level l is the value level l-1 already computed there.  The
+level terms of one shift are no longer independent, so the variance of Q^ML
+is estimated from the R per-shift totals sum_l Q_l^(r) (eq. sample_var
+applied to them); sum_l V_l bounds it only up to the factor L the paper
+gives.
 """
 
 from __future__ import annotations
@@ -93,3 +103,59 @@ def estimate(levels, zs, Ns, shifts, fam) -> Estimate:
             vals = level_samples(levels[l], zs[l], Ns[l], shifts[l][r], fam)
             Q_lr[l, r] = qmc.qmc_mean(v.Y for v in vals)
     return combine(Q_lr)
+
+
+def check_nested(levels, Ns) -> None:
+    """The level list the nested estimator accepts: level 0 direct, level
+    l >= 1 two-grid from the level-0 mesh and truncation, its previous term
+    on level l-1's mesh and truncation, N non-increasing."""
+    l0 = levels[0]
+    if l0.n_coarse != 0 or l0.n_prev != 0:
+        raise ValueError("level 0 must be a direct level without a previous term")
+    for l in range(1, len(levels)):
+        lv, pv = levels[l], levels[l - 1]
+        if (lv.n_coarse, lv.s_coarse) != (l0.n_fine, l0.s_fine):
+            raise ValueError("level %d: coarse mesh and truncation must be level 0's" % l)
+        if (lv.n_prev, lv.s_prev) != (pv.n_fine, pv.s_fine):
+            raise ValueError("level %d: previous term must be on level %d's mesh" % (l, l - 1))
+        if Ns[l] > Ns[l - 1]:
+            raise ValueError("N must not increase with the level")
+
+
+def nested_values(levels, z, Ns, shift, fam):
+    """lambda^l(t_k) for one shift: lams[l][k], k < N_l, l = 0..L, on the
+    first N_l points of the embedded rule with N_0 points (z of length
+    max_l s_l; level l reads y_{1:s_l})."""
+    check_nested(levels, Ns)
+    l0 = levels[0]
+    pts = qmc.embedded_points(z, Ns[0], shift, Ns[0])
+    lams = [np.empty(N) for N in Ns]
+    for k in range(Ns[0]):
+        y = pts[k]
+        lam0, u0 = twogrid.direct(l0.n_fine, l0.s_fine, y, fam)
+        lams[0][k] = lam0
+        for l in range(1, len(levels)):
+            if k >= Ns[l]:
+                break
+            lv = levels[l]
+            lams[l][k], _ = twogrid.two_grid_update(lv.n_fine, lv.s_fine, y, fam, lam0, u0,
+                                                    l0.n_fine)
+    return lams
+
+
+def estimate_nested(levels, z, Ns, shifts, fam) -> Estimate:
+    """Nested estimator: Y_l(t_k) = lambda^l(t_k) - lambda^{l-1}(t_k)
+    (lambda^{-1} = 0), Q_l^(r) their mean over k < N_l, Qhat_l and V_l as in
+    Algorithm 2, Q^ML = sum_l Qhat_l, and V_ml the sample variance of the
+    per-shift totals."""
+    L1 = len(levels)
+    R = np.asarray(shifts).shape[0]
+    Q_lr = np.empty((L1, R))
+    for r in range(R):
+        lams = nested_values(levels, z, Ns, shifts[r], fam)
+        for l in range(L1):
+            prev = lams[l - 1][:Ns[l]] if l else np.zeros(Ns[l])
+            Q_lr[l, r] = qmc.qmc_mean(lams[l] - prev)
+    est = combine(Q_lr)
+    totals = [math.fsum(Q_lr[:, r]) for r in range(R)]
+    return Estimate(Q_lr, est.Qhat, est.V, est.Q_ml, qmc.sample_variance(totals))

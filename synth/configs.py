@@ -9,6 +9,12 @@ the number of lattice points N.  All levels share R random shifts.
 
 Shifts are independent per level and per replicate, drawn uniformly on
 [0, 1)^s from ``numpy.random.default_rng([210303407, cfg, level, r])``.
+
+A nested workload (end of section 4.3) shares one set of R shifts (level 0's
+seeds, s_max components) and one generating vector (the CBC vector for the
+largest N with s_max components, enumerated as an embedded base-2 rule)
+across its levels; levels l >= 1 take level 0's mesh and truncation as the
+coarse pair.
 """
 
 from __future__ import annotations
@@ -45,6 +51,7 @@ class Workload:
     R: int
     description: str = ""
     a0: float = 1.0
+    nested: bool = False
 
     @property
     def s_max(self) -> int:
@@ -60,6 +67,14 @@ class Workload:
     def shifts(self, level: int) -> np.ndarray:
         lv = self.levels[level]
         return shifts_for(self.cfg_id, level, self.R, lv.s_fine)
+
+    def z_shared(self) -> np.ndarray:
+        """Nested workloads: one vector for every level (first s_l used)."""
+        return lattice_vector(max(lv.N for lv in self.levels), self.s_max)
+
+    def shifts_shared(self) -> np.ndarray:
+        """Nested workloads: R shifts with s_max components for every level."""
+        return shifts_for(self.cfg_id, 0, self.R, self.s_max)
 
     def n_samples(self) -> int:
         return self.R * sum(lv.N for lv in self.levels)
@@ -99,6 +114,13 @@ def _cfg4_levels():
     return tuple(out)
 
 
+def _nested_levels(base):
+    """The levels of ``base`` with H_l = h_0 and S_l = s_0 for l >= 1."""
+    l0 = base[0]
+    return tuple([l0] + [LevelSpec(lv.n_fine, lv.s_fine, l0.n_fine, l0.s_fine, lv.n_prev,
+                                   lv.s_prev, lv.N) for lv in base[1:]])
+
+
 CONFIGS = {
     1: Workload("cfg1-direct-h32-s16", 1, "fp64", 2.5,
                 (LevelSpec(32, 16, 0, 0, 0, 0, 256),), 4,
@@ -114,6 +136,9 @@ CONFIGS = {
     5: Workload("cfg5-twogrid-H64-h1024-s512", 5, "mixed", 2.0,
                 (LevelSpec(1024, 512, 64, 23, 0, 0, 1024),), 8,
                 "large fine level, H=1/64 -> h=1/1024, s=512, S=23, decay j^-2"),
+    6: Workload("cfg6-mlqmc-5level-nested", 6, "fp64", 2.5, _nested_levels(_cfg4_levels()), 8,
+                "cfg4's meshes, truncations and N_l with shared shifts, one embedded rule "
+                "and H_l = h_0 = 1/16, S_l = s_0 = 16 (end of section 4.3)", nested=True),
 }
 
 

@@ -9,7 +9,15 @@ eq. sample_var, eq. mlqmc_R, eq. ml-var, Algorithm 2).
 * the telescoping sum (eq. tele_sum) is exact sample by sample when all
   levels share points and use direct eigensolves;
 * a degenerate two-grid level whose two meshes coincide gives Y = 0 at
-  every point (the coarse pair and point are shared by both terms).
+  every point (the coarse pair and point are shared by both terms);
+* embedded rules: hand-computed radical inverses and points, every prefix of
+  2^m points is the plain rank-1 lattice with 2^m points, and each block of
+  the enumeration fills exactly the gaps of the ones before;
+* the nested estimator (shared shifts, nested points, H_l = h_0): the level
+  terms telescope to the finest two-grid value point by point, its values
+  are those of Algorithm 2's level evaluation at the same points, and the
+  variance of the per-shift totals is at most the number of levels times
+  sum_l V_l (Cauchy-Schwarz: the factor the paper states for shared shifts).
 """
 
 import cmath
@@ -116,3 +124,138 @@ def test_estimate_small_two_level():
     # small corrections (variance reduction across levels)
     assert est.Qhat[0] > 10 and abs(est.Qhat[1]) < 0.2 * est.Qhat[0]
     assert est.V[1] < est.V[0]
+
+
+def test_radical_inverse_hand_values():
+    assert [qmc.radical_inverse_numerator(k, 3) for k in range(8)] == [0, 4, 2, 6, 1, 5, 3, 7]
+    assert qmc.radical_inverse_numerator(1, 10) == 512
+    assert qmc.radical_inverse_numerator(6, 4) == 6       # 0110 -> 0110
+    assert qmc.radical_inverse_numerator(11, 5) == 26     # 01011 -> 11010
+    with pytest.raises(ValueError):
+        qmc.radical_inverse_numerator(8, 3)
+
+
+def test_embedded_points_hand_computed():
+    z, N, sh = [1, 3], 8, np.zeros(2)
+    got = qmc.embedded_points(z, N, sh, 4)
+    want = np.array([[-0.5, -0.5], [0.0, 0.0], [-0.25, 0.25], [0.25, -0.25]])
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("N,s", [(64, 8), (256, 16)])
+def test_embedded_prefixes_are_lattices_and_blocks_fill_gaps(N, s):
+    z = lattice_vector(N, s)
+    sh = shifts_for(98, 0, 1, s)[0]
+    pts = [tuple(p) for p in qmc.embedded_points(z, N, sh, N)]
+    assert len(set(pts)) == N
+    m_max = N.bit_length() - 1
+    prev = set()
+    for m in range(m_max + 1):
+        Nm = 1 << m
+        plain = {tuple(p) for p in qmc.lattice_points(z, Nm, sh)}
+        assert set(pts[:Nm]) == plain
+        if m:
+            assert set(pts[Nm // 2:Nm]) == plain - prev
+        prev = plain
+
+
+def _nested_levels(N):
+    # level 0 direct on 1/4, levels 1-2 two-grid from (1/4, s_0)
+    return [LevelSpec(4, 2, 0, 0, 0, 0, N[0]), LevelSpec(8, 3, 4, 2, 4, 2, N[1]),
+            LevelSpec(16, 5, 4, 2, 8, 3, N[2])]
+
+
+def test_nested_levels_telescope_to_finest_two_grid_value():
+    fam = problem1_family(5, 2.0)
+    N = [4, 4, 4]
+    levels = _nested_levels(N)
+    z = lattice_vector(64, 8)[:5]
+    sh = shifts_for(99, 0, 1, 5)[0]
+    lams = mlqmc.nested_values(levels, z, N, sh, fam)
+    pts = qmc.embedded_points(z, N[0], sh, N[0])
+    for k in range(N[0]):
+        tot = sum(lams[l][k] - (lams[l - 1][k] if l else 0.0) for l in range(3))
+        lam_L = twogrid.two_grid(16, 5, 4, 2, pts[k], fam)[0]
+        assert abs(tot - lam_L) < 1e-12 * lam_L
+        lam0 = twogrid.direct(4, 2, pts[k], fam)[0]
+        assert abs(lams[0][k] - lam0) < 1e-13 * lam0
+
+
+def test_nested_values_equal_algorithm2_values_at_the_same_points():
+    fam = problem1_family(5, 2.0)
+    N = [8, 4, 2]
+    levels = _nested_levels(N)
+    z = lattice_vector(64, 8)[:5]
+    sh = shifts_for(99, 1, 1, 5)[0]
+    lams = mlqmc.nested_values(levels, z, N, sh, fam)
+    pts = qmc.embedded_points(z, N[0], sh, N[0])
+    for l in range(1, 3):
+        assert len(lams[l]) == N[l]
+        for k in range(N[l]):
+            v = mlqmc.level_value(levels[l], pts[k], fam)
+            assert abs(v.lam - lams[l][k]) < 1e-12 * v.lam
+            assert abs(v.lam_prev - lams[l - 1][k]) < 1e-12 * v.lam
+
+
+def test_nested_estimate_variance_and_identical_shifts():
+    fam = problem1_family(5, 2.0)
+    N = [8, 4, 2]
+    levels = _nested_levels(N)
+    z = lattice_vector(64, 8)[:5]
+    shifts = shifts_for(99, 2, 3, 5)
+    est = mlqmc.estimate_nested(levels, z, N, shifts, fam)
+    assert est.Q_lr.shape == (3, 3)
+    assert abs(est.Q_ml - est.Qhat.sum()) < 1e-13 * abs(est.Q_ml)
+    assert est.V_ml <= 3 * est.V.sum() * (1 + 1e-12)
+    totals = est.Q_lr.sum(axis=0)
+    assert abs(est.V_ml - np.var(totals, ddof=1) / 3) < 1e-12 * np.var(totals)
+    same = mlqmc.estimate_nested(levels, z, N, np.repeat(shifts[:1], 2, axis=0), fam)
+    # equal up to the eigensolver's last-bit differences between calls
+    assert same.V_ml < 1e-26 and np.all(same.V < 1e-26)
+    assert np.allclose(same.Q_lr[:, 0], est.Q_lr[:, 0], rtol=1e-13, atol=0)
+
+
+def test_nested_level_list_checks():
+    ok = _nested_levels([4, 4, 2])
+    mlqmc.check_nested(ok, [4, 4, 2])
+    with pytest.raises(ValueError):
+        mlqmc.check_nested(ok, [4, 8, 2])
+    bad = list(ok)
+    bad[2] = LevelSpec(16, 5, 8, 3, 8, 3, 2)   # coarse mesh is not level 0's
+    with pytest.raises(ValueError):
+        mlqmc.check_nested(bad, [4, 4, 2])
+    bad = list(ok)
+    bad[2] = LevelSpec(16, 5, 4, 2, 4, 2, 2)   # previous term not on level 1's mesh
+    with pytest.raises(ValueError):
+        mlqmc.check_nested(bad, [4, 4, 2])
+
+
+def test_nested_estimate_telescopes_per_shift():
+    # with equal N the per-shift total is the plain QMC mean of the finest
+    # two-grid value over the same points
+    fam = problem1_family(5, 2.0)
+    N = [4, 4, 4]
+    levels = _nested_levels(N)
+    z = lattice_vector(64, 8)[:5]
+    shifts = shifts_for(99, 3, 2, 5)
+    est = mlqmc.estimate_nested(levels, z, N, shifts, fam)
+    for r in range(2):
+        pts = qmc.embedded_points(z, 4, shifts[r], 4)
+        want = np.mean([twogrid.two_grid(16, 5, 4, 2, y, fam)[0] for y in pts])
+        assert abs(est.Q_lr[:, r].sum() - want) < 1e-12 * want
+
+
+def test_nested_estimate_level_means_use_the_leading_points():
+    # Q_l^(r) is Algorithm 2's level mean over the first N_l points of the
+    # embedded rule (each Y_l evaluated afresh there)
+    fam = problem1_family(5, 2.0)
+    N = [8, 4, 2]
+    levels = _nested_levels(N)
+    z = lattice_vector(64, 8)[:5]
+    shifts = shifts_for(99, 4, 2, 5)
+    est = mlqmc.estimate_nested(levels, z, N, shifts, fam)
+    for r in range(2):
+        pts = qmc.embedded_points(z, 8, shifts[r], 8)
+        for l in range(3):
+            want = np.mean([mlqmc.level_value(levels[l], pts[k], fam).Y for k in range(N[l])])
+            assert abs(est.Q_lr[l, r] - want) < 1e-12 * max(abs(want), 1.0)
