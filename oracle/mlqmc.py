@@ -38,7 +38,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import qmc, twogrid
+from . import fem, functional, qmc, twogrid
 
 
 @dataclass
@@ -47,27 +47,36 @@ class LevelValue:
     lam: float        # lambda^l
     lam_prev: float   # lambda^{l-1}
     lam_coarse: float # lambda_{H_l,S_l}, NaN for direct levels
+    G: float = float("nan")       # G(u^l), the functional of oracle.functional
+    G_prev: float = 0.0           # G(u^{l-1}) (0 without a previous level)
+
+
+def _G(n, u):
+    return functional.G(n, u, fem.mass(n))
 
 
 def level_value(lv, y, fam) -> LevelValue:
     y = np.asarray(y, dtype=np.float64)
     if lv.n_coarse == 0:
-        lam, _ = twogrid.direct(lv.n_fine, lv.s_fine, y, fam)
-        lam_prev = 0.0
+        lam, u = twogrid.direct(lv.n_fine, lv.s_fine, y, fam)
+        lam_prev, G_prev = 0.0, 0.0
         if lv.n_prev:
-            lam_prev, _ = twogrid.direct(lv.n_prev, lv.s_prev, y, fam)
-        return LevelValue(lam - lam_prev, lam, lam_prev, float("nan"))
+            lam_prev, up = twogrid.direct(lv.n_prev, lv.s_prev, y, fam)
+            G_prev = _G(lv.n_prev, up)
+        return LevelValue(lam - lam_prev, lam, lam_prev, float("nan"), _G(lv.n_fine, u), G_prev)
     lam_H, u_H = twogrid.coarse_pair(lv.n_coarse, lv.s_coarse, y, fam)
-    lam, _ = twogrid.two_grid_update(lv.n_fine, lv.s_fine, y, fam, lam_H, u_H, lv.n_coarse)
-    lam_prev = 0.0
+    lam, w = twogrid.two_grid_update(lv.n_fine, lv.s_fine, y, fam, lam_H, u_H, lv.n_coarse)
+    lam_prev, G_prev = 0.0, 0.0
     if lv.n_prev:
         if lv.n_prev == lv.n_coarse and lv.s_prev == lv.s_coarse:
             # (A - lambda_H M) is exactly singular here; its two-grid value is lambda_H
-            lam_prev = lam_H
+            # (and its eigenfunction u_H)
+            lam_prev, G_prev = lam_H, _G(lv.n_coarse, u_H)
         else:
-            lam_prev, _ = twogrid.two_grid_update(lv.n_prev, lv.s_prev, y, fam, lam_H, u_H,
-                                                  lv.n_coarse)
-    return LevelValue(lam - lam_prev, lam, lam_prev, lam_H)
+            lam_prev, wp = twogrid.two_grid_update(lv.n_prev, lv.s_prev, y, fam, lam_H, u_H,
+                                                   lv.n_coarse)
+            G_prev = _G(lv.n_prev, wp)
+    return LevelValue(lam - lam_prev, lam, lam_prev, lam_H, _G(lv.n_fine, w), G_prev)
 
 
 def level_samples(lv, z, N: int, shift, fam, ks=None):
@@ -93,15 +102,21 @@ def combine(Q_lr) -> Estimate:
     return Estimate(Q_lr, Qhat, V, math.fsum(Qhat), math.fsum(V))
 
 
-def estimate(levels, zs, Ns, shifts, fam) -> Estimate:
-    """Algorithm 2: levels[l], zs[l] (int[s_l]), Ns[l], shifts[l] (float[R, s_l])."""
+def estimate(levels, zs, Ns, shifts, fam, with_G: bool = False):
+    """Algorithm 2: levels[l], zs[l] (int[s_l]), Ns[l], shifts[l] (float[R, s_l]).
+    With with_G, also the same estimator for G(u) (the telescoping sum of the
+    introduction with Y_l = G(u^l) - G(u^{l-1})): returns (lambda, G)."""
     L1 = len(levels)
     R = np.asarray(shifts[0]).shape[0]
     Q_lr = np.empty((L1, R))
+    QG_lr = np.empty((L1, R))
     for l in range(L1):
         for r in range(R):
             vals = level_samples(levels[l], zs[l], Ns[l], shifts[l][r], fam)
             Q_lr[l, r] = qmc.qmc_mean(v.Y for v in vals)
+            QG_lr[l, r] = qmc.qmc_mean(v.G - v.G_prev for v in vals)
+    if with_G:
+        return combine(Q_lr), combine(QG_lr)
     return combine(Q_lr)
 
 
@@ -122,24 +137,32 @@ def check_nested(levels, Ns) -> None:
             raise ValueError("N must not increase with the level")
 
 
+def nested_point(levels, z, Ns, shift, k: int, fam):
+    """lambda^l(t_k) for l = 0 .. (the last level with k < N_l), at point k
+    of the embedded rule with N_0 points: the level-0 direct pair, then the
+    two-grid update from it on each finer level."""
+    l0 = levels[0]
+    y = qmc.embedded_point(z, Ns[0], shift, k)
+    lam0, u0 = twogrid.direct(l0.n_fine, l0.s_fine, y, fam)
+    out = [lam0]
+    for l in range(1, len(levels)):
+        if k >= Ns[l]:
+            break
+        lv = levels[l]
+        out.append(twogrid.two_grid_update(lv.n_fine, lv.s_fine, y, fam, lam0, u0,
+                                           l0.n_fine)[0])
+    return out
+
+
 def nested_values(levels, z, Ns, shift, fam):
     """lambda^l(t_k) for one shift: lams[l][k], k < N_l, l = 0..L, on the
     first N_l points of the embedded rule with N_0 points (z of length
     max_l s_l; level l reads y_{1:s_l})."""
     check_nested(levels, Ns)
-    l0 = levels[0]
-    pts = qmc.embedded_points(z, Ns[0], shift, Ns[0])
     lams = [np.empty(N) for N in Ns]
     for k in range(Ns[0]):
-        y = pts[k]
-        lam0, u0 = twogrid.direct(l0.n_fine, l0.s_fine, y, fam)
-        lams[0][k] = lam0
-        for l in range(1, len(levels)):
-            if k >= Ns[l]:
-                break
-            lv = levels[l]
-            lams[l][k], _ = twogrid.two_grid_update(lv.n_fine, lv.s_fine, y, fam, lam0, u0,
-                                                    l0.n_fine)
+        for l, v in enumerate(nested_point(levels, z, Ns, shift, k, fam)):
+            lams[l][k] = v
     return lams
 
 
