@@ -73,6 +73,52 @@ def _oracle_worker(args):
     return v.Y, v.lam
 
 
+def _oracle_nested_worker(args):
+    # CPU baseline of a nested workload: the oracle's evaluation of one point
+    # of shift r (every level whose N_l exceeds k), as its nested estimator
+    # runs it
+    cfg_id, r, k = args
+    from oracle import mlqmc
+    from synth import CONFIGS
+    w = CONFIGS[cfg_id]
+    lams = mlqmc.nested_point(list(w.levels), w.z_shared(), [lv.N for lv in w.levels],
+                              w.shifts_shared()[r], k, w.family())
+    return [(l, lam - (lams[l - 1] if l else 0.0), lam) for l, lam in enumerate(lams)]
+
+
+def cpu_baseline_nested(cfg_id: int, seconds: float, cores: int):
+    import multiprocessing as mp
+    from synth import CONFIGS
+    w = CONFIGS[cfg_id]
+    N0 = w.levels[0].N
+    t0 = time.perf_counter()
+    _oracle_nested_worker((cfg_id, 0, 0))            # a point on every level
+    t_all = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _oracle_nested_worker((cfg_id, 0, N0 - 1))       # a level-0-only point
+    t_one = time.perf_counter() - t0
+    share = w.levels[-1].N / N0
+    per = share * t_all + (1 - share) * t_one
+    count = max(cores, min(N0, int(seconds * cores / max(per, 1e-3))))
+    pts = [(cfg_id, i % w.R, (i * 7919) % N0) for i in range(count)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        vals = pool.map(_oracle_nested_worker, pts, chunksize=1)
+    dt = time.perf_counter() - t0
+    idx, ref = [], []
+    for (_, r, k), lv in zip(pts, vals):
+        for l, y, lam in lv:
+            assert math.isfinite(y)
+            idx.append((l, r, k))
+            ref.append((y, lam))
+    base = {"value": len(idx) / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"{count} of the {w.R * N0} points of the nested rule (strided), "
+                      f"{len(idx)} level samples Y_l, scipy/SuperLU FP64, {cores} processes, "
+                      f"{dt:.1f} s"}
+    return base, idx, ref
+
+
 def cpu_baseline(cfg_id: int, seconds: float):
     import multiprocessing as mp
     from synth import CONFIGS
@@ -81,6 +127,8 @@ def cpu_baseline(cfg_id: int, seconds: float):
     cores = len(os.sched_getaffinity(0))
     cores = min(cores, 16)
     w = CONFIGS[cfg_id]
+    if w.nested:
+        return cpu_baseline_nested(cfg_id, seconds, cores)
     n_total = w.n_samples()
     # calibrate: one sample of every level on this process, weighted by the
     # level's share of the samples; then size the sample to ~`seconds`
@@ -152,6 +200,37 @@ def per_level(ctx, m, w, opts, idx=None, ref=None):
     return out, acc
 
 
+def per_level_nested(ctx, m, w, opts, idx=None, ref=None):
+    """Untimed nested estimate with the per-point values: flags and, given
+    oracle values of the CPU-baseline sample, the per-sample error of Y_l."""
+    import numpy as np
+    levels = [_lv6(lv) for lv in w.levels]
+    Ns = [lv.N for lv in w.levels]
+    st, Q, Qh, V, est, lam = ctx.estimate_nested(levels, Ns, w.R, w.z_shared(),
+                                                 w.shifts_shared(), opts=opts, lam_out=True)
+    out = [{"level": l, "h": f"1/{lv.n_fine}",
+            "H": f"1/{lv.n_coarse}" if lv.n_coarse else None, "s": lv.s_fine,
+            "samples": w.R * lv.N, "Qhat": float(Qh[l]), "V": float(V[l])}
+           for l, lv in enumerate(w.levels)]
+    acc = None
+    if idx is not None:
+        errs, lev_err = [], {}
+        for (l, r, k), (yref, lref) in zip(idx, ref):
+            yv = lam[l][r, k] - (lam[l - 1][r, k] if l else 0.0)
+            errs.append(abs(yv - yref) / abs(lref))
+            lev_err.setdefault(l, []).append(errs[-1])
+        for x in out:
+            le = lev_err.get(x["level"])
+            x["max_rel_err"] = float(max(le)) if le else None
+            x["oracle_samples"] = len(le) if le else 0
+        e = np.asarray(errs)
+        acc = {"max_rel_err": float(e.max()), "median_rel_err": float(np.median(e)),
+               "samples": int(e.size), "flagged": int(st != m.MLQMC_OK),
+               "bound": 1e-10 if opts.prec == m.MLQMC_FP64 else 1e-8,
+               "quantity": "Y_l = lambda^l - lambda^(l-1), error relative to lambda^l"}
+    return out, acc
+
+
 def _traffic(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source changed since the counters were taken."""
@@ -197,13 +276,21 @@ def main():
     tuned = ctx.apply_tuning()  # the autotuner's table for this device, if shipped
     levels = [_lv6(lv) for lv in w.levels]
     Ns = [lv.N for lv in w.levels]
-    zs = [w.z(l) for l in range(len(w.levels))]
-    shs = [w.shifts(l) for l in range(len(w.levels))]
+    zs = shs = None
+    if not w.nested:
+        zs = [w.z(l) for l in range(len(w.levels))]
+        shs = [w.shifts(l) for l in range(len(w.levels))]
     opts = m.default_opts(prec=m.MLQMC_MIXED if a.prec == "mixed" else m.MLQMC_FP64)
     n_samples = w.n_samples()
 
+    if w.nested:
+        z_sh, sh_sh = w.z_shared(), w.shifts_shared()
+
     def step():
-        st, Q, Qh, V, est = ctx.estimate(levels, Ns, w.R, zs, shs, opts=opts)
+        if w.nested:
+            st, Q, Qh, V, est, _ = ctx.estimate_nested(levels, Ns, w.R, z_sh, sh_sh, opts=opts)
+        else:
+            st, Q, Qh, V, est = ctx.estimate(levels, Ns, w.R, zs, shs, opts=opts)
         if st != m.MLQMC_OK:
             raise RuntimeError(f"estimate flagged samples (status {st})")
         return est
@@ -237,7 +324,8 @@ def main():
             if not lv.n_coarse:
                 continue
             meshes = [(lv.n_fine, lv.s_fine)]
-            if lv.n_prev and not (lv.n_prev == lv.n_coarse and lv.s_prev == lv.s_coarse):
+            if lv.n_prev and not w.nested and not (lv.n_prev == lv.n_coarse and
+                                                    lv.s_prev == lv.s_coarse):
                 meshes.append((lv.n_prev, lv.s_prev))
             for nm, sm in meshes:
                 if nm >= 64:  # meshes of the batched path (finer ones solve in LDS)
@@ -263,7 +351,10 @@ def main():
     idx = ref = None
     if not a.no_cpu_baseline:
         cpu, idx, ref = cpu_baseline(a.cfg, a.cpu_seconds)
-    levels_out, acc = per_level(ctx, m, w, opts, idx, ref)
+    if w.nested:
+        levels_out, acc = per_level_nested(ctx, m, w, opts, idx, ref)
+    else:
+        levels_out, acc = per_level(ctx, m, w, opts, idx, ref)
 
     out = {
         "metric": "two-grid eigen-samples/sec per level; stencil HBM GB/s in roofline",
@@ -276,6 +367,7 @@ def main():
                    "H": [f"1/{lv.n_coarse}" if lv.n_coarse else None for lv in w.levels],
                    "s": [lv.s_fine for lv in w.levels], "S": [lv.s_coarse for lv in w.levels],
                    "N": Ns, "R": w.R, "samples_per_step": n_samples,
+                   "nested_shared_shifts": bool(w.nested),
                    "estimate": est[0], "variance": est[1]},
         "roofline": roof, "cpu_baseline": cpu, "accuracy_vs_oracle": acc,
         "per_level": levels_out, "tuning_entries_applied": tuned,

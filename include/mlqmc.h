@@ -128,6 +128,17 @@ mlqmc_status mlqmc_lattice_points(mlqmc_ctx* ctx, int64_t N, int32_t s, const in
                                   const double* shift, int64_t k0, int64_t count,
                                   double* Y, int32_t io_on_device);
 
+/* Points of the base-2 embedded lattice rule (embedded rules of section 2.5;
+ * the block-by-block enumeration of section 5): point k of N = 2^m points is
+ * the lattice point with index rev_m(k), the m-bit reversal of k,
+ *   Y[i][j] = frac((rev_m(k0+i) * z[j] mod N) / N + shift[j]) - 1/2,
+ * so the first 2^m' points always form the 2^m'-point lattice and each later
+ * block fills the gaps between the earlier points.  k0 + count <= N; other
+ * arguments and errors as mlqmc_lattice_points. */
+mlqmc_status mlqmc_embedded_points(mlqmc_ctx* ctx, int64_t N, int32_t s, const int64_t* z,
+                                   const double* shift, int64_t k0, int64_t count,
+                                   double* Y, int32_t io_on_device);
+
 /* Coefficient at the element centroids (eq. coeff_s, centroid rule):
  *   aK[b][e] = a0 + sum_{j<s} Y[b][j] c_j sin(pi k1_j xc_e) sin(pi k2_j yc_e)
  * Y is [B x s], aK is [B x 2n^2]. */
@@ -162,11 +173,17 @@ mlqmc_status mlqmc_prolong(mlqmc_ctx* ctx, int32_t nH, int32_t nh, int64_t B, co
  * lam_prev, lam_coarse, rq_iters, lin_iters may be NULL.  lam_coarse[i] =
  * lambda_{H,S}(y_i) (NaN on direct levels); rq_iters[i] = RQ iterations of the
  * coarse eigensolve; lin_iters[i] = PCG iterations of the fine solve(s);
- * flags[i] = MLQMC_FLAG_* bits.  Returns MLQMC_ENOCONV if any flag is set. */
+ * flags[i] = MLQMC_FLAG_* bits.
+ * g, g_prev (NULL or [n]): the linear functional of the eigenfunction the
+ * introduction estimates alongside lambda, G(u) = integral over D of u, for
+ * the level's eigenvector approximation (the direct eigenvector, or the
+ * two-grid w) normalised to ||u||_M = 1 with the sign that makes the
+ * integral positive; g_prev the same for the level-(l-1) approximation
+ * (written only if n_prev > 0).  Returns MLQMC_ENOCONV if any flag is set. */
 mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* lvl, const mlqmc_opts* opt,
                              int64_t n, const double* Y, int32_t warm_chain, double* lam,
                              double* lam_prev, double* lam_coarse, int32_t* rq_iters,
-                             int32_t* lin_iters, uint8_t* flags);
+                             int32_t* lin_iters, uint8_t* flags, double* g, double* g_prev);
 
 /* Two-grid MLQMC estimator (Algorithm 2; eq. tg-mlqmc, eq. sample_var, eq. ml-var).
  * Levels l = 0..n_levels-1 with N[l] points (powers of two), R shifts, z the
@@ -174,11 +191,41 @@ mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* lvl, const mlqmc
  * concatenated [R x s_fine] blocks per level, values in [0,1).  All of z, N,
  * shifts and lvls are host arrays.  Outputs (host unless opt->io_on_device):
  *   Q_lr [n_levels x R] = Q_l^(r), Qhat [n_levels], V [n_levels] (NaN if R == 1),
- *   est[0] = Q^ML = sum_l Qhat_l, est[1] = sum_l V_l. */
+ *   est[0] = Q^ML = sum_l Qhat_l, est[1] = sum_l V_l.
+ * g_stats (NULL, or [n_levels x R + 2 n_levels + 2]): the same estimator for
+ * E[G(u)] (G as in mlqmc_eig_level; the telescoping sum of the introduction
+ * with Y_l = G(u^l) - G(u^{l-1})), laid out as Q_lr, Qhat, V, est. */
 mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t n_levels, const mlqmc_level* lvls,
                             const int64_t* N, int32_t R, const int64_t* z, const double* shifts,
                             const mlqmc_opts* opt, double* Q_lr, double* Qhat, double* V,
-                            double* est);
+                            double* est, double* g_stats);
+
+/* Nested two-grid MLQMC estimator with shared shifts (end of section 4.3):
+ * one embedded rule (z [s_max], s_max = max_l s_fine) and one set of R shifts
+ * ([R x s_max], values in [0,1)) serve every level; level l uses the first
+ * N[l] points of the rule with N[0] points (N[l] powers of two, non-increasing)
+ * and the first s_fine components.  The level list must be:
+ *   level 0   direct (n_coarse = 0, n_prev = 0);
+ *   level l>0 two-grid with (n_coarse, s_coarse) = level 0's (n_fine, s_fine)
+ *             and (n_prev, s_prev) = level l-1's (n_fine, s_fine);
+ * so the coarse pair of every point is its level-0 eigenpair (H_l = h_0) and
+ * lambda^{l-1} at level l is the value level l-1 computed at the same point:
+ * no coarse eigensolve after level 0 and no recomputed previous term.
+ * Outputs as mlqmc_estimate, except est[1] = the sample variance (eq.
+ * sample_var) of the per-shift totals sum_l Q_l^(r): with shared shifts the
+ * level terms of one shift are dependent and sum_l V_l is no longer the
+ * variance of Q^ML.  lam_out (NULL, or [R * sum_l N[l]]) receives lambda^l at
+ * every point, level-major, then shift r, then point k.  g_stats as in
+ * mlqmc_estimate (with est[1] of the functional again the variance of the
+ * per-shift totals).
+ * Errors: MLQMC_EINVAL (a level list of another shape, N, z or shifts out of
+ * range), MLQMC_ENOMEM, MLQMC_EDEVICE; MLQMC_ENOCONV if a sample is flagged
+ * (all outputs still written). */
+mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t n_levels, const mlqmc_level* lvls,
+                                   const int64_t* N, int32_t R, const int64_t* z,
+                                   const double* shifts, const mlqmc_opts* opt, double* Q_lr,
+                                   double* Qhat, double* V, double* est, double* lam_out,
+                                   double* g_stats);
 
 /* ---- tuning ---- */
 

@@ -26,9 +26,9 @@ K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE, K_PRE = 0, 1, 2, 3, 4, 5
 # every symbol include/mlqmc.h declares
 EXPORTS = [
     "mlqmc_default_opts", "mlqmc_create", "mlqmc_destroy", "mlqmc_last_error",
-    "mlqmc_lattice_points", "mlqmc_coefficient", "mlqmc_apply_operator", "mlqmc_prolong",
-    "mlqmc_eig_level", "mlqmc_estimate", "mlqmc_set_tuning", "mlqmc_set_timing",
-    "mlqmc_get_timing",
+    "mlqmc_lattice_points", "mlqmc_embedded_points", "mlqmc_coefficient",
+    "mlqmc_apply_operator", "mlqmc_prolong", "mlqmc_eig_level", "mlqmc_estimate",
+    "mlqmc_estimate_nested", "mlqmc_set_tuning", "mlqmc_set_timing", "mlqmc_get_timing",
 ]
 
 
@@ -86,18 +86,22 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlqmc_last_error.argtypes = [P]
     lib.mlqmc_last_error.restype = C.c_char_p
     lib.mlqmc_lattice_points.argtypes = [P, I64, I32, P, P, I64, I64, P, I32]
+    lib.mlqmc_embedded_points.argtypes = [P, I64, I32, P, P, I64, I64, P, I32]
     lib.mlqmc_coefficient.argtypes = [P, I32, I32, I64, P, P, I32]
     lib.mlqmc_apply_operator.argtypes = [P, I32, I32, I64, P, P, P, P, I32]
     lib.mlqmc_prolong.argtypes = [P, I32, I32, I64, P, P, I32]
     lib.mlqmc_eig_level.argtypes = [P, C.POINTER(Level), C.POINTER(Opts), I64, P, I32, P, P, P,
-                                    P, P, P]
+                                    P, P, P, P, P]
     lib.mlqmc_estimate.argtypes = [P, I32, C.POINTER(Level), P, I32, P, P, C.POINTER(Opts), P,
-                                   P, P, P]
+                                   P, P, P, P]
+    lib.mlqmc_estimate_nested.argtypes = [P, I32, C.POINTER(Level), P, I32, P, P,
+                                          C.POINTER(Opts), P, P, P, P, P, P]
     lib.mlqmc_set_tuning.argtypes = [P, I32, I32, I64]
     lib.mlqmc_set_timing.argtypes = [P, I32]
     lib.mlqmc_get_timing.argtypes = [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
-    for name in ("mlqmc_create", "mlqmc_lattice_points", "mlqmc_coefficient",
-                 "mlqmc_apply_operator", "mlqmc_prolong", "mlqmc_eig_level", "mlqmc_estimate",
+    for name in ("mlqmc_create", "mlqmc_lattice_points", "mlqmc_embedded_points",
+                 "mlqmc_coefficient", "mlqmc_apply_operator", "mlqmc_prolong",
+                 "mlqmc_eig_level", "mlqmc_estimate", "mlqmc_estimate_nested",
                  "mlqmc_set_tuning", "mlqmc_set_timing", "mlqmc_get_timing"):
         getattr(lib, name).restype = C.c_int
     if path == LIB_PATH:
@@ -218,6 +222,14 @@ class Context:
             self._h, int(N), int(z.size), C.c_void_p(z.ctypes.data),
             C.c_void_p(shift.ctypes.data), int(k0), int(count), py, int(bool(dy))))
 
+    def embedded_points(self, N, z, shift, k0, count, Y):
+        z = np.ascontiguousarray(z, dtype=np.int64)
+        shift = np.ascontiguousarray(shift, dtype=np.float64)
+        py, dy = _ptr(Y, np.float64)
+        return self._check(self._lib.mlqmc_embedded_points(
+            self._h, int(N), int(z.size), C.c_void_p(z.ctypes.data),
+            C.c_void_p(shift.ctypes.data), int(k0), int(count), py, int(bool(dy))))
+
     def coefficient(self, n, s, Y, aK):
         py, dy = _ptr(Y, np.float64)
         pa, da = _ptr(aK, np.float64)
@@ -242,7 +254,7 @@ class Context:
 
     # ---- hot path ----
     def eig_level(self, level, Y, lam, flags, lam_prev=None, lam_coarse=None, rq_iters=None,
-                  lin_iters=None, warm_chain=1, opts=None):
+                  lin_iters=None, warm_chain=1, opts=None, g=None, g_prev=None):
         o = opts if opts is not None else default_opts()
         lv = Level(*[int(x) for x in level])
         py, d0 = _ptr(Y, np.float64)
@@ -252,15 +264,23 @@ class Context:
         pc, d4 = _ptr(lam_coarse, np.float64)
         pr, d5 = _ptr(rq_iters, np.int32)
         pi, d6 = _ptr(lin_iters, np.int32)
-        o.io_on_device = _one_side(d0, d1, d2, d3, d4, d5, d6)
+        pg, d7 = _ptr(g, np.float64)
+        pgp, d8 = _ptr(g_prev, np.float64)
+        o.io_on_device = _one_side(d0, d1, d2, d3, d4, d5, d6, d7, d8)
         n = Y.shape[0]
         return self._check(self._lib.mlqmc_eig_level(
             self._h, C.byref(lv), C.byref(o), int(n), py, int(warm_chain), pl, pp, pc, pr, pi,
-            pf), allow_noconv=True)
+            pf, pg, pgp), allow_noconv=True)
 
-    def estimate(self, levels, N, R, z, shifts, opts=None):
+    @staticmethod
+    def _g_split(G, L, R):
+        Q = G[:L * R].reshape(L, R)
+        return Q, G[L * R:L * R + L], G[L * R + L:L * R + 2 * L], G[L * R + 2 * L:]
+
+    def estimate(self, levels, N, R, z, shifts, opts=None, functional=False):
         """levels: list of 6-tuples; z, shifts: per-level arrays.  Returns
-        (status, Q_lr [L,R], Qhat [L], V [L], est [2]) as host arrays."""
+        (status, Q_lr [L,R], Qhat [L], V [L], est [2]) as host arrays, and with
+        functional=True a sixth item (Q_lr, Qhat, V, est) for E[G(u)]."""
         o = opts if opts is not None else default_opts()
         o.io_on_device = 0
         L = len(levels)
@@ -273,12 +293,50 @@ class Context:
         Qh = np.zeros(L)
         V = np.zeros(L)
         est = np.zeros(2)
+        G = np.zeros(L * R + 2 * L + 2) if functional else None
         st = self._check(self._lib.mlqmc_estimate(
             self._h, L, lv, C.c_void_p(Nn.ctypes.data), int(R), C.c_void_p(zc.ctypes.data),
             C.c_void_p(sc.ctypes.data), C.byref(o), C.c_void_p(Q.ctypes.data),
-            C.c_void_p(Qh.ctypes.data), C.c_void_p(V.ctypes.data), C.c_void_p(est.ctypes.data)),
-            allow_noconv=True)
+            C.c_void_p(Qh.ctypes.data), C.c_void_p(V.ctypes.data), C.c_void_p(est.ctypes.data),
+            C.c_void_p(G.ctypes.data) if functional else None), allow_noconv=True)
+        if functional:
+            return st, Q, Qh, V, est, self._g_split(G, L, R)
         return st, Q, Qh, V, est
+
+    def estimate_nested(self, levels, N, R, z, shifts, opts=None, lam_out=False,
+                        functional=False):
+        """Nested estimator with shared shifts: z [s_max], shifts [R, s_max].
+        Returns (status, Q_lr, Qhat, V, est, lam) with lam the per-level
+        lambda^l values [level][r, k] (or None), and with functional=True a
+        seventh item (Q_lr, Qhat, V, est) for E[G(u)]."""
+        o = opts if opts is not None else default_opts()
+        o.io_on_device = 0
+        L = len(levels)
+        lv = (Level * L)(*[Level(*[int(x) for x in l]) for l in levels])
+        Nn = np.ascontiguousarray(N, dtype=np.int64)
+        zc = np.ascontiguousarray(z, dtype=np.int64)
+        sc = np.ascontiguousarray(shifts, dtype=np.float64)
+        Q = np.zeros((L, R))
+        Qh = np.zeros(L)
+        V = np.zeros(L)
+        est = np.zeros(2)
+        lo = np.zeros(int(R * Nn.sum())) if lam_out else None
+        G = np.zeros(L * R + 2 * L + 2) if functional else None
+        st = self._check(self._lib.mlqmc_estimate_nested(
+            self._h, L, lv, C.c_void_p(Nn.ctypes.data), int(R), C.c_void_p(zc.ctypes.data),
+            C.c_void_p(sc.ctypes.data), C.byref(o), C.c_void_p(Q.ctypes.data),
+            C.c_void_p(Qh.ctypes.data), C.c_void_p(V.ctypes.data), C.c_void_p(est.ctypes.data),
+            C.c_void_p(lo.ctypes.data) if lam_out else None,
+            C.c_void_p(G.ctypes.data) if functional else None), allow_noconv=True)
+        lam = None
+        if lam_out:
+            lam, off = [], 0
+            for Nl in Nn:
+                lam.append(lo[off:off + R * Nl].reshape(R, Nl))
+                off += R * Nl
+        if functional:
+            return st, Q, Qh, V, est, lam, self._g_split(G, L, R)
+        return st, Q, Qh, V, est, lam
 
     # ---- instrumentation ----
     def set_timing(self, kernel_class):
@@ -312,6 +370,14 @@ def mlqmc_default_opts(**kw) -> Opts:
 
 def mlqmc_lattice_points(ctx, *a, **k):
     return ctx.lattice_points(*a, **k)
+
+
+def mlqmc_embedded_points(ctx, *a, **k):
+    return ctx.embedded_points(*a, **k)
+
+
+def mlqmc_estimate_nested(ctx, *a, **k):
+    return ctx.estimate_nested(*a, **k)
 
 
 def mlqmc_coefficient(ctx, *a, **k):

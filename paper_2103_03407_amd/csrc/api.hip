@@ -262,6 +262,7 @@ double lin_tol(const mlqmc_opts* o) {
   return o->prec == MLQMC_MIXED ? 1e-7 : 1e-10;
 }
 double lam_tol(const mlqmc_opts* o) {
+  if (o->lam_rtol < 0) return 0.0;  // internal: the residual test alone
   if (o->lam_rtol > 0) return o->lam_rtol;
   return o->prec == MLQMC_MIXED ? 5e-10 : 5e-12;
 }
@@ -340,7 +341,7 @@ std::vector<uint64_t> graph_key(int nh, int64_t Bn, const mlqmc_opts* o, const F
   k.push_back(bits[1]);
   for (const void* p : ptrs) k.push_back((uint64_t)(uintptr_t)p);
   const void* sp[] = {S.mu, S.vs, S.rho, S.rz, S.rz0, S.alpha, S.c, S.c2, S.beta, S.lam, S.f,
-                      S.m, S.dmp, S.rzp, S.its, S.lin_acc, S.active, S.vact, S.flags};
+                      S.m, S.dmp, S.rzp, S.g, S.its, S.lin_acc, S.active, S.vact, S.flags};
   for (const void* p : sp) k.push_back((uint64_t)(uintptr_t)p);
   for (const V* v : {&W, &X, &Xb, &Bv})
     for (auto* p : *v) k.push_back((uint64_t)(uintptr_t)p);
@@ -387,7 +388,8 @@ mlqmc_status pcg_graph(mlqmc_ctx* ctx, const char* tag, int64_t, F body,
 template <typename T>
 mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, const double* Y,
                           int64_t ldY, const double* uH, const double* lamH, int nH, int64_t n,
-                          double* lam, int* lin_iters, uint8_t* flags, const char* tag) {
+                          double* lam, double* g, int* lin_iters, uint8_t* flags,
+                          const char* tag) {
   constexpr bool kMixed = std::is_same<T, float>::value;
   Table* tb = nullptr;
   CS(ctx->table(nh, s, &tb));
@@ -501,6 +503,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     S.dmp = sc + 10 * batch;
     S.rzp = sc + 11 * batch;
     S.lam = lam + b0;
+    S.g = g ? g + b0 : nullptr;
     S.its = its;
     S.lin_acc = lin_iters ? lin_iters + b0 : nullptr;
     S.active = active;
@@ -643,7 +646,13 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
 // Two-grid update on mesh nh from the coarse pairs (uH on mesh nH, lamH).
 mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, const double* Y,
                          int64_t ldY, const double* uH, const double* lamH, int nH, int64_t n,
-                         double* lam, int* lin_iters, uint8_t* flags, const char* tag) {
+                         double* lam, double* g, int* lin_iters, uint8_t* flags,
+                         const char* tag) {
+  // G is linear in the eigenvector, whose error is only the square root of
+  // the eigenvalue's: with G requested the solve runs to the residual test
+  mlqmc_opts og = *o;
+  if (g) og.lam_rtol = -1.0;
+  o = &og;
   if (nh <= 32) {
     Table* tb = nullptr;
     CS(ctx->table(nh, s, &tb));
@@ -662,27 +671,22 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
     a.mixed = o->prec == MLQMC_MIXED ? 1 : 0;
     a.max_lin = o->max_lin_iter;
     a.lam = lam;
+    a.g = g;
     a.lin_iters = lin_iters;
     a.flags = flags;
     CK(launch_tg_small(nh, a, ctx->stream), "two-grid (LDS)");
     return MLQMC_OK;
   }
   if (o->prec == MLQMC_MIXED)
-    return fine_batched<float>(ctx, o, nh, s, Y, ldY, uH, lamH, nH, n, lam, lin_iters, flags, tag);
-  return fine_batched<double>(ctx, o, nh, s, Y, ldY, uH, lamH, nH, n, lam, lin_iters, flags, tag);
+    return fine_batched<float>(ctx, o, nh, s, Y, ldY, uH, lamH, nH, n, lam, g, lin_iters, flags,
+                               tag);
+  return fine_batched<double>(ctx, o, nh, s, Y, ldY, uH, lamH, nH, n, lam, g, lin_iters, flags,
+                              tag);
 }
 
-// Whole level on device buffers (Y [n x ldY] on device); outputs on device.
-mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* o, int64_t n,
-                        const double* Y, int64_t ldY, int warm, double* lam, double* lam_prev,
-                        double* lam_coarse, int* rq_iters, int* lin_iters, uint8_t* flags) {
-  hipStream_t st = ctx->stream;
-  if (n == 0) return MLQMC_OK;
-  CK(hipMemsetAsync(flags, 0, n, st), "memset");
-  CK(hipMemsetAsync(lin_iters, 0, n * sizeof(int), st), "memset");
-  const int mixed = o->prec == MLQMC_MIXED ? 1 : 0;
-  const int chain =
-      default_chain(n, warm, o->chain_len, L->n_coarse ? L->n_coarse : L->n_fine, mixed);
+// Arguments of the warm-started RQ eigensolve shared by every caller.
+RqiArgs rqi_base(mlqmc_ctx* ctx, const mlqmc_opts* o, int64_t n, const double* Y, int64_t ldY,
+                 int chain, int warm, int* rq_iters, int* lin_iters, uint8_t* flags) {
   RqiArgs a{};
   a.Y = Y;
   a.ldY = ldY;
@@ -697,7 +701,39 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   a.rq_iters = rq_iters;
   a.lin_iters = lin_iters;
   a.flags = flags;
-  a.mixed = mixed;
+  a.mixed = o->prec == MLQMC_MIXED ? 1 : 0;
+  // the refinement step of a vector G is taken from: FP64 only (an FP32
+  // correction solve cannot improve an FP32 vector, its right-hand side is
+  // rounding noise)
+  a.g_lin_rtol = a.mixed ? 0.0 : lin_tol(o);
+  return a;
+}
+
+// Chain length for R shifts of N points each: a power of two dividing N, so
+// no warm-start chain crosses from one shift to the next.
+int shift_chain(int64_t N, int R, const mlqmc_opts* o, int mesh) {
+  const int chain =
+      default_chain(N * R, 1, o->chain_len, mesh, o->prec == MLQMC_MIXED ? 1 : 0);
+  int c2 = 1;
+  while (c2 < chain) c2 *= 2;
+  return (int)std::min<int64_t>(c2, N);
+}
+
+// Whole level on device buffers (Y [n x ldY] on device); outputs on device.
+// g, g_prev (nullable): G(u^l), G(u^{l-1}) of the normalised, sign-fixed
+// eigenvector approximations.
+mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* o, int64_t n,
+                        const double* Y, int64_t ldY, int warm, double* lam, double* lam_prev,
+                        double* lam_coarse, int* rq_iters, int* lin_iters, uint8_t* flags,
+                        double* g = nullptr, double* g_prev = nullptr) {
+  hipStream_t st = ctx->stream;
+  if (n == 0) return MLQMC_OK;
+  CK(hipMemsetAsync(flags, 0, n, st), "memset");
+  CK(hipMemsetAsync(lin_iters, 0, n * sizeof(int), st), "memset");
+  const int mixed = o->prec == MLQMC_MIXED ? 1 : 0;
+  const int chain =
+      default_chain(n, warm, o->chain_len, L->n_coarse ? L->n_coarse : L->n_fine, mixed);
+  RqiArgs a = rqi_base(ctx, o, n, Y, ldY, chain, warm, rq_iters, lin_iters, flags);
   if (L->n_coarse == 0) {
     Table* tb = nullptr;
     CS(ctx->table(L->n_fine, L->s_fine, &tb));
@@ -705,6 +741,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
     a.phi = tb->pad;
     a.lam = lam;
     a.u_out = nullptr;
+    a.g_out = g;
     ctx->t_begin(MLQMC_K_COARSE);
     CK(launch_rqi(L->n_fine, a, st), "eigensolve (LDS)");
     ctx->t_end(MLQMC_K_COARSE, 0.0);
@@ -727,6 +764,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
       b.rq_iters = i2;
       b.lin_iters = nullptr;
       b.flags = f2;
+      b.g_out = g_prev;
       CK(launch_rqi(L->n_prev, b, st), "eigensolve (LDS)");
       // merge the flags of the previous-level eigensolve on the host
       std::vector<uint8_t> h1(n), h2(n);
@@ -750,6 +788,9 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   a.phi = tb->pad;
   a.lam = lamH;
   a.u_out = uH;
+  const bool degenerate = L->n_prev == L->n_coarse && L->s_prev == L->s_coarse;
+  // on the degenerate previous mesh the update's eigenvector is u_H itself
+  a.g_out = (L->n_prev && lam_prev && degenerate) ? g_prev : nullptr;
   if (const int64_t per = rqi_scratch_doubles(L->n_coarse)) {
     a.scratch_doubles = per * ((n + chain - 1) / chain);
     CS(ctx->getT("rqi_scratch", a.scratch_doubles, &a.scratch));
@@ -757,15 +798,15 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   ctx->t_begin(MLQMC_K_COARSE);
   CK(launch_rqi(L->n_coarse, a, st), "coarse eigensolve (LDS)");
   ctx->t_end(MLQMC_K_COARSE, 0.0);
-  CS(fine_update(ctx, o, L->n_fine, L->s_fine, Y, ldY, uH, lamH, L->n_coarse, n, lam, lin_iters,
-                 flags, "f_"));
+  CS(fine_update(ctx, o, L->n_fine, L->s_fine, Y, ldY, uH, lamH, L->n_coarse, n, lam, g,
+                 lin_iters, flags, "f_"));
   if (L->n_prev && lam_prev) {
-    if (L->n_prev == L->n_coarse && L->s_prev == L->s_coarse) {
+    if (degenerate) {
       // (A - lambda_H M) is singular on the coarse space itself: its update is lambda_H
       CK(hipMemcpyAsync(lam_prev, lamH, n * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
     } else {
       CS(fine_update(ctx, o, L->n_prev, L->s_prev, Y, ldY, uH, lamH, L->n_coarse, n, lam_prev,
-                     lin_iters, flags, "p_"));
+                     g_prev, lin_iters, flags, "p_"));
     }
   }
   return MLQMC_OK;
@@ -901,9 +942,10 @@ const char* mlqmc_last_error(const mlqmc_ctx* ctx) {
   return ctx ? ctx->err.c_str() : g_create_error.c_str();
 }
 
-mlqmc_status mlqmc_lattice_points(mlqmc_ctx* ctx, int64_t N, int32_t s, const int64_t* z,
-                                  const double* shift, int64_t k0, int64_t count, double* Y,
-                                  int32_t on_dev) {
+namespace {
+mlqmc_status lattice_entry(mlqmc_ctx* ctx, int64_t N, int32_t s, const int64_t* z,
+                           const double* shift, int64_t k0, int64_t count, double* Y,
+                           int32_t on_dev, bool embedded) {
   if (!ctx) return MLQMC_EINVAL;
   if (!is_pow2(N) || N > ((int64_t)1 << 30)) return ctx->fail(MLQMC_EINVAL, "N must be a power of two <= 2^30");
   if (s < 0 || count < 0 || k0 < 0 || k0 + count > N)
@@ -922,9 +964,25 @@ mlqmc_status mlqmc_lattice_points(mlqmc_ctx* ctx, int64_t N, int32_t s, const in
   CS(stage_in(ctx, "in_z", z, s, 0, &dz));
   CS(stage_in(ctx, "in_shift", shift, s, 0, &dsh));
   CS(out_buf(ctx, "out_Y", Y, (size_t)(count * s), on_dev, &dY));
-  CK(launch_lattice(N, s, dz, dsh, k0, count, dY, s, ctx->stream), "lattice");
+  if (embedded)
+    CK(launch_lattice_embedded(N, s, 1, dz, dsh, s, k0, count, dY, s, ctx->stream), "lattice");
+  else
+    CK(launch_lattice(N, s, dz, dsh, k0, count, dY, s, ctx->stream), "lattice");
   CS(stage_out(ctx, Y, dY, (size_t)(count * s), on_dev));
   return ctx->sync("lattice");
+}
+}  // namespace
+
+mlqmc_status mlqmc_lattice_points(mlqmc_ctx* ctx, int64_t N, int32_t s, const int64_t* z,
+                                  const double* shift, int64_t k0, int64_t count, double* Y,
+                                  int32_t on_dev) {
+  return lattice_entry(ctx, N, s, z, shift, k0, count, Y, on_dev, false);
+}
+
+mlqmc_status mlqmc_embedded_points(mlqmc_ctx* ctx, int64_t N, int32_t s, const int64_t* z,
+                                   const double* shift, int64_t k0, int64_t count, double* Y,
+                                   int32_t on_dev) {
+  return lattice_entry(ctx, N, s, z, shift, k0, count, Y, on_dev, true);
 }
 
 mlqmc_status mlqmc_coefficient(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B, const double* Y,
@@ -993,7 +1051,7 @@ mlqmc_status mlqmc_prolong(mlqmc_ctx* ctx, int32_t nH, int32_t nh, int64_t B, co
 mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* o,
                              int64_t n, const double* Y, int32_t warm, double* lam,
                              double* lam_prev, double* lam_coarse, int32_t* rq_iters,
-                             int32_t* lin_iters, uint8_t* flags) {
+                             int32_t* lin_iters, uint8_t* flags, double* g, double* g_prev) {
   if (!ctx) return MLQMC_EINVAL;
   CS(check_opts(ctx, o));
   CS(check_level(ctx, L));
@@ -1018,7 +1076,12 @@ mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_o
   if (rq_iters) CS(out_buf(ctx, "o_rq", rq_iters, n, dev, &dri));
   CS(out_buf(ctx, "o_li", lin_iters, n, dev && lin_iters, &dli));
   CS(out_buf(ctx, "o_fl", flags, n, dev, &dfl));
-  CS(level_core(ctx, L, o, n, dY, s, warm, dl, dlp, dlc, dri, dli, dfl));
+  double *dg = nullptr, *dgp = nullptr;
+  if (g) CS(out_buf(ctx, "o_g", g, n, dev, &dg));
+  if (g_prev && L->n_prev) CS(out_buf(ctx, "o_gp", g_prev, n, dev, &dgp));
+  CS(level_core(ctx, L, o, n, dY, s, warm, dl, dlp, dlc, dri, dli, dfl, dg, dgp));
+  if (dg) CS(stage_out(ctx, g, dg, n, dev));
+  if (dgp) CS(stage_out(ctx, g_prev, dgp, n, dev));
   CS(stage_out(ctx, lam, dl, n, dev));
   if (dlp) CS(stage_out(ctx, lam_prev, dlp, n, dev));
   if (dlc) CS(stage_out(ctx, lam_coarse, dlc, n, dev));
@@ -1034,7 +1097,7 @@ mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_o
 mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, const int64_t* N,
                             int32_t R, const int64_t* z, const double* shifts,
                             const mlqmc_opts* o, double* Q_lr, double* Qhat, double* V,
-                            double* est) {
+                            double* est, double* g_stats) {
   if (!ctx) return MLQMC_EINVAL;
   CS(check_opts(ctx, o));
   if (nl < 1 || !lv || !N || !z || !shifts || R < 1)
@@ -1064,6 +1127,10 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
   CS(out_buf(ctx, "e_Qh", Qhat, nl, dev, &dQh));
   CS(out_buf(ctx, "e_V", V, nl, dev, &dV));
   CS(out_buf(ctx, "e_est", est, 2, dev, &dest));
+  // G statistics: [Q_lr | Qhat | V | est] of the functional, same shapes
+  const size_t gsz = (size_t)nl * R + 2 * (size_t)nl + 2;
+  double* dG = nullptr;
+  if (g_stats) CS(out_buf(ctx, "e_G", g_stats, gsz, dev, &dG));
   bool flagged = false;
   zoff = soff = 0;
   for (int l = 0; l < nl; ++l) {
@@ -1085,26 +1152,204 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
     CS(ctx->getT("e_fl", n, &fl));
     CK(launch_lattice_multi(N[l], s, R, dz, dsh, N[l], Y, std::max(s, 1), st), "lattice");
     mlqmc_opts oo = *o;
-    // chains never cross a shift: chain length divides N_l
-    int chain = default_chain(N[l] * R, 1, o->chain_len, L.n_coarse ? L.n_coarse : L.n_fine,
-                              o->prec == MLQMC_MIXED ? 1 : 0);
-    int c2 = 1;
-    while (c2 < chain) c2 *= 2;
-    oo.chain_len = (int)std::min<int64_t>(c2, N[l]);
-    CS(level_core(ctx, &L, &oo, n, Y, std::max(s, 1), 1, lam, lamp, nullptr, rqi, lini, fl));
+    oo.chain_len = shift_chain(N[l], R, o, L.n_coarse ? L.n_coarse : L.n_fine);
+    double *gv = nullptr, *gp = nullptr;
+    if (dG) {
+      CS(ctx->getT("e_g", n, &gv));
+      if (L.n_prev) CS(ctx->getT("e_gp", n, &gp));
+    }
+    CS(level_core(ctx, &L, &oo, n, Y, std::max(s, 1), 1, lam, lamp, nullptr, rqi, lini, fl, gv,
+                  gp));
     CK(launch_level_sums(N[l], R, lam, lamp, dQ + (int64_t)l * R, st), "level sums");
+    if (dG) CK(launch_level_sums(N[l], R, gv, gp, dG + (int64_t)l * R, st), "level sums");
     bool any = false;
     CS(any_flag(ctx, fl, n, &any));
     flagged |= any;
     zoff += s;
     soff += (int64_t)R * s;
   }
-  CK(launch_estimator_final(nl, R, dQ, dQh, dV, dest, st), "estimator");
+  CK(launch_estimator_final(nl, R, dQ, dQh, dV, dest, 0, st), "estimator");
+  if (dG) {
+    double* q = dG + (size_t)nl * R;
+    CK(launch_estimator_final(nl, R, dG, q, q + nl, q + 2 * nl, 0, st), "estimator");
+  }
   CS(stage_out(ctx, Q_lr, dQ, (size_t)nl * R, dev));
   CS(stage_out(ctx, Qhat, dQh, nl, dev));
   CS(stage_out(ctx, V, dV, nl, dev));
   CS(stage_out(ctx, est, dest, 2, dev));
+  if (dG) CS(stage_out(ctx, g_stats, dG, gsz, dev));
   CS(ctx->sync("estimate"));
+  return flagged ? ctx->fail(MLQMC_ENOCONV, "at least one sample is flagged") : MLQMC_OK;
+}
+
+mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv,
+                                   const int64_t* N, int32_t R, const int64_t* z,
+                                   const double* shifts, const mlqmc_opts* o, double* Q_lr,
+                                   double* Qhat, double* V, double* est, double* lam_out,
+                                   double* g_stats) {
+  if (!ctx) return MLQMC_EINVAL;
+  CS(check_opts(ctx, o));
+  if (nl < 1 || !lv || !N || !z || !shifts || R < 1)
+    return ctx->fail(MLQMC_EINVAL, "need n_levels >= 1, R >= 1 and non-NULL inputs");
+  if (!Q_lr || !Qhat || !V || !est) return ctx->fail(MLQMC_EINVAL, "NULL output");
+  int s_max = 0;
+  int64_t total = 0, ymax = 0;
+  for (int l = 0; l < nl; ++l) {
+    CS(check_level(ctx, &lv[l]));
+    if (!is_pow2(N[l]) || N[l] > ((int64_t)1 << 30))
+      return ctx->fail(MLQMC_EINVAL, "N[%d] must be a power of two <= 2^30", l);
+    if (l > 0 && N[l] > N[l - 1])
+      return ctx->fail(MLQMC_EINVAL, "N must not increase with the level (N[%d] > N[%d])", l,
+                       l - 1);
+    s_max = std::max(s_max, (int)lv[l].s_fine);
+    total += (int64_t)R * N[l];
+    ymax = std::max<int64_t>(ymax, (int64_t)R * N[l] * std::max(1, (int)lv[l].s_fine));
+  }
+  const mlqmc_level& L0 = lv[0];
+  if (L0.n_coarse != 0 || L0.n_prev != 0)
+    return ctx->fail(MLQMC_EINVAL, "level 0 must be direct with no previous term");
+  for (int l = 1; l < nl; ++l) {
+    if (lv[l].n_coarse != L0.n_fine || lv[l].s_coarse != L0.s_fine)
+      return ctx->fail(MLQMC_EINVAL, "level %d: coarse mesh and truncation must be level 0's", l);
+    if (lv[l].n_prev != lv[l - 1].n_fine || lv[l].s_prev != lv[l - 1].s_fine)
+      return ctx->fail(MLQMC_EINVAL, "level %d: previous term must be on level %d's mesh", l,
+                       l - 1);
+  }
+  for (int j = 0; j < s_max; ++j)
+    if (z[j] < 0 || z[j] >= N[0]) return ctx->fail(MLQMC_EINVAL, "z[%d] outside [0, N[0])", j);
+  for (int64_t k = 0; k < (int64_t)R * s_max; ++k)
+    if (!(shifts[k] >= 0.0 && shifts[k] < 1.0))
+      return ctx->fail(MLQMC_EINVAL, "shift entry %lld outside [0, 1)", (long long)k);
+  ctx->mem_cap = o->device_mem_cap;
+  hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+  const int dev = o->io_on_device;
+  double *dQ, *dQh, *dV, *dest, *dlo = nullptr;
+  CS(out_buf(ctx, "e_Q", Q_lr, (size_t)nl * R, dev, &dQ));
+  CS(out_buf(ctx, "e_Qh", Qhat, nl, dev, &dQh));
+  CS(out_buf(ctx, "e_V", V, nl, dev, &dV));
+  CS(out_buf(ctx, "e_est", est, 2, dev, &dest));
+  if (lam_out) CS(out_buf(ctx, "e_lamout", lam_out, (size_t)total, dev, &dlo));
+  const size_t gsz = (size_t)nl * R + 2 * (size_t)nl + 2;
+  double *dG = nullptr, *g0 = nullptr;
+  if (g_stats) CS(out_buf(ctx, "e_G", g_stats, gsz, dev, &dG));
+  const int64_t* dz;
+  const double* dsh;
+  CS(stage_in(ctx, "e_z", z, s_max, 0, &dz));
+  CS(stage_in(ctx, "e_sh", shifts, (size_t)R * s_max, 0, &dsh));
+  const int64_t N0 = N[0], B0 = (int64_t)R * N0;
+  const int n0 = L0.n_fine, s0 = L0.s_fine;
+  const int64_t D0 = (int64_t)(n0 - 1) * (n0 - 1);
+  double *Y, *lam0, *u0 = nullptr;
+  int *rqi, *lini;
+  uint8_t* fl;
+  CS(ctx->getT("n_Y", (size_t)ymax, &Y));
+  CS(ctx->getT("n_lam0", B0, &lam0));
+  if (nl > 1) CS(ctx->getT("n_u0", (size_t)(B0 * D0), &u0));
+  CS(ctx->getT("n_rq", B0, &rqi));
+  CS(ctx->getT("n_li", B0, &lini));
+  CS(ctx->getT("n_fl", B0, &fl));
+  if (dG) CS(ctx->getT("n_g0", B0, &g0));
+  bool flagged = false;
+  // level 0: direct eigenpairs of all N_0 points of every shift; the
+  // eigenvectors are the coarse pairs of the levels above
+  CK(hipMemsetAsync(fl, 0, B0, st), "memset");
+  CK(hipMemsetAsync(lini, 0, B0 * sizeof(int), st), "memset");
+  CK(launch_lattice_embedded(N0, s0, R, dz, dsh, s_max, 0, N0, Y, std::max(s0, 1), st),
+     "lattice");
+  {
+    Table* tb = nullptr;
+    CS(ctx->table(n0, s0, &tb));
+    const int chain = shift_chain(N0, R, o, n0);
+    RqiArgs a = rqi_base(ctx, o, B0, Y, std::max(s0, 1), chain, 1, rqi, lini, fl);
+    a.S = s0;
+    a.phi = tb->pad;
+    a.lam = lam0;
+    a.u_out = u0;
+    a.g_out = g0;
+    if (const int64_t per = rqi_scratch_doubles(n0)) {
+      a.scratch_doubles = per * ((B0 + chain - 1) / chain);
+      CS(ctx->getT("rqi_scratch", a.scratch_doubles, &a.scratch));
+    }
+    ctx->t_begin(MLQMC_K_COARSE);
+    CK(launch_rqi(n0, a, st), "eigensolve (LDS)");
+    ctx->t_end(MLQMC_K_COARSE, 0.0);
+  }
+  CK(launch_level_sums(N0, R, lam0, nullptr, dQ, st), "level sums");
+  if (dG) CK(launch_level_sums(N0, R, g0, nullptr, dG, st), "level sums");
+  if (dlo) CK(hipMemcpyAsync(dlo, lam0, B0 * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+  {
+    bool any = false;
+    CS(any_flag(ctx, fl, B0, &any));
+    flagged |= any;
+  }
+  // levels l >= 1: the two-grid update from the level-0 pair of the same
+  // point (the first N_l points of each shift), minus level l-1's value there
+  const double* prev = lam0;
+  const double* gprev = g0;
+  int64_t Nprev = N0, off = B0;
+  // the first Nl of every shift's Ncur entries (rows of `width` elements)
+  auto leading = [&](const double* src, int64_t Ncur, int64_t Nl, int64_t width,
+                     const char* name, const double** out) -> mlqmc_status {
+    if (Nl == Ncur) {
+      *out = src;
+      return MLQMC_OK;
+    }
+    double* dst = nullptr;
+    CS(ctx->getT(name, (size_t)(R * Nl * width), &dst));
+    CK(hipMemcpy2DAsync(dst, Nl * width * sizeof(double), src, Ncur * width * sizeof(double),
+                        Nl * width * sizeof(double), R, hipMemcpyDeviceToDevice, st),
+       "gather");
+    *out = dst;
+    return MLQMC_OK;
+  };
+  for (int l = 1; l < nl; ++l) {
+    const mlqmc_level& L = lv[l];
+    const int64_t Nl = N[l], Bl = (int64_t)R * Nl;
+    const int sl = L.s_fine;
+    const double *uH, *lamH, *lamP;
+    double* lam = nullptr;
+    CS(ctx->getT((l & 1) ? "n_lamA" : "n_lamB", Bl, &lam));
+    CS(leading(u0, N0, Nl, D0, "n_uH", &uH));
+    CS(leading(lam0, N0, Nl, 1, "n_lamH", &lamH));
+    CS(leading(prev, Nprev, Nl, 1, "n_lamP", &lamP));
+    double* gl = nullptr;
+    const double* gP = nullptr;
+    if (dG) {
+      CS(ctx->getT((l & 1) ? "n_gA" : "n_gB", Bl, &gl));
+      CS(leading(gprev, Nprev, Nl, 1, "n_gP", &gP));
+    }
+    CK(launch_lattice_embedded(N0, sl, R, dz, dsh, s_max, 0, Nl, Y, std::max(sl, 1), st),
+       "lattice");
+    CK(hipMemsetAsync(fl, 0, Bl, st), "memset");
+    CK(hipMemsetAsync(lini, 0, Bl * sizeof(int), st), "memset");
+    CS(fine_update(ctx, o, L.n_fine, sl, Y, std::max(sl, 1), uH, lamH, n0, Bl, lam, gl, lini,
+                   fl, "f_"));
+    CK(launch_level_sums(Nl, R, lam, lamP, dQ + (int64_t)l * R, st), "level sums");
+    if (dG) CK(launch_level_sums(Nl, R, gl, gP, dG + (int64_t)l * R, st), "level sums");
+    if (dlo)
+      CK(hipMemcpyAsync(dlo + off, lam, Bl * sizeof(double), hipMemcpyDeviceToDevice, st),
+         "copy");
+    bool any = false;
+    CS(any_flag(ctx, fl, Bl, &any));
+    flagged |= any;
+    prev = lam;
+    gprev = gl;
+    Nprev = Nl;
+    off += Bl;
+  }
+  CK(launch_estimator_final(nl, R, dQ, dQh, dV, dest, 1, st), "estimator");
+  if (dG) {
+    double* q = dG + (size_t)nl * R;
+    CK(launch_estimator_final(nl, R, dG, q, q + nl, q + 2 * nl, 1, st), "estimator");
+  }
+  CS(stage_out(ctx, Q_lr, dQ, (size_t)nl * R, dev));
+  CS(stage_out(ctx, Qhat, dQh, nl, dev));
+  CS(stage_out(ctx, V, dV, nl, dev));
+  CS(stage_out(ctx, est, dest, 2, dev));
+  if (dlo) CS(stage_out(ctx, lam_out, dlo, (size_t)total, dev));
+  if (dG) CS(stage_out(ctx, g_stats, dG, gsz, dev));
+  CS(ctx->sync("estimate_nested"));
   return flagged ? ctx->fail(MLQMC_ENOCONV, "at least one sample is flagged") : MLQMC_OK;
 }
 

@@ -903,7 +903,8 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
 
 // ---------------------------------------------------------------- final
 
-// w = vs v + t (FP64): partials w.A w, w.M12 w with FP64 weights
+// w = vs v + t (FP64): partials w.A w, w.M12 w with FP64 weights, and the
+// sum of w (h^2 times it is the integral of the P1 function w)
 template <typename T, int NTC>
 __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, const double* __restrict__ v,
                                                     const T* __restrict__ t,
@@ -925,7 +926,7 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, const double* __rest
   const double vs = S.vs[b];
   const double* wx = w + b * 2 * g.P;
   const double* wy = wx + g.P;
-  double s[2] = {0.0, 0.0};
+  double s[3] = {0.0, 0.0, 0.0};
   struct Fin {
     double v;
     T t, p;
@@ -939,8 +940,9 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, const double* __rest
         const double aw = ring_Aw(rs, rc, rn, ci, wt);
         s[0] += rc[ci] * aw;
         s[1] += rc[ci] * ring_M12(rs, rc, rn, ci);
+        s[2] += rc[ci];
       });
-  write_partials_m<NTC, 2>(s, part, b, blk, g.nblk);
+  write_partials_m<NTC, 3>(s, part, b, blk, g.nblk);
 }
 
 // one wavefront per sample: sum the sample's block partials in fixed order
@@ -951,7 +953,7 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
   const int lane = threadIdx.x & 63;
   if (b >= B) return;
   int K = 3;
-  if (phase == PH_SETUP || phase == PH_FINAL) K = 2;
+  if (phase == PH_SETUP) K = 2;
   if (phase == PH_ALPHA) K = 6;
   if ((phase == PH_ALPHA || phase == PH_BETA) && !S.active[b]) return;
   double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1044,9 +1046,10 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
       S.c2[b] = s[1];
       break;
     }
-    case PH_FINAL: {  // s0 = w.Aw, s1 = w.M12w
+    case PH_FINAL: {  // s0 = w.Aw, s1 = w.M12w, s2 = sum of w
       const double lam = s[0] / (s[1] * hm);
       S.lam[b] = lam;
+      if (S.g) S.g[b] = fabs(s[2]) / ((double)n * n * sqrt(s[1] * hm));
       if (S.lin_acc) S.lin_acc[b] += S.its[b];
       if (!isfinite(lam)) S.flags[b] |= MLQMC_FLAG_NONFINITE;
       break;

@@ -93,6 +93,22 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* 
     }
     if (!conv) fl |= MLQMC_FLAG_RQ_NOCONV;
     if (!isfinite(sigma)) fl |= MLQMC_FLAG_NONFINITE;
+    if (A.g_out) {
+      // G is linear in the vector: one correction solve at the converged
+      // sigma to the linear tolerance (a Newton step) makes the vector as
+      // accurate as the two-grid ones; lambda stays the converged sigma
+      if (conv && A.g_lin_rtol > 0.0) {
+        bool c, b;
+        lin += lds::jd_pcg<NT, N>(a, sigma, sigma, A.g_lin_rtol, A.max_lin, &c, &b);
+        if (!c) fl |= MLQMC_FLAG_LIN_NOCONV;
+        LDS_FOR_NODES(NT, N, k) s_v[k] += a.t[k];
+        __syncthreads();
+      }
+      double sm, mn;
+      lds::sum_and_mnorm<NT, N>(a, s_v, sm, mn);
+      if (threadIdx.x == 0) A.g_out[i] = fabs(sm) / ((double)N * N * sqrt(mn));
+      lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(mn));
+    }
     const double ov = sine_overlap<NT, N>(s_v, a.red);
     if (!(ov >= 0.5)) fl |= MLQMC_FLAG_WRONG_PAIR;
     if (threadIdx.x == 0) {
@@ -229,6 +245,11 @@ __global__ __launch_bounds__(NT, (N >= 32 && sizeof(T) == 8) ? 2 : 4) void k_tg_
     __syncthreads();
     lds::rayleigh_parts<NT, N>(a, s_v, wf, vMv, vAv);
     const double lam = vAv / vMv;
+    if (A.g) {
+      double sm, mn;
+      lds::sum_and_mnorm<NT, N>(a, s_v, sm, mn);
+      if (threadIdx.x == 0) A.g[i] = fabs(sm) / ((double)N * N * sqrt(mn));
+    }
     if (threadIdx.x == 0) {
       A.lam[i] = lam;
       if (A.lin_iters) A.lin_iters[i] += its;

@@ -21,11 +21,15 @@ __device__ __forceinline__ double lattice_coord(int64_t k, int64_t z, int64_t N,
   return u - 0.5;
 }
 
+// Points k0 + i, i < count, of R shifted rules: Y[(r count + i) ldY + j] for
+// j < s, shift r at shifts[r sld + j].  rad_bits = 0: natural order k;
+// rad_bits = m > 0 (N = 2^m): the embedded base-2 order, index = the m-bit
+// reversal of k, so every prefix of 2^m' points is the 2^m'-point lattice.
 __global__ __launch_bounds__(256) void k_lattice(int64_t N, double invN, int s, int R,
                                                  const int64_t* __restrict__ z,
-                                                 const double* __restrict__ shifts, int64_t k0,
-                                                 int64_t count, double* __restrict__ Y,
-                                                 int64_t ldY) {
+                                                 const double* __restrict__ shifts, int64_t sld,
+                                                 int64_t k0, int64_t count, double* __restrict__ Y,
+                                                 int64_t ldY, int rad_bits) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t total = (int64_t)R * count * s;
   if (idx >= total) return;
@@ -33,7 +37,9 @@ __global__ __launch_bounds__(256) void k_lattice(int64_t N, double invN, int s, 
   const int64_t row = idx / s;  // r * count + i
   const int r = (int)(row / count);
   const int64_t i = row - (int64_t)r * count;
-  Y[row * ldY + j] = lattice_coord(k0 + i, z[j], N, invN, shifts[(int64_t)r * s + j]);
+  int64_t k = k0 + i;
+  if (rad_bits > 0) k = (int64_t)(__brevll((unsigned long long)k) >> (64 - rad_bits));
+  Y[row * ldY + j] = lattice_coord(k, z[j], N, invN, shifts[(int64_t)r * sld + j]);
 }
 
 __global__ __launch_bounds__(256) void k_phi_elements(int n, int s, const double* __restrict__ c,
@@ -225,9 +231,12 @@ __global__ __launch_bounds__(256) void k_level_sums(int64_t N, const double* __r
   if (threadIdx.x == 0) Q[r] = s[0] / (double)N;
 }
 
+// Qhat_l, V_l (eq. sample_var) and Q^ML = sum_l Qhat_l; est[1] = sum_l V_l, or
+// with shared = 1 (one set of shifts for all levels) the sample variance of
+// the per-shift totals sum_l Q_l^(r)
 __global__ void k_estimator_final(int L, int R, const double* __restrict__ Q,
                                   double* __restrict__ Qhat, double* __restrict__ V,
-                                  double* __restrict__ est) {
+                                  double* __restrict__ est, int shared) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double qml = 0.0, vml = 0.0;
   for (int l = 0; l < L; ++l) {
@@ -245,10 +254,37 @@ __global__ void k_estimator_final(int L, int R, const double* __restrict__ Q,
     qml += qh;
     vml += v;
   }
+  if (shared) {
+    vml = NAN;
+    if (R > 1) {
+      double m = 0.0;
+      for (int r = 0; r < R; ++r) {
+        double t = 0.0;
+        for (int l = 0; l < L; ++l) t += Q[l * R + r];
+        m += t;
+      }
+      m /= R;
+      double d = 0.0;
+      for (int r = 0; r < R; ++r) {
+        double t = 0.0;
+        for (int l = 0; l < L; ++l) t += Q[l * R + r];
+        d += (m - t) * (m - t);
+      }
+      vml = d / ((double)R * (R - 1));
+    }
+  }
   est[0] = qml;
   est[1] = vml;
 }
 
+}  // namespace
+
+namespace {
+int log2_exact(int64_t N) {
+  int m = 0;
+  while (((int64_t)1 << m) < N) ++m;
+  return m;
+}
 }  // namespace
 
 hipError_t launch_lattice(int64_t N, int s, const int64_t* z_dev, const double* shift_dev,
@@ -256,7 +292,8 @@ hipError_t launch_lattice(int64_t N, int s, const int64_t* z_dev, const double* 
   const int64_t total = count * s;
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_lattice, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, N,
-                     ldexp(1.0, -(int)log2((double)N)), s, 1, z_dev, shift_dev, k0, count, Y, ldY);
+                     ldexp(1.0, -log2_exact(N)), s, 1, z_dev, shift_dev, (int64_t)s, k0, count, Y,
+                     ldY, 0);
   return hipGetLastError();
 }
 
@@ -266,8 +303,19 @@ hipError_t launch_lattice_multi(int64_t N, int s, int R, const int64_t* z_dev,
   const int64_t total = (int64_t)R * count * s;
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_lattice, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, N,
-                     ldexp(1.0, -(int)log2((double)N)), s, R, z_dev, shifts_dev, (int64_t)0,
-                     count, Y, ldY);
+                     ldexp(1.0, -log2_exact(N)), s, R, z_dev, shifts_dev, (int64_t)s, (int64_t)0,
+                     count, Y, ldY, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_lattice_embedded(int64_t N, int s, int R, const int64_t* z_dev,
+                                   const double* shifts_dev, int64_t sld, int64_t k0,
+                                   int64_t count, double* Y, int64_t ldY, hipStream_t st) {
+  const int64_t total = (int64_t)R * count * s;
+  if (total <= 0) return hipSuccess;
+  const int m = log2_exact(N);
+  hipLaunchKernelGGL(k_lattice, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, N,
+                     ldexp(1.0, -m), s, R, z_dev, shifts_dev, sld, k0, count, Y, ldY, m);
   return hipGetLastError();
 }
 
@@ -319,8 +367,8 @@ hipError_t launch_level_sums(int64_t N, int R, const double* lam, const double* 
 }
 
 hipError_t launch_estimator_final(int L, int R, const double* Q, double* Qhat, double* V,
-                                  double* est, hipStream_t st) {
-  hipLaunchKernelGGL(k_estimator_final, dim3(1), dim3(64), 0, st, L, R, Q, Qhat, V, est);
+                                  double* est, int shared, hipStream_t st) {
+  hipLaunchKernelGGL(k_estimator_final, dim3(1), dim3(64), 0, st, L, R, Q, Qhat, V, est, shared);
   return hipGetLastError();
 }
 

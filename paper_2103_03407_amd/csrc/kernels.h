@@ -27,6 +27,10 @@ struct RqiArgs {
   int* rq_iters;        // [n] or nullptr
   int* lin_iters;       // [n] or nullptr
   uint8_t* flags;       // [n]
+  double* g_out;        // [n] G(u) = integral of the M-normalised eigenvector, sign
+                        // fixed positive, or nullptr; then each converged vector is
+                        // first refined by one correction solve to g_lin_rtol (0: not)
+  double g_lin_rtol;
   double* scratch;      // meshes above 1/32: per-chain global scratch
   int64_t scratch_doubles;
   int mixed;            // 1: FP32 vectors, weights and V-cycle (meshes up to 1/32)
@@ -52,6 +56,7 @@ struct TgSmallArgs {
   int mixed;            // 1: FP32 vectors, weights and V-cycle
   int max_lin;
   double* lam;          // [n] two-grid value
+  double* g;            // [n] G of the two-grid eigenvector (integral, normalised), or nullptr
   int* lin_iters;       // [n] added to, or nullptr
   uint8_t* flags;       // [n] OR-ed
 };
@@ -75,6 +80,7 @@ struct FineState {      // per-sample scalars of the projected PCG, arrays of le
   // f = w^T (A - mu M) w, m = w^T M w; dmp = the previous step's change of m,
   // rzp = the previous r.z (for the observed contraction)
   double *f, *m, *dmp, *rzp;
+  double* g;            // G(w / ||w||_M) = |integral of w| / ||w||_M at the end, or nullptr
   int* its;
   int* lin_acc;         // per-sample PCG iteration totals, added to at the end (or nullptr)
   uint8_t* active;      // the sample still takes PCG steps
@@ -150,6 +156,11 @@ hipError_t launch_lattice(int64_t N, int s, const int64_t* z_dev, const double* 
 hipError_t launch_lattice_multi(int64_t N, int s, int R, const int64_t* z_dev,
                                 const double* shifts_dev, int64_t count, double* Y,
                                 int64_t ldY, hipStream_t st);
+// the embedded base-2 order (N = 2^m): point k0 + i is lattice point
+// rev_m(k0 + i); rows r * count + i, shift r at shifts_dev[r * sld ...]
+hipError_t launch_lattice_embedded(int64_t N, int s, int R, const int64_t* z_dev,
+                                   const double* shifts_dev, int64_t sld, int64_t k0,
+                                   int64_t count, double* Y, int64_t ldY, hipStream_t st);
 // element table phi[j][e] = c_j sin(pi k1_j xc_e) sin(pi k2_j yc_e), e < 2n^2
 hipError_t launch_phi_elements(int n, int s, const double* c, const int* k1, const int* k2,
                                double* phi, hipStream_t st);
@@ -167,8 +178,9 @@ hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t l
 // lam_prev may be nullptr (lambda^{-1} = 0)
 hipError_t launch_level_sums(int64_t N, int R, const double* lam, const double* lam_prev,
                              double* Q, hipStream_t st);
-// Qhat, V, est from Q [L x R]
+// Qhat, V, est from Q [L x R]; shared = 1: est[1] is the variance of the
+// per-shift totals (one set of shifts for all levels) instead of sum_l V_l
 hipError_t launch_estimator_final(int L, int R, const double* Q, double* Qhat, double* V,
-                                  double* est, hipStream_t st);
+                                  double* est, int shared, hipStream_t st);
 
 }  // namespace mlqmc

@@ -281,6 +281,22 @@ MLQMC_DEV void rayleigh_parts(const PcgArrays<T>& a, const T* x, const WF& wf, d
   xAx = s[1];
 }
 
+// sum of the nodal values and x^T M x, both in FP64: the integral of the P1
+// function with these nodal values is h^2 times the sum (each hat function
+// integrates to h^2 on this mesh)
+template <int NT, int n, typename T>
+MLQMC_DEV void sum_and_mnorm(const PcgArrays<T>& a, const T* x, double& sum, double& xMx) {
+  double s[2] = {0.0, 0.0};
+  LDS_FOR_NODES(NT, n, k) {
+    const double xc = (double)x[k];
+    s[0] += xc;
+    s[1] += xc * pM12d<n>(x, k);
+  }
+  block_sums<NT, 2>(s, a.red);
+  sum = s[0];
+  xMx = s[1] * mass_scale(n);
+}
+
 template <int NT, int n, typename T>
 MLQMC_DEV void scale_vec(T* x, double f) {
   LDS_FOR_NODES(NT, n, k) x[k] = (T)((double)x[k] * f);

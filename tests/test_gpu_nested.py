@@ -1,0 +1,247 @@
+"""GPU parity of the nested estimator with shared shifts (end of section 4.3)
+and of the embedded base-2 lattice points, through the C ABI, against the
+FP64 oracle.
+
+Tolerances: points bit-exact (the same IEEE operations); eigenvalues
+relative 1e-10 per sample in FP64 and 1e-8 in mixed precision; level means
+and variances to the rounding those per-sample errors allow.
+"""
+
+import numpy as np
+import pytest
+
+import paper_2103_03407_amd as m
+from oracle import mlqmc, qmc, twogrid
+from synth import CONFIGS, LevelSpec, coeff_family, lattice_vector, shifts_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fam():
+    return coeff_family(512, decay=2.5)
+
+
+@pytest.fixture(scope="module")
+def ctx(fam):
+    c = m.Context(fam)
+    yield c
+    c.close()
+
+
+def _lv6(lv):
+    return (lv.n_fine, lv.s_fine, lv.n_coarse, lv.s_coarse, lv.n_prev, lv.s_prev)
+
+
+@pytest.mark.parametrize("N,s,k0,count", [(1024, 16, 0, 1024), (16384, 32, 5000, 333),
+                                          (8, 2, 0, 8), (1, 3, 0, 1)])
+def test_embedded_points_bit_exact(ctx, N, s, k0, count):
+    z = lattice_vector(1024, 64)[:s] % N
+    sh = shifts_for(12, 0, 1, s)[0]
+    Y = np.empty((count, s))
+    ctx.embedded_points(N, z, sh, k0, count, Y)
+    ref = np.array([qmc.embedded_point(z, N, sh, k) for k in range(k0, k0 + count)])
+    assert np.array_equal(Y, ref)
+
+
+def _small_levels(N):
+    # direct on 1/8 (s_0 = 4); two-grid from it on 1/16 and 1/32 (LDS
+    # kernels) and 1/64 (batched kernels)
+    return [LevelSpec(8, 4, 0, 0, 0, 0, N[0]), LevelSpec(16, 6, 8, 4, 8, 4, N[1]),
+            LevelSpec(32, 8, 8, 4, 16, 6, N[2]), LevelSpec(64, 8, 8, 4, 32, 8, N[3])]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_nested_estimate_matches_oracle(ctx, fam, prec, tol):
+    N = [16, 8, 8, 4]
+    levels = _small_levels(N)
+    R = 2
+    z = lattice_vector(64, 8) % N[0]
+    shifts = shifts_for(13, 0, R, 8)
+    o = m.default_opts(prec=m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED)
+    st, Q, Qh, V, est, lam = ctx.estimate_nested([_lv6(l) for l in levels], N, R, z, shifts,
+                                                 opts=o, lam_out=True)
+    assert st == m.MLQMC_OK
+    for r in range(R):
+        ref = mlqmc.nested_values(levels, z, N, shifts[r], fam)
+        for l in range(4):
+            assert np.max(np.abs(lam[l][r] - ref[l]) / ref[l]) <= tol, (l, r)
+    ref = mlqmc.estimate_nested(levels, z, N, shifts, fam)
+    scale = ref.Qhat[0]
+    assert np.max(np.abs(Q - ref.Q_lr)) <= 4 * tol * scale
+    assert np.max(np.abs(Qh - ref.Qhat)) <= 4 * tol * scale
+    assert abs(est[0] - ref.Q_ml) <= 4 * tol * scale
+    assert np.max(np.abs(np.sqrt(V) - np.sqrt(ref.V))) <= 8 * tol * scale
+    assert abs(np.sqrt(est[1]) - np.sqrt(ref.V_ml)) <= 8 * tol * scale
+    # the shared-shift variance is bounded by (L+1) sum_l V_l
+    assert est[1] <= 4 * V.sum() * (1 + 1e-12)
+
+
+def test_nested_level_terms_reduce_lam_out(ctx):
+    # Q_l^(r) is the mean of lambda^l - lambda^{l-1} over the first N_l points
+    N = [32, 16, 8, 8]
+    levels = _small_levels(N)
+    R = 3
+    z = lattice_vector(64, 8) % N[0]
+    shifts = shifts_for(14, 0, R, 8)
+    st, Q, Qh, V, est, lam = ctx.estimate_nested([_lv6(l) for l in levels], N, R, z, shifts,
+                                                 lam_out=True)
+    assert st == m.MLQMC_OK
+    for l in range(4):
+        for r in range(R):
+            prev = lam[l - 1][r, :N[l]] if l else 0.0
+            want = np.mean(lam[l][r] - prev)
+            assert abs(Q[l, r] - want) <= 1e-13 * lam[0].max()
+    tot = Q.sum(axis=0)
+    assert abs(est[1] - np.var(tot, ddof=1) / R) <= 1e-10 * np.var(tot)
+    assert abs(est[0] - Qh.sum()) <= 1e-13 * abs(est[0])
+
+
+def test_nested_single_level_and_single_shift(ctx, fam):
+    lv = LevelSpec(16, 8, 0, 0, 0, 0, 8)
+    z = lattice_vector(64, 8) % 8
+    shifts = shifts_for(15, 0, 1, 8)
+    st, Q, Qh, V, est, lam = ctx.estimate_nested([_lv6(lv)], [8], 1, z, shifts, lam_out=True)
+    assert st == m.MLQMC_OK
+    assert np.isnan(V[0]) and np.isnan(est[1])
+    pts = qmc.embedded_points(z, 8, shifts[0], 8)
+    ref = np.array([twogrid.direct(16, 8, y, fam)[0] for y in pts])
+    assert np.max(np.abs(lam[0][0] - ref) / ref) <= 1e-10
+
+
+@pytest.mark.parametrize("case", ["coarse_not_level0", "prev_not_previous", "N_increases",
+                                  "level0_two_grid", "z_out_of_range"])
+def test_nested_rejects_other_level_lists(ctx, case):
+    N = [8, 8, 4, 4]
+    levels = [_lv6(l) for l in _small_levels(N)]
+    z = lattice_vector(64, 8) % N[0]
+    shifts = shifts_for(16, 0, 2, 8)
+    if case == "coarse_not_level0":
+        levels[2] = (32, 8, 16, 6, 16, 6)
+    elif case == "prev_not_previous":
+        levels[3] = (64, 8, 8, 4, 16, 6)
+    elif case == "N_increases":
+        N = [8, 8, 4, 8]
+    elif case == "level0_two_grid":
+        levels[0] = (8, 4, 4, 2, 0, 0)
+    else:
+        z = z.copy()
+        z[3] = N[0]
+    with pytest.raises(m.MlqmcError) as e:
+        ctx.estimate_nested(levels, N, 2, z, shifts)
+    assert e.value.code == m.MLQMC_EINVAL
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_nested_five_level_workload_sampled(ctx, fam, prec, tol):
+    # the full nested five-level workload (h = 1/16 .. 1/256, N_l = 2^14 ..
+    # 2^8, R = 8); sampled points against the oracle
+    w = CONFIGS[6]
+    levels = list(w.levels)
+    N = [lv.N for lv in levels]
+    z, shifts = w.z_shared(), w.shifts_shared()
+    o = m.default_opts(prec=m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED)
+    st, Q, Qh, V, est, lam = ctx.estimate_nested([_lv6(l) for l in levels], N, w.R, z, shifts,
+                                                 opts=o, lam_out=True)
+    assert st == m.MLQMC_OK
+    rng = np.random.default_rng(6)
+    l0 = levels[0]
+    for l in range(len(levels)):
+        for _ in range(3 if l < 4 else 2):
+            r, k = int(rng.integers(w.R)), int(rng.integers(N[l]))
+            y = qmc.embedded_point(z, N[0], shifts[r], k)
+            lam0, u0 = twogrid.direct(l0.n_fine, l0.s_fine, y, fam)
+            if l == 0:
+                want = lam0
+            else:
+                lv = levels[l]
+                want = twogrid.two_grid_update(lv.n_fine, lv.s_fine, y, fam, lam0, u0,
+                                               l0.n_fine)[0]
+            assert abs(lam[l][r, k] - want) <= tol * want, (l, r, k)
+    assert np.all(np.isfinite(Q)) and np.isfinite(est[0]) and est[1] > 0
+
+
+# ---------------- the eigenfunction functional G(u) ----------------
+
+G_TOL = {"fp64": 1e-9, "mixed": 1e-7}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("lv", [(32, 16, 0, 0, 16, 8), (32, 32, 8, 16, 16, 16),
+                                (128, 64, 32, 8, 64, 32), (64, 64, 8, 16, 32, 32),
+                                (64, 64, 8, 16, 8, 16)])
+def test_functional_per_sample(ctx, fam, lv, prec):
+    # G of the level's eigenvector approximation and of the level-(l-1) one:
+    # direct levels, LDS and batched two-grid updates, the degenerate
+    # previous mesh (its eigenvector is u_H)
+    spec = LevelSpec(*lv, 0)
+    n = 40
+    z = lattice_vector(1024, 64)[:lv[1]]
+    sh = shifts_for(17, 0, 1, lv[1])[0]
+    Y = qmc.lattice_points(z, 1024, sh, range(n))
+    lam, lamp = np.empty(n), np.empty(n)
+    g, gp = np.empty(n), np.empty(n)
+    fl = np.zeros(n, np.uint8)
+    o = m.default_opts(prec=m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED)
+    ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp, opts=o, g=g, g_prev=gp)
+    assert not fl.any()
+    tol = G_TOL[prec]
+    lam_tol = 1e-10 if prec == "fp64" else 1e-8
+    for k in (0, 1, 17, n - 1):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(g[k] - v.G) <= tol * v.G, (k, g[k], v.G)
+        assert abs(gp[k] - v.G_prev) <= tol * v.G_prev, (k, gp[k], v.G_prev)
+        assert abs(lam[k] - v.lam) <= lam_tol * v.lam
+
+
+def test_functional_does_not_change_lambda_much(ctx):
+    # asking for G refines the vectors and runs the two-grid solves to the
+    # residual test: eigenvalues move only within their accuracy
+    lv = (128, 64, 32, 8, 0, 0)
+    n = 64
+    z = lattice_vector(1024, 64)
+    Y = qmc.lattice_points(z, 1024, shifts_for(18, 0, 1, 64)[0], range(n))
+    lam0, lam1, g = np.empty(n), np.empty(n), np.empty(n)
+    fl = np.zeros(n, np.uint8)
+    ctx.eig_level(lv, Y, lam0, fl)
+    ctx.eig_level(lv, Y, lam1, fl, g=g)
+    assert np.max(np.abs(lam1 - lam0) / lam0) < 2e-11
+    assert np.all((g > 0.5) & (g < 1.0))
+
+
+def test_functional_estimate_matches_oracle(ctx, fam):
+    levels = [LevelSpec(16, 8, 0, 0, 0, 0, 8), LevelSpec(32, 16, 8, 8, 16, 8, 4),
+              LevelSpec(64, 16, 8, 8, 32, 16, 4)]
+    R = 2
+    zs = [lattice_vector(1024, 64)[:lv.s_fine] % lv.N for lv in levels]
+    shs = [shifts_for(19, l, R, lv.s_fine) for l, lv in enumerate(levels)]
+    Ns = [lv.N for lv in levels]
+    st, Q, Qh, V, est, (QG, QhG, VG, estG) = ctx.estimate([_lv6(l) for l in levels], Ns, R,
+                                                          zs, shs, functional=True)
+    assert st == m.MLQMC_OK
+    ref, refG = mlqmc.estimate(levels, zs, Ns, shs, fam, with_G=True)
+    assert np.max(np.abs(Q - ref.Q_lr)) <= 1e-9 * ref.Qhat[0]
+    assert np.max(np.abs(QG - refG.Q_lr)) <= 4e-9
+    assert abs(estG[0] - refG.Q_ml) <= 4e-9
+    assert abs(np.sqrt(estG[1]) - np.sqrt(refG.V_ml)) <= 1e-8
+
+
+def test_functional_nested_matches_level_values(ctx, fam):
+    N = [16, 8, 8, 4]
+    levels = _small_levels(N)
+    R = 2
+    z = lattice_vector(64, 8) % N[0]
+    shifts = shifts_for(20, 0, R, 8)
+    st, Q, Qh, V, est, lam, (QG, QhG, VG, estG) = ctx.estimate_nested(
+        [_lv6(l) for l in levels], N, R, z, shifts, lam_out=True, functional=True)
+    assert st == m.MLQMC_OK
+    for r in range(R):
+        pts = qmc.embedded_points(z, N[0], shifts[r], N[0])
+        for l in range(4):
+            want = np.mean([mlqmc.level_value(levels[l], pts[k], fam).G -
+                            mlqmc.level_value(levels[l], pts[k], fam).G_prev
+                            for k in range(N[l])]) if l else \
+                np.mean([mlqmc.level_value(levels[0], pts[k], fam).G for k in range(N[0])])
+            assert abs(QG[l, r] - want) <= 4e-9, (l, r)
+    tot = QG.sum(axis=0)
+    assert abs(estG[1] - np.var(tot, ddof=1) / R) <= 1e-10 * max(np.var(tot), 1e-30)
