@@ -19,7 +19,17 @@
 
 namespace mlqmc {
 
-constexpr double kOmega = 0.8;  // damped-Jacobi weight of the multigrid smoother
+// Weights of the two Jacobi sweeps of each multigrid smoothing step (pre- and
+// post-smoothing use the same pair, so the V-cycle stays symmetric: both
+// sweeps are polynomials in D^{-1} A and commute).
+#ifndef MLQMC_OMEGA1
+#define MLQMC_OMEGA1 0.8
+#endif
+#ifndef MLQMC_OMEGA2
+#define MLQMC_OMEGA2 0.8
+#endif
+constexpr double kOmega1 = MLQMC_OMEGA1;
+constexpr double kOmega2 = MLQMC_OMEGA2;
 
 // Butterfly sum over the 64 lanes; every lane ends with the same value
 // (each stage adds the same two operands in both partner lanes).

@@ -671,7 +671,7 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
           if constexpr (kUpd) {
             if (j >= lo && j < own_hi) rout[b * g.P + k] = in0[q][0];
           }
-          v = T(kOmega) * in0[q][0] / (in0[q][1] + in0[q][2] + in0[q][3] + in0[q][4]);
+          v = T(kOmega1) * in0[q][0] / (in0[q][1] + in0[q][2] + in0[q][3] + in0[q][4]);
         }
         row[c] = v;
       }
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
           const T d = in[1] + in[2] + in[3] + in[4];
           const T ax = in[1] * (x - zc[c - 1]) + in[2] * (x - zc[c + 1]) + in[3] * (x - zs[c]) +
                        in[4] * (x - zn[c]);
-          v = x + T(kOmega) * (in[0] - ax) / d;
+          v = x + T(kOmega2) * (in[0] - ax) / d;
           if (jz >= lo && jz < own_hi) xb[k] = v;
         }
         row[c] = v;
@@ -859,7 +859,7 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
           const T d = in[1] + in[2] + in[3] + in[4];
           const T ax = in[1] * (x - uc0[c - 1]) + in[2] * (x - uc0[c + 1]) + in[3] * (x - us[c]) +
                        in[4] * (x - un[c]);
-          v = x + T(kOmega) * (in[0] - ax) / d;
+          v = x + T(kOmega1) * (in[0] - ax) / d;
         }
         row[c] = v;
       }
@@ -878,7 +878,7 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
           const T d = in[1] + in[2] + in[3] + in[4];
           const T ax = in[1] * (x - zc[c - 1]) + in[2] * (x - zc[c + 1]) + in[3] * (x - zs[c]) +
                        in[4] * (x - zn[c]);
-          const T zz = x + T(kOmega) * (in[0] - ax) / d;
+          const T zz = x + T(kOmega2) * (in[0] - ax) / d;
           xo[k] = zz;
           if constexpr (kDots) {
             acc[0] += (double)in[0] * (double)zz;

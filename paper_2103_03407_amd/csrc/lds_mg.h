@@ -117,14 +117,14 @@ MLQMC_DEV void coarsen_all(const T* wx, const T* wy, T* nxt) {
 
 // X = omega * B / diag  (first sweep from a zero start)
 template <int NT, int n, typename T>
-MLQMC_DEV void jacobi_first(const T* wx, const T* wy, const T* B, T* X) {
-  LDS_FOR_NODES(NT, n, k) X[k] = T(kOmega) * B[k] / pdiag<n>(wx, wy, k);
+MLQMC_DEV void jacobi_first(const T* wx, const T* wy, const T* B, T* X, double om) {
+  LDS_FOR_NODES(NT, n, k) X[k] = T(om) * B[k] / pdiag<n>(wx, wy, k);
   __syncthreads();
 }
 
 // X <- X + omega (B - A X) / diag, new values staged in registers
 template <int NT, int n, typename T>
-MLQMC_DEV void jacobi_sweep(const T* wx, const T* wy, const T* B, T* X) {
+MLQMC_DEV void jacobi_sweep(const T* wx, const T* wy, const T* B, T* X, double om) {
   constexpr int PT = (n * n - n + NT - 1) / NT;
   T nv[PT];
 #pragma unroll
@@ -133,7 +133,7 @@ MLQMC_DEV void jacobi_sweep(const T* wx, const T* wy, const T* B, T* X) {
     if (k < n * n && (k & (n - 1)) != 0) {
       T d;
       const T ax = pA<n>(X, wx, wy, k, d);
-      nv[q] = X[k] + T(kOmega) * (B[k] - ax) / d;
+      nv[q] = X[k] + T(om) * (B[k] - ax) / d;
     }
   }
   __syncthreads();
@@ -148,11 +148,12 @@ MLQMC_DEV void jacobi_sweep(const T* wx, const T* wy, const T* B, T* X) {
 // Xout = Xin + omega (B - A Xin) / diag (two distinct arrays; for top levels
 // too large for register staging)
 template <int NT, int n, typename T>
-MLQMC_DEV void jacobi_to(const T* wx, const T* wy, const T* B, const T* Xin, T* Xout) {
+MLQMC_DEV void jacobi_to(const T* wx, const T* wy, const T* B, const T* Xin, T* Xout,
+                         double om) {
   LDS_FOR_NODES(NT, n, k) {
     T d;
     const T ax = pA<n>(Xin, wx, wy, k, d);
-    Xout[k] = Xin[k] + T(kOmega) * (B[k] - ax) / d;
+    Xout[k] = Xin[k] + T(om) * (B[k] - ax) / d;
   }
   __syncthreads();
 }
@@ -203,21 +204,21 @@ MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtm
     T* Bc = nxt + 2 * Pc;
     T* Xc = Bc + Pc;
     if constexpr (kStage) {
-      jacobi_first<NT, n>(wx, wy, B, X);
-      jacobi_sweep<NT, n>(wx, wy, B, X);
+      jacobi_first<NT, n>(wx, wy, B, X, kOmega1);
+      jacobi_sweep<NT, n>(wx, wy, B, X, kOmega2);
     } else {
-      jacobi_first<NT, n>(wx, wy, B, Xtmp);
-      jacobi_to<NT, n>(wx, wy, B, Xtmp, X);
+      jacobi_first<NT, n>(wx, wy, B, Xtmp, kOmega1);
+      jacobi_to<NT, n>(wx, wy, B, Xtmp, X, kOmega2);
     }
     restrict_residual<NT, n>(wx, wy, B, X, Bc);
     vcycle<NT, nc, true, T>(wxc, wyc, Bc, Xc, Xc + Pc);
     prolong_add<NT, n>(Xc, X);
     if constexpr (kStage) {
-      jacobi_sweep<NT, n>(wx, wy, B, X);
-      jacobi_sweep<NT, n>(wx, wy, B, X);
+      jacobi_sweep<NT, n>(wx, wy, B, X, kOmega1);
+      jacobi_sweep<NT, n>(wx, wy, B, X, kOmega2);
     } else {
-      jacobi_to<NT, n>(wx, wy, B, X, Xtmp);
-      jacobi_to<NT, n>(wx, wy, B, Xtmp, X);
+      jacobi_to<NT, n>(wx, wy, B, X, Xtmp, kOmega1);
+      jacobi_to<NT, n>(wx, wy, B, Xtmp, X, kOmega2);
     }
   }
 }
