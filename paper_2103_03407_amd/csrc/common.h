@@ -28,6 +28,11 @@ namespace mlqmc {
 // stays symmetric (both sweeps are polynomials in D^{-1} A and commute).
 constexpr double kOmega1 = 0.5663522991524661;
 constexpr double kOmega2 = 1.5765048437046771;
+// The degree-3 Chebyshev smoother for the same interval (nodes
+// 1.2 + 0.8 cos((2i - 1) pi / 6)), which damps it by 1/9 per smoothing step;
+// used by the V-cycle levels below the batched ones, where one more sweep in
+// LDS costs little next to the PCG iteration it saves.
+constexpr double kCheb3[3] = {0.5283121635129678, 0.8333333333333334, 1.9716878364870327};
 
 // Butterfly sum over the 64 lanes; every lane ends with the same value
 // (each stage adds the same two operands in both partner lanes).

@@ -268,7 +268,8 @@ __global__ __launch_bounds__(NT, (N >= 32 && sizeof(T) == 8) ? 2 : 4) void k_tg_
 
 // The V-cycle below the batched levels: one workgroup per sample reads its
 // padded arrays of the batched layout ((N + 2) N per vector, same indexing)
-// into LDS, runs the cycle, writes the interior of X back.
+// into LDS, runs the cycle (three Chebyshev sweeps per smoothing step),
+// writes the interior of X back.
 template <int N, int NT, typename T>
 __global__ __launch_bounds__(NT) void k_bottom(const T* __restrict__ w, const T* __restrict__ rhs,
                                                T* __restrict__ X,
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(NT) void k_bottom(const T* __restrict__ w, const T*
   }
   __syncthreads();
   lds::coarsen_all<NT, N>(s_w, s_w + P, s_mg);
-  lds::vcycle<NT, N, true, T>(s_w, s_w + P, s_b, s_x, s_mg);
+  lds::vcycle<NT, N, true, T, 3>(s_w, s_w + P, s_b, s_x, s_mg);
   LDS_FOR_NODES(NT, N, k) X[b * PG + k] = s_x[k];
 }
 

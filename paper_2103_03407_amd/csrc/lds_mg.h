@@ -191,9 +191,12 @@ MLQMC_DEV void prolong_add(const T* Xc, T* X) {
 
 // One V-cycle X = K^{-1} B on mesh n; `nxt` holds the coarser levels (weights
 // built by coarsen_all).  kStage: register-staged sweeps (false: the sweeps
-// alternate between X and Xtmp, for top levels in global scratch).
-template <int NT, int n, bool kStage = true, typename T>
+// alternate between X and Xtmp, for top levels in global scratch).  kSw: 2 or
+// 3 Jacobi sweeps per smoothing step with the Chebyshev weights of that
+// degree (3 needs kStage).
+template <int NT, int n, bool kStage = true, typename T, int kSw = 2>
 MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtmp = nullptr) {
+  static_assert(kSw == 2 || (kSw == 3 && kStage), "3 sweeps need register staging");
   if constexpr (n == 2) {
     if (threadIdx.x == 0) X[3] = B[3] / pdiag<2>(wx, wy, 3);
     __syncthreads();
@@ -203,7 +206,11 @@ MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtm
     const T* wyc = wxc + Pc;
     T* Bc = nxt + 2 * Pc;
     T* Xc = Bc + Pc;
-    if constexpr (kStage) {
+    if constexpr (kSw == 3) {
+      jacobi_first<NT, n>(wx, wy, B, X, kCheb3[0]);
+      jacobi_sweep<NT, n>(wx, wy, B, X, kCheb3[1]);
+      jacobi_sweep<NT, n>(wx, wy, B, X, kCheb3[2]);
+    } else if constexpr (kStage) {
       jacobi_first<NT, n>(wx, wy, B, X, kOmega1);
       jacobi_sweep<NT, n>(wx, wy, B, X, kOmega2);
     } else {
@@ -211,9 +218,13 @@ MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtm
       jacobi_to<NT, n>(wx, wy, B, Xtmp, X, kOmega2);
     }
     restrict_residual<NT, n>(wx, wy, B, X, Bc);
-    vcycle<NT, nc, true, T>(wxc, wyc, Bc, Xc, Xc + Pc);
+    vcycle<NT, nc, true, T, kSw>(wxc, wyc, Bc, Xc, Xc + Pc);
     prolong_add<NT, n>(Xc, X);
-    if constexpr (kStage) {
+    if constexpr (kSw == 3) {
+      jacobi_sweep<NT, n>(wx, wy, B, X, kCheb3[0]);
+      jacobi_sweep<NT, n>(wx, wy, B, X, kCheb3[1]);
+      jacobi_sweep<NT, n>(wx, wy, B, X, kCheb3[2]);
+    } else if constexpr (kStage) {
       jacobi_sweep<NT, n>(wx, wy, B, X, kOmega1);
       jacobi_sweep<NT, n>(wx, wy, B, X, kOmega2);
     } else {
