@@ -123,6 +123,11 @@ struct MGeo {
 // their shared halo rows at the same time and the second read hits in L2.
 // The target is a per-mesh tuning value set before each batch.
 constexpr int64_t kDefaultTargetBlocks = 65536;
+// Jacobi sweeps per smoothing step in the fused V-cycle kernels of the
+// batched levels (the kernels take 2 or 3; the weights follow from the
+// count).  Three saved under 0.1 PCG iterations per sample on 1/128 and 1/256
+// while every pre/post launch got longer (mixed precision lost 5-9 %), so two.
+constexpr int kFineSweeps = 2;
 thread_local int64_t t_target_blocks = kDefaultTargetBlocks;
 inline int strips_for(int rows, int64_t units) {
   const int64_t tb = t_target_blocks;
@@ -584,15 +589,26 @@ __device__ __forceinline__ T rowA(const T* rs, const T* rc, const T* rn, int c, 
   return ww * (x - rc[c - 1]) + we * (x - rc[c + 1]) + ws * (x - rs[c]) + wn * (x - rn[c]);
 }
 
-// Pre-smoothing and restriction of one level:
-//   zb = omega rhs / D;  X = zb + omega (rhs - A zb) / D;  rhs_c = P^T (rhs - A X)
+// Weight of sweep m (0-based) of an NS-sweep smoothing step: the Chebyshev
+// weights of that degree.
+template <int NS>
+__device__ __forceinline__ constexpr double sweep_omega(int m) {
+  if constexpr (NS == 3) return kCheb3[m];
+  return m == 0 ? kOmega1 : kOmega2;
+}
+
+// Pre-smoothing and restriction of one level, NS Jacobi sweeps from zero:
+//   X_1 = omega_1 rhs / D;  X_m = X_{m-1} + omega_m (rhs - A X_{m-1}) / D;
+//   X = X_NS;  rhs_c = P^T (rhs - A X)
 // Strip s owns coarse rows [J0, J1) and fine rows [2 J0 - 1, 2 J1 - 1) (the last
-// strip also row n-1).
+// strip also row n-1).  Sweep m is computed on the owned rows widened by
+// NS - m rows on each side (the halo its successor reads), marching one row
+// behind sweep m - 1.
 // With kUpd (the finest level inside the PCG loop) the right-hand side is
 // first brought up to date, r' = r - alpha (q - c M vn), and r' written to
 // rout on the rows the strip owns (a second buffer: neighbouring strips still
 // read r on their halo rows).
-template <typename T, int NTC, int CPT, bool kUpd>
+template <typename T, int NTC, int CPT, bool kUpd, int NS>
 __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
                                              const T* __restrict__ rhs, T* __restrict__ X,
                                              T* __restrict__ rhs_c,
@@ -600,7 +616,7 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
                                              const T* __restrict__ qd, const T* __restrict__ mvn,
                                              FineState S, T* __restrict__ rout) {
   constexpr int NR = NTC * CPT + 1;
-  __shared__ T s_zb[4][NR], s_x[4][NR], s_res[4][NR];
+  __shared__ T s_sw[NS][4][NR], s_res[4][NR];
   int64_t b;
   int s;
   if (!map_strip<NTC, CPT>(g, b, s) || !active[b]) return;
@@ -620,11 +636,16 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
     cc = (T)S.c[b];
   }
   if (t == 0)
-    for (int r = 0; r < 4; ++r) s_zb[r][n] = s_x[r][n] = s_res[r][n] = T(0);
-  // register window of the row inputs (rhs, the 4 edge weights) of the rows at
-  // stages 1, 2 and 3: each is loaded once, one row ahead of stage 1 (nx;
-  // with kUpd also q and M vn), and carried through the stages
-  T nx[CPT][7], in0[CPT][5], in1[CPT][5], in2[CPT][5];
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int m = 0; m < NS; ++m) s_sw[m][r][n] = T(0);
+      s_res[r][n] = T(0);
+    }
+  // register window of the row inputs (rhs, the 4 edge weights) of the rows
+  // at the NS sweep stages and the residual stage: each is loaded once, one
+  // row ahead of the first sweep (nx; with kUpd also q and M vn), and carried
+  // through the stages (in[0] -> in[NS])
+  T nx[CPT][7], in[NS + 1][CPT][5];
   auto fetch = [&](int j) {
     if (!(j >= 1 && j <= n - 1)) return;
 #pragma unroll
@@ -643,24 +664,24 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
       }
     }
   };
-  const int jfirst = dir > 0 ? lo - 2 : hi + 2;
-  const int last = hi - lo + 4;
+  const int jfirst = dir > 0 ? lo - NS : hi + NS;
+  const int last = hi - lo + 2 * NS;
   fetch(jfirst);
   for (int i = 0; i <= last; ++i) {
     const int j = jfirst + i * dir;
-    // stage 1: zb(j)
+    // first sweep (from zero) at row j
     {
-      T* row = s_zb[j & 3];
+      T* row = s_sw[0][j & 3];
       const bool ok = (j >= 1 && j <= n - 1);
 #pragma unroll
       for (int q = 0; q < CPT; ++q) {
 #pragma unroll
-        for (int e = 0; e < 5; ++e) {
-          in2[q][e] = in1[q][e];
-          in1[q][e] = in0[q][e];
-          in0[q][e] = nx[q][e];
-        }
-        if constexpr (kUpd) in0[q][0] = nx[q][0] - alpha * (nx[q][5] - cc * nx[q][6]);
+        for (int m = NS; m > 0; --m)
+#pragma unroll
+          for (int e = 0; e < 5; ++e) in[m][q][e] = in[m - 1][q][e];
+#pragma unroll
+        for (int e = 0; e < 5; ++e) in[0][q][e] = nx[q][e];
+        if constexpr (kUpd) in[0][q][0] = nx[q][0] - alpha * (nx[q][5] - cc * nx[q][6]);
       }
       if (i < last) fetch(j + dir);
 #pragma unroll
@@ -669,61 +690,66 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
         T v = T(0);
         if (ok && c >= 1) {
           if constexpr (kUpd) {
-            if (j >= lo && j < own_hi) rout[b * g.P + k] = in0[q][0];
+            if (j >= lo && j < own_hi) rout[b * g.P + k] = in[0][q][0];
           }
-          v = T(kOmega1) * in0[q][0] / (in0[q][1] + in0[q][2] + in0[q][3] + in0[q][4]);
+          v = T(sweep_omega<NS>(0)) * in[0][q][0] /
+              (in[0][q][1] + in[0][q][2] + in[0][q][3] + in[0][q][4]);
         }
         row[c] = v;
       }
     }
     __syncthreads();
-    // stage 2: X at the row one behind
-    const int jz = j - dir;
-    if (jz >= lo - 1 && jz <= hi + 1) {
-      T* row = s_x[jz & 3];
-      const bool ok = (jz >= 1 && jz <= n - 1);
-      const T* zs = s_zb[(jz - 1) & 3];
-      const T* zc = s_zb[jz & 3];
-      const T* zn = s_zb[(jz + 1) & 3];
+    // sweeps 2..NS, sweep m one row behind sweep m - 1
 #pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const int c = t + q * NTC, k = jz * n + c;
-        T v = T(0);
-        if (ok && c >= 1) {
-          const T* in = in1[q];
-          const T x = zc[c];
-          const T d = in[1] + in[2] + in[3] + in[4];
-          const T ax = in[1] * (x - zc[c - 1]) + in[2] * (x - zc[c + 1]) + in[3] * (x - zs[c]) +
-                       in[4] * (x - zn[c]);
-          v = x + T(kOmega2) * (in[0] - ax) / d;
-          if (jz >= lo && jz < own_hi) xb[k] = v;
+    for (int m = 1; m < NS; ++m) {
+      const int jz = j - m * dir;
+      const int wide = NS - m;  // halo rows this sweep still feeds
+      if (jz >= lo - wide && jz <= hi + wide) {
+        T* row = s_sw[m][jz & 3];
+        const bool ok = (jz >= 1 && jz <= n - 1);
+        const T* zs = s_sw[m - 1][(jz - 1) & 3];
+        const T* zc = s_sw[m - 1][jz & 3];
+        const T* zn = s_sw[m - 1][(jz + 1) & 3];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          const int c = t + q * NTC, k = jz * n + c;
+          T v = T(0);
+          if (ok && c >= 1) {
+            const T* inm = in[m][q];
+            const T x = zc[c];
+            const T d = inm[1] + inm[2] + inm[3] + inm[4];
+            const T ax = inm[1] * (x - zc[c - 1]) + inm[2] * (x - zc[c + 1]) +
+                         inm[3] * (x - zs[c]) + inm[4] * (x - zn[c]);
+            v = x + T(sweep_omega<NS>(m)) * (inm[0] - ax) / d;
+            if (m == NS - 1 && jz >= lo && jz < own_hi) xb[k] = v;
+          }
+          row[c] = v;
         }
-        row[c] = v;
       }
+      __syncthreads();
     }
-    __syncthreads();
-    // stage 3: residual two rows behind
-    const int jr = j - 2 * dir;
+    // residual NS rows behind the first sweep
+    const int jr = j - NS * dir;
     if (jr >= lo && jr <= hi) {
       T* row = s_res[jr & 3];
-      const T* xs = s_x[(jr - 1) & 3];
-      const T* xc = s_x[jr & 3];
-      const T* xn = s_x[(jr + 1) & 3];
+      const T* xs = s_sw[NS - 1][(jr - 1) & 3];
+      const T* xc = s_sw[NS - 1][jr & 3];
+      const T* xn = s_sw[NS - 1][(jr + 1) & 3];
 #pragma unroll
       for (int q = 0; q < CPT; ++q) {
         const int c = t + q * NTC;
         T v = T(0);
         if (c >= 1) {
-          const T* in = in2[q];
+          const T* inr = in[NS][q];
           const T x = xc[c];
-          v = in[0] - (in[1] * (x - xc[c - 1]) + in[2] * (x - xc[c + 1]) + in[3] * (x - xs[c]) +
-                       in[4] * (x - xn[c]));
+          v = inr[0] - (inr[1] * (x - xc[c - 1]) + inr[2] * (x - xc[c + 1]) +
+                        inr[3] * (x - xs[c]) + inr[4] * (x - xn[c]));
         }
         row[c] = v;
       }
       __syncthreads();
-      // stage 4: restriction at the coarse row J whose residual rows 2J-1..2J+1
-      // are complete (jr = 2J+1 upwards, 2J-1 downwards)
+      // restriction at the coarse row J whose residual rows 2J-1..2J+1 are
+      // complete (jr = 2J+1 upwards, 2J-1 downwards)
       if ((jr & 1) && (dir > 0 ? jr >= lo + 2 : jr <= hi - 2)) {
         const int J = dir > 0 ? (jr - 1) >> 1 : (jr + 1) >> 1;
         const T* rs = s_res[(2 * J - 1) & 3];
@@ -739,11 +765,12 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
   }
 }
 
-// Post-smoothing of one level: U = Xin + P Xc; two sweeps; Xout.  On level 0
+// Post-smoothing of one level: U = Xin + P Xc; NS sweeps; Xout.  On level 0
 // (kDots) the last sweep also forms the partials r.z, M vn.z, r.vn.  Strip s
-// owns fine rows [f0, f1).  Xout must differ from Xin (neighbour strips read
-// Xin rows across the strip boundary).
-template <typename T, int NTC, int CPT, bool kDots>
+// owns fine rows [f0, f1); sweep m runs on them widened by NS - m rows on
+// each side.  Xout must differ from Xin (neighbour strips read Xin rows
+// across the strip boundary).
+template <typename T, int NTC, int CPT, bool kDots, int NS>
 __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
                                               const T* __restrict__ rhs,
                                               const T* __restrict__ Xin,
@@ -752,7 +779,8 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
                                               const uint8_t* __restrict__ active,
                                               double* __restrict__ part) {
   constexpr int NR = NTC * CPT + 1;
-  __shared__ T s_u[4][NR], s_zb[4][NR];
+  // s_sw[0]: U; s_sw[m]: after sweep m (the last sweep goes straight out)
+  __shared__ T s_sw[NS][4][NR];
   int64_t b;
   int s;
   if (!map_strip<NTC, CPT>(g, b, s) || !active[b]) return;
@@ -769,12 +797,15 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
   T* xo = Xout + b * g.P;
   double acc[3] = {0.0, 0.0, 0.0};
   if (t == 0)
-    for (int r = 0; r < 4; ++r) s_u[r][n] = s_zb[r][n] = T(0);
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int m = 0; m < NS; ++m) s_sw[m][r][n] = T(0);
   // Every global input is requested one pipeline step before it is used:
   // u-row sources (X_in and the two coarse values of the prolongation) one
-  // row ahead, the row inputs of the sweeps (rhs, 4 edge weights) as in0 one
-  // row ahead of stage 2, then kept through stage 3 (in1 -> in2).
-  T ux[CPT][3], in0[CPT][5], in1[CPT][5], in2[CPT][5];
+  // row ahead, the row inputs of the sweeps (rhs, 4 edge weights) as in[0]
+  // one row ahead of the first sweep, then kept through the later sweeps
+  // (in[1] -> in[NS]).
+  T ux[CPT][3], in[NS + 1][CPT][5];
   auto fetch_u = [&](int j) {
     const bool ok = (j >= 1 && j <= n - 1);
 #pragma unroll
@@ -790,21 +821,21 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
     }
   };
   auto fetch_in = [&](int j) {
-    if (!(j >= max(f0 - 1, 1) && j <= min(f1, n - 1))) return;
+    if (!(j >= max(f0 - NS + 1, 1) && j <= min(f1 + NS - 2, n - 1))) return;
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int c = t + q * NTC, k = j * n + c;
       if (c >= 1) {
-        in0[q][0] = rb[k];
-        in0[q][1] = wx[k];
-        in0[q][2] = wx[k + 1];
-        in0[q][3] = wy[k];
-        in0[q][4] = wy[k + n];
+        in[0][q][0] = rb[k];
+        in[0][q][1] = wx[k];
+        in[0][q][2] = wx[k + 1];
+        in[0][q][3] = wy[k];
+        in[0][q][4] = wy[k + n];
       }
     }
   };
-  const int jfirst = dir > 0 ? f0 - 2 : f1 + 1;
-  const int last = f1 - f0 + 3;
+  const int jfirst = dir > 0 ? f0 - NS : f1 + NS - 1;
+  const int last = f1 - f0 + 2 * NS - 1;
   fetch_u(jfirst);
   for (int i = 0; i <= last; ++i) {
     const int j = jfirst + i * dir;
@@ -814,76 +845,81 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
 #pragma unroll
       for (int e = 0; e < 3; ++e) uc[q][e] = ux[q][e];
 #pragma unroll
-      for (int e = 0; e < 5; ++e) {
-        in2[q][e] = in1[q][e];
-        in1[q][e] = in0[q][e];
-      }
+      for (int m = NS; m > 0; --m)
+#pragma unroll
+        for (int e = 0; e < 5; ++e) in[m][q][e] = in[m - 1][q][e];
     }
     if (i < last) {
       fetch_u(j + dir);
       fetch_in(j);
     }
-    const int j2 = j - 2 * dir;
+    const int jo = j - NS * dir;
     T dv[CPT][2];
     if constexpr (kDots) {
-      if (j2 >= f0 && j2 < f1) {
+      if (jo >= f0 && jo < f1) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
-          const int k = j2 * n + t + q * NTC;
+          const int k = jo * n + t + q * NTC;
           dv[q][0] = mb[k];
           dv[q][1] = vb[k];
         }
       }
     }
     {
-      T* row = s_u[j & 3];
+      T* row = s_sw[0][j & 3];
 #pragma unroll
       for (int q = 0; q < CPT; ++q)
         row[t + q * NTC] = uc[q][0] + T(0.5) * (uc[q][1] + uc[q][2]);
     }
     __syncthreads();
-    const int j1 = j - dir;
-    if (j1 >= f0 - 1 && j1 <= f1) {
-      T* row = s_zb[j1 & 3];
-      const bool ok = (j1 >= 1 && j1 <= n - 1);
-      const T* us = s_u[(j1 - 1) & 3];
-      const T* uc0 = s_u[j1 & 3];
-      const T* un = s_u[(j1 + 1) & 3];
+    // sweeps 1..NS-1 into LDS, sweep m one row behind sweep m - 1
 #pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const int c = t + q * NTC;
-        T v = T(0);
-        if (ok && c >= 1) {
-          const T* in = in1[q];
-          const T x = uc0[c];
-          const T d = in[1] + in[2] + in[3] + in[4];
-          const T ax = in[1] * (x - uc0[c - 1]) + in[2] * (x - uc0[c + 1]) + in[3] * (x - us[c]) +
-                       in[4] * (x - un[c]);
-          v = x + T(kOmega1) * (in[0] - ax) / d;
+    for (int m = 1; m < NS; ++m) {
+      const int jm = j - m * dir;
+      const int wide = NS - m;
+      if (jm >= f0 - wide && jm <= f1 - 1 + wide) {
+        T* row = s_sw[m][jm & 3];
+        const bool ok = (jm >= 1 && jm <= n - 1);
+        const T* us = s_sw[m - 1][(jm - 1) & 3];
+        const T* uc0 = s_sw[m - 1][jm & 3];
+        const T* un = s_sw[m - 1][(jm + 1) & 3];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          const int c = t + q * NTC;
+          T v = T(0);
+          if (ok && c >= 1) {
+            const T* inm = in[m][q];
+            const T x = uc0[c];
+            const T d = inm[1] + inm[2] + inm[3] + inm[4];
+            const T ax = inm[1] * (x - uc0[c - 1]) + inm[2] * (x - uc0[c + 1]) +
+                         inm[3] * (x - us[c]) + inm[4] * (x - un[c]);
+            v = x + T(sweep_omega<NS>(m - 1)) * (inm[0] - ax) / d;
+          }
+          row[c] = v;
         }
-        row[c] = v;
       }
+      __syncthreads();
     }
-    __syncthreads();
-    if (j2 >= f0 && j2 < f1) {
-      const T* zs = s_zb[(j2 - 1) & 3];
-      const T* zc = s_zb[j2 & 3];
-      const T* zn = s_zb[(j2 + 1) & 3];
+    // the last sweep on the owned rows, straight to Xout
+    if (jo >= f0 && jo < f1) {
+      const T* zs = s_sw[NS - 1][(jo - 1) & 3];
+      const T* zc = s_sw[NS - 1][jo & 3];
+      const T* zn = s_sw[NS - 1][(jo + 1) & 3];
 #pragma unroll
       for (int q = 0; q < CPT; ++q) {
-        const int c = t + q * NTC, k = j2 * n + c;
+        const int c = t + q * NTC, k = jo * n + c;
         if (c >= 1) {
-          const T* in = in2[q];
+          const T* inl = in[NS][q];
           const T x = zc[c];
-          const T d = in[1] + in[2] + in[3] + in[4];
-          const T ax = in[1] * (x - zc[c - 1]) + in[2] * (x - zc[c + 1]) + in[3] * (x - zs[c]) +
-                       in[4] * (x - zn[c]);
-          const T zz = x + T(kOmega2) * (in[0] - ax) / d;
+          const T d = inl[1] + inl[2] + inl[3] + inl[4];
+          const T ax = inl[1] * (x - zc[c - 1]) + inl[2] * (x - zc[c + 1]) +
+                       inl[3] * (x - zs[c]) + inl[4] * (x - zn[c]);
+          const T zz = x + T(sweep_omega<NS>(NS - 1)) * (inl[0] - ax) / d;
           xo[k] = zz;
           if constexpr (kDots) {
-            acc[0] += (double)in[0] * (double)zz;
+            acc[0] += (double)inl[0] * (double)zz;
             acc[1] += (double)dv[q][0] * (double)zz;
-            acc[2] += (double)in[0] * (double)dv[q][1];
+            acc[2] += (double)inl[0] * (double)dv[q][1];
           }
         }
       }
@@ -1246,11 +1282,11 @@ hipError_t launch_pre(int n, int64_t B, const T* w, const T* rhs, T* X, T* rhs_c
   ROW_DISPATCH(n, {
     if (NTC * CPT != n) return hipErrorInvalidValue;  // a block covers one full row
     if (upd)
-      hipLaunchKernelGGL((k_pre<T, NTC, CPT, true>), sgrid(g), dim3(NTC), 0, st, g, w, rhs, X,
-                         rhs_c, active, q, mvn, s0, rout);
+      hipLaunchKernelGGL((k_pre<T, NTC, CPT, true, kFineSweeps>), sgrid(g), dim3(NTC), 0, st, g,
+                         w, rhs, X, rhs_c, active, q, mvn, s0, rout);
     else
-      hipLaunchKernelGGL((k_pre<T, NTC, CPT, false>), sgrid(g), dim3(NTC), 0, st, g, w, rhs, X,
-                         rhs_c, active, q, mvn, s0, rout);
+      hipLaunchKernelGGL((k_pre<T, NTC, CPT, false, kFineSweeps>), sgrid(g), dim3(NTC), 0, st, g,
+                         w, rhs, X, rhs_c, active, q, mvn, s0, rout);
   });
   return hipGetLastError();
 }
@@ -1263,11 +1299,11 @@ hipError_t launch_post(int n, int64_t B, const T* w, const T* rhs, const T* Xin,
   ROW_DISPATCH(n, {
     if (NTC * CPT != n) return hipErrorInvalidValue;  // a block covers one full row
     if (part)
-      hipLaunchKernelGGL((k_post<T, NTC, CPT, true>), sgrid(g), dim3(NTC), 0, st, g, w, rhs, Xin,
-                         Xc, Xout, vn, mvn, active, part);
+      hipLaunchKernelGGL((k_post<T, NTC, CPT, true, kFineSweeps>), sgrid(g), dim3(NTC), 0, st, g,
+                         w, rhs, Xin, Xc, Xout, vn, mvn, active, part);
     else
-      hipLaunchKernelGGL((k_post<T, NTC, CPT, false>), sgrid(g), dim3(NTC), 0, st, g, w, rhs, Xin,
-                         Xc, Xout, vn, mvn, active, part);
+      hipLaunchKernelGGL((k_post<T, NTC, CPT, false, kFineSweeps>), sgrid(g), dim3(NTC), 0, st, g,
+                         w, rhs, Xin, Xc, Xout, vn, mvn, active, part);
   });
   return hipGetLastError();
 }
