@@ -417,7 +417,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
 
   std::string p = tag;
   auto nm = [&](const char* x) { return p + x; };
-  double *w64, *v64, *part;
+  double *w64, *part;
   T *wT, *vn, *mvn, *t, *r, *r2, *z, *zb, *q, *pp[2];
   CS(ctx->getT(nm("w64").c_str(), batch * EW(nh), &w64));
   if constexpr (kMixed) {
@@ -425,7 +425,6 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   } else {
     wT = w64;
   }
-  CS(ctx->getT(nm("v64").c_str(), batch * P(nh), &v64));
   // blocks per sample <= (rows + 7) / 8 strips x (column blocks <= 4): bound the
   // partial-sum buffer by the most strips any batch size can take, 3 partials each
   CS(ctx->getT(nm("part").c_str(), batch * (4 * ((nh + 6) / 8) + 4) * 6, &part));
@@ -466,7 +465,6 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
       return MLQMC_OK;
     };
     CS(zero(nh, {vn, t, r, z, zb, q, pp[0], pp[1], mvn, r2}, (int)sz));
-    CS(zero(nh, {v64}, 8));
     for (size_t k = 1; k <= nL; ++k) {
       const int m = (k < nL) ? lv[k] : nb;
       if (k < nL)
@@ -522,10 +520,11 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
                                   (8.0 + (kMixed ? 4.0 : 0.0)) * (double)Bn * EW(nh));
     for (size_t k = 0; k < nL; ++k) CK(launch_coarsen<T>(lv[k], Bn, W[k], W[k + 1], st), "coarsen");
 
-    CK(launch_prolong(nH, nh, Bn, uH + b0 * D(nH), v64, st), "prolong");
-    CK(launch_setup_dots(nh, Bn, v64, w64, part, st), "setup dots");
+    // v = P u_H is evaluated inside these kernels from the coarse vectors
+    const double* uHb = uH + b0 * D(nH);
+    CK(launch_setup_dots(nh, Bn, uHb, nH, w64, part, st), "setup dots");
     CK(launch_scalar(PH_SETUP, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
-    CK(launch_setup_rhs<T>(nh, Bn, v64, w64, S, r, t, vn, mvn, st), "setup rhs");
+    CK(launch_setup_rhs<T>(nh, Bn, uHb, nH, w64, S, r, t, vn, mvn, st), "setup rhs");
 
     // z = K^{-1} r by one V-cycle: fused pre-smoothing + restriction per level,
     // the LDS bottom solve, fused coarse correction + post-smoothing per level;
@@ -637,7 +636,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
         }
       }
     }
-    CK(launch_final_dots<T>(nh, Bn, v64, t, pp[0], pp[1], w64, S, part, st), "final dots");
+    CK(launch_final_dots<T>(nh, Bn, uHb, nH, t, pp[0], pp[1], w64, S, part, st), "final dots");
     CK(launch_scalar(PH_FINAL, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
   }
   return MLQMC_OK;

@@ -312,20 +312,18 @@ __device__ __forceinline__ double interp_pow2(const double* __restrict__ uH, int
   return u00 + eta * (u01 - u00) + xi * (u11 - u01);
 }
 
-__global__ __launch_bounds__(NT) void k_prolong(Geo g, int nH, const double* __restrict__ uH,
-                                                double* __restrict__ uh) {
-  int64_t b;
-  int blk;
-  if (!map_block(g, b, blk)) return;
-  const int mH = nH - 1;
-  int lr = 0;
-  while ((nH << lr) < g.n) ++lr;
-  const double inv_r = 1.0 / (double)(1 << lr);
-  const double* ub = uH + b * (int64_t)(mH * mH);
-  FOR_NODES(g, blk) {
-    const int i = k & (g.n - 1), j = k >> g.lg;
-    uh[b * g.P + k] = interp_pow2(ub, nH, lr, inv_r, i, j);
-  }
+// The prolongated coarse eigenvector v = P u_H, evaluated where it is needed
+// instead of being stored: node k of mesh n (padded layout) of sample b.
+// Padding positions (column 0, rows 0 and n) come out as 0.
+struct Coarse {
+  const double* uH;  // [B x (nH - 1)^2] interior layout
+  int nH, lr;        // coarse mesh, log2(n / nH)
+  double inv_r;      // 2^-lr
+};
+__device__ __forceinline__ double coarse_v(const Coarse& cv, const MGeo& g, int64_t b, int k) {
+  const int mH = cv.nH - 1;
+  return interp_pow2(cv.uH + b * (int64_t)(mH * mH), cv.nH, cv.lr, cv.inv_r, k & (g.n - 1),
+                     k >> g.lg);
 }
 
 // interior-layout prolongation for the component entry point
@@ -368,19 +366,19 @@ __global__ __launch_bounds__(256) void k_coarsen(int xblk, int n, int64_t B, con
 
 // partials: v.M12 v, v.A v  (raw FP64 v, FP64 weights)
 template <int NTC>
-__global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, const double* __restrict__ v,
+__global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, Coarse cv,
                                                     const double* __restrict__ w,
                                                     double* __restrict__ part) {
   __shared__ double ring[4][NTC + 2];
   int64_t b;
   int c0, j0, j1, blk, dir;
   if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir)) return;
-  const double* vb = v + b * g.P;
   const double* wx = w + b * 2 * g.P;
   const double* wy = wx + g.P;
   double s[2] = {0.0, 0.0};
   march_pf<double, NTC>(
-      ring, g, c0, j0, j1, dir, [&](int k) { return vb[k]; }, [](double f) { return f; },
+      ring, g, c0, j0, j1, dir, [&](int k) { return coarse_v(cv, g, b, k); },
+      [](double f) { return f; },
       [&](int k) { return load_wts(wx, wy, k, g.n); },
       [&](int, int, const double* rs, const double* rc, const double* rn, int ci,
           const Wts<double>& wt, double) {
@@ -393,7 +391,7 @@ __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, const double* __rest
 
 // r = -(A v_n - rho M v_n) (FP64), t = 0, vn = v_n, mvn = M v_n
 template <typename T, int NTC>
-__global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, const double* __restrict__ v,
+__global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
                                                    const double* __restrict__ w64, FineState S,
                                                    T* __restrict__ r, T* __restrict__ t,
                                                    T* __restrict__ vn, T* __restrict__ mvn) {
@@ -401,12 +399,12 @@ __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, const double* __restr
   int64_t b;
   int c0, j0, j1, blk, dir;
   if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir)) return;
-  const double* vb = v + b * g.P;
   const double* wx = w64 + b * 2 * g.P;
   const double* wy = wx + g.P;
   const double vs = S.vs[b], rho = S.rho[b], hm = mass_scale(g.n);
   march_pf<double, NTC>(
-      ring, g, c0, j0, j1, dir, [&](int k) { return vb[k]; }, [](double f) { return f; },
+      ring, g, c0, j0, j1, dir, [&](int k) { return coarse_v(cv, g, b, k); },
+      [](double f) { return f; },
       [&](int k) { return load_wts(wx, wy, k, g.n); },
       [&](int, int k, const double* rs, const double* rc, const double* rn, int ci,
           const Wts<double>& wt, double) {
@@ -942,7 +940,7 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
 // w = vs v + t (FP64): partials w.A w, w.M12 w with FP64 weights, and the
 // sum of w (h^2 times it is the integral of the P1 function w)
 template <typename T, int NTC>
-__global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, const double* __restrict__ v,
+__global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, Coarse cv,
                                                     const T* __restrict__ t,
                                                     const T* __restrict__ p0,
                                                     const T* __restrict__ p1,
@@ -952,7 +950,6 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, const double* __rest
   int64_t b;
   int c0, j0, j1, blk, dir;
   if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir)) return;
-  const double* vb = v + b * g.P;
   const T* tb = t + b * g.P;
   // the sample's last step alpha p is still to be added to t: its direction
   // sits in the buffer that iteration its - 1 wrote
@@ -968,7 +965,7 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, const double* __rest
     T t, p;
   };
   march_pf<double, NTC>(
-      ring, g, c0, j0, j1, dir, [&](int k) { return Fin{vb[k], tb[k], pl[k]}; },
+      ring, g, c0, j0, j1, dir, [&](int k) { return Fin{coarse_v(cv, g, b, k), tb[k], pl[k]}; },
       [&](const Fin& f) { return vs * f.v + (double)(T)(f.t + al * f.p); },
       [&](int k) { return load_wts(wx, wy, k, g.n); },
       [&](int, int, const double* rs, const double* rc, const double* rn, int ci,
@@ -1142,14 +1139,6 @@ hipError_t launch_zero_boundary(int n, int64_t B, void* const* ptrs, int cnt, in
   return hipGetLastError();
 }
 
-hipError_t launch_prolong(int nH, int nh, int64_t B, const double* uH, double* uh,
-                          hipStream_t st) {
-  if (B <= 0) return hipSuccess;
-  const Geo g = geo(nh, B);
-  hipLaunchKernelGGL(k_prolong, grid_of(g), dim3(NT), 0, st, g, nH, uH, uh);
-  return hipGetLastError();
-}
-
 hipError_t launch_prolong_interior(int nH, int nh, int64_t B, const double* uH, double* uh,
                                   hipStream_t st) {
   if (B <= 0) return hipSuccess;
@@ -1191,22 +1180,35 @@ inline dim3 mgrid(const MGeo& g) {
   return dim3((unsigned)(Bp * g.nblk));
 }
 
-hipError_t launch_setup_dots(int n, int64_t B, const double* v, const double* w, double* part,
-                             hipStream_t st) {
+namespace {
+// uH of mesh nH prolongated to mesh n (n / nH a power of two)
+Coarse coarse_of(const double* uH, int nH, int n) {
+  int lr = 0;
+  while ((nH << lr) < n) ++lr;
+  return Coarse{uH, nH, lr, 1.0 / (double)(1 << lr)};
+}
+}  // namespace
+
+hipError_t launch_setup_dots(int n, int64_t B, const double* uH, int nH, const double* w,
+                             double* part, hipStream_t st) {
+  if (nH < 2 || n % nH) return hipErrorInvalidValue;
+  const Coarse cv = coarse_of(uH, nH, n);
   MARCH_DISPATCH(n, {
     const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_setup_dots<NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, v, w, part);
+    hipLaunchKernelGGL((k_setup_dots<NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, w, part);
   });
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64,
+hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const double* w64,
                             const FineState& S, T* r, T* t, T* vn, T* mvn, hipStream_t st) {
+  if (nH < 2 || n % nH) return hipErrorInvalidValue;
+  const Coarse cv = coarse_of(uH, nH, n);
   MARCH_DISPATCH(n, {
     const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_setup_rhs<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, v, w64, S, r, t,
-                       vn, mvn);
+    hipLaunchKernelGGL((k_setup_rhs<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, w64, S, r,
+                       t, vn, mvn);
   });
   return hipGetLastError();
 }
@@ -1319,13 +1321,15 @@ int march_blocks(int n, int64_t B) {
 }
 
 template <typename T>
-hipError_t launch_final_dots(int n, int64_t B, const double* v, const T* t, const T* p0,
+hipError_t launch_final_dots(int n, int64_t B, const double* uH, int nH, const T* t, const T* p0,
                              const T* p1, const double* w, const FineState& S, double* part,
                              hipStream_t st) {
+  if (nH < 2 || n % nH) return hipErrorInvalidValue;
+  const Coarse cv = coarse_of(uH, nH, n);
   MARCH_DISPATCH(n, {
     const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_final_dots<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, v, t, p0, p1,
-                       w, S, part);
+    hipLaunchKernelGGL((k_final_dots<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, t, p0,
+                       p1, w, S, part);
   });
   return hipGetLastError();
 }
@@ -1350,14 +1354,14 @@ hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* s
 
 #define INST(T)                                                                                 \
   template hipError_t launch_coarsen<T>(int, int64_t, const T*, T*, hipStream_t);                \
-  template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, const double*,           \
+  template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, int, const double*,      \
                                           const FineState&, T*, T*, T*, T*, hipStream_t);       \
   template hipError_t launch_pupdate_apply<T>(int, int64_t, const T*, const T*, const T*,       \
                                               const T*, const T*, T*, const FineState&,         \
                                               int, T*, T*, double*, hipStream_t);               \
-  template hipError_t launch_final_dots<T>(int, int64_t, const double*, const T*, const T*,     \
-                                           const T*, const double*, const FineState&, double*,  \
-                                           hipStream_t);
+  template hipError_t launch_final_dots<T>(int, int64_t, const double*, int, const T*,          \
+                                           const T*, const T*, const double*, const FineState&, \
+                                           double*, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

@@ -96,18 +96,17 @@ inline int64_t padded_size(int n) { return (int64_t)(n + 2) * n; }
 hipError_t launch_zero_boundary(int n, int64_t B, void* const* ptrs, int cnt, int elem,
                                 hipStream_t st);
 
-// interior-layout coarse field (mesh nH) -> padded fine field (mesh nh)
-hipError_t launch_prolong(int nH, int nh, int64_t B, const double* uH, double* uh,
-                          hipStream_t st);
 // interior layout -> interior layout (component entry point)
 hipError_t launch_prolong_interior(int nH, int nh, int64_t B, const double* uH, double* uh,
                                    hipStream_t st);
 template <typename T>
 hipError_t launch_coarsen(int n, int64_t B, const T* w, T* wc, hipStream_t st);
-hipError_t launch_setup_dots(int n, int64_t B, const double* v, const double* w, double* part,
-                             hipStream_t st);
+// The set-up and final kernels take the coarse eigenvectors uH [B x (nH-1)^2]
+// and evaluate v = P u_H (P1 interpolation to mesh n) where they need it.
+hipError_t launch_setup_dots(int n, int64_t B, const double* uH, int nH, const double* w,
+                             double* part, hipStream_t st);
 template <typename T>
-hipError_t launch_setup_rhs(int n, int64_t B, const double* v, const double* w64,
+hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const double* w64,
                             const FineState& S, T* r, T* t, T* vn, T* mvn, hipStream_t st);
 template <typename T>
 hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
@@ -135,7 +134,7 @@ void set_target_blocks(int64_t v);
 // blocks per sample of the row-marching kernels for a batch of B (their partial-sum count)
 int march_blocks(int n, int64_t B);
 template <typename T>
-hipError_t launch_final_dots(int n, int64_t B, const double* v, const T* t, const T* p0,
+hipError_t launch_final_dots(int n, int64_t B, const double* uH, int nH, const T* t, const T* p0,
                              const T* p1, const double* w, const FineState& S, double* part,
                              hipStream_t st);
 
