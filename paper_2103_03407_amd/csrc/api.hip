@@ -524,7 +524,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     const double* uHb = uH + b0 * D(nH);
     CK(launch_setup_dots(nh, Bn, uHb, nH, w64, part, st), "setup dots");
     CK(launch_scalar(PH_SETUP, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
-    CK(launch_setup_rhs<T>(nh, Bn, uHb, nH, w64, S, r, t, vn, mvn, st), "setup rhs");
+    CK(launch_setup_rhs<T>(nh, Bn, uHb, nH, w64, S, r, vn, mvn, st), "setup rhs");
 
     // z = K^{-1} r by one V-cycle: fused pre-smoothing + restriction per level,
     // the LDS bottom solve, fused coarse correction + post-smoothing per level;
@@ -575,8 +575,9 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     all_active = false;
     const int nblk_post = post_strips(nh, Bn);
     CK(launch_scalar(PH_FIRST_RZ, nh, Bn, nblk_post, part, S, 0.0, 0, st), "scalar");
-    // first apply: z, vn, mvn, t, 2 weights per node in (no previous p); p, q out
-    const double ab = (double)sz * Bn * (8 * D(nh));
+    // first apply: z, vn, mvn, 2 weights per node in (no previous p, t = 0 not
+    // read); p, q out
+    const double ab = (double)sz * Bn * (7 * D(nh));
     int cur = 0;
     // one PCG iteration: apply (with the previous step's t update), alpha and
     // the eigenvalue test, the V-cycle (with the residual update), beta

@@ -389,12 +389,13 @@ __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, Coarse cv,
   write_partials_m<NTC, 2>(s, part, b, blk, g.nblk);
 }
 
-// r = -(A v_n - rho M v_n) (FP64), t = 0, vn = v_n, mvn = M v_n
+// r = -(A v_n - rho M v_n) (FP64), vn = v_n, mvn = M v_n (t starts at 0 without
+// being stored: the PCG kernels read t only from its third step on)
 template <typename T, int NTC>
 __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
                                                    const double* __restrict__ w64, FineState S,
-                                                   T* __restrict__ r, T* __restrict__ t,
-                                                   T* __restrict__ vn, T* __restrict__ mvn) {
+                                                   T* __restrict__ r, T* __restrict__ vn,
+                                                   T* __restrict__ mvn) {
   __shared__ double ring[4][NTC + 2];
   int64_t b;
   int c0, j0, j1, blk, dir;
@@ -414,7 +415,6 @@ __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
                        const T rT = (T)rv;
                        const int64_t o = b * g.P + k;
                        r[o] = rT;
-                       t[o] = T(0);
                        vn[o] = (T)(vs * rc[ci]);
                        mvn[o] = (T)(vs * mv);
                      });
@@ -447,6 +447,9 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
   T* tb = t + b * g.P;
   const T c2 = (T)S.c2[b], beta = first ? T(0) : (T)S.beta[b], mu = (T)S.mu[b];
   const T alpha = first ? T(0) : (T)S.alpha[b];  // the previous step, not yet applied to t
+  // t holds t_{k-1} from step 2 on (step k writes t_k = t_{k-1} + alpha p_{k-1});
+  // t_0 = 0 is never stored, so steps 0 and 1 do not read it
+  const bool tread = !first && S.its[b] >= 2;
   const T hm = (T)mass_scale(g.n);
   const int n = g.n, tx = threadIdx.x, c = c0 + tx, ci = tx + 1;
   // the two threads at the block's edges also load one halo column
@@ -494,7 +497,7 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
       r.ws = wy[k];
       r.wn = wy[k + n];
       r.m = mb[k];
-      r.tt = tb[k];
+      r.tt = tread ? tb[k] : T(0);
     }
   };
   double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -956,6 +959,7 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, Coarse cv,
   const int its = S.its[b];
   const T* pl = ((its & 1) ? p1 : p0) + b * g.P;
   const T al = its > 0 ? (T)S.alpha[b] : T(0);
+  const bool tread = its >= 2;  // t_{its-1} stored (t_0 = 0 never is)
   const double vs = S.vs[b];
   const double* wx = w + b * 2 * g.P;
   const double* wy = wx + g.P;
@@ -965,7 +969,8 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, Coarse cv,
     T t, p;
   };
   march_pf<double, NTC>(
-      ring, g, c0, j0, j1, dir, [&](int k) { return Fin{coarse_v(cv, g, b, k), tb[k], pl[k]}; },
+      ring, g, c0, j0, j1, dir,
+      [&](int k) { return Fin{coarse_v(cv, g, b, k), tread ? tb[k] : T(0), pl[k]}; },
       [&](const Fin& f) { return vs * f.v + (double)(T)(f.t + al * f.p); },
       [&](int k) { return load_wts(wx, wy, k, g.n); },
       [&](int, int, const double* rs, const double* rc, const double* rn, int ci,
@@ -1202,13 +1207,13 @@ hipError_t launch_setup_dots(int n, int64_t B, const double* uH, int nH, const d
 
 template <typename T>
 hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const double* w64,
-                            const FineState& S, T* r, T* t, T* vn, T* mvn, hipStream_t st) {
+                            const FineState& S, T* r, T* vn, T* mvn, hipStream_t st) {
   if (nH < 2 || n % nH) return hipErrorInvalidValue;
   const Coarse cv = coarse_of(uH, nH, n);
   MARCH_DISPATCH(n, {
     const MGeo g = mgeo<NTC>(n, B);
     hipLaunchKernelGGL((k_setup_rhs<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, w64, S, r,
-                       t, vn, mvn);
+                       vn, mvn);
   });
   return hipGetLastError();
 }
@@ -1355,7 +1360,7 @@ hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* s
 #define INST(T)                                                                                 \
   template hipError_t launch_coarsen<T>(int, int64_t, const T*, T*, hipStream_t);                \
   template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, int, const double*,      \
-                                          const FineState&, T*, T*, T*, T*, hipStream_t);       \
+                                          const FineState&, T*, T*, T*, hipStream_t);           \
   template hipError_t launch_pupdate_apply<T>(int, int64_t, const T*, const T*, const T*,       \
                                               const T*, const T*, T*, const FineState&,         \
                                               int, T*, T*, double*, hipStream_t);               \

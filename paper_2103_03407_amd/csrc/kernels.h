@@ -107,7 +107,7 @@ hipError_t launch_setup_dots(int n, int64_t B, const double* uH, int nH, const d
                              double* part, hipStream_t st);
 template <typename T>
 hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const double* w64,
-                            const FineState& S, T* r, T* t, T* vn, T* mvn, hipStream_t st);
+                            const FineState& S, T* r, T* vn, T* mvn, hipStream_t st);
 template <typename T>
 hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
                                 const T* mvn, const T* w, T* t, const FineState& S,
