@@ -534,8 +534,9 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     // active (the set-up V-cycle, the first PCG step), so the byte model counts
     // exactly the work done: rhs, 2 edge weights per node in; X and rhs_c out.
     const double pre_b = (double)sz * Bn * (4.25 * D(nh));
-    // post: Xin, rhs, vn, mvn, 2 weights per node and 1/4 of a coarse vector in; Xout out
-    const double post_b = (double)sz * Bn * (7.25 * D(nh));
+    // post: Xin, rhs, mvn, 2 weights per node and 1/4 of a coarse vector in (and vn
+    // for the product r.vn in FP32 storage only); Xout out
+    const double post_b = (double)sz * Bn * ((kMixed ? 7.25 : 6.25) * D(nh));
     bool all_active = true;
     T* zc = z;   // current preconditioned residual
     T* zo = zb;  // the other buffer

@@ -767,7 +767,12 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
 }
 
 // Post-smoothing of one level: U = Xin + P Xc; NS sweeps; Xout.  On level 0
-// (kDots) the last sweep also forms the partials r.z, M vn.z, r.vn.  Strip s
+// (kDots) the last sweep also forms the partials r.z, M vn.z, r.vn.  The
+// recursive residual keeps vn^T r at vn^T r_0 = 0 up to the rounding of the
+// updates r - alpha (q - c M vn) (vn^T M vn = 1, c = vn^T q); in
+// FP64 that drift is ~1e-16 |r_0| against |r| >= 1e-10 |r_0| (the tightest
+// residual test), so r.vn is taken as 0 there and vn is not read; FP32
+// storage drifts by ~1e-7 |r_0| and keeps the explicit product.  Strip s
 // owns fine rows [f0, f1); sweep m runs on them widened by NS - m rows on
 // each side.  Xout must differ from Xin (neighbour strips read Xin rows
 // across the strip boundary).
@@ -780,6 +785,7 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
                                               const uint8_t* __restrict__ active,
                                               double* __restrict__ part) {
   constexpr int NR = NTC * CPT + 1;
+  constexpr bool kRv = sizeof(T) < 8;  // r.vn formed explicitly (FP32 storage)
   // s_sw[0]: U; s_sw[m]: after sweep m (the last sweep goes straight out)
   __shared__ T s_sw[NS][4][NR];
   int64_t b;
@@ -862,7 +868,7 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
         for (int q = 0; q < CPT; ++q) {
           const int k = jo * n + t + q * NTC;
           dv[q][0] = mb[k];
-          dv[q][1] = vb[k];
+          dv[q][1] = kRv ? vb[k] : T(0);
         }
       }
     }
@@ -920,7 +926,7 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
           if constexpr (kDots) {
             acc[0] += (double)inl[0] * (double)zz;
             acc[1] += (double)dv[q][0] * (double)zz;
-            acc[2] += (double)inl[0] * (double)dv[q][1];
+            if constexpr (kRv) acc[2] += (double)inl[0] * (double)dv[q][1];
           }
         }
       }
