@@ -401,7 +401,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   auto P = [](int m) { return padded_size(m); };                // padded vector
   auto EW = [](int m) { return 2 * padded_size(m); };           // padded [WX | WY]
   const int64_t sz = (int64_t)sizeof(T);
-  int64_t per_sample = 8 * (EW(nh) + 2 * P(nh)) + sz * (10 * P(nh)) + (kMixed ? 4 * EW(nh) : 0);
+  int64_t per_sample = 8 * (EW(nh) + 2 * P(nh)) + sz * (9 * P(nh)) + (kMixed ? 4 * EW(nh) : 0);
   for (size_t k = 1; k < nL; ++k) per_sample += sz * (EW(lv[k]) + 3 * P(lv[k]));
   per_sample += sz * (EW(nb) + 2 * P(nb));
   // default batch: up to 48 GB of working arrays (HBM holds 288 GB), in
@@ -418,7 +418,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   std::string p = tag;
   auto nm = [&](const char* x) { return p + x; };
   double *w64, *part;
-  T *wT, *vn, *mvn, *t, *r, *r2, *z, *zb, *q, *pp[2];
+  T *wT, *vn, *mvn, *t, *r, *r2, *z, *zb, *pp[2];
   CS(ctx->getT(nm("w64").c_str(), batch * EW(nh), &w64));
   if constexpr (kMixed) {
     CS(ctx->getT(nm("w32").c_str(), batch * EW(nh), &wT));
@@ -428,9 +428,9 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   // blocks per sample <= (rows + 7) / 8 strips x (column blocks <= 4): bound the
   // partial-sum buffer by the most strips any batch size can take, 3 partials each
   CS(ctx->getT(nm("part").c_str(), batch * (4 * ((nh + 6) / 8) + 4) * 6, &part));
-  const char* vnames[] = {"vn", "t", "r", "z", "zb", "q", "p0", "p1", "mvn", "r2"};
-  T** vptr[] = {&vn, &t, &r, &z, &zb, &q, &pp[0], &pp[1], &mvn, &r2};
-  for (int k = 0; k < 10; ++k) {
+  const char* vnames[] = {"vn", "t", "r", "z", "zb", "p0", "p1", "mvn", "r2"};
+  T** vptr[] = {&vn, &t, &r, &z, &zb, &pp[0], &pp[1], &mvn, &r2};
+  for (int k = 0; k < 9; ++k) {
     std::string key = nm(vnames[k]) + (kMixed ? "_f" : "_d");
     CS(ctx->getT(key.c_str(), batch * P(nh), vptr[k]));
   }
@@ -464,7 +464,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
       for (void* q : todo) ctx->zeroed[q] = mlqmc_ctx::ZeroKey{m, elem, batch};
       return MLQMC_OK;
     };
-    CS(zero(nh, {vn, t, r, z, zb, q, pp[0], pp[1], mvn, r2}, (int)sz));
+    CS(zero(nh, {vn, t, r, z, zb, pp[0], pp[1], mvn, r2}, (int)sz));
     for (size_t k = 1; k <= nL; ++k) {
       const int m = (k < nL) ? lv[k] : nb;
       if (k < nL)
@@ -538,16 +538,18 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     // for the product r.vn in FP32 storage only); Xout out
     const double post_b = (double)sz * Bn * ((kMixed ? 7.25 : 6.25) * D(nh));
     bool all_active = true;
+    int cur = 0;  // pp[cur]: the current search direction
     T* zc = z;   // current preconditioned residual
     T* zo = zb;  // the other buffer
     T* rc = r;   // current residual
     T* ro = r2;  // the other buffer
     // upd: bring the residual up to date first, r <- r - alpha (q - c M vn),
-    // inside the finest pre-smoothing kernel (the result lands in ro)
+    // inside the finest pre-smoothing kernel, which recomputes q = (A - mu M) p
+    // from the current direction (the result lands in ro)
     auto vcycle = [&](bool upd) -> mlqmc_status {
       if (all_active) ctx->t_begin(MLQMC_K_PRE);
       if (upd) {
-        CK(launch_pre<T>(nh, Bn, wT, rc, zc, Bv[1], act, q, mvn, &S, ro, st), "pre");
+        CK(launch_pre<T>(nh, Bn, wT, rc, zc, Bv[1], act, pp[cur], mvn, &S, ro, st), "pre");
         std::swap(rc, ro);
       } else {
         CK(launch_pre<T>(nh, Bn, wT, rc, zc, Bv[1], act, nullptr, nullptr, nullptr, nullptr, st),
@@ -577,15 +579,14 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     const int nblk_post = post_strips(nh, Bn);
     CK(launch_scalar(PH_FIRST_RZ, nh, Bn, nblk_post, part, S, 0.0, 0, st), "scalar");
     // first apply: z, vn, mvn, 2 weights per node in (no previous p, t = 0 not
-    // read); p, q out
-    const double ab = (double)sz * Bn * (7 * D(nh));
-    int cur = 0;
+    // read); p out (q feeds only the partial sums)
+    const double ab = (double)sz * Bn * (6 * D(nh));
     // one PCG iteration: apply (with the previous step's t update), alpha and
     // the eigenvalue test, the V-cycle (with the residual update), beta
     auto iteration = [&](int it) -> mlqmc_status {
       if (it == 0) ctx->t_begin(MLQMC_K_APPLY);
       CK(launch_pupdate_apply<T>(nh, Bn, zc, vn, pp[cur], mvn, wT, t, S, it == 0, pp[1 - cur],
-                                 q, part, st),
+                                 nullptr, part, st),
          "apply");
       if (it == 0) ctx->t_end(MLQMC_K_APPLY, ab);
       cur = 1 - cur;
@@ -618,7 +619,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
         if (r == MLQMC_OK) r = iteration(2);
         st = keep;
         return r;
-      }, graph_key<T>(nh, Bn, o, S, {zc, zo, rc, ro, pp[0], pp[1], vn, mvn, wT, t, q, part, act,
+      }, graph_key<T>(nh, Bn, o, S, {zc, zo, rc, ro, pp[0], pp[1], vn, mvn, wT, t, part, act,
                                      active}, W, X, Xb, Bv, nblk0, nblk_post), &exec));
       while (done_its < o->max_lin_iter) {
         CK(hipGraphLaunch(exec, st), "graph launch");

@@ -534,7 +534,7 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
       const T qv = ap - mu * hm * m12;
       const int64_t o = b * g.P + j * n + c;
       pout[o] = pc;
-      q[o] = qv;
+      if (q) q[o] = qv;
       // t_k = t_{k-1} + alpha_{k-1} p_{k-1}, the iterate this step starts from
       T tn = rc.tt;
       if (!first) {
@@ -608,16 +608,19 @@ __device__ __forceinline__ constexpr double sweep_omega(int m) {
 // With kUpd (the finest level inside the PCG loop) the right-hand side is
 // first brought up to date, r' = r - alpha (q - c M vn), and r' written to
 // rout on the rows the strip owns (a second buffer: neighbouring strips still
-// read r on their halo rows).
+// read r on their halo rows).  q = (A - mu M) p is recomputed here from the
+// direction p (a ring of p rows two rows ahead of the first sweep) with the
+// same operations as the apply kernel, so q is never stored.
 template <typename T, int NTC, int CPT, bool kUpd, int NS>
 __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
                                              const T* __restrict__ rhs, T* __restrict__ X,
                                              T* __restrict__ rhs_c,
                                              const uint8_t* __restrict__ active,
-                                             const T* __restrict__ qd, const T* __restrict__ mvn,
+                                             const T* __restrict__ pd, const T* __restrict__ mvn,
                                              FineState S, T* __restrict__ rout) {
   constexpr int NR = NTC * CPT + 1;
-  __shared__ T s_sw[NS][4][NR], s_res[4][NR];
+  constexpr int PR = kUpd ? 4 : 1, PN = kUpd ? NR : 1;
+  __shared__ T s_sw[NS][4][NR], s_res[4][NR], s_p[PR][PN];
   int64_t b;
   int s;
   if (!map_strip<NTC, CPT>(g, b, s) || !active[b]) return;
@@ -631,22 +634,39 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
   const T* wy = wx + g.P;
   T* xb = X + b * g.P;
   T* cb = rhs_c + b * (int64_t)((nc + 2) * nc);
-  T alpha = T(0), cc = T(0);
+  T alpha = T(0), cc = T(0), mu = T(0);
+  const T hm = (T)mass_scale(n);
   if constexpr (kUpd) {
     alpha = (T)S.alpha[b];
     cc = (T)S.c[b];
+    mu = (T)S.mu[b];
   }
   if (t == 0)
     for (int r = 0; r < 4; ++r) {
 #pragma unroll
       for (int m = 0; m < NS; ++m) s_sw[m][r][n] = T(0);
       s_res[r][n] = T(0);
+      if constexpr (kUpd) s_p[r][n] = T(0);
     }
   // register window of the row inputs (rhs, the 4 edge weights) of the rows
   // at the NS sweep stages and the residual stage: each is loaded once, one
-  // row ahead of the first sweep (nx; with kUpd also q and M vn), and carried
+  // row ahead of the first sweep (nx; with kUpd also M vn), and carried
   // through the stages (in[0] -> in[NS])
   T nx[CPT][7], in[NS + 1][CPT][5];
+  // with kUpd: p of the row the ring takes next, loaded one iteration early
+  T pn[CPT];
+  auto fetch_p = [&](int j) {
+    const bool ok = (j >= 1 && j <= n - 1);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = t + q * NTC;
+      pn[q] = (ok && c >= 1) ? pd[b * g.P + j * n + c] : T(0);
+    }
+  };
+  auto store_p = [&](int j) {
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) s_p[j & 3][t + q * NTC] = pn[q];
+  };
   auto fetch = [&](int j) {
     if (!(j >= 1 && j <= n - 1)) return;
 #pragma unroll
@@ -658,22 +678,28 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
         nx[q][2] = wx[k + 1];
         nx[q][3] = wy[k];
         nx[q][4] = wy[k + n];
-        if constexpr (kUpd) {
-          nx[q][5] = qd[b * g.P + k];
-          nx[q][6] = mvn[b * g.P + k];
-        }
+        if constexpr (kUpd) nx[q][6] = mvn[b * g.P + k];
       }
     }
   };
   const int jfirst = dir > 0 ? lo - NS : hi + NS;
   const int last = hi - lo + 2 * NS;
   fetch(jfirst);
+  if constexpr (kUpd) {  // the p ring holds rows j - 1 .. j + 1 when row j is updated
+    for (int d = -1; d <= 1; ++d) {
+      fetch_p(jfirst + d * dir);
+      store_p(jfirst + d * dir);
+    }
+    fetch_p(jfirst + 2 * dir);
+    __syncthreads();
+  }
   for (int i = 0; i <= last; ++i) {
     const int j = jfirst + i * dir;
     // first sweep (from zero) at row j
     {
       T* row = s_sw[0][j & 3];
       const bool ok = (j >= 1 && j <= n - 1);
+      T mvj[CPT];
 #pragma unroll
       for (int q = 0; q < CPT; ++q) {
 #pragma unroll
@@ -682,15 +708,32 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
           for (int e = 0; e < 5; ++e) in[m][q][e] = in[m - 1][q][e];
 #pragma unroll
         for (int e = 0; e < 5; ++e) in[0][q][e] = nx[q][e];
-        if constexpr (kUpd) in[0][q][0] = nx[q][0] - alpha * (nx[q][5] - cc * nx[q][6]);
+        if constexpr (kUpd) mvj[q] = nx[q][6];
       }
       if (i < last) fetch(j + dir);
+      if constexpr (kUpd) {
+        // slot of row j + 2 dir is free (row j - 2 dir is done with); read
+        // from the next iteration on, after this one's barriers
+        store_p(j + 2 * dir);
+        if (i < last) fetch_p(j + 3 * dir);
+      }
 #pragma unroll
       for (int q = 0; q < CPT; ++q) {
         const int c = t + q * NTC, k = j * n + c;
         T v = T(0);
         if (ok && c >= 1) {
           if constexpr (kUpd) {
+            const T* xs = s_p[(j - 1) & 3];
+            const T* xc = s_p[j & 3];
+            const T* xn = s_p[(j + 1) & 3];
+            const T* inq = in[0][q];
+            const T pc = xc[c];
+            const T ap = inq[1] * (pc - xc[c - 1]) + inq[2] * (pc - xc[c + 1]) +
+                         inq[3] * (pc - xs[c]) + inq[4] * (pc - xn[c]);
+            const T m12 = T(6) * pc + xc[c - 1] + xc[c + 1] + xs[c] + xn[c] + xn[c + 1] +
+                          xs[c - 1];
+            const T qv = ap - mu * hm * m12;
+            in[0][q][0] = inq[0] - alpha * (qv - cc * mvj[q]);
             if (j >= lo && j < own_hi) rout[b * g.P + k] = in[0][q][0];
           }
           v = T(sweep_omega<NS>(0)) * in[0][q][0] /
@@ -1286,20 +1329,20 @@ inline dim3 sgrid(const VGeo& g) {
 
 template <typename T>
 hipError_t launch_pre(int n, int64_t B, const T* w, const T* rhs, T* X, T* rhs_c,
-                      const uint8_t* active, const T* q, const T* mvn, const FineState* S,
+                      const uint8_t* active, const T* p, const T* mvn, const FineState* S,
                       T* rout, hipStream_t st) {
   const VGeo g = vgeo_pre(n, B);
-  const bool upd = q != nullptr;
+  const bool upd = p != nullptr;
   if (upd && (!mvn || !S || !rout || rout == rhs)) return hipErrorInvalidValue;
   const FineState s0 = S ? *S : FineState{};
   ROW_DISPATCH(n, {
     if (NTC * CPT != n) return hipErrorInvalidValue;  // a block covers one full row
     if (upd)
       hipLaunchKernelGGL((k_pre<T, NTC, CPT, true, kFineSweeps>), sgrid(g), dim3(NTC), 0, st, g,
-                         w, rhs, X, rhs_c, active, q, mvn, s0, rout);
+                         w, rhs, X, rhs_c, active, p, mvn, s0, rout);
     else
       hipLaunchKernelGGL((k_pre<T, NTC, CPT, false, kFineSweeps>), sgrid(g), dim3(NTC), 0, st, g,
-                         w, rhs, X, rhs_c, active, q, mvn, s0, rout);
+                         w, rhs, X, rhs_c, active, p, mvn, s0, rout);
   });
   return hipGetLastError();
 }

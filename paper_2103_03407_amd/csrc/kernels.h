@@ -108,20 +108,25 @@ hipError_t launch_setup_dots(int n, int64_t B, const double* uH, int nH, const d
 template <typename T>
 hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const double* w64,
                             const FineState& S, T* r, T* vn, T* mvn, hipStream_t st);
+// the new direction pout = z - c2 vn + beta pin and q = (A - mu M) pout (stored
+// only if q != nullptr), with the dot-product partials of the step
 template <typename T>
 hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
                                 const T* mvn, const T* w, T* t, const FineState& S,
                                 int first, T* pout, T* q, double* part, hipStream_t st);
 // fused V-cycle level, pre-smoothing from zero and restriction:
-//   X = two damped-Jacobi sweeps on A X = rhs from X = 0; rhs_c = P^T (rhs - A X);
-//   with q != nullptr the rhs is first updated, rhs - alpha (q - c mvn) -> rout
+//   X = Chebyshev-weighted Jacobi sweeps on A X = rhs from X = 0;
+//   rhs_c = P^T (rhs - A X); with p != nullptr (the current direction) the rhs
+//   is first updated, rhs - alpha (q - c mvn) -> rout, q = (A - mu M) p
+//   recomputed from p
 template <typename T>
 hipError_t launch_pre(int n, int64_t B, const T* w, const T* rhs, T* X, T* rhs_c,
-                      const uint8_t* active, const T* q, const T* mvn, const FineState* S,
+                      const uint8_t* active, const T* p, const T* mvn, const FineState* S,
                       T* rout, hipStream_t st);
 // fused V-cycle level, coarse correction and post-smoothing:
-//   Xout = two sweeps from Xin + P Xc; with part != nullptr also the partials
-//   rhs.Xout, mvn.Xout, rhs.vn per strip (level 0 of the projected PCG)
+//   Xout = Chebyshev-weighted sweeps from Xin + P Xc; with part != nullptr also
+//   the partials rhs.Xout, mvn.Xout, rhs.vn per strip (level 0 of the projected
+//   PCG; rhs.vn is 0 with FP64 storage)
 template <typename T>
 hipError_t launch_post(int n, int64_t B, const T* w, const T* rhs, const T* Xin, const T* Xc,
                        T* Xout, const T* vn, const T* mvn, const uint8_t* active, double* part,
