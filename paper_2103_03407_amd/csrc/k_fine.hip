@@ -434,7 +434,12 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
                                                        int first, T* __restrict__ pout,
                                                        T* __restrict__ q,
                                                        double* __restrict__ part) {
+  // FP64 storage: M vn is recomputed from a ring of vn rows (vn is read anyway)
+  // instead of being read; FP32 storage reads the stored M vn, rounded from
+  // the FP64 product at set-up
+  constexpr bool kMv = sizeof(T) == 8;
   __shared__ T ring[4][NTC + 2];
+  __shared__ T ringv[kMv ? 4 : 1][kMv ? NTC + 2 : 1];
   int64_t b;
   int c0, j0, j1, blk, dir;
   if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir) || !S.active[b]) return;
@@ -488,6 +493,12 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
     row[ci] = f.z - c2 * f.v + beta * f.p;
     if (hl) row[0] = f.zh - c2 * f.vh + beta * f.ph;
     if (hr) row[NTC + 1] = f.zh - c2 * f.vh + beta * f.ph;
+    if constexpr (kMv) {
+      T* rv = ringv[j & 3];
+      rv[ci] = f.v;
+      if (hl) rv[0] = f.vh;
+      if (hr) rv[NTC + 1] = f.vh;
+    }
   };
   auto fetch_row = [&](int j, Row& r) {
     if (c >= 1 && j >= j0 && j < j1) {
@@ -496,7 +507,7 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
       r.we = wx[k + 1];
       r.ws = wy[k];
       r.wn = wy[k + n];
-      r.m = mb[k];
+      if constexpr (!kMv) r.m = mb[k];
       r.tt = tread ? tb[k] : T(0);
     }
   };
@@ -544,7 +555,16 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
       const double tk = (double)tn;
       s[0] += (double)pc * (double)qv;
       s[1] += (double)sv * (double)qv;
-      s[2] += (double)pc * (double)rc.m;
+      if constexpr (kMv) {
+        const T* vs = ringv[(j - 1) & 3];
+        const T* vc = ringv[j & 3];
+        const T* vnr = ringv[(j + 1) & 3];
+        const T mv = hm * (T(6) * vc[ci] + vc[ci - 1] + vc[ci + 1] + vs[ci] + vnr[ci] +
+                           vnr[ci + 1] + vs[ci - 1]);
+        s[2] += (double)pc * (double)mv;
+      } else {
+        s[2] += (double)pc * (double)rc.m;
+      }
       s[3] += (double)pc * (double)m12;
       s[4] += tk * (double)m12;
       s[5] += tk * (double)qv;
