@@ -578,15 +578,14 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     all_active = false;
     const int nblk_post = post_strips(nh, Bn);
     CK(launch_scalar(PH_FIRST_RZ, nh, Bn, nblk_post, part, S, 0.0, 0, st), "scalar");
-    // first apply: z, vn, 2 weights per node in, and M vn in FP32 storage (FP64
-    // recomputes it from vn); no previous p, t = 0 not read; p out (q feeds
-    // only the partial sums)
-    const double ab = (double)sz * Bn * ((kMixed ? 6 : 5) * D(nh));
+    // first apply: z, vn, 2 weights per node in (M vn is formed from vn; no
+    // previous p; t = 0 not read); p out (q feeds only the partial sums)
+    const double ab = (double)sz * Bn * (5 * D(nh));
     // one PCG iteration: apply (with the previous step's t update), alpha and
     // the eigenvalue test, the V-cycle (with the residual update), beta
     auto iteration = [&](int it) -> mlqmc_status {
       if (it == 0) ctx->t_begin(MLQMC_K_APPLY);
-      CK(launch_pupdate_apply<T>(nh, Bn, zc, vn, pp[cur], mvn, wT, t, S, it == 0, pp[1 - cur],
+      CK(launch_pupdate_apply<T>(nh, Bn, zc, vn, pp[cur], wT, t, S, it == 0, pp[1 - cur],
                                  nullptr, part, st),
          "apply");
       if (it == 0) ctx->t_end(MLQMC_K_APPLY, ab);

@@ -428,25 +428,22 @@ template <typename T, int NTC>
 __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restrict__ z,
                                                        const T* __restrict__ vn,
                                                        const T* __restrict__ pin,
-                                                       const T* __restrict__ mvn,
                                                        const T* __restrict__ w,
                                                        T* __restrict__ t, FineState S,
                                                        int first, T* __restrict__ pout,
                                                        T* __restrict__ q,
                                                        double* __restrict__ part) {
-  // FP64 storage: M vn is recomputed from a ring of vn rows (vn is read anyway)
-  // instead of being read; FP32 storage reads the stored M vn, rounded from
-  // the FP64 product at set-up
-  constexpr bool kMv = sizeof(T) == 8;
+  // M vn is recomputed from a ring of vn rows (vn is read anyway) instead of
+  // being read; in FP32 storage it then differs from the stored M vn the
+  // other kernels read by rounding only
   __shared__ T ring[4][NTC + 2];
-  __shared__ T ringv[kMv ? 4 : 1][kMv ? NTC + 2 : 1];
+  __shared__ T ringv[4][NTC + 2];
   int64_t b;
   int c0, j0, j1, blk, dir;
   if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir) || !S.active[b]) return;
   const T* zz = z + b * g.P;
   const T* vb = vn + b * g.P;
   const T* pb = pin + b * g.P;
-  const T* mb = mvn + b * g.P;
   const T* wx = w + b * 2 * g.P;
   const T* wy = wx + g.P;
   T* tb = t + b * g.P;
@@ -463,14 +460,14 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
   const bool hok = (hl && c0 >= 2) || (hr && c0 + NTC <= n - 1);
   // Inputs are requested one row step before they are used: the sources of
   // the ring row p = z - c2 vn + beta p_prev (z, vn, p_prev at the column and
-  // the halo column) one row ahead of the ring, the stencil row's weights,
-  // M vn and t one row ahead of the stencil; vn and p_prev of a row are kept
-  // from its ring fill for its stencil step.
+  // the halo column) one row ahead of the rings, the stencil row's weights
+  // and t one row ahead of the stencil; vn and p_prev of a row are kept from
+  // its ring fill for its stencil step.
   struct Src {
     T z, v, p, zh, vh, ph;
   };
   struct Row {
-    T ww, we, ws, wn, m, tt;
+    T ww, we, ws, wn, tt;
   };
   auto fetch_src = [&](int j, Src& f) {
     const bool rowok = (j >= 1 && j <= n - 1);
@@ -493,12 +490,10 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
     row[ci] = f.z - c2 * f.v + beta * f.p;
     if (hl) row[0] = f.zh - c2 * f.vh + beta * f.ph;
     if (hr) row[NTC + 1] = f.zh - c2 * f.vh + beta * f.ph;
-    if constexpr (kMv) {
-      T* rv = ringv[j & 3];
-      rv[ci] = f.v;
-      if (hl) rv[0] = f.vh;
-      if (hr) rv[NTC + 1] = f.vh;
-    }
+    T* rv = ringv[j & 3];
+    rv[ci] = f.v;
+    if (hl) rv[0] = f.vh;
+    if (hr) rv[NTC + 1] = f.vh;
   };
   auto fetch_row = [&](int j, Row& r) {
     if (c >= 1 && j >= j0 && j < j1) {
@@ -507,7 +502,7 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
       r.we = wx[k + 1];
       r.ws = wy[k];
       r.wn = wy[k + n];
-      if constexpr (!kMv) r.m = mb[k];
+
       r.tt = tread ? tb[k] : T(0);
     }
   };
@@ -555,15 +550,13 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
       const double tk = (double)tn;
       s[0] += (double)pc * (double)qv;
       s[1] += (double)sv * (double)qv;
-      if constexpr (kMv) {
+      {
         const T* vs = ringv[(j - 1) & 3];
         const T* vc = ringv[j & 3];
         const T* vnr = ringv[(j + 1) & 3];
         const T mv = hm * (T(6) * vc[ci] + vc[ci - 1] + vc[ci + 1] + vs[ci] + vnr[ci] +
                            vnr[ci + 1] + vs[ci - 1]);
         s[2] += (double)pc * (double)mv;
-      } else {
-        s[2] += (double)pc * (double)rc.m;
       }
       s[3] += (double)pc * (double)m12;
       s[4] += tk * (double)m12;
@@ -1289,12 +1282,12 @@ hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const do
 
 template <typename T>
 hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
-                                const T* mvn, const T* w, T* t, const FineState& S,
-                                int first, T* pout, T* q, double* part, hipStream_t st) {
+                                const T* w, T* t, const FineState& S, int first, T* pout, T* q,
+                                double* part, hipStream_t st) {
   MARCH_DISPATCH(n, {
     const MGeo g = mgeo<NTC>(n, B);
     hipLaunchKernelGGL((k_pupdate_apply<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, z, vn, pin,
-                       mvn, w, t, S, first, pout, q, part);
+                       w, t, S, first, pout, q, part);
   });
   return hipGetLastError();
 }
@@ -1431,8 +1424,8 @@ hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* s
   template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, int, const double*,      \
                                           const FineState&, T*, T*, T*, hipStream_t);           \
   template hipError_t launch_pupdate_apply<T>(int, int64_t, const T*, const T*, const T*,       \
-                                              const T*, const T*, T*, const FineState&,         \
-                                              int, T*, T*, double*, hipStream_t);               \
+                                              const T*, T*, const FineState&, int, T*, T*,      \
+                                              double*, hipStream_t);                            \
   template hipError_t launch_final_dots<T>(int, int64_t, const double*, int, const T*,          \
                                            const T*, const T*, const double*, const FineState&, \
                                            double*, hipStream_t);
