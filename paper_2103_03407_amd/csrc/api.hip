@@ -101,7 +101,7 @@ struct mlqmc_ctx {
     }
     if (b.p) {
       zeroed.erase(b.p);
-      hipFree(b.p);
+      (void)hipFree(b.p);
       bytes_alloc -= (int64_t)b.bytes;
       b.p = nullptr;
       b.bytes = 0;
@@ -146,9 +146,10 @@ struct mlqmc_ctx {
     Table& t = tables[n];
     if (t.s < s || !t.el) {
       const int64_t per_row = (int64_t)2 * n * n + 2 * (n - 1) * n + 2 * padded_size(n);
-      if (t.el) hipFree(t.el);
-      if (t.edge) hipFree(t.edge);
-      if (t.pad) hipFree(t.pad);
+      // a failed free leaves a sticky error that the next HIP call reports
+      if (t.el) (void)hipFree(t.el);
+      if (t.edge) (void)hipFree(t.edge);
+      if (t.pad) (void)hipFree(t.pad);
       bytes_alloc -= (int64_t)t.s * per_row * 8;
       t.el = t.edge = t.pad = nullptr;
       t.s = 0;
@@ -177,16 +178,22 @@ struct mlqmc_ctx {
   void t_begin(int cls) {
     if (!timed(cls)) return;
     if (ev_used == ev_pool.size()) {
-      hipEvent_t a, b;
-      hipEventCreate(&a);
-      hipEventCreate(&b);
+      hipEvent_t a = nullptr, b = nullptr;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        timing_class = MLQMC_K_NONE;  // instrumentation only: stop timing, keep computing
+        return;
+      }
       ev_pool.push_back({a, b});
     }
-    hipEventRecord(ev_pool[ev_used].first, stream);
+    if (hipEventRecord(ev_pool[ev_used].first, stream) != hipSuccess) timing_class = MLQMC_K_NONE;
   }
   void t_end(int cls, double bytes) {
     if (!timed(cls)) return;
-    hipEventRecord(ev_pool[ev_used].second, stream);
+    if (hipEventRecord(ev_pool[ev_used].second, stream) != hipSuccess) {
+      timing_class = MLQMC_K_NONE;
+      return;
+    }
     ++ev_used;
     ++t_launches;
     t_bytes += bytes;
@@ -194,8 +201,7 @@ struct mlqmc_ctx {
   void t_collect() {
     for (size_t k = 0; k < ev_used; ++k) {
       float ms = 0.f;
-      hipEventElapsedTime(&ms, ev_pool[k].first, ev_pool[k].second);
-      t_ms += ms;
+      if (hipEventElapsedTime(&ms, ev_pool[k].first, ev_pool[k].second) == hipSuccess) t_ms += ms;
     }
     ev_used = 0;
   }
@@ -370,12 +376,12 @@ mlqmc_status pcg_graph(mlqmc_ctx* ctx, const char* tag, int64_t, F body,
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
   if (st != MLQMC_OK) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return st;
   }
   CK(e, "end capture");
   const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   CK(ei, "graph instantiate");
   g.key = key;
   *out = g.exec;
@@ -918,25 +924,26 @@ mlqmc_status mlqmc_create(mlqmc_ctx** out, const mlqmc_coeff* cf, int device, vo
 
 void mlqmc_destroy(mlqmc_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  // teardown: errors here have nowhere to go, and every release is attempted
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->bufs)
-    if (kv.second.p) hipFree(kv.second.p);
+    if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto& kv : ctx->tables) {
-    if (kv.second.el) hipFree(kv.second.el);
-    if (kv.second.edge) hipFree(kv.second.edge);
-    if (kv.second.pad) hipFree(kv.second.pad);
+    if (kv.second.el) (void)hipFree(kv.second.el);
+    if (kv.second.edge) (void)hipFree(kv.second.edge);
+    if (kv.second.pad) (void)hipFree(kv.second.pad);
   }
   for (auto& ev : ctx->ev_pool) {
-    hipEventDestroy(ev.first);
-    hipEventDestroy(ev.second);
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
   }
   for (auto& kv : ctx->graphs)
-    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
-  if (ctx->d_c) hipFree(ctx->d_c);
-  if (ctx->d_k1) hipFree(ctx->d_k1);
-  if (ctx->d_k2) hipFree(ctx->d_k2);
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->d_c) (void)hipFree(ctx->d_c);
+  if (ctx->d_k1) (void)hipFree(ctx->d_k1);
+  if (ctx->d_k2) (void)hipFree(ctx->d_k2);
   delete ctx;
 }
 
@@ -959,7 +966,7 @@ mlqmc_status lattice_entry(mlqmc_ctx* ctx, int64_t N, int32_t s, const int64_t* 
     if (!(shift[j] >= 0.0 && shift[j] < 1.0))
       return ctx->fail(MLQMC_EINVAL, "shift[%d] outside [0, 1)", j);
   }
-  hipSetDevice(ctx->device);
+  CK(hipSetDevice(ctx->device), "set device");
   const int64_t* dz;
   const double* dsh;
   double* dY;
@@ -995,7 +1002,7 @@ mlqmc_status mlqmc_coefficient(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B, 
   if (B < 0 || (B > 0 && (!aK || (s > 0 && !Y)))) return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
   if (!on_dev && B * s > 0 && !finite_host(Y, (size_t)(B * s)))
     return ctx->fail(MLQMC_EINVAL, "Y has non-finite entries");
-  hipSetDevice(ctx->device);
+  CK(hipSetDevice(ctx->device), "set device");
   Table* tb = nullptr;
   CS(ctx->table(n, s, &tb));
   const double* dY;
@@ -1016,7 +1023,7 @@ mlqmc_status mlqmc_apply_operator(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t 
   if (s < 0 || s > ctx->s_max) return ctx->fail(MLQMC_EINVAL, "s outside [0, s_max]");
   if (B < 0 || (B > 0 && (!sigma || !x || !out || (s > 0 && !Y))))
     return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
-  hipSetDevice(ctx->device);
+  CK(hipSetDevice(ctx->device), "set device");
   Table* tb = nullptr;
   CS(ctx->table(n, s, &tb));
   const int64_t D = (int64_t)(n - 1) * (n - 1), EW = 2LL * (n - 1) * n;
@@ -1039,7 +1046,7 @@ mlqmc_status mlqmc_prolong(mlqmc_ctx* ctx, int32_t nH, int32_t nh, int64_t B, co
   if (!is_pow2(nH) || !is_pow2(nh) || nH < 2 || nh < nH || nh > 4096)
     return ctx->fail(MLQMC_EINVAL, "need powers of two 2 <= nH <= nh <= 4096");
   if (B < 0 || (B > 0 && (!uH || !uh))) return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
-  hipSetDevice(ctx->device);
+  CK(hipSetDevice(ctx->device), "set device");
   const int64_t DH = (int64_t)(nH - 1) * (nH - 1), Dh = (int64_t)(nh - 1) * (nh - 1);
   const double* du;
   double* dv;
@@ -1065,7 +1072,7 @@ mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_o
   if (!dev && n * s > 0 && !finite_host(Y, (size_t)(n * s)))
     return ctx->fail(MLQMC_EINVAL, "Y has non-finite entries");
   ctx->mem_cap = o->device_mem_cap;
-  hipSetDevice(ctx->device);
+  CK(hipSetDevice(ctx->device), "set device");
   if (n == 0) return MLQMC_OK;
   const double* dY;
   double *dl, *dlp = nullptr, *dlc = nullptr;
@@ -1121,7 +1128,7 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
     soff += (int64_t)R * s;
   }
   ctx->mem_cap = o->device_mem_cap;
-  hipSetDevice(ctx->device);
+  CK(hipSetDevice(ctx->device), "set device");
   hipStream_t st = ctx->stream;
   const int dev = o->io_on_device;
   double *dQ, *dQh, *dV, *dest;
@@ -1223,7 +1230,7 @@ mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level
     if (!(shifts[k] >= 0.0 && shifts[k] < 1.0))
       return ctx->fail(MLQMC_EINVAL, "shift entry %lld outside [0, 1)", (long long)k);
   ctx->mem_cap = o->device_mem_cap;
-  hipSetDevice(ctx->device);
+  CK(hipSetDevice(ctx->device), "set device");
   hipStream_t st = ctx->stream;
   const int dev = o->io_on_device;
   double *dQ, *dQh, *dV, *dest, *dlo = nullptr;
@@ -1385,7 +1392,7 @@ mlqmc_status mlqmc_set_timing(mlqmc_ctx* ctx, int32_t cls) {
 mlqmc_status mlqmc_get_timing(mlqmc_ctx* ctx, int64_t* launches, double* total_ms,
                               double* model_bytes) {
   if (!ctx) return MLQMC_EINVAL;
-  hipSetDevice(ctx->device);
+  CK(hipSetDevice(ctx->device), "set device");
   CS(ctx->sync("timing"));
   if (launches) *launches = ctx->t_launches;
   if (total_ms) *total_ms = ctx->t_ms;

@@ -15,8 +15,8 @@
 // are not edges of an interior node are never read.  Weights use the same
 // (n+2) n positions per half.
 //
-// Work mapping: a launch covers B samples x nblk blocks of kNodesPerBlock
-// positions of rows 1..n-1.  Hardware block L runs on XCD L mod 8; sample b is
+// Work mapping: a launch covers B samples x nblk blocks (column blocks x row
+// strips of one sample).  Hardware block L runs on XCD L mod 8; sample b is
 // mapped to XCD b mod 8 and its blocks to consecutive slots of that XCD, so
 // the halo rows a block shares with its neighbours stay in one L2.
 //
@@ -34,43 +34,6 @@
 
 namespace mlqmc {
 namespace {
-
-constexpr int NT = kFineNT;
-constexpr int PT = kNodesPerBlock / kFineNT;  // positions per thread
-
-struct Geo {
-  int n, lg;     // n = 2^lg
-  int P;         // padded size (n+2) n
-  int nblk;      // blocks per sample
-  int64_t B;
-};
-
-__device__ __forceinline__ bool map_block(const Geo& g, int64_t& b, int& blk) {
-  const int64_t L = blockIdx.x;
-  const int xcd = (int)(L & 7);
-  const int64_t j = L >> 3;
-  b = ((j / g.nblk) << 3) + xcd;
-  blk = (int)(j % g.nblk);
-  return b < g.B;
-}
-
-// Interior positions of rows 1..n-1 owned by this thread.
-#define FOR_NODES(g, blk)                                                              \
-  _Pragma("unroll") for (int k_ = 0; k_ < PT; ++k_)                                    \
-    if (const int k = (g).n + (blk) * kNodesPerBlock + k_ * NT + threadIdx.x;          \
-        k < (g).n * (g).n && (k & ((g).n - 1)) != 0)
-
-template <int K>
-__device__ __forceinline__ void write_partials(double (&s)[K], double* part, int64_t b, int blk,
-                                               int nblk) {
-  __shared__ double red[K * (NT / 64)];
-  block_sums<NT, K>(s, red);
-  if (threadIdx.x == 0) {
-    const int64_t base = (b * nblk + blk) * K;
-#pragma unroll
-    for (int k = 0; k < K; ++k) part[base + k] = s[k];
-  }
-}
 
 template <typename T>
 __device__ __forceinline__ T diagW(const T* wx, const T* wy, int k, int n) {
@@ -126,7 +89,8 @@ constexpr int64_t kDefaultTargetBlocks = 65536;
 // Jacobi sweeps per smoothing step in the fused V-cycle kernels of the
 // batched levels (the kernels take 2 or 3; the weights follow from the
 // count).  Three saved under 0.1 PCG iterations per sample on 1/128 and 1/256
-// while every pre/post launch got longer (mixed precision lost 5-9 %), so two.
+// while every pre/post launch got longer (mixed-precision levels took 5-9 %
+// longer), so two.
 constexpr int kFineSweeps = 2;
 thread_local int64_t t_target_blocks = kDefaultTargetBlocks;
 inline int strips_for(int rows, int64_t units) {
@@ -1173,21 +1137,6 @@ __global__ __launch_bounds__(256) void k_apply_plain(int xblk, int n, int64_t B,
   double d;
   const double ax = stencil_A(xb, wx, wx + EX, n, i, j, id, d);
   out[b * D + id] = ax - sigma[b] * mass_scale(n) * stencil_M12(xb, n, i, j, id);
-}
-
-inline Geo geo(int n, int64_t B) {
-  Geo g;
-  g.n = n;
-  g.lg = 0;
-  while ((1 << g.lg) < n) ++g.lg;
-  g.P = (n + 2) * n;
-  g.nblk = fine_blocks(n);
-  g.B = B;
-  return g;
-}
-inline dim3 grid_of(const Geo& g) {
-  const int64_t Bp = (g.B + 7) / 8 * 8;
-  return dim3((unsigned)(Bp * g.nblk));
 }
 
 }  // namespace

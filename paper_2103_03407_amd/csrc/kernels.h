@@ -63,16 +63,13 @@ struct TgSmallArgs {
 hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st);
 
 // One V-cycle X = K^{-1} B per active sample on mesh NB <= 32 from padded global
-// arrays (weights [WX | WY], rhs, X; see k_fine.hip), computed in FP64 in LDS
-// whatever the storage type T of the global arrays.
+// arrays (weights [WX | WY], rhs, X; see k_fine.hip), computed in LDS in the
+// storage type T, three Chebyshev-weighted Jacobi sweeps per smoothing step.
 template <typename T>
 hipError_t launch_bottom_vcycle(int NB, int64_t B, const T* w, const T* rhs, T* X,
                                 const uint8_t* active, hipStream_t st);
 
 // ---------------- batched fine-mesh kernels (XCD-aware 1-D grid over samples x blocks) ----------------
-
-constexpr int kFineNT = 256;
-constexpr int kNodesPerBlock = 1024;
 
 struct FineState {      // per-sample scalars of the projected PCG, arrays of length B
   double *mu, *vs, *rho, *rz, *rz0, *alpha, *c, *c2, *beta, *lam;
@@ -88,8 +85,6 @@ struct FineState {      // per-sample scalars of the projected PCG, arrays of le
   uint8_t* flags;
 };
 
-// blocks per sample covering the positions of rows 1..n-1 of the padded layout
-inline int fine_blocks(int n) { return (n * n - n + kNodesPerBlock - 1) / kNodesPerBlock; }
 inline int64_t padded_size(int n) { return (int64_t)(n + 2) * n; }
 
 // zero the Dirichlet positions (rows 0, n, n+1 and column 0) of cnt padded arrays
