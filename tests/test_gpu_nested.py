@@ -245,3 +245,24 @@ def test_functional_nested_matches_level_values(ctx, fam):
             assert abs(QG[l, r] - want) <= 4e-9, (l, r)
     tot = QG.sum(axis=0)
     assert abs(estG[1] - np.var(tot, ddof=1) / R) <= 1e-10 * max(np.var(tot), 1e-30)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_functional_across_batches(ctx, prec):
+    # G written at each batch's offset when the batched solve splits the samples
+    lv = (128, 64, 32, 8, 64, 32)
+    n = 24
+    z = lattice_vector(1024, 64)
+    Y = qmc.lattice_points(z, 1024, shifts_for(21, 0, 1, 64)[0], range(n))
+    pr = m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED
+    out = []
+    for batch in (0, 10):
+        lam, lamp, g, gp = (np.empty(n) for _ in range(4))
+        fl = np.zeros(n, np.uint8)
+        st = ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp, g=g, g_prev=gp,
+                           opts=m.default_opts(prec=pr, batch=batch))
+        assert st == m.MLQMC_OK and not fl.any()
+        out.append((lam, lamp, g, gp))
+    tol = 1e-10 if prec == "fp64" else 1e-7
+    for a, b in zip(out[0], out[1]):
+        assert np.max(np.abs(a - b) / np.abs(b)) <= tol
