@@ -231,10 +231,14 @@ def per_level_nested(ctx, m, w, opts, idx=None, ref=None):
     return out, acc
 
 
-def _traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source changed since the counters were taken."""
-    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+def _traffic(kernel: str, prec: str = "fp64", cfg: int = 2):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel, precision and workload, or None when there is none or the
+    kernel source changed since the counters were taken."""
+    name = f"traffic_{kernel}" + ("" if prec == "fp64" else f"_{prec}")
+    if cfg != 2:
+        name += f"_cfg{cfg}"
+    p = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(p):
         return None
     try:
@@ -334,7 +338,8 @@ def main():
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 2),
                 "peak": PEAK_FP64_MFMA_TFS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_MFMA_TFS, 4), "traffic": _traffic(kname),
+                "frac": round(achieved / PEAK_FP64_MFMA_TFS, 4),
+                "traffic": _traffic(kname, a.prec, a.cfg),
                 "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
                 "algorithmic_flops_per_launch": flops_per_launch,
                 "hbm_GBs": round(kbytes / launches / (avg_ms * 1e-3) / 1e9, 1)}
@@ -344,7 +349,7 @@ def main():
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": _traffic(kname), "avg_launch_us": round(avg_ms * 1e3, 2),
+                "traffic": _traffic(kname, a.prec, a.cfg), "avg_launch_us": round(avg_ms * 1e3, 2),
                 "launches": launches, "algorithmic_bytes_per_launch": bytes_per_launch}
 
     cpu = None
