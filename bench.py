@@ -347,10 +347,17 @@ def main():
         avg_ms = kms / launches
         bytes_per_launch = kbytes / launches
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        traffic = _traffic(kname, a.prec, a.cfg)
         roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": _traffic(kname, a.prec, a.cfg), "avg_launch_us": round(avg_ms * 1e3, 2),
+                "traffic": traffic, "avg_launch_us": round(avg_ms * 1e3, 2),
                 "launches": launches, "algorithmic_bytes_per_launch": bytes_per_launch}
+        if traffic:
+            # the counted HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
+            # over the same live launch time: what the memory system moved
+            tg = traffic / (avg_ms * 1e-3) / 1e9
+            roof["traffic_GBs"] = round(tg, 1)
+            roof["traffic_frac"] = round(tg / PEAK_HBM_GBS, 4)
 
     cpu = None
     idx = ref = None
