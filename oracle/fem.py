@@ -1,7 +1,11 @@
-"""P1 finite element matrices (section 2.3, eq. fe-evp; b = 0, c = 1).
+"""P1 finite element matrices (section 2.3, eq. fe-evp; c = 1).
 
     A_ab = sum_K a_K |K| grad(phi_a) . grad(phi_b)      (stiffness, y-dependent)
+    R_ab = sum_K b_K |K|/12 (1 + delta_ab)              (reaction, Problem 2)
     M_ab = sum_K |K|/12 (1 + delta_ab)                  (mass, exact for c = 1)
+
+The reaction term uses the element value of b (centroid rule) with the exact
+P1 element mass matrix; for Problem 1 (b = 0) the operator is A alone.
 
 assembled element by element into CSR; the homogeneous Dirichlet condition
 removes the boundary nodes.  ``full=True`` keeps every node (used by tests
@@ -72,3 +76,22 @@ def mass(n: int, full: bool = False) -> sp.csr_matrix:
     M = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(N, N))
     return _restrict(M, n, full)
+
+
+def reaction(n: int, bK, full: bool = False) -> sp.csr_matrix:
+    """R(b) on mesh 1/n for per-element reaction values bK[2n^2]."""
+    bK = np.asarray(bK, dtype=np.float64)
+    el, area, _, _ = _element_geometry(n)
+    if bK.shape != (el.shape[0],):
+        raise ValueError("bK must have one value per element")
+    rows, cols, vals = [], [], []
+    for a in range(3):
+        for b in range(3):
+            rows.append(el[:, a])
+            cols.append(el[:, b])
+            vals.append(bK * area / 12.0 * (2.0 if a == b else 1.0))
+    N = (n + 1) * (n + 1)
+    R = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(N, N))
+    return _restrict(R, n, full)
+

@@ -45,9 +45,19 @@ def prolong(u_H: np.ndarray, nH: int, nh: int) -> np.ndarray:
     return out
 
 
+def operator(n: int, s: int, y, fam):
+    """The y-dependent operator on mesh 1/n with y_{1:s}: the stiffness matrix,
+    plus the reaction matrix for Problem 2 families."""
+    yy = np.asarray(y)[:s]
+    if fam.get("kind") == "islands":
+        aK, bK = coeff.islands_coefficients(n, yy, fam)
+        return fem.stiffness(n, aK) + fem.reaction(n, bK)
+    return fem.stiffness(n, coeff.coefficient(n, yy, fam))
+
+
 def coarse_pair(nH: int, S: int, y, fam):
     """Step 1: (lambda_{H,S}(y), u_{H,S}(y)) on mesh 1/nH with y_{1:S}."""
-    A = fem.stiffness(nH, coeff.coefficient(nH, np.asarray(y)[:S], fam))
+    A = operator(nH, S, y, fam)
     M = fem.mass(nH)
     return eig.smallest_eigenpair(A, M)
 
@@ -55,7 +65,7 @@ def coarse_pair(nH: int, S: int, y, fam):
 def two_grid_update(nh: int, s: int, y, fam, lam_H: float, u_H: np.ndarray, nH: int):
     """Steps 2-4 on mesh 1/nh with y_{1:s}, from a coarse pair on mesh 1/nH.
     Returns (lambda^h, w)."""
-    A = fem.stiffness(nh, coeff.coefficient(nh, np.asarray(y)[:s], fam))
+    A = operator(nh, s, y, fam)
     M = fem.mass(nh)
     v = prolong(u_H, nH, nh)
     lu = spla.splu((A - lam_H * M).tocsc())
@@ -73,6 +83,6 @@ def two_grid(nh: int, s: int, nH: int, S: int, y, fam):
 
 def direct(nh: int, s: int, y, fam):
     """lambda_{h,s}(y): the FE eigenvalue by a direct eigensolve (section 2.4)."""
-    A = fem.stiffness(nh, coeff.coefficient(nh, np.asarray(y)[:s], fam))
+    A = operator(nh, s, y, fam)
     M = fem.mass(nh)
     return eig.smallest_eigenpair(A, M)

@@ -8,13 +8,14 @@ element operators, the eigensolves and the estimator are computed separately
 by ``oracle/`` (plain CPU reference) and by the HIP library.
 """
 
-from .family import coeff_family, problem1_family, pair_ordering
+from .family import coeff_family, islands_family, problem1_family, pair_ordering
 from .cbc import cbc_vector, lattice_vector
 from .configs import CONFIGS, LevelSpec, Workload, workload, shifts_for
 
 __all__ = [
     "coeff_family",
     "problem1_family",
+    "islands_family",
     "pair_ordering",
     "cbc_vector",
     "lattice_vector",

@@ -1,0 +1,95 @@
+"""Pins for the oracle's Problem 2 (islands: reaction term, region-masked
+coefficients) from the numerical section.
+
+* the islands cover a quarter of the domain, element by element, on every
+  mesh aligned with them, and the region test matches hand-picked points;
+* the reaction matrix of a constant b is b times the mass matrix;
+* with constant a and b the eigenvalue is a lambda(-Laplace) + b;
+* each term changes the coefficients on its own region only, and the
+  background values take exactly their two values;
+* adding reaction on the islands raises the eigenvalue, by at most the
+  added amount (min-max);
+* the two-grid value tends to the direct one as the coarse mesh is refined.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import coeff, eig, fem, mesh, twogrid
+from synth import islands_family
+
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_islands_cover_a_quarter(n):
+    xc, yc = mesh.centroids(n)
+    inside = coeff.in_islands(xc, yc)
+    assert inside.sum() * 4 == inside.size
+
+
+def test_region_test_hand_points():
+    pts = [((0.2, 0.2), True), ((0.5, 0.2), False), ((0.7, 0.8), True),
+           ((0.125, 0.375), True), ((0.4, 0.6), False), ((0.9, 0.7), False),
+           ((0.3, 0.65), True)]
+    for (x, y), want in pts:
+        assert bool(coeff.in_islands(x, y)) is want, (x, y)
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_reaction_of_constant_is_mass(n):
+    c = 0.37
+    R = fem.reaction(n, np.full(2 * n * n, c))
+    M = fem.mass(n)
+    assert abs(R - c * M).max() <= 1e-17
+
+
+def test_constant_coefficients_shift_the_laplacian_eigenvalue():
+    a, b = 0.013, 1.7
+    fam = {"kind": "islands", "a0_in": a, "a0_out": a, "b0_in": b, "b0_out": b,
+           "ca": np.zeros(0), "cb": np.zeros(0), "k1": np.zeros(0, np.int32),
+           "k2": np.zeros(0, np.int32), "region": np.zeros(0, np.int32)}
+    n = 16
+    lam, _ = twogrid.direct(n, 0, np.zeros(0), fam)
+    lap, _ = eig.smallest_eigenpair(fem.stiffness(n, np.ones(2 * n * n)), fem.mass(n))
+    assert abs(lam - (a * lap + b)) <= 1e-12 * lam
+
+
+def test_terms_live_on_their_region():
+    fam = islands_family(4, 2.0, 2.0, 2.0, 2.0)
+    n = 16
+    xc, yc = mesh.centroids(n)
+    inside = coeff.in_islands(xc, yc)
+    a0, b0 = coeff.islands_coefficients(n, np.zeros(4), fam)
+    assert set(np.unique(a0)) == {fam["a0_in"], fam["a0_out"]}
+    assert np.all((a0 == fam["a0_in"]) == inside) and np.all((b0 == fam["b0_in"]) == inside)
+    for j in range(4):
+        y = np.zeros(4)
+        y[j] = 0.4
+        a, b = coeff.islands_coefficients(n, y, fam)
+        own = inside if fam["region"][j] == 1 else ~inside
+        assert np.all(a[~own] == a0[~own]) and np.all(b[~own] == b0[~own])
+        assert np.any(a[own] != a0[own]) and np.any(b[own] != b0[own])
+
+
+def test_reaction_on_islands_raises_lambda_by_at_most_the_increase():
+    fam = islands_family(6, 4.0 / 3.0, 2.0, 4.0 / 3.0, 2.0)
+    y = np.array([0.3, -0.2, 0.45, -0.4, 0.1, 0.0])
+    n = 16
+    lam, _ = twogrid.direct(n, 6, y, fam)
+    more = dict(fam)
+    more["b0_in"] = fam["b0_in"] + 0.5
+    lam2, _ = twogrid.direct(n, 6, y, more)
+    assert lam < lam2 <= lam + 0.5
+
+
+def test_two_grid_tends_to_direct():
+    fam = islands_family(6, 2.0, 2.0, 2.0, 2.0)
+    y = np.array([0.3, -0.2, 0.45, -0.4, 0.1, 0.0])
+    h = 32
+    lam, _ = twogrid.direct(h, 6, y, fam)
+    errs = []
+    for H in (8, 16):
+        errs.append(abs(twogrid.two_grid(h, 6, H, 6, y, fam)[0] - lam))
+    assert errs[1] < errs[0] and errs[1] < 1e-3 * lam
+    assert all(twogrid.two_grid(h, 6, H, 6, y, fam)[0] >= lam * (1 - 1e-13) for H in (8, 16))
