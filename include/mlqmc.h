@@ -112,6 +112,35 @@ void mlqmc_default_opts(mlqmc_opts* opt);
  * the coefficient family. */
 mlqmc_status mlqmc_create(mlqmc_ctx** out, const mlqmc_coeff* coeff, int device,
                           void* hip_stream);
+/* Problem 2 of the numerical section (the domain with four interior islands
+ * D_f = [1/8,3/8] or [5/8,7/8] in each coordinate): a diffusion coefficient a
+ * and a reaction coefficient b, both affine in y with region-wise parts,
+ *   a(x, y) = a0(x) + sum_{j<s} y_j ca[j] phi_j(x),
+ *   b(x, y) = b0(x) + sum_{j<s} y_j cb[j] phi_j(x),
+ *   a0 = a0_in on D_f and a0_out elsewhere (b0 likewise),
+ *   phi_j = sin(pi k1[j] x1) sin(pi k2[j] x2) on region[j] (1: D_f, 2: the
+ *           rest of D) and 0 on the other region.
+ * The operator is the P1 stiffness matrix of a plus the P1 mass matrix
+ * weighted by b (the element mass matrices times b at the centroid). */
+typedef struct {
+  int32_t s_max;
+  double a0_in, a0_out, b0_in, b0_out;
+  const double* ca;       /* [s_max] host */
+  const double* cb;       /* [s_max] host */
+  const int32_t* k1;      /* [s_max] host, >= 1 */
+  const int32_t* k2;      /* [s_max] host, >= 1 */
+  const int32_t* region;  /* [s_max] host, 1 or 2 */
+} mlqmc_islands;
+
+/* Creates a context for the Problem 2 family (arguments as mlqmc_create).
+ * Requires a >= a0_* - 0.5 sum |ca| > 0 and b >= 0 on each region for all
+ * |y_j| <= 1/2 (MLQMC_EINVAL otherwise).  Contexts of this family run in
+ * MLQMC_FP64 on meshes 1/8 .. 1/32 (every array of a solve in LDS; meshes are
+ * multiples of 1/8 so that the islands' edges are mesh lines); the level and
+ * estimator calls return MLQMC_EINVAL for other meshes or precisions, and
+ * mlqmc_coefficient / mlqmc_apply_operator for any call (they cover Problem 1). */
+mlqmc_status mlqmc_create_islands(mlqmc_ctx** out, const mlqmc_islands* cf, int device,
+                                  void* hip_stream);
 /* Frees everything the context allocated.  NULL-safe. */
 void mlqmc_destroy(mlqmc_ctx* ctx);
 /* Text of the last error on this context (owned by ctx, valid until the next
@@ -179,7 +208,10 @@ mlqmc_status mlqmc_prolong(mlqmc_ctx* ctx, int32_t nH, int32_t nh, int64_t B, co
  * the level's eigenvector approximation (the direct eigenvector, or the
  * two-grid w) normalised to ||u||_M = 1 with the sign that makes the
  * integral positive; g_prev the same for the level-(l-1) approximation
- * (written only if n_prev > 0).  Returns MLQMC_ENOCONV if any flag is set. */
+ * (written only if n_prev > 0).  With g or g_prev requested the two-grid
+ * solves stop on the residual test alone, and each converged eigenvector of
+ * the RQ iteration (direct or coarse) is refined by one correction solve to
+ * lin_rtol (FP64).  Returns MLQMC_ENOCONV if any flag is set. */
 mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* lvl, const mlqmc_opts* opt,
                              int64_t n, const double* Y, int32_t warm_chain, double* lam,
                              double* lam_prev, double* lam_coarse, int32_t* rq_iters,

@@ -25,7 +25,8 @@ K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE, K_PRE = 0, 1, 2, 3, 4, 5
 
 # every symbol include/mlqmc.h declares
 EXPORTS = [
-    "mlqmc_default_opts", "mlqmc_create", "mlqmc_destroy", "mlqmc_last_error",
+    "mlqmc_default_opts", "mlqmc_create", "mlqmc_create_islands", "mlqmc_destroy",
+    "mlqmc_last_error",
     "mlqmc_lattice_points", "mlqmc_embedded_points", "mlqmc_coefficient",
     "mlqmc_apply_operator", "mlqmc_prolong", "mlqmc_eig_level", "mlqmc_estimate",
     "mlqmc_estimate_nested", "mlqmc_set_tuning", "mlqmc_set_timing", "mlqmc_get_timing",
@@ -41,6 +42,14 @@ class MlqmcError(RuntimeError):
 class Coeff(C.Structure):
     _fields_ = [("s_max", C.c_int32), ("a0", C.c_double), ("c", C.POINTER(C.c_double)),
                 ("k1", C.POINTER(C.c_int32)), ("k2", C.POINTER(C.c_int32))]
+
+
+class Islands(C.Structure):
+    _fields_ = [("s_max", C.c_int32), ("a0_in", C.c_double), ("a0_out", C.c_double),
+                ("b0_in", C.c_double), ("b0_out", C.c_double),
+                ("ca", C.POINTER(C.c_double)), ("cb", C.POINTER(C.c_double)),
+                ("k1", C.POINTER(C.c_int32)), ("k2", C.POINTER(C.c_int32)),
+                ("region", C.POINTER(C.c_int32))]
 
 
 class Level(C.Structure):
@@ -81,6 +90,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlqmc_default_opts.argtypes = [C.POINTER(Opts)]
     lib.mlqmc_default_opts.restype = None
     lib.mlqmc_create.argtypes = [C.POINTER(P), C.POINTER(Coeff), C.c_int, P]
+    lib.mlqmc_create_islands.argtypes = [C.POINTER(P), C.POINTER(Islands), C.c_int, P]
     lib.mlqmc_destroy.argtypes = [P]
     lib.mlqmc_destroy.restype = None
     lib.mlqmc_last_error.argtypes = [P]
@@ -99,8 +109,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlqmc_set_tuning.argtypes = [P, I32, I32, I64]
     lib.mlqmc_set_timing.argtypes = [P, I32]
     lib.mlqmc_get_timing.argtypes = [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
-    for name in ("mlqmc_create", "mlqmc_lattice_points", "mlqmc_embedded_points",
-                 "mlqmc_coefficient", "mlqmc_apply_operator", "mlqmc_prolong",
+    for name in ("mlqmc_create", "mlqmc_create_islands", "mlqmc_lattice_points",
+                 "mlqmc_embedded_points", "mlqmc_coefficient", "mlqmc_apply_operator", "mlqmc_prolong",
                  "mlqmc_eig_level", "mlqmc_estimate", "mlqmc_estimate_nested",
                  "mlqmc_set_tuning", "mlqmc_set_timing", "mlqmc_get_timing"):
         getattr(lib, name).restype = C.c_int
@@ -147,15 +157,28 @@ def _one_side(*flags):
 
 
 class Context:
-    """An mlqmc_ctx bound to one device and stream."""
+    """An mlqmc_ctx bound to one device and stream.  ``family`` is a Problem 1
+    table (keys a0, c, k1, k2) or, with ``kind == "islands"``, a Problem 2 table
+    (keys a0_in, a0_out, b0_in, b0_out, ca, cb, k1, k2, region)."""
 
     def __init__(self, family, device: int = 0, stream=None):
         lib = load()
-        c = np.ascontiguousarray(family["c"], dtype=np.float64)
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int32)
         k1 = np.ascontiguousarray(family["k1"], dtype=np.int32)
         k2 = np.ascontiguousarray(family["k2"], dtype=np.int32)
-        cf = Coeff(int(c.size), float(family["a0"]), c.ctypes.data_as(C.POINTER(C.c_double)),
-                   k1.ctypes.data_as(C.POINTER(C.c_int32)), k2.ctypes.data_as(C.POINTER(C.c_int32)))
+        islands = family.get("kind") == "islands"
+        if islands:
+            c = np.ascontiguousarray(family["ca"], dtype=np.float64)
+            cb = np.ascontiguousarray(family["cb"], dtype=np.float64)
+            rg = np.ascontiguousarray(family["region"], dtype=np.int32)
+            cf = Islands(int(c.size), float(family["a0_in"]), float(family["a0_out"]),
+                         float(family["b0_in"]), float(family["b0_out"]), c.ctypes.data_as(dp),
+                         cb.ctypes.data_as(dp), k1.ctypes.data_as(ip), k2.ctypes.data_as(ip),
+                         rg.ctypes.data_as(ip))
+        else:
+            c = np.ascontiguousarray(family["c"], dtype=np.float64)
+            cf = Coeff(int(c.size), float(family["a0"]), c.ctypes.data_as(dp),
+                       k1.ctypes.data_as(ip), k2.ctypes.data_as(ip))
         if stream is None:
             try:
                 import torch
@@ -164,7 +187,8 @@ class Context:
             except ImportError:
                 stream = None
         h = C.c_void_p()
-        st = lib.mlqmc_create(C.byref(h), C.byref(cf), int(device), C.c_void_p(stream or 0))
+        create = lib.mlqmc_create_islands if islands else lib.mlqmc_create
+        st = create(C.byref(h), C.byref(cf), int(device), C.c_void_p(stream or 0))
         if st != MLQMC_OK:
             raise MlqmcError(st, lib.mlqmc_last_error(None).decode())
         self._lib, self._h = lib, h
@@ -352,6 +376,12 @@ class Context:
 
 # module-level functions with the C names
 def mlqmc_create(family, device=0, stream=None) -> Context:
+    return Context(family, device, stream)
+
+
+def mlqmc_create_islands(family, device=0, stream=None) -> Context:
+    if family.get("kind") != "islands":
+        raise ValueError("mlqmc_create_islands takes a Problem 2 (islands) family")
     return Context(family, device, stream)
 
 

@@ -28,11 +28,26 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Coefficient tables of one mesh.  Problem 1: s rows, one per term.
+// Problem 2: s + 1 rows, row 0 the background values a0, b0 by region; no
+// interior-layout table; the reaction b in rel / rpad.
 struct Table {
   int s = 0;
+  int64_t bytes = 0;
   double* el = nullptr;    // [s][2n^2]
   double* edge = nullptr;  // [s][2(n-1)n]   interior-layout edge weights (LDS kernels)
   double* pad = nullptr;   // [s][2(n+2)n]   padded [WX | WY] edge weights (batched kernels)
+  double* rel = nullptr;   // Problem 2: [s+1][2n^2] reaction at the centroids
+  double* rpad = nullptr;  // Problem 2: [s+1][3(n+2)n] padded [RX | RY | RD] edge means
+  void release() {
+    // a failed free leaves a sticky error that the next HIP call reports
+    for (double** q : {&el, &edge, &pad, &rel, &rpad}) {
+      if (*q) (void)hipFree(*q);
+      *q = nullptr;
+    }
+    s = 0;
+    bytes = 0;
+  }
 };
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
@@ -66,6 +81,11 @@ struct mlqmc_ctx {
   double* d_c = nullptr;
   int* d_k1 = nullptr;
   int* d_k2 = nullptr;
+  // Problem 2 (islands): d_c holds the diffusion terms, d_cb the reaction's
+  bool islands = false;
+  double a_in = 0.0, a_out = 0.0, b_in = 0.0, b_out = 0.0;
+  double* d_cb = nullptr;
+  int* d_region = nullptr;
   std::map<std::string, DevBuf> bufs;
   std::map<int, Table> tables;
   int64_t bytes_alloc = 0;
@@ -141,32 +161,47 @@ struct mlqmc_ctx {
     return s;
   }
 
-  // coefficient tables for mesh n with at least s rows
+  // coefficient tables for mesh n with at least s terms
   mlqmc_status table(int n, int s, Table** out) {
     Table& t = tables[n];
     if (t.s < s || !t.el) {
-      const int64_t per_row = (int64_t)2 * n * n + 2 * (n - 1) * n + 2 * padded_size(n);
-      // a failed free leaves a sticky error that the next HIP call reports
-      if (t.el) (void)hipFree(t.el);
-      if (t.edge) (void)hipFree(t.edge);
-      if (t.pad) (void)hipFree(t.pad);
-      bytes_alloc -= (int64_t)t.s * per_row * 8;
-      t.el = t.edge = t.pad = nullptr;
-      t.s = 0;
-      const int srows = std::max(s, 1);
-      const size_t be = (size_t)srows * 2 * n * n * 8, bw = (size_t)srows * 2 * (n - 1) * n * 8,
-                   bp = (size_t)srows * 2 * padded_size(n) * 8;
-      if (mem_cap > 0 && bytes_alloc + (int64_t)(be + bw + bp) > mem_cap)
+      bytes_alloc -= t.bytes;
+      t.release();
+      // Problem 1: one row per term; Problem 2: the background row and s terms
+      const int rows = islands ? s + 1 : std::max(s, 1);
+      const size_t be = (size_t)rows * 2 * n * n * 8,
+                   bw = islands ? 0 : (size_t)rows * 2 * (n - 1) * n * 8,
+                   bp = (size_t)rows * 2 * padded_size(n) * 8,
+                   br = islands ? (size_t)rows * 3 * padded_size(n) * 8 : 0;
+      const size_t total = be + bw + bp + (islands ? be + br : 0);
+      if (mem_cap > 0 && bytes_alloc + (int64_t)total > mem_cap)
         return fail(MLQMC_ENOMEM, "coefficient table for n=%d exceeds the device memory cap", n);
       hipError_t e = hipMalloc(&t.el, be);
-      if (e == hipSuccess) e = hipMalloc(&t.edge, bw);
+      if (e == hipSuccess && bw) e = hipMalloc(&t.edge, bw);
       if (e == hipSuccess) e = hipMalloc(&t.pad, bp);
-      if (e != hipSuccess) return fail(MLQMC_ENOMEM, "table allocation: %s", hipGetErrorString(e));
-      bytes_alloc += (int64_t)(be + bw + bp);
-      t.s = srows;
-      e = launch_phi_elements(n, srows, d_c, d_k1, d_k2, t.el, stream);
-      if (e == hipSuccess) e = launch_phi_edges(n, srows, t.el, t.edge, stream);
-      if (e == hipSuccess) e = launch_phi_edges_padded(n, srows, t.el, t.pad, stream);
+      if (e == hipSuccess && islands) e = hipMalloc(&t.rel, be);
+      if (e == hipSuccess && islands) e = hipMalloc(&t.rpad, br);
+      if (e != hipSuccess) {
+        t.release();
+        return fail(MLQMC_ENOMEM, "table allocation: %s", hipGetErrorString(e));
+      }
+      t.bytes = (int64_t)total;
+      bytes_alloc += t.bytes;
+      if (islands) {
+        t.s = s;
+        e = launch_phi_elements_islands(n, rows, d_c, d_k1, d_k2, d_region, a_in, a_out, t.el,
+                                        stream);
+        if (e == hipSuccess) e = launch_phi_edges_padded(n, rows, t.el, t.pad, stream);
+        if (e == hipSuccess)
+          e = launch_phi_elements_islands(n, rows, d_cb, d_k1, d_k2, d_region, b_in, b_out, t.rel,
+                                          stream);
+        if (e == hipSuccess) e = launch_phi_reaction_padded(n, rows, t.rel, t.rpad, stream);
+      } else {
+        t.s = rows;
+        e = launch_phi_elements(n, rows, d_c, d_k1, d_k2, t.el, stream);
+        if (e == hipSuccess) e = launch_phi_edges(n, rows, t.el, t.edge, stream);
+        if (e == hipSuccess) e = launch_phi_edges_padded(n, rows, t.el, t.pad, stream);
+      }
       if (e != hipSuccess) return hip_fail(e, "coefficient tables");
     }
     *out = &t;
@@ -282,8 +317,14 @@ mlqmc_status check_opts(mlqmc_ctx* ctx, const mlqmc_opts* o) {
   if (o->max_rq_iter < 1 || o->max_lin_iter < 1)
     return ctx->fail(MLQMC_EINVAL, "iteration caps must be >= 1");
   if (o->device_mem_cap < 0) return ctx->fail(MLQMC_EINVAL, "device_mem_cap must be >= 0");
+  if (ctx->islands && o->prec != MLQMC_FP64)
+    return ctx->fail(MLQMC_EINVAL, "the islands family (Problem 2) runs in FP64 only");
   return MLQMC_OK;
 }
+
+// Problem 2 meshes: multiples of 1/8 (the islands' edges are mesh lines) up
+// to 1/32 (every array of a solve in LDS); 0 = not used
+bool islands_mesh_ok(int n) { return n == 0 || (n >= 8 && n <= 32); }
 
 mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
   if (!l) return ctx->fail(MLQMC_EINVAL, "level is NULL");
@@ -314,6 +355,11 @@ mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
       return ctx->fail(MLQMC_EINVAL, "need n_coarse <= n_prev <= 1024 (got %d)", l->n_prev);
     }
   }
+  if (ctx->islands &&
+      !(islands_mesh_ok(l->n_fine) && islands_mesh_ok(l->n_coarse) && islands_mesh_ok(l->n_prev)))
+    return ctx->fail(MLQMC_EINVAL,
+                     "the islands family (Problem 2) needs meshes 1/8 .. 1/32 (got %d, %d, %d)",
+                     l->n_fine, l->n_coarse, l->n_prev);
   return MLQMC_OK;
 }
 
@@ -670,6 +716,7 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
     a.s = s;
     a.phi = tb->pad;
     a.a0 = ctx->a0;
+    a.rphi = tb->rpad;
     a.uH = uH;
     a.lamH = lamH;
     a.nH = nH;
@@ -747,6 +794,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
     CS(ctx->table(L->n_fine, L->s_fine, &tb));
     a.S = L->s_fine;
     a.phi = tb->pad;
+    a.rphi = tb->rpad;
     a.lam = lam;
     a.u_out = nullptr;
     a.g_out = g;
@@ -768,6 +816,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
       RqiArgs b = a;
       b.S = L->s_prev;
       b.phi = tb->pad;
+      b.rphi = tb->rpad;
       b.lam = lam_prev;
       b.rq_iters = i2;
       b.lin_iters = nullptr;
@@ -794,11 +843,14 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   if (!lamH) CS(ctx->getT("lamH", n, &lamH));
   a.S = L->s_coarse;
   a.phi = tb->pad;
+  a.rphi = tb->rpad;
   a.lam = lamH;
   a.u_out = uH;
   const bool degenerate = L->n_prev == L->n_coarse && L->s_prev == L->s_coarse;
   // on the degenerate previous mesh the update's eigenvector is u_H itself
   a.g_out = (L->n_prev && lam_prev && degenerate) ? g_prev : nullptr;
+  // the fine updates' G inherit the error of u_H: refine it too
+  a.refine = (g || (L->n_prev && g_prev)) ? 1 : 0;
   if (const int64_t per = rqi_scratch_doubles(L->n_coarse)) {
     a.scratch_doubles = per * ((n + chain - 1) / chain);
     CS(ctx->getT("rqi_scratch", a.scratch_doubles, &a.scratch));
@@ -922,6 +974,94 @@ mlqmc_status mlqmc_create(mlqmc_ctx** out, const mlqmc_coeff* cf, int device, vo
   return MLQMC_OK;
 }
 
+mlqmc_status mlqmc_create_islands(mlqmc_ctx** out, const mlqmc_islands* cf, int device,
+                                  void* stream) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return MLQMC_EINVAL;
+  }
+  *out = nullptr;
+  if (!cf || cf->s_max < 0 ||
+      (cf->s_max > 0 && (!cf->ca || !cf->cb || !cf->k1 || !cf->k2 || !cf->region))) {
+    g_create_error = "invalid islands description";
+    return MLQMC_EINVAL;
+  }
+  for (double v : {cf->a0_in, cf->a0_out, cf->b0_in, cf->b0_out})
+    if (!std::isfinite(v)) {
+      g_create_error = "a background value is not finite";
+      return MLQMC_EINVAL;
+    }
+  // bounds over |y_j| <= 1/2 on each region (Assumption A1 for a; b >= 0)
+  double ha[2] = {0.0, 0.0}, hb[2] = {0.0, 0.0};
+  for (int j = 0; j < cf->s_max; ++j) {
+    const int r = cf->region[j];
+    if (!std::isfinite(cf->ca[j]) || !std::isfinite(cf->cb[j]) || cf->k1[j] < 1 ||
+        cf->k2[j] < 1 || (r != 1 && r != 2)) {
+      g_create_error = "islands term " + std::to_string(j) + " is invalid";
+      return MLQMC_EINVAL;
+    }
+    ha[r - 1] += 0.5 * std::fabs(cf->ca[j]);
+    hb[r - 1] += 0.5 * std::fabs(cf->cb[j]);
+  }
+  if (!(cf->a0_in - ha[0] > 0.0) || !(cf->a0_out - ha[1] > 0.0)) {
+    g_create_error = "the diffusion coefficient is not uniformly positive on a region";
+    return MLQMC_EINVAL;
+  }
+  if (!(cf->b0_in - hb[0] >= 0.0) || !(cf->b0_out - hb[1] >= 0.0)) {
+    g_create_error = "the reaction coefficient can be negative on a region";
+    return MLQMC_EINVAL;
+  }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || device < 0 || device >= ndev) {
+    g_create_error = std::string("no HIP device ") + std::to_string(device) +
+                     (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
+    return MLQMC_EDEVICE;
+  }
+  e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+    return MLQMC_EDEVICE;
+  }
+  mlqmc_ctx* ctx = new mlqmc_ctx();
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  ctx->s_max = cf->s_max;
+  ctx->islands = true;
+  ctx->a_in = cf->a0_in;
+  ctx->a_out = cf->a0_out;
+  ctx->b_in = cf->b0_in;
+  ctx->b_out = cf->b0_out;
+  const int sm = std::max(cf->s_max, 1);
+  std::vector<double> ca(sm, 0.0), cb(sm, 0.0);
+  std::vector<int> k1(sm, 1), k2(sm, 1), rg(sm, 1);
+  for (int j = 0; j < cf->s_max; ++j) {
+    ca[j] = cf->ca[j];
+    cb[j] = cf->cb[j];
+    k1[j] = cf->k1[j];
+    k2[j] = cf->k2[j];
+    rg[j] = cf->region[j];
+  }
+  const size_t bd = sm * sizeof(double), bi = sm * sizeof(int);
+  e = hipMalloc(&ctx->d_c, bd);
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_cb, bd);
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_k1, bi);
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_k2, bi);
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_region, bi);
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_c, ca.data(), bd, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_cb, cb.data(), bd, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_k1, k1.data(), bi, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_k2, k2.data(), bi, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_region, rg.data(), bi, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    g_create_error = std::string("device setup: ") + hipGetErrorString(e);
+    mlqmc_destroy(ctx);
+    return MLQMC_EDEVICE;
+  }
+  *out = ctx;
+  return MLQMC_OK;
+}
+
 void mlqmc_destroy(mlqmc_ctx* ctx) {
   if (!ctx) return;
   // teardown: errors here have nowhere to go, and every release is attempted
@@ -929,11 +1069,7 @@ void mlqmc_destroy(mlqmc_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
-  for (auto& kv : ctx->tables) {
-    if (kv.second.el) (void)hipFree(kv.second.el);
-    if (kv.second.edge) (void)hipFree(kv.second.edge);
-    if (kv.second.pad) (void)hipFree(kv.second.pad);
-  }
+  for (auto& kv : ctx->tables) kv.second.release();
   for (auto& ev : ctx->ev_pool) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
@@ -944,6 +1080,8 @@ void mlqmc_destroy(mlqmc_ctx* ctx) {
   if (ctx->d_c) (void)hipFree(ctx->d_c);
   if (ctx->d_k1) (void)hipFree(ctx->d_k1);
   if (ctx->d_k2) (void)hipFree(ctx->d_k2);
+  if (ctx->d_cb) (void)hipFree(ctx->d_cb);
+  if (ctx->d_region) (void)hipFree(ctx->d_region);
   delete ctx;
 }
 
@@ -999,6 +1137,7 @@ mlqmc_status mlqmc_coefficient(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B, 
   if (!ctx) return MLQMC_EINVAL;
   if (!is_pow2(n) || n < 2 || n > 4096) return ctx->fail(MLQMC_EINVAL, "n must be a power of two in [2, 4096]");
   if (s < 0 || s > ctx->s_max) return ctx->fail(MLQMC_EINVAL, "s outside [0, s_max]");
+  if (ctx->islands) return ctx->fail(MLQMC_EINVAL, "mlqmc_coefficient covers Problem 1 only");
   if (B < 0 || (B > 0 && (!aK || (s > 0 && !Y)))) return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
   if (!on_dev && B * s > 0 && !finite_host(Y, (size_t)(B * s)))
     return ctx->fail(MLQMC_EINVAL, "Y has non-finite entries");
@@ -1021,6 +1160,7 @@ mlqmc_status mlqmc_apply_operator(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t 
   if (!ctx) return MLQMC_EINVAL;
   if (!is_pow2(n) || n < 2 || n > 4096) return ctx->fail(MLQMC_EINVAL, "n must be a power of two in [2, 4096]");
   if (s < 0 || s > ctx->s_max) return ctx->fail(MLQMC_EINVAL, "s outside [0, s_max]");
+  if (ctx->islands) return ctx->fail(MLQMC_EINVAL, "mlqmc_apply_operator covers Problem 1 only");
   if (B < 0 || (B > 0 && (!sigma || !x || !out || (s > 0 && !Y))))
     return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
   CK(hipSetDevice(ctx->device), "set device");
@@ -1273,6 +1413,7 @@ mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level
     RqiArgs a = rqi_base(ctx, o, B0, Y, std::max(s0, 1), chain, 1, rqi, lini, fl);
     a.S = s0;
     a.phi = tb->pad;
+    a.rphi = tb->rpad;
     a.lam = lam0;
     a.u_out = u0;
     a.g_out = g0;

@@ -2,6 +2,8 @@
 // coarse (or direct-level) mesh, the two-grid update on small fine meshes, and
 // the bottom of the batched V-cycle.  One workgroup owns one sample (or one
 // warm-start chain of samples) and keeps every vector in LDS.
+#include <type_traits>
+
 #include "../../include/mlqmc.h"
 #include "kernels.h"
 #include "lds_mg.h"
@@ -48,9 +50,47 @@ __device__ __forceinline__ double sine_overlap(const T* v, double* red) {
   return fabs(s[0] * hm) / sqrt(s[1] * hm);
 }
 
+// Share of the l1 norm of v carried by its dominant sign: 1 for a vector of
+// one sign, as the discrete ground state of Problem 2 is; an excited state
+// changes sign and scores well below.
+template <int NT, int n, typename T>
+__device__ __forceinline__ double sign_share(const T* v, double* red) {
+  double s[2] = {0.0, 0.0};
+  LDS_FOR_NODES(NT, n, k) {
+    const double x = (double)v[k];
+    s[0] += x;
+    s[1] += fabs(x);
+  }
+  block_sums<NT, 2>(s, red);
+  return s[1] > 0.0 ? fabs(s[0]) / s[1] : 0.0;
+}
+
+// Stages the point of sample i into s_y and forms the level's weights.
+// Problem 1: w = a0 + sum_{j<S} y_j Phi_j.  Problem 2 (kR): the tables carry
+// the background values as row 0, so s_y = (1, y_1, ..., y_S) weights S + 1
+// rows of both the diffusion table [WX | WY] and the reaction table
+// [RX | RY | RD].
+template <int N, int NT, bool kR, typename T>
+__device__ __forceinline__ void stage_weights(const double* Y, int64_t ldY, int64_t i, int S,
+                                              const double* phi, const double* rphi, double a0,
+                                              const lds::PcgArrays<T>& a, double* s_y) {
+  constexpr int P = lds::Mesh<N>::P;
+  if constexpr (kR) {
+    for (int j = threadIdx.x; j <= S; j += NT) s_y[j] = j == 0 ? 1.0 : Y[i * ldY + j - 1];
+    __syncthreads();
+    lds::weights_from_table<NT, N>(phi, s_y, S + 1, 0.0, a.wx);
+    lds::weights_from_table<NT, N, T, 3>(rphi, s_y, S + 1, 0.0, a.wx + 2 * P);
+  } else {
+    for (int j = threadIdx.x; j < S; j += NT) s_y[j] = Y[i * ldY + j];
+    __syncthreads();
+    lds::weights_from_table<NT, N>(phi, s_y, S, a0, a.wx);
+  }
+  lds::coarsen_all<NT, N, T, kR>(a.wx, a.wy, a.mg);
+}
+
 // The chain of samples [blockIdx.x * chain_len, ...) on mesh N: arrays in `a`
 // (zero padding), the staged point in s_y.
-template <int N, int NT, typename T, class WF>
+template <int N, int NT, bool kR = false, typename T, class WF>
 __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* s_y,
                           const WF& wf) {
   using Mh = lds::Mesh<N>;
@@ -60,14 +100,11 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* 
   const int64_t i1 = (i0 + A.chain_len < A.n) ? i0 + A.chain_len : A.n;
   bool have_prev = false;
   for (int64_t i = i0; i < i1; ++i) {
-    for (int j = threadIdx.x; j < A.S; j += NT) s_y[j] = A.Y[i * A.ldY + j];
-    __syncthreads();
-    lds::weights_from_table<NT, N>(A.phi, s_y, A.S, A.a0, a.wx);
-    lds::coarsen_all<NT, N>(a.wx, a.wy, a.mg);
+    stage_weights<N, NT, kR>(A.Y, A.ldY, i, A.S, A.phi, A.rphi, A.a0, a, s_y);
     if (!(A.warm && have_prev)) init_sine<NT, N>(s_v);
 
     double vMv, vAv;
-    lds::rayleigh_parts<NT, N>(a, s_v, wf, vMv, vAv);
+    lds::rayleigh_parts<NT, N, T, WF, kR>(a, s_v, wf, vMv, vAv);
     lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
     double sigma = vAv / vMv;  // sigma_0 = A(t_k; v0, v0) for the M-normalised start
 
@@ -77,10 +114,10 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* 
     while (rq < A.max_rq) {
       ++rq;
       bool c, b;
-      lin += lds::jd_pcg<NT, N>(a, sigma, sigma, A.lin_rtol, A.max_lin, &c, &b);
+      lin += lds::jd_pcg<NT, N, false, kR>(a, sigma, sigma, A.lin_rtol, A.max_lin, &c, &b);
       LDS_FOR_NODES(NT, N, k) s_v[k] += a.t[k];
       __syncthreads();
-      lds::rayleigh_parts<NT, N>(a, s_v, wf, vMv, vAv);
+      lds::rayleigh_parts<NT, N, T, WF, kR>(a, s_v, wf, vMv, vAv);
       lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
       const double sig_new = vAv / vMv;
       const bool done = fabs(sig_new - sigma) <= A.eig_rtol * fabs(sig_new);
@@ -93,24 +130,33 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* 
     }
     if (!conv) fl |= MLQMC_FLAG_RQ_NOCONV;
     if (!isfinite(sigma)) fl |= MLQMC_FLAG_NONFINITE;
-    if (A.g_out) {
-      // G is linear in the vector: one correction solve at the converged
-      // sigma to the linear tolerance (a Newton step) makes the vector as
-      // accurate as the two-grid ones; lambda stays the converged sigma
-      if (conv && A.g_lin_rtol > 0.0) {
-        bool c, b;
-        lin += lds::jd_pcg<NT, N>(a, sigma, sigma, A.g_lin_rtol, A.max_lin, &c, &b);
-        if (!c) fl |= MLQMC_FLAG_LIN_NOCONV;
-        LDS_FOR_NODES(NT, N, k) s_v[k] += a.t[k];
-        __syncthreads();
-      }
+    // The inexact inner solves leave the vector's error near the square root
+    // of sigma's.  G is linear in the vector (here, or through the two-grid
+    // update that starts from it): one correction solve at the converged
+    // sigma to the linear tolerance (a Newton step) makes it as accurate as
+    // the two-grid vectors; lambda stays the converged sigma
+    const bool refine = conv && A.g_lin_rtol > 0.0 && (A.g_out || A.refine);
+    if (refine) {
+      bool c, b;
+      lin += lds::jd_pcg<NT, N, false, kR>(a, sigma, sigma, A.g_lin_rtol, A.max_lin, &c, &b);
+      if (!c) fl |= MLQMC_FLAG_LIN_NOCONV;
+      LDS_FOR_NODES(NT, N, k) s_v[k] += a.t[k];
+      __syncthreads();
+    }
+    if (A.g_out || refine) {
       double sm, mn;
       lds::sum_and_mnorm<NT, N>(a, s_v, sm, mn);
-      if (threadIdx.x == 0) A.g_out[i] = fabs(sm) / ((double)N * N * sqrt(mn));
+      if (A.g_out && threadIdx.x == 0) A.g_out[i] = fabs(sm) / ((double)N * N * sqrt(mn));
       lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(mn));
     }
-    const double ov = sine_overlap<NT, N>(s_v, a.red);
-    if (!(ov >= 0.5)) fl |= MLQMC_FLAG_WRONG_PAIR;
+    // ground-state check: overlap with the first sine mode (Problem 1), or
+    // one sign (Problem 2, whose islands can pull the ground state away from
+    // the sine mode)
+    if constexpr (kR) {
+      if (!(sign_share<NT, N>(s_v, a.red) >= 0.9)) fl |= MLQMC_FLAG_WRONG_PAIR;
+    } else {
+      if (!(sine_overlap<NT, N>(s_v, a.red) >= 0.5)) fl |= MLQMC_FLAG_WRONG_PAIR;
+    }
     if (threadIdx.x == 0) {
       A.lam[i] = sigma;
       if (A.rq_iters) A.rq_iters[i] = rq;
@@ -132,13 +178,18 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* 
 // zeroed once; the solvers write interior positions only.  T = float keeps
 // vectors, weights and V-cycle in FP32 (mixed precision); the Rayleigh
 // quotients then use FP64 weights recomputed from the edge table.
-template <int N, int NT, typename T>
-__global__ __launch_bounds__(NT, (N >= 32 && sizeof(T) == 8) ? 2 : 4) void k_rqi(RqiArgs A) {
+// With kR (Problem 2, FP64) the weight block also holds the reaction arrays.
+template <int N, int NT, bool kR>
+constexpr int lds_blocks_per_cu(int tsize) {
+  return kR ? 1 : ((N >= 32 && tsize == 8) ? 2 : 4);
+}
+template <int N, int NT, typename T, bool kR = false>
+__global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void k_rqi(RqiArgs A) {
   using Mh = lds::Mesh<N>;
   constexpr int P = Mh::P;
-  __shared__ T s_w[Mh::EW];
+  __shared__ T s_w[lds::wblock<kR>() * P];
   __shared__ T s_vec[5 * P];
-  __shared__ T s_mg[lds::mg_scratch<N>() + 1];
+  __shared__ T s_mg[lds::mg_scratch<N, kR>() + 1];
   __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
   lds::PcgArrays<T> a;
@@ -156,7 +207,7 @@ __global__ __launch_bounds__(NT, (N >= 32 && sizeof(T) == 8) ? 2 : 4) void k_rqi
   lds::zero<NT>(s_vec, 5 * P);
   __syncthreads();
   if constexpr (sizeof(T) == 8) {
-    rqi_chain<N, NT>(A, a, s_y, lds::WeightsFromArrays<N>{s_w, s_w + P});
+    rqi_chain<N, NT, kR>(A, a, s_y, lds::WeightsFromArrays<N>{s_w, s_w + P});
   } else {
     rqi_chain<N, NT>(A, a, s_y, lds::WeightsFromTable<N>{A.phi, s_y, A.S, A.a0});
   }
@@ -196,14 +247,14 @@ __global__ __launch_bounds__(NT) void k_rqi_global(RqiArgs A) {
   rqi_chain<N, NT>(A, a, s_y, lds::WeightsFromArrays<N>{g, g + P});
 }
 
-template <int N, int NT, typename T>
-__global__ __launch_bounds__(NT, (N >= 32 && sizeof(T) == 8) ? 2 : 4) void k_tg_small(
+template <int N, int NT, typename T, bool kR = false>
+__global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void k_tg_small(
     TgSmallArgs A) {
   using Mh = lds::Mesh<N>;
   constexpr int P = Mh::P;
-  __shared__ T s_w[Mh::EW];
+  __shared__ T s_w[lds::wblock<kR>() * P];
   __shared__ T s_vec[5 * P];
-  __shared__ T s_mg[lds::mg_scratch<N>() + 1];
+  __shared__ T s_mg[lds::mg_scratch<N, kR>() + 1];
   __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
   lds::PcgArrays<T> a;
@@ -221,10 +272,7 @@ __global__ __launch_bounds__(NT, (N >= 32 && sizeof(T) == 8) ? 2 : 4) void k_tg_
   T* const s_v = a.v;
   const int64_t i = blockIdx.x;
   lds::zero<NT>(s_vec, 5 * P);
-  for (int j = threadIdx.x; j < A.s; j += NT) s_y[j] = A.Y[i * A.ldY + j];
-  __syncthreads();
-  lds::weights_from_table<NT, N>(A.phi, s_y, A.s, A.a0, s_w);
-  lds::coarsen_all<NT, N>(a.wx, a.wy, s_mg);
+  stage_weights<N, NT, kR>(A.Y, A.ldY, i, A.s, A.phi, A.rphi, A.a0, a, s_y);
   const int mH = A.nH - 1, ratio = N / A.nH;
   const double* uH = A.uH + i * (int64_t)(mH * mH);
   LDS_FOR_NODES(NT, N, k) {
@@ -233,17 +281,18 @@ __global__ __launch_bounds__(NT, (N >= 32 && sizeof(T) == 8) ? 2 : 4) void k_tg_
   }
   __syncthreads();
   auto run = [&](const auto& wf) {
+    using WF = std::decay_t<decltype(wf)>;
     double vMv, vAv;
-    lds::rayleigh_parts<NT, N>(a, s_v, wf, vMv, vAv);
+    lds::rayleigh_parts<NT, N, T, WF, kR>(a, s_v, wf, vMv, vAv);
     lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
     const double rho = vAv / vMv;
     const double mu = A.lamH[i];
     bool c, b;
     const int its =
-        lds::jd_pcg<NT, N, true>(a, mu, rho, A.lin_rtol, A.max_lin, &c, &b, A.lam_rtol);
+        lds::jd_pcg<NT, N, true, kR>(a, mu, rho, A.lin_rtol, A.max_lin, &c, &b, A.lam_rtol);
     LDS_FOR_NODES(NT, N, k) s_v[k] += a.t[k];
     __syncthreads();
-    lds::rayleigh_parts<NT, N>(a, s_v, wf, vMv, vAv);
+    lds::rayleigh_parts<NT, N, T, WF, kR>(a, s_v, wf, vMv, vAv);
     const double lam = vAv / vMv;
     if (A.g) {
       double sm, mn;
@@ -302,11 +351,17 @@ hipError_t rqi_n(const RqiArgs& a, hipStream_t st) {
   if (chains <= 0) return hipSuccess;
   if constexpr (N <= 32) {
     constexpr int NT = threads_for<N>();
-    if (a.mixed)
+    if (a.rphi) {  // Problem 2: FP64 only
+      if (a.mixed) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_rqi<N, NT, double, true>), dim3((unsigned)chains), dim3(NT), 0, st,
+                         a);
+    } else if (a.mixed) {
       hipLaunchKernelGGL((k_rqi<N, NT, float>), dim3((unsigned)chains), dim3(NT), 0, st, a);
-    else
+    } else {
       hipLaunchKernelGGL((k_rqi<N, NT, double>), dim3((unsigned)chains), dim3(NT), 0, st, a);
+    }
   } else {
+    if (a.rphi) return hipErrorInvalidValue;  // Problem 2 runs on meshes up to 1/32
     // the caller provides chains x rqi_scratch_doubles(N) doubles of scratch
     if (!a.scratch || a.scratch_doubles < chains * rqi_global_doubles<N>())
       return hipErrorInvalidValue;
@@ -319,10 +374,15 @@ template <int N>
 hipError_t tg_small_n(const TgSmallArgs& a, hipStream_t st) {
   constexpr int NT = threads_for<N>();
   if (a.n <= 0) return hipSuccess;
-  if (a.mixed)
+  if (a.rphi) {  // Problem 2: FP64 only
+    if (a.mixed) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_tg_small<N, NT, double, true>), dim3((unsigned)a.n), dim3(NT), 0, st,
+                       a);
+  } else if (a.mixed) {
     hipLaunchKernelGGL((k_tg_small<N, NT, float>), dim3((unsigned)a.n), dim3(NT), 0, st, a);
-  else
+  } else {
     hipLaunchKernelGGL((k_tg_small<N, NT, double>), dim3((unsigned)a.n), dim3(NT), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -338,7 +398,7 @@ hipError_t bottom_n(int64_t B, const T* w, const T* rhs, T* X, const uint8_t* ac
 }  // namespace
 
 hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st) {
-  if (a.S > kMaxStagedS) return hipErrorInvalidValue;
+  if (a.S + (a.rphi ? 1 : 0) > kMaxStagedS) return hipErrorInvalidValue;
   switch (N) {
     case 4: return rqi_n<4>(a, st);
     case 8: return rqi_n<8>(a, st);
@@ -380,7 +440,7 @@ int rqi_chains_in_flight(int N, int mixed) {
 }
 
 hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st) {
-  if (a.s > kMaxStagedS) return hipErrorInvalidValue;
+  if (a.s + (a.rphi ? 1 : 0) > kMaxStagedS) return hipErrorInvalidValue;
   switch (N) {
     case 4: return tg_small_n<4>(a, st);
     case 8: return tg_small_n<8>(a, st);

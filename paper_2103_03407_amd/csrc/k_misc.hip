@@ -58,6 +58,39 @@ __global__ __launch_bounds__(256) void k_phi_elements(int n, int s, const double
   phi[(int64_t)j * E + e] = c[j] * sinpi((double)k1[j] * xc) * sinpi((double)k2[j] * yc);
 }
 
+// Problem 2 element table, rows 0 .. s: row 0 the background value (base_in on
+// the islands, base_out elsewhere), row j >= 1 term j: c_{j-1} sin(pi k1 x)
+// sin(pi k2 y) on its region (region 1: the islands [1/8, 3/8] or [5/8, 7/8] in
+// each coordinate; 2: the rest), 0 elsewhere.  Meshes are multiples of 1/8, so
+// no centroid lies on an island boundary.
+__device__ __forceinline__ bool in_islands(double x, double y) {
+  auto band = [](double t) { return (t >= 0.125 && t <= 0.375) || (t >= 0.625 && t <= 0.875); };
+  return band(x) && band(y);
+}
+__global__ __launch_bounds__(256) void k_phi_elements_islands(
+    int n, int s, const double* __restrict__ c, const int* __restrict__ k1,
+    const int* __restrict__ k2, const int* __restrict__ region, double base_in, double base_out,
+    double* __restrict__ phi) {
+  const int E = 2 * n * n;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int row = blockIdx.y;
+  if (e >= E || row > s) return;
+  const int sq = e >> 1, tri = e & 1;
+  const int i = sq % n, jj = sq / n;
+  const double xc = (double)(3 * i + (tri ? 1 : 2)) / (3.0 * n);
+  const double yc = (double)(3 * jj + (tri ? 2 : 1)) / (3.0 * n);
+  const bool inside = in_islands(xc, yc);
+  double v;
+  if (row == 0) {
+    v = inside ? base_in : base_out;
+  } else {
+    const int j = row - 1;
+    const bool own = (region[j] == 1) == inside;
+    v = own ? c[j] * sinpi((double)k1[j] * xc) * sinpi((double)k2[j] * yc) : 0.0;
+  }
+  phi[(int64_t)row * E + e] = v;
+}
+
 // edge table: horizontal edge (i,j)-(i+1,j) touches lower(i,j) and upper(i,j-1);
 // vertical edge (i,j)-(i,j+1) touches upper(i,j) and lower(i-1,j)
 __global__ __launch_bounds__(256) void k_phi_edges(int n, int s, const double* __restrict__ pe,
@@ -86,7 +119,8 @@ __global__ __launch_bounds__(256) void k_phi_edges(int n, int s, const double* _
 // P = (n+2) n.  Other positions are 0.
 __global__ __launch_bounds__(256) void k_phi_edges_padded(int n, int s,
                                                           const double* __restrict__ pe,
-                                                          double* __restrict__ pw) {
+                                                          double* __restrict__ pw,
+                                                          int64_t row_stride) {
   const int E = 2 * n * n, P = (n + 2) * n;
   const int e = blockIdx.x * 256 + threadIdx.x;
   const int jt = blockIdx.y;
@@ -106,7 +140,36 @@ __global__ __launch_bounds__(256) void k_phi_edges_padded(int n, int s,
     if (j >= 1 && j <= n && i >= 1)
       v = 0.5 * (el[2 * ((j - 1) * n + i) + 1] + el[2 * ((j - 1) * n + i - 1)]);
   }
-  pw[(int64_t)jt * 2 * P + e] = v;
+  pw[(int64_t)jt * row_stride + e] = v;
+}
+
+// padded diagonal-edge table (the third segment of the reaction table): the
+// edge (i,j)-(i+1,j+1) inside square (i, j) touches its two elements; it is
+// stored at (j+1)*n + i + 1 (the index of its north-east end, so i = n-1 lands
+// in column 0 of row j+2), for 0 <= i, j <= n-1.  Other positions are 0.
+__global__ __launch_bounds__(256) void k_phi_diag_padded(int n, int s,
+                                                         const double* __restrict__ pe,
+                                                         double* __restrict__ pd,
+                                                         int64_t row_stride) {
+  const int E = 2 * n * n, P = (n + 2) * n;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int jt = blockIdx.y;
+  if (e >= P || jt >= s) return;
+  const double* el = pe + (int64_t)jt * E;
+  // invert e = (j+1) n + i + 1: column 0 of row r is square (n-1, r-2)
+  int r = e / n, c = e % n;
+  int i, j;
+  if (c == 0) {
+    i = n - 1;
+    j = r - 2;
+  } else {
+    i = c - 1;
+    j = r - 1;
+  }
+  double v = 0.0;
+  if (i >= 0 && i <= n - 1 && j >= 0 && j <= n - 1)
+    v = 0.5 * (el[2 * (j * n + i)] + el[2 * (j * n + i) + 1]);
+  pd[(int64_t)jt * row_stride + e] = v;
 }
 
 // out[b][e] = a0 + sum_j Y[b][j] phi[j][e] (eq. coeff at the quadrature points
@@ -342,7 +405,29 @@ hipError_t launch_phi_edges_padded(int n, int s, const double* phi_el, double* p
   if (s <= 0) return hipSuccess;
   const int E = 2 * (n + 2) * n;
   hipLaunchKernelGGL(k_phi_edges_padded, dim3((E + 255) / 256, s), dim3(256), 0, st, n, s,
-                     phi_el, phi_pad);
+                     phi_el, phi_pad, (int64_t)E);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_elements_islands(int n, int rows, const double* c, const int* k1,
+                                       const int* k2, const int* region, double base_in,
+                                       double base_out, double* phi, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const int E = 2 * n * n;
+  hipLaunchKernelGGL(k_phi_elements_islands, dim3((E + 255) / 256, rows), dim3(256), 0, st, n,
+                     rows - 1, c, k1, k2, region, base_in, base_out, phi);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_reaction_padded(int n, int rows, const double* phi_el, double* phi_r,
+                                      hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const int PG = (n + 2) * n;
+  const int64_t stride = 3 * (int64_t)PG;
+  hipLaunchKernelGGL(k_phi_edges_padded, dim3((2 * PG + 255) / 256, rows), dim3(256), 0, st, n,
+                     rows, phi_el, phi_r, stride);
+  hipLaunchKernelGGL(k_phi_diag_padded, dim3((PG + 255) / 256, rows), dim3(256), 0, st, n, rows,
+                     phi_el, phi_r + 2 * PG, stride);
   return hipGetLastError();
 }
 

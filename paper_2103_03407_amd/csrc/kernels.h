@@ -15,6 +15,9 @@ struct RqiArgs {
   int S;
   const double* phi;    // edge table [>=S][EW] of the mesh
   double a0;
+  const double* rphi;   // Problem 2: reaction table [>=S+1][3 (n+2) n]; then phi and
+                        // rphi carry the background values as row 0 and a0 is unused
+                        // (FP64, meshes up to 1/32).  nullptr: Problem 1
   int64_t n;            // samples
   int chain_len;        // samples per warm-start chain (one workgroup per chain)
   int warm;             // 1: start from the previous sample's eigenvector
@@ -31,6 +34,7 @@ struct RqiArgs {
                         // fixed positive, or nullptr; then each converged vector is
                         // first refined by one correction solve to g_lin_rtol (0: not)
   double g_lin_rtol;
+  int refine;           // 1: refine converged vectors (as with g_out) without writing G
   double* scratch;      // meshes above 1/32: per-chain global scratch
   int64_t scratch_doubles;
   int mixed;            // 1: FP32 vectors, weights and V-cycle (meshes up to 1/32)
@@ -47,6 +51,7 @@ struct TgSmallArgs {
   int s;
   const double* phi;    // edge table [>=s][EW] of the fine mesh
   double a0;
+  const double* rphi;   // Problem 2 reaction table (as in RqiArgs), or nullptr
   const double* uH;     // [n x DH] coarse eigenvectors
   const double* lamH;   // [n]
   int nH;               // coarse mesh
@@ -170,6 +175,17 @@ hipError_t launch_phi_edges(int n, int s, const double* phi_el, double* phi_edge
 // the same edge table in the padded [WX | WY] layout of the batched kernels
 hipError_t launch_phi_edges_padded(int n, int s, const double* phi_el, double* phi_pad,
                                    hipStream_t st);
+// Problem 2 element table, `rows` = s + 1 rows: row 0 the background value by
+// region (base_in on the islands), row j the region-masked term j - 1
+hipError_t launch_phi_elements_islands(int n, int rows, const double* c, const int* k1,
+                                       const int* k2, const int* region, double base_in,
+                                       double base_out, double* phi, hipStream_t st);
+// reaction edge table, rows of [RX | RY | RD], (n + 2) n entries each: the mean
+// of the element table over the two elements of each horizontal, vertical and
+// diagonal edge, in the padded layout (RX, RY as WX, WY; RD[k] the diagonal
+// edge arriving at node k from the south-west)
+hipError_t launch_phi_reaction_padded(int n, int rows, const double* phi_el, double* phi_r,
+                                      hipStream_t st);
 // out[b][e] = a0 + sum_{j<s} Y[b][j] phi[j][e], e < E
 hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t ldY,
                          const double* phi, double a0, double* out, float* out32,

@@ -23,7 +23,14 @@
 // WX[k] is the edge arriving at node k from the west, WY[k] from the south
 // (so the east and north edges of node k are WX[k + 1] and WY[k + n]), two
 // arrays of P(n) entries.  Loops run over the positions n .. n n - 1 and skip
-// column 0.  T is the storage and arithmetic type of the vectors, weights and
+// column 0.  With the reaction term of Problem 2 (template flag kR) the
+// weight block of a level is [WX | WY | RX | RY | RD]: RX, RY hold the mean
+// reaction coefficient of the same edges as WX, WY and RD[k] that of the
+// diagonal edge arriving at node k from the south-west (RD[k + n + 1] is the
+// edge to the north-east); the operator adds
+//   (R x)_k = h^2/12 sum over the six edges e of k of r_e (x_k + x_other end)
+// (the element mass matrices weighted by b).
+// T is the storage and arithmetic type of the vectors, weights and
 // V-cycle (double, or float in mixed precision); every dot product and every
 // Rayleigh quotient is accumulated in double, the quotients from FP64 weights.
 #pragma once
@@ -48,18 +55,46 @@ struct Mesh {
   for (int k = (n) + (int)threadIdx.x; k < (n) * (n); k += (NT)) \
     if ((k & ((n) - 1)) != 0)
 
-// (A x)_k with the diagonal in d
-template <int n, typename T>
+// weight arrays per level: [WX | WY], or [WX | WY | RX | RY | RD] with reaction
+template <bool kR>
+constexpr int wblock() {
+  return kR ? 5 : 2;
+}
+
+// (A x)_k (plus (R x)_k with kR) with the diagonal in d
+template <int n, typename T, bool kR = false>
 MLQMC_DEV T pA(const T* x, const T* wx, const T* wy, int k, T& d) {
   const T ww = wx[k], we = wx[k + 1], ws = wy[k], wn = wy[k + n];
   d = ww + we + ws + wn;
   const T xc = x[k];
-  return ww * (xc - x[k - 1]) + we * (xc - x[k + 1]) + ws * (xc - x[k - n]) +
+  T ax = ww * (xc - x[k - 1]) + we * (xc - x[k + 1]) + ws * (xc - x[k - n]) +
          wn * (xc - x[k + n]);
+  if constexpr (kR) {
+    constexpr int P = (n + 1) * n + 1;
+    const T* rx = wx + 2 * P;
+    const T* ry = wx + 3 * P;
+    const T* rd = wx + 4 * P;
+    const T hm = (T)(1.0 / (12.0 * n * n));
+    const T r1 = rx[k], r2 = rx[k + 1], r3 = ry[k], r4 = ry[k + n], r5 = rd[k],
+            r6 = rd[k + n + 1];
+    ax += hm * (r1 * (xc + x[k - 1]) + r2 * (xc + x[k + 1]) + r3 * (xc + x[k - n]) +
+                r4 * (xc + x[k + n]) + r5 * (xc + x[k - n - 1]) + r6 * (xc + x[k + n + 1]));
+    d += hm * (r1 + r2 + r3 + r4 + r5 + r6);
+  }
+  return ax;
 }
-template <int n, typename T>
+template <int n, typename T, bool kR = false>
 MLQMC_DEV T pdiag(const T* wx, const T* wy, int k) {
-  return wx[k] + wx[k + 1] + wy[k] + wy[k + n];
+  T d = wx[k] + wx[k + 1] + wy[k] + wy[k + n];
+  if constexpr (kR) {
+    constexpr int P = (n + 1) * n + 1;
+    const T* rx = wx + 2 * P;
+    const T* ry = wx + 3 * P;
+    const T* rd = wx + 4 * P;
+    d += (T)(1.0 / (12.0 * n * n)) *
+         (rx[k] + rx[k + 1] + ry[k] + ry[k + n] + rd[k] + rd[k + n + 1]);
+  }
+  return d;
 }
 // (M x)_k without the h^2/12 factor
 template <int n, typename T>
@@ -77,11 +112,11 @@ MLQMC_DEV double pM12d(const T* x, int k) {
 }
 
 // Entries of the V-cycle levels strictly below mesh n: per level nc, the
-// weights (2 P) and B, X (2 P).
-template <int n>
+// weights (2 P, or 5 P with reaction) and B, X (2 P).
+template <int n, bool kR = false>
 constexpr int mg_scratch() {
   int s = 0;
-  for (int c = n / 2; c >= 2; c /= 2) s += 4 * ((c + 1) * c + 1);
+  for (int c = n / 2; c >= 2; c /= 2) s += (wblock<kR>() + 2) * ((c + 1) * c + 1);
   return s;
 }
 
@@ -92,38 +127,55 @@ MLQMC_DEV void zero(T* x, int count) {
 }
 
 // Weights of every level below n, each the mean of the two collinear fine
-// edges it covers; the B and X arrays of every level are zeroed.
-template <int NT, int n, typename T>
+// edges it covers (horizontal, vertical and, with reaction, diagonal); the B
+// and X arrays of every level are zeroed.
+template <int NT, int n, typename T, bool kR = false>
 MLQMC_DEV void coarsen_all(const T* wx, const T* wy, T* nxt) {
   if constexpr (n > 2) {
-    constexpr int nc = n / 2, Pc = Mesh<nc>::P;
+    constexpr int nc = n / 2, Pc = Mesh<nc>::P, P = Mesh<n>::P;
     T* wxc = nxt;
     T* wyc = wxc + Pc;
     for (int e = threadIdx.x; e < Pc; e += NT) {
       const int J = e / nc, I = e % nc;
       const int Ie = (I == 0) ? nc : I, Je = (I == 0) ? J - 1 : J;
-      wxc[e] = (Je >= 1 && Je <= nc - 1)
-                   ? T(0.5) * (wx[2 * Je * n + 2 * Ie - 1] + wx[2 * Je * n + 2 * Ie])
-                   : T(0);
-      wyc[e] = (J >= 1 && J <= nc && I >= 1)
-                   ? T(0.5) * (wy[(2 * J - 1) * n + 2 * I] + wy[2 * J * n + 2 * I])
-                   : T(0);
+      const bool okx = Je >= 1 && Je <= nc - 1, oky = J >= 1 && J <= nc && I >= 1;
+      const int fx0 = 2 * Je * n + 2 * Ie - 1, fy0 = (2 * J - 1) * n + 2 * I;
+      wxc[e] = okx ? T(0.5) * (wx[fx0] + wx[fx0 + 1]) : T(0);
+      wyc[e] = oky ? T(0.5) * (wy[fy0] + wy[fy0 + n]) : T(0);
+      if constexpr (kR) {
+        const T* rx = wx + 2 * P;
+        const T* ry = wx + 3 * P;
+        const T* rd = wx + 4 * P;
+        wxc[2 * Pc + e] = okx ? T(0.5) * (rx[fx0] + rx[fx0 + 1]) : T(0);
+        wxc[3 * Pc + e] = oky ? T(0.5) * (ry[fy0] + ry[fy0 + n]) : T(0);
+        // diagonal edge of coarse square (Ic, Jc), stored at its north-east
+        // end (column 0 of row Jc + 2 when Ic = nc - 1); it covers the
+        // diagonals of fine squares (2Ic, 2Jc) and (2Ic + 1, 2Jc + 1)
+        const int Ic = (I == 0) ? nc - 1 : I - 1, Jc = (I == 0) ? J - 2 : J - 1;
+        T v = T(0);
+        if (Ic >= 0 && Ic <= nc - 1 && Jc >= 0 && Jc <= nc - 1) {
+          const int f1 = (2 * Jc + 1) * n + 2 * Ic + 1, f2 = (2 * Jc + 2) * n + 2 * Ic + 2;
+          v = T(0.5) * (rd[f1] + rd[f2]);
+        }
+        wxc[4 * Pc + e] = v;
+      }
     }
-    zero<NT>(wyc + Pc, 2 * Pc);
+    T* rest = wxc + wblock<kR>() * Pc;  // B and X of this level, then the next level
+    zero<NT>(rest, 2 * Pc);
     __syncthreads();
-    coarsen_all<NT, nc>(wxc, wyc, wyc + 3 * Pc);
+    coarsen_all<NT, nc, T, kR>(wxc, wyc, rest + 2 * Pc);
   }
 }
 
 // X = omega * B / diag  (first sweep from a zero start)
-template <int NT, int n, typename T>
+template <int NT, int n, typename T, bool kR = false>
 MLQMC_DEV void jacobi_first(const T* wx, const T* wy, const T* B, T* X, double om) {
-  LDS_FOR_NODES(NT, n, k) X[k] = T(om) * B[k] / pdiag<n>(wx, wy, k);
+  LDS_FOR_NODES(NT, n, k) X[k] = T(om) * B[k] / pdiag<n, T, kR>(wx, wy, k);
   __syncthreads();
 }
 
 // X <- X + omega (B - A X) / diag, new values staged in registers
-template <int NT, int n, typename T>
+template <int NT, int n, typename T, bool kR = false>
 MLQMC_DEV void jacobi_sweep(const T* wx, const T* wy, const T* B, T* X, double om) {
   constexpr int PT = (n * n - n + NT - 1) / NT;
   T nv[PT];
@@ -132,7 +184,7 @@ MLQMC_DEV void jacobi_sweep(const T* wx, const T* wy, const T* B, T* X, double o
     const int k = n + (int)threadIdx.x + q * NT;
     if (k < n * n && (k & (n - 1)) != 0) {
       T d;
-      const T ax = pA<n>(X, wx, wy, k, d);
+      const T ax = pA<n, T, kR>(X, wx, wy, k, d);
       nv[q] = X[k] + T(om) * (B[k] - ax) / d;
     }
   }
@@ -147,12 +199,12 @@ MLQMC_DEV void jacobi_sweep(const T* wx, const T* wy, const T* B, T* X, double o
 
 // Xout = Xin + omega (B - A Xin) / diag (two distinct arrays; for top levels
 // too large for register staging)
-template <int NT, int n, typename T>
+template <int NT, int n, typename T, bool kR = false>
 MLQMC_DEV void jacobi_to(const T* wx, const T* wy, const T* B, const T* Xin, T* Xout,
                          double om) {
   LDS_FOR_NODES(NT, n, k) {
     T d;
-    const T ax = pA<n>(Xin, wx, wy, k, d);
+    const T ax = pA<n, T, kR>(Xin, wx, wy, k, d);
     Xout[k] = Xin[k] + T(om) * (B[k] - ax) / d;
   }
   __syncthreads();
@@ -161,12 +213,12 @@ MLQMC_DEV void jacobi_to(const T* wx, const T* wy, const T* B, const T* Xin, T* 
 // Bc = P^T (B - A X): the residual at the seven fine nodes each coarse node's
 // hat function covers (weight 1 at the node, 1/2 at E, W, N, S, NE, SW, all
 // interior), formed on the fly, so no residual array is stored.
-template <int NT, int n, typename T>
+template <int NT, int n, typename T, bool kR = false>
 MLQMC_DEV void restrict_residual(const T* wx, const T* wy, const T* B, const T* X, T* Bc) {
   constexpr int nc = n / 2;
   auto res = [&](int k) {
     T d;
-    return B[k] - pA<n>(X, wx, wy, k, d);
+    return B[k] - pA<n, T, kR>(X, wx, wy, k, d);
   };
   LDS_FOR_NODES(NT, nc, kc) {
     const int I = kc & (nc - 1), J = kc >> Mesh<nc>::lg;
@@ -194,39 +246,40 @@ MLQMC_DEV void prolong_add(const T* Xc, T* X) {
 // alternate between X and Xtmp, for top levels in global scratch).  kSw: 2 or
 // 3 Jacobi sweeps per smoothing step with the Chebyshev weights of that
 // degree (3 needs kStage).
-template <int NT, int n, bool kStage = true, typename T, int kSw = 2>
+template <int NT, int n, bool kStage = true, typename T, int kSw = 2, bool kR = false>
 MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtmp = nullptr) {
   static_assert(kSw == 2 || (kSw == 3 && kStage), "3 sweeps need register staging");
+  static_assert(!kR || kStage, "the reaction term runs with register staging only");
   if constexpr (n == 2) {
-    if (threadIdx.x == 0) X[3] = B[3] / pdiag<2>(wx, wy, 3);
+    if (threadIdx.x == 0) X[3] = B[3] / pdiag<2, T, kR>(wx, wy, 3);
     __syncthreads();
   } else {
     constexpr int nc = n / 2, Pc = Mesh<nc>::P;
     const T* wxc = nxt;
     const T* wyc = wxc + Pc;
-    T* Bc = nxt + 2 * Pc;
+    T* Bc = nxt + wblock<kR>() * Pc;
     T* Xc = Bc + Pc;
     if constexpr (kSw == 3) {
-      jacobi_first<NT, n>(wx, wy, B, X, kCheb3[0]);
-      jacobi_sweep<NT, n>(wx, wy, B, X, kCheb3[1]);
-      jacobi_sweep<NT, n>(wx, wy, B, X, kCheb3[2]);
+      jacobi_first<NT, n, T, kR>(wx, wy, B, X, kCheb3[0]);
+      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[1]);
+      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[2]);
     } else if constexpr (kStage) {
-      jacobi_first<NT, n>(wx, wy, B, X, kOmega1);
-      jacobi_sweep<NT, n>(wx, wy, B, X, kOmega2);
+      jacobi_first<NT, n, T, kR>(wx, wy, B, X, kOmega1);
+      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kOmega2);
     } else {
       jacobi_first<NT, n>(wx, wy, B, Xtmp, kOmega1);
       jacobi_to<NT, n>(wx, wy, B, Xtmp, X, kOmega2);
     }
-    restrict_residual<NT, n>(wx, wy, B, X, Bc);
-    vcycle<NT, nc, true, T, kSw>(wxc, wyc, Bc, Xc, Xc + Pc);
+    restrict_residual<NT, n, T, kR>(wx, wy, B, X, Bc);
+    vcycle<NT, nc, true, T, kSw, kR>(wxc, wyc, Bc, Xc, Xc + Pc);
     prolong_add<NT, n>(Xc, X);
     if constexpr (kSw == 3) {
-      jacobi_sweep<NT, n>(wx, wy, B, X, kCheb3[0]);
-      jacobi_sweep<NT, n>(wx, wy, B, X, kCheb3[1]);
-      jacobi_sweep<NT, n>(wx, wy, B, X, kCheb3[2]);
+      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[0]);
+      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[1]);
+      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[2]);
     } else if constexpr (kStage) {
-      jacobi_sweep<NT, n>(wx, wy, B, X, kOmega1);
-      jacobi_sweep<NT, n>(wx, wy, B, X, kOmega2);
+      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kOmega1);
+      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kOmega2);
     } else {
       jacobi_to<NT, n>(wx, wy, B, X, Xtmp, kOmega1);
       jacobi_to<NT, n>(wx, wy, B, Xtmp, X, kOmega2);
@@ -275,16 +328,24 @@ struct WeightsFromTable {
 };
 
 // ||x||_M^2 and x^T A x in one pass in FP64 with FP64 weights from wf (all
-// threads get both)
-template <int NT, int n, typename T, class WF>
+// threads get both).  With the reaction term (FP64 storage only) the operator
+// is applied from the arrays in `a` and wf is not used.
+template <int NT, int n, typename T, class WF, bool kR = false>
 MLQMC_DEV void rayleigh_parts(const PcgArrays<T>& a, const T* x, const WF& wf, double& xMx,
                               double& xAx) {
+  static_assert(!kR || sizeof(T) == 8, "the reaction term runs in FP64");
   double s[2] = {0.0, 0.0};
   LDS_FOR_NODES(NT, n, k) {
-    const Wd w = wf(k);
     const double xc = (double)x[k];
-    const double ax = w.ww * (xc - (double)x[k - 1]) + w.we * (xc - (double)x[k + 1]) +
-                      w.ws * (xc - (double)x[k - n]) + w.wn * (xc - (double)x[k + n]);
+    double ax;
+    if constexpr (kR) {
+      T d;
+      ax = (double)pA<n, T, true>(x, a.wx, a.wy, k, d);
+    } else {
+      const Wd w = wf(k);
+      ax = w.ww * (xc - (double)x[k - 1]) + w.we * (xc - (double)x[k + 1]) +
+           w.ws * (xc - (double)x[k - n]) + w.wn * (xc - (double)x[k + n]);
+    }
     s[0] += xc * pM12d<n>(x, k);
     s[1] += xc * ax;
   }
@@ -315,12 +376,12 @@ MLQMC_DEV void scale_vec(T* x, double f) {
   __syncthreads();
 }
 
-template <int NT, int n, typename T>
+template <int NT, int n, bool kR = false, typename T>
 MLQMC_DEV void precondition(const PcgArrays<T>& a, const T* r, T* z) {
   if constexpr (n > 32)
     vcycle<NT, n, false, T>(a.wx, a.wy, r, z, a.mg, a.xtmp);
   else
-    vcycle<NT, n, true, T>(a.wx, a.wy, r, z, a.mg);
+    vcycle<NT, n, true, T, 2, kR>(a.wx, a.wy, r, z, a.mg);
 }
 
 // Projected PCG for  P (A - mu M) P^T t = -(A v - rho M v), t = 0 initially.
@@ -332,7 +393,7 @@ MLQMC_DEV void precondition(const PcgArrays<T>& a, const T* r, T* z) {
 // w = v + t, from the step's dot products, and the error estimated from the
 // tails of f (energy, factor c^2) and m (first order, factor c, scaled by
 // |lambda - mu|), c the observed residual contraction.
-template <int NT, int n, bool kTrack = false, typename T>
+template <int NT, int n, bool kTrack = false, bool kR = false, typename T>
 MLQMC_DEV int jd_pcg(const PcgArrays<T>& a, double mu, double rho, double rtol, int maxit,
                      bool* conv, bool* brk, double lam_tol = 0.0) {
   constexpr int K = kTrack ? 6 : 3;
@@ -345,12 +406,12 @@ MLQMC_DEV int jd_pcg(const PcgArrays<T>& a, double mu, double rho, double rtol, 
   T* const q = a.q;
   LDS_FOR_NODES(NT, n, k) {
     T d;
-    const T av = pA<n>(v, a.wx, a.wy, k, d);
+    const T av = pA<n, T, kR>(v, a.wx, a.wy, k, d);
     r[k] = -(av - (T)rho * hm * pM12<n>(v, k));
     t[k] = T(0);
   }
   __syncthreads();
-  precondition<NT, n>(a, r, z);
+  precondition<NT, n, kR>(a, r, z);
   // rz = r.(P^T z) = r.z - (r.v)(Mv.z);  p = P^T z
   double s3[3] = {0.0, 0.0, 0.0};
   LDS_FOR_NODES(NT, n, k) {
@@ -380,7 +441,7 @@ MLQMC_DEV int jd_pcg(const PcgArrays<T>& a, double mu, double rho, double rtol, 
     for (int e = 0; e < K; ++e) s[e] = 0.0;
     LDS_FOR_NODES(NT, n, k) {
       T d;
-      const T ap = pA<n>(p, a.wx, a.wy, k, d);
+      const T ap = pA<n, T, kR>(p, a.wx, a.wy, k, d);
       const T mp = hm * pM12<n>(p, k);
       const T qv = ap - muT * mp;
       const double pk = (double)p[k], qd = (double)qv;
@@ -426,7 +487,7 @@ MLQMC_DEV int jd_pcg(const PcgArrays<T>& a, double mu, double rho, double rtol, 
       *conv = true;
       break;
     }
-    precondition<NT, n>(a, r, z);
+    precondition<NT, n, kR>(a, r, z);
     double u[3] = {0.0, 0.0, 0.0};
     LDS_FOR_NODES(NT, n, k) {
       const double zk = (double)z[k];
@@ -450,20 +511,21 @@ MLQMC_DEV int jd_pcg(const PcgArrays<T>& a, double mu, double rho, double rtol, 
   return it;
 }
 
-// Padded edge weights of mesh n from the padded edge table of the batched
-// path (rows of [WX | WY] with (n + 2) n entries each):
-// w_e = a0 + sum_{j<S} y_j Phi[j][e].  Entries that no stencil reads are
-// finite and otherwise unused.
-template <int NT, int n, typename T>
+// Padded edge weights of mesh n from a padded edge table of the batched
+// path (rows of NSEG segments of (n + 2) n entries: [WX | WY], or the
+// reaction's [RX | RY | RD]): w_e = a0 + sum_{j<S} y_j Phi[j][e], the
+// segments written contiguously with stride P.  Entries that no stencil
+// reads are finite and otherwise unused.
+template <int NT, int n, typename T, int NSEG = 2>
 MLQMC_DEV void weights_from_table(const double* __restrict__ phi, const double* ys, int S,
                                   double a0, T* w) {
   constexpr int P = Mesh<n>::P, PG = (n + 2) * n;
-  for (int e = threadIdx.x; e < 2 * P; e += NT) {
-    const int half = e >= P, idx = e - half * P;
-    const double* src = phi + half * PG + idx;
+  for (int e = threadIdx.x; e < NSEG * P; e += NT) {
+    const int seg = e / P, idx = e - seg * P;
+    const double* src = phi + seg * PG + idx;
     double acc = a0;
-    for (int j = 0; j < S; ++j) acc += ys[j] * src[(int64_t)j * 2 * PG];
-    w[e] = (T)acc;  // WY follows WX contiguously
+    for (int j = 0; j < S; ++j) acc += ys[j] * src[(int64_t)j * NSEG * PG];
+    w[e] = (T)acc;
   }
   __syncthreads();
 }

@@ -1,0 +1,179 @@
+"""GPU parity for Problem 2 of the numerical section (four interior islands:
+region-wise diffusion a and reaction b), against the FP64 CPU oracle,
+through the C ABI (mlqmc_create_islands).
+
+The family runs in FP64 on meshes 1/8 .. 1/32, every array of a solve in
+LDS.  Tolerances as for Problem 1: eigenvalues relative 1e-10 per sample,
+G(u) relative 1e-9, estimator sums from the per-sample bound.  Both parameter
+sets of the paper's complexity figure are covered: decays (4/3, 2, 4/3, 2)
+and (2, 2, 2, 2) for (a on the islands, a outside, b on the islands, b
+outside).
+"""
+
+import numpy as np
+import pytest
+
+import paper_2103_03407_amd as m
+from oracle import mlqmc, qmc, twogrid
+from synth import LevelSpec, islands_family, lattice_vector, shifts_for
+
+pytestmark = pytest.mark.gpu
+
+LAM_RTOL = 1e-10
+G_RTOL = 1e-9
+PARS = {"p43": (4.0 / 3.0, 2.0, 4.0 / 3.0, 2.0), "p2": (2.0, 2.0, 2.0, 2.0)}
+
+
+@pytest.fixture(scope="module", params=sorted(PARS))
+def fam(request):
+    return islands_family(64, *PARS[request.param])
+
+
+@pytest.fixture(scope="module")
+def ctx(fam):
+    c = m.Context(fam)
+    yield c
+    c.close()
+
+
+def _lv6(lv):
+    return (lv.n_fine, lv.s_fine, lv.n_coarse, lv.s_coarse, lv.n_prev, lv.s_prev)
+
+
+def _points(s, count, seed):
+    z = lattice_vector(1024, 64)[:s]
+    sh = shifts_for(seed, 0, 1, s)[0]
+    return np.ascontiguousarray(qmc.lattice_points(z, 1024, sh, range(count)))
+
+
+def _rel(a, b):
+    return np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.abs(np.asarray(b)))
+
+
+@pytest.mark.parametrize("n,s,count", [(8, 8, 17), (16, 16, 12), (32, 16, 9), (32, 64, 7),
+                                       (16, 0, 3)])
+def test_direct_eigenvalues(ctx, fam, n, s, count):
+    Y = _points(max(s, 1), count, 31)[:, :s]
+    Y = np.ascontiguousarray(Y)
+    lam = np.empty(count)
+    fl = np.zeros(count, np.uint8)
+    rq = np.zeros(count, np.int32)
+    ctx.eig_level((n, s, 0, 0, 0, 0), Y, lam, fl, rq_iters=rq)
+    assert not fl.any(), fl
+    ref = np.array([twogrid.direct(n, s, y, fam)[0] for y in Y])
+    assert _rel(lam, ref) <= LAM_RTOL
+    assert rq.min() >= 1 and rq.max() <= 8
+
+
+def test_warm_and_cold_chains_agree(ctx, fam):
+    Y = _points(32, 24, 32)
+    out = {}
+    for warm in (0, 1):
+        lam = np.empty(24)
+        fl = np.zeros(24, np.uint8)
+        o = m.default_opts(chain_len=8)
+        ctx.eig_level((32, 32, 0, 0, 0, 0), Y, lam, fl, warm_chain=warm, opts=o)
+        assert not fl.any()
+        out[warm] = lam
+    assert _rel(out[1], out[0]) <= LAM_RTOL
+
+
+@pytest.mark.parametrize("lv", [(16, 16, 8, 8, 0, 0), (32, 64, 16, 32, 0, 0),
+                                (32, 32, 8, 16, 16, 16), (32, 32, 8, 8, 8, 8)])
+def test_two_grid_level(ctx, fam, lv):
+    # two-grid value, its coarse value and the level-(l-1) term (including
+    # the degenerate previous mesh, which is the coarse mesh itself)
+    spec = LevelSpec(*lv, 0)
+    count = 10
+    Y = _points(lv[1], count, 33)
+    lam, lamc, lamp = np.empty(count), np.empty(count), np.empty(count)
+    fl = np.zeros(count, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl, lam_coarse=lamc, lam_prev=lamp if lv[4] else None)
+    assert not fl.any(), fl
+    for k in range(count):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= LAM_RTOL * v.lam, (k, lam[k], v.lam)
+        assert abs(lamc[k] - v.lam_coarse) <= LAM_RTOL * v.lam_coarse
+        if lv[4]:
+            assert abs(lamp[k] - v.lam_prev) <= LAM_RTOL * v.lam_prev
+
+
+@pytest.mark.parametrize("lv", [(32, 16, 0, 0, 16, 8), (32, 32, 8, 16, 16, 16)])
+def test_functional(ctx, fam, lv):
+    spec = LevelSpec(*lv, 0)
+    count = 8
+    Y = _points(lv[1], count, 34)
+    lam, lamp, g, gp = (np.empty(count) for _ in range(4))
+    fl = np.zeros(count, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp, g=g, g_prev=gp)
+    assert not fl.any(), fl
+    for k in range(count):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= LAM_RTOL * v.lam
+        assert abs(lamp[k] - v.lam_prev) <= LAM_RTOL * v.lam_prev
+        assert abs(g[k] - v.G) <= G_RTOL * v.G, (k, g[k], v.G)
+        assert abs(gp[k] - v.G_prev) <= G_RTOL * v.G_prev
+
+
+def test_estimate_three_levels(ctx, fam):
+    levels = [LevelSpec(8, 8, 0, 0, 0, 0, 16), LevelSpec(16, 16, 8, 8, 8, 8, 8),
+              LevelSpec(32, 32, 8, 16, 16, 16, 4)]
+    R = 3
+    Ns = [16, 8, 4]
+    zs = [lattice_vector(N, lv.s_fine) for N, lv in zip(Ns, levels)]
+    shifts = [shifts_for(35, l, R, lv.s_fine) for l, lv in enumerate(levels)]
+    st, Q, Qh, V, est = ctx.estimate([_lv6(lv) for lv in levels], Ns, R, zs, shifts)
+    assert st == m.MLQMC_OK
+    ref = mlqmc.estimate(levels, zs, Ns, shifts, fam)
+    # each level value is a difference of two eigenvalues, each below 5 here
+    lam_max = 5.0
+    assert ref.Qhat[0] < lam_max
+    dq = 2 * lam_max * LAM_RTOL
+    assert np.max(np.abs(Q - ref.Q_lr)) <= dq
+    assert np.max(np.abs(Qh - ref.Qhat)) <= dq
+    assert abs(est[0] - ref.Q_ml) <= 3 * dq
+    dq = 2 * dq
+    for l in range(3):
+        bound = 2.0 / (R * (R - 1)) * np.sum(np.abs(ref.Qhat[l] - ref.Q_lr[l]) * dq) + R * dq * dq
+        assert abs(V[l] - ref.V[l]) <= bound + 1e-18
+
+
+def test_nested_estimate(ctx, fam):
+    N = [16, 8, 4]
+    levels = [LevelSpec(8, 4, 0, 0, 0, 0, N[0]), LevelSpec(16, 6, 8, 4, 8, 4, N[1]),
+              LevelSpec(32, 8, 8, 4, 16, 6, N[2])]
+    R = 2
+    z = lattice_vector(64, 8) % N[0]
+    shifts = shifts_for(36, 0, R, 8)
+    st, Q, Qh, V, est, lam = ctx.estimate_nested([_lv6(l) for l in levels], N, R, z, shifts,
+                                                 lam_out=True)
+    assert st == m.MLQMC_OK
+    for r in range(R):
+        ref = mlqmc.nested_values(levels, z, N, shifts[r], fam)
+        for l in range(3):
+            assert np.max(np.abs(lam[l][r] - ref[l]) / ref[l]) <= LAM_RTOL, (l, r)
+    ref = mlqmc.estimate_nested(levels, z, N, shifts, fam)
+    scale = ref.Qhat[0]
+    assert np.max(np.abs(Q - ref.Q_lr)) <= 4 * LAM_RTOL * scale
+    assert abs(est[0] - ref.Q_ml) <= 4 * LAM_RTOL * scale
+
+
+@pytest.mark.parametrize("lv,prec", [((64, 32, 16, 16, 0, 0), m.MLQMC_FP64),
+                                     ((4, 4, 0, 0, 0, 0), m.MLQMC_FP64),
+                                     ((32, 16, 8, 8, 64, 16), m.MLQMC_FP64),
+                                     ((16, 8, 0, 0, 0, 0), m.MLQMC_MIXED)])
+def test_rejected_levels(ctx, lv, prec):
+    # meshes outside 1/8 .. 1/32 and mixed precision are refused on the host
+    Y = _points(max(lv[1], 1), 2, 37)
+    lam = np.empty(2)
+    fl = np.zeros(2, np.uint8)
+    with pytest.raises(m.MlqmcError) as e:
+        ctx.eig_level(lv, Y, lam, fl, opts=m.default_opts(prec=prec))
+    assert e.value.code == m.MLQMC_EINVAL
+
+
+def test_problem1_calls_refused(ctx):
+    Y = _points(4, 2, 38)
+    with pytest.raises(m.MlqmcError) as e:
+        ctx.coefficient(8, 4, Y, np.empty((2, 128)))
+    assert e.value.code == m.MLQMC_EINVAL

@@ -9,7 +9,9 @@ coefficients) from the numerical section.
   background values take exactly their two values;
 * adding reaction on the islands raises the eigenvalue, by at most the
   added amount (min-max);
-* the two-grid value tends to the direct one as the coarse mesh is refined.
+* the two-grid value tends to the direct one as the coarse mesh is refined;
+* the discrete ground state has one sign and the second eigenvector does not
+  (the reading behind the GPU path's wrong-pair check for this problem).
 """
 
 import math
@@ -93,3 +95,24 @@ def test_two_grid_tends_to_direct():
         errs.append(abs(twogrid.two_grid(h, 6, H, 6, y, fam)[0] - lam))
     assert errs[1] < errs[0] and errs[1] < 1e-3 * lam
     assert all(twogrid.two_grid(h, 6, H, 6, y, fam)[0] >= lam * (1 - 1e-13) for H in (8, 16))
+
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_ground_state_has_one_sign(n):
+    # the GPU path flags a converged Problem 2 eigenvector as the wrong pair
+    # when the share of its l1 norm carried by its dominant sign is below 0.9;
+    # the direct ground state must carry (almost) all of it, the second
+    # eigenvector well under the threshold
+    import scipy.sparse.linalg as spla
+    for pars in ((4.0 / 3.0, 2.0, 4.0 / 3.0, 2.0), (2.0, 2.0, 2.0, 2.0)):
+        fam = islands_family(16, *pars)
+        rng = np.random.default_rng(n)
+        for _ in range(3):
+            y = rng.random(16) - 0.5
+            A = twogrid.operator(n, 16, y, fam)
+            M = fem.mass(n)
+            vals, vecs = spla.eigsh(A.tocsc(), k=2, M=M.tocsc(), sigma=0.0, which="LM")
+            order = np.argsort(vals)
+            share = [abs(vecs[:, k].sum()) / np.abs(vecs[:, k]).sum() for k in order]
+            assert share[0] >= 0.999, share
+            assert share[1] < 0.9, share
