@@ -8,6 +8,12 @@ i.e. one ``mlqmc_estimate`` call on the single-level two-grid workload
 H = 1/32 -> h = 1/128, s = 64, S = 8, N = 1024 lattice points x R = 8 shifts
 (8192 eigen-samples), all synthetic (CBC lattice, seeded shifts).
 
+``--cfg`` selects another workload of ``synth/configs.py``: 4 and 6 are the
+five-level estimators (independent and shared shifts), 7 and 8 Problem 2 (the
+islands) as one two-grid level H = 1/8 -> h = 1/32 and as the three-level
+estimator on h = 1/8, 1/16, 1/32; their two-grid updates run in LDS, and the
+roofline is then that kernel's FP64 rate against the FP64 vector peak.
+
 Prints one JSON line.  ``value`` = eigen-samples per second on one GPU.
 """
 
@@ -26,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
 PEAK_FP64_MFMA_TFS = 78.6  # MI355X dense FP64 matrix, published
+PEAK_FP64_VALU_TFS = 78.6  # MI355X FP64 vector, published
 
 
 def _parse():
@@ -34,9 +41,11 @@ def _parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cfg", type=int, default=2, help="workload id (2: two-grid 1/32->1/128)")
-    ap.add_argument("--kernel-class", default="post",
-                    choices=["post", "pre", "apply", "coeff"],
-                    help="kernel timed for the roofline (post: the dominant kernel)")
+    ap.add_argument("--kernel-class", default=None,
+                    choices=["post", "pre", "apply", "coeff", "lds"],
+                    help="kernel timed for the roofline (default: post, the dominant kernel of "
+                         "the batched path; lds, the two-grid update in LDS, for workloads "
+                         "whose fine meshes are all 1/32 or coarser)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"],
                     help="fp64, or mixed (FP32 fine PCG/V-cycle, FP64 residual and RQ)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -231,6 +240,81 @@ def per_level_nested(ctx, m, w, opts, idx=None, ref=None):
     return out, acc
 
 
+def lds_update_flops(n: int, rows: int, its: int, reaction: bool) -> int:
+    """Algorithmic FP64 flops of one two-grid update on mesh 1/n in LDS
+    (k_tg_small) that took `its` projected-PCG iterations, counted per
+    interior node (one add or multiply = 1; a divide = 1):
+
+    * operator (A [+ R]) x: 11 (4 differences, 4 products, 3 sums), with the
+      reaction 30 (six sums x_k + x_j, six products, 5 sums, the h^2/12 scale,
+      1 sum); mass M x: 8;
+    * V-cycle, per node of each level 1/n .. 1/2: three Jacobi sweeps (op + 4),
+      the first from zero (2), the residual (op + 1), restriction (2) and
+      prolongation (3): 4 op + 20;
+    * PCG iteration on the top level: q = (A - mu M) p (op + mass + 2), three
+      dots (6), three tracking dots (6), t and r updates (6), three dots after
+      the V-cycle (6), p update (4): op + 38, plus one V-cycle;
+    * per sample: the weights (2 rows segs P, segs = 5 with the reaction, 2
+      without), the initial residual and V-cycle, and two Rayleigh quotients
+      (2 (op + mass + 4))."""
+    D = (n - 1) ** 2
+    P = (n + 1) * n + 1
+    op = 30 if reaction else 11
+    mass = 8
+    levels, c = 0, n
+    while c >= 2:
+        levels += (c - 1) ** 2
+        c //= 2
+    vcycle = (4 * op + 20) * levels
+    weights = 2 * rows * (5 if reaction else 2) * P
+    init = (op + mass + 3) * D + vcycle + 8 * D
+    rq = 2 * (op + mass + 4) * D
+    return weights + init + rq + its * ((op + 38) * D + vcycle)
+
+
+def lds_step_flops(ctx, m, w, opts):
+    """Algorithmic flops of every k_tg_small launch of one step of workload w,
+    from the PCG iteration counts of the same points (an untimed pass; the
+    solves are deterministic).  mlqmc_eig_level reports the coarse eigensolve's
+    inner iterations plus the fine update's; the direct coarse eigensolve alone
+    on the same points gives the first part (on Problem 2 with the one-step
+    refinement of its vectors that the two-grid levels apply, which a
+    requested G switches on)."""
+    import numpy as np
+    total = 0
+    reaction = w.problem == 2
+    for l, lv in enumerate(w.levels):
+        if not lv.n_coarse:
+            continue
+        n = w.R * lv.N
+        Y = np.empty((n, max(lv.s_fine, 1)))
+        for r in range(w.R):
+            ctx.lattice_points(lv.N, w.z(l), w.shifts(l)[r], 0, lv.N, Y[r * lv.N:(r + 1) * lv.N])
+        lam = np.empty(n)
+        fl = np.zeros(n, np.uint8)
+        base = np.zeros(n, np.int32)
+        Yc = np.ascontiguousarray(Y[:, :lv.s_coarse])
+        ctx.eig_level((lv.n_coarse, lv.s_coarse, 0, 0, 0, 0), Yc, lam, fl, lin_iters=base,
+                      opts=opts, g=np.empty(n) if reaction else None)
+        updates = [(lv.n_fine, lv.s_fine)]
+        if lv.n_prev and not (lv.n_prev == lv.n_coarse and lv.s_prev == lv.s_coarse):
+            updates.append((lv.n_prev, lv.s_prev))
+        for nm, sm in updates:
+            if nm > 32:
+                continue
+            li = np.zeros(n, np.int32)
+            ctx.eig_level((nm, sm, lv.n_coarse, lv.s_coarse, 0, 0),
+                          np.ascontiguousarray(Y[:, :sm]), lam, fl, lin_iters=li, opts=opts)
+            its = (li - base).astype(np.int64)
+            if its.min() < 0:
+                raise RuntimeError("iteration counts of the coarse eigensolve differ")
+            rows = sm + 1 if reaction else sm
+            total += n * lds_update_flops(nm, rows, 0, reaction)
+            total += int(its.sum()) * (lds_update_flops(nm, rows, 1, reaction) -
+                                       lds_update_flops(nm, rows, 0, reaction))
+    return total
+
+
 def _traffic(kernel: str, prec: str = "fp64", cfg: int = 2):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
     this kernel, precision and workload, or None when there is none or the
@@ -301,8 +385,11 @@ def main():
 
     for _ in range(a.warmup):
         step()
+    if a.kernel_class is None:
+        lds_only = all(lv.n_fine <= 32 for lv in w.levels) and any(lv.n_coarse for lv in w.levels)
+        a.kernel_class = "lds" if lds_only else "post"
     kcls = {"post": m.K_SMOOTH, "pre": m.K_PRE, "apply": m.K_APPLY,
-            "coeff": m.K_COEFF}[a.kernel_class]
+            "coeff": m.K_COEFF, "lds": m.K_TG_LDS}[a.kernel_class]
     ctx.set_timing(kcls)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -317,9 +404,21 @@ def main():
     value = n_samples * a.steps / dt
 
     kname = {"post": "k_post", "pre": "k_pre", "apply": "k_pupdate_apply",
-             "coeff": "k_expand_mfma"}[a.kernel_class]
+             "coeff": "k_expand_mfma", "lds": "k_tg_small"}[a.kernel_class]
     roof = None
-    if launches > 0 and kms > 0 and a.kernel_class == "coeff":
+    if launches > 0 and kms > 0 and a.kernel_class == "lds":
+        # the LDS-resident two-grid update: FP64 vector arithmetic on data in
+        # LDS, so the FP64 vector peak bounds it (HBM traffic is the tables and
+        # points only)
+        avg_ms = kms / launches
+        flops_per_launch = lds_step_flops(ctx, m, w, opts) * a.steps / launches
+        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
+                "peak": PEAK_FP64_VALU_TFS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_VALU_TFS, 4), "traffic": None,
+                "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
+                "algorithmic_flops_per_launch": flops_per_launch}
+    elif launches > 0 and kms > 0 and a.kernel_class == "coeff":
         # the coefficient product on FP64 MFMA: 2 s E flops per sample, every
         # sample expanded once per step (E = edge weights of the padded mesh)
         avg_ms = kms / launches
@@ -369,12 +468,15 @@ def main():
         levels_out, acc = per_level(ctx, m, w, opts, idx, ref)
 
     out = {
-        "metric": "two-grid eigen-samples/sec per level; stencil HBM GB/s in roofline",
+        "metric": "two-grid eigen-samples/sec per level; stencil HBM GB/s in roofline"
+                  if w.problem == 1 else
+                  "two-grid eigen-samples/sec per level (Problem 2, islands); LDS-update "
+                  "FP64 TFLOP/s in roofline",
         "value": round(value, 1), "unit": "samples/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if a.prec == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"workload": w.name, "levels": len(w.levels),
+        "config": {"workload": w.name, "problem": w.problem, "levels": len(w.levels),
                    "h": [f"1/{lv.n_fine}" for lv in w.levels],
                    "H": [f"1/{lv.n_coarse}" if lv.n_coarse else None for lv in w.levels],
                    "s": [lv.s_fine for lv in w.levels], "S": [lv.s_coarse for lv in w.levels],

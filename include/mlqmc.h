@@ -281,7 +281,9 @@ enum {
   MLQMC_K_APPLY = 2,     /* fine operator apply inside the projected PCG */
   MLQMC_K_SMOOTH = 3,    /* finest-level coarse correction + post-smoothing + PCG dots */
   MLQMC_K_COARSE = 4,    /* coarse eigensolve (persistent chain kernel) */
-  MLQMC_K_PRE = 5        /* finest-level pre-smoothing + residual restriction */
+  MLQMC_K_PRE = 5,       /* finest-level pre-smoothing + residual restriction */
+  MLQMC_K_TG_LDS = 6     /* two-grid update in LDS (fine meshes up to 1/32), one launch
+                            per level update; its model bytes are 0 */
 };
 /* Selects the kernel class whose launches are bracketed by HIP events on the
  * context's stream (MLQMC_K_NONE disables) and clears the totals. */

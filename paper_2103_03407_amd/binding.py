@@ -21,7 +21,7 @@ TUNING_PATH = os.path.join(HERE, "tuning.json")
 MLQMC_OK, MLQMC_EINVAL, MLQMC_ENOMEM, MLQMC_EDEVICE, MLQMC_ENOCONV = 0, -1, -2, -3, -4
 MLQMC_FP64, MLQMC_MIXED = 0, 1
 FLAG_RQ_NOCONV, FLAG_LIN_NOCONV, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_WRONG_PAIR = 1, 2, 4, 8, 16
-K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE, K_PRE = 0, 1, 2, 3, 4, 5
+K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE, K_PRE, K_TG_LDS = 0, 1, 2, 3, 4, 5, 6
 
 # every symbol include/mlqmc.h declares
 EXPORTS = [
@@ -281,6 +281,10 @@ class Context:
                   lin_iters=None, warm_chain=1, opts=None, g=None, g_prev=None):
         o = opts if opts is not None else default_opts()
         lv = Level(*[int(x) for x in level])
+        # the library reads Y with row stride s_fine
+        if len(Y.shape) != 2 or (Y.shape[1] != lv.s_fine and not (lv.s_fine == 0 and
+                                                                   Y.shape[1] <= 1)):
+            raise ValueError(f"Y must be [n, s_fine={lv.s_fine}] (got {tuple(Y.shape)})")
         py, d0 = _ptr(Y, np.float64)
         pl, d1 = _ptr(lam, np.float64)
         pf, d2 = _ptr(flags, np.uint8)

@@ -29,7 +29,7 @@ _STORE = os.path.join(_HERE, "lattice")
 # (N, s) pairs the workloads need; gamma_j = j^-2 throughout.
 NEEDED = [(256, 16), (1024, 64), (16384, 16), (8192, 32), (2048, 64),
           (1024, 128), (256, 256), (1024, 512), (64, 8), (128, 16), (512, 32),
-          (16384, 256)]
+          (16384, 256), (4096, 32)]
 
 
 def _b2(x: np.ndarray) -> np.ndarray:
@@ -84,8 +84,13 @@ def lattice_vector(N: int, s: int) -> np.ndarray:
 
 
 def main(argv=None) -> int:
+    """Writes the stored vectors: all of NEEDED, or the (N, s) pairs given as
+    N:s arguments."""
     os.makedirs(_STORE, exist_ok=True)
-    for N, s in NEEDED:
+    todo = NEEDED
+    if argv:
+        todo = [tuple(int(v) for v in a.split(":")) for a in argv]
+    for N, s in todo:
         z = cbc_vector(N, s)
         np.savetxt(_path(N, s), z, fmt="%d",
                    header=f"CBC generating vector N={N} s={s} gamma_j=j^-2")

@@ -10,6 +10,10 @@ the number of lattice points N.  All levels share R random shifts.
 Shifts are independent per level and per replicate, drawn uniformly on
 [0, 1)^s from ``numpy.random.default_rng([210303407, cfg, level, r])``.
 
+Problem 2 workloads (``problem=2``) use the islands family with the decays
+(p_a, p_a', p_b, p_b') of the left panel of the paper's Problem 2 complexity
+figure, (4/3, 2, 4/3, 2), and meshes h_l = 2^-(l+3) up to 1/32.
+
 A nested workload (end of section 4.3) shares one set of R shifts (level 0's
 seeds, s_max components) and one generating vector (the CBC vector for the
 largest N with s_max components, enumerated as an embedded base-2 rule)
@@ -25,7 +29,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .cbc import lattice_vector
-from .family import coeff_family
+from .family import coeff_family, islands_family
 
 SEED_ROOT = 210303407
 
@@ -52,12 +56,16 @@ class Workload:
     description: str = ""
     a0: float = 1.0
     nested: bool = False
+    problem: int = 1              # 1: benchmark / Problem 1 table; 2: islands
+    decays: tuple = ()            # Problem 2: (p_a, p_a', p_b, p_b')
 
     @property
     def s_max(self) -> int:
         return max(lv.s_fine for lv in self.levels)
 
     def family(self):
+        if self.problem == 2:
+            return islands_family(self.s_max, *self.decays)
         return coeff_family(self.s_max, decay=self.decay, a0=self.a0)
 
     def z(self, level: int) -> np.ndarray:
@@ -114,6 +122,20 @@ def _cfg4_levels():
     return tuple(out)
 
 
+def _islands_levels():
+    """h_l = 1/8, 1/16, 1/32 (h_l = 2^-(l+3)), s_l = 16, 32, 64; H_l = 1/8 (the
+    coarsest mesh that resolves the islands) and S_l = s_0 = 16 for l >= 1."""
+    ns, ss, Ns = [8, 16, 32], [16, 32, 64], [1 << 13, 1 << 12, 1 << 11]
+    out = [LevelSpec(8, 16, 0, 0, 0, 0, Ns[0])]
+    for l in (1, 2):
+        out.append(LevelSpec(ns[l], ss[l], 8, coarse_trunc(ss[l], ss[0]), ns[l - 1], ss[l - 1],
+                             Ns[l]))
+    return tuple(out)
+
+
+P2_DECAYS = (4.0 / 3.0, 2.0, 4.0 / 3.0, 2.0)
+
+
 def _nested_levels(base):
     """The levels of ``base`` with H_l = h_0 and S_l = s_0 for l >= 1."""
     l0 = base[0]
@@ -139,6 +161,13 @@ CONFIGS = {
     6: Workload("cfg6-mlqmc-5level-nested", 6, "fp64", 2.5, _nested_levels(_cfg4_levels()), 8,
                 "cfg4's meshes, truncations and N_l with shared shifts, one embedded rule "
                 "and H_l = h_0 = 1/16, S_l = s_0 = 16 (end of section 4.3)", nested=True),
+    7: Workload("cfg7-islands-twogrid-H8-h32-s64", 7, "fp64", 0.0,
+                (LevelSpec(32, 64, 8, 8, 0, 0, 1024),), 8,
+                "Problem 2 (islands), single-level two-grid H=1/8 -> h=1/32, s=64, S=8, "
+                "N=1024 x R=8", problem=2, decays=P2_DECAYS),
+    8: Workload("cfg8-islands-mlqmc-3level", 8, "fp64", 0.0, _islands_levels(), 8,
+                "Problem 2 (islands), three-level two-grid MLQMC, h=1/8..1/32, s=16..64, "
+                "H=1/8, S=16", problem=2, decays=P2_DECAYS),
 }
 
 

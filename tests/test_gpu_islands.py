@@ -15,7 +15,7 @@ import pytest
 
 import paper_2103_03407_amd as m
 from oracle import mlqmc, qmc, twogrid
-from synth import LevelSpec, islands_family, lattice_vector, shifts_for
+from synth import CONFIGS, LevelSpec, islands_family, lattice_vector, shifts_for
 
 pytestmark = pytest.mark.gpu
 
@@ -177,3 +177,71 @@ def test_problem1_calls_refused(ctx):
     with pytest.raises(m.MlqmcError) as e:
         ctx.coefficient(8, 4, Y, np.empty((2, 128)))
     assert e.value.code == m.MLQMC_EINVAL
+
+
+# ---------------- the Problem 2 workloads at full size, sampled ----------------
+
+def _level_points(ctx, w, l):
+    lv = w.levels[l]
+    Y = np.empty((w.R * lv.N, lv.s_fine))
+    for r in range(w.R):
+        ctx.lattice_points(lv.N, w.z(l), w.shifts(l)[r], 0, lv.N, Y[r * lv.N:(r + 1) * lv.N])
+    return Y
+
+
+@pytest.fixture(scope="module")
+def ctx_p2():
+    c = m.Context(CONFIGS[7].family())
+    yield c
+    c.close()
+
+
+def test_cfg7_full_batch_sampled(ctx_p2):
+    # the bench workload of Problem 2: every sample of the step unflagged,
+    # strided samples against the oracle, the estimator from the same values
+    w = CONFIGS[7]
+    fam = w.family()
+    lv = w.levels[0]
+    Y = _level_points(ctx_p2, w, 0)
+    n = Y.shape[0]
+    lam, lamc = np.empty(n), np.empty(n)
+    fl = np.zeros(n, np.uint8)
+    ctx_p2.eig_level(_lv6(lv), Y, lam, fl, lam_coarse=lamc)
+    assert not fl.any()
+    for i in range(0, n, 1021):
+        lt, lH, _ = twogrid.two_grid(lv.n_fine, lv.s_fine, lv.n_coarse, lv.s_coarse, Y[i], fam)
+        assert abs(lam[i] - lt) <= LAM_RTOL * lt, (i, lam[i], lt)
+        assert abs(lamc[i] - lH) <= LAM_RTOL * lH
+    st, Q, Qh, V, est = ctx_p2.estimate([_lv6(lv)], [lv.N], w.R, [w.z(0)],
+                                        [w.shifts(0)])
+    assert st == m.MLQMC_OK
+    per_r = lam.reshape(w.R, lv.N).mean(axis=1)
+    assert np.max(np.abs(Q[0] - per_r)) <= 1e-12 * np.max(per_r)
+
+
+def test_cfg8_three_levels_sampled(ctx_p2):
+    # the three-level Problem 2 workload (h = 1/8, 1/16, 1/32): per level, the
+    # level values of every point unflagged, strided ones against the oracle,
+    # and the estimator's level means equal to the means of those values
+    w = CONFIGS[8]
+    fam = w.family()
+    st, Q, Qh, V, est = ctx_p2.estimate([_lv6(lv) for lv in w.levels],
+                                        [lv.N for lv in w.levels], w.R,
+                                        [w.z(l) for l in range(3)],
+                                        [w.shifts(l) for l in range(3)])
+    assert st == m.MLQMC_OK
+    for l, lv in enumerate(w.levels):
+        Y = _level_points(ctx_p2, w, l)
+        n = Y.shape[0]
+        lam, lamp = np.empty(n), np.empty(n)
+        fl = np.zeros(n, np.uint8)
+        ctx_p2.eig_level(_lv6(lv), Y, lam, fl, lam_prev=lamp if lv.n_prev else None)
+        assert not fl.any()
+        Yl = lam - lamp if lv.n_prev else lam
+        for i in range(0, n, n // 5 + 7):
+            v = mlqmc.level_value(lv, Y[i], fam)
+            assert abs(lam[i] - v.lam) <= LAM_RTOL * v.lam, (l, i)
+            assert abs(Yl[i] - v.Y) <= 2 * LAM_RTOL * v.lam, (l, i)
+        per_r = Yl.reshape(w.R, lv.N).mean(axis=1)
+        assert np.max(np.abs(Q[l] - per_r)) <= 1e-12 * np.max(lam)
+    assert abs(est[0] - Qh.sum()) <= 1e-13 * abs(est[0])

@@ -272,6 +272,16 @@ def test_estimate_small_multilevel(ctx, fam):
     assert abs(est[1] - ref.V_ml) <= 3 * (np.sum(np.abs(ref.Q_lr)) * dq) + 1e-18
 
 
+def test_points_must_match_the_truncation(ctx):
+    # the library reads Y with row stride s_fine: the binding refuses a Y with
+    # another column count instead of passing misread points
+    Y = np.ascontiguousarray(_points(256, 16, 1, 0, 0, range(3)))
+    lam = np.empty(3)
+    fl = np.zeros(3, np.uint8)
+    with pytest.raises(ValueError):
+        ctx.eig_level((8, 8, 0, 0, 0, 0), Y, lam, fl)
+
+
 def test_estimate_single_shift_variance_is_nan(ctx, fam):
     st, Q, Qh, V, est = ctx.estimate([(8, 8, 0, 0, 0, 0)], [8], 1, [lattice_vector(8, 8)],
                                      [shifts_for(8, 0, 1, 8)])
