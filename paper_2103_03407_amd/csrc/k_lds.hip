@@ -17,6 +17,13 @@ template <int N>
 constexpr int threads_for() {
   return N >= 32 ? 256 : (N >= 16 ? 128 : 64);
 }
+// With the reaction term the 1/32 two-grid update holds 110 KB of LDS, one
+// workgroup per CU: twice the threads keep two waves on each SIMD.  (The
+// eigensolve keeps 256: at 512 its live state no longer fits the registers.)
+template <int N>
+constexpr int threads_for_reaction() {
+  return N >= 32 ? 512 : threads_for<N>();
+}
 
 // v = sin(pi x1) sin(pi x2) at the interior nodes
 template <int NT, int n, typename T>
@@ -376,7 +383,8 @@ hipError_t tg_small_n(const TgSmallArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   if (a.rphi) {  // Problem 2: FP64 only
     if (a.mixed) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_tg_small<N, NT, double, true>), dim3((unsigned)a.n), dim3(NT), 0, st,
+    constexpr int NTR = threads_for_reaction<N>();
+    hipLaunchKernelGGL((k_tg_small<N, NTR, double, true>), dim3((unsigned)a.n), dim3(NTR), 0, st,
                        a);
   } else if (a.mixed) {
     hipLaunchKernelGGL((k_tg_small<N, NT, float>), dim3((unsigned)a.n), dim3(NT), 0, st, a);
