@@ -233,10 +233,11 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t n_levels, const mlqmc_level*
                             double* est, double* g_stats);
 
 /* Nested two-grid MLQMC estimator with shared shifts (end of section 4.3):
- * one embedded rule (z [s_max], s_max = max_l s_fine) and one set of R shifts
- * ([R x s_max], values in [0,1)) serve every level; level l uses the first
- * N[l] points of the rule with N[0] points (N[l] powers of two, non-increasing)
- * and the first s_fine components.  The level list must be:
+ * one embedded rule (z [s_max], s_max = max_l s_fine, entries in [0, 2^31); a
+ * rule of N points uses them modulo N) and one set of R shifts ([R x s_max],
+ * values in [0,1)) serve every level; level l uses the first N[l] points of
+ * the embedded rule (N[l] powers of two, non-increasing) and the first s_fine
+ * components.  The level list must be:
  *   level 0   direct (n_coarse = 0, n_prev = 0);
  *   level l>0 two-grid with (n_coarse, s_coarse) = level 0's (n_fine, s_fine)
  *             and (n_prev, s_prev) = level l-1's (n_fine, s_fine);
@@ -258,6 +259,31 @@ mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t n_levels, const mlqmc
                                    const double* shifts, const mlqmc_opts* opt, double* Q_lr,
                                    double* Qhat, double* V, double* est, double* lam_out,
                                    double* g_stats);
+
+/* Extensible nested estimate (embedded rules of sections 2.5 and 5, shared
+ * shifts of section 4.3): the points of the embedded base-2 rule do not depend
+ * on its size (point k is the lattice point phi_2(k) z + shift for every rule
+ * of more than k points), so an estimate over N_done[l] points per level
+ * continues to N[l] by adding the level values of the points
+ * [N_done[l], N[l]).  sums [n_levels x R] (in/out, host or device as
+ * io_on_device) holds the per-(level, shift) sums of Y_l = lambda^l -
+ * lambda^{l-1} over the first N_done[l] points (zeros with N_done = 0); on
+ * return it holds them over the first N[l].  Q_lr = sums / N[l] and Qhat, V,
+ * est then follow as in mlqmc_estimate_nested, for N[l] points.  g_sums and
+ * g_stats (both NULL, or [n_levels x R] and as in mlqmc_estimate) do the same
+ * for G.  Calling it with N_done = 0 and zero sums equals
+ * mlqmc_estimate_nested (without lam_out); a chain of calls equals one call
+ * to rounding (the sums are added in another order).  The values at a point
+ * are recomputed where a level needs the previous level's there (level l is
+ * evaluated from min(N_done[l], N_done[l+1])).
+ * Errors as mlqmc_estimate_nested, and MLQMC_EINVAL for N_done[l] outside
+ * [0, N[l]]; on an error other than MLQMC_ENOCONV the sums are unchanged. */
+mlqmc_status mlqmc_estimate_nested_extend(mlqmc_ctx* ctx, int32_t n_levels,
+                                          const mlqmc_level* lvls, const int64_t* N_done,
+                                          const int64_t* N, int32_t R, const int64_t* z,
+                                          const double* shifts, const mlqmc_opts* opt,
+                                          double* sums, double* Q_lr, double* Qhat, double* V,
+                                          double* est, double* g_sums, double* g_stats);
 
 /* ---- tuning ---- */
 

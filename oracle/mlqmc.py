@@ -166,6 +166,27 @@ def nested_values(levels, z, Ns, shift, fam):
     return lams
 
 
+def nested_level_sums(levels, z, N_done, Ns, shift, fam):
+    """For one shift, per level l: the sum of Y_l(t_k) = lambda^l(t_k) -
+    lambda^{l-1}(t_k) over k in [N_done[l], Ns[l]), summed exactly rounded.
+    This is what an extensible nested estimate adds when it grows from
+    N_done[l] to Ns[l] points: the points of the embedded rule do not depend
+    on its size (sections 2.5 and 5), so the sums over disjoint blocks add up
+    to the sum over all points."""
+    check_nested(levels, Ns)
+    cache = {}
+    out = []
+    for l in range(len(levels)):
+        terms = []
+        for k in range(N_done[l], Ns[l]):
+            if k not in cache:
+                cache[k] = nested_point(levels, z, Ns, shift, k, fam)
+            lams = cache[k]
+            terms.append(lams[l] - (lams[l - 1] if l else 0.0))
+        out.append(math.fsum(terms))
+    return out
+
+
 def estimate_nested(levels, z, Ns, shifts, fam) -> Estimate:
     """Nested estimator: Y_l(t_k) = lambda^l(t_k) - lambda^{l-1}(t_k)
     (lambda^{-1} = 0), Q_l^(r) their mean over k < N_l, Qhat_l and V_l as in

@@ -29,7 +29,8 @@ EXPORTS = [
     "mlqmc_last_error",
     "mlqmc_lattice_points", "mlqmc_embedded_points", "mlqmc_coefficient",
     "mlqmc_apply_operator", "mlqmc_prolong", "mlqmc_eig_level", "mlqmc_estimate",
-    "mlqmc_estimate_nested", "mlqmc_set_tuning", "mlqmc_set_timing", "mlqmc_get_timing",
+    "mlqmc_estimate_nested", "mlqmc_estimate_nested_extend", "mlqmc_set_tuning",
+    "mlqmc_set_timing", "mlqmc_get_timing",
 ]
 
 
@@ -106,12 +107,15 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                    P, P, P, P]
     lib.mlqmc_estimate_nested.argtypes = [P, I32, C.POINTER(Level), P, I32, P, P,
                                           C.POINTER(Opts), P, P, P, P, P, P]
+    lib.mlqmc_estimate_nested_extend.argtypes = [P, I32, C.POINTER(Level), P, P, I32, P, P,
+                                                 C.POINTER(Opts), P, P, P, P, P, P, P]
     lib.mlqmc_set_tuning.argtypes = [P, I32, I32, I64]
     lib.mlqmc_set_timing.argtypes = [P, I32]
     lib.mlqmc_get_timing.argtypes = [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
     for name in ("mlqmc_create", "mlqmc_create_islands", "mlqmc_lattice_points",
                  "mlqmc_embedded_points", "mlqmc_coefficient", "mlqmc_apply_operator", "mlqmc_prolong",
                  "mlqmc_eig_level", "mlqmc_estimate", "mlqmc_estimate_nested",
+                 "mlqmc_estimate_nested_extend",
                  "mlqmc_set_tuning", "mlqmc_set_timing", "mlqmc_get_timing"):
         getattr(lib, name).restype = C.c_int
     if path == LIB_PATH:
@@ -366,6 +370,43 @@ class Context:
             return st, Q, Qh, V, est, lam, self._g_split(G, L, R)
         return st, Q, Qh, V, est, lam
 
+    def estimate_nested_extend(self, levels, N_done, N, R, z, shifts, sums, opts=None,
+                               g_sums=None):
+        """Continues a nested estimate from N_done[l] to N[l] points per level.
+        sums: float64 [L, R], updated in place (the per-(level, shift) sums of
+        Y_l over the points done; zeros to start).  g_sums: the same for G, or
+        None.  Returns (status, Q_lr, Qhat, V, est) and, with g_sums, a sixth
+        item (Q_lr, Qhat, V, est) for E[G(u)]."""
+        o = opts if opts is not None else default_opts()
+        o.io_on_device = 0
+        L = len(levels)
+        lv = (Level * L)(*[Level(*[int(x) for x in l]) for l in levels])
+        Nd = np.ascontiguousarray(N_done, dtype=np.int64)
+        Nn = np.ascontiguousarray(N, dtype=np.int64)
+        zc = np.ascontiguousarray(z, dtype=np.int64)
+        sc = np.ascontiguousarray(shifts, dtype=np.float64)
+        for arr in (sums, g_sums):
+            if arr is not None and (not isinstance(arr, np.ndarray) or arr.dtype != np.float64
+                                    or not arr.flags.c_contiguous or arr.size != L * R):
+                raise TypeError("sums must be a C-contiguous float64 array of L x R entries")
+        if Nd.size != L or Nn.size != L:
+            raise ValueError("N_done and N need one entry per level")
+        Q = np.zeros((L, R))
+        Qh = np.zeros(L)
+        V = np.zeros(L)
+        est = np.zeros(2)
+        G = np.zeros(L * R + 2 * L + 2) if g_sums is not None else None
+        st = self._check(self._lib.mlqmc_estimate_nested_extend(
+            self._h, L, lv, C.c_void_p(Nd.ctypes.data), C.c_void_p(Nn.ctypes.data), int(R),
+            C.c_void_p(zc.ctypes.data), C.c_void_p(sc.ctypes.data), C.byref(o),
+            C.c_void_p(sums.ctypes.data), C.c_void_p(Q.ctypes.data), C.c_void_p(Qh.ctypes.data),
+            C.c_void_p(V.ctypes.data), C.c_void_p(est.ctypes.data),
+            C.c_void_p(g_sums.ctypes.data) if g_sums is not None else None,
+            C.c_void_p(G.ctypes.data) if G is not None else None), allow_noconv=True)
+        if G is not None:
+            return st, Q, Qh, V, est, self._g_split(G, L, R)
+        return st, Q, Qh, V, est
+
     # ---- instrumentation ----
     def set_timing(self, kernel_class):
         return self._check(self._lib.mlqmc_set_timing(self._h, int(kernel_class)))
@@ -412,6 +453,10 @@ def mlqmc_embedded_points(ctx, *a, **k):
 
 def mlqmc_estimate_nested(ctx, *a, **k):
     return ctx.estimate_nested(*a, **k)
+
+
+def mlqmc_estimate_nested_extend(ctx, *a, **k):
+    return ctx.estimate_nested_extend(*a, **k)
 
 
 def mlqmc_coefficient(ctx, *a, **k):

@@ -1338,18 +1338,23 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
   return flagged ? ctx->fail(MLQMC_ENOCONV, "at least one sample is flagged") : MLQMC_OK;
 }
 
-mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv,
-                                   const int64_t* N, int32_t R, const int64_t* z,
-                                   const double* shifts, const mlqmc_opts* o, double* Q_lr,
-                                   double* Qhat, double* V, double* est, double* lam_out,
-                                   double* g_stats) {
-  if (!ctx) return MLQMC_EINVAL;
-  CS(check_opts(ctx, o));
-  if (nl < 1 || !lv || !N || !z || !shifts || R < 1)
-    return ctx->fail(MLQMC_EINVAL, "need n_levels >= 1, R >= 1 and non-NULL inputs");
-  if (!Q_lr || !Qhat || !V || !est) return ctx->fail(MLQMC_EINVAL, "NULL output");
+namespace {
+// The nested estimator over the points [Nd[l], N[l]) of each level (Nd =
+// nullptr: none done), added to running per-(level, shift) sums of Y_l on the
+// device (dsum [nl x R]; dgsum the same for G, when g_stats is requested).
+// The embedded rule makes the points independent of N (point k is the lattice
+// point phi_2(k) z + shift for every rule size above k), so an estimate over
+// N points continues to any larger N.  Level l is evaluated on [e_l, N[l]),
+// e_l = min(Nd[l], Nd[l+1]): its own new points and those where level l+1
+// needs lambda^l; level 0 provides the coarse pairs on [min_l Nd[l], N[0]).
+mlqmc_status nested_core(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, const int64_t* Nd,
+                         const int64_t* N, int32_t R, const int64_t* z, const double* shifts,
+                         const mlqmc_opts* o, double* dsum, double* dgsum, double* Q_lr,
+                         double* Qhat, double* V, double* est, double* lam_out,
+                         double* g_stats) {
   int s_max = 0;
-  int64_t total = 0, ymax = 0;
+  int64_t total = 0;
+  std::vector<int64_t> a(nl), e(nl);
   for (int l = 0; l < nl; ++l) {
     CS(check_level(ctx, &lv[l]));
     if (!is_pow2(N[l]) || N[l] > ((int64_t)1 << 30))
@@ -1357,9 +1362,11 @@ mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level
     if (l > 0 && N[l] > N[l - 1])
       return ctx->fail(MLQMC_EINVAL, "N must not increase with the level (N[%d] > N[%d])", l,
                        l - 1);
+    a[l] = Nd ? Nd[l] : 0;
+    if (a[l] < 0 || a[l] > N[l])
+      return ctx->fail(MLQMC_EINVAL, "N_done[%d] outside [0, N[%d]]", l, l);
     s_max = std::max(s_max, (int)lv[l].s_fine);
     total += (int64_t)R * N[l];
-    ymax = std::max<int64_t>(ymax, (int64_t)R * N[l] * std::max(1, (int)lv[l].s_fine));
   }
   const mlqmc_level& L0 = lv[0];
   if (L0.n_coarse != 0 || L0.n_prev != 0)
@@ -1371,13 +1378,21 @@ mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level
       return ctx->fail(MLQMC_EINVAL, "level %d: previous term must be on level %d's mesh", l,
                        l - 1);
   }
+  // z: the generating vector of the largest rule the estimate may grow to;
+  // a rule of N points uses it modulo N
   for (int j = 0; j < s_max; ++j)
-    if (z[j] < 0 || z[j] >= N[0]) return ctx->fail(MLQMC_EINVAL, "z[%d] outside [0, N[0])", j);
+    if (z[j] < 0 || z[j] >= ((int64_t)1 << 31))
+      return ctx->fail(MLQMC_EINVAL, "z[%d] outside [0, 2^31)", j);
   for (int64_t k = 0; k < (int64_t)R * s_max; ++k)
     if (!(shifts[k] >= 0.0 && shifts[k] < 1.0))
       return ctx->fail(MLQMC_EINVAL, "shift entry %lld outside [0, 1)", (long long)k);
-  ctx->mem_cap = o->device_mem_cap;
-  CK(hipSetDevice(ctx->device), "set device");
+  for (int l = 0; l < nl; ++l) e[l] = (l + 1 < nl) ? std::min(a[l], a[l + 1]) : a[l];
+  e[0] = *std::min_element(e.begin(), e.end());
+  if (lam_out && std::any_of(a.begin(), a.end(), [](int64_t v) { return v != 0; }))
+    return ctx->fail(MLQMC_EINVAL, "lam_out needs every level to start at point 0");
+  int64_t ymax = 1;
+  for (int l = 0; l < nl; ++l)
+    ymax = std::max<int64_t>(ymax, (int64_t)R * (N[l] - e[l]) * std::max(1, (int)lv[l].s_fine));
   hipStream_t st = ctx->stream;
   const int dev = o->io_on_device;
   double *dQ, *dQh, *dV, *dest, *dlo = nullptr;
@@ -1393,107 +1408,123 @@ mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level
   const double* dsh;
   CS(stage_in(ctx, "e_z", z, s_max, 0, &dz));
   CS(stage_in(ctx, "e_sh", shifts, (size_t)R * s_max, 0, &dsh));
-  const int64_t N0 = N[0], B0 = (int64_t)R * N0;
+  const int64_t N0 = N[0], c0 = e[0], n0pts = N0 - c0, B0 = (int64_t)R * n0pts;
   const int n0 = L0.n_fine, s0 = L0.s_fine;
   const int64_t D0 = (int64_t)(n0 - 1) * (n0 - 1);
-  double *Y, *lam0, *u0 = nullptr;
+  double *Y, *lam0 = nullptr, *u0 = nullptr;
   int *rqi, *lini;
   uint8_t* fl;
+  const int64_t Bmax = std::max<int64_t>(B0, 1);
   CS(ctx->getT("n_Y", (size_t)ymax, &Y));
-  CS(ctx->getT("n_lam0", B0, &lam0));
-  if (nl > 1) CS(ctx->getT("n_u0", (size_t)(B0 * D0), &u0));
-  CS(ctx->getT("n_rq", B0, &rqi));
-  CS(ctx->getT("n_li", B0, &lini));
-  CS(ctx->getT("n_fl", B0, &fl));
-  if (dG) CS(ctx->getT("n_g0", B0, &g0));
+  CS(ctx->getT("n_lam0", Bmax, &lam0));
+  if (nl > 1) CS(ctx->getT("n_u0", (size_t)(Bmax * D0), &u0));
+  CS(ctx->getT("n_rq", Bmax, &rqi));
+  CS(ctx->getT("n_li", Bmax, &lini));
+  CS(ctx->getT("n_fl", Bmax, &fl));
+  if (dG) CS(ctx->getT("n_g0", Bmax, &g0));
   bool flagged = false;
-  // level 0: direct eigenpairs of all N_0 points of every shift; the
-  // eigenvectors are the coarse pairs of the levels above
-  CK(hipMemsetAsync(fl, 0, B0, st), "memset");
-  CK(hipMemsetAsync(lini, 0, B0 * sizeof(int), st), "memset");
-  CK(launch_lattice_embedded(N0, s0, R, dz, dsh, s_max, 0, N0, Y, std::max(s0, 1), st),
-     "lattice");
-  {
+  // level 0: direct eigenpairs of its points; the eigenvectors are the
+  // coarse pairs of the levels above
+  if (B0 > 0) {
+    CK(hipMemsetAsync(fl, 0, B0, st), "memset");
+    CK(hipMemsetAsync(lini, 0, B0 * sizeof(int), st), "memset");
+    CK(launch_lattice_embedded(N0, s0, R, dz, dsh, s_max, c0, n0pts, Y, std::max(s0, 1), st),
+       "lattice");
     Table* tb = nullptr;
     CS(ctx->table(n0, s0, &tb));
-    const int chain = shift_chain(N0, R, o, n0);
-    RqiArgs a = rqi_base(ctx, o, B0, Y, std::max(s0, 1), chain, 1, rqi, lini, fl);
-    a.S = s0;
-    a.phi = tb->pad;
-    a.rphi = tb->rpad;
-    a.lam = lam0;
-    a.u_out = u0;
-    a.g_out = g0;
-    a.refine = ctx->islands ? 1 : 0;  // the coarse pairs of every level above
+    // a power of two dividing the points per shift: no chain crosses shifts
+    int chain = shift_chain(n0pts, R, o, n0);
+    while (n0pts % chain) chain /= 2;
+    RqiArgs ra = rqi_base(ctx, o, B0, Y, std::max(s0, 1), chain, 1, rqi, lini, fl);
+    ra.S = s0;
+    ra.phi = tb->pad;
+    ra.rphi = tb->rpad;
+    ra.lam = lam0;
+    ra.u_out = u0;
+    ra.g_out = g0;
+    ra.refine = ctx->islands ? 1 : 0;  // the coarse pairs of every level above
     if (const int64_t per = rqi_scratch_doubles(n0)) {
-      a.scratch_doubles = per * ((B0 + chain - 1) / chain);
-      CS(ctx->getT("rqi_scratch", a.scratch_doubles, &a.scratch));
+      ra.scratch_doubles = per * ((B0 + chain - 1) / chain);
+      CS(ctx->getT("rqi_scratch", ra.scratch_doubles, &ra.scratch));
     }
     ctx->t_begin(MLQMC_K_COARSE);
-    CK(launch_rqi(n0, a, st), "eigensolve (LDS)");
+    CK(launch_rqi(n0, ra, st), "eigensolve (LDS)");
     ctx->t_end(MLQMC_K_COARSE, 0.0);
   }
-  CK(launch_level_sums(N0, R, lam0, nullptr, dQ, st), "level sums");
-  if (dG) CK(launch_level_sums(N0, R, g0, nullptr, dG, st), "level sums");
+  CK(launch_level_sums_acc(N0 - a[0], N0, R, lam0, n0pts, a[0] - c0, nullptr, 0, 0, dsum, dQ, st),
+     "level sums");
+  if (dG)
+    CK(launch_level_sums_acc(N0 - a[0], N0, R, g0, n0pts, a[0] - c0, nullptr, 0, 0, dgsum, dG,
+                             st),
+       "level sums");
   if (dlo) CK(hipMemcpyAsync(dlo, lam0, B0 * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
-  {
+  if (B0 > 0) {
     bool any = false;
     CS(any_flag(ctx, fl, B0, &any));
     flagged |= any;
   }
   // levels l >= 1: the two-grid update from the level-0 pair of the same
-  // point (the first N_l points of each shift), minus level l-1's value there
+  // point, minus level l-1's value there
   const double* prev = lam0;
   const double* gprev = g0;
-  int64_t Nprev = N0, off = B0;
-  // the first Nl of every shift's Ncur entries (rows of `width` elements)
-  auto leading = [&](const double* src, int64_t Ncur, int64_t Nl, int64_t width,
-                     const char* name, const double** out) -> mlqmc_status {
-    if (Nl == Ncur) {
+  int64_t prev_lo = c0, prev_cnt = n0pts, off = B0;
+  // rows [lo - c0, lo - c0 + cnt) of every shift's n0pts rows of `width`
+  // elements of a level-0 array
+  auto rows0 = [&](const double* src, int64_t lo, int64_t cnt, int64_t width, const char* name,
+                   const double** out) -> mlqmc_status {
+    if (lo == c0 && cnt == n0pts) {
       *out = src;
       return MLQMC_OK;
     }
     double* dst = nullptr;
-    CS(ctx->getT(name, (size_t)(R * Nl * width), &dst));
-    CK(hipMemcpy2DAsync(dst, Nl * width * sizeof(double), src, Ncur * width * sizeof(double),
-                        Nl * width * sizeof(double), R, hipMemcpyDeviceToDevice, st),
+    CS(ctx->getT(name, (size_t)(R * cnt * width), &dst));
+    CK(hipMemcpy2DAsync(dst, cnt * width * sizeof(double), src + (lo - c0) * width,
+                        n0pts * width * sizeof(double), cnt * width * sizeof(double), R,
+                        hipMemcpyDeviceToDevice, st),
        "gather");
     *out = dst;
     return MLQMC_OK;
   };
   for (int l = 1; l < nl; ++l) {
     const mlqmc_level& L = lv[l];
-    const int64_t Nl = N[l], Bl = (int64_t)R * Nl;
+    const int64_t cnt = N[l] - e[l], Bl = (int64_t)R * cnt;
     const int sl = L.s_fine;
-    const double *uH, *lamH, *lamP;
     double* lam = nullptr;
-    CS(ctx->getT((l & 1) ? "n_lamA" : "n_lamB", Bl, &lam));
-    CS(leading(u0, N0, Nl, D0, "n_uH", &uH));
-    CS(leading(lam0, N0, Nl, 1, "n_lamH", &lamH));
-    CS(leading(prev, Nprev, Nl, 1, "n_lamP", &lamP));
     double* gl = nullptr;
-    const double* gP = nullptr;
-    if (dG) {
-      CS(ctx->getT((l & 1) ? "n_gA" : "n_gB", Bl, &gl));
-      CS(leading(gprev, Nprev, Nl, 1, "n_gP", &gP));
+    CS(ctx->getT((l & 1) ? "n_lamA" : "n_lamB", std::max<int64_t>(Bl, 1), &lam));
+    if (dG) CS(ctx->getT((l & 1) ? "n_gA" : "n_gB", std::max<int64_t>(Bl, 1), &gl));
+    if (Bl > 0) {
+      const double *uH, *lamH;
+      CS(rows0(u0, e[l], cnt, D0, "n_uH", &uH));
+      CS(rows0(lam0, e[l], cnt, 1, "n_lamH", &lamH));
+      CK(launch_lattice_embedded(N0, sl, R, dz, dsh, s_max, e[l], cnt, Y, std::max(sl, 1), st),
+         "lattice");
+      CK(hipMemsetAsync(fl, 0, Bl, st), "memset");
+      CK(hipMemsetAsync(lini, 0, Bl * sizeof(int), st), "memset");
+      CS(fine_update(ctx, o, L.n_fine, sl, Y, std::max(sl, 1), uH, lamH, n0, Bl, lam, gl, lini,
+                     fl, "f_"));
     }
-    CK(launch_lattice_embedded(N0, sl, R, dz, dsh, s_max, 0, Nl, Y, std::max(sl, 1), st),
-       "lattice");
-    CK(hipMemsetAsync(fl, 0, Bl, st), "memset");
-    CK(hipMemsetAsync(lini, 0, Bl * sizeof(int), st), "memset");
-    CS(fine_update(ctx, o, L.n_fine, sl, Y, std::max(sl, 1), uH, lamH, n0, Bl, lam, gl, lini,
-                   fl, "f_"));
-    CK(launch_level_sums(Nl, R, lam, lamP, dQ + (int64_t)l * R, st), "level sums");
-    if (dG) CK(launch_level_sums(Nl, R, gl, gP, dG + (int64_t)l * R, st), "level sums");
-    if (dlo)
+    // Y_l over the new points [a_l, N_l): lambda^l at offset a_l - e_l of its
+    // rows, lambda^{l-1} at a_l - e_{l-1} of level l-1's
+    CK(launch_level_sums_acc(N[l] - a[l], N[l], R, lam, cnt, a[l] - e[l], prev, prev_cnt,
+                             a[l] - prev_lo, dsum + (int64_t)l * R, dQ + (int64_t)l * R, st),
+       "level sums");
+    if (dG)
+      CK(launch_level_sums_acc(N[l] - a[l], N[l], R, gl, cnt, a[l] - e[l], gprev, prev_cnt,
+                               a[l] - prev_lo, dgsum + (int64_t)l * R, dG + (int64_t)l * R, st),
+         "level sums");
+    if (dlo && Bl > 0)
       CK(hipMemcpyAsync(dlo + off, lam, Bl * sizeof(double), hipMemcpyDeviceToDevice, st),
          "copy");
-    bool any = false;
-    CS(any_flag(ctx, fl, Bl, &any));
-    flagged |= any;
+    if (Bl > 0) {
+      bool any = false;
+      CS(any_flag(ctx, fl, Bl, &any));
+      flagged |= any;
+    }
     prev = lam;
     gprev = gl;
-    Nprev = Nl;
+    prev_lo = e[l];
+    prev_cnt = cnt;
     off += Bl;
   }
   CK(launch_estimator_final(nl, R, dQ, dQh, dV, dest, 1, st), "estimator");
@@ -1509,6 +1540,68 @@ mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level
   if (dG) CS(stage_out(ctx, g_stats, dG, gsz, dev));
   CS(ctx->sync("estimate_nested"));
   return flagged ? ctx->fail(MLQMC_ENOCONV, "at least one sample is flagged") : MLQMC_OK;
+}
+}  // namespace
+
+mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv,
+                                   const int64_t* N, int32_t R, const int64_t* z,
+                                   const double* shifts, const mlqmc_opts* o, double* Q_lr,
+                                   double* Qhat, double* V, double* est, double* lam_out,
+                                   double* g_stats) {
+  if (!ctx) return MLQMC_EINVAL;
+  CS(check_opts(ctx, o));
+  if (nl < 1 || !lv || !N || !z || !shifts || R < 1)
+    return ctx->fail(MLQMC_EINVAL, "need n_levels >= 1, R >= 1 and non-NULL inputs");
+  if (!Q_lr || !Qhat || !V || !est) return ctx->fail(MLQMC_EINVAL, "NULL output");
+  ctx->mem_cap = o->device_mem_cap;
+  CK(hipSetDevice(ctx->device), "set device");
+  double *dsum = nullptr, *dgsum = nullptr;
+  CS(ctx->getT("e_sum", (size_t)nl * R, &dsum));
+  CK(hipMemsetAsync(dsum, 0, (size_t)nl * R * sizeof(double), ctx->stream), "memset");
+  if (g_stats) {
+    CS(ctx->getT("e_gsum", (size_t)nl * R, &dgsum));
+    CK(hipMemsetAsync(dgsum, 0, (size_t)nl * R * sizeof(double), ctx->stream), "memset");
+  }
+  return nested_core(ctx, nl, lv, nullptr, N, R, z, shifts, o, dsum, dgsum, Q_lr, Qhat, V, est,
+                     lam_out, g_stats);
+}
+
+mlqmc_status mlqmc_estimate_nested_extend(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv,
+                                          const int64_t* N_done, const int64_t* N, int32_t R,
+                                          const int64_t* z, const double* shifts,
+                                          const mlqmc_opts* o, double* sums, double* Q_lr,
+                                          double* Qhat, double* V, double* est, double* g_sums,
+                                          double* g_stats) {
+  if (!ctx) return MLQMC_EINVAL;
+  CS(check_opts(ctx, o));
+  if (nl < 1 || !lv || !N || !N_done || !z || !shifts || R < 1 || !sums)
+    return ctx->fail(MLQMC_EINVAL, "need n_levels >= 1, R >= 1 and non-NULL inputs");
+  if (!Q_lr || !Qhat || !V || !est) return ctx->fail(MLQMC_EINVAL, "NULL output");
+  if ((g_sums == nullptr) != (g_stats == nullptr))
+    return ctx->fail(MLQMC_EINVAL, "g_sums and g_stats go together");
+  ctx->mem_cap = o->device_mem_cap;
+  CK(hipSetDevice(ctx->device), "set device");
+  const int dev = o->io_on_device;
+  const size_t n = (size_t)nl * R;
+  const hipMemcpyKind in = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const hipMemcpyKind back = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  double *dsum = nullptr, *dgsum = nullptr;
+  // private copies: on an error the caller's sums stay as they were
+  CS(ctx->getT("e_sum", n, &dsum));
+  CK(hipMemcpyAsync(dsum, sums, n * sizeof(double), in, ctx->stream), "copy in");
+  if (g_sums) {
+    CS(ctx->getT("e_gsum", n, &dgsum));
+    CK(hipMemcpyAsync(dgsum, g_sums, n * sizeof(double), in, ctx->stream), "copy in");
+  }
+  const mlqmc_status stc = nested_core(ctx, nl, lv, N_done, N, R, z, shifts, o, dsum, dgsum,
+                                       Q_lr, Qhat, V, est, nullptr, g_stats);
+  if (stc != MLQMC_OK && stc != MLQMC_ENOCONV) return stc;
+  const std::string msg = ctx->err;
+  CK(hipMemcpyAsync(sums, dsum, n * sizeof(double), back, ctx->stream), "copy out");
+  if (g_sums) CK(hipMemcpyAsync(g_sums, dgsum, n * sizeof(double), back, ctx->stream), "copy out");
+  CS(ctx->sync("estimate_nested_extend"));
+  if (stc == MLQMC_ENOCONV) ctx->err = msg;
+  return stc;
 }
 
 mlqmc_status mlqmc_set_tuning(mlqmc_ctx* ctx, int32_t n_fine, int32_t prec,

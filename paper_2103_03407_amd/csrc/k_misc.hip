@@ -294,6 +294,32 @@ __global__ __launch_bounds__(256) void k_level_sums(int64_t N, const double* __r
   if (threadIdx.x == 0) Q[r] = s[0] / (double)N;
 }
 
+// Running sums of an extensible estimate: for shift r = blockIdx.x,
+// sums[r] += sum_{i < count} (lam[r ld + off + i] - lam_prev[r ldp + offp + i])
+// (the same fixed-order tree as k_level_sums) and Q[r] = sums[r] / N.
+__global__ __launch_bounds__(256) void k_level_sums_acc(int64_t count, int64_t N,
+                                                        const double* __restrict__ lam,
+                                                        int64_t ld, int64_t off,
+                                                        const double* __restrict__ lam_prev,
+                                                        int64_t ldp, int64_t offp,
+                                                        double* __restrict__ sums,
+                                                        double* __restrict__ Q) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  double s[1] = {0.0};
+  if (count > 0) {
+    const double* a = lam + (int64_t)r * ld + off;
+    const double* p = lam_prev ? lam_prev + (int64_t)r * ldp + offp : nullptr;
+    for (int64_t k = threadIdx.x; k < count; k += 256) s[0] += a[k] - (p ? p[k] : 0.0);
+  }
+  block_sums<256, 1>(s, red);
+  if (threadIdx.x == 0) {
+    const double t = sums[r] + s[0];
+    sums[r] = t;
+    Q[r] = t / (double)N;
+  }
+}
+
 // Qhat_l, V_l (eq. sample_var) and Q^ML = sum_l Qhat_l; est[1] = sum_l V_l, or
 // with shared = 1 (one set of shifts for all levels) the sample variance of
 // the per-shift totals sum_l Q_l^(r)
@@ -448,6 +474,14 @@ hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t l
 hipError_t launch_level_sums(int64_t N, int R, const double* lam, const double* lam_prev,
                              double* Q, hipStream_t st) {
   hipLaunchKernelGGL(k_level_sums, dim3(R), dim3(256), 0, st, N, lam, lam_prev, Q);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_sums_acc(int64_t count, int64_t N, int R, const double* lam, int64_t ld,
+                                 int64_t off, const double* lam_prev, int64_t ldp, int64_t offp,
+                                 double* sums, double* Q, hipStream_t st) {
+  hipLaunchKernelGGL(k_level_sums_acc, dim3(R), dim3(256), 0, st, count, N, lam, ld, off,
+                     lam_prev, ldp, offp, sums, Q);
   return hipGetLastError();
 }
 

@@ -194,6 +194,11 @@ hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t l
 // lam_prev may be nullptr (lambda^{-1} = 0)
 hipError_t launch_level_sums(int64_t N, int R, const double* lam, const double* lam_prev,
                              double* Q, hipStream_t st);
+// sums[r] += sum_{i<count} (lam[r*ld + off + i] - lam_prev[r*ldp + offp + i]),
+// Q[r] = sums[r] / N, r < R (lam_prev may be nullptr; the same tree as above)
+hipError_t launch_level_sums_acc(int64_t count, int64_t N, int R, const double* lam, int64_t ld,
+                                 int64_t off, const double* lam_prev, int64_t ldp, int64_t offp,
+                                 double* sums, double* Q, hipStream_t st);
 // Qhat, V, est from Q [L x R]; shared = 1: est[1] is the variance of the
 // per-shift totals (one set of shifts for all levels) instead of sum_l V_l
 hipError_t launch_estimator_final(int L, int R, const double* Q, double* Qhat, double* V,

@@ -126,7 +126,7 @@ def test_nested_rejects_other_level_lists(ctx, case):
         levels[0] = (8, 4, 4, 2, 0, 0)
     else:
         z = z.copy()
-        z[3] = N[0]
+        z[3] = -1
     with pytest.raises(m.MlqmcError) as e:
         ctx.estimate_nested(levels, N, 2, z, shifts)
     assert e.value.code == m.MLQMC_EINVAL
@@ -266,3 +266,93 @@ def test_functional_across_batches(ctx, prec):
     tol = 1e-10 if prec == "fp64" else 1e-7
     for a, b in zip(out[0], out[1]):
         assert np.max(np.abs(a - b) / np.abs(b)) <= tol
+
+
+# ---------------- extensible nested estimates ----------------
+
+def test_unreduced_z_gives_the_same_estimate(ctx):
+    # a rule of N points uses z modulo N: the vector of a larger rule (the one
+    # an estimate will grow to) gives bit-identical results
+    N = [16, 8, 8, 4]
+    levels = [_lv6(l) for l in _small_levels(N)]
+    z = lattice_vector(64, 8)
+    shifts = shifts_for(50, 0, 2, 8)
+    a = ctx.estimate_nested(levels, N, 2, z, shifts)
+    b = ctx.estimate_nested(levels, N, 2, z % N[0], shifts)
+    for x, y in zip(a[1:5], b[1:5]):
+        assert np.array_equal(x, y)
+
+
+def test_extend_from_zero_equals_nested(ctx):
+    N = [16, 8, 8, 4]
+    levels = [_lv6(l) for l in _small_levels(N)]
+    z = lattice_vector(64, 8)
+    shifts = shifts_for(51, 0, 2, 8)
+    ref = ctx.estimate_nested(levels, N, 2, z, shifts)
+    sums = np.zeros((4, 2))
+    got = ctx.estimate_nested_extend(levels, [0, 0, 0, 0], N, 2, z, shifts, sums)
+    assert got[0] == m.MLQMC_OK
+    for x, y in zip(ref[1:5], got[1:5]):
+        assert np.array_equal(x, y)
+    assert np.allclose(sums, ref[1] * np.array(N)[:, None], rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("path", [[[8, 4, 4, 2]], [[16, 4, 4, 1]], [[4, 2, 2, 1], [8, 8, 4, 2]]])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_extend_in_steps(ctx, fam, path, prec, tol):
+    # grow to N in steps (including a level whose block is empty and
+    # uneven starting points): the same estimate as one call and as the
+    # oracle at N.  Against the one call the bar is the parity bar, not
+    # rounding: other batch sizes change the warm-start chains of level 0 and
+    # the strip order of the batched level's dot products
+    N = [16, 8, 8, 4]
+    levels = _small_levels(N)
+    l6 = [_lv6(l) for l in levels]
+    z = lattice_vector(64, 8)
+    R = 2
+    shifts = shifts_for(52, 0, R, 8)
+    o = m.default_opts(prec=m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED)
+    one = ctx.estimate_nested(l6, N, R, z, shifts, opts=o)
+    sums = np.zeros((4, R))
+    done = [0, 0, 0, 0]
+    for step in path + [N]:
+        st, Q, Qh, V, est = ctx.estimate_nested_extend(l6, done, step, R, z, shifts, sums,
+                                                       opts=o)
+        assert st == m.MLQMC_OK
+        done = step
+    scale = one[2][0]
+    assert np.max(np.abs(Q - one[1])) <= 2 * tol * scale
+    assert abs(est[0] - one[4][0]) <= 4 * tol * scale
+    assert np.allclose(Q, sums / np.array(N)[:, None], rtol=1e-15, atol=0)
+    ref = mlqmc.estimate_nested(levels, z, N, shifts, fam)
+    assert np.max(np.abs(Q - ref.Q_lr)) <= 4 * tol * scale
+    assert abs(est[0] - ref.Q_ml) <= 4 * tol * scale
+
+
+def test_extend_functional(ctx):
+    N = [16, 8, 8, 4]
+    l6 = [_lv6(l) for l in _small_levels(N)]
+    z = lattice_vector(64, 8)
+    shifts = shifts_for(53, 0, 2, 8)
+    one = ctx.estimate_nested(l6, N, 2, z, shifts, functional=True)
+    sums, gs = np.zeros((4, 2)), np.zeros((4, 2))
+    ctx.estimate_nested_extend(l6, [0] * 4, [8, 4, 4, 2], 2, z, shifts, sums, g_sums=gs)
+    out = ctx.estimate_nested_extend(l6, [8, 4, 4, 2], N, 2, z, shifts, sums, g_sums=gs)
+    Gq, Gqh, GV, Gest = out[5]
+    assert np.max(np.abs(Gq - one[6][0])) <= 2e-9
+    assert abs(Gest[0] - one[6][3][0]) <= 4e-9
+    assert np.allclose(Gq, gs / np.array(N)[:, None], rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("case", ["done_above_N", "done_negative"])
+def test_extend_rejects(ctx, case):
+    N = [8, 4, 4, 2]
+    l6 = [_lv6(l) for l in _small_levels(N)]
+    done = [0, 8, 0, 0] if case == "done_above_N" else [0, -1, 0, 0]
+    sums = np.full((4, 2), 7.0)
+    with pytest.raises(m.MlqmcError) as e:
+        ctx.estimate_nested_extend(l6, done, N, 2, lattice_vector(64, 8), shifts_for(54, 0, 2, 8),
+                                   sums)
+    assert e.value.code == m.MLQMC_EINVAL
+    assert np.all(sums == 7.0)  # unchanged on an error
+

@@ -17,7 +17,10 @@ eq. sample_var, eq. mlqmc_R, eq. ml-var, Algorithm 2).
   terms telescope to the finest two-grid value point by point, its values
   are those of Algorithm 2's level evaluation at the same points, and the
   variance of the per-shift totals is at most the number of levels times
-  sum_l V_l (Cauchy-Schwarz: the factor the paper states for shared shifts).
+  sum_l V_l (Cauchy-Schwarz: the factor the paper states for shared shifts);
+* extensible nested estimates: a point of the embedded rule does not depend on
+  the rule's size (or on z being reduced modulo it), and level sums over
+  disjoint blocks of points add up to the one-shot sums, N_l Q_l^(r).
 """
 
 import cmath
@@ -259,3 +262,39 @@ def test_nested_estimate_level_means_use_the_leading_points():
         for l in range(3):
             want = np.mean([mlqmc.level_value(levels[l], pts[k], fam).Y for k in range(N[l])])
             assert abs(est.Q_lr[l, r] - want) < 1e-12 * max(abs(want), 1.0)
+
+
+def test_embedded_points_do_not_depend_on_the_rule_size():
+    # the property that makes a nested estimate extensible: point k of the
+    # embedded rule is the same for every rule of more than k points, with z
+    # reduced modulo the rule size or not
+    z = lattice_vector(1024, 8)
+    sh = shifts_for(41, 0, 1, 8)[0]
+    for N in (8, 32, 128):
+        for k in range(N):
+            a = qmc.embedded_point(z, N, sh, k)
+            assert np.array_equal(a, qmc.embedded_point(z % N, N, sh, k))
+            assert np.array_equal(a, qmc.embedded_point(z, 1024, sh, k))
+
+
+def test_nested_block_sums_add_up_to_the_estimate():
+    # sums over [0, N/2) and [N/2, N) per level give the one-shot level sums,
+    # and those are N_l Q_l^(r) of the nested estimator; a level whose block
+    # is empty adds 0
+    N = [8, 4, 4]
+    levels = _nested_levels(N)
+    z = lattice_vector(64, 8)
+    sh = shifts_for(42, 0, 1, 8)
+    fam = problem1_family(8, 2.0)
+    whole = mlqmc.nested_level_sums(levels, z, [0, 0, 0], N, sh[0], fam)
+    half = [n // 2 for n in N]
+    lo = mlqmc.nested_level_sums(levels, z, [0, 0, 0], half, sh[0], fam)
+    hi = mlqmc.nested_level_sums(levels, z, half, N, sh[0], fam)
+    # 1e-13: the direct eigensolve (ARPACK, random start) is reproducible to
+    # about 1e-15 relative per eigenvalue, not bit for bit
+    for l in range(3):
+        assert abs(lo[l] + hi[l] - whole[l]) <= 1e-13 * max(1.0, abs(whole[l]))
+    est = mlqmc.estimate_nested(levels, z, N, sh, fam)
+    for l in range(3):
+        assert abs(whole[l] / N[l] - est.Q_lr[l, 0]) <= 1e-13 * max(1.0, abs(est.Q_lr[l, 0]))
+    assert mlqmc.nested_level_sums(levels, z, N, N, sh[0], fam) == [0.0, 0.0, 0.0]
