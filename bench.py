@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
 PEAK_FP64_MFMA_TFS = 78.6  # MI355X dense FP64 matrix, published
 PEAK_FP64_VALU_TFS = 78.6  # MI355X FP64 vector, published
+PEAK_FP32_VALU_TFS = 157.3  # MI355X FP32 vector, published
 
 
 def _parse():
@@ -407,15 +408,17 @@ def main():
              "coeff": "k_expand_mfma", "lds": "k_tg_small"}[a.kernel_class]
     roof = None
     if launches > 0 and kms > 0 and a.kernel_class == "lds":
-        # the LDS-resident two-grid update: FP64 vector arithmetic on data in
-        # LDS, so the FP64 vector peak bounds it (HBM traffic is the tables and
-        # points only)
+        # the LDS-resident two-grid update: vector arithmetic on data in LDS,
+        # so the vector peak of its precision bounds it (FP64, or FP32 for
+        # the mixed solve, whose Rayleigh quotients stay FP64); HBM traffic is
+        # the tables and points only
         avg_ms = kms / launches
         flops_per_launch = lds_step_flops(ctx, m, w, opts) * a.steps / launches
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        peak = PEAK_FP64_VALU_TFS if a.prec == "fp64" else PEAK_FP32_VALU_TFS
         roof = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
-                "peak": PEAK_FP64_VALU_TFS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_VALU_TFS, 4), "traffic": None,
+                "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
                 "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
                 "algorithmic_flops_per_launch": flops_per_launch}
     elif launches > 0 and kms > 0 and a.kernel_class == "coeff":

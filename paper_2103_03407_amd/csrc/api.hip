@@ -317,8 +317,6 @@ mlqmc_status check_opts(mlqmc_ctx* ctx, const mlqmc_opts* o) {
   if (o->max_rq_iter < 1 || o->max_lin_iter < 1)
     return ctx->fail(MLQMC_EINVAL, "iteration caps must be >= 1");
   if (o->device_mem_cap < 0) return ctx->fail(MLQMC_EINVAL, "device_mem_cap must be >= 0");
-  if (ctx->islands && o->prec != MLQMC_FP64)
-    return ctx->fail(MLQMC_EINVAL, "the islands family (Problem 2) runs in FP64 only");
   return MLQMC_OK;
 }
 

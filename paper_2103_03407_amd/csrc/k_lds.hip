@@ -76,17 +76,26 @@ __device__ __forceinline__ double sign_share(const T* v, double* red) {
 // Problem 1: w = a0 + sum_{j<S} y_j Phi_j.  Problem 2 (kR): the tables carry
 // the background values as row 0, so s_y = (1, y_1, ..., y_S) weights S + 1
 // rows of both the diffusion table [WX | WY] and the reaction table
-// [RX | RY | RD].
+// [RX | RY | RD]; with FP32 storage the FP64 block goes to w64 (for the
+// Rayleigh quotients) and its rounding to a.wx.
 template <int N, int NT, bool kR, typename T>
 __device__ __forceinline__ void stage_weights(const double* Y, int64_t ldY, int64_t i, int S,
                                               const double* phi, const double* rphi, double a0,
-                                              const lds::PcgArrays<T>& a, double* s_y) {
+                                              const lds::PcgArrays<T>& a, double* s_y,
+                                              double* w64) {
   constexpr int P = lds::Mesh<N>::P;
   if constexpr (kR) {
     for (int j = threadIdx.x; j <= S; j += NT) s_y[j] = j == 0 ? 1.0 : Y[i * ldY + j - 1];
     __syncthreads();
-    lds::weights_from_table<NT, N>(phi, s_y, S + 1, 0.0, a.wx);
-    lds::weights_from_table<NT, N, T, 3>(rphi, s_y, S + 1, 0.0, a.wx + 2 * P);
+    if constexpr (std::is_same_v<T, double>) {
+      lds::weights_from_table<NT, N>(phi, s_y, S + 1, 0.0, a.wx);
+      lds::weights_from_table<NT, N, T, 3>(rphi, s_y, S + 1, 0.0, a.wx + 2 * P);
+    } else {
+      lds::weights_from_table<NT, N>(phi, s_y, S + 1, 0.0, w64);
+      lds::weights_from_table<NT, N, double, 3>(rphi, s_y, S + 1, 0.0, w64 + 2 * P);
+      for (int e = threadIdx.x; e < 5 * P; e += NT) a.wx[e] = (T)w64[e];
+      __syncthreads();
+    }
   } else {
     for (int j = threadIdx.x; j < S; j += NT) s_y[j] = Y[i * ldY + j];
     __syncthreads();
@@ -99,7 +108,7 @@ __device__ __forceinline__ void stage_weights(const double* Y, int64_t ldY, int6
 // (zero padding), the staged point in s_y.
 template <int N, int NT, bool kR = false, typename T, class WF>
 __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* s_y,
-                          const WF& wf) {
+                          const WF& wf, double* w64 = nullptr) {
   using Mh = lds::Mesh<N>;
   constexpr int m = N - 1;
   T* const s_v = a.v;
@@ -107,7 +116,7 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* 
   const int64_t i1 = (i0 + A.chain_len < A.n) ? i0 + A.chain_len : A.n;
   bool have_prev = false;
   for (int64_t i = i0; i < i1; ++i) {
-    stage_weights<N, NT, kR>(A.Y, A.ldY, i, A.S, A.phi, A.rphi, A.a0, a, s_y);
+    stage_weights<N, NT, kR>(A.Y, A.ldY, i, A.S, A.phi, A.rphi, A.a0, a, s_y, w64);
     if (!(A.warm && have_prev)) init_sine<NT, N>(s_v);
 
     double vMv, vAv;
@@ -185,7 +194,8 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* 
 // zeroed once; the solvers write interior positions only.  T = float keeps
 // vectors, weights and V-cycle in FP32 (mixed precision); the Rayleigh
 // quotients then use FP64 weights recomputed from the edge table.
-// With kR (Problem 2, FP64) the weight block also holds the reaction arrays.
+// With kR (Problem 2) the weight block also holds the reaction arrays; with
+// FP32 storage an FP64 copy of it serves the Rayleigh quotients.
 template <int N, int NT, bool kR>
 constexpr int lds_blocks_per_cu(int tsize) {
   return kR ? 1 : ((N >= 32 && tsize == 8) ? 2 : 4);
@@ -199,6 +209,7 @@ __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void
   __shared__ T s_mg[lds::mg_scratch<N, kR>() + 1];
   __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
+  __shared__ double s_w64[(kR && sizeof(T) < 8) ? 5 * P : 1];
   lds::PcgArrays<T> a;
   a.wx = s_w;
   a.wy = s_w + P;
@@ -215,6 +226,8 @@ __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void
   __syncthreads();
   if constexpr (sizeof(T) == 8) {
     rqi_chain<N, NT, kR>(A, a, s_y, lds::WeightsFromArrays<N>{s_w, s_w + P});
+  } else if constexpr (kR) {
+    rqi_chain<N, NT, kR>(A, a, s_y, lds::WeightsFromArrays<N>{s_w64, s_w64 + P}, s_w64);
   } else {
     rqi_chain<N, NT>(A, a, s_y, lds::WeightsFromTable<N>{A.phi, s_y, A.S, A.a0});
   }
@@ -264,6 +277,7 @@ __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void
   __shared__ T s_mg[lds::mg_scratch<N, kR>() + 1];
   __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
+  __shared__ double s_w64[(kR && sizeof(T) < 8) ? 5 * P : 1];
   lds::PcgArrays<T> a;
   a.wx = s_w;
   a.wy = s_w + P;
@@ -279,7 +293,7 @@ __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void
   T* const s_v = a.v;
   const int64_t i = blockIdx.x;
   lds::zero<NT>(s_vec, 5 * P);
-  stage_weights<N, NT, kR>(A.Y, A.ldY, i, A.s, A.phi, A.rphi, A.a0, a, s_y);
+  stage_weights<N, NT, kR>(A.Y, A.ldY, i, A.s, A.phi, A.rphi, A.a0, a, s_y, s_w64);
   const int mH = A.nH - 1, ratio = N / A.nH;
   const double* uH = A.uH + i * (int64_t)(mH * mH);
   LDS_FOR_NODES(NT, N, k) {
@@ -318,6 +332,8 @@ __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void
   };
   if constexpr (sizeof(T) == 8)
     run(lds::WeightsFromArrays<N>{s_w, s_w + P});
+  else if constexpr (kR)
+    run(lds::WeightsFromArrays<N>{s_w64, s_w64 + P});
   else
     run(lds::WeightsFromTable<N>{A.phi, s_y, A.s, A.a0});
 }
@@ -358,8 +374,10 @@ hipError_t rqi_n(const RqiArgs& a, hipStream_t st) {
   if (chains <= 0) return hipSuccess;
   if constexpr (N <= 32) {
     constexpr int NT = threads_for<N>();
-    if (a.rphi) {  // Problem 2: FP64 only
-      if (a.mixed) return hipErrorInvalidValue;
+    if (a.rphi && a.mixed) {  // Problem 2
+      hipLaunchKernelGGL((k_rqi<N, NT, float, true>), dim3((unsigned)chains), dim3(NT), 0, st,
+                         a);
+    } else if (a.rphi) {
       hipLaunchKernelGGL((k_rqi<N, NT, double, true>), dim3((unsigned)chains), dim3(NT), 0, st,
                          a);
     } else if (a.mixed) {
@@ -381,9 +399,11 @@ template <int N>
 hipError_t tg_small_n(const TgSmallArgs& a, hipStream_t st) {
   constexpr int NT = threads_for<N>();
   if (a.n <= 0) return hipSuccess;
-  if (a.rphi) {  // Problem 2: FP64 only
-    if (a.mixed) return hipErrorInvalidValue;
-    constexpr int NTR = threads_for_reaction<N>();
+  constexpr int NTR = threads_for_reaction<N>();
+  if (a.rphi && a.mixed) {  // Problem 2
+    hipLaunchKernelGGL((k_tg_small<N, NTR, float, true>), dim3((unsigned)a.n), dim3(NTR), 0, st,
+                       a);
+  } else if (a.rphi) {
     hipLaunchKernelGGL((k_tg_small<N, NTR, double, true>), dim3((unsigned)a.n), dim3(NTR), 0, st,
                        a);
   } else if (a.mixed) {

@@ -17,7 +17,7 @@ struct RqiArgs {
   double a0;
   const double* rphi;   // Problem 2: reaction table [>=S+1][3 (n+2) n]; then phi and
                         // rphi carry the background values as row 0 and a0 is unused
-                        // (FP64, meshes up to 1/32).  nullptr: Problem 1
+                        // (meshes up to 1/32).  nullptr: Problem 1
   int64_t n;            // samples
   int chain_len;        // samples per warm-start chain (one workgroup per chain)
   int warm;             // 1: start from the previous sample's eigenvector

@@ -61,14 +61,15 @@ constexpr int wblock() {
   return kR ? 5 : 2;
 }
 
-// (A x)_k (plus (R x)_k with kR) with the diagonal in d
-template <int n, typename T, bool kR = false>
-MLQMC_DEV T pA(const T* x, const T* wx, const T* wy, int k, T& d) {
+// (A x)_k (plus (R x)_k with kR) with the diagonal in d, in the weights'
+// type T (x may be stored narrower: FP32 vectors with FP64 weights)
+template <int n, typename T, bool kR = false, typename X>
+MLQMC_DEV T pA(const X* x, const T* wx, const T* wy, int k, T& d) {
   const T ww = wx[k], we = wx[k + 1], ws = wy[k], wn = wy[k + n];
   d = ww + we + ws + wn;
-  const T xc = x[k];
-  T ax = ww * (xc - x[k - 1]) + we * (xc - x[k + 1]) + ws * (xc - x[k - n]) +
-         wn * (xc - x[k + n]);
+  const T xc = (T)x[k];
+  T ax = ww * (xc - (T)x[k - 1]) + we * (xc - (T)x[k + 1]) + ws * (xc - (T)x[k - n]) +
+         wn * (xc - (T)x[k + n]);
   if constexpr (kR) {
     constexpr int P = (n + 1) * n + 1;
     const T* rx = wx + 2 * P;
@@ -77,8 +78,9 @@ MLQMC_DEV T pA(const T* x, const T* wx, const T* wy, int k, T& d) {
     const T hm = (T)(1.0 / (12.0 * n * n));
     const T r1 = rx[k], r2 = rx[k + 1], r3 = ry[k], r4 = ry[k + n], r5 = rd[k],
             r6 = rd[k + n + 1];
-    ax += hm * (r1 * (xc + x[k - 1]) + r2 * (xc + x[k + 1]) + r3 * (xc + x[k - n]) +
-                r4 * (xc + x[k + n]) + r5 * (xc + x[k - n - 1]) + r6 * (xc + x[k + n + 1]));
+    ax += hm * (r1 * (xc + (T)x[k - 1]) + r2 * (xc + (T)x[k + 1]) + r3 * (xc + (T)x[k - n]) +
+                r4 * (xc + (T)x[k + n]) + r5 * (xc + (T)x[k - n - 1]) +
+                r6 * (xc + (T)x[k + n + 1]));
     d += hm * (r1 + r2 + r3 + r4 + r5 + r6);
   }
   return ax;
@@ -328,19 +330,18 @@ struct WeightsFromTable {
 };
 
 // ||x||_M^2 and x^T A x in one pass in FP64 with FP64 weights from wf (all
-// threads get both).  With the reaction term (FP64 storage only) the operator
-// is applied from the arrays in `a` and wf is not used.
+// threads get both).  With the reaction term wf is WeightsFromArrays over the
+// FP64 block [WX | WY | RX | RY | RD] and the stencil runs on it.
 template <int NT, int n, typename T, class WF, bool kR = false>
 MLQMC_DEV void rayleigh_parts(const PcgArrays<T>& a, const T* x, const WF& wf, double& xMx,
                               double& xAx) {
-  static_assert(!kR || sizeof(T) == 8, "the reaction term runs in FP64");
   double s[2] = {0.0, 0.0};
   LDS_FOR_NODES(NT, n, k) {
     const double xc = (double)x[k];
     double ax;
     if constexpr (kR) {
-      T d;
-      ax = (double)pA<n, T, true>(x, a.wx, a.wy, k, d);
+      double d;
+      ax = pA<n, double, true>(x, wf.wx, wf.wy, k, d);
     } else {
       const Wd w = wf(k);
       ax = w.ww * (xc - (double)x[k - 1]) + w.we * (xc - (double)x[k + 1]) +

@@ -2,9 +2,10 @@
 region-wise diffusion a and reaction b), against the FP64 CPU oracle,
 through the C ABI (mlqmc_create_islands).
 
-The family runs in FP64 on meshes 1/8 .. 1/32, every array of a solve in
-LDS.  Tolerances as for Problem 1: eigenvalues relative 1e-10 per sample,
-G(u) relative 1e-9, estimator sums from the per-sample bound.  Both parameter
+The family runs on meshes 1/8 .. 1/32, every array of a solve in LDS, in FP64
+or mixed precision.  Tolerances as for Problem 1: eigenvalues relative 1e-10
+per sample (mixed 1e-8), G(u) relative 1e-9 (mixed 1e-7), estimator sums from
+the per-sample bound.  Both parameter
 sets of the paper's complexity figure are covered: decays (4/3, 2, 4/3, 2)
 and (2, 2, 2, 2) for (a on the islands, a outside, b on the islands, b
 outside).
@@ -161,9 +162,9 @@ def test_nested_estimate(ctx, fam):
 @pytest.mark.parametrize("lv,prec", [((64, 32, 16, 16, 0, 0), m.MLQMC_FP64),
                                      ((4, 4, 0, 0, 0, 0), m.MLQMC_FP64),
                                      ((32, 16, 8, 8, 64, 16), m.MLQMC_FP64),
-                                     ((16, 8, 0, 0, 0, 0), m.MLQMC_MIXED)])
+                                     ((64, 8, 0, 0, 0, 0), m.MLQMC_MIXED)])
 def test_rejected_levels(ctx, lv, prec):
-    # meshes outside 1/8 .. 1/32 and mixed precision are refused on the host
+    # meshes outside 1/8 .. 1/32 are refused on the host
     Y = _points(max(lv[1], 1), 2, 37)
     lam = np.empty(2)
     fl = np.zeros(2, np.uint8)
@@ -245,3 +246,75 @@ def test_cfg8_three_levels_sampled(ctx_p2):
         per_r = Yl.reshape(w.R, lv.N).mean(axis=1)
         assert np.max(np.abs(Q[l] - per_r)) <= 1e-12 * np.max(lam)
     assert abs(est[0] - Qh.sum()) <= 1e-13 * abs(est[0])
+
+
+# ---------------- mixed precision ----------------
+
+def _mixed():
+    return m.default_opts(prec=m.MLQMC_MIXED)
+
+
+@pytest.mark.parametrize("n,s,count", [(8, 8, 9), (16, 16, 8), (32, 64, 7)])
+def test_mixed_direct(ctx, fam, n, s, count):
+    Y = _points(s, count, 60)
+    lam = np.empty(count)
+    fl = np.zeros(count, np.uint8)
+    ctx.eig_level((n, s, 0, 0, 0, 0), Y, lam, fl, opts=_mixed())
+    assert not fl.any(), fl
+    ref = np.array([twogrid.direct(n, s, y, fam)[0] for y in Y])
+    assert _rel(lam, ref) <= 1e-8
+
+
+@pytest.mark.parametrize("lv", [(16, 16, 8, 8, 0, 0), (32, 64, 8, 8, 16, 32),
+                                (32, 32, 8, 16, 8, 16)])
+def test_mixed_two_grid_level(ctx, fam, lv):
+    spec = LevelSpec(*lv, 0)
+    count = 8
+    Y = _points(lv[1], count, 61)
+    lam, lamc, lamp = np.empty(count), np.empty(count), np.empty(count)
+    fl = np.zeros(count, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl, lam_coarse=lamc, lam_prev=lamp if lv[4] else None,
+                  opts=_mixed())
+    assert not fl.any(), fl
+    for k in range(count):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= 1e-8 * v.lam, (k, lam[k], v.lam)
+        assert abs(lamc[k] - v.lam_coarse) <= 1e-8 * v.lam_coarse
+        if lv[4]:
+            assert abs(lamp[k] - v.lam_prev) <= 1e-8 * v.lam_prev
+
+
+def test_mixed_functional(ctx, fam):
+    lv = (32, 32, 8, 16, 16, 16)
+    spec = LevelSpec(*lv, 0)
+    count = 6
+    Y = _points(lv[1], count, 62)
+    lam, lamp, g, gp = (np.empty(count) for _ in range(4))
+    fl = np.zeros(count, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp, g=g, g_prev=gp, opts=_mixed())
+    assert not fl.any(), fl
+    for k in range(count):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(g[k] - v.G) <= 1e-7 * v.G, (k, g[k], v.G)
+        assert abs(gp[k] - v.G_prev) <= 1e-7 * v.G_prev
+
+
+def test_mixed_cfg8_sampled(ctx_p2):
+    # the three-level Problem 2 workload in mixed precision: every level value
+    # unflagged, strided ones within 1e-8 of the oracle
+    w = CONFIGS[8]
+    fam = w.family()
+    for l, lv in enumerate(w.levels):
+        Y = _level_points(ctx_p2, w, l)
+        n = Y.shape[0]
+        lam, lamp = np.empty(n), np.empty(n)
+        fl = np.zeros(n, np.uint8)
+        ctx_p2.eig_level(_lv6(lv), Y, lam, fl, lam_prev=lamp if lv.n_prev else None,
+                         opts=_mixed())
+        assert not fl.any()
+        Yl = lam - lamp if lv.n_prev else lam
+        for i in range(0, n, n // 4 + 11):
+            v = mlqmc.level_value(lv, Y[i], fam)
+            assert abs(lam[i] - v.lam) <= 1e-8 * v.lam, (l, i)
+            assert abs(Yl[i] - v.Y) <= 2e-8 * v.lam, (l, i)
+
