@@ -9,10 +9,12 @@ H = 1/32 -> h = 1/128, s = 64, S = 8, N = 1024 lattice points x R = 8 shifts
 (8192 eigen-samples), all synthetic (CBC lattice, seeded shifts).
 
 ``--cfg`` selects another workload of ``synth/configs.py``: 4 and 6 are the
-five-level estimators (independent and shared shifts), 7 and 8 Problem 2 (the
-islands) as one two-grid level H = 1/8 -> h = 1/32 and as the three-level
-estimator on h = 1/8, 1/16, 1/32; their two-grid updates run in LDS, and the
-roofline is then that kernel's FP64 rate against the FP64 vector peak.
+five-level estimators (independent and shared shifts), 7, 8 and 9 Problem 2
+(the islands) as one two-grid level H = 1/8 -> h = 1/32 and as the three- and
+four-level estimators on h = 1/8 .. 1/32 and 1/8 .. 1/64; their two-grid
+updates run per sample (in LDS, and on 1/64 with the top level in global
+scratch), and the roofline is then those kernels' rate against the vector
+peak of the precision.
 
 Prints one JSON line.  ``value`` = eigen-samples per second on one GPU.
 """
@@ -301,8 +303,8 @@ def lds_step_flops(ctx, m, w, opts):
         if lv.n_prev and not (lv.n_prev == lv.n_coarse and lv.s_prev == lv.s_coarse):
             updates.append((lv.n_prev, lv.s_prev))
         for nm, sm in updates:
-            if nm > 32:
-                continue
+            if nm > 32 and not (reaction and nm == 64):
+                continue  # the batched kernels: not this kernel class
             li = np.zeros(n, np.int32)
             ctx.eig_level((nm, sm, lv.n_coarse, lv.s_coarse, 0, 0),
                           np.ascontiguousarray(Y[:, :sm]), lam, fl, lin_iters=li, opts=opts)
@@ -387,8 +389,8 @@ def main():
     for _ in range(a.warmup):
         step()
     if a.kernel_class is None:
-        lds_only = all(lv.n_fine <= 32 for lv in w.levels) and any(lv.n_coarse for lv in w.levels)
-        a.kernel_class = "lds" if lds_only else "post"
+        per_sample = all(lv.n_fine <= (64 if w.problem == 2 else 32) for lv in w.levels)
+        a.kernel_class = "lds" if per_sample and any(lv.n_coarse for lv in w.levels) else "post"
     kcls = {"post": m.K_SMOOTH, "pre": m.K_PRE, "apply": m.K_APPLY,
             "coeff": m.K_COEFF, "lds": m.K_TG_LDS}[a.kernel_class]
     ctx.set_timing(kcls)
@@ -406,6 +408,8 @@ def main():
 
     kname = {"post": "k_post", "pre": "k_pre", "apply": "k_pupdate_apply",
              "coeff": "k_expand_mfma", "lds": "k_tg_small"}[a.kernel_class]
+    if a.kernel_class == "lds" and any(lv.n_fine > 32 for lv in w.levels):
+        kname = "k_tg_small+k_tg_global"
     roof = None
     if launches > 0 and kms > 0 and a.kernel_class == "lds":
         # the LDS-resident two-grid update: vector arithmetic on data in LDS,

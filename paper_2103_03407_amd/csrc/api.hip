@@ -321,8 +321,23 @@ mlqmc_status check_opts(mlqmc_ctx* ctx, const mlqmc_opts* o) {
 }
 
 // Problem 2 meshes: multiples of 1/8 (the islands' edges are mesh lines) up
-// to 1/32 (every array of a solve in LDS); 0 = not used
-bool islands_mesh_ok(int n) { return n == 0 || (n >= 8 && n <= 32); }
+// to 1/64 (every array of a solve in LDS up to 1/32; the two-grid update on
+// 1/64 keeps its top level in global scratch); 0 = not used
+bool islands_mesh_ok(int n) { return n == 0 || (n >= 8 && n <= 64); }
+
+// Problem 2 on 1/64 runs in FP64, and only as a two-grid fine or previous
+// mesh (the eigensolves stay at 1/32 or coarser)
+mlqmc_status check_islands_level(mlqmc_ctx* ctx, const mlqmc_level* l, const mlqmc_opts* o) {
+  if (!ctx->islands) return MLQMC_OK;
+  const bool has64 = l->n_fine == 64 || l->n_prev == 64;
+  if (has64 && o->prec != MLQMC_FP64)
+    return ctx->fail(MLQMC_EINVAL, "the islands family on 1/64 runs in FP64 only");
+  if (l->n_coarse == 0 && (l->n_fine > 32 || l->n_prev > 32))
+    return ctx->fail(MLQMC_EINVAL, "islands direct levels need meshes up to 1/32");
+  if (l->n_coarse > 32)
+    return ctx->fail(MLQMC_EINVAL, "islands coarse meshes go up to 1/32");
+  return MLQMC_OK;
+}
 
 mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
   if (!l) return ctx->fail(MLQMC_EINVAL, "level is NULL");
@@ -356,7 +371,7 @@ mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
   if (ctx->islands &&
       !(islands_mesh_ok(l->n_fine) && islands_mesh_ok(l->n_coarse) && islands_mesh_ok(l->n_prev)))
     return ctx->fail(MLQMC_EINVAL,
-                     "the islands family (Problem 2) needs meshes 1/8 .. 1/32 (got %d, %d, %d)",
+                     "the islands family (Problem 2) needs meshes 1/8 .. 1/64 (got %d, %d, %d)",
                      l->n_fine, l->n_coarse, l->n_prev);
   return MLQMC_OK;
 }
@@ -705,7 +720,7 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
   mlqmc_opts og = *o;
   if (g) og.lam_rtol = -1.0;
   o = &og;
-  if (nh <= 32) {
+  if (nh <= 32 || ctx->islands) {
     Table* tb = nullptr;
     CS(ctx->table(nh, s, &tb));
     TgSmallArgs a{};
@@ -727,6 +742,30 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
     a.g = g;
     a.lin_iters = lin_iters;
     a.flags = flags;
+    if (const int64_t per = tg_scratch_doubles(nh)) {
+      // Problem 2 on 1/64: the top level of each sample in a scratch slice,
+      // in chunks of samples so the scratch stays bounded (1.5 GB)
+      constexpr int64_t kChunk = 4096;
+      const int64_t chunk = std::min<int64_t>(n, kChunk);
+      CS(ctx->getT("tg_scratch", (size_t)(chunk * per), &a.scratch));
+      a.scratch_doubles = chunk * per;
+      const int64_t DH = (int64_t)(nH - 1) * (nH - 1);
+      for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+        TgSmallArgs b = a;
+        b.n = std::min(chunk, n - c0);
+        b.Y = Y + c0 * ldY;
+        b.uH = uH + c0 * DH;
+        b.lamH = lamH + c0;
+        b.lam = lam + c0;
+        b.g = g ? g + c0 : nullptr;
+        b.lin_iters = lin_iters ? lin_iters + c0 : nullptr;
+        b.flags = flags + c0;
+        ctx->t_begin(MLQMC_K_TG_LDS);
+        CK(launch_tg_small(nh, b, ctx->stream), "two-grid (global scratch)");
+        ctx->t_end(MLQMC_K_TG_LDS, 0.0);
+      }
+      return MLQMC_OK;
+    }
     ctx->t_begin(MLQMC_K_TG_LDS);
     CK(launch_tg_small(nh, a, ctx->stream), "two-grid (LDS)");
     ctx->t_end(MLQMC_K_TG_LDS, 0.0);
@@ -1209,6 +1248,7 @@ mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_o
   if (!ctx) return MLQMC_EINVAL;
   CS(check_opts(ctx, o));
   CS(check_level(ctx, L));
+  CS(check_islands_level(ctx, L, o));
   if (n < 0) return ctx->fail(MLQMC_EINVAL, "n < 0");
   if (n > 0 && (!Y || !lam || !flags)) return ctx->fail(MLQMC_EINVAL, "NULL buffer");
   if (n > 0 && L->n_prev && !lam_prev) return ctx->fail(MLQMC_EINVAL, "lam_prev is NULL but n_prev > 0");
@@ -1260,6 +1300,7 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
   int64_t zoff = 0, soff = 0;
   for (int l = 0; l < nl; ++l) {
     CS(check_level(ctx, &lv[l]));
+    CS(check_islands_level(ctx, &lv[l], o));
     if (!is_pow2(N[l]) || N[l] > ((int64_t)1 << 30))
       return ctx->fail(MLQMC_EINVAL, "N[%d] must be a power of two <= 2^30", l);
     const int s = lv[l].s_fine;
@@ -1355,6 +1396,7 @@ mlqmc_status nested_core(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, cons
   std::vector<int64_t> a(nl), e(nl);
   for (int l = 0; l < nl; ++l) {
     CS(check_level(ctx, &lv[l]));
+    CS(check_islands_level(ctx, &lv[l], o));
     if (!is_pow2(N[l]) || N[l] > ((int64_t)1 << 30))
       return ctx->fail(MLQMC_EINVAL, "N[%d] must be a power of two <= 2^30", l);
     if (l > 0 && N[l] > N[l - 1])

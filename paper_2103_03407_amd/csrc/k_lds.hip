@@ -233,23 +233,23 @@ __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void
   }
 }
 
-// Meshes whose vectors exceed LDS (1/64): the top-level weights, the five
-// PCG vectors and the smoother's second array live in the chain's slice of a
-// global scratch buffer (L2/MALL resident while the chain runs); the levels
-// below stay in LDS.
-template <int N>
-constexpr int64_t rqi_global_doubles() {
-  return (int64_t)lds::Mesh<N>::EW + 6 * (int64_t)lds::Mesh<N>::P;
+// Meshes whose vectors exceed LDS (1/64): the top-level weights (with the
+// reaction arrays for Problem 2), the five PCG vectors and the smoother's
+// second array live in the workgroup's slice of a global scratch buffer
+// (L2/MALL resident while it runs); the levels below stay in LDS.
+template <int N, bool kR = false>
+constexpr int64_t global_doubles() {
+  return (int64_t)lds::wblock<kR>() * lds::Mesh<N>::P + 6 * (int64_t)lds::Mesh<N>::P;
 }
-template <int N, int NT>
+template <int N, int NT, bool kR = false>
 __global__ __launch_bounds__(NT) void k_rqi_global(RqiArgs A) {
   using Mh = lds::Mesh<N>;
   constexpr int P = Mh::P;
-  __shared__ double s_mg[lds::mg_scratch<N>() + 1];
+  __shared__ double s_mg[lds::mg_scratch<N, kR>() + 1];
   __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
-  double* g = A.scratch + (int64_t)blockIdx.x * rqi_global_doubles<N>();
-  double* vec = g + Mh::EW;
+  double* g = A.scratch + (int64_t)blockIdx.x * global_doubles<N, kR>();
+  double* vec = g + lds::wblock<kR>() * P;
   lds::PcgArrays<double> a;
   a.wx = g;
   a.wy = g + P;
@@ -264,36 +264,19 @@ __global__ __launch_bounds__(NT) void k_rqi_global(RqiArgs A) {
   a.red = s_red;
   lds::zero<NT>(vec, 6 * P);
   __syncthreads();
-  rqi_chain<N, NT>(A, a, s_y, lds::WeightsFromArrays<N>{g, g + P});
+  rqi_chain<N, NT, kR>(A, a, s_y, lds::WeightsFromArrays<N>{g, g + P});
 }
 
-template <int N, int NT, typename T, bool kR = false>
-__global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void k_tg_small(
-    TgSmallArgs A) {
+// Two-grid update of sample i from its coarse pair: arrays in `a` (zero
+// padding), the staged point in s_y (w64: the FP64 weight block of FP32
+// storage with the reaction term).
+template <int N, int NT, bool kR, typename T>
+__device__ void tg_sample(const TgSmallArgs& A, const lds::PcgArrays<T>& a, double* s_y,
+                          double* w64, int64_t i) {
   using Mh = lds::Mesh<N>;
   constexpr int P = Mh::P;
-  __shared__ T s_w[lds::wblock<kR>() * P];
-  __shared__ T s_vec[5 * P];
-  __shared__ T s_mg[lds::mg_scratch<N, kR>() + 1];
-  __shared__ double s_red[6 * (NT / 64)];
-  __shared__ double s_y[kMaxStagedS];
-  __shared__ double s_w64[(kR && sizeof(T) < 8) ? 5 * P : 1];
-  lds::PcgArrays<T> a;
-  a.wx = s_w;
-  a.wy = s_w + P;
-  a.v = s_vec;
-  a.t = s_vec + P;
-  a.r = s_vec + 2 * P;
-  a.z = s_vec + 3 * P;
-  a.p = s_vec + 4 * P;
-  a.q = a.z;
-  a.mg = s_mg;
-  a.red = s_red;
-  a.xtmp = nullptr;
   T* const s_v = a.v;
-  const int64_t i = blockIdx.x;
-  lds::zero<NT>(s_vec, 5 * P);
-  stage_weights<N, NT, kR>(A.Y, A.ldY, i, A.s, A.phi, A.rphi, A.a0, a, s_y, s_w64);
+  stage_weights<N, NT, kR>(A.Y, A.ldY, i, A.s, A.phi, A.rphi, A.a0, a, s_y, w64);
   const int mH = A.nH - 1, ratio = N / A.nH;
   const double* uH = A.uH + i * (int64_t)(mH * mH);
   LDS_FOR_NODES(NT, N, k) {
@@ -331,11 +314,66 @@ __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void
     }
   };
   if constexpr (sizeof(T) == 8)
-    run(lds::WeightsFromArrays<N>{s_w, s_w + P});
+    run(lds::WeightsFromArrays<N>{(const double*)a.wx, (const double*)a.wx + P});
   else if constexpr (kR)
-    run(lds::WeightsFromArrays<N>{s_w64, s_w64 + P});
+    run(lds::WeightsFromArrays<N>{w64, w64 + P});
   else
     run(lds::WeightsFromTable<N>{A.phi, s_y, A.s, A.a0});
+}
+
+template <int N, int NT, typename T, bool kR = false>
+__global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void k_tg_small(
+    TgSmallArgs A) {
+  using Mh = lds::Mesh<N>;
+  constexpr int P = Mh::P;
+  __shared__ T s_w[lds::wblock<kR>() * P];
+  __shared__ T s_vec[5 * P];
+  __shared__ T s_mg[lds::mg_scratch<N, kR>() + 1];
+  __shared__ double s_red[6 * (NT / 64)];
+  __shared__ double s_y[kMaxStagedS];
+  __shared__ double s_w64[(kR && sizeof(T) < 8) ? 5 * P : 1];
+  lds::PcgArrays<T> a;
+  a.wx = s_w;
+  a.wy = s_w + P;
+  a.v = s_vec;
+  a.t = s_vec + P;
+  a.r = s_vec + 2 * P;
+  a.z = s_vec + 3 * P;
+  a.p = s_vec + 4 * P;
+  a.q = a.z;
+  a.mg = s_mg;
+  a.red = s_red;
+  a.xtmp = nullptr;
+  lds::zero<NT>(s_vec, 5 * P);
+  tg_sample<N, NT, kR>(A, a, s_y, s_w64, (int64_t)blockIdx.x);
+}
+
+// Problem 2 on 1/64: the top-level arrays in the workgroup's slice of a
+// global scratch buffer (weights and reaction, five vectors, the smoother's
+// second array), the V-cycle levels below in LDS; FP64.
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_tg_global(TgSmallArgs A) {
+  using Mh = lds::Mesh<N>;
+  constexpr int P = Mh::P;
+  __shared__ double s_mg[lds::mg_scratch<N, true>() + 1];
+  __shared__ double s_red[6 * (NT / 64)];
+  __shared__ double s_y[kMaxStagedS];
+  double* g = A.scratch + (int64_t)blockIdx.x * global_doubles<N, true>();
+  double* vec = g + lds::wblock<true>() * P;
+  lds::PcgArrays<double> a;
+  a.wx = g;
+  a.wy = g + P;
+  a.v = vec;
+  a.t = vec + P;
+  a.r = vec + 2 * P;
+  a.z = vec + 3 * P;
+  a.p = vec + 4 * P;
+  a.q = a.z;
+  a.xtmp = vec + 5 * P;
+  a.mg = s_mg;
+  a.red = s_red;
+  lds::zero<NT>(vec, 6 * P);
+  tg_sample<N, NT, true>(A, a, s_y, nullptr, (int64_t)blockIdx.x);
 }
 
 // The V-cycle below the batched levels: one workgroup per sample reads its
@@ -386,9 +424,10 @@ hipError_t rqi_n(const RqiArgs& a, hipStream_t st) {
       hipLaunchKernelGGL((k_rqi<N, NT, double>), dim3((unsigned)chains), dim3(NT), 0, st, a);
     }
   } else {
-    if (a.rphi) return hipErrorInvalidValue;  // Problem 2 runs on meshes up to 1/32
+    // Problem 2's eigensolves (direct and coarse meshes) stay at 1/32 or coarser
+    if (a.rphi) return hipErrorInvalidValue;
     // the caller provides chains x rqi_scratch_doubles(N) doubles of scratch
-    if (!a.scratch || a.scratch_doubles < chains * rqi_global_doubles<N>())
+    if (!a.scratch || a.scratch_doubles < chains * global_doubles<N>())
       return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_rqi_global<N, 512>), dim3((unsigned)chains), dim3(512), 0, st, a);
   }
@@ -437,7 +476,9 @@ hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st) {
   }
 }
 
-int64_t rqi_scratch_doubles(int N) { return N == 64 ? rqi_global_doubles<64>() : 0; }
+int64_t rqi_scratch_doubles(int N) { return N == 64 ? global_doubles<64>() : 0; }
+
+int64_t tg_scratch_doubles(int N) { return N == 64 ? global_doubles<64, true>() : 0; }
 
 template <int N>
 hipError_t rqi_occupancy(int* per, int mixed) {
@@ -474,6 +515,16 @@ hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st) {
     case 8: return tg_small_n<8>(a, st);
     case 16: return tg_small_n<16>(a, st);
     case 32: return tg_small_n<32>(a, st);
+    case 64: {
+      // Problem 2, FP64: one workgroup per sample, a.n x tg_scratch_doubles(64)
+      // doubles of scratch
+      if (!a.rphi || a.mixed) return hipErrorInvalidValue;
+      if (a.n <= 0) return hipSuccess;
+      if (!a.scratch || a.scratch_doubles < a.n * global_doubles<64, true>())
+        return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_tg_global<64, 512>), dim3((unsigned)a.n), dim3(512), 0, st, a);
+      return hipGetLastError();
+    }
     default: return hipErrorInvalidValue;
   }
 }

@@ -42,6 +42,9 @@ struct RqiArgs {
 hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st);
 // doubles of global scratch one chain needs on mesh N (0: all in LDS)
 int64_t rqi_scratch_doubles(int N);
+// doubles of global scratch one sample of the two-grid update needs on mesh N
+// (Problem 2 on 1/64; 0: all in LDS)
+int64_t tg_scratch_doubles(int N);
 // workgroups of the eigensolve on mesh N resident on the current device at once
 int rqi_chains_in_flight(int N, int mixed);
 
@@ -64,7 +67,11 @@ struct TgSmallArgs {
   double* g;            // [n] G of the two-grid eigenvector (integral, normalised), or nullptr
   int* lin_iters;       // [n] added to, or nullptr
   uint8_t* flags;       // [n] OR-ed
+  double* scratch;      // mesh 1/64 (Problem 2): n x tg_scratch_doubles(64) doubles
+  int64_t scratch_doubles;
 };
+// Two-grid update in LDS (N <= 32), or on 1/64 for Problem 2 in FP64 with the
+// top level in global scratch
 hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st);
 
 // One V-cycle X = K^{-1} B per active sample on mesh NB <= 32 from padded global

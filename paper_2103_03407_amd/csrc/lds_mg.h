@@ -251,7 +251,6 @@ MLQMC_DEV void prolong_add(const T* Xc, T* X) {
 template <int NT, int n, bool kStage = true, typename T, int kSw = 2, bool kR = false>
 MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtmp = nullptr) {
   static_assert(kSw == 2 || (kSw == 3 && kStage), "3 sweeps need register staging");
-  static_assert(!kR || kStage, "the reaction term runs with register staging only");
   if constexpr (n == 2) {
     if (threadIdx.x == 0) X[3] = B[3] / pdiag<2, T, kR>(wx, wy, 3);
     __syncthreads();
@@ -269,8 +268,8 @@ MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtm
       jacobi_first<NT, n, T, kR>(wx, wy, B, X, kOmega1);
       jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kOmega2);
     } else {
-      jacobi_first<NT, n>(wx, wy, B, Xtmp, kOmega1);
-      jacobi_to<NT, n>(wx, wy, B, Xtmp, X, kOmega2);
+      jacobi_first<NT, n, T, kR>(wx, wy, B, Xtmp, kOmega1);
+      jacobi_to<NT, n, T, kR>(wx, wy, B, Xtmp, X, kOmega2);
     }
     restrict_residual<NT, n, T, kR>(wx, wy, B, X, Bc);
     vcycle<NT, nc, true, T, kSw, kR>(wxc, wyc, Bc, Xc, Xc + Pc);
@@ -283,8 +282,8 @@ MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtm
       jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kOmega1);
       jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kOmega2);
     } else {
-      jacobi_to<NT, n>(wx, wy, B, X, Xtmp, kOmega1);
-      jacobi_to<NT, n>(wx, wy, B, Xtmp, X, kOmega2);
+      jacobi_to<NT, n, T, kR>(wx, wy, B, X, Xtmp, kOmega1);
+      jacobi_to<NT, n, T, kR>(wx, wy, B, Xtmp, X, kOmega2);
     }
   }
 }
@@ -380,7 +379,7 @@ MLQMC_DEV void scale_vec(T* x, double f) {
 template <int NT, int n, bool kR = false, typename T>
 MLQMC_DEV void precondition(const PcgArrays<T>& a, const T* r, T* z) {
   if constexpr (n > 32)
-    vcycle<NT, n, false, T>(a.wx, a.wy, r, z, a.mg, a.xtmp);
+    vcycle<NT, n, false, T, 2, kR>(a.wx, a.wy, r, z, a.mg, a.xtmp);
   else
     vcycle<NT, n, true, T, 2, kR>(a.wx, a.wy, r, z, a.mg);
 }

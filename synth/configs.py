@@ -136,6 +136,13 @@ def _islands_levels():
 P2_DECAYS = (4.0 / 3.0, 2.0, 4.0 / 3.0, 2.0)
 
 
+def _islands_levels4():
+    """_islands_levels plus level 3 on h = 1/64 (s = 128, N = 2^10)."""
+    lv = list(_islands_levels())
+    lv.append(LevelSpec(64, 128, 8, coarse_trunc(128, 16), 32, 64, 1 << 10))
+    return tuple(lv)
+
+
 def _nested_levels(base):
     """The levels of ``base`` with H_l = h_0 and S_l = s_0 for l >= 1."""
     l0 = base[0]
@@ -167,6 +174,9 @@ CONFIGS = {
                 "N=1024 x R=8", problem=2, decays=P2_DECAYS),
     8: Workload("cfg8-islands-mlqmc-3level", 8, "fp64", 0.0, _islands_levels(), 8,
                 "Problem 2 (islands), three-level two-grid MLQMC, h=1/8..1/32, s=16..64, "
+                "H=1/8, S=16", problem=2, decays=P2_DECAYS),
+    9: Workload("cfg9-islands-mlqmc-4level", 9, "fp64", 0.0, _islands_levels4(), 8,
+                "Problem 2 (islands), four-level two-grid MLQMC, h=1/8..1/64, s=16..128, "
                 "H=1/8, S=16", problem=2, decays=P2_DECAYS),
 }
 

@@ -3,7 +3,8 @@ region-wise diffusion a and reaction b), against the FP64 CPU oracle,
 through the C ABI (mlqmc_create_islands).
 
 The family runs on meshes 1/8 .. 1/32, every array of a solve in LDS, in FP64
-or mixed precision.  Tolerances as for Problem 1: eigenvalues relative 1e-10
+or mixed precision, and as the fine or previous mesh of a two-grid level on
+1/64 in FP64 (top level in global scratch).  Tolerances as for Problem 1: eigenvalues relative 1e-10
 per sample (mixed 1e-8), G(u) relative 1e-9 (mixed 1e-7), estimator sums from
 the per-sample bound.  Both parameter
 sets of the paper's complexity figure are covered: decays (4/3, 2, 4/3, 2)
@@ -159,12 +160,15 @@ def test_nested_estimate(ctx, fam):
     assert abs(est[0] - ref.Q_ml) <= 4 * LAM_RTOL * scale
 
 
-@pytest.mark.parametrize("lv,prec", [((64, 32, 16, 16, 0, 0), m.MLQMC_FP64),
+@pytest.mark.parametrize("lv,prec", [((128, 32, 16, 16, 0, 0), m.MLQMC_FP64),
                                      ((4, 4, 0, 0, 0, 0), m.MLQMC_FP64),
-                                     ((32, 16, 8, 8, 64, 16), m.MLQMC_FP64),
-                                     ((64, 8, 0, 0, 0, 0), m.MLQMC_MIXED)])
+                                     ((32, 16, 8, 8, 128, 16), m.MLQMC_FP64),
+                                     ((64, 8, 0, 0, 0, 0), m.MLQMC_FP64),
+                                     ((64, 32, 8, 8, 0, 0), m.MLQMC_MIXED),
+                                     ((32, 16, 8, 8, 64, 16), m.MLQMC_MIXED)])
 def test_rejected_levels(ctx, lv, prec):
-    # meshes outside 1/8 .. 1/32 are refused on the host
+    # meshes outside 1/8 .. 1/64, direct levels above 1/32 and mixed
+    # precision on 1/64 are refused on the host
     Y = _points(max(lv[1], 1), 2, 37)
     lam = np.empty(2)
     fl = np.zeros(2, np.uint8)
@@ -317,4 +321,74 @@ def test_mixed_cfg8_sampled(ctx_p2):
             v = mlqmc.level_value(lv, Y[i], fam)
             assert abs(lam[i] - v.lam) <= 1e-8 * v.lam, (l, i)
             assert abs(Yl[i] - v.Y) <= 2e-8 * v.lam, (l, i)
+
+
+# ---------------- two-grid updates on 1/64 (top level in global scratch) ----------------
+
+@pytest.mark.parametrize("lv", [(64, 32, 8, 8, 0, 0), (64, 64, 16, 16, 32, 32),
+                                (64, 64, 8, 16, 8, 16)])
+def test_two_grid_level_64(ctx, fam, lv):
+    spec = LevelSpec(*lv, 0)
+    count = 6
+    Y = _points(lv[1], count, 70)
+    lam, lamc, lamp = np.empty(count), np.empty(count), np.empty(count)
+    fl = np.zeros(count, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl, lam_coarse=lamc, lam_prev=lamp if lv[4] else None)
+    assert not fl.any(), fl
+    for k in range(count):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= LAM_RTOL * v.lam, (k, lam[k], v.lam)
+        assert abs(lamc[k] - v.lam_coarse) <= LAM_RTOL * v.lam_coarse
+        if lv[4]:
+            assert abs(lamp[k] - v.lam_prev) <= LAM_RTOL * v.lam_prev
+
+
+def test_functional_64(ctx, fam):
+    lv = (64, 32, 8, 8, 32, 16)
+    spec = LevelSpec(*lv, 0)
+    count = 5
+    Y = _points(lv[1], count, 71)
+    lam, lamp, g, gp = (np.empty(count) for _ in range(4))
+    fl = np.zeros(count, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp, g=g, g_prev=gp)
+    assert not fl.any(), fl
+    for k in range(count):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= LAM_RTOL * v.lam
+        assert abs(g[k] - v.G) <= G_RTOL * v.G, (k, g[k], v.G)
+        assert abs(gp[k] - v.G_prev) <= G_RTOL * v.G_prev
+
+
+def test_64_across_scratch_chunks(ctx, fam):
+    # more samples than one scratch chunk (4096): samples on both sides of
+    # the chunk boundary and the last one against the oracle
+    lv = (64, 16, 8, 8, 0, 0)
+    n = 4100
+    z = lattice_vector(16384, 16)
+    sh = shifts_for(72, 0, 1, 16)[0]
+    Y = np.ascontiguousarray(qmc.lattice_points(z, 16384, sh, range(n)))
+    lam = np.empty(n)
+    fl = np.zeros(n, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl)
+    assert not fl.any()
+    for k in (0, 4095, 4096, n - 1):
+        ref = twogrid.two_grid(64, 16, 8, 8, Y[k], fam)[0]
+        assert abs(lam[k] - ref) <= LAM_RTOL * ref, (k, lam[k], ref)
+
+
+def test_estimate_four_levels(ctx, fam):
+    # h = 1/8, 1/16, 1/32, 1/64 (h_l = 2^-(l+3)), H = 1/8: the paper's
+    # Problem 2 hierarchy through level 3
+    levels = [LevelSpec(8, 8, 0, 0, 0, 0, 16), LevelSpec(16, 16, 8, 8, 8, 8, 8),
+              LevelSpec(32, 32, 8, 8, 16, 16, 4), LevelSpec(64, 32, 8, 8, 32, 32, 4)]
+    R = 2
+    Ns = [16, 8, 4, 4]
+    zs = [lattice_vector(N, lv.s_fine) for N, lv in zip(Ns, levels)]
+    shifts = [shifts_for(73, l, R, lv.s_fine) for l, lv in enumerate(levels)]
+    st, Q, Qh, V, est = ctx.estimate([_lv6(lv) for lv in levels], Ns, R, zs, shifts)
+    assert st == m.MLQMC_OK
+    ref = mlqmc.estimate(levels, zs, Ns, shifts, fam)
+    dq = 2 * 5.0 * LAM_RTOL
+    assert np.max(np.abs(Q - ref.Q_lr)) <= dq
+    assert abs(est[0] - ref.Q_ml) <= 4 * dq
 
