@@ -350,7 +350,9 @@ __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void
 
 // Problem 2 on 1/64: the top-level arrays in the workgroup's slice of a
 // global scratch buffer (weights and reaction, five vectors, the smoother's
-// second array), the V-cycle levels below in LDS; FP64.
+// second array), the V-cycle levels below in LDS; FP64.  Launched with 512
+// threads: latency-bound, it runs faster with two waves per SIMD and 30
+// spilled registers than with one wave and none (and no faster with four).
 template <int N, int NT>
 __global__ __launch_bounds__(NT) void k_tg_global(TgSmallArgs A) {
   using Mh = lds::Mesh<N>;
