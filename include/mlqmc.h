@@ -135,13 +135,13 @@ typedef struct {
 /* Creates a context for the Problem 2 family (arguments as mlqmc_create).
  * Requires a >= a0_* - 0.5 sum |ca| > 0 and b >= 0 on each region for all
  * |y_j| <= 1/2 (MLQMC_EINVAL otherwise).  Contexts of this family run on
- * meshes 1/8 .. 1/32 in either precision (every array of a solve in LDS;
- * meshes are multiples of 1/8 so that the islands' edges are mesh lines), and
- * take 1/64 as the fine or previous mesh of a two-grid level in FP64 (its top
- * level in global scratch, up to 1.5 GB per call); the level and estimator
- * calls return MLQMC_EINVAL for other meshes or precisions (direct and coarse
- * meshes up to 1/32), and mlqmc_coefficient / mlqmc_apply_operator for any
- * call (they cover Problem 1). */
+ * meshes 1/8 .. 1/32 (every array of a solve in LDS; meshes are multiples of
+ * 1/8 so that the islands' edges are mesh lines), and take 1/64 as the fine
+ * or previous mesh of a two-grid level (its top level in global scratch, up
+ * to 1.5 GB per call), in either precision; the level and estimator calls
+ * return MLQMC_EINVAL for other meshes (direct and coarse meshes up to 1/32),
+ * and mlqmc_coefficient / mlqmc_apply_operator for any call (they cover
+ * Problem 1). */
 mlqmc_status mlqmc_create_islands(mlqmc_ctx** out, const mlqmc_islands* cf, int device,
                                   void* hip_stream);
 /* Frees everything the context allocated.  NULL-safe. */

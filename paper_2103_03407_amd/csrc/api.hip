@@ -325,13 +325,11 @@ mlqmc_status check_opts(mlqmc_ctx* ctx, const mlqmc_opts* o) {
 // 1/64 keeps its top level in global scratch); 0 = not used
 bool islands_mesh_ok(int n) { return n == 0 || (n >= 8 && n <= 64); }
 
-// Problem 2 on 1/64 runs in FP64, and only as a two-grid fine or previous
-// mesh (the eigensolves stay at 1/32 or coarser)
+// Problem 2 takes 1/64 only as a two-grid fine or previous mesh (the
+// eigensolves stay at 1/32 or coarser)
 mlqmc_status check_islands_level(mlqmc_ctx* ctx, const mlqmc_level* l, const mlqmc_opts* o) {
+  (void)o;
   if (!ctx->islands) return MLQMC_OK;
-  const bool has64 = l->n_fine == 64 || l->n_prev == 64;
-  if (has64 && o->prec != MLQMC_FP64)
-    return ctx->fail(MLQMC_EINVAL, "the islands family on 1/64 runs in FP64 only");
   if (l->n_coarse == 0 && (l->n_fine > 32 || l->n_prev > 32))
     return ctx->fail(MLQMC_EINVAL, "islands direct levels need meshes up to 1/32");
   if (l->n_coarse > 32)
@@ -742,7 +740,7 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
     a.g = g;
     a.lin_iters = lin_iters;
     a.flags = flags;
-    if (const int64_t per = tg_scratch_doubles(nh)) {
+    if (const int64_t per = tg_scratch_doubles(nh, a.mixed)) {
       // Problem 2 on 1/64: the top level of each sample in a scratch slice,
       // in chunks of samples so the scratch stays bounded (1.5 GB)
       constexpr int64_t kChunk = 4096;

@@ -350,19 +350,28 @@ __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void
 
 // Problem 2 on 1/64: the top-level arrays in the workgroup's slice of a
 // global scratch buffer (weights and reaction, five vectors, the smoother's
-// second array), the V-cycle levels below in LDS; FP64.  Launched with 512
-// threads: latency-bound, it runs faster with two waves per SIMD and 30
-// spilled registers than with one wave and none (and no faster with four).
-template <int N, int NT>
+// second array), the V-cycle levels below in LDS.  With FP32 storage the
+// slice starts with the FP64 weight block of the Rayleigh quotients.
+// Launched with 512 threads: latency-bound, the FP64 kernel runs faster with
+// two waves per SIMD and 30 spilled registers than with one wave and none
+// (and no faster with four).
+template <int N, typename T>
+constexpr int64_t tg_global_doubles() {
+  constexpr int64_t P = lds::Mesh<N>::P;
+  return sizeof(T) == 8 ? 11 * P : 5 * P + (11 * P * (int64_t)sizeof(T) + 7) / 8;
+}
+template <int N, int NT, typename T>
 __global__ __launch_bounds__(NT) void k_tg_global(TgSmallArgs A) {
   using Mh = lds::Mesh<N>;
   constexpr int P = Mh::P;
-  __shared__ double s_mg[lds::mg_scratch<N, true>() + 1];
+  __shared__ T s_mg[lds::mg_scratch<N, true>() + 1];
   __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
-  double* g = A.scratch + (int64_t)blockIdx.x * global_doubles<N, true>();
-  double* vec = g + lds::wblock<true>() * P;
-  lds::PcgArrays<double> a;
+  double* base = A.scratch + (int64_t)blockIdx.x * tg_global_doubles<N, T>();
+  double* w64 = sizeof(T) < 8 ? base : nullptr;
+  T* g = sizeof(T) < 8 ? reinterpret_cast<T*>(base + 5 * P) : reinterpret_cast<T*>(base);
+  T* vec = g + lds::wblock<true>() * P;
+  lds::PcgArrays<T> a;
   a.wx = g;
   a.wy = g + P;
   a.v = vec;
@@ -375,7 +384,7 @@ __global__ __launch_bounds__(NT) void k_tg_global(TgSmallArgs A) {
   a.mg = s_mg;
   a.red = s_red;
   lds::zero<NT>(vec, 6 * P);
-  tg_sample<N, NT, true>(A, a, s_y, nullptr, (int64_t)blockIdx.x);
+  tg_sample<N, NT, true>(A, a, s_y, w64, (int64_t)blockIdx.x);
 }
 
 // The V-cycle below the batched levels: one workgroup per sample reads its
@@ -480,7 +489,10 @@ hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st) {
 
 int64_t rqi_scratch_doubles(int N) { return N == 64 ? global_doubles<64>() : 0; }
 
-int64_t tg_scratch_doubles(int N) { return N == 64 ? global_doubles<64, true>() : 0; }
+int64_t tg_scratch_doubles(int N, int mixed) {
+  if (N != 64) return 0;
+  return mixed ? tg_global_doubles<64, float>() : tg_global_doubles<64, double>();
+}
 
 template <int N>
 hipError_t rqi_occupancy(int* per, int mixed) {
@@ -518,13 +530,19 @@ hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st) {
     case 16: return tg_small_n<16>(a, st);
     case 32: return tg_small_n<32>(a, st);
     case 64: {
-      // Problem 2, FP64: one workgroup per sample, a.n x tg_scratch_doubles(64)
-      // doubles of scratch
-      if (!a.rphi || a.mixed) return hipErrorInvalidValue;
+      // Problem 2: one workgroup per sample, a.n x tg_scratch_doubles(64,
+      // mixed) doubles of scratch
+      if (!a.rphi) return hipErrorInvalidValue;
       if (a.n <= 0) return hipSuccess;
-      if (!a.scratch || a.scratch_doubles < a.n * global_doubles<64, true>())
-        return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_tg_global<64, 512>), dim3((unsigned)a.n), dim3(512), 0, st, a);
+      const int64_t per =
+          a.mixed ? tg_global_doubles<64, float>() : tg_global_doubles<64, double>();
+      if (!a.scratch || a.scratch_doubles < a.n * per) return hipErrorInvalidValue;
+      if (a.mixed)
+        hipLaunchKernelGGL((k_tg_global<64, 512, float>), dim3((unsigned)a.n), dim3(512), 0, st,
+                           a);
+      else
+        hipLaunchKernelGGL((k_tg_global<64, 512, double>), dim3((unsigned)a.n), dim3(512), 0, st,
+                           a);
       return hipGetLastError();
     }
     default: return hipErrorInvalidValue;

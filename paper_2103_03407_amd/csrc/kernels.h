@@ -44,7 +44,7 @@ hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st);
 int64_t rqi_scratch_doubles(int N);
 // doubles of global scratch one sample of the two-grid update needs on mesh N
 // (Problem 2 on 1/64; 0: all in LDS)
-int64_t tg_scratch_doubles(int N);
+int64_t tg_scratch_doubles(int N, int mixed);
 // workgroups of the eigensolve on mesh N resident on the current device at once
 int rqi_chains_in_flight(int N, int mixed);
 
@@ -67,7 +67,7 @@ struct TgSmallArgs {
   double* g;            // [n] G of the two-grid eigenvector (integral, normalised), or nullptr
   int* lin_iters;       // [n] added to, or nullptr
   uint8_t* flags;       // [n] OR-ed
-  double* scratch;      // mesh 1/64 (Problem 2): n x tg_scratch_doubles(64) doubles
+  double* scratch;      // mesh 1/64 (Problem 2): n x tg_scratch_doubles(64, mixed) doubles
   int64_t scratch_doubles;
 };
 // Two-grid update in LDS (N <= 32), or on 1/64 for Problem 2 in FP64 with the

@@ -2,9 +2,9 @@
 region-wise diffusion a and reaction b), against the FP64 CPU oracle,
 through the C ABI (mlqmc_create_islands).
 
-The family runs on meshes 1/8 .. 1/32, every array of a solve in LDS, in FP64
-or mixed precision, and as the fine or previous mesh of a two-grid level on
-1/64 in FP64 (top level in global scratch).  Tolerances as for Problem 1: eigenvalues relative 1e-10
+The family runs on meshes 1/8 .. 1/32, every array of a solve in LDS, and as
+the fine or previous mesh of a two-grid level on 1/64 (top level in global
+scratch), in FP64 or mixed precision.  Tolerances as for Problem 1: eigenvalues relative 1e-10
 per sample (mixed 1e-8), G(u) relative 1e-9 (mixed 1e-7), estimator sums from
 the per-sample bound.  Both parameter
 sets of the paper's complexity figure are covered: decays (4/3, 2, 4/3, 2)
@@ -164,11 +164,11 @@ def test_nested_estimate(ctx, fam):
                                      ((4, 4, 0, 0, 0, 0), m.MLQMC_FP64),
                                      ((32, 16, 8, 8, 128, 16), m.MLQMC_FP64),
                                      ((64, 8, 0, 0, 0, 0), m.MLQMC_FP64),
-                                     ((64, 32, 8, 8, 0, 0), m.MLQMC_MIXED),
-                                     ((32, 16, 8, 8, 64, 16), m.MLQMC_MIXED)])
+                                     ((64, 8, 0, 0, 0, 0), m.MLQMC_MIXED),
+                                     ((16, 8, 0, 0, 64, 8), m.MLQMC_MIXED)])
 def test_rejected_levels(ctx, lv, prec):
-    # meshes outside 1/8 .. 1/64, direct levels above 1/32 and mixed
-    # precision on 1/64 are refused on the host
+    # meshes outside 1/8 .. 1/64 and direct levels above 1/32 are refused on
+    # the host
     Y = _points(max(lv[1], 1), 2, 37)
     lam = np.empty(2)
     fl = np.zeros(2, np.uint8)
@@ -391,4 +391,20 @@ def test_estimate_four_levels(ctx, fam):
     dq = 2 * 5.0 * LAM_RTOL
     assert np.max(np.abs(Q - ref.Q_lr)) <= dq
     assert abs(est[0] - ref.Q_ml) <= 4 * dq
+
+
+@pytest.mark.parametrize("lv", [(64, 32, 8, 8, 0, 0), (64, 64, 16, 16, 32, 32)])
+def test_mixed_two_grid_level_64(ctx, fam, lv):
+    spec = LevelSpec(*lv, 0)
+    count = 6
+    Y = _points(lv[1], count, 74)
+    lam, lamp = np.empty(count), np.empty(count)
+    fl = np.zeros(count, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp if lv[4] else None, opts=_mixed())
+    assert not fl.any(), fl
+    for k in range(count):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= 1e-8 * v.lam, (k, lam[k], v.lam)
+        if lv[4]:
+            assert abs(lamp[k] - v.lam_prev) <= 1e-8 * v.lam_prev
 
