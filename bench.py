@@ -9,12 +9,12 @@ H = 1/32 -> h = 1/128, s = 64, S = 8, N = 1024 lattice points x R = 8 shifts
 (8192 eigen-samples), all synthetic (CBC lattice, seeded shifts).
 
 ``--cfg`` selects another workload of ``synth/configs.py``: 4 and 6 are the
-five-level estimators (independent and shared shifts), 7, 8 and 9 Problem 2
-(the islands) as one two-grid level H = 1/8 -> h = 1/32 and as the three- and
-four-level estimators on h = 1/8 .. 1/32 and 1/8 .. 1/64; their two-grid
-updates run per sample (in LDS, and on 1/64 with the top level in global
-scratch), and the roofline is then those kernels' rate against the vector
-peak of the precision.
+five-level estimators (independent and shared shifts), 7 to 10 Problem 2
+(the islands) as one two-grid level H = 1/8 -> h = 1/32 and as the three-,
+four- and five-level estimators on h = 1/8 .. 1/32, 1/64 and 1/128; their
+two-grid updates run per sample (in LDS, and on 1/64 and 1/128 with the top
+levels in global scratch), and the roofline is then those kernels' rate
+against the vector peak of the precision.
 
 Prints one JSON line.  ``value`` = eigen-samples per second on one GPU.
 """
@@ -303,7 +303,7 @@ def lds_step_flops(ctx, m, w, opts):
         if lv.n_prev and not (lv.n_prev == lv.n_coarse and lv.s_prev == lv.s_coarse):
             updates.append((lv.n_prev, lv.s_prev))
         for nm, sm in updates:
-            if nm > 32 and not (reaction and nm == 64):
+            if nm > 32 and not (reaction and nm <= 128):
                 continue  # the batched kernels: not this kernel class
             li = np.zeros(n, np.int32)
             ctx.eig_level((nm, sm, lv.n_coarse, lv.s_coarse, 0, 0),
@@ -389,7 +389,7 @@ def main():
     for _ in range(a.warmup):
         step()
     if a.kernel_class is None:
-        per_sample = all(lv.n_fine <= (64 if w.problem == 2 else 32) for lv in w.levels)
+        per_sample = all(lv.n_fine <= (128 if w.problem == 2 else 32) for lv in w.levels)
         a.kernel_class = "lds" if per_sample and any(lv.n_coarse for lv in w.levels) else "post"
     kcls = {"post": m.K_SMOOTH, "pre": m.K_PRE, "apply": m.K_APPLY,
             "coeff": m.K_COEFF, "lds": m.K_TG_LDS}[a.kernel_class]

@@ -136,9 +136,9 @@ typedef struct {
  * Requires a >= a0_* - 0.5 sum |ca| > 0 and b >= 0 on each region for all
  * |y_j| <= 1/2 (MLQMC_EINVAL otherwise).  Contexts of this family run on
  * meshes 1/8 .. 1/32 (every array of a solve in LDS; meshes are multiples of
- * 1/8 so that the islands' edges are mesh lines), and take 1/64 as the fine
- * or previous mesh of a two-grid level (its top level in global scratch, up
- * to 1.5 GB per call), in either precision; the level and estimator calls
+ * 1/8 so that the islands' edges are mesh lines), and take 1/64 and 1/128 as
+ * the fine or previous mesh of a two-grid level (top levels in global
+ * scratch, up to 1.5 GiB per call), in either precision; the level and estimator calls
  * return MLQMC_EINVAL for other meshes (direct and coarse meshes up to 1/32),
  * and mlqmc_coefficient / mlqmc_apply_operator for any call (they cover
  * Problem 1). */

@@ -321,12 +321,12 @@ mlqmc_status check_opts(mlqmc_ctx* ctx, const mlqmc_opts* o) {
 }
 
 // Problem 2 meshes: multiples of 1/8 (the islands' edges are mesh lines) up
-// to 1/64 (every array of a solve in LDS up to 1/32; the two-grid update on
-// 1/64 keeps its top level in global scratch); 0 = not used
-bool islands_mesh_ok(int n) { return n == 0 || (n >= 8 && n <= 64); }
+// to 1/128 (every array of a solve in LDS up to 1/32; the two-grid update on
+// 1/64 and 1/128 keeps its top levels in global scratch); 0 = not used
+bool islands_mesh_ok(int n) { return n == 0 || (n >= 8 && n <= 128); }
 
-// Problem 2 takes 1/64 only as a two-grid fine or previous mesh (the
-// eigensolves stay at 1/32 or coarser)
+// Problem 2 takes 1/64 and 1/128 only as a two-grid fine or previous mesh
+// (the eigensolves stay at 1/32 or coarser)
 mlqmc_status check_islands_level(mlqmc_ctx* ctx, const mlqmc_level* l, const mlqmc_opts* o) {
   (void)o;
   if (!ctx->islands) return MLQMC_OK;
@@ -369,7 +369,7 @@ mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
   if (ctx->islands &&
       !(islands_mesh_ok(l->n_fine) && islands_mesh_ok(l->n_coarse) && islands_mesh_ok(l->n_prev)))
     return ctx->fail(MLQMC_EINVAL,
-                     "the islands family (Problem 2) needs meshes 1/8 .. 1/64 (got %d, %d, %d)",
+                     "the islands family (Problem 2) needs meshes 1/8 .. 1/128 (got %d, %d, %d)",
                      l->n_fine, l->n_coarse, l->n_prev);
   return MLQMC_OK;
 }
@@ -741,10 +741,12 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
     a.lin_iters = lin_iters;
     a.flags = flags;
     if (const int64_t per = tg_scratch_doubles(nh, a.mixed)) {
-      // Problem 2 on 1/64: the top level of each sample in a scratch slice,
-      // in chunks of samples so the scratch stays bounded (1.5 GB)
-      constexpr int64_t kChunk = 4096;
-      const int64_t chunk = std::min<int64_t>(n, kChunk);
+      // Problem 2 on 1/64 and 1/128: each sample's slice of scratch, in
+      // chunks of a power of two of samples within 1.5 GiB (4096 on 1/64)
+      constexpr int64_t kScratchBytes = (int64_t)3 << 29;
+      int64_t cap = 1;
+      while (2 * cap * per * (int64_t)sizeof(double) <= kScratchBytes) cap *= 2;
+      const int64_t chunk = std::min<int64_t>(n, cap);
       CS(ctx->getT("tg_scratch", (size_t)(chunk * per), &a.scratch));
       a.scratch_doubles = chunk * per;
       const int64_t DH = (int64_t)(nH - 1) * (nH - 1);

@@ -348,23 +348,29 @@ __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void
   tg_sample<N, NT, kR>(A, a, s_y, s_w64, (int64_t)blockIdx.x);
 }
 
-// Problem 2 on 1/64: the top-level arrays in the workgroup's slice of a
-// global scratch buffer (weights and reaction, five vectors, the smoother's
-// second array), the V-cycle levels below in LDS.  With FP32 storage the
-// slice starts with the FP64 weight block of the Rayleigh quotients.
-// Launched with 512 threads: latency-bound, the FP64 kernel runs faster with
-// two waves per SIMD and 30 spilled registers than with one wave and none
-// (and no faster with four).
+// Problem 2 on 1/64 and 1/128: the top-level arrays in the workgroup's slice
+// of a global scratch buffer (weights and reaction, five vectors, the
+// smoother's second array), the V-cycle levels below in LDS on 1/64; on
+// 1/128 they follow in the slice too (the 1/64 level alone would take 233 KB
+// of LDS).  With FP32 storage the slice starts with the FP64 weight block of
+// the Rayleigh quotients.  Launched with 512 threads: latency-bound, the FP64
+// kernel on 1/64 runs faster with two waves per SIMD and 30 spilled registers
+// than with one wave and none (and no faster with four).
+template <int N>
+constexpr bool mg_in_scratch() {
+  return N > 64;
+}
 template <int N, typename T>
 constexpr int64_t tg_global_doubles() {
   constexpr int64_t P = lds::Mesh<N>::P;
-  return sizeof(T) == 8 ? 11 * P : 5 * P + (11 * P * (int64_t)sizeof(T) + 7) / 8;
+  constexpr int64_t elems = 11 * P + (mg_in_scratch<N>() ? lds::mg_scratch<N, true>() : 0);
+  return sizeof(T) == 8 ? elems : 5 * P + (elems * (int64_t)sizeof(T) + 7) / 8;
 }
 template <int N, int NT, typename T>
 __global__ __launch_bounds__(NT) void k_tg_global(TgSmallArgs A) {
   using Mh = lds::Mesh<N>;
   constexpr int P = Mh::P;
-  __shared__ T s_mg[lds::mg_scratch<N, true>() + 1];
+  __shared__ T s_mg[mg_in_scratch<N>() ? 1 : lds::mg_scratch<N, true>() + 1];
   __shared__ double s_red[6 * (NT / 64)];
   __shared__ double s_y[kMaxStagedS];
   double* base = A.scratch + (int64_t)blockIdx.x * tg_global_doubles<N, T>();
@@ -381,7 +387,7 @@ __global__ __launch_bounds__(NT) void k_tg_global(TgSmallArgs A) {
   a.p = vec + 4 * P;
   a.q = a.z;
   a.xtmp = vec + 5 * P;
-  a.mg = s_mg;
+  a.mg = mg_in_scratch<N>() ? vec + 6 * P : s_mg;
   a.red = s_red;
   lds::zero<NT>(vec, 6 * P);
   tg_sample<N, NT, true>(A, a, s_y, w64, (int64_t)blockIdx.x);
@@ -490,9 +496,28 @@ hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st) {
 int64_t rqi_scratch_doubles(int N) { return N == 64 ? global_doubles<64>() : 0; }
 
 int64_t tg_scratch_doubles(int N, int mixed) {
-  if (N != 64) return 0;
-  return mixed ? tg_global_doubles<64, float>() : tg_global_doubles<64, double>();
+  if (N == 64) return mixed ? tg_global_doubles<64, float>() : tg_global_doubles<64, double>();
+  if (N == 128)
+    return mixed ? tg_global_doubles<128, float>() : tg_global_doubles<128, double>();
+  return 0;
 }
+
+namespace {
+template <int N>
+hipError_t tg_global_n(const TgSmallArgs& a, hipStream_t st) {
+  // Problem 2: one workgroup per sample, a.n x tg_scratch_doubles(N, mixed)
+  // doubles of scratch
+  if (!a.rphi) return hipErrorInvalidValue;
+  if (a.n <= 0) return hipSuccess;
+  const int64_t per = a.mixed ? tg_global_doubles<N, float>() : tg_global_doubles<N, double>();
+  if (!a.scratch || a.scratch_doubles < a.n * per) return hipErrorInvalidValue;
+  if (a.mixed)
+    hipLaunchKernelGGL((k_tg_global<N, 512, float>), dim3((unsigned)a.n), dim3(512), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_tg_global<N, 512, double>), dim3((unsigned)a.n), dim3(512), 0, st, a);
+  return hipGetLastError();
+}
+}  // namespace
 
 template <int N>
 hipError_t rqi_occupancy(int* per, int mixed) {
@@ -529,22 +554,8 @@ hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st) {
     case 8: return tg_small_n<8>(a, st);
     case 16: return tg_small_n<16>(a, st);
     case 32: return tg_small_n<32>(a, st);
-    case 64: {
-      // Problem 2: one workgroup per sample, a.n x tg_scratch_doubles(64,
-      // mixed) doubles of scratch
-      if (!a.rphi) return hipErrorInvalidValue;
-      if (a.n <= 0) return hipSuccess;
-      const int64_t per =
-          a.mixed ? tg_global_doubles<64, float>() : tg_global_doubles<64, double>();
-      if (!a.scratch || a.scratch_doubles < a.n * per) return hipErrorInvalidValue;
-      if (a.mixed)
-        hipLaunchKernelGGL((k_tg_global<64, 512, float>), dim3((unsigned)a.n), dim3(512), 0, st,
-                           a);
-      else
-        hipLaunchKernelGGL((k_tg_global<64, 512, double>), dim3((unsigned)a.n), dim3(512), 0, st,
-                           a);
-      return hipGetLastError();
-    }
+    case 64: return tg_global_n<64>(a, st);
+    case 128: return tg_global_n<128>(a, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -40,13 +40,16 @@
 namespace mlqmc {
 namespace lds {
 
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
 template <int n>
 struct Mesh {
+  static_assert(n >= 2 && (n & (n - 1)) == 0, "meshes are 1/n with n a power of two");
   static constexpr int m = n - 1;
   static constexpr int D = m * m;            // interior nodes
   static constexpr int P = (n + 1) * n + 1;  // padded length of a vector
   static constexpr int EW = 2 * P;           // [WX | WY]
-  static constexpr int lg = n == 2 ? 1 : n == 4 ? 2 : n == 8 ? 3 : n == 16 ? 4 : n == 32 ? 5 : 6;
+  static constexpr int lg = ilog2(n);
 };
 
 // Loop over the interior positions owned by this thread: k = n + t, n + t +

@@ -143,6 +143,13 @@ def _islands_levels4():
     return tuple(lv)
 
 
+def _islands_levels5():
+    """_islands_levels4 plus level 4 on h = 1/128 (s = 256, N = 2^9)."""
+    lv = list(_islands_levels4())
+    lv.append(LevelSpec(128, 256, 8, coarse_trunc(256, 16), 64, 128, 1 << 9))
+    return tuple(lv)
+
+
 def _nested_levels(base):
     """The levels of ``base`` with H_l = h_0 and S_l = s_0 for l >= 1."""
     l0 = base[0]
@@ -178,6 +185,9 @@ CONFIGS = {
     9: Workload("cfg9-islands-mlqmc-4level", 9, "fp64", 0.0, _islands_levels4(), 8,
                 "Problem 2 (islands), four-level two-grid MLQMC, h=1/8..1/64, s=16..128, "
                 "H=1/8, S=16", problem=2, decays=P2_DECAYS),
+    10: Workload("cfg10-islands-mlqmc-5level", 10, "fp64", 0.0, _islands_levels5(), 8,
+                 "Problem 2 (islands), five-level two-grid MLQMC, h=1/8..1/128, s=16..256, "
+                 "H=1/8, S=16", problem=2, decays=P2_DECAYS),
 }
 
 

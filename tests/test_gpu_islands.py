@@ -3,8 +3,8 @@ region-wise diffusion a and reaction b), against the FP64 CPU oracle,
 through the C ABI (mlqmc_create_islands).
 
 The family runs on meshes 1/8 .. 1/32, every array of a solve in LDS, and as
-the fine or previous mesh of a two-grid level on 1/64 (top level in global
-scratch), in FP64 or mixed precision.  Tolerances as for Problem 1: eigenvalues relative 1e-10
+the fine or previous mesh of a two-grid level on 1/64 and 1/128 (top levels in
+global scratch), in FP64 or mixed precision.  Tolerances as for Problem 1: eigenvalues relative 1e-10
 per sample (mixed 1e-8), G(u) relative 1e-9 (mixed 1e-7), estimator sums from
 the per-sample bound.  Both parameter
 sets of the paper's complexity figure are covered: decays (4/3, 2, 4/3, 2)
@@ -160,15 +160,15 @@ def test_nested_estimate(ctx, fam):
     assert abs(est[0] - ref.Q_ml) <= 4 * LAM_RTOL * scale
 
 
-@pytest.mark.parametrize("lv,prec", [((128, 32, 16, 16, 0, 0), m.MLQMC_FP64),
+@pytest.mark.parametrize("lv,prec", [((256, 32, 16, 16, 0, 0), m.MLQMC_FP64),
                                      ((4, 4, 0, 0, 0, 0), m.MLQMC_FP64),
-                                     ((32, 16, 8, 8, 128, 16), m.MLQMC_FP64),
+                                     ((32, 16, 8, 8, 256, 16), m.MLQMC_FP64),
                                      ((64, 8, 0, 0, 0, 0), m.MLQMC_FP64),
                                      ((64, 8, 0, 0, 0, 0), m.MLQMC_MIXED),
                                      ((16, 8, 0, 0, 64, 8), m.MLQMC_MIXED)])
 def test_rejected_levels(ctx, lv, prec):
-    # meshes outside 1/8 .. 1/64 and direct levels above 1/32 are refused on
-    # the host
+    # meshes outside 1/8 .. 1/128 and direct levels above 1/32 are refused
+    # on the host
     Y = _points(max(lv[1], 1), 2, 37)
     lam = np.empty(2)
     fl = np.zeros(2, np.uint8)
@@ -407,4 +407,40 @@ def test_mixed_two_grid_level_64(ctx, fam, lv):
         assert abs(lam[k] - v.lam) <= 1e-8 * v.lam, (k, lam[k], v.lam)
         if lv[4]:
             assert abs(lamp[k] - v.lam_prev) <= 1e-8 * v.lam_prev
+
+
+# ---------------- two-grid updates on 1/128 (V-cycle in global scratch too) ----------------
+
+@pytest.mark.parametrize("prec,tol", [("fp64", LAM_RTOL), ("mixed", 1e-8)])
+@pytest.mark.parametrize("lv", [(128, 64, 8, 8, 0, 0), (128, 64, 16, 16, 64, 32)])
+def test_two_grid_level_128(ctx, fam, lv, prec, tol):
+    spec = LevelSpec(*lv, 0)
+    count = 4
+    Y = _points(lv[1], count, 80)
+    lam, lamp = np.empty(count), np.empty(count)
+    fl = np.zeros(count, np.uint8)
+    o = m.default_opts(prec=m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED)
+    ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp if lv[4] else None, opts=o)
+    assert not fl.any(), fl
+    for k in range(count):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= tol * v.lam, (k, lam[k], v.lam)
+        if lv[4]:
+            assert abs(lamp[k] - v.lam_prev) <= tol * v.lam_prev
+
+
+def test_128_across_scratch_chunks(ctx, fam):
+    # 1/128 runs 512 samples per scratch chunk: both sides of the boundary
+    lv = (128, 16, 8, 8, 0, 0)
+    n = 520
+    z = lattice_vector(16384, 16)
+    sh = shifts_for(81, 0, 1, 16)[0]
+    Y = np.ascontiguousarray(qmc.lattice_points(z, 16384, sh, range(n)))
+    lam = np.empty(n)
+    fl = np.zeros(n, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl)
+    assert not fl.any()
+    for k in (511, 512, n - 1):
+        ref = twogrid.two_grid(128, 16, 8, 8, Y[k], fam)[0]
+        assert abs(lam[k] - ref) <= LAM_RTOL * ref, (k, lam[k], ref)
 
