@@ -444,3 +444,35 @@ def test_128_across_scratch_chunks(ctx, fam):
         ref = twogrid.two_grid(128, 16, 8, 8, Y[k], fam)[0]
         assert abs(lam[k] - ref) <= LAM_RTOL * ref, (k, lam[k], ref)
 
+
+
+def test_no_random_terms_on_64(ctx, fam):
+    # s = S = 0: the background coefficients alone (the tables' base rows)
+    lv = (64, 0, 8, 0, 0, 0)
+    Y = np.zeros((3, 0))
+    lam = np.empty(3)
+    fl = np.zeros(3, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl)
+    assert not fl.any()
+    ref = twogrid.two_grid(64, 0, 8, 0, np.zeros(0), fam)[0]
+    assert np.max(np.abs(lam - ref)) <= LAM_RTOL * ref
+
+
+def test_nested_and_extended_with_a_64_level(ctx, fam):
+    # shared shifts with level 3 on 1/64 (the global-scratch update), grown
+    # in two steps, against the oracle's nested estimate
+    N = [8, 4, 4, 2]
+    levels = [LevelSpec(8, 4, 0, 0, 0, 0, N[0]), LevelSpec(16, 6, 8, 4, 8, 4, N[1]),
+              LevelSpec(32, 8, 8, 4, 16, 6, N[2]), LevelSpec(64, 8, 8, 4, 32, 8, N[3])]
+    l6 = [_lv6(l) for l in levels]
+    z = lattice_vector(64, 8)
+    R = 2
+    shifts = shifts_for(75, 0, R, 8)
+    sums = np.zeros((4, R))
+    ctx.estimate_nested_extend(l6, [0] * 4, [4, 2, 2, 1], R, z, shifts, sums)
+    st, Q, Qh, V, est = ctx.estimate_nested_extend(l6, [4, 2, 2, 1], N, R, z, shifts, sums)
+    assert st == m.MLQMC_OK
+    ref = mlqmc.estimate_nested(levels, z, N, shifts, fam)
+    scale = ref.Qhat[0]
+    assert np.max(np.abs(Q - ref.Q_lr)) <= 4 * LAM_RTOL * scale
+    assert abs(est[0] - ref.Q_ml) <= 4 * LAM_RTOL * scale

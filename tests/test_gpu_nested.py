@@ -356,3 +356,19 @@ def test_extend_rejects(ctx, case):
     assert e.value.code == m.MLQMC_EINVAL
     assert np.all(sums == 7.0)  # unchanged on an error
 
+
+
+def test_extend_with_no_new_points(ctx):
+    # N_done = N: nothing is evaluated, the sums stay, the estimate is the
+    # previous one
+    N = [8, 4, 4, 2]
+    l6 = [_lv6(l) for l in _small_levels(N)]
+    z = lattice_vector(64, 8)
+    shifts = shifts_for(55, 0, 2, 8)
+    sums = np.zeros((4, 2))
+    first = ctx.estimate_nested_extend(l6, [0] * 4, N, 2, z, shifts, sums)
+    kept = sums.copy()
+    again = ctx.estimate_nested_extend(l6, N, N, 2, z, shifts, sums)
+    assert np.array_equal(sums, kept)
+    for x, y in zip(first[1:5], again[1:5]):
+        assert np.array_equal(x, y)
