@@ -327,8 +327,7 @@ bool islands_mesh_ok(int n) { return n == 0 || (n >= 8 && n <= 128); }
 
 // Problem 2 takes 1/64 and 1/128 only as a two-grid fine or previous mesh
 // (the eigensolves stay at 1/32 or coarser)
-mlqmc_status check_islands_level(mlqmc_ctx* ctx, const mlqmc_level* l, const mlqmc_opts* o) {
-  (void)o;
+mlqmc_status check_islands_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
   if (!ctx->islands) return MLQMC_OK;
   if (l->n_coarse == 0 && (l->n_fine > 32 || l->n_prev > 32))
     return ctx->fail(MLQMC_EINVAL, "islands direct levels need meshes up to 1/32");
@@ -1248,7 +1247,7 @@ mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_o
   if (!ctx) return MLQMC_EINVAL;
   CS(check_opts(ctx, o));
   CS(check_level(ctx, L));
-  CS(check_islands_level(ctx, L, o));
+  CS(check_islands_level(ctx, L));
   if (n < 0) return ctx->fail(MLQMC_EINVAL, "n < 0");
   if (n > 0 && (!Y || !lam || !flags)) return ctx->fail(MLQMC_EINVAL, "NULL buffer");
   if (n > 0 && L->n_prev && !lam_prev) return ctx->fail(MLQMC_EINVAL, "lam_prev is NULL but n_prev > 0");
@@ -1300,7 +1299,7 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
   int64_t zoff = 0, soff = 0;
   for (int l = 0; l < nl; ++l) {
     CS(check_level(ctx, &lv[l]));
-    CS(check_islands_level(ctx, &lv[l], o));
+    CS(check_islands_level(ctx, &lv[l]));
     if (!is_pow2(N[l]) || N[l] > ((int64_t)1 << 30))
       return ctx->fail(MLQMC_EINVAL, "N[%d] must be a power of two <= 2^30", l);
     const int s = lv[l].s_fine;
@@ -1396,7 +1395,7 @@ mlqmc_status nested_core(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, cons
   std::vector<int64_t> a(nl), e(nl);
   for (int l = 0; l < nl; ++l) {
     CS(check_level(ctx, &lv[l]));
-    CS(check_islands_level(ctx, &lv[l], o));
+    CS(check_islands_level(ctx, &lv[l]));
     if (!is_pow2(N[l]) || N[l] > ((int64_t)1 << 30))
       return ctx->fail(MLQMC_EINVAL, "N[%d] must be a power of two <= 2^30", l);
     if (l > 0 && N[l] > N[l - 1])
