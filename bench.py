@@ -45,10 +45,10 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cfg", type=int, default=2, help="workload id (2: two-grid 1/32->1/128)")
     ap.add_argument("--kernel-class", default=None,
-                    choices=["post", "pre", "apply", "coeff", "lds"],
+                    choices=["post", "pre", "apply", "coeff", "lds", "rqi"],
                     help="kernel timed for the roofline (default: post, the dominant kernel of "
-                         "the batched path; lds, the two-grid update in LDS, for workloads "
-                         "whose fine meshes are all 1/32 or coarser)")
+                         "the batched path; lds, the per-sample two-grid update, for workloads "
+                         "without batched levels; rqi, the eigensolve, for direct-only ones)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"],
                     help="fp64, or mixed (FP32 fine PCG/V-cycle, FP64 residual and RQ)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -275,6 +275,54 @@ def lds_update_flops(n: int, rows: int, its: int, reaction: bool) -> int:
     return weights + init + rq + its * ((op + 38) * D + vcycle)
 
 
+def rqi_sample_flops(n: int, rows: int, rq: int, lin: int, reaction: bool) -> int:
+    """Algorithmic FP64 flops of one warm-started RQ eigensolve on mesh 1/n in
+    LDS (k_rqi) that took `rq` RQ steps and `lin` inner PCG iterations in all,
+    with the per-node counts of lds_update_flops: the weights, the starting
+    Rayleigh quotient, and per RQ step one correction solve's set-up (the
+    initial residual, V-cycle and dots) and one Rayleigh quotient with its
+    normalisation (op + mass + 5 per node), plus `lin` PCG iterations."""
+    D = (n - 1) ** 2
+    P = (n + 1) * n + 1
+    op = 30 if reaction else 11
+    mass = 8
+    levels, c = 0, n
+    while c >= 2:
+        levels += (c - 1) ** 2
+        c //= 2
+    vcycle = (4 * op + 20) * levels
+    weights = 2 * rows * (5 if reaction else 2) * P
+    setup = (op + mass + 3) * D + vcycle + 8 * D
+    rq_eval = (op + mass + 5) * D
+    return (weights + rq_eval + rq * (setup + rq_eval) +
+            lin * ((op + 38) * D + vcycle))
+
+
+def rqi_step_flops(ctx, m, w, opts):
+    """Algorithmic flops of every k_rqi launch of one step of a direct-only
+    workload, from the RQ-step and inner-iteration counts of the same points
+    (an untimed pass)."""
+    import numpy as np
+    total = 0
+    reaction = w.problem == 2
+    for l, lv in enumerate(w.levels):
+        n = w.R * lv.N
+        Y = np.empty((n, max(lv.s_fine, 1)))
+        for r in range(w.R):
+            ctx.lattice_points(lv.N, w.z(l), w.shifts(l)[r], 0, lv.N, Y[r * lv.N:(r + 1) * lv.N])
+        lam = np.empty(n)
+        fl = np.zeros(n, np.uint8)
+        for nm, sm in [(lv.n_fine, lv.s_fine)] + ([(lv.n_prev, lv.s_prev)] if lv.n_prev else []):
+            rq = np.zeros(n, np.int32)
+            li = np.zeros(n, np.int32)
+            ctx.eig_level((nm, sm, 0, 0, 0, 0), np.ascontiguousarray(Y[:, :sm]), lam, fl,
+                          rq_iters=rq, lin_iters=li, opts=opts)
+            rows = sm + 1 if reaction else sm
+            for q, k in zip(rq.tolist(), li.tolist()):
+                total += rqi_sample_flops(nm, rows, q, k, reaction)
+    return total
+
+
 def lds_step_flops(ctx, m, w, opts):
     """Algorithmic flops of every k_tg_small launch of one step of workload w,
     from the PCG iteration counts of the same points (an untimed pass; the
@@ -390,9 +438,12 @@ def main():
         step()
     if a.kernel_class is None:
         per_sample = all(lv.n_fine <= (128 if w.problem == 2 else 32) for lv in w.levels)
-        a.kernel_class = "lds" if per_sample and any(lv.n_coarse for lv in w.levels) else "post"
+        if not any(lv.n_coarse for lv in w.levels):
+            a.kernel_class = "rqi"
+        else:
+            a.kernel_class = "lds" if per_sample else "post"
     kcls = {"post": m.K_SMOOTH, "pre": m.K_PRE, "apply": m.K_APPLY,
-            "coeff": m.K_COEFF, "lds": m.K_TG_LDS}[a.kernel_class]
+            "coeff": m.K_COEFF, "lds": m.K_TG_LDS, "rqi": m.K_COARSE}[a.kernel_class]
     ctx.set_timing(kcls)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -407,11 +458,23 @@ def main():
     value = n_samples * a.steps / dt
 
     kname = {"post": "k_post", "pre": "k_pre", "apply": "k_pupdate_apply",
-             "coeff": "k_expand_mfma", "lds": "k_tg_small"}[a.kernel_class]
+             "coeff": "k_expand_mfma", "lds": "k_tg_small", "rqi": "k_rqi"}[a.kernel_class]
     if a.kernel_class == "lds" and any(lv.n_fine > 32 for lv in w.levels):
         kname = "k_tg_small+k_tg_global"
     roof = None
-    if launches > 0 and kms > 0 and a.kernel_class == "lds":
+    if launches > 0 and kms > 0 and a.kernel_class == "rqi":
+        # the warm-started eigensolve in LDS: like the two-grid update, bound
+        # by vector arithmetic on LDS data, against the vector peak of its
+        # precision
+        avg_ms = kms / launches
+        flops_per_launch = rqi_step_flops(ctx, m, w, opts) * a.steps / launches
+        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        peak = PEAK_FP64_VALU_TFS if a.prec == "fp64" else PEAK_FP32_VALU_TFS
+        roof = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": None, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
+                "algorithmic_flops_per_launch": flops_per_launch}
+    elif launches > 0 and kms > 0 and a.kernel_class == "lds":
         # the LDS-resident two-grid update: vector arithmetic on data in LDS,
         # so the vector peak of its precision bounds it (FP64, or FP32 for
         # the mixed solve, whose Rayleigh quotients stay FP64); HBM traffic is

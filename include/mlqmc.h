@@ -309,7 +309,8 @@ enum {
   MLQMC_K_COEFF = 1,     /* coefficient expansion on the fine mesh */
   MLQMC_K_APPLY = 2,     /* fine operator apply inside the projected PCG */
   MLQMC_K_SMOOTH = 3,    /* finest-level coarse correction + post-smoothing + PCG dots */
-  MLQMC_K_COARSE = 4,    /* coarse eigensolve (persistent chain kernel) */
+  MLQMC_K_COARSE = 4,    /* eigensolves (coarse, direct and direct previous-level; the
+                            chain kernel) */
   MLQMC_K_PRE = 5,       /* finest-level pre-smoothing + residual restriction */
   MLQMC_K_TG_LDS = 6     /* per-sample two-grid update: in LDS (fine meshes up to 1/32),
                             or with its top level in global scratch (Problem 2 on 1/64,

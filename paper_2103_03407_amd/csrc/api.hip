@@ -860,7 +860,9 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
       b.lin_iters = nullptr;
       b.flags = f2;
       b.g_out = g_prev;
+      ctx->t_begin(MLQMC_K_COARSE);
       CK(launch_rqi(L->n_prev, b, st), "eigensolve (LDS)");
+      ctx->t_end(MLQMC_K_COARSE, 0.0);
       // merge the flags of the previous-level eigensolve on the host
       std::vector<uint8_t> h1(n), h2(n);
       CK(hipMemcpyAsync(h1.data(), flags, n, hipMemcpyDeviceToHost, st), "flags");
