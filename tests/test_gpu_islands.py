@@ -476,3 +476,33 @@ def test_nested_and_extended_with_a_64_level(ctx, fam):
     scale = ref.Qhat[0]
     assert np.max(np.abs(Q - ref.Q_lr)) <= 4 * LAM_RTOL * scale
     assert abs(est[0] - ref.Q_ml) <= 4 * LAM_RTOL * scale
+
+
+def test_cfg10_five_levels_sampled(ctx_p2):
+    # the five-level Problem 2 workload (h = 1/8 .. 1/128, s = 16 .. 256) at
+    # full size: the estimator's level means equal the means of the level
+    # values, every value unflagged, strided ones against the oracle
+    w = CONFIGS[10]
+    fam = w.family()
+    c = m.Context(fam)
+    try:
+        st, Q, Qh, V, est = c.estimate([_lv6(lv) for lv in w.levels], [lv.N for lv in w.levels],
+                                       w.R, [w.z(l) for l in range(5)],
+                                       [w.shifts(l) for l in range(5)])
+        assert st == m.MLQMC_OK
+        for l, lv in enumerate(w.levels):
+            Y = _level_points(c, w, l)
+            n = Y.shape[0]
+            lam, lamp = np.empty(n), np.empty(n)
+            fl = np.zeros(n, np.uint8)
+            c.eig_level(_lv6(lv), Y, lam, fl, lam_prev=lamp if lv.n_prev else None)
+            assert not fl.any()
+            Yl = lam - lamp if lv.n_prev else lam
+            for i in range(0, n, n // 3 + 5):
+                v = mlqmc.level_value(lv, Y[i], fam)
+                assert abs(lam[i] - v.lam) <= LAM_RTOL * v.lam, (l, i)
+                assert abs(Yl[i] - v.Y) <= 2 * LAM_RTOL * v.lam, (l, i)
+            per_r = Yl.reshape(w.R, lv.N).mean(axis=1)
+            assert np.max(np.abs(Q[l] - per_r)) <= 2 * LAM_RTOL * np.max(lam)
+    finally:
+        c.close()
