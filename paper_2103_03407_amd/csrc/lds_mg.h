@@ -116,12 +116,19 @@ MLQMC_DEV double pM12d(const T* x, int k) {
          (double)x[k + n] + (double)x[k + n + 1] + (double)x[k - n - 1];
 }
 
+// Coarse levels finer than 1/32 (only below a 1/128 top level, in global
+// memory) sweep between two arrays instead of staging in registers, so they
+// carry a third vector
+constexpr int level_vectors(int c) { return c > 32 ? 3 : 2; }
+
 // Entries of the V-cycle levels strictly below mesh n: per level nc, the
-// weights (2 P, or 5 P with reaction) and B, X (2 P).
+// weights (2 P, or 5 P with reaction) and B, X (2 P; 3 P with the second
+// sweep array).
 template <int n, bool kR = false>
 constexpr int mg_scratch() {
   int s = 0;
-  for (int c = n / 2; c >= 2; c /= 2) s += (wblock<kR>() + 2) * ((c + 1) * c + 1);
+  for (int c = n / 2; c >= 2; c /= 2)
+    s += (wblock<kR>() + level_vectors(c)) * ((c + 1) * c + 1);
   return s;
 }
 
@@ -165,10 +172,10 @@ MLQMC_DEV void coarsen_all(const T* wx, const T* wy, T* nxt) {
         wxc[4 * Pc + e] = v;
       }
     }
-    T* rest = wxc + wblock<kR>() * Pc;  // B and X of this level, then the next level
-    zero<NT>(rest, 2 * Pc);
+    T* rest = wxc + wblock<kR>() * Pc;  // B, X (and X2) of this level, then the next
+    zero<NT>(rest, level_vectors(nc) * Pc);
     __syncthreads();
-    coarsen_all<NT, nc, T, kR>(wxc, wyc, rest + 2 * Pc);
+    coarsen_all<NT, nc, T, kR>(wxc, wyc, rest + level_vectors(nc) * Pc);
   }
 }
 
@@ -263,6 +270,8 @@ MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtm
     const T* wyc = wxc + Pc;
     T* Bc = nxt + wblock<kR>() * Pc;
     T* Xc = Bc + Pc;
+    T* X2c = level_vectors(nc) == 3 ? Xc + Pc : nullptr;
+    T* nxtc = Xc + (level_vectors(nc) - 1) * Pc;
     if constexpr (kSw == 3) {
       jacobi_first<NT, n, T, kR>(wx, wy, B, X, kCheb3[0]);
       jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[1]);
@@ -275,7 +284,7 @@ MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtm
       jacobi_to<NT, n, T, kR>(wx, wy, B, Xtmp, X, kOmega2);
     }
     restrict_residual<NT, n, T, kR>(wx, wy, B, X, Bc);
-    vcycle<NT, nc, true, T, kSw, kR>(wxc, wyc, Bc, Xc, Xc + Pc);
+    vcycle<NT, nc, (nc <= 32), T, kSw, kR>(wxc, wyc, Bc, Xc, nxtc, X2c);
     prolong_add<NT, n>(Xc, X);
     if constexpr (kSw == 3) {
       jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[0]);
