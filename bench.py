@@ -55,6 +55,10 @@ def _parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES bytes (counter calibration)")
+    ap.add_argument("--plain-vs-enhanced", action="store_true",
+                    help="only compare, per level of the workload (meshes up to 1/32), the "
+                         "enhanced method (two-grid update, warm-started RQ) with plain MLQMC "
+                         "(direct eigensolves, cold start) on the same points")
     return ap.parse_args()
 
 
@@ -275,6 +279,53 @@ def lds_update_flops(n: int, rows: int, its: int, reaction: bool) -> int:
     return weights + init + rq + its * ((op + 38) * D + vcycle)
 
 
+def plain_vs_enhanced(m, w, opts):
+    """Time of each level's values with the enhanced method (Algorithm 2: the
+    two-grid update from the coarse pair, warm-started RQ chains) and with
+    plain MLQMC (a direct, cold-started eigensolve on the level's fine and
+    previous meshes), on the same points; the paper compares the two in its
+    numerical section.  Direct solves run up to 1/32, so levels beyond are
+    skipped."""
+    import numpy as np
+    import torch
+    ctx = m.Context(w.family(), device=0)
+
+    def timed(L, Y, warm, reps=3):
+        n = Y.shape[0]
+        lam, lp = np.empty(n), np.empty(n)
+        fl = np.zeros(n, np.uint8)
+        prev = lp if L[4] else None
+        ctx.eig_level(L, Y, lam, fl, lam_prev=prev, warm_chain=warm, opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.eig_level(L, Y, lam, fl, lam_prev=prev, warm_chain=warm, opts=opts)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, float(((lam - lp) if L[4] else lam).mean())
+
+    out, te_all, tp_all = [], 0.0, 0.0
+    for l, lv in enumerate(w.levels):
+        if lv.n_fine > 32:
+            continue
+        n = w.R * lv.N
+        Y = np.empty((n, max(lv.s_fine, 1)))
+        for r in range(w.R):
+            ctx.lattice_points(lv.N, w.z(l), w.shifts(l)[r], 0, lv.N, Y[r * lv.N:(r + 1) * lv.N])
+        enh = _lv6(lv)
+        plain = (lv.n_fine, lv.s_fine, 0, 0, lv.n_prev, lv.s_prev)
+        te, ye = timed(enh, Y, 1)
+        tp, yp = timed(plain, Y, 0)
+        te_all += te
+        tp_all += tp
+        out.append({"level": l, "h": f"1/{lv.n_fine}", "samples": n,
+                    "enhanced_ms": round(te * 1e3, 3), "plain_ms": round(tp * 1e3, 3),
+                    "plain_over_enhanced": round(tp / te, 3),
+                    "mean_Y_enhanced": ye, "mean_Y_plain": yp})
+    ctx.close()
+    return {"workload": w.name, "precision": "fp64" if opts.prec == m.MLQMC_FP64 else "mixed",
+            "levels": out, "plain_over_enhanced": round(tp_all / max(te_all, 1e-30), 3)}
+
+
 def rqi_sample_flops(n: int, rows: int, rq: int, lin: int, reaction: bool) -> int:
     """Algorithmic FP64 flops of one warm-started RQ eigensolve on mesh 1/n in
     LDS (k_rqi) that took `rq` RQ steps and `lin` inner PCG iterations in all,
@@ -411,6 +462,10 @@ def main():
     w = CONFIGS[a.cfg]
     fam = w.family()
     torch.cuda.init()
+    if a.plain_vs_enhanced:
+        o = m.default_opts(prec=m.MLQMC_MIXED if a.prec == "mixed" else m.MLQMC_FP64)
+        print(json.dumps(plain_vs_enhanced(m, w, o)), flush=True)
+        return 0
     ctx = m.Context(fam, device=0)
     tuned = ctx.apply_tuning()  # the autotuner's table for this device, if shipped
     levels = [_lv6(lv) for lv in w.levels]
