@@ -29,7 +29,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .cbc import lattice_vector
-from .family import coeff_family, islands_family
+from .family import coeff_family, islands_family, problem1_family
 
 SEED_ROOT = 210303407
 
@@ -58,6 +58,7 @@ class Workload:
     nested: bool = False
     problem: int = 1              # 1: benchmark / Problem 1 table; 2: islands
     decays: tuple = ()            # Problem 2: (p_a, p_a', p_b, p_b')
+    p1_decay: float = 0.0         # > 0: Problem 1's own table (k1 = j, k2 = j + 1) with this decay
 
     @property
     def s_max(self) -> int:
@@ -66,6 +67,8 @@ class Workload:
     def family(self):
         if self.problem == 2:
             return islands_family(self.s_max, *self.decays)
+        if self.p1_decay > 0:
+            return problem1_family(self.s_max, self.p1_decay)
         return coeff_family(self.s_max, decay=self.decay, a0=self.a0)
 
     def z(self, level: int) -> np.ndarray:
@@ -188,6 +191,9 @@ CONFIGS = {
     10: Workload("cfg10-islands-mlqmc-5level", 10, "fp64", 0.0, _islands_levels5(), 8,
                  "Problem 2 (islands), five-level two-grid MLQMC, h=1/8..1/128, s=16..256, "
                  "H=1/8, S=16", problem=2, decays=P2_DECAYS),
+    11: Workload("cfg11-problem1-mlqmc-3level", 11, "fp64", 2.0, _islands_levels(), 8,
+                 "Problem 1 of the numerical section (decay 2) on workload 8's meshes, "
+                 "truncations and N_l", p1_decay=2.0),
 }
 
 
