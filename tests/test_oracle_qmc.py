@@ -298,3 +298,24 @@ def test_nested_block_sums_add_up_to_the_estimate():
     for l in range(3):
         assert abs(whole[l] / N[l] - est.Q_lr[l, 0]) <= 1e-13 * max(1.0, abs(est.Q_lr[l, 0]))
     assert mlqmc.nested_level_sums(levels, z, N, N, sh[0], fam) == [0.0, 0.0, 0.0]
+
+
+def test_every_workload_reads_stored_generating_vectors():
+    # the bench and the tests must not fall back to a component-by-component
+    # search at run time: every (N, s) a workload uses has a stored vector
+    # (or a longer one with the same N, whose prefix it is)
+    import os
+    from synth import CONFIGS
+    store = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         "synth", "lattice")
+    have = {}
+    for name in os.listdir(store):
+        if name.startswith("cbc_N") and name.endswith(".txt"):
+            N = int(name[5:name.index("_s")])
+            s = int(name[name.index("_s") + 2:-4])
+            have[N] = max(have.get(N, 0), s)
+    for w in CONFIGS.values():
+        pairs = ([(max(lv.N for lv in w.levels), w.s_max)] if w.nested else
+                 [(lv.N, lv.s_fine) for lv in w.levels])
+        for N, s in pairs:
+            assert have.get(N, 0) >= s, (w.name, N, s)
