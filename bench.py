@@ -56,7 +56,7 @@ def _parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES bytes (counter calibration)")
     ap.add_argument("--plain-vs-enhanced", action="store_true",
-                    help="only compare, per level of the workload (meshes up to 1/32), the "
+                    help="only compare, per level of the workload (direct solves up to 1/64), the "
                          "enhanced method (two-grid update, warm-started RQ) with plain MLQMC "
                          "(direct eigensolves, cold start) on the same points")
     return ap.parse_args()
@@ -284,8 +284,8 @@ def plain_vs_enhanced(m, w, opts):
     two-grid update from the coarse pair, warm-started RQ chains) and with
     plain MLQMC (a direct, cold-started eigensolve on the level's fine and
     previous meshes), on the same points; the paper compares the two in its
-    numerical section.  Direct solves run up to 1/32, so levels beyond are
-    skipped."""
+    numerical section.  Direct solves run up to 1/64 (Problem 2: 1/32), so
+    levels beyond are skipped."""
     import numpy as np
     import torch
     ctx = m.Context(w.family(), device=0)
@@ -305,7 +305,7 @@ def plain_vs_enhanced(m, w, opts):
 
     out, te_all, tp_all = [], 0.0, 0.0
     for l, lv in enumerate(w.levels):
-        if lv.n_fine > 32:
+        if lv.n_fine > (32 if w.problem == 2 else 64):
             continue
         n = w.R * lv.N
         Y = np.empty((n, max(lv.s_fine, 1)))

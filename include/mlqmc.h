@@ -70,8 +70,9 @@ typedef struct {
  *                     on the fine mesh (lambda_{h_l,s_l}, level 0 of Algorithm 2);
  *  n_prev, s_prev   : mesh and truncation of the level-(l-1) term evaluated at
  *                     the same point with the same coarse pair; 0 = no such term.
- * Limits: 4 <= n_coarse <= 32 and n_coarse < n_fine <= 1024 for two-grid levels;
- * 4 <= n_fine <= 32 for direct levels (the coarse eigensolve runs in LDS). */
+ * Limits: 4 <= n_coarse <= 64 and n_coarse < n_fine <= 1024 for two-grid levels;
+ * 4 <= n_fine <= 64 for direct levels (the eigensolve runs in LDS up to 1/32; on
+ * 1/64 in FP64 with each chain's top level in global scratch). */
 typedef struct {
   int32_t n_fine, s_fine;
   int32_t n_coarse, s_coarse;

@@ -343,8 +343,8 @@ mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
     return ctx->fail(MLQMC_EINVAL, "s_fine=%d outside [0, s_max=%d]", l->s_fine, ctx->s_max);
   if (l->s_fine > 512) return ctx->fail(MLQMC_EINVAL, "s_fine=%d exceeds 512", l->s_fine);
   if (l->n_coarse == 0) {
-    if (l->n_fine < 4 || l->n_fine > 32)
-      return ctx->fail(MLQMC_EINVAL, "direct levels need 4 <= n_fine <= 32 (got %d)", l->n_fine);
+    if (l->n_fine < 4 || l->n_fine > 64)
+      return ctx->fail(MLQMC_EINVAL, "direct levels need 4 <= n_fine <= 64 (got %d)", l->n_fine);
   } else {
     if (!is_pow2(l->n_coarse) || l->n_coarse < 4 || l->n_coarse > 64)
       return ctx->fail(MLQMC_EINVAL, "n_coarse=%d must be a power of two in [4, 64]", l->n_coarse);
@@ -359,8 +359,8 @@ mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
     if (l->s_prev < 0 || l->s_prev > l->s_fine)
       return ctx->fail(MLQMC_EINVAL, "s_prev=%d outside [0, s_fine]", l->s_prev);
     if (l->n_coarse == 0) {
-      if (l->n_prev < 4 || l->n_prev > 32)
-        return ctx->fail(MLQMC_EINVAL, "direct previous level needs 4 <= n_prev <= 32");
+      if (l->n_prev < 4 || l->n_prev > 64)
+        return ctx->fail(MLQMC_EINVAL, "direct previous level needs 4 <= n_prev <= 64");
     } else if (l->n_prev < l->n_coarse || l->n_prev > 1024) {
       return ctx->fail(MLQMC_EINVAL, "need n_coarse <= n_prev <= 1024 (got %d)", l->n_prev);
     }
@@ -836,6 +836,15 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
     a.lam = lam;
     a.u_out = nullptr;
     a.g_out = g;
+    // 1/64: each chain's top level in a slice of global scratch (FP64)
+    auto scratch_for = [&](int mesh, RqiArgs& ra) -> mlqmc_status {
+      if (const int64_t per = rqi_scratch_doubles(mesh)) {
+        ra.scratch_doubles = per * ((n + chain - 1) / chain);
+        CS(ctx->getT("rqi_scratch", ra.scratch_doubles, &ra.scratch));
+      }
+      return MLQMC_OK;
+    };
+    CS(scratch_for(L->n_fine, a));
     ctx->t_begin(MLQMC_K_COARSE);
     CK(launch_rqi(L->n_fine, a, st), "eigensolve (LDS)");
     ctx->t_end(MLQMC_K_COARSE, 0.0);
@@ -860,6 +869,9 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
       b.lin_iters = nullptr;
       b.flags = f2;
       b.g_out = g_prev;
+      b.scratch = nullptr;
+      b.scratch_doubles = 0;
+      CS(scratch_for(L->n_prev, b));
       ctx->t_begin(MLQMC_K_COARSE);
       CK(launch_rqi(L->n_prev, b, st), "eigensolve (LDS)");
       ctx->t_end(MLQMC_K_COARSE, 0.0);

@@ -571,3 +571,24 @@ def test_mixed_multilevel_top_level(ctx, fam):
         v = mlqmc.level_value(lv, Y[k], fam)
         assert abs(lam[k] - v.lam) <= MIXED_RTOL * v.lam
         assert abs(lamp[k] - v.lam_prev) <= MIXED_RTOL * v.lam_prev
+
+
+# ---------------- direct eigensolves on 1/64 (top level in global scratch) ----------------
+
+@pytest.mark.parametrize("lv", [(64, 16, 0, 0, 0, 0), (64, 16, 0, 0, 32, 8)])
+def test_direct_level_64(ctx, fam, lv):
+    spec = LevelSpec(*lv, 0)
+    count = 9
+    Y = np.ascontiguousarray(_points(256, lv[1], 1, 0, 0, range(count)))
+    lam, lamp, g, gp = (np.empty(count) for _ in range(4))
+    fl = np.zeros(count, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp if lv[4] else None, g=g,
+                  g_prev=gp if lv[4] else None)
+    assert not fl.any()
+    for k in range(count):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= LAM_RTOL * v.lam, (k, lam[k], v.lam)
+        assert abs(g[k] - v.G) <= 1e-9 * v.G
+        if lv[4]:
+            assert abs(lamp[k] - v.lam_prev) <= LAM_RTOL * v.lam_prev
+            assert abs(gp[k] - v.G_prev) <= 1e-9 * v.G_prev
