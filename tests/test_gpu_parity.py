@@ -372,7 +372,7 @@ def test_zero_truncation_is_constant_coefficient(ctx, fam):
     assert _rel(lam, np.full(3, ref)) <= LAM_RTOL
 
 
-@pytest.mark.parametrize("lv", [(48, 16, 0, 0, 0, 0), (64, 16, 0, 0, 0, 0), (64, 16, 64, 8, 0, 0),
+@pytest.mark.parametrize("lv", [(48, 16, 0, 0, 0, 0), (128, 16, 0, 0, 0, 0), (64, 16, 64, 8, 0, 0),
                                 (256, 16, 128, 8, 0, 0),
                                 (128, 16, 32, 32, 0, 0), (128, 600, 32, 8, 0, 0),
                                 (128, 16, 32, 8, 64, 32), (64, 16, 32, 8, 16, 8)])
