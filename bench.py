@@ -440,7 +440,7 @@ def _traffic(kernel: str, prec: str = "fp64", cfg: int = 2):
 def main():
     a = _parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU only; --gpus {a.gpus} is not supported "
               "(samples shard across GPUs by warm-start chain, see the design notes)",
               file=sys.stderr)
         return 2
