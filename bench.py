@@ -441,7 +441,8 @@ def main():
     a = _parse()
     if a.gpus != 1:
         print(f"bench.py: the library runs on one GPU only; --gpus {a.gpus} is not supported "
-              "(samples shard across GPUs by warm-start chain, see the design notes)",
+              "(samples would shard across GPUs by warm-start chain, with one all-reduce of "
+              "the per-level sums)",
               file=sys.stderr)
         return 2
     import numpy as np
