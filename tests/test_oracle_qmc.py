@@ -6,6 +6,10 @@ eq. sample_var, eq. mlqmc_R, eq. ml-var, Algorithm 2).
 * the character property: the rule integrates e^{2 pi i h.x} to 0 unless
   h.z = 0 mod N, when the shifted rule returns e^{2 pi i h.Delta};
 * hand-computed shift averages and sample variances;
+* the estimator's assembly (Algorithm 2): on three levels with different z,
+  N, truncations and shifts, each Q_l^(r) is the mean of the level values at
+  exactly that cell's hand-listed points, so another level's z, N or shift
+  fails it;
 * the telescoping sum (eq. tele_sum) is exact sample by sample when all
   levels share points and use direct eigensolves;
 * a degenerate two-grid level whose two meshes coincide gives Y = 0 at
@@ -127,6 +131,70 @@ def test_estimate_small_two_level():
     # small corrections (variance reduction across levels)
     assert est.Qhat[0] > 10 and abs(est.Qhat[1]) < 0.2 * est.Qhat[0]
     assert est.V[1] < est.V[0]
+
+
+# Hand-listed points of a three-level, two-shift estimate whose levels differ
+# in z, N, s and shifts, and no level's points are a prefix of another's.
+# y = {k z / N + Delta} - 1/2 worked out by hand per (level, shift, k), in
+# units of 1/8.  Level 1's previous term differs from its coarse problem only
+# through y_2, which is nonzero at all its points (y_2 = 0 would make that
+# update exactly singular).
+_EST_LEVELS = [LevelSpec(4, 2, 0, 0, 0, 0, 8),      # direct, h = 1/4, s = 2
+               LevelSpec(8, 3, 4, 1, 4, 2, 4),      # two-grid 1/4 -> 1/8, prev on 1/4
+               LevelSpec(16, 4, 4, 2, 8, 3, 2)]     # two-grid 1/4 -> 1/16, prev on 1/8
+_EST_Z = [[1, 3], [3, 1, 1], [1, 1, 1, 1]]
+_EST_SHIFTS = [[[1 / 8, 1 / 2], [5 / 8, 1 / 4]],
+               [[0.0, 5 / 8, 1 / 2], [1 / 4, 1 / 8, 7 / 8]],
+               [[1 / 4, 1 / 2, 3 / 4, 0.0], [1 / 8, 3 / 8, 5 / 8, 7 / 8]]]
+_EST_POINTS = [
+    # level 0, N = 8, z = (1, 3): t = (k/8, (3k mod 8)/8)
+    [[(-3, 0), (-2, 3), (-1, -2), (0, 1), (1, -4), (2, -1), (3, 2), (-4, -3)],   # Delta (1/8, 1/2)
+     [(1, -2), (2, 1), (3, -4), (-4, -1), (-3, 2), (-2, -3), (-1, 0), (0, 3)]],  # Delta (5/8, 1/4)
+    # level 1, N = 4, z = (3, 1, 1): t = ((3k mod 4)/4, k/4, k/4)
+    [[(-4, 1, 0), (2, 3, 2), (0, -3, -4), (-2, -1, -2)],        # Delta (0, 5/8, 1/2)
+     [(-2, -3, 3), (-4, -1, -3), (2, 1, -1), (0, 3, 1)]],       # Delta (1/4, 1/8, 7/8)
+    # level 2, N = 2, z = (1, 1, 1, 1): t = (k/2, k/2, k/2, k/2)
+    [[(-2, 0, 2, -4), (2, -4, -2, 0)],                          # Delta (1/4, 1/2, 3/4, 0)
+     [(-3, -1, 1, 3), (1, 3, -3, -1)]],                         # Delta (1/8, 3/8, 5/8, 7/8)
+]
+
+
+def test_estimate_assembles_each_level_and_shift():
+    """Algorithm 2 / eq. mlqmc_R / eq. sample_var: Q_l^(r) is the mean of
+    level_value over exactly the N_l points of (level l, shift r), Qhat_l the
+    shift average, V_l = sum_r (Qhat_l - Q_l^(r))^2 / (R (R - 1)).  Taking
+    another level's z, N, truncation or shift changes the point set (the
+    hand-listed sets below are pairwise different) and fails the comparison."""
+    fam = problem1_family(8, 2.0)
+    Ns = [lv.N for lv in _EST_LEVELS]
+    zs = [np.array(z, dtype=np.int64) for z in _EST_Z]
+    shifts = [np.array(sh, dtype=np.float64) for sh in _EST_SHIFTS]
+    est = mlqmc.estimate(_EST_LEVELS, zs, Ns, shifts, fam)
+    # the point sets are pairwise distinct across (level, shift)
+    sets = [frozenset(tuple(p) for p in _EST_POINTS[l][r]) for l in range(3) for r in range(2)]
+    assert len(set(sets)) == 6
+    Q = np.empty((3, 2))
+    for l, lv in enumerate(_EST_LEVELS):
+        for r in range(2):
+            pts = _EST_POINTS[l][r]
+            assert len(pts) == lv.N
+            # the oracle's own point generator agrees with the hand list
+            got = qmc.lattice_points(zs[l], lv.N, shifts[l][r])
+            assert got.tolist() == [[v / 8 for v in p] for p in pts]
+            ys = [mlqmc.level_value(lv, np.array(p, dtype=np.float64) / 8, fam).Y for p in pts]
+            Q[l, r] = math.fsum(ys) / lv.N
+            # ARPACK starts from a random vector: equal to round-off, not bitwise
+            assert abs(est.Q_lr[l, r] - Q[l, r]) <= 1e-12 * abs(Q[l, r]) + 1e-14
+        # the shift average and sample variance of the oracle's own Q_l^(r)
+        q0, q1 = est.Q_lr[l]
+        qh = (q0 + q1) / 2
+        assert est.Qhat[l] == qh
+        assert est.V[l] == ((qh - q0) ** 2 + (qh - q1) ** 2) / 2
+        assert abs(est.V[l] - (Q[l, 0] - Q[l, 1]) ** 2 / 4) <= 1e-9 * est.V[l] + 1e-28
+    assert est.Q_ml == math.fsum(est.Qhat)
+    assert est.V_ml == math.fsum(est.V)
+    # every cell carries its own value: a swap of points between cells shows
+    assert len(set(Q.ravel().tolist())) == 6
 
 
 def test_radical_inverse_hand_values():
