@@ -16,6 +16,8 @@ Every step follows the paper's statement in FP64 with library primitives
 * ``fem``      P1 stiffness and mass matrices (section 2.3, eq. fe-evp)
 * ``eig``      smallest eigenpair of the generalised EVP (section 2.4)
 * ``twogrid``  two-grid-truncation method (Algorithm 1, eq. 2grid_src_ell)
+* ``rqi``      counted RQ iteration from the fixed or the nearby-point start
+               (section 4.3; section 5's absolute tolerance)
 * ``qmc``      randomly shifted rank-1 lattice points (eq. rqmc, eq. t_kl),
                shift average and sample variance (eq. sample_var)
 * ``mlqmc``    level differences and the estimator (Algorithm 2,
@@ -27,4 +29,4 @@ the final multilevel estimate itself, whose value the paper does not print
 (its pins are the telescoping identity and the hand-computed estimator).
 """
 
-from . import mesh, coeff, fem, eig, twogrid, qmc, mlqmc  # noqa: F401
+from . import mesh, coeff, fem, eig, twogrid, qmc, mlqmc, rqi  # noqa: F401

@@ -1,13 +1,20 @@
-"""Writes oracle eigenvalues for a few lattice points of the large two-grid
+"""Writes oracle eigenvalues for lattice points of the large two-grid
 workload (H = 1/64 -> h = 1/1024, s = 512, S = 23, coefficients decaying as
 j^-2), where one oracle sample takes minutes.  Calls only oracle/ (and the
-input generators in synth/); the GPU parity test reads the stored values.
+input generators in synth/); the GPU parity tests read the stored values.
 
-    python tests/golden/make_large_samples.py   # writes large_twogrid_samples.json
+    python tests/golden/make_large_samples.py            # large_twogrid_samples.json
+    python tests/golden/make_large_samples.py --chain    # large_twogrid_chain.json
+
+The first set is four scattered points; the second is eight consecutive
+points of one shift, so that warm-start chains (each eigensolve started from
+the previous point's eigenvector, section 4.3) can be checked at this size.
+One worker holds about 9 GB; --workers caps the pool.
 """
 
 from __future__ import annotations
 
+import argparse
 import json
 import multiprocessing as mp
 import os
@@ -21,6 +28,7 @@ from synth import CONFIGS  # noqa: E402
 
 CFG = 5
 POINTS = [(0, 0), (0, 1), (3, 517), (7, 1023)]  # (shift r, lattice index k)
+CHAIN = [(2, k) for k in range(300, 308)]       # consecutive points of shift 2
 
 
 def one(rk):
@@ -33,14 +41,20 @@ def one(rk):
 
 
 def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--chain", action="store_true")
+    ap.add_argument("--workers", type=int, default=4)
+    a = ap.parse_args()
     for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[v] = "1"
-    with mp.get_context("fork").Pool(len(POINTS)) as pool:
-        rows = pool.map(one, POINTS, chunksize=1)
+    pts = CHAIN if a.chain else POINTS
+    with mp.get_context("fork").Pool(min(a.workers, len(pts))) as pool:
+        rows = pool.map(one, pts, chunksize=1)
     w = CONFIGS[CFG]
     out = {"workload": w.name, "source": "oracle.twogrid.two_grid (Algorithm 1), FP64, SuperLU",
            "samples": rows}
-    with open(os.path.join(HERE, "large_twogrid_samples.json"), "w") as f:
+    name = "large_twogrid_chain.json" if a.chain else "large_twogrid_samples.json"
+    with open(os.path.join(HERE, name), "w") as f:
         json.dump(out, f, indent=1)
 
 
