@@ -4,9 +4,14 @@
 One step = one pass of the whole hot path over one batch: lattice points ->
 coefficient expansion -> warm-started coarse RQ eigensolve -> prolongation ->
 projected-PCG shifted fine solve -> Rayleigh quotient -> level accumulation,
-i.e. one ``mlqmc_estimate`` call on the single-level two-grid workload
-H = 1/32 -> h = 1/128, s = 64, S = 8, N = 1024 lattice points x R = 8 shifts
-(8192 eigen-samples), all synthetic (CBC lattice, seeded shifts).
+i.e. one ``mlqmc_estimate`` call.  The default workload is the largest that
+fits one GPU: the two-grid level H = 1/64 -> h = 1/1024 (1 046 529 fine
+unknowns), s = 512, S = 23, coefficients decaying as j^-2, N = 1024 lattice
+points x R = 8 shifts (8192 eigen-samples), all synthetic (CBC lattice,
+seeded shifts), in FP64.  On that workload (and on ``--cfg 2``) the line also
+carries: the other batched kernels' rates, the mixed-precision path, the FP64
+path stopped at the mixed path's tolerances (equal accuracy), each with its
+error against the oracle, and the two-grid 1/32 -> 1/128 workload (s = 64).
 
 ``--cfg`` selects another workload of ``synth/configs.py``: 4 and 6 are the
 five-level estimators (independent and shared shifts), 7 to 10 Problem 2
@@ -17,6 +22,7 @@ levels in global scratch), and the roofline is then those kernels' rate
 against the vector peak of the precision.
 
 Prints one JSON line.  ``value`` = eigen-samples per second on one GPU.
+Progress goes to stderr.
 """
 
 from __future__ import annotations
@@ -43,7 +49,8 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cfg", type=int, default=2, help="workload id (2: two-grid 1/32->1/128)")
+    ap.add_argument("--cfg", type=int, default=5,
+                    help="workload id (5: two-grid 1/64 -> 1/1024, s = 512; 2: 1/32 -> 1/128)")
     ap.add_argument("--kernel-class", default=None,
                     choices=["post", "pre", "apply", "coeff", "lds", "rqi"],
                     help="kernel timed for the roofline (default: post, the dominant kernel of "
@@ -52,6 +59,11 @@ def _parse():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"],
                     help="fp64, or mixed (FP32 fine PCG/V-cycle, FP64 residual and RQ)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the main leg (no other kernel classes, no second precision, no "
+                         "equal-accuracy FP64 leg, no 1/32 -> 1/128 workload)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the untimed accuracy pass (for profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES bytes (counter calibration)")
@@ -135,42 +147,94 @@ def cpu_baseline_nested(cfg_id: int, seconds: float, cores: int):
     return base, idx, ref
 
 
+def _worker_bytes(w) -> float:
+    """Peak memory of one oracle worker on workload w: the [s, 2 n^2] table of
+    coefficient terms (oracle.coeff.basis_at) or the sparse LU factors of the
+    finest mesh, whichever is larger, plus the interpreter."""
+    peak = 0.0
+    for lv in w.levels:
+        n, s = lv.n_fine, lv.s_fine
+        peak = max(peak, 8.0 * s * 2 * n * n, 4e9 * (n / 1024.0) ** 2)
+    return peak + 1e9
+
+
+def _oracle_pool_size(w) -> int:
+    """Oracle processes: every affinity core, as many as the host memory
+    holds (MemAvailable, at most 240 GiB) at the workload's peak per worker."""
+    cores = len(os.sched_getaffinity(0))
+    avail = 240 * 2.0 ** 30
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemAvailable:"):
+                avail = min(avail, float(line.split()[1]) * 1024.0 - 8e9)
+    except OSError:
+        pass
+    return max(1, min(cores, int(avail // _worker_bytes(w))))
+
+
 def cpu_baseline(cfg_id: int, seconds: float):
+    """The oracle as it stands on the host cores: a strided sample of the
+    workload's points, one per task, in rounds of at least one point per
+    process until about `seconds` have passed (a workload whose single point
+    takes longer runs one round)."""
     import multiprocessing as mp
     from synth import CONFIGS
     for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[v] = "1"
-    cores = len(os.sched_getaffinity(0))
-    cores = min(cores, 16)
     w = CONFIGS[cfg_id]
+    cores = _oracle_pool_size(w)
     if w.nested:
         return cpu_baseline_nested(cfg_id, seconds, cores)
     n_total = w.n_samples()
-    # calibrate: one sample of every level on this process, weighted by the
-    # level's share of the samples; then size the sample to ~`seconds`
-    per = 0.0
-    for l, lv in enumerate(w.levels):
-        t0 = time.perf_counter()
-        _oracle_worker((cfg_id, l, 0, 0))
-        per += (time.perf_counter() - t0) * w.R * lv.N / n_total
-    count = max(cores, int(seconds * cores / max(per, 1e-3)))
-    count = min(count, n_total)
-    flat = [(i * 7919) % n_total for i in range(count)]
-    idx = [(cfg_id, *_flat(w, i)) for i in flat]
+    order = [(i * 7919) % n_total for i in range(n_total)]
+    idx, vals = [], []
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
-        vals = pool.map(_oracle_worker, idx, chunksize=1)
+        take = cores
+        while len(idx) < n_total:
+            chunk = [(cfg_id, *_flat(w, i)) for i in order[len(idx):len(idx) + take]]
+            got = []
+            for v in pool.imap(_oracle_worker, chunk, chunksize=1):
+                got.append(v)
+                if len(got) % cores == 0 or len(got) == len(chunk):
+                    _log(f"oracle: {len(idx) + len(got)} samples, "
+                         f"{time.perf_counter() - t0:.0f} s")
+            vals += got
+            idx += chunk
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+            rate = len(idx) / el
+            take = max(cores, int((seconds - el) * rate))
     dt = time.perf_counter() - t0
     assert all(math.isfinite(v[0]) for v in vals)
+    count = len(idx)
     kind = "two-grid eigen-samples" if len(w.levels) == 1 else "level samples Y_l"
     base = {"value": count / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
             "sample": f"{count} of the {n_total} {kind} of the workload (strided indices), "
-                      f"scipy/SuperLU FP64, {cores} processes, {dt:.1f} s"}
+                      f"scipy/SuperLU FP64, {cores} processes (affinity cores, capped by host "
+                      f"memory at {_worker_bytes(w) / 1e9:.1f} GB each), {dt:.1f} s"}
     return base, [i[1:] for i in idx], vals
 
 
-def per_level(ctx, m, w, opts, idx=None, ref=None):
+def golden_points(cfg_id: int):
+    """Stored oracle values of workload cfg_id (tests/golden, written by a
+    script that calls only the oracle): ([(level, r, k)], [(Y, lambda)])."""
+    if cfg_id != 5:
+        return [], []
+    idx, ref = [], []
+    for name in ("large_twogrid_samples.json", "large_twogrid_chain.json"):
+        p = os.path.join(ROOT, "tests", "golden", name)
+        if not os.path.exists(p):
+            continue
+        for x in json.load(open(p))["samples"]:
+            idx.append((0, int(x["r"]), int(x["k"])))
+            ref.append((float(x["lambda"]), float(x["lambda"])))
+    return idx, ref
+
+
+def per_level(ctx, m, w, opts, idx=None, ref=None, bound=None):
     """Untimed pass over every level with mlqmc_eig_level and the bench
     options: samples/s per level and, given oracle values of the CPU-baseline
     sample, the per-sample error of Y_l (relative to lambda) against them."""
@@ -210,7 +274,7 @@ def per_level(ctx, m, w, opts, idx=None, ref=None):
         e = np.asarray(errs)
         acc = {"max_rel_err": float(e.max()), "median_rel_err": float(np.median(e)),
                "samples": int(e.size), "flagged": int(sum(x["flagged"] for x in out)),
-               "bound": 1e-10 if opts.prec == m.MLQMC_FP64 else 1e-8,
+               "bound": bound or (1e-10 if opts.prec == m.MLQMC_FP64 else 1e-8),
                "quantity": "Y_l = lambda^l - lambda^(l-1), error relative to lambda^l"
                if len(w.levels) > 1 else "lambda"}
     return out, acc
@@ -437,6 +501,165 @@ def _traffic(kernel: str, prec: str = "fp64", cfg: int = 2):
         return None
 
 
+def _workload_opts(m, prec: str, **kw):
+    return m.default_opts(prec=m.MLQMC_MIXED if prec == "mixed" else m.MLQMC_FP64, **kw)
+
+
+def _default_class(w) -> str:
+    per_sample = all(lv.n_fine <= (128 if w.problem == 2 else 32) for lv in w.levels)
+    if not any(lv.n_coarse for lv in w.levels):
+        return "rqi"
+    return "lds" if per_sample else "post"
+
+
+KCLS_NAME = {"post": "k_post", "pre": "k_pre", "apply": "k_pupdate_apply",
+             "coeff": "k_expand_mfma", "lds": "k_tg_small", "rqi": "k_rqi"}
+
+
+def timed_leg(ctx, m, w, opts, steps: int, warmup: int, kernel_class: str):
+    """`warmup` untimed and `steps` timed estimates of workload w (one step =
+    one mlqmc_estimate over all its levels), the launches of `kernel_class`
+    in which every sample is active bracketed by HIP events on the library's
+    stream.  Returns samples/s, ms per step, the last estimate and the live
+    kernel timing."""
+    import torch
+    levels = [_lv6(lv) for lv in w.levels]
+    Ns = [lv.N for lv in w.levels]
+    if w.nested:
+        z_sh, sh_sh = w.z_shared(), w.shifts_shared()
+    else:
+        zs = [w.z(l) for l in range(len(w.levels))]
+        shs = [w.shifts(l) for l in range(len(w.levels))]
+
+    def step():
+        if w.nested:
+            st, Q, Qh, V, est, _ = ctx.estimate_nested(levels, Ns, w.R, z_sh, sh_sh, opts=opts)
+        else:
+            st, Q, Qh, V, est = ctx.estimate(levels, Ns, w.R, zs, shs, opts=opts)
+        if st != m.MLQMC_OK:
+            raise RuntimeError(f"estimate flagged samples (status {st})")
+        return est
+
+    for _ in range(warmup):
+        step()
+    kcls = {"post": m.K_SMOOTH, "pre": m.K_PRE, "apply": m.K_APPLY, "coeff": m.K_COEFF,
+            "lds": m.K_TG_LDS, "rqi": m.K_COARSE}[kernel_class]
+    ctx.set_timing(kcls)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    est = None
+    for _ in range(steps):
+        est = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, kms, kbytes = ctx.get_timing()
+    ctx.set_timing(m.K_NONE)
+    return {"value": w.n_samples() * steps / dt, "ms_per_step": 1e3 * dt / steps, "est": est,
+            "launches": launches, "kms": kms, "kbytes": kbytes, "steps": steps}
+
+
+def roofline(ctx, m, w, opts, prec: str, kernel_class: str, leg, cfg: int):
+    """The roofline object of one kernel class from a timed leg: achieved =
+    algorithmic bytes (or flops) per launch / live average launch time."""
+    launches, kms, kbytes, steps = leg["launches"], leg["kms"], leg["kbytes"], leg["steps"]
+    if not (launches > 0 and kms > 0):
+        return None
+    kname = KCLS_NAME[kernel_class]
+    avg_ms = kms / launches
+    if kernel_class in ("rqi", "lds"):
+        # LDS-resident solvers: vector arithmetic on data in LDS, against the
+        # vector peak of the precision they compute in
+        if kernel_class == "lds" and any(lv.n_fine > 32 for lv in w.levels):
+            kname = "k_tg_small+k_tg_global"
+        fl = (rqi_step_flops if kernel_class == "rqi" else lds_step_flops)(ctx, m, w, opts)
+        flops_per_launch = fl * steps / launches
+        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        peak = PEAK_FP64_VALU_TFS if prec == "fp64" else PEAK_FP32_VALU_TFS
+        return {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
+                "algorithmic_flops_per_launch": flops_per_launch}
+    if kernel_class == "coeff":
+        # the coefficient product on FP64 MFMA: 2 s E flops per sample
+        # (E = edge weights of the padded mesh) on the batched meshes
+        flops_step = 0.0
+        for lv in w.levels:
+            if not lv.n_coarse:
+                continue
+            meshes = [(lv.n_fine, lv.s_fine)]
+            if lv.n_prev and not w.nested and not (lv.n_prev == lv.n_coarse and
+                                                    lv.s_prev == lv.s_coarse):
+                meshes.append((lv.n_prev, lv.s_prev))
+            for nm, sm in meshes:
+                if nm >= 64:
+                    flops_step += 2.0 * sm * 2 * (nm + 2) * nm * w.R * lv.N
+        flops_per_launch = flops_step * steps / launches
+        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        return {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 2),
+                "peak": PEAK_FP64_MFMA_TFS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_MFMA_TFS, 4),
+                "traffic": _traffic(kname, prec, cfg), "avg_launch_us": round(avg_ms * 1e3, 2),
+                "launches": launches, "algorithmic_flops_per_launch": flops_per_launch,
+                "hbm_GBs": round(kbytes / launches / (avg_ms * 1e-3) / 1e9, 1)}
+    bytes_per_launch = kbytes / launches
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = _traffic(kname, prec, cfg)
+    roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
+            "algorithmic_bytes_per_launch": bytes_per_launch}
+    if traffic:
+        # the counted HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
+        # over the same live launch time: what the memory system moved
+        tg = traffic / (avg_ms * 1e-3) / 1e9
+        roof["traffic_GBs"] = round(tg, 1)
+        roof["traffic_frac"] = round(tg / PEAK_HBM_GBS, 4)
+    return roof
+
+
+def rq_counts(ctx, m, w, opts, count: int = 256):
+    """RQ iterations of the coarse eigensolve of the first two-grid level on
+    `count` consecutive points of shift 0: at the paper's criterion (section 5:
+    |sigma_k - sigma_{k-1}| <= 5e-8, exact inner solves, here to 1e-12) from
+    the fixed start and from the previous point's eigenvector (section 4.3),
+    and with the library's own settings (relative 1e-8, inner solves to the
+    bench options' rq_lin_rtol) from the previous point."""
+    import numpy as np
+    lv = next((lv for lv in w.levels if lv.n_coarse), None)
+    if lv is None or w.nested:
+        return None
+    l = list(w.levels).index(lv)
+    count = min(count, lv.N)
+    full = np.empty((count, lv.s_fine))
+    ctx.lattice_points(lv.N, w.z(l), w.shifts(l)[0], 0, count, full)
+    Y = np.ascontiguousarray(full[:, :lv.s_coarse]) if lv.s_coarse else np.zeros((count, 1))
+    out = {"mesh": f"1/{lv.n_coarse}", "S": lv.s_coarse, "points": count}
+    runs = [("paper_cold", 0, m.default_opts(prec=opts.prec, eig_atol=5e-8, rq_lin_rtol=1e-12,
+                                             max_lin_iter=400, chain_len=count)),
+            ("paper_nearby", 1, m.default_opts(prec=opts.prec, eig_atol=5e-8, rq_lin_rtol=1e-12,
+                                               max_lin_iter=400, chain_len=count)),
+            ("library_nearby", 1, m.default_opts(prec=opts.prec, chain_len=count))]
+    for name, warm, o in runs:
+        lam = np.empty(count)
+        fl = np.zeros(count, np.uint8)
+        rq = np.zeros(count, np.int32)
+        ctx.eig_level((lv.n_coarse, lv.s_coarse, 0, 0, 0, 0), Y, lam, fl, rq_iters=rq,
+                      warm_chain=warm, opts=o)
+        out[name] = {"mean": round(float(rq.mean()), 3),
+                     "histogram": {int(k): int(v) for k, v in
+                                   zip(*np.unique(rq, return_counts=True))},
+                     "flagged": int((fl != 0).sum())}
+    return out
+
+
+def _brief(roof):
+    if not roof:
+        return None
+    keep = ("kernel", "achieved", "peak", "unit", "frac", "avg_launch_us", "launches",
+            "traffic_frac")
+    return {k: roof[k] for k in keep if k in roof}
+
+
 def main():
     a = _parse()
     if a.gpus != 1:
@@ -445,7 +668,7 @@ def main():
               "the per-level sums)",
               file=sys.stderr)
         return 2
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
     if a.copy_probe:
         # plain copy kernel of known size: calibrates the HBM byte counters
@@ -461,159 +684,117 @@ def main():
     from synth import CONFIGS
 
     w = CONFIGS[a.cfg]
-    fam = w.family()
     torch.cuda.init()
     if a.plain_vs_enhanced:
-        o = m.default_opts(prec=m.MLQMC_MIXED if a.prec == "mixed" else m.MLQMC_FP64)
-        print(json.dumps(plain_vs_enhanced(m, w, o)), flush=True)
+        print(json.dumps(plain_vs_enhanced(m, w, _workload_opts(m, a.prec))), flush=True)
         return 0
-    ctx = m.Context(fam, device=0)
+    extras = (not a.no_extras) and a.cfg in (2, 5)
+    ctx = m.Context(w.family(), device=0)
     tuned = ctx.apply_tuning()  # the autotuner's table for this device, if shipped
-    levels = [_lv6(lv) for lv in w.levels]
-    Ns = [lv.N for lv in w.levels]
-    zs = shs = None
-    if not w.nested:
-        zs = [w.z(l) for l in range(len(w.levels))]
-        shs = [w.shifts(l) for l in range(len(w.levels))]
-    opts = m.default_opts(prec=m.MLQMC_MIXED if a.prec == "mixed" else m.MLQMC_FP64)
-    n_samples = w.n_samples()
+    opts = _workload_opts(m, a.prec)
+    kclass = a.kernel_class or _default_class(w)
+    _log(f"{w.name} {a.prec}: {a.warmup} warm-up + {a.steps} timed steps")
+    main_leg = timed_leg(ctx, m, w, opts, a.steps, a.warmup, kclass)
+    roof = roofline(ctx, m, w, opts, a.prec, kclass, main_leg, a.cfg)
 
-    if w.nested:
-        z_sh, sh_sh = w.z_shared(), w.shifts_shared()
-
-    def step():
-        if w.nested:
-            st, Q, Qh, V, est, _ = ctx.estimate_nested(levels, Ns, w.R, z_sh, sh_sh, opts=opts)
-        else:
-            st, Q, Qh, V, est = ctx.estimate(levels, Ns, w.R, zs, shs, opts=opts)
-        if st != m.MLQMC_OK:
-            raise RuntimeError(f"estimate flagged samples (status {st})")
-        return est
-
-    for _ in range(a.warmup):
-        step()
-    if a.kernel_class is None:
-        per_sample = all(lv.n_fine <= (128 if w.problem == 2 else 32) for lv in w.levels)
-        if not any(lv.n_coarse for lv in w.levels):
-            a.kernel_class = "rqi"
-        else:
-            a.kernel_class = "lds" if per_sample else "post"
-    kcls = {"post": m.K_SMOOTH, "pre": m.K_PRE, "apply": m.K_APPLY,
-            "coeff": m.K_COEFF, "lds": m.K_TG_LDS, "rqi": m.K_COARSE}[a.kernel_class]
-    ctx.set_timing(kcls)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    est = None
-    for _ in range(a.steps):
-        est = step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    launches, kms, kbytes = ctx.get_timing()
-    ctx.set_timing(m.K_NONE)
-    ms_per_step = 1e3 * dt / a.steps
-    value = n_samples * a.steps / dt
-
-    kname = {"post": "k_post", "pre": "k_pre", "apply": "k_pupdate_apply",
-             "coeff": "k_expand_mfma", "lds": "k_tg_small", "rqi": "k_rqi"}[a.kernel_class]
-    if a.kernel_class == "lds" and any(lv.n_fine > 32 for lv in w.levels):
-        kname = "k_tg_small+k_tg_global"
-    roof = None
-    if launches > 0 and kms > 0 and a.kernel_class == "rqi":
-        # the warm-started eigensolve in LDS: like the two-grid update, bound
-        # by vector arithmetic on LDS data, against the vector peak of its
-        # precision
-        avg_ms = kms / launches
-        flops_per_launch = rqi_step_flops(ctx, m, w, opts) * a.steps / launches
-        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-        peak = PEAK_FP64_VALU_TFS if a.prec == "fp64" else PEAK_FP32_VALU_TFS
-        roof = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
-                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": None, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
-                "algorithmic_flops_per_launch": flops_per_launch}
-    elif launches > 0 and kms > 0 and a.kernel_class == "lds":
-        # the LDS-resident two-grid update: vector arithmetic on data in LDS,
-        # so the vector peak of its precision bounds it (FP64, or FP32 for
-        # the mixed solve, whose Rayleigh quotients stay FP64); HBM traffic is
-        # the tables and points only
-        avg_ms = kms / launches
-        flops_per_launch = lds_step_flops(ctx, m, w, opts) * a.steps / launches
-        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-        peak = PEAK_FP64_VALU_TFS if a.prec == "fp64" else PEAK_FP32_VALU_TFS
-        roof = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3),
-                "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
-                "algorithmic_flops_per_launch": flops_per_launch}
-    elif launches > 0 and kms > 0 and a.kernel_class == "coeff":
-        # the coefficient product on FP64 MFMA: 2 s E flops per sample, every
-        # sample expanded once per step (E = edge weights of the padded mesh)
-        avg_ms = kms / launches
-        flops_step = 0.0
-        for lv in w.levels:
-            if not lv.n_coarse:
-                continue
-            meshes = [(lv.n_fine, lv.s_fine)]
-            if lv.n_prev and not w.nested and not (lv.n_prev == lv.n_coarse and
-                                                    lv.s_prev == lv.s_coarse):
-                meshes.append((lv.n_prev, lv.s_prev))
-            for nm, sm in meshes:
-                if nm >= 64:  # meshes of the batched path (finer ones solve in LDS)
-                    flops_step += 2.0 * sm * 2 * (nm + 2) * nm * w.R * lv.N
-        flops_per_launch = flops_step * a.steps / launches
-        achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 2),
-                "peak": PEAK_FP64_MFMA_TFS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_MFMA_TFS, 4),
-                "traffic": _traffic(kname, a.prec, a.cfg),
-                "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
-                "algorithmic_flops_per_launch": flops_per_launch,
-                "hbm_GBs": round(kbytes / launches / (avg_ms * 1e-3) / 1e9, 1)}
-    elif launches > 0 and kms > 0:
-        avg_ms = kms / launches
-        bytes_per_launch = kbytes / launches
-        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = _traffic(kname, a.prec, a.cfg)
-        roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
-                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": traffic, "avg_launch_us": round(avg_ms * 1e3, 2),
-                "launches": launches, "algorithmic_bytes_per_launch": bytes_per_launch}
-        if traffic:
-            # the counted HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
-            # over the same live launch time: what the memory system moved
-            tg = traffic / (avg_ms * 1e-3) / 1e9
-            roof["traffic_GBs"] = round(tg, 1)
-            roof["traffic_frac"] = round(tg / PEAK_HBM_GBS, 4)
+    extra = {}
+    legs = {}
+    if extras:
+        # the other batched kernels of the same step (one timed step each)
+        rates = {}
+        for kc in ("pre", "apply", "coeff"):
+            _log(f"{w.name} {a.prec}: kernel class {kc}")
+            leg = timed_leg(ctx, m, w, opts, 1, 0, kc)
+            rates[KCLS_NAME[kc]] = _brief(roofline(ctx, m, w, opts, a.prec, kc, leg, a.cfg))
+        extra["kernels"] = rates
+        # mixed precision, and FP64 stopped at the mixed path's tolerances
+        # (equal accuracy), on the same workload
+        k2 = min(a.steps, 5)
+        other = "mixed" if a.prec == "fp64" else "fp64"
+        o_other = _workload_opts(m, other)
+        _log(f"{w.name} {other}: 1 warm-up + {k2} timed steps")
+        legs[other] = (o_other, timed_leg(ctx, m, w, o_other, k2, 1, kclass))
+        extra["rq_iterations"] = rq_counts(ctx, m, w, opts)
+        o_eq = _workload_opts(m, "fp64", lam_rtol=5e-10, lin_rtol=1e-7)
+        _log(f"{w.name} fp64 at the mixed tolerances: 1 warm-up + {k2} timed steps")
+        legs["fp64_mixed_tol"] = (o_eq, timed_leg(ctx, m, w, o_eq, k2, 1, kclass))
 
     cpu = None
     idx = ref = None
     if not a.no_cpu_baseline:
+        _log(f"oracle CPU baseline ({_oracle_pool_size(w)} processes)")
         cpu, idx, ref = cpu_baseline(a.cfg, a.cpu_seconds)
-    if w.nested:
+    gi, gr = golden_points(a.cfg)
+    aidx = (idx or []) + gi
+    aref = (ref or []) + gr
+    _log("accuracy pass")
+    if a.no_accuracy:
+        levels_out, acc = None, None
+    elif w.nested:
         levels_out, acc = per_level_nested(ctx, m, w, opts, idx, ref)
     else:
-        levels_out, acc = per_level(ctx, m, w, opts, idx, ref)
+        levels_out, acc = per_level(ctx, m, w, opts, aidx or None, aref or None)
+    if acc is not None and gi:
+        acc["golden_samples"] = len(gi)
+    if extras:
+        for name, (o, leg) in legs.items():
+            lo, lacc = per_level(ctx, m, w, o, aidx or None, aref or None, bound=1e-8)
+            prec_name = "mixed" if o.prec == m.MLQMC_MIXED else "fp64"
+            extra[name] = {"samples_per_s": round(leg["value"], 1),
+                           "ms_per_step": round(leg["ms_per_step"], 3), "steps": leg["steps"],
+                           "estimate": leg["est"][0],
+                           "roofline": _brief(roofline(ctx, m, w, o, prec_name, kclass, leg,
+                                                       a.cfg)),
+                           "accuracy_vs_oracle": lacc}
+        if "mixed" in extra:
+            fp64_v = main_leg["value"] if a.prec == "fp64" else legs["fp64"][1]["value"]
+            mixed_v = legs["mixed"][1]["value"] if a.prec == "fp64" else main_leg["value"]
+            extra["mixed_over_fp64"] = round(mixed_v / fp64_v, 3)
+            extra["mixed_over_fp64_at_mixed_tolerances"] = round(
+                mixed_v / legs["fp64_mixed_tol"][1]["value"], 3)
+    ctx.close()
+    if extras and a.cfg != 2:
+        # the two-grid 1/32 -> 1/128 workload (s = 64), both precisions
+        w2 = CONFIGS[2]
+        c2 = m.Context(w2.family(), device=0)
+        c2.apply_tuning()
+        small = {}
+        for prec in ("fp64", "mixed"):
+            _log(f"{w2.name} {prec}")
+            o2 = _workload_opts(m, prec)
+            leg = timed_leg(c2, m, w2, o2, max(a.steps, 5), 1, "post")
+            small[prec] = {"samples_per_s": round(leg["value"], 1),
+                           "ms_per_step": round(leg["ms_per_step"], 3),
+                           "roofline": _brief(roofline(c2, m, w2, o2, prec, "post", leg, 2))}
+        c2.close()
+        extra[w2.name] = small
 
     out = {
         "metric": "two-grid eigen-samples/sec per level; stencil HBM GB/s in roofline"
                   if w.problem == 1 else
                   "two-grid eigen-samples/sec per level (Problem 2, islands); LDS-update "
                   "FP64 TFLOP/s in roofline",
-        "value": round(value, 1), "unit": "samples/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
+        "value": round(main_leg["value"], 1), "unit": "samples/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(main_leg["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if a.prec == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": w.name, "problem": w.problem, "levels": len(w.levels),
                    "h": [f"1/{lv.n_fine}" for lv in w.levels],
                    "H": [f"1/{lv.n_coarse}" if lv.n_coarse else None for lv in w.levels],
                    "s": [lv.s_fine for lv in w.levels], "S": [lv.s_coarse for lv in w.levels],
-                   "N": Ns, "R": w.R, "samples_per_step": n_samples,
-                   "nested_shared_shifts": bool(w.nested),
-                   "estimate": est[0], "variance": est[1]},
+                   "N": [lv.N for lv in w.levels], "R": w.R,
+                   "samples_per_step": w.n_samples(), "nested_shared_shifts": bool(w.nested),
+                   "estimate": main_leg["est"][0], "variance": main_leg["est"][1]},
         "roofline": roof, "cpu_baseline": cpu, "accuracy_vs_oracle": acc,
         "per_level": levels_out, "tuning_entries_applied": tuned,
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def _log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

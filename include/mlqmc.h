@@ -101,6 +101,9 @@ typedef struct {
                                 (cached per layout); 0: launch them one by one */
   int32_t io_on_device;      /* 1: device pointers, 0: host pointers */
   int64_t device_mem_cap;    /* bytes; 0 = unlimited (a test hook for MLQMC_ENOMEM) */
+  double eig_atol;           /* > 0: the RQ iteration stops when |sigma_k - sigma_{k-1}| <= eig_atol
+                                instead (an absolute tolerance, as in section 5, which uses
+                                5e-8); 0 (default): eig_rtol */
 } mlqmc_opts;
 
 /* Fills *opt with the defaults (FP64, eig_rtol 1e-8, max_rq_iter 12,

@@ -63,7 +63,7 @@ class Opts(C.Structure):
                 ("lin_rtol", C.c_double), ("lam_rtol", C.c_double), ("rq_lin_rtol", C.c_double),
                 ("max_lin_iter", C.c_int32), ("chain_len", C.c_int32), ("batch", C.c_int32),
                 ("pcg_graph", C.c_int32), ("io_on_device", C.c_int32),
-                ("device_mem_cap", C.c_int64)]
+                ("device_mem_cap", C.c_int64), ("eig_atol", C.c_double)]
 
 
 _lib = None

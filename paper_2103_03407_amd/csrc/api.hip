@@ -72,6 +72,8 @@ struct mlqmc_ctx {
   // tuning: workgroups in flight for the batched stencil kernels, per
   // (fine mesh, precision); absent = the library default
   std::map<std::pair<int, int>, int64_t> target_blocks;
+  // eigensolve workgroups resident on the device at once, per (mesh, precision)
+  std::map<std::pair<int, int>, int> chain_slots;
   int64_t target_for(int n, int prec) const {
     auto it = target_blocks.find({n, prec});
     return it == target_blocks.end() ? 0 : it->second;
@@ -312,8 +314,10 @@ mlqmc_status check_opts(mlqmc_ctx* ctx, const mlqmc_opts* o) {
   if (!o) return ctx->fail(MLQMC_EINVAL, "opts is NULL");
   if (o->prec != MLQMC_FP64 && o->prec != MLQMC_MIXED)
     return ctx->fail(MLQMC_EINVAL, "unknown precision %d", o->prec);
-  if (!(o->eig_rtol > 0) || !(o->lin_rtol >= 0) || !(o->lam_rtol >= 0) || !(o->rq_lin_rtol > 0))
-    return ctx->fail(MLQMC_EINVAL, "tolerances must be positive (lin_rtol, lam_rtol: >= 0)");
+  if (!(o->eig_rtol > 0) || !(o->eig_atol >= 0) || !(o->lin_rtol >= 0) || !(o->lam_rtol >= 0) ||
+      !(o->rq_lin_rtol > 0))
+    return ctx->fail(MLQMC_EINVAL,
+                     "tolerances must be positive (eig_atol, lin_rtol, lam_rtol: >= 0)");
   if (o->max_rq_iter < 1 || o->max_lin_iter < 1)
     return ctx->fail(MLQMC_EINVAL, "iteration caps must be >= 1");
   if (o->device_mem_cap < 0) return ctx->fail(MLQMC_EINVAL, "device_mem_cap must be >= 0");
@@ -375,14 +379,15 @@ mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
 
 // Samples per warm-start chain of the eigensolve on mesh N: as short as keeps
 // every workgroup slot of the device busy (one chain per workgroup).
-int default_chain(int64_t n, int warm, int chain_len, int N, int mixed) {
+// The occupancy is cached in the context (a context is used by one host
+// thread at a time), per (mesh, precision), for the context's family.
+int default_chain(mlqmc_ctx* ctx, int64_t n, int warm, int chain_len, int N, int mixed) {
   if (!warm) return 1;
   if (chain_len > 0) return chain_len;
-  static std::map<std::pair<int, int>, int> slots;  // (mesh, precision) -> chains in flight
-  auto it = slots.find({N, mixed});
-  if (it == slots.end()) {
-    const int c = rqi_chains_in_flight(N, mixed);
-    it = slots.emplace(std::make_pair(N, mixed), c > 0 ? c : 512).first;
+  auto it = ctx->chain_slots.find({N, mixed});
+  if (it == ctx->chain_slots.end()) {
+    const int c = rqi_chains_in_flight(N, mixed, ctx->islands ? 1 : 0);
+    it = ctx->chain_slots.emplace(std::make_pair(N, mixed), c > 0 ? c : 512).first;
   }
   const int64_t target = it->second;
   const int64_t c = (n + target - 1) / target;
@@ -788,6 +793,7 @@ RqiArgs rqi_base(mlqmc_ctx* ctx, const mlqmc_opts* o, int64_t n, const double* Y
   a.chain_len = chain;
   a.warm = warm;
   a.eig_rtol = o->eig_rtol;
+  a.eig_atol = o->eig_atol;
   a.max_rq = o->max_rq_iter;
   a.lin_rtol = o->rq_lin_rtol;
   a.max_lin = o->max_lin_iter;
@@ -804,9 +810,9 @@ RqiArgs rqi_base(mlqmc_ctx* ctx, const mlqmc_opts* o, int64_t n, const double* Y
 
 // Chain length for R shifts of N points each: a power of two dividing N, so
 // no warm-start chain crosses from one shift to the next.
-int shift_chain(int64_t N, int R, const mlqmc_opts* o, int mesh) {
+int shift_chain(mlqmc_ctx* ctx, int64_t N, int R, const mlqmc_opts* o, int mesh) {
   const int chain =
-      default_chain(N * R, 1, o->chain_len, mesh, o->prec == MLQMC_MIXED ? 1 : 0);
+      default_chain(ctx, N * R, 1, o->chain_len, mesh, o->prec == MLQMC_MIXED ? 1 : 0);
   int c2 = 1;
   while (c2 < chain) c2 *= 2;
   return (int)std::min<int64_t>(c2, N);
@@ -825,7 +831,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   CK(hipMemsetAsync(lin_iters, 0, n * sizeof(int), st), "memset");
   const int mixed = o->prec == MLQMC_MIXED ? 1 : 0;
   const int chain =
-      default_chain(n, warm, o->chain_len, L->n_coarse ? L->n_coarse : L->n_fine, mixed);
+      default_chain(ctx, n, warm, o->chain_len, L->n_coarse ? L->n_coarse : L->n_fine, mixed);
   RqiArgs a = rqi_base(ctx, o, n, Y, ldY, chain, warm, rq_iters, lin_iters, flags);
   if (L->n_coarse == 0) {
     Table* tb = nullptr;
@@ -1360,7 +1366,7 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
     CS(ctx->getT("e_fl", n, &fl));
     CK(launch_lattice_multi(N[l], s, R, dz, dsh, N[l], Y, std::max(s, 1), st), "lattice");
     mlqmc_opts oo = *o;
-    oo.chain_len = shift_chain(N[l], R, o, L.n_coarse ? L.n_coarse : L.n_fine);
+    oo.chain_len = shift_chain(ctx, N[l], R, o, L.n_coarse ? L.n_coarse : L.n_fine);
     double *gv = nullptr, *gp = nullptr;
     if (dG) {
       CS(ctx->getT("e_g", n, &gv));
@@ -1486,7 +1492,7 @@ mlqmc_status nested_core(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, cons
     Table* tb = nullptr;
     CS(ctx->table(n0, s0, &tb));
     // a power of two dividing the points per shift: no chain crosses shifts
-    int chain = shift_chain(n0pts, R, o, n0);
+    int chain = shift_chain(ctx, n0pts, R, o, n0);
     while (n0pts % chain) chain /= 2;
     RqiArgs ra = rqi_base(ctx, o, B0, Y, std::max(s0, 1), chain, 1, rqi, lini, fl);
     ra.S = s0;

@@ -136,7 +136,8 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* 
       lds::rayleigh_parts<NT, N, T, WF, kR>(a, s_v, wf, vMv, vAv);
       lds::scale_vec<NT, N>(s_v, 1.0 / sqrt(vMv));
       const double sig_new = vAv / vMv;
-      const bool done = fabs(sig_new - sigma) <= A.eig_rtol * fabs(sig_new);
+      const double tol = A.eig_atol > 0.0 ? A.eig_atol : A.eig_rtol * fabs(sig_new);
+      const bool done = fabs(sig_new - sigma) <= tol;
       sigma = sig_new;
       if (!isfinite(sigma)) break;
       if (done) {
@@ -520,27 +521,35 @@ hipError_t tg_global_n(const TgSmallArgs& a, hipStream_t st) {
 }  // namespace
 
 template <int N>
-hipError_t rqi_occupancy(int* per, int mixed) {
+hipError_t rqi_occupancy(int* per, int mixed, int reaction) {
   constexpr int NT = threads_for<N>();
+  if (reaction) {
+    if (mixed)
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_rqi<N, NT, float, true>, NT, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_rqi<N, NT, double, true>, NT, 0);
+  }
   if (mixed) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_rqi<N, NT, float>, NT, 0);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_rqi<N, NT, double>, NT, 0);
 }
 
 // Workgroups of the eigensolve on mesh N that the current device holds at
-// once (compute units x resident workgroups per unit); 0 if unknown.
-int rqi_chains_in_flight(int N, int mixed) {
+// once (compute units x resident workgroups per unit); 0 if unknown.  reaction
+// selects the Problem 2 instantiation (more LDS per workgroup).
+int rqi_chains_in_flight(int N, int mixed, int reaction) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   hipError_t e = hipErrorInvalidValue;
   switch (N) {
-    case 4: e = rqi_occupancy<4>(&per, mixed); break;
-    case 8: e = rqi_occupancy<8>(&per, mixed); break;
-    case 16: e = rqi_occupancy<16>(&per, mixed); break;
-    case 32: e = rqi_occupancy<32>(&per, mixed); break;
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rqi_global<64, 512>, 512, 0);
-             break;
+    case 4: e = rqi_occupancy<4>(&per, mixed, reaction); break;
+    case 8: e = rqi_occupancy<8>(&per, mixed, reaction); break;
+    case 16: e = rqi_occupancy<16>(&per, mixed, reaction); break;
+    case 32: e = rqi_occupancy<32>(&per, mixed, reaction); break;
+    case 64:
+      if (!reaction)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rqi_global<64, 512>, 512, 0);
+      break;
     default: break;
   }
   if (e != hipSuccess || per <= 0) return 0;

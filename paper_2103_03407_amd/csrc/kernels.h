@@ -22,6 +22,7 @@ struct RqiArgs {
   int chain_len;        // samples per warm-start chain (one workgroup per chain)
   int warm;             // 1: start from the previous sample's eigenvector
   double eig_rtol;
+  double eig_atol;  // > 0: absolute RQ stopping tolerance instead of eig_rtol
   int max_rq;
   double lin_rtol;
   int max_lin;
@@ -46,7 +47,7 @@ int64_t rqi_scratch_doubles(int N);
 // (Problem 2 on 1/64; 0: all in LDS)
 int64_t tg_scratch_doubles(int N, int mixed);
 // workgroups of the eigensolve on mesh N resident on the current device at once
-int rqi_chains_in_flight(int N, int mixed);
+int rqi_chains_in_flight(int N, int mixed, int reaction);
 
 struct TgSmallArgs {
   const double* Y;      // [n x ldY], first s columns

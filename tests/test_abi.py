@@ -42,7 +42,7 @@ def test_default_opts():
     assert o.prec == m.MLQMC_FP64
     assert o.eig_rtol == 1e-8 and o.lin_rtol == 0.0 and o.lam_rtol == 0.0 and o.rq_lin_rtol == 1e-2
     assert o.max_rq_iter == 12 and o.max_lin_iter == 60 and o.pcg_graph == 1
-    assert o.io_on_device == 0 and o.device_mem_cap == 0
+    assert o.io_on_device == 0 and o.device_mem_cap == 0 and o.eig_atol == 0.0
 
 
 @pytest.mark.parametrize("bad", ["nonpositive", "k_zero", "nan"])

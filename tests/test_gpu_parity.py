@@ -158,20 +158,25 @@ def test_two_grid_cfg2_shape(ctx, fam):
     assert li.min() >= 1
 
 
-@pytest.mark.parametrize("warm", [0, 1])
-def test_two_grid_coarse_64(ctx, fam, warm):
-    # coarse mesh 1/64: the eigensolve keeps its top level in global scratch
+@pytest.mark.parametrize("warm,prec,tol", [(0, "fp64", LAM_RTOL), (1, "fp64", LAM_RTOL),
+                                           (1, "mixed", 1e-8)])
+def test_two_grid_coarse_64(ctx, fam, warm, prec, tol):
+    # coarse mesh 1/64: the eigensolve keeps its top level in global scratch;
+    # warm = 1 runs the five points as one chain (each eigensolve starts from
+    # the previous point's vector), so the warm path is really taken
     cnt = 5
     Y = np.ascontiguousarray(_points(1024, 32, 5, 0, 1, range(40, 40 + cnt)))
     lam, lamc = np.empty(cnt), np.empty(cnt)
     fl = np.zeros(cnt, np.uint8)
     rq = np.zeros(cnt, np.int32)
+    o = m.default_opts(prec=m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED,
+                       chain_len=cnt if warm else 0)
     ctx.eig_level((128, 32, 64, 16, 0, 0), Y, lam, fl, lam_coarse=lamc, rq_iters=rq,
-                  warm_chain=warm)
+                  warm_chain=warm, opts=o)
     assert not fl.any(), fl
     for k in range(cnt):
         tg, lamH, _ = twogrid.two_grid(128, 32, 64, 16, Y[k], fam)
-        assert abs(lam[k] - tg) <= LAM_RTOL * tg
+        assert abs(lam[k] - tg) <= tol * tg
         assert abs(lamc[k] - lamH) <= LAM_RTOL * lamH
     assert rq.min() >= 1
 
@@ -199,6 +204,38 @@ def test_large_two_grid_golden(ctx, prec, tol):
     ctx_l = m.Context(w.family())
     try:
         ctx_l.eig_level(_lv6(lv), Y, lam, fl, lam_coarse=lamc, warm_chain=0, opts=o)
+    finally:
+        ctx_l.close()
+    assert not fl.any(), fl
+    for k, p in enumerate(pts):
+        assert abs(lamc[k] - p["lambda_H"]) <= LAM_RTOL * p["lambda_H"]
+        assert abs(lam[k] - p["lambda"]) <= tol * p["lambda"], (k, lam[k], p["lambda"])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", LAM_RTOL), ("mixed", 1e-8)])
+@pytest.mark.parametrize("chain", [4, 8])
+def test_large_two_grid_warm_chain(ctx, prec, tol, chain):
+    # H = 1/64 -> h = 1/1024, s = 512, S = 23 on eight consecutive points of one
+    # shift, solved as warm-start chains of 4 or 8 (section 4.3), against
+    # stored oracle values
+    import json
+    import os
+    p = os.path.join(os.path.dirname(__file__), "golden", "large_twogrid_chain.json")
+    g = json.load(open(p))
+    w = CONFIGS[5]
+    lv = w.levels[0]
+    z, sh = w.z(0), w.shifts(0)
+    pts = g["samples"]
+    assert [p["k"] for p in pts] == list(range(pts[0]["k"], pts[0]["k"] + len(pts)))
+    Y = np.ascontiguousarray(np.stack([qmc.lattice_point(z, lv.N, sh[p["r"]], p["k"]) for p in pts]))
+    n = len(pts)
+    lam, lamc = np.empty(n), np.empty(n)
+    fl = np.zeros(n, np.uint8)
+    rq = np.zeros(n, np.int32)
+    o = m.default_opts(prec=m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED, chain_len=chain)
+    ctx_l = m.Context(w.family())
+    try:
+        ctx_l.eig_level(_lv6(lv), Y, lam, fl, lam_coarse=lamc, rq_iters=rq, warm_chain=1, opts=o)
     finally:
         ctx_l.close()
     assert not fl.any(), fl
@@ -576,14 +613,16 @@ def test_mixed_multilevel_top_level(ctx, fam):
 # ---------------- direct eigensolves on 1/64 (top level in global scratch) ----------------
 
 @pytest.mark.parametrize("lv", [(64, 16, 0, 0, 0, 0), (64, 16, 0, 0, 32, 8)])
-def test_direct_level_64(ctx, fam, lv):
+@pytest.mark.parametrize("chain", [1, 9])
+def test_direct_level_64(ctx, fam, lv, chain):
+    # chain 9: the nine points form one warm-start chain on each mesh
     spec = LevelSpec(*lv, 0)
     count = 9
     Y = np.ascontiguousarray(_points(256, lv[1], 1, 0, 0, range(count)))
     lam, lamp, g, gp = (np.empty(count) for _ in range(4))
     fl = np.zeros(count, np.uint8)
     ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp if lv[4] else None, g=g,
-                  g_prev=gp if lv[4] else None)
+                  g_prev=gp if lv[4] else None, opts=m.default_opts(chain_len=chain))
     assert not fl.any()
     for k in range(count):
         v = mlqmc.level_value(spec, Y[k], fam)
