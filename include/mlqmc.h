@@ -224,6 +224,34 @@ mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* lvl, const mlqmc
                              double* lam_prev, double* lam_coarse, int32_t* rq_iters,
                              int32_t* lin_iters, uint8_t* flags, double* g, double* g_prev);
 
+/* Bytes of device scratch the library holds on every GPU it runs on (one
+ * static copy per device, kept until the process ends) for
+ * mlqmc_eig_level_noalloc. */
+#define MLQMC_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as mlqmc_eig_level, without g / g_prev, that allocates nothing.
+ * Every intermediate (coefficient tables of the level's meshes, coarse
+ * vectors, counters) lives in the library's static device scratch of
+ * MLQMC_NOALLOC_SCRATCH_BYTES on this context's device; its address is taken
+ * once per device when a context is created there.
+ * Requirements: opt->io_on_device = 1 (Y and every output are device
+ * pointers); every mesh of the level (fine, coarse, previous) 1/32 or coarser
+ * (the per-sample LDS solvers).  Arguments, outputs, flags and return codes
+ * as mlqmc_eig_level.  MLQMC_EINVAL (nothing written) when the call would
+ * need more scratch than the maximum: about 8 (n_coarse - 1)^2 bytes per
+ * sample on a two-grid level plus the coefficient tables, 8 (2 n^2 +
+ * 2 (n + 2) n) bytes per term and mesh (twice that for Problem 2).
+ * The scratch is shared by every call on one GPU and keeps the last call's
+ * contents (each call rebuilds what it reads): calls that overlap on one GPU
+ * (other streams, threads or contexts) race, so the caller serialises them. */
+mlqmc_status mlqmc_eig_level_noalloc(mlqmc_ctx* ctx, const mlqmc_level* lvl,
+                                     const mlqmc_opts* opt, int64_t n, const double* Y,
+                                     int32_t warm_chain, double* lam, double* lam_prev,
+                                     double* lam_coarse, int32_t* rq_iters, int32_t* lin_iters,
+                                     uint8_t* flags);
+
 /* Two-grid MLQMC estimator (Algorithm 2; eq. tg-mlqmc, eq. sample_var, eq. ml-var).
  * Levels l = 0..n_levels-1 with N[l] points (powers of two), R shifts, z the
  * concatenated generating vectors ([s_fine of level l] each) and shifts the

@@ -12,6 +12,6 @@ from .binding import (  # noqa: F401
     K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE, K_PRE, K_TG_LDS,
     mlqmc_create, mlqmc_create_islands, mlqmc_destroy, mlqmc_last_error, mlqmc_default_opts,
     mlqmc_lattice_points, mlqmc_coefficient, mlqmc_apply_operator, mlqmc_prolong,
-    mlqmc_eig_level, mlqmc_estimate, mlqmc_set_tuning, mlqmc_set_timing, mlqmc_get_timing,
+    mlqmc_eig_level, mlqmc_eig_level_noalloc, mlqmc_estimate, mlqmc_set_tuning, mlqmc_set_timing, mlqmc_get_timing,
     mlqmc_embedded_points, mlqmc_estimate_nested, mlqmc_estimate_nested_extend,
 )

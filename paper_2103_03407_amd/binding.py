@@ -28,7 +28,8 @@ EXPORTS = [
     "mlqmc_default_opts", "mlqmc_create", "mlqmc_create_islands", "mlqmc_destroy",
     "mlqmc_last_error",
     "mlqmc_lattice_points", "mlqmc_embedded_points", "mlqmc_coefficient",
-    "mlqmc_apply_operator", "mlqmc_prolong", "mlqmc_eig_level", "mlqmc_estimate",
+    "mlqmc_apply_operator", "mlqmc_prolong", "mlqmc_eig_level", "mlqmc_eig_level_noalloc",
+    "mlqmc_estimate",
     "mlqmc_estimate_nested", "mlqmc_estimate_nested_extend", "mlqmc_set_tuning",
     "mlqmc_set_timing", "mlqmc_get_timing",
 ]
@@ -103,6 +104,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlqmc_prolong.argtypes = [P, I32, I32, I64, P, P, I32]
     lib.mlqmc_eig_level.argtypes = [P, C.POINTER(Level), C.POINTER(Opts), I64, P, I32, P, P, P,
                                     P, P, P, P, P]
+    lib.mlqmc_eig_level_noalloc.argtypes = [P, C.POINTER(Level), C.POINTER(Opts), I64, P, I32,
+                                            P, P, P, P, P, P]
     lib.mlqmc_estimate.argtypes = [P, I32, C.POINTER(Level), P, I32, P, P, C.POINTER(Opts), P,
                                    P, P, P, P]
     lib.mlqmc_estimate_nested.argtypes = [P, I32, C.POINTER(Level), P, I32, P, P,
@@ -114,7 +117,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlqmc_get_timing.argtypes = [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
     for name in ("mlqmc_create", "mlqmc_create_islands", "mlqmc_lattice_points",
                  "mlqmc_embedded_points", "mlqmc_coefficient", "mlqmc_apply_operator", "mlqmc_prolong",
-                 "mlqmc_eig_level", "mlqmc_estimate", "mlqmc_estimate_nested",
+                 "mlqmc_eig_level", "mlqmc_eig_level_noalloc", "mlqmc_estimate",
+                 "mlqmc_estimate_nested",
                  "mlqmc_estimate_nested_extend",
                  "mlqmc_set_tuning", "mlqmc_set_timing", "mlqmc_get_timing"):
         getattr(lib, name).restype = C.c_int
@@ -304,6 +308,27 @@ class Context:
             self._h, C.byref(lv), C.byref(o), int(n), py, int(warm_chain), pl, pp, pc, pr, pi,
             pf, pg, pgp), allow_noconv=True)
 
+    def eig_level_noalloc(self, level, Y, lam, flags, lam_prev=None, lam_coarse=None,
+                          rq_iters=None, lin_iters=None, warm_chain=1, opts=None):
+        """mlqmc_eig_level_noalloc: device tensors only (the library allocates
+        nothing; meshes up to 1/32)."""
+        o = opts if opts is not None else default_opts()
+        lv = Level(*[int(x) for x in level])
+        if len(Y.shape) != 2 or (Y.shape[1] != lv.s_fine and not (lv.s_fine == 0 and
+                                                                   Y.shape[1] <= 1)):
+            raise ValueError(f"Y must be [n, s_fine={lv.s_fine}] (got {tuple(Y.shape)})")
+        py, d0 = _ptr(Y, np.float64)
+        pl, d1 = _ptr(lam, np.float64)
+        pf, d2 = _ptr(flags, np.uint8)
+        pp, d3 = _ptr(lam_prev, np.float64)
+        pc, d4 = _ptr(lam_coarse, np.float64)
+        pr, d5 = _ptr(rq_iters, np.int32)
+        pi, d6 = _ptr(lin_iters, np.int32)
+        o.io_on_device = _one_side(d0, d1, d2, d3, d4, d5, d6)
+        return self._check(self._lib.mlqmc_eig_level_noalloc(
+            self._h, C.byref(lv), C.byref(o), int(Y.shape[0]), py, int(warm_chain), pl, pp, pc,
+            pr, pi, pf), allow_noconv=True)
+
     @staticmethod
     def _g_split(G, L, R):
         Q = G[:L * R].reshape(L, R)
@@ -473,6 +498,10 @@ def mlqmc_prolong(ctx, *a, **k):
 
 def mlqmc_eig_level(ctx, *a, **k):
     return ctx.eig_level(*a, **k)
+
+
+def mlqmc_eig_level_noalloc(ctx, *a, **k):
+    return ctx.eig_level_noalloc(*a, **k)
 
 
 def mlqmc_estimate(ctx, *a, **k):

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <utility>
 #include <string>
 #include <type_traits>
@@ -52,11 +53,46 @@ struct Table {
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 struct Status {
   mlqmc_status code = MLQMC_OK;
 };
 
 }  // namespace
+
+// Device scratch of mlqmc_eig_level_noalloc: one copy per GPU, held until the
+// process ends.  Host code never passes this name to a kernel or a copy; it
+// uses the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[MLQMC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device -> address of `scratch` on it
+
+// Address of `scratch` on `device`, which must be current: looked up once
+// per device and kept.
+hipError_t scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_addr[device] = p;
+  *out = p;
+  return hipSuccess;
+}
+}  // namespace
+
+#define CARVE_OR_FAIL(expr)          \
+  do {                               \
+    mlqmc_status c_ = (expr);        \
+    if (c_ != MLQMC_OK) return c_;   \
+  } while (0)
 
 struct mlqmc_ctx {
   int device = 0;
@@ -90,6 +126,14 @@ struct mlqmc_ctx {
   int* d_region = nullptr;
   std::map<std::string, DevBuf> bufs;
   std::map<int, Table> tables;
+  // No-allocation mode (mlqmc_eig_level_noalloc): named buffers and tables
+  // are carved in order from this device's copy of `scratch` and live for one
+  // call; nothing is allocated and nothing is cached past the call.
+  void* scratch_base = nullptr;
+  hipError_t scratch_err = hipSuccess;
+  char* arena = nullptr;
+  size_t arena_size = 0, arena_used = 0;
+  std::map<int, Table> arena_tables;
   int64_t bytes_alloc = 0;
   int64_t mem_cap = 0;
   std::string err;
@@ -114,8 +158,19 @@ struct mlqmc_ctx {
     return fail(MLQMC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
   }
 
+  mlqmc_status carve(const char* name, size_t bytes, void** out) {
+    const size_t b = round256(bytes ? bytes : 8);
+    if (arena_used + b > arena_size)
+      return fail(MLQMC_ENOMEM, "no-allocation scratch exhausted by %s (%zu of %zu bytes used)",
+                  name, arena_used, arena_size);
+    *out = arena + arena_used;
+    arena_used += b;
+    return MLQMC_OK;
+  }
+
   // growable named device buffer
   mlqmc_status get(const char* name, size_t bytes, void** out) {
+    if (arena) return carve(name, bytes, out);
     DevBuf& b = bufs[name];
     if (b.bytes >= bytes && b.p) {
       *out = b.p;
@@ -163,8 +218,53 @@ struct mlqmc_ctx {
     return s;
   }
 
+  // Tables in the no-allocation scratch: the element and padded edge tables
+  // (and the reaction's), rebuilt in every call.
+  mlqmc_status arena_table(int n, int s, Table** out) {
+    Table& t = arena_tables[n];
+    const int rows = islands ? s + 1 : std::max(s, 1);
+    if (t.el && t.s >= (islands ? s : rows)) {
+      *out = &t;
+      return MLQMC_OK;
+    }
+    void *el = nullptr, *pad = nullptr, *rel = nullptr, *rpad = nullptr;
+    CARVE_OR_FAIL(carve("table", (size_t)rows * 2 * n * n * 8, &el));
+    CARVE_OR_FAIL(carve("table", (size_t)rows * 2 * padded_size(n) * 8, &pad));
+    if (islands) {
+      CARVE_OR_FAIL(carve("table", (size_t)rows * 2 * n * n * 8, &rel));
+      CARVE_OR_FAIL(carve("table", (size_t)rows * 3 * padded_size(n) * 8, &rpad));
+    }
+    t.el = (double*)el;
+    t.pad = (double*)pad;
+    t.rel = (double*)rel;
+    t.rpad = (double*)rpad;
+    t.edge = nullptr;
+    hipError_t e;
+    if (islands) {
+      t.s = s;
+      e = launch_phi_elements_islands(n, rows, d_c, d_k1, d_k2, d_region, a_in, a_out, t.el,
+                                      stream);
+      if (e == hipSuccess) e = launch_phi_edges_padded(n, rows, t.el, t.pad, stream);
+      if (e == hipSuccess)
+        e = launch_phi_elements_islands(n, rows, d_cb, d_k1, d_k2, d_region, b_in, b_out, t.rel,
+                                        stream);
+      if (e == hipSuccess) e = launch_phi_reaction_padded(n, rows, t.rel, t.rpad, stream);
+    } else {
+      t.s = rows;
+      e = launch_phi_elements(n, rows, d_c, d_k1, d_k2, t.el, stream);
+      if (e == hipSuccess) e = launch_phi_edges_padded(n, rows, t.el, t.pad, stream);
+    }
+    if (e != hipSuccess) {
+      t = Table{};
+      return hip_fail(e, "coefficient tables (scratch)");
+    }
+    *out = &t;
+    return MLQMC_OK;
+  }
+
   // coefficient tables for mesh n with at least s terms
   mlqmc_status table(int n, int s, Table** out) {
+    if (arena) return arena_table(n, s, out);
     Table& t = tables[n];
     if (t.s < s || !t.el) {
       bytes_alloc -= t.bytes;
@@ -1012,6 +1112,8 @@ mlqmc_status mlqmc_create(mlqmc_ctx** out, const mlqmc_coeff* cf, int device, vo
   mlqmc_ctx* ctx = new mlqmc_ctx();
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(stream);
+  // the no-allocation entry point's scratch on this device (device current)
+  ctx->scratch_err = scratch_address(device, &ctx->scratch_base);
   ctx->s_max = cf->s_max;
   ctx->a0 = cf->a0;
   const int sm = std::max(cf->s_max, 1);
@@ -1089,6 +1191,8 @@ mlqmc_status mlqmc_create_islands(mlqmc_ctx** out, const mlqmc_islands* cf, int 
   mlqmc_ctx* ctx = new mlqmc_ctx();
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(stream);
+  // the no-allocation entry point's scratch on this device (device current)
+  ctx->scratch_err = scratch_address(device, &ctx->scratch_base);
   ctx->s_max = cf->s_max;
   ctx->islands = true;
   ctx->a_in = cf->a0_in;
@@ -1304,6 +1408,92 @@ mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_o
   CS(ctx->sync("eig_level"));
   bool any = false;
   CS(any_flag(ctx, dfl, n, &any));
+  return any ? ctx->fail(MLQMC_ENOCONV, "at least one sample is flagged") : MLQMC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Upper bound of the scratch bytes level_core carves for this level without
+// allocating (meshes up to 1/32: coefficient tables, the coarse vectors and
+// eigenvalues, the previous-level eigensolve's flags and counts, the inner
+// iteration counts when the caller passes none).
+size_t noalloc_bytes(const mlqmc_ctx* ctx, const mlqmc_level* L, int64_t n, bool have_lamc,
+                     bool have_lin) {
+  auto table = [&](int m, int s) -> size_t {
+    if (m == 0) return 0;
+    const size_t rows = ctx->islands ? (size_t)s + 1 : (size_t)std::max(s, 1);
+    size_t b = round256(rows * 2 * m * m * 8) + round256(rows * 2 * padded_size(m) * 8);
+    if (ctx->islands)
+      b += round256(rows * 2 * m * m * 8) + round256(rows * 3 * padded_size(m) * 8);
+    return b;
+  };
+  size_t need = have_lin ? 0 : round256((size_t)n * 4);
+  if (L->n_coarse == 0) {
+    need += table(L->n_fine, L->s_fine);
+    if (L->n_prev) need += table(L->n_prev, L->s_prev) + round256((size_t)n) + round256((size_t)n * 4);
+    return need;
+  }
+  const size_t DH = (size_t)(L->n_coarse - 1) * (L->n_coarse - 1);
+  need += table(L->n_coarse, L->s_coarse) + round256((size_t)n * DH * 8);
+  if (!have_lamc) need += round256((size_t)n * 8);
+  need += table(L->n_fine, L->s_fine);
+  const bool degenerate = L->n_prev == L->n_coarse && L->s_prev == L->s_coarse;
+  if (L->n_prev && !degenerate) need += table(L->n_prev, L->s_prev);
+  return need;
+}
+}  // namespace
+
+extern "C" {
+
+mlqmc_status mlqmc_eig_level_noalloc(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* o,
+                                     int64_t n, const double* Y, int32_t warm, double* lam,
+                                     double* lam_prev, double* lam_coarse, int32_t* rq_iters,
+                                     int32_t* lin_iters, uint8_t* flags) {
+  if (!ctx) return MLQMC_EINVAL;
+  CS(check_opts(ctx, o));
+  CS(check_level(ctx, L));
+  CS(check_islands_level(ctx, L));
+  if (!o->io_on_device)
+    return ctx->fail(MLQMC_EINVAL, "the no-allocation entry point takes device pointers only "
+                                   "(io_on_device = 1)");
+  if (L->n_fine > 32 || L->n_coarse > 32 || L->n_prev > 32)
+    return ctx->fail(MLQMC_EINVAL, "the no-allocation entry point covers meshes up to 1/32 "
+                                   "(got %d, %d, %d)", L->n_fine, L->n_coarse, L->n_prev);
+  if (n < 0) return ctx->fail(MLQMC_EINVAL, "n < 0");
+  if (n > 0 && (!Y || !lam || !flags)) return ctx->fail(MLQMC_EINVAL, "NULL buffer");
+  if (n > 0 && L->n_prev && !lam_prev)
+    return ctx->fail(MLQMC_EINVAL, "lam_prev is NULL but n_prev > 0");
+  const size_t need = noalloc_bytes(ctx, L, n, lam_coarse != nullptr, lin_iters != nullptr);
+  if (need > (size_t)MLQMC_NOALLOC_SCRATCH_BYTES)
+    return ctx->fail(MLQMC_EINVAL, "this call needs %zu bytes of scratch; the maximum is %zu "
+                                   "(MLQMC_NOALLOC_SCRATCH_BYTES)",
+                     need, (size_t)MLQMC_NOALLOC_SCRATCH_BYTES);
+  if (!ctx->scratch_base)
+    return ctx->hip_fail(ctx->scratch_err != hipSuccess ? ctx->scratch_err : hipErrorInvalidValue,
+                         "address of the no-allocation scratch");
+  CK(hipSetDevice(ctx->device), "set device");
+  if (n == 0) return MLQMC_OK;
+  // every named buffer and table of this call comes from the scratch
+  struct Arena {
+    mlqmc_ctx* c;
+    ~Arena() {
+      c->arena = nullptr;
+      c->arena_size = c->arena_used = 0;
+      c->arena_tables.clear();
+    }
+  } guard{ctx};
+  ctx->arena = static_cast<char*>(ctx->scratch_base);
+  ctx->arena_size = MLQMC_NOALLOC_SCRATCH_BYTES;
+  ctx->arena_used = 0;
+  ctx->arena_tables.clear();
+  int* dli = lin_iters;
+  if (!dli) CS(ctx->getT("o_li", n, &dli));
+  CS(level_core(ctx, L, o, n, Y, L->s_fine, warm, lam, L->n_prev ? lam_prev : nullptr,
+                lam_coarse, rq_iters, dli, flags));
+  CS(ctx->sync("eig_level_noalloc"));
+  bool any = false;
+  CS(any_flag(ctx, flags, n, &any));
   return any ? ctx->fail(MLQMC_ENOCONV, "at least one sample is flagged") : MLQMC_OK;
 }
 
