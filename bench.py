@@ -14,12 +14,12 @@ path stopped at the mixed path's tolerances (equal accuracy), each with its
 error against the oracle, and the two-grid 1/32 -> 1/128 workload (s = 64).
 
 ``--cfg`` selects another workload of ``synth/configs.py``: 4 and 6 are the
-five-level estimators (independent and shared shifts), 7 to 10 Problem 2
-(the islands) as one two-grid level H = 1/8 -> h = 1/32 and as the three-,
-four- and five-level estimators on h = 1/8 .. 1/32, 1/64 and 1/128; their
-two-grid updates run per sample (in LDS, and on 1/64 and 1/128 with the top
-levels in global scratch), and the roofline is then those kernels' rate
-against the vector peak of the precision.
+five-level estimators (independent and shared shifts), 7 to 10 and 12
+Problem 2 (the islands) as one two-grid level H = 1/8 -> h = 1/32 and as the
+three- to six-level estimators on h = 1/8 .. 1/32, 1/64, 1/128 and 1/256.
+Updates on meshes up to 1/32 run per sample in LDS (the roofline is then
+those kernels' rate against the vector peak of the precision); finer ones on
+the batched stencil kernels (HBM roofline).
 
 Prints one JSON line.  ``value`` = eigen-samples per second on one GPU.
 Progress goes to stderr.
@@ -466,7 +466,7 @@ def lds_step_flops(ctx, m, w, opts):
         if lv.n_prev and not (lv.n_prev == lv.n_coarse and lv.s_prev == lv.s_coarse):
             updates.append((lv.n_prev, lv.s_prev))
         for nm, sm in updates:
-            if nm > 32 and not (reaction and nm <= 128):
+            if nm > 32:
                 continue  # the batched kernels: not this kernel class
             li = np.zeros(n, np.int32)
             ctx.eig_level((nm, sm, lv.n_coarse, lv.s_coarse, 0, 0),
@@ -506,7 +506,7 @@ def _workload_opts(m, prec: str, **kw):
 
 
 def _default_class(w) -> str:
-    per_sample = all(lv.n_fine <= (128 if w.problem == 2 else 32) for lv in w.levels)
+    per_sample = all(lv.n_fine <= 32 for lv in w.levels)
     if not any(lv.n_coarse for lv in w.levels):
         return "rqi"
     return "lds" if per_sample else "post"
@@ -569,8 +569,6 @@ def roofline(ctx, m, w, opts, prec: str, kernel_class: str, leg, cfg: int):
     if kernel_class in ("rqi", "lds"):
         # LDS-resident solvers: vector arithmetic on data in LDS, against the
         # vector peak of the precision they compute in
-        if kernel_class == "lds" and any(lv.n_fine > 32 for lv in w.levels):
-            kname = "k_tg_small+k_tg_global"
         fl = (rqi_step_flops if kernel_class == "rqi" else lds_step_flops)(ctx, m, w, opts)
         flops_per_launch = fl * steps / launches
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
@@ -772,8 +770,9 @@ def main():
     out = {
         "metric": "two-grid eigen-samples/sec per level; stencil HBM GB/s in roofline"
                   if w.problem == 1 else
-                  "two-grid eigen-samples/sec per level (Problem 2, islands); LDS-update "
-                  "FP64 TFLOP/s in roofline",
+                  "two-grid eigen-samples/sec per level (Problem 2, islands); "
+                  + ("LDS-update TFLOP/s" if kclass in ("lds", "rqi") else "stencil HBM GB/s")
+                  + " in roofline",
         "value": round(main_leg["value"], 1), "unit": "samples/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(main_leg["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

@@ -138,12 +138,13 @@ typedef struct {
 
 /* Creates a context for the Problem 2 family (arguments as mlqmc_create).
  * Requires a >= a0_* - 0.5 sum |ca| > 0 and b >= 0 on each region for all
- * |y_j| <= 1/2 (MLQMC_EINVAL otherwise).  Contexts of this family run on
- * meshes 1/8 .. 1/32 (every array of a solve in LDS; meshes are multiples of
- * 1/8 so that the islands' edges are mesh lines), and take 1/64 and 1/128 as
- * the fine or previous mesh of a two-grid level (top levels in global
- * scratch, up to 1.5 GiB per call), in either precision; the level and estimator calls
- * return MLQMC_EINVAL for other meshes (direct and coarse meshes up to 1/32),
+ * |y_j| <= 1/2 (MLQMC_EINVAL otherwise).  Contexts of this family run their
+ * eigensolves (direct and coarse meshes) on 1/8 .. 1/32, every array of a
+ * solve in LDS, and take 1/64 .. 1/1024 as the fine or previous mesh of a
+ * two-grid level (the batched kernels with the reaction term: weight blocks
+ * [WX | WY | RX | RY | RD] from two coefficient products), in either
+ * precision; meshes are multiples of 1/8 so that the islands' edges are mesh
+ * lines.  The level and estimator calls return MLQMC_EINVAL for other meshes,
  * and mlqmc_coefficient / mlqmc_apply_operator for any call (they cover
  * Problem 1). */
 mlqmc_status mlqmc_create_islands(mlqmc_ctx** out, const mlqmc_islands* cf, int device,
@@ -322,6 +323,67 @@ mlqmc_status mlqmc_estimate_nested_extend(mlqmc_ctx* ctx, int32_t n_levels,
 
 /* ---- tuning ---- */
 
+/* ---- adaptive choice of N_l and L (nested estimator) ----
+ *
+ * The paper picks the points per level and the number of levels with a greedy
+ * adaptive MLQMC algorithm it cites but does not state (section 4.2; the
+ * numerical section's set-up).  This library's own rule, from what the paper
+ * does state: the mean-square error is variance plus squared bias, so ask
+ * sum_l V_l <= eps^2 / 2 (eq. sample_var, eq. ml-var) and bias <= eps / sqrt 2;
+ * a sample on level l costs C_l = s_l h_l^-2 + h_l^-gamma (section 4.2, d = 2).
+ *  - While the variance is too large, double N_l on the level with the largest
+ *    V_l / (N_l C_l) (the first on ties); coarser levels are raised to at
+ *    least the new N (nested rules need N_0 >= N_1 >= ...).
+ *  - Then, while |Qhat_{L-1}| / (2^alpha - 1) (the remaining bias for level
+ *    differences decaying like h_l^alpha, h halving per level) exceeds
+ *    eps / sqrt 2, add a level with N_init points.
+ * Sums are taken left to right in FP64. */
+typedef struct {
+  double eps;       /* target root-mean-square error of Q^ML */
+  double alpha;     /* decay of E[Y_l] in h_l (2 for the eigenvalue, section 2.3) */
+  double gamma;     /* solve-cost exponent (2: the multigrid-preconditioned solves) */
+  int64_t N_init;   /* points of a level when it starts (power of two) */
+  int64_t N_max;    /* no level grows beyond this (power of two, <= 2^30) */
+} mlqmc_adaptive_opts;
+
+enum {
+  MLQMC_ADAPT_DONE = 0,    /* both targets met */
+  MLQMC_ADAPT_DOUBLE = 1,  /* double N on *level */
+  MLQMC_ADAPT_ADD = 2,     /* add level *level (= n_levels) */
+  MLQMC_ADAPT_BUDGET = 3,  /* doubling *level would pass N_max: stop, not converged */
+  MLQMC_ADAPT_LEVELS = 4   /* the bias needs a level beyond max_levels: stop, not converged */
+};
+
+/* One decision of the rule (host arithmetic only; no context or device):
+ * from the current n_levels <= max_levels, Qhat, V, N and per-sample cost
+ * arrays [n_levels].  Returns an MLQMC_ADAPT_* code and the level it concerns
+ * in *level (-1 for DONE), or -1 on invalid arguments. */
+int32_t mlqmc_adaptive_decide(int32_t n_levels, int32_t max_levels, const double* Qhat,
+                              const double* V, const int64_t* N, const double* cost, double eps,
+                              double alpha, int64_t N_max, int32_t* level);
+
+/* The nested estimator (shared shifts, one embedded rule; as
+ * mlqmc_estimate_nested, whose level list shape it requires for
+ * lvls[0 .. max_levels)) with N_l and L chosen by the rule above: it starts
+ * with min(2, max_levels) levels of N_init points and, after every decision,
+ * evaluates only the new points (the extensible rule of
+ * mlqmc_estimate_nested_extend).  z [s_max] and shifts [R x s_max] with s_max
+ * = max s_fine over all max_levels levels.  Host arrays (opt->io_on_device =
+ * 0); R >= 2.
+ * Outputs: *n_levels = L used; N [max_levels] (first L written); Q_lr
+ * [max_levels x R] (first L rows), Qhat, V [max_levels]; est[0] = Q^ML,
+ * est[1] = sum_l V_l; *converged = 1 if the rule ended with both targets met;
+ * trace [trace_cap x 2] the (action, level) of every decision, *trace_len
+ * their count (may exceed trace_cap; only the first trace_cap are stored).
+ * Errors as mlqmc_estimate_nested; MLQMC_ENOCONV if a sample was flagged (all
+ * outputs still written). */
+mlqmc_status mlqmc_estimate_adaptive(mlqmc_ctx* ctx, int32_t max_levels, const mlqmc_level* lvls,
+                                     int32_t R, const int64_t* z, const double* shifts,
+                                     const mlqmc_adaptive_opts* aopt, const mlqmc_opts* opt,
+                                     int32_t* n_levels, int64_t* N, double* Q_lr, double* Qhat,
+                                     double* V, double* est, int32_t* converged, int32_t* trace,
+                                     int32_t trace_cap, int32_t* trace_len);
+
 /* Sets how many workgroups in flight the batched stencil kernels of the fine
  * solve on mesh 1/n_fine (64..1024, a power of two) aim for in precision
  * `prec`; the number of row strips per sample follows from it and the batch
@@ -344,9 +406,8 @@ enum {
   MLQMC_K_COARSE = 4,    /* eigensolves (coarse, direct and direct previous-level; the
                             chain kernel) */
   MLQMC_K_PRE = 5,       /* finest-level pre-smoothing + residual restriction */
-  MLQMC_K_TG_LDS = 6     /* per-sample two-grid update: in LDS (fine meshes up to 1/32),
-                            or with its top level in global scratch (Problem 2 on 1/64,
-                            one launch per chunk of samples); its model bytes are 0 */
+  MLQMC_K_TG_LDS = 6     /* per-sample two-grid update in LDS (fine meshes up to 1/32);
+                            its model bytes are 0 */
 };
 /* Selects the kernel class whose launches are bracketed by HIP events on the
  * context's stream (MLQMC_K_NONE disables) and clears the totals. */

@@ -14,4 +14,6 @@ from .binding import (  # noqa: F401
     mlqmc_lattice_points, mlqmc_coefficient, mlqmc_apply_operator, mlqmc_prolong,
     mlqmc_eig_level, mlqmc_eig_level_noalloc, mlqmc_estimate, mlqmc_set_tuning, mlqmc_set_timing, mlqmc_get_timing,
     mlqmc_embedded_points, mlqmc_estimate_nested, mlqmc_estimate_nested_extend,
+    mlqmc_adaptive_decide, mlqmc_estimate_adaptive, AdaptiveOpts,
+    ADAPT_DONE, ADAPT_DOUBLE, ADAPT_ADD, ADAPT_BUDGET, ADAPT_LEVELS,
 )

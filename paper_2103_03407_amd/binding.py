@@ -30,7 +30,8 @@ EXPORTS = [
     "mlqmc_lattice_points", "mlqmc_embedded_points", "mlqmc_coefficient",
     "mlqmc_apply_operator", "mlqmc_prolong", "mlqmc_eig_level", "mlqmc_eig_level_noalloc",
     "mlqmc_estimate",
-    "mlqmc_estimate_nested", "mlqmc_estimate_nested_extend", "mlqmc_set_tuning",
+    "mlqmc_estimate_nested", "mlqmc_estimate_nested_extend", "mlqmc_adaptive_decide",
+    "mlqmc_estimate_adaptive", "mlqmc_set_tuning",
     "mlqmc_set_timing", "mlqmc_get_timing",
 ]
 
@@ -57,6 +58,14 @@ class Islands(C.Structure):
 class Level(C.Structure):
     _fields_ = [("n_fine", C.c_int32), ("s_fine", C.c_int32), ("n_coarse", C.c_int32),
                 ("s_coarse", C.c_int32), ("n_prev", C.c_int32), ("s_prev", C.c_int32)]
+
+
+class AdaptiveOpts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("alpha", C.c_double), ("gamma", C.c_double),
+                ("N_init", C.c_int64), ("N_max", C.c_int64)]
+
+
+ADAPT_DONE, ADAPT_DOUBLE, ADAPT_ADD, ADAPT_BUDGET, ADAPT_LEVELS = 0, 1, 2, 3, 4
 
 
 class Opts(C.Structure):
@@ -112,6 +121,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                           C.POINTER(Opts), P, P, P, P, P, P]
     lib.mlqmc_estimate_nested_extend.argtypes = [P, I32, C.POINTER(Level), P, P, I32, P, P,
                                                  C.POINTER(Opts), P, P, P, P, P, P, P]
+    lib.mlqmc_adaptive_decide.argtypes = [I32, I32, P, P, P, P, D, D, I64, C.POINTER(I32)]
+    lib.mlqmc_adaptive_decide.restype = C.c_int32
+    lib.mlqmc_estimate_adaptive.argtypes = [P, I32, C.POINTER(Level), I32, P, P,
+                                            C.POINTER(AdaptiveOpts), C.POINTER(Opts),
+                                            C.POINTER(I32), P, P, P, P, P, C.POINTER(I32), P, I32,
+                                            C.POINTER(I32)]
     lib.mlqmc_set_tuning.argtypes = [P, I32, I32, I64]
     lib.mlqmc_set_timing.argtypes = [P, I32]
     lib.mlqmc_get_timing.argtypes = [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
@@ -119,7 +134,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                  "mlqmc_embedded_points", "mlqmc_coefficient", "mlqmc_apply_operator", "mlqmc_prolong",
                  "mlqmc_eig_level", "mlqmc_eig_level_noalloc", "mlqmc_estimate",
                  "mlqmc_estimate_nested",
-                 "mlqmc_estimate_nested_extend",
+                 "mlqmc_estimate_nested_extend", "mlqmc_estimate_adaptive",
                  "mlqmc_set_tuning", "mlqmc_set_timing", "mlqmc_get_timing"):
         getattr(lib, name).restype = C.c_int
     if path == LIB_PATH:
@@ -155,6 +170,18 @@ def _ptr(x, dtype):
     if not isinstance(x, np.ndarray) or x.dtype != np.dtype(dtype) or not x.flags.c_contiguous:
         raise TypeError(f"expected a C-contiguous numpy array of {np.dtype(dtype)}")
     return C.c_void_p(x.ctypes.data), False
+
+
+def _shared_rule(levels, z, shifts, R):
+    """z [s_max] and shifts [R, s_max] of a nested estimate, s_max the largest
+    truncation of `levels` (longer rows are cut to it)."""
+    s_max = max(int(l[1]) for l in levels)
+    z = np.asarray(z)
+    shifts = np.asarray(shifts, dtype=np.float64).reshape(R, -1)
+    if z.shape[0] < s_max or shifts.shape[1] < s_max:
+        raise ValueError(f"z and the shift rows need s_max = {s_max} entries")
+    return (np.ascontiguousarray(z[:s_max], dtype=np.int64),
+            np.ascontiguousarray(shifts[:, :s_max]))
 
 
 def _one_side(*flags):
@@ -329,6 +356,36 @@ class Context:
             self._h, C.byref(lv), C.byref(o), int(Y.shape[0]), py, int(warm_chain), pl, pp, pc,
             pr, pi, pf), allow_noconv=True)
 
+    def estimate_adaptive(self, levels, R, z, shifts, eps, alpha=2.0, gamma=2.0, N_init=8,
+                          N_max=1 << 20, opts=None, trace_cap=256):
+        """mlqmc_estimate_adaptive over the nested hierarchy `levels` (6-tuples,
+        the most levels allowed).  Returns (status, dict) with n_levels, N,
+        Q_lr, Qhat, V, est, converged and trace [(action, level)]."""
+        o = opts if opts is not None else default_opts()
+        o.io_on_device = 0
+        Lm = len(levels)
+        lv = (Level * Lm)(*[Level(*[int(x) for x in l]) for l in levels])
+        zc, sc = _shared_rule(levels, z, shifts, R)
+        ao = AdaptiveOpts(float(eps), float(alpha), float(gamma), int(N_init), int(N_max))
+        nl = C.c_int32()
+        conv = C.c_int32()
+        tlen = C.c_int32()
+        N = np.zeros(Lm, np.int64)
+        Q = np.zeros((Lm, R))
+        Qh, V, est = np.zeros(Lm), np.zeros(Lm), np.zeros(2)
+        tr = np.zeros((trace_cap, 2), np.int32)
+        st = self._check(self._lib.mlqmc_estimate_adaptive(
+            self._h, Lm, lv, int(R), C.c_void_p(zc.ctypes.data), C.c_void_p(sc.ctypes.data),
+            C.byref(ao), C.byref(o), C.byref(nl), C.c_void_p(N.ctypes.data),
+            C.c_void_p(Q.ctypes.data), C.c_void_p(Qh.ctypes.data), C.c_void_p(V.ctypes.data),
+            C.c_void_p(est.ctypes.data), C.byref(conv), C.c_void_p(tr.ctypes.data),
+            int(trace_cap), C.byref(tlen)), allow_noconv=True)
+        L = nl.value
+        return st, {"n_levels": L, "N": N[:L].tolist(), "Q_lr": Q[:L], "Qhat": Qh[:L],
+                    "V": V[:L], "est": est, "converged": bool(conv.value),
+                    "trace": [tuple(int(v) for v in tr[i]) for i in range(min(tlen.value,
+                                                                               trace_cap))]}
+
     @staticmethod
     def _g_split(G, L, R):
         Q = G[:L * R].reshape(L, R)
@@ -371,8 +428,7 @@ class Context:
         L = len(levels)
         lv = (Level * L)(*[Level(*[int(x) for x in l]) for l in levels])
         Nn = np.ascontiguousarray(N, dtype=np.int64)
-        zc = np.ascontiguousarray(z, dtype=np.int64)
-        sc = np.ascontiguousarray(shifts, dtype=np.float64)
+        zc, sc = _shared_rule(levels, z, shifts, R)
         Q = np.zeros((L, R))
         Qh = np.zeros(L)
         V = np.zeros(L)
@@ -408,8 +464,7 @@ class Context:
         lv = (Level * L)(*[Level(*[int(x) for x in l]) for l in levels])
         Nd = np.ascontiguousarray(N_done, dtype=np.int64)
         Nn = np.ascontiguousarray(N, dtype=np.int64)
-        zc = np.ascontiguousarray(z, dtype=np.int64)
-        sc = np.ascontiguousarray(shifts, dtype=np.float64)
+        zc, sc = _shared_rule(levels, z, shifts, R)
         for arr in (sums, g_sums):
             if arr is not None and (not isinstance(arr, np.ndarray) or arr.dtype != np.float64
                                     or not arr.flags.c_contiguous or arr.size != L * R):
@@ -502,6 +557,29 @@ def mlqmc_eig_level(ctx, *a, **k):
 
 def mlqmc_eig_level_noalloc(ctx, *a, **k):
     return ctx.eig_level_noalloc(*a, **k)
+
+
+def mlqmc_adaptive_decide(Qhat, V, N, cost, eps, alpha, max_levels, N_max):
+    """The adaptive rule's decision (host arithmetic in the library, no
+    device): returns (action, level)."""
+    lib = load()
+    L = len(Qhat)
+    q = np.ascontiguousarray(Qhat, dtype=np.float64)
+    v = np.ascontiguousarray(V, dtype=np.float64)
+    n = np.ascontiguousarray(N, dtype=np.int64)
+    c = np.ascontiguousarray(cost, dtype=np.float64)
+    lev = C.c_int32()
+    act = lib.mlqmc_adaptive_decide(L, int(max_levels), C.c_void_p(q.ctypes.data),
+                                    C.c_void_p(v.ctypes.data), C.c_void_p(n.ctypes.data),
+                                    C.c_void_p(c.ctypes.data), float(eps), float(alpha),
+                                    int(N_max), C.byref(lev))
+    if act < 0:
+        raise MlqmcError(MLQMC_EINVAL, "mlqmc_adaptive_decide: invalid arguments")
+    return int(act), int(lev.value)
+
+
+def mlqmc_estimate_adaptive(ctx, *a, **k):
+    return ctx.estimate_adaptive(*a, **k)
 
 
 def mlqmc_estimate(ctx, *a, **k):

@@ -425,12 +425,12 @@ mlqmc_status check_opts(mlqmc_ctx* ctx, const mlqmc_opts* o) {
 }
 
 // Problem 2 meshes: multiples of 1/8 (the islands' edges are mesh lines) up
-// to 1/128 (every array of a solve in LDS up to 1/32; the two-grid update on
-// 1/64 and 1/128 keeps its top levels in global scratch); 0 = not used
-bool islands_mesh_ok(int n) { return n == 0 || (n >= 8 && n <= 128); }
+// to 1/1024 (every array of a solve in LDS up to 1/32; finer two-grid meshes
+// on the batched kernels with the reaction term); 0 = not used
+bool islands_mesh_ok(int n) { return n == 0 || (n >= 8 && n <= 1024); }
 
-// Problem 2 takes 1/64 and 1/128 only as a two-grid fine or previous mesh
-// (the eigensolves stay at 1/32 or coarser)
+// Problem 2 takes meshes finer than 1/32 only as a two-grid fine or previous
+// mesh (the eigensolves stay at 1/32 or coarser)
 mlqmc_status check_islands_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
   if (!ctx->islands) return MLQMC_OK;
   if (l->n_coarse == 0 && (l->n_fine > 32 || l->n_prev > 32))
@@ -472,7 +472,7 @@ mlqmc_status check_level(mlqmc_ctx* ctx, const mlqmc_level* l) {
   if (ctx->islands &&
       !(islands_mesh_ok(l->n_fine) && islands_mesh_ok(l->n_coarse) && islands_mesh_ok(l->n_prev)))
     return ctx->fail(MLQMC_EINVAL,
-                     "the islands family (Problem 2) needs meshes 1/8 .. 1/128 (got %d, %d, %d)",
+                     "the islands family (Problem 2) needs meshes 1/8 .. 1/1024 (got %d, %d, %d)",
                      l->n_fine, l->n_coarse, l->n_prev);
   return MLQMC_OK;
 }
@@ -552,12 +552,18 @@ mlqmc_status pcg_graph(mlqmc_ctx* ctx, const char* tag, int64_t, F body,
 // Two-grid update on mesh nh (>= 64) for n samples, batched.  T is the
 // storage type of the projected PCG and the V-cycle (double; float in mixed
 // precision); the right-hand side and the Rayleigh quotient are FP64.
+// Problem 2 (ctx->islands): weight blocks [WX | WY | RX | RY | RD] from the
+// two coefficient products of the diffusion and reaction tables (their row 0
+// the background values, selected by a leading 1 in the point), and the
+// operator A + R in every kernel.
 template <typename T>
 mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, const double* Y,
                           int64_t ldY, const double* uH, const double* lamH, int nH, int64_t n,
                           double* lam, double* g, int* lin_iters, uint8_t* flags,
                           const char* tag) {
   constexpr bool kMixed = std::is_same<T, float>::value;
+  const int rx = ctx->islands ? 1 : 0;   // reaction term
+  const int WB = rx ? 5 : 2;             // weight arrays per sample
   Table* tb = nullptr;
   CS(ctx->table(nh, s, &tb));
   std::vector<int> lv;
@@ -566,11 +572,12 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   const size_t nL = lv.size();
   auto D = [](int m) { return (int64_t)(m - 1) * (m - 1); };  // interior nodes (coarse uH)
   auto P = [](int m) { return padded_size(m); };                // padded vector
-  auto EW = [](int m) { return 2 * padded_size(m); };           // padded [WX | WY]
+  auto EW = [WB](int m) { return WB * padded_size(m); };        // padded weight block
   const int64_t sz = (int64_t)sizeof(T);
   int64_t per_sample = 8 * (EW(nh) + 2 * P(nh)) + sz * (9 * P(nh)) + (kMixed ? 4 * EW(nh) : 0);
   for (size_t k = 1; k < nL; ++k) per_sample += sz * (EW(lv[k]) + 3 * P(lv[k]));
   per_sample += sz * (EW(nb) + 2 * P(nb));
+  if (rx) per_sample += 8 * (s + 1);  // the points with their leading 1
   // default batch: up to 48 GB of working arrays (HBM holds 288 GB), in
   // multiples of the 128-sample tile of the coefficient product when larger
   int64_t batch = o->batch;
@@ -584,9 +591,10 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
 
   std::string p = tag;
   auto nm = [&](const char* x) { return p + x; };
-  double *w64, *part;
+  double *w64, *part, *Y1 = nullptr;
   T *wT, *vn, *mvn, *t, *r, *r2, *z, *zb, *pp[2];
   CS(ctx->getT(nm("w64").c_str(), batch * EW(nh), &w64));
+  if (rx) CS(ctx->getT(nm("Y1").c_str(), batch * (s + 1), &Y1));
   if constexpr (kMixed) {
     CS(ctx->getT(nm("w32").c_str(), batch * EW(nh), &wT));
   } else {
@@ -681,17 +689,30 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     ctx->t_begin(MLQMC_K_COEFF);
     float* w32 = nullptr;
     if constexpr (kMixed) w32 = wT;
-    CK(launch_expand(Bn, s, EW(nh), Y + b0 * ldY, ldY, tb->pad, ctx->a0, w64, w32, st), "expand");
+    if (rx) {
+      // (1, y) against the tables of a and b (row 0: the background values)
+      CK(launch_prepend_one(Bn, s, Y + b0 * ldY, ldY, Y1, st), "points");
+      CK(launch_expand(Bn, s + 1, 2 * P(nh), Y1, s + 1, tb->pad, 0.0, w64, w32, st, EW(nh)),
+         "expand");
+      CK(launch_expand(Bn, s + 1, 3 * P(nh), Y1, s + 1, tb->rpad, 0.0, w64 + 2 * P(nh),
+                       w32 ? w32 + 2 * P(nh) : nullptr, st, EW(nh)),
+         "expand");
+    } else {
+      CK(launch_expand(Bn, s, EW(nh), Y + b0 * ldY, ldY, tb->pad, ctx->a0, w64, w32, st),
+         "expand");
+    }
     // Y and phi in, the weights out (FP64, plus the FP32 copy in mixed precision)
-    ctx->t_end(MLQMC_K_COEFF, 8.0 * ((double)Bn * s + (double)s * EW(nh)) +
+    const int rows = rx ? s + 1 : s;
+    ctx->t_end(MLQMC_K_COEFF, 8.0 * ((double)Bn * rows + (double)rows * EW(nh)) +
                                   (8.0 + (kMixed ? 4.0 : 0.0)) * (double)Bn * EW(nh));
-    for (size_t k = 0; k < nL; ++k) CK(launch_coarsen<T>(lv[k], Bn, W[k], W[k + 1], st), "coarsen");
+    for (size_t k = 0; k < nL; ++k)
+      CK(launch_coarsen<T>(lv[k], Bn, W[k], W[k + 1], rx, st), "coarsen");
 
     // v = P u_H is evaluated inside these kernels from the coarse vectors
     const double* uHb = uH + b0 * D(nH);
-    CK(launch_setup_dots(nh, Bn, uHb, nH, w64, part, st), "setup dots");
+    CK(launch_setup_dots(nh, Bn, uHb, nH, w64, part, rx, st), "setup dots");
     CK(launch_scalar(PH_SETUP, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
-    CK(launch_setup_rhs<T>(nh, Bn, uHb, nH, w64, S, r, vn, mvn, st), "setup rhs");
+    CK(launch_setup_rhs<T>(nh, Bn, uHb, nH, w64, S, r, vn, mvn, rx, st), "setup rhs");
 
     // z = K^{-1} r by one V-cycle: fused pre-smoothing + restriction per level,
     // the LDS bottom solve, fused coarse correction + post-smoothing per level;
@@ -700,10 +721,11 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     // cannot write in place).  Timed launches are those in which every sample is
     // active (the set-up V-cycle, the first PCG step), so the byte model counts
     // exactly the work done: rhs, 2 edge weights per node in; X and rhs_c out.
-    const double pre_b = (double)sz * Bn * (4.25 * D(nh));
+    // (with the reaction three more weight arrays per node in every stencil kernel)
+    const double pre_b = (double)sz * Bn * ((4.25 + 3 * rx) * D(nh));
     // post: Xin, rhs, mvn, 2 weights per node and 1/4 of a coarse vector in (and vn
     // for the product r.vn in FP32 storage only); Xout out
-    const double post_b = (double)sz * Bn * ((kMixed ? 7.25 : 6.25) * D(nh));
+    const double post_b = (double)sz * Bn * ((kMixed ? 7.25 : 6.25) + 3 * rx) * D(nh);
     bool all_active = true;
     int cur = 0;  // pp[cur]: the current search direction
     T* zc = z;   // current preconditioned residual
@@ -716,27 +738,28 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     auto vcycle = [&](bool upd) -> mlqmc_status {
       if (all_active) ctx->t_begin(MLQMC_K_PRE);
       if (upd) {
-        CK(launch_pre<T>(nh, Bn, wT, rc, zc, Bv[1], act, pp[cur], mvn, &S, ro, st), "pre");
+        CK(launch_pre<T>(nh, Bn, wT, rc, zc, Bv[1], act, pp[cur], mvn, &S, ro, rx, st), "pre");
         std::swap(rc, ro);
       } else {
-        CK(launch_pre<T>(nh, Bn, wT, rc, zc, Bv[1], act, nullptr, nullptr, nullptr, nullptr, st),
+        CK(launch_pre<T>(nh, Bn, wT, rc, zc, Bv[1], act, nullptr, nullptr, nullptr, nullptr, rx,
+                         st),
            "pre");
       }
       if (all_active) ctx->t_end(MLQMC_K_PRE, pre_b);
       for (size_t k = 1; k < nL; ++k)
         CK(launch_pre<T>(lv[k], Bn, W[k], Bv[k], X[k], Bv[k + 1], act, nullptr, nullptr, nullptr,
-                         nullptr, st),
+                         nullptr, rx, st),
            "pre");
-      CK(launch_bottom_vcycle<T>(nb, Bn, W[nL], Bv[nL], X[nL], act, st), "bottom");
+      CK(launch_bottom_vcycle<T>(nb, Bn, W[nL], Bv[nL], X[nL], act, rx, st), "bottom");
       const T* xc = X[nL];
       for (size_t k = nL - 1; k >= 1; --k) {
         CK(launch_post<T>(lv[k], Bn, W[k], Bv[k], X[k], xc, Xb[k], nullptr, nullptr, act, nullptr,
-                          st),
+                          rx, st),
            "post");
         xc = Xb[k];
       }
       if (all_active) ctx->t_begin(MLQMC_K_SMOOTH);
-      CK(launch_post<T>(nh, Bn, wT, rc, zc, xc, zo, vn, mvn, act, part, st), "post");
+      CK(launch_post<T>(nh, Bn, wT, rc, zc, xc, zo, vn, mvn, act, part, rx, st), "post");
       if (all_active) ctx->t_end(MLQMC_K_SMOOTH, post_b);
       std::swap(zc, zo);
       return MLQMC_OK;
@@ -747,13 +770,13 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     CK(launch_scalar(PH_FIRST_RZ, nh, Bn, nblk_post, part, S, 0.0, 0, st), "scalar");
     // first apply: z, vn, 2 weights per node in (M vn is formed from vn; no
     // previous p; t = 0 not read); p out (q feeds only the partial sums)
-    const double ab = (double)sz * Bn * (5 * D(nh));
+    const double ab = (double)sz * Bn * ((5 + 3 * rx) * D(nh));
     // one PCG iteration: apply (with the previous step's t update), alpha and
     // the eigenvalue test, the V-cycle (with the residual update), beta
     auto iteration = [&](int it) -> mlqmc_status {
       if (it == 0) ctx->t_begin(MLQMC_K_APPLY);
       CK(launch_pupdate_apply<T>(nh, Bn, zc, vn, pp[cur], wT, t, S, it == 0, pp[1 - cur],
-                                 nullptr, part, st),
+                                 nullptr, part, rx, st),
          "apply");
       if (it == 0) ctx->t_end(MLQMC_K_APPLY, ab);
       cur = 1 - cur;
@@ -806,7 +829,8 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
         }
       }
     }
-    CK(launch_final_dots<T>(nh, Bn, uHb, nH, t, pp[0], pp[1], w64, S, part, st), "final dots");
+    CK(launch_final_dots<T>(nh, Bn, uHb, nH, t, pp[0], pp[1], w64, S, part, rx, st),
+       "final dots");
     CK(launch_scalar(PH_FINAL, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
   }
   return MLQMC_OK;
@@ -822,7 +846,7 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
   mlqmc_opts og = *o;
   if (g) og.lam_rtol = -1.0;
   o = &og;
-  if (nh <= 32 || ctx->islands) {
+  if (nh <= 32) {
     Table* tb = nullptr;
     CS(ctx->table(nh, s, &tb));
     TgSmallArgs a{};
@@ -844,32 +868,6 @@ mlqmc_status fine_update(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, con
     a.g = g;
     a.lin_iters = lin_iters;
     a.flags = flags;
-    if (const int64_t per = tg_scratch_doubles(nh, a.mixed)) {
-      // Problem 2 on 1/64 and 1/128: each sample's slice of scratch, in
-      // chunks of a power of two of samples within 1.5 GiB (4096 on 1/64)
-      constexpr int64_t kScratchBytes = (int64_t)3 << 29;
-      int64_t cap = 1;
-      while (2 * cap * per * (int64_t)sizeof(double) <= kScratchBytes) cap *= 2;
-      const int64_t chunk = std::min<int64_t>(n, cap);
-      CS(ctx->getT("tg_scratch", (size_t)(chunk * per), &a.scratch));
-      a.scratch_doubles = chunk * per;
-      const int64_t DH = (int64_t)(nH - 1) * (nH - 1);
-      for (int64_t c0 = 0; c0 < n; c0 += chunk) {
-        TgSmallArgs b = a;
-        b.n = std::min(chunk, n - c0);
-        b.Y = Y + c0 * ldY;
-        b.uH = uH + c0 * DH;
-        b.lamH = lamH + c0;
-        b.lam = lam + c0;
-        b.g = g ? g + c0 : nullptr;
-        b.lin_iters = lin_iters ? lin_iters + c0 : nullptr;
-        b.flags = flags + c0;
-        ctx->t_begin(MLQMC_K_TG_LDS);
-        CK(launch_tg_small(nh, b, ctx->stream), "two-grid (global scratch)");
-        ctx->t_end(MLQMC_K_TG_LDS, 0.0);
-      }
-      return MLQMC_OK;
-    }
     ctx->t_begin(MLQMC_K_TG_LDS);
     CK(launch_tg_small(nh, a, ctx->stream), "two-grid (LDS)");
     ctx->t_end(MLQMC_K_TG_LDS, 0.0);
@@ -1635,13 +1633,30 @@ mlqmc_status nested_core(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, cons
   for (int64_t k = 0; k < (int64_t)R * s_max; ++k)
     if (!(shifts[k] >= 0.0 && shifts[k] < 1.0))
       return ctx->fail(MLQMC_EINVAL, "shift entry %lld outside [0, 1)", (long long)k);
-  for (int l = 0; l < nl; ++l) e[l] = (l + 1 < nl) ? std::min(a[l], a[l + 1]) : a[l];
-  e[0] = *std::min_element(e.begin(), e.end());
+  // Level l is evaluated on [e_l, f_l): its own new points [a_l, N_l) and the
+  // points [a_{l+1}, N_{l+1}) where level l+1 needs lambda^l; level 0 on the
+  // union of the non-empty ranges (it supplies every level's coarse pairs).
+  std::vector<int64_t> f(nl);
+  for (int l = 0; l < nl; ++l) {
+    e[l] = (l + 1 < nl) ? std::min(a[l], a[l + 1]) : a[l];
+    f[l] = a[l] < N[l] ? N[l] : e[l];
+    if (l + 1 < nl && a[l + 1] < N[l + 1]) f[l] = std::max(f[l], N[l + 1]);
+  }
+  {
+    int64_t lo = -1, hi = -1;
+    for (int l = 0; l < nl; ++l)
+      if (f[l] > e[l]) {
+        lo = lo < 0 ? e[l] : std::min(lo, e[l]);
+        hi = std::max(hi, f[l]);
+      }
+    e[0] = lo < 0 ? N[0] : lo;
+    f[0] = lo < 0 ? N[0] : hi;
+  }
   if (lam_out && std::any_of(a.begin(), a.end(), [](int64_t v) { return v != 0; }))
     return ctx->fail(MLQMC_EINVAL, "lam_out needs every level to start at point 0");
   int64_t ymax = 1;
   for (int l = 0; l < nl; ++l)
-    ymax = std::max<int64_t>(ymax, (int64_t)R * (N[l] - e[l]) * std::max(1, (int)lv[l].s_fine));
+    ymax = std::max<int64_t>(ymax, (int64_t)R * (f[l] - e[l]) * std::max(1, (int)lv[l].s_fine));
   hipStream_t st = ctx->stream;
   const int dev = o->io_on_device;
   double *dQ, *dQh, *dV, *dest, *dlo = nullptr;
@@ -1657,7 +1672,7 @@ mlqmc_status nested_core(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, cons
   const double* dsh;
   CS(stage_in(ctx, "e_z", z, s_max, 0, &dz));
   CS(stage_in(ctx, "e_sh", shifts, (size_t)R * s_max, 0, &dsh));
-  const int64_t N0 = N[0], c0 = e[0], n0pts = N0 - c0, B0 = (int64_t)R * n0pts;
+  const int64_t N0 = N[0], c0 = e[0], n0pts = f[0] - c0, B0 = (int64_t)R * n0pts;
   const int n0 = L0.n_fine, s0 = L0.s_fine;
   const int64_t D0 = (int64_t)(n0 - 1) * (n0 - 1);
   double *Y, *lam0 = nullptr, *u0 = nullptr;
@@ -1736,7 +1751,7 @@ mlqmc_status nested_core(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, cons
   };
   for (int l = 1; l < nl; ++l) {
     const mlqmc_level& L = lv[l];
-    const int64_t cnt = N[l] - e[l], Bl = (int64_t)R * cnt;
+    const int64_t cnt = f[l] - e[l], Bl = (int64_t)R * cnt;
     const int sl = L.s_fine;
     double* lam = nullptr;
     double* gl = nullptr;
@@ -1851,6 +1866,146 @@ mlqmc_status mlqmc_estimate_nested_extend(mlqmc_ctx* ctx, int32_t nl, const mlqm
   CS(ctx->sync("estimate_nested_extend"));
   if (stc == MLQMC_ENOCONV) ctx->err = msg;
   return stc;
+}
+
+int32_t mlqmc_adaptive_decide(int32_t n_levels, int32_t max_levels, const double* Qhat,
+                              const double* V, const int64_t* N, const double* cost, double eps,
+                              double alpha, int64_t N_max, int32_t* level) {
+  if (n_levels < 1 || n_levels > max_levels || !Qhat || !V || !N || !cost || !level ||
+      !(eps > 0) || !(alpha > 0) || N_max < 1)
+    return -1;
+  // variance first: sum_l V_l <= eps^2 / 2 (summed left to right)
+  double var = 0.0;
+  for (int l = 0; l < n_levels; ++l) var += V[l];
+  if (var > eps * eps / 2.0) {
+    int best = 0;
+    double score = -1.0;
+    for (int l = 0; l < n_levels; ++l) {
+      const double sc = V[l] / ((double)N[l] * cost[l]);
+      if (sc > score) {
+        best = l;
+        score = sc;
+      }
+    }
+    *level = best;
+    return 2 * N[best] > N_max ? MLQMC_ADAPT_BUDGET : MLQMC_ADAPT_DOUBLE;
+  }
+  // then the bias of the finest level in use: |Qhat_{L-1}| / (2^alpha - 1)
+  if (n_levels >= 2) {
+    const double bias = std::fabs(Qhat[n_levels - 1]) / (std::pow(2.0, alpha) - 1.0);
+    if (bias > eps / std::sqrt(2.0)) {
+      if (n_levels >= max_levels) {
+        *level = n_levels - 1;
+        return MLQMC_ADAPT_LEVELS;
+      }
+      *level = n_levels;
+      return MLQMC_ADAPT_ADD;
+    }
+  }
+  *level = -1;
+  return MLQMC_ADAPT_DONE;
+}
+
+mlqmc_status mlqmc_estimate_adaptive(mlqmc_ctx* ctx, int32_t max_levels, const mlqmc_level* lv,
+                                     int32_t R, const int64_t* z, const double* shifts,
+                                     const mlqmc_adaptive_opts* ao, const mlqmc_opts* o,
+                                     int32_t* n_levels, int64_t* N_out, double* Q_lr,
+                                     double* Qhat, double* V, double* est, int32_t* converged,
+                                     int32_t* trace, int32_t trace_cap, int32_t* trace_len) {
+  if (!ctx) return MLQMC_EINVAL;
+  CS(check_opts(ctx, o));
+  if (max_levels < 1 || !lv || !z || !shifts || !ao)
+    return ctx->fail(MLQMC_EINVAL, "need max_levels >= 1 and non-NULL inputs");
+  if (R < 2) return ctx->fail(MLQMC_EINVAL, "the adaptive rule needs R >= 2 shifts (V_l)");
+  if (!n_levels || !N_out || !Q_lr || !Qhat || !V || !est || !converged || !trace_len ||
+      (trace_cap > 0 && !trace) || trace_cap < 0)
+    return ctx->fail(MLQMC_EINVAL, "NULL output");
+  if (o->io_on_device) return ctx->fail(MLQMC_EINVAL, "the adaptive estimate takes host arrays");
+  if (!(ao->eps > 0) || !(ao->alpha > 0) || !(ao->gamma > 0) || !is_pow2(ao->N_init) ||
+      !is_pow2(ao->N_max) || ao->N_max < ao->N_init || ao->N_max > ((int64_t)1 << 30))
+    return ctx->fail(MLQMC_EINVAL, "adaptive options: eps, alpha, gamma > 0; N_init <= N_max "
+                                   "powers of two, N_max <= 2^30");
+  // cost of one sample (section 4.2, d = 2): s_l h_l^-2 + h_l^-gamma
+  std::vector<double> cost(max_levels);
+  for (int l = 0; l < max_levels; ++l) {
+    const double n = (double)lv[l].n_fine;
+    cost[l] = (double)lv[l].s_fine * n * n + std::pow(n, ao->gamma);
+  }
+  mlqmc_opts oh = *o;
+  oh.io_on_device = 0;
+  // z [s_all] and shifts [R x s_all] cover every level allowed; a call over
+  // the first L levels reads them with row length max_{l<L} s_l
+  int s_all = 0;
+  for (int l = 0; l < max_levels; ++l) s_all = std::max(s_all, (int)lv[l].s_fine);
+  std::vector<double> sh_l;
+  auto shifts_for = [&](int L) -> const double* {
+    int s_l = 0;
+    for (int l = 0; l < L; ++l) s_l = std::max(s_l, (int)lv[l].s_fine);
+    sh_l.resize((size_t)R * s_l);
+    for (int r = 0; r < R; ++r)
+      for (int j = 0; j < s_l; ++j) sh_l[(size_t)r * s_l + j] = shifts[(size_t)r * s_all + j];
+    return sh_l.data();
+  };
+  CK(hipSetDevice(ctx->device), "set device");
+  ctx->mem_cap = o->device_mem_cap;
+  double* dsum = nullptr;
+  CS(ctx->getT("a_sum", (size_t)max_levels * R, &dsum));
+  CK(hipMemsetAsync(dsum, 0, (size_t)max_levels * R * sizeof(double), ctx->stream), "memset");
+  int L = std::min(2, (int)max_levels);
+  std::vector<int64_t> N(L, ao->N_init), Nd(L, 0);
+  std::vector<double> q((size_t)max_levels * R), qh(max_levels), vv(max_levels), e2(2);
+  bool flagged = false;
+  std::string flag_msg;
+  int len = 0, act = MLQMC_ADAPT_DONE;
+  for (;;) {
+    const mlqmc_status st =
+        nested_core(ctx, L, lv, Nd.data(), N.data(), R, z, shifts_for(L), &oh, dsum, nullptr,
+                    q.data(), qh.data(), vv.data(), e2.data(), nullptr, nullptr);
+    if (st == MLQMC_ENOCONV) {
+      flagged = true;
+      flag_msg = ctx->err;
+    } else if (st != MLQMC_OK) {
+      return st;
+    }
+    Nd = N;
+    int lev = -1;
+    act = mlqmc_adaptive_decide(L, max_levels, qh.data(), vv.data(), N.data(), cost.data(),
+                                ao->eps, ao->alpha, ao->N_max, &lev);
+    if (len < trace_cap) {
+      trace[2 * len] = act;
+      trace[2 * len + 1] = lev;
+    }
+    ++len;
+    if (act == MLQMC_ADAPT_DOUBLE) {
+      // nested rules: N non-increasing in l, so coarser levels follow
+      N[lev] *= 2;
+      for (int l = lev - 1; l >= 0; --l) N[l] = std::max(N[l], N[l + 1]);
+    } else if (act == MLQMC_ADAPT_ADD) {
+      N.push_back(ao->N_init);
+      Nd.push_back(0);
+      ++L;
+    } else {
+      break;
+    }
+  }
+  *n_levels = L;
+  for (int l = 0; l < L; ++l) {
+    N_out[l] = N[l];
+    Qhat[l] = qh[l];
+    V[l] = vv[l];
+    for (int r = 0; r < R; ++r) Q_lr[(size_t)l * R + r] = q[(size_t)l * R + r];
+  }
+  double vs = 0.0;
+  for (int l = 0; l < L; ++l) vs += vv[l];
+  est[0] = e2[0];
+  est[1] = vs;
+  *converged = act == MLQMC_ADAPT_DONE ? 1 : 0;
+  *trace_len = len;
+  if (flagged) {
+    ctx->err = flag_msg;
+    return MLQMC_ENOCONV;
+  }
+  return MLQMC_OK;
 }
 
 mlqmc_status mlqmc_set_tuning(mlqmc_ctx* ctx, int32_t n_fine, int32_t prec,

@@ -14,6 +14,13 @@
 // WY[k+n]).  A sample's weights are [WX | WY], 2 (n+2) n values.  Entries that
 // are not edges of an interior node are never read.  Weights use the same
 // (n+2) n positions per half.
+// With the reaction term of Problem 2 (kR) a sample's block is
+// [WX | WY | RX | RY | RD], 5 (n+2) n values: RX, RY the means of b over the two
+// elements of each horizontal and vertical edge, indexed as WX, WY, and RD
+// those of each "/" diagonal, stored at its north-east end (RD[k] is the
+// south-west and RD[k+n+1] the north-east diagonal of node k).  The operator
+// is then A + R with (R x)_k = h^2/12 sum over the six edges e at k of
+// r_e (x_k + x_e) (element mass matrices weighted by b).
 //
 // Work mapping: a launch covers B samples x nblk blocks (column blocks x row
 // strips of one sample).  Hardware block L runs on XCD L mod 8; sample b is
@@ -196,20 +203,52 @@ __device__ __forceinline__ void march_pf(T (*ring)[NTC + 2], const MGeo& g, int 
   }
 }
 
-// the four edge weights of node k
-template <typename W>
+// weight arrays per sample block: [WX | WY], or with the reaction [WX | WY | RX | RY | RD]
+template <bool kR>
+constexpr int wblk() {
+  return kR ? 5 : 2;
+}
+
+// The coefficients of node k: the four edge weights of A and, with the
+// reaction, h^2/12 times the means of b on the six edges at k (west, east,
+// south, north, south-west, north-east).
+template <typename W, bool kR = false>
 struct Wts {
   W ww, we, ws, wn;
+  W rw, re, rs, rn, rsw, rne;
 };
-template <typename W>
-__device__ __forceinline__ Wts<W> load_wts(const W* wx, const W* wy, int k, int n) {
-  return Wts<W>{wx[k], wx[k + 1], wy[k], wy[k + n]};
+template <typename W, bool kR = false>
+__device__ __forceinline__ Wts<W, kR> load_wts(const W* wx, const W* wy, int k, int n, int P = 0,
+                                               W hm = W(0)) {
+  Wts<W, kR> o;
+  o.ww = wx[k];
+  o.we = wx[k + 1];
+  o.ws = wy[k];
+  o.wn = wy[k + n];
+  if constexpr (kR) {
+    const W* rx = wx + 2 * P;
+    const W* ry = wx + 3 * P;
+    const W* rd = wx + 4 * P;
+    o.rw = hm * rx[k];
+    o.re = hm * rx[k + 1];
+    o.rs = hm * ry[k];
+    o.rn = hm * ry[k + n];
+    o.rsw = hm * rd[k];
+    o.rne = hm * rd[k + n + 1];
+  }
+  return o;
 }
-template <typename T, typename W>
-__device__ __forceinline__ T ring_Aw(const T* rs, const T* rc, const T* rn, int ci, const Wts<W>& w) {
+// ((A [+ R]) x)_k from a ring of x rows (south, centre, north; column ci)
+template <typename T, typename W, bool kR = false>
+__device__ __forceinline__ T ring_Aw(const T* rs, const T* rc, const T* rn, int ci,
+                                     const Wts<W, kR>& w) {
   const T c = rc[ci];
-  return (T)w.ww * (c - rc[ci - 1]) + (T)w.we * (c - rc[ci + 1]) + (T)w.ws * (c - rs[ci]) +
-         (T)w.wn * (c - rn[ci]);
+  T a = (T)w.ww * (c - rc[ci - 1]) + (T)w.we * (c - rc[ci + 1]) + (T)w.ws * (c - rs[ci]) +
+        (T)w.wn * (c - rn[ci]);
+  if constexpr (kR)
+    a += (T)w.rw * (c + rc[ci - 1]) + (T)w.re * (c + rc[ci + 1]) + (T)w.rs * (c + rs[ci]) +
+         (T)w.rn * (c + rn[ci]) + (T)w.rsw * (c + rs[ci - 1]) + (T)w.rne * (c + rn[ci + 1]);
+  return a;
 }
 
 template <int NTC, int K>
@@ -302,34 +341,39 @@ __global__ __launch_bounds__(256) void k_prolong_interior(int xblk, int nH, int 
   uh[b * Dh + id] = interp_coarse(uH + b * (int64_t)(mH * mH), nH, nh / nH, i, j);
 }
 
-// padded weights of mesh n/2 from those of mesh n (means of collinear fine edges)
-template <typename T>
+// padded weights of mesh n/2 from those of mesh n: each coarse edge weight is
+// the mean of the two collinear fine edges it covers (horizontal, vertical
+// and, with the reaction, the "/" diagonal of a coarse square, which covers the
+// diagonals of fine squares (2I, 2J) and (2I+1, 2J+1))
+template <typename T, bool kR>
 __global__ __launch_bounds__(256) void k_coarsen(int xblk, int n, int64_t B, const T* __restrict__ w,
                                                  T* __restrict__ wc) {
   const int nc = n / 2;
   const int P = (n + 2) * n, Pc = (nc + 2) * nc;
   const int64_t b = blockIdx.x / xblk;  // grid x = xblk blocks per sample x samples
   const int e = (int)(blockIdx.x - b * xblk) * 256 + threadIdx.x;
-  if (e >= 2 * Pc || b >= B) return;
-  const T* wx = w + b * 2 * P;
-  const T* wy = wx + P;
+  if (e >= wblk<kR>() * Pc || b >= B) return;
+  const int seg = e / Pc, f = e - seg * Pc;  // [WX | WY | RX | RY | RD]
+  const T* src = w + b * wblk<kR>() * P + (int64_t)seg * P;
+  const int J = f / nc, I = f % nc;
   T val = T(0);
-  if (e < Pc) {  // WXc(J, I) = edge (I-1,J)-(I,J), I in [1, nc], stored at J*nc + I
-    const int J = e / nc, I = e % nc;
+  if (seg == 0 || seg == 2) {  // edge (I-1,J)-(I,J), stored at J*nc + I (I = 0: (nc, J-1))
     const int Ie = (I == 0) ? nc : I, Je = (I == 0) ? J - 1 : J;
     if (Je >= 1 && Je <= nc - 1)
-      val = T(0.5) * (wx[2 * Je * n + 2 * Ie - 1] + wx[2 * Je * n + 2 * Ie]);
-  } else {       // WYc(J, I) = edge (I,J-1)-(I,J), stored at J*nc + I
-    const int f = e - Pc;
-    const int J = f / nc, I = f % nc;
+      val = T(0.5) * (src[2 * Je * n + 2 * Ie - 1] + src[2 * Je * n + 2 * Ie]);
+  } else if (seg == 1 || seg == 3) {  // edge (I,J-1)-(I,J), stored at J*nc + I
     if (J >= 1 && J <= nc && I >= 1)
-      val = T(0.5) * (wy[(2 * J - 1) * n + 2 * I] + wy[2 * J * n + 2 * I]);
+      val = T(0.5) * (src[(2 * J - 1) * n + 2 * I] + src[2 * J * n + 2 * I]);
+  } else {  // diagonal of coarse square (Ic, Jc) at its north-east end (Jc+1)*nc + Ic+1
+    const int Ic = (I == 0) ? nc - 1 : I - 1, Jc = (I == 0) ? J - 2 : J - 1;
+    if (Ic >= 0 && Ic <= nc - 1 && Jc >= 0 && Jc <= nc - 1)
+      val = T(0.5) * (src[(2 * Jc + 1) * n + 2 * Ic + 1] + src[(2 * Jc + 2) * n + 2 * Ic + 2]);
   }
-  wc[b * 2 * Pc + e] = val;
+  wc[b * wblk<kR>() * Pc + e] = val;
 }
 
 // partials: v.M12 v, v.A v  (raw FP64 v, FP64 weights)
-template <int NTC>
+template <int NTC, bool kR>
 __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, Coarse cv,
                                                     const double* __restrict__ w,
                                                     double* __restrict__ part) {
@@ -337,15 +381,16 @@ __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, Coarse cv,
   int64_t b;
   int c0, j0, j1, blk, dir;
   if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir)) return;
-  const double* wx = w + b * 2 * g.P;
+  const double* wx = w + b * wblk<kR>() * g.P;
   const double* wy = wx + g.P;
+  const double hm = mass_scale(g.n);
   double s[2] = {0.0, 0.0};
   march_pf<double, NTC>(
       ring, g, c0, j0, j1, dir, [&](int k) { return coarse_v(cv, g, b, k); },
       [](double f) { return f; },
-      [&](int k) { return load_wts(wx, wy, k, g.n); },
+      [&](int k) { return load_wts<double, kR>(wx, wy, k, g.n, g.P, hm); },
       [&](int, int, const double* rs, const double* rc, const double* rn, int ci,
-          const Wts<double>& wt, double) {
+          const Wts<double, kR>& wt, double) {
         const double av = ring_Aw(rs, rc, rn, ci, wt);
         s[0] += rc[ci] * ring_M12(rs, rc, rn, ci);
         s[1] += rc[ci] * av;
@@ -355,7 +400,7 @@ __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, Coarse cv,
 
 // r = -(A v_n - rho M v_n) (FP64), vn = v_n, mvn = M v_n (t starts at 0 without
 // being stored: the PCG kernels read t only from its third step on)
-template <typename T, int NTC>
+template <typename T, int NTC, bool kR>
 __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
                                                    const double* __restrict__ w64, FineState S,
                                                    T* __restrict__ r, T* __restrict__ vn,
@@ -364,15 +409,15 @@ __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
   int64_t b;
   int c0, j0, j1, blk, dir;
   if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir)) return;
-  const double* wx = w64 + b * 2 * g.P;
+  const double* wx = w64 + b * wblk<kR>() * g.P;
   const double* wy = wx + g.P;
   const double vs = S.vs[b], rho = S.rho[b], hm = mass_scale(g.n);
   march_pf<double, NTC>(
       ring, g, c0, j0, j1, dir, [&](int k) { return coarse_v(cv, g, b, k); },
       [](double f) { return f; },
-      [&](int k) { return load_wts(wx, wy, k, g.n); },
+      [&](int k) { return load_wts<double, kR>(wx, wy, k, g.n, g.P, hm); },
       [&](int, int k, const double* rs, const double* rc, const double* rn, int ci,
-          const Wts<double>& wt, double) {
+          const Wts<double, kR>& wt, double) {
                        const double av = ring_Aw(rs, rc, rn, ci, wt);
                        const double mv = hm * ring_M12(rs, rc, rn, ci);
                        const double rv = -vs * (av - rho * mv);
@@ -388,7 +433,7 @@ __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
 
 // p = z - c2 vn + beta p_in (first: beta = 0), q = (A - mu M) p;
 // partials p.q, vn.q, p.M vn
-template <typename T, int NTC>
+template <typename T, int NTC, bool kR>
 __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restrict__ z,
                                                        const T* __restrict__ vn,
                                                        const T* __restrict__ pin,
@@ -408,7 +453,7 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
   const T* zz = z + b * g.P;
   const T* vb = vn + b * g.P;
   const T* pb = pin + b * g.P;
-  const T* wx = w + b * 2 * g.P;
+  const T* wx = w + b * wblk<kR>() * g.P;
   const T* wy = wx + g.P;
   T* tb = t + b * g.P;
   const T c2 = (T)S.c2[b], beta = first ? T(0) : (T)S.beta[b], mu = (T)S.mu[b];
@@ -431,7 +476,8 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
     T z, v, p, zh, vh, ph;
   };
   struct Row {
-    T ww, we, ws, wn, tt;
+    Wts<T, kR> w;
+    T tt;
   };
   auto fetch_src = [&](int j, Src& f) {
     const bool rowok = (j >= 1 && j <= n - 1);
@@ -462,11 +508,7 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
   auto fetch_row = [&](int j, Row& r) {
     if (c >= 1 && j >= j0 && j < j1) {
       const int k = j * n + c;
-      r.ww = wx[k];
-      r.we = wx[k + 1];
-      r.ws = wy[k];
-      r.wn = wy[k + n];
-
+      r.w = load_wts<T, kR>(wx, wy, k, n, g.P, hm);
       r.tt = tread ? tb[k] : T(0);
     }
   };
@@ -497,8 +539,7 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restri
       const T* xc = ring[j & 3];
       const T* xn = ring[(j + 1) & 3];
       const T pc = xc[ci];
-      const T ap = rc.ww * (pc - xc[ci - 1]) + rc.we * (pc - xc[ci + 1]) + rc.ws * (pc - xs[ci]) +
-                   rc.wn * (pc - xn[ci]);
+      const T ap = ring_Aw<T, T, kR>(xs, xc, xn, ci, rc.w);
       const T m12 = T(6) * pc + xc[ci - 1] + xc[ci + 1] + xs[ci] + xn[ci] + xn[ci + 1] +
                     xs[ci - 1];
       const T qv = ap - mu * hm * m12;
@@ -575,6 +616,53 @@ __device__ __forceinline__ constexpr double sweep_omega(int m) {
   return m == 0 ? kOmega1 : kOmega2;
 }
 
+// Row inputs of a node in the fused V-cycle kernels: in[0] the right-hand
+// side, in[1..4] the edge weights (west, east, south, north) and, with the
+// reaction, in[5..10] h^2/12 times the edge means of b (west, east, south,
+// north, south-west, north-east).
+template <bool kR>
+constexpr int row_inputs() {
+  return kR ? 11 : 5;
+}
+template <typename T, bool kR>
+__device__ __forceinline__ void fetch_row_inputs(T* dst, const T* rb, const T* wx, const T* wy,
+                                                 int k, int n, int P, T hm) {
+  dst[0] = rb[k];
+  dst[1] = wx[k];
+  dst[2] = wx[k + 1];
+  dst[3] = wy[k];
+  dst[4] = wy[k + n];
+  if constexpr (kR) {
+    const T* rx = wx + 2 * P;
+    const T* ry = wx + 3 * P;
+    const T* rd = wx + 4 * P;
+    dst[5] = hm * rx[k];
+    dst[6] = hm * rx[k + 1];
+    dst[7] = hm * ry[k];
+    dst[8] = hm * ry[k + n];
+    dst[9] = hm * rd[k];
+    dst[10] = hm * rd[k + n + 1];
+  }
+}
+// the diagonal of A [+ R] at a node from its row inputs
+template <typename T, bool kR>
+__device__ __forceinline__ T row_diag(const T* in) {
+  T d = in[1] + in[2] + in[3] + in[4];
+  if constexpr (kR) d += in[5] + in[6] + in[7] + in[8] + in[9] + in[10];
+  return d;
+}
+// ((A [+ R]) x) at column c of the centre row zc (rows zs, zn south and north)
+template <typename T, bool kR>
+__device__ __forceinline__ T row_op(const T* in, const T* zs, const T* zc, const T* zn, int c) {
+  const T x = zc[c];
+  T ax = in[1] * (x - zc[c - 1]) + in[2] * (x - zc[c + 1]) + in[3] * (x - zs[c]) +
+         in[4] * (x - zn[c]);
+  if constexpr (kR)
+    ax += in[5] * (x + zc[c - 1]) + in[6] * (x + zc[c + 1]) + in[7] * (x + zs[c]) +
+          in[8] * (x + zn[c]) + in[9] * (x + zs[c - 1]) + in[10] * (x + zn[c + 1]);
+  return ax;
+}
+
 // Pre-smoothing and restriction of one level, NS Jacobi sweeps from zero:
 //   X_1 = omega_1 rhs / D;  X_m = X_{m-1} + omega_m (rhs - A X_{m-1}) / D;
 //   X = X_NS;  rhs_c = P^T (rhs - A X)
@@ -588,7 +676,7 @@ __device__ __forceinline__ constexpr double sweep_omega(int m) {
 // read r on their halo rows).  q = (A - mu M) p is recomputed here from the
 // direction p (a ring of p rows two rows ahead of the first sweep) with the
 // same operations as the apply kernel, so q is never stored.
-template <typename T, int NTC, int CPT, bool kUpd, int NS>
+template <typename T, int NTC, int CPT, bool kUpd, int NS, bool kR>
 __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
                                              const T* __restrict__ rhs, T* __restrict__ X,
                                              T* __restrict__ rhs_c,
@@ -607,10 +695,11 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
   const int own_hi = (J1 == nc) ? hi + 1 : hi;  // owned fine rows [lo, own_hi)
   const int dir = (s & 1) ? -1 : 1;             // odd strips march downwards
   const T* rb = rhs + b * g.P;
-  const T* wx = w + b * 2 * g.P;
+  const T* wx = w + b * wblk<kR>() * g.P;
   const T* wy = wx + g.P;
   T* xb = X + b * g.P;
   T* cb = rhs_c + b * (int64_t)((nc + 2) * nc);
+  constexpr int NI = row_inputs<kR>();
   T alpha = T(0), cc = T(0), mu = T(0);
   const T hm = (T)mass_scale(n);
   if constexpr (kUpd) {
@@ -625,11 +714,11 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
       s_res[r][n] = T(0);
       if constexpr (kUpd) s_p[r][n] = T(0);
     }
-  // register window of the row inputs (rhs, the 4 edge weights) of the rows
+  // register window of the row inputs (rhs, the edge weights) of the rows
   // at the NS sweep stages and the residual stage: each is loaded once, one
   // row ahead of the first sweep (nx; with kUpd also M vn), and carried
   // through the stages (in[0] -> in[NS])
-  T nx[CPT][7], in[NS + 1][CPT][5];
+  T nx[CPT][NI + 1], in[NS + 1][CPT][NI];
   // with kUpd: p of the row the ring takes next, loaded one iteration early
   T pn[CPT];
   auto fetch_p = [&](int j) {
@@ -650,12 +739,8 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
     for (int q = 0; q < CPT; ++q) {
       const int c = t + q * NTC, k = j * n + c;
       if (c >= 1) {
-        nx[q][0] = rb[k];
-        nx[q][1] = wx[k];
-        nx[q][2] = wx[k + 1];
-        nx[q][3] = wy[k];
-        nx[q][4] = wy[k + n];
-        if constexpr (kUpd) nx[q][6] = mvn[b * g.P + k];
+        fetch_row_inputs<T, kR>(nx[q], rb, wx, wy, k, n, g.P, hm);
+        if constexpr (kUpd) nx[q][NI] = mvn[b * g.P + k];
       }
     }
   };
@@ -682,10 +767,10 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
 #pragma unroll
         for (int m = NS; m > 0; --m)
 #pragma unroll
-          for (int e = 0; e < 5; ++e) in[m][q][e] = in[m - 1][q][e];
+          for (int e = 0; e < NI; ++e) in[m][q][e] = in[m - 1][q][e];
 #pragma unroll
-        for (int e = 0; e < 5; ++e) in[0][q][e] = nx[q][e];
-        if constexpr (kUpd) mvj[q] = nx[q][6];
+        for (int e = 0; e < NI; ++e) in[0][q][e] = nx[q][e];
+        if constexpr (kUpd) mvj[q] = nx[q][NI];
       }
       if (i < last) fetch(j + dir);
       if constexpr (kUpd) {
@@ -705,16 +790,14 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
             const T* xn = s_p[(j + 1) & 3];
             const T* inq = in[0][q];
             const T pc = xc[c];
-            const T ap = inq[1] * (pc - xc[c - 1]) + inq[2] * (pc - xc[c + 1]) +
-                         inq[3] * (pc - xs[c]) + inq[4] * (pc - xn[c]);
+            const T ap = row_op<T, kR>(inq, xs, xc, xn, c);
             const T m12 = T(6) * pc + xc[c - 1] + xc[c + 1] + xs[c] + xn[c] + xn[c + 1] +
                           xs[c - 1];
             const T qv = ap - mu * hm * m12;
             in[0][q][0] = inq[0] - alpha * (qv - cc * mvj[q]);
             if (j >= lo && j < own_hi) rout[b * g.P + k] = in[0][q][0];
           }
-          v = T(sweep_omega<NS>(0)) * in[0][q][0] /
-              (in[0][q][1] + in[0][q][2] + in[0][q][3] + in[0][q][4]);
+          v = T(sweep_omega<NS>(0)) * in[0][q][0] / row_diag<T, kR>(in[0][q]);
         }
         row[c] = v;
       }
@@ -738,10 +821,8 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
           if (ok && c >= 1) {
             const T* inm = in[m][q];
             const T x = zc[c];
-            const T d = inm[1] + inm[2] + inm[3] + inm[4];
-            const T ax = inm[1] * (x - zc[c - 1]) + inm[2] * (x - zc[c + 1]) +
-                         inm[3] * (x - zs[c]) + inm[4] * (x - zn[c]);
-            v = x + T(sweep_omega<NS>(m)) * (inm[0] - ax) / d;
+            const T ax = row_op<T, kR>(inm, zs, zc, zn, c);
+            v = x + T(sweep_omega<NS>(m)) * (inm[0] - ax) / row_diag<T, kR>(inm);
             if (m == NS - 1 && jz >= lo && jz < own_hi) xb[k] = v;
           }
           row[c] = v;
@@ -762,9 +843,7 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
         T v = T(0);
         if (c >= 1) {
           const T* inr = in[NS][q];
-          const T x = xc[c];
-          v = inr[0] - (inr[1] * (x - xc[c - 1]) + inr[2] * (x - xc[c + 1]) +
-                        inr[3] * (x - xs[c]) + inr[4] * (x - xn[c]));
+          v = inr[0] - row_op<T, kR>(inr, xs, xc, xn, c);
         }
         row[c] = v;
       }
@@ -796,7 +875,7 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
 // owns fine rows [f0, f1); sweep m runs on them widened by NS - m rows on
 // each side.  Xout must differ from Xin (neighbour strips read Xin rows
 // across the strip boundary).
-template <typename T, int NTC, int CPT, bool kDots, int NS>
+template <typename T, int NTC, int CPT, bool kDots, int NS, bool kR>
 __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
                                               const T* __restrict__ rhs,
                                               const T* __restrict__ Xin,
@@ -817,9 +896,11 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
   const T* rb = rhs + b * g.P;
   const T* xi = Xin + b * g.P;
   const T* xc = Xc + b * (int64_t)((nc + 2) * nc);
-  const T* wx = w + b * 2 * g.P;
+  const T* wx = w + b * wblk<kR>() * g.P;
   const T* wy = wx + g.P;
   const T* vb = vn + b * g.P;
+  constexpr int NI = row_inputs<kR>();
+  const T hm = (T)mass_scale(n);
   const T* mb = mvn + b * g.P;
   T* xo = Xout + b * g.P;
   double acc[3] = {0.0, 0.0, 0.0};
@@ -832,7 +913,7 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
   // row ahead, the row inputs of the sweeps (rhs, 4 edge weights) as in[0]
   // one row ahead of the first sweep, then kept through the later sweeps
   // (in[1] -> in[NS]).
-  T ux[CPT][3], in[NS + 1][CPT][5];
+  T ux[CPT][3], in[NS + 1][CPT][NI];
   auto fetch_u = [&](int j) {
     const bool ok = (j >= 1 && j <= n - 1);
 #pragma unroll
@@ -852,13 +933,7 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int c = t + q * NTC, k = j * n + c;
-      if (c >= 1) {
-        in[0][q][0] = rb[k];
-        in[0][q][1] = wx[k];
-        in[0][q][2] = wx[k + 1];
-        in[0][q][3] = wy[k];
-        in[0][q][4] = wy[k + n];
-      }
+      if (c >= 1) fetch_row_inputs<T, kR>(in[0][q], rb, wx, wy, k, n, g.P, hm);
     }
   };
   const int jfirst = dir > 0 ? f0 - NS : f1 + NS - 1;
@@ -874,7 +949,7 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
 #pragma unroll
       for (int m = NS; m > 0; --m)
 #pragma unroll
-        for (int e = 0; e < 5; ++e) in[m][q][e] = in[m - 1][q][e];
+        for (int e = 0; e < NI; ++e) in[m][q][e] = in[m - 1][q][e];
     }
     if (i < last) {
       fetch_u(j + dir);
@@ -917,10 +992,8 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
           if (ok && c >= 1) {
             const T* inm = in[m][q];
             const T x = uc0[c];
-            const T d = inm[1] + inm[2] + inm[3] + inm[4];
-            const T ax = inm[1] * (x - uc0[c - 1]) + inm[2] * (x - uc0[c + 1]) +
-                         inm[3] * (x - us[c]) + inm[4] * (x - un[c]);
-            v = x + T(sweep_omega<NS>(m - 1)) * (inm[0] - ax) / d;
+            const T ax = row_op<T, kR>(inm, us, uc0, un, c);
+            v = x + T(sweep_omega<NS>(m - 1)) * (inm[0] - ax) / row_diag<T, kR>(inm);
           }
           row[c] = v;
         }
@@ -938,10 +1011,8 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
         if (c >= 1) {
           const T* inl = in[NS][q];
           const T x = zc[c];
-          const T d = inl[1] + inl[2] + inl[3] + inl[4];
-          const T ax = inl[1] * (x - zc[c - 1]) + inl[2] * (x - zc[c + 1]) +
-                       inl[3] * (x - zs[c]) + inl[4] * (x - zn[c]);
-          const T zz = x + T(sweep_omega<NS>(NS - 1)) * (inl[0] - ax) / d;
+          const T ax = row_op<T, kR>(inl, zs, zc, zn, c);
+          const T zz = x + T(sweep_omega<NS>(NS - 1)) * (inl[0] - ax) / row_diag<T, kR>(inl);
           xo[k] = zz;
           if constexpr (kDots) {
             acc[0] += (double)inl[0] * (double)zz;
@@ -968,7 +1039,7 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
 
 // w = vs v + t (FP64): partials w.A w, w.M12 w with FP64 weights, and the
 // sum of w (h^2 times it is the integral of the P1 function w)
-template <typename T, int NTC>
+template <typename T, int NTC, bool kR>
 __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, Coarse cv,
                                                     const T* __restrict__ t,
                                                     const T* __restrict__ p0,
@@ -987,8 +1058,9 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, Coarse cv,
   const T al = its > 0 ? (T)S.alpha[b] : T(0);
   const bool tread = its >= 2;  // t_{its-1} stored (t_0 = 0 never is)
   const double vs = S.vs[b];
-  const double* wx = w + b * 2 * g.P;
+  const double* wx = w + b * wblk<kR>() * g.P;
   const double* wy = wx + g.P;
+  const double hm = mass_scale(g.n);
   double s[3] = {0.0, 0.0, 0.0};
   struct Fin {
     double v;
@@ -998,9 +1070,9 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, Coarse cv,
       ring, g, c0, j0, j1, dir,
       [&](int k) { return Fin{coarse_v(cv, g, b, k), tread ? tb[k] : T(0), pl[k]}; },
       [&](const Fin& f) { return vs * f.v + (double)(T)(f.t + al * f.p); },
-      [&](int k) { return load_wts(wx, wy, k, g.n); },
+      [&](int k) { return load_wts<double, kR>(wx, wy, k, g.n, g.P, hm); },
       [&](int, int, const double* rs, const double* rc, const double* rn, int ci,
-          const Wts<double>& wt, const Fin&) {
+          const Wts<double, kR>& wt, const Fin&) {
         const double aw = ring_Aw(rs, rc, rn, ci, wt);
         s[0] += rc[ci] * aw;
         s[1] += rc[ci] * ring_M12(rs, rc, rn, ci);
@@ -1166,14 +1238,29 @@ hipError_t launch_prolong_interior(int nH, int nh, int64_t B, const double* uH, 
 }
 
 template <typename T>
-hipError_t launch_coarsen(int n, int64_t B, const T* w, T* wc, hipStream_t st) {
+hipError_t launch_coarsen(int n, int64_t B, const T* w, T* wc, int reaction, hipStream_t st) {
   const int nc = n / 2;
-  const int E = 2 * (nc + 2) * nc;
-  hipLaunchKernelGGL(k_coarsen<T>, dim3((unsigned)((E + 255) / 256 * B)), dim3(256), 0, st,
-                     (E + 255) / 256, n, B, w,
-                     wc);
+  const int E = (reaction ? 5 : 2) * (nc + 2) * nc;
+  const dim3 grid((unsigned)((E + 255) / 256 * B));
+  if (reaction)
+    hipLaunchKernelGGL((k_coarsen<T, true>), grid, dim3(256), 0, st, (E + 255) / 256, n, B, w, wc);
+  else
+    hipLaunchKernelGGL((k_coarsen<T, false>), grid, dim3(256), 0, st, (E + 255) / 256, n, B, w,
+                       wc);
   return hipGetLastError();
 }
+
+// compile-time reaction flag from the runtime one
+#define KR_DISPATCH(r, BODY)      \
+  do {                            \
+    if (r) {                      \
+      constexpr bool kR = true;   \
+      BODY;                       \
+    } else {                      \
+      constexpr bool kR = false;  \
+      BODY;                       \
+    }                             \
+  } while (0)
 
 // marching launches: NTC = 64 (n = 64), 128 (n = 128) or 256 (n >= 256)
 #define MARCH_DISPATCH(n, BODY)                \
@@ -1206,43 +1293,69 @@ Coarse coarse_of(const double* uH, int nH, int n) {
 }  // namespace
 
 hipError_t launch_setup_dots(int n, int64_t B, const double* uH, int nH, const double* w,
-                             double* part, hipStream_t st) {
+                             double* part, int reaction, hipStream_t st) {
   if (nH < 2 || n % nH) return hipErrorInvalidValue;
   const Coarse cv = coarse_of(uH, nH, n);
-  MARCH_DISPATCH(n, {
+  MARCH_DISPATCH(n, KR_DISPATCH(reaction, {
     const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_setup_dots<NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, w, part);
-  });
+    hipLaunchKernelGGL((k_setup_dots<NTC, kR>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, w, part);
+  }));
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const double* w64,
-                            const FineState& S, T* r, T* vn, T* mvn, hipStream_t st) {
+                            const FineState& S, T* r, T* vn, T* mvn, int reaction,
+                            hipStream_t st) {
   if (nH < 2 || n % nH) return hipErrorInvalidValue;
   const Coarse cv = coarse_of(uH, nH, n);
-  MARCH_DISPATCH(n, {
+  MARCH_DISPATCH(n, KR_DISPATCH(reaction, {
     const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_setup_rhs<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, w64, S, r,
-                       vn, mvn);
-  });
+    hipLaunchKernelGGL((k_setup_rhs<T, NTC, kR>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, w64, S,
+                       r, vn, mvn);
+  }));
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
                                 const T* w, T* t, const FineState& S, int first, T* pout, T* q,
-                                double* part, hipStream_t st) {
-  MARCH_DISPATCH(n, {
+                                double* part, int reaction, hipStream_t st) {
+  MARCH_DISPATCH(n, KR_DISPATCH(reaction, {
     const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_pupdate_apply<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, z, vn, pin,
-                       w, t, S, first, pout, q, part);
-  });
+    hipLaunchKernelGGL((k_pupdate_apply<T, NTC, kR>), mgrid<NTC>(g), dim3(NTC), 0, st, g, z, vn,
+                       pin, w, t, S, first, pout, q, part);
+  }));
   return hipGetLastError();
 }
 
-// fused V-cycle launches: (NTC, CPT) = (64,1), (128,1), (256,1), (256,2), (256,4)
-#define ROW_DISPATCH(n, BODY)                               \
+// fused V-cycle launches, (threads, columns per thread) per mesh.  Pre-
+// smoothing: one thread per column, (n, 1): its LDS rings of full rows
+// (three stages plus the direction's ring with the update) allow one
+// workgroup per compute unit on 1/1024, and 16 waves keep more loads in
+// flight than 4 (1/1024: 2.99 against 4.18 ms per launch).  Post-smoothing
+// holds fewer rings (two workgroups per unit) and keeps four columns per
+// thread there (4.19 against 4.39 ms with one).
+#define ROW_DISPATCH_PRE(n, BODY)                           \
+  do {                                                      \
+    if ((n) <= 64) {                                        \
+      constexpr int NTC = 64, CPT = 1;                      \
+      BODY;                                                 \
+    } else if ((n) == 128) {                                \
+      constexpr int NTC = 128, CPT = 1;                     \
+      BODY;                                                 \
+    } else if ((n) == 256) {                                \
+      constexpr int NTC = 256, CPT = 1;                     \
+      BODY;                                                 \
+    } else if ((n) == 512) {                                \
+      constexpr int NTC = 512, CPT = 1;                     \
+      BODY;                                                 \
+    } else {                                                \
+      constexpr int NTC = 1024, CPT = 1;                    \
+      BODY;                                                 \
+    }                                                       \
+  } while (0)
+#define ROW_DISPATCH_POST(n, BODY)                          \
   do {                                                      \
     if ((n) <= 64) {                                        \
       constexpr int NTC = 64, CPT = 1;                      \
@@ -1292,37 +1405,37 @@ inline dim3 sgrid(const VGeo& g) {
 template <typename T>
 hipError_t launch_pre(int n, int64_t B, const T* w, const T* rhs, T* X, T* rhs_c,
                       const uint8_t* active, const T* p, const T* mvn, const FineState* S,
-                      T* rout, hipStream_t st) {
+                      T* rout, int reaction, hipStream_t st) {
   const VGeo g = vgeo_pre(n, B);
   const bool upd = p != nullptr;
   if (upd && (!mvn || !S || !rout || rout == rhs)) return hipErrorInvalidValue;
   const FineState s0 = S ? *S : FineState{};
-  ROW_DISPATCH(n, {
+  ROW_DISPATCH_PRE(n, KR_DISPATCH(reaction, {
     if (NTC * CPT != n) return hipErrorInvalidValue;  // a block covers one full row
     if (upd)
-      hipLaunchKernelGGL((k_pre<T, NTC, CPT, true, kFineSweeps>), sgrid(g), dim3(NTC), 0, st, g,
-                         w, rhs, X, rhs_c, active, p, mvn, s0, rout);
+      hipLaunchKernelGGL((k_pre<T, NTC, CPT, true, kFineSweeps, kR>), sgrid(g), dim3(NTC), 0, st,
+                         g, w, rhs, X, rhs_c, active, p, mvn, s0, rout);
     else
-      hipLaunchKernelGGL((k_pre<T, NTC, CPT, false, kFineSweeps>), sgrid(g), dim3(NTC), 0, st, g,
-                         w, rhs, X, rhs_c, active, p, mvn, s0, rout);
-  });
+      hipLaunchKernelGGL((k_pre<T, NTC, CPT, false, kFineSweeps, kR>), sgrid(g), dim3(NTC), 0, st,
+                         g, w, rhs, X, rhs_c, active, p, mvn, s0, rout);
+  }));
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_post(int n, int64_t B, const T* w, const T* rhs, const T* Xin, const T* Xc,
                        T* Xout, const T* vn, const T* mvn, const uint8_t* active, double* part,
-                       hipStream_t st) {
+                       int reaction, hipStream_t st) {
   const VGeo g = vgeo_post(n, B);
-  ROW_DISPATCH(n, {
+  ROW_DISPATCH_POST(n, KR_DISPATCH(reaction, {
     if (NTC * CPT != n) return hipErrorInvalidValue;  // a block covers one full row
     if (part)
-      hipLaunchKernelGGL((k_post<T, NTC, CPT, true, kFineSweeps>), sgrid(g), dim3(NTC), 0, st, g,
-                         w, rhs, Xin, Xc, Xout, vn, mvn, active, part);
+      hipLaunchKernelGGL((k_post<T, NTC, CPT, true, kFineSweeps, kR>), sgrid(g), dim3(NTC), 0, st,
+                         g, w, rhs, Xin, Xc, Xout, vn, mvn, active, part);
     else
-      hipLaunchKernelGGL((k_post<T, NTC, CPT, false, kFineSweeps>), sgrid(g), dim3(NTC), 0, st, g,
-                         w, rhs, Xin, Xc, Xout, vn, mvn, active, part);
-  });
+      hipLaunchKernelGGL((k_post<T, NTC, CPT, false, kFineSweeps, kR>), sgrid(g), dim3(NTC), 0,
+                         st, g, w, rhs, Xin, Xc, Xout, vn, mvn, active, part);
+  }));
   return hipGetLastError();
 }
 
@@ -1339,14 +1452,14 @@ int march_blocks(int n, int64_t B) {
 template <typename T>
 hipError_t launch_final_dots(int n, int64_t B, const double* uH, int nH, const T* t, const T* p0,
                              const T* p1, const double* w, const FineState& S, double* part,
-                             hipStream_t st) {
+                             int reaction, hipStream_t st) {
   if (nH < 2 || n % nH) return hipErrorInvalidValue;
   const Coarse cv = coarse_of(uH, nH, n);
-  MARCH_DISPATCH(n, {
+  MARCH_DISPATCH(n, KR_DISPATCH(reaction, {
     const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_final_dots<T, NTC>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, t, p0,
+    hipLaunchKernelGGL((k_final_dots<T, NTC, kR>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, t, p0,
                        p1, w, S, part);
-  });
+  }));
   return hipGetLastError();
 }
 
@@ -1369,23 +1482,24 @@ hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* s
 }
 
 #define INST(T)                                                                                 \
-  template hipError_t launch_coarsen<T>(int, int64_t, const T*, T*, hipStream_t);                \
+  template hipError_t launch_coarsen<T>(int, int64_t, const T*, T*, int, hipStream_t);           \
   template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, int, const double*,      \
-                                          const FineState&, T*, T*, T*, hipStream_t);           \
+                                          const FineState&, T*, T*, T*, int, hipStream_t);      \
   template hipError_t launch_pupdate_apply<T>(int, int64_t, const T*, const T*, const T*,       \
                                               const T*, T*, const FineState&, int, T*, T*,      \
-                                              double*, hipStream_t);                            \
+                                              double*, int, hipStream_t);                       \
   template hipError_t launch_final_dots<T>(int, int64_t, const double*, int, const T*,          \
                                            const T*, const T*, const double*, const FineState&, \
-                                           double*, hipStream_t);
+                                           double*, int, hipStream_t);
 INST(double)
 INST(float)
 #undef INST
 #define INST(T)                                                                                 \
   template hipError_t launch_pre<T>(int, int64_t, const T*, const T*, T*, T*, const uint8_t*,   \
-                                    const T*, const T*, const FineState*, T*, hipStream_t);     \
+                                    const T*, const T*, const FineState*, T*, int, hipStream_t); \
   template hipError_t launch_post<T>(int, int64_t, const T*, const T*, const T*, const T*, T*,  \
-                                     const T*, const T*, const uint8_t*, double*, hipStream_t);
+                                     const T*, const T*, const uint8_t*, double*, int,          \
+                                     hipStream_t);
 INST(double)
 INST(float)
 #undef INST

@@ -349,78 +349,33 @@ __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void
   tg_sample<N, NT, kR>(A, a, s_y, s_w64, (int64_t)blockIdx.x);
 }
 
-// Problem 2 on 1/64 and 1/128: the top-level arrays in the workgroup's slice
-// of a global scratch buffer (weights and reaction, five vectors, the
-// smoother's second array), the V-cycle levels below in LDS on 1/64; on
-// 1/128 they follow in the slice too (the 1/64 level alone would take 233 KB
-// of LDS).  With FP32 storage the slice starts with the FP64 weight block of
-// the Rayleigh quotients.  Launched with 512 threads: latency-bound, the FP64
-// kernel on 1/64 runs faster with two waves per SIMD and 30 spilled registers
-// than with one wave and none (and no faster with four).
-template <int N>
-constexpr bool mg_in_scratch() {
-  return N > 64;
-}
-template <int N, typename T>
-constexpr int64_t tg_global_doubles() {
-  constexpr int64_t P = lds::Mesh<N>::P;
-  constexpr int64_t elems = 11 * P + (mg_in_scratch<N>() ? lds::mg_scratch<N, true>() : 0);
-  return sizeof(T) == 8 ? elems : 5 * P + (elems * (int64_t)sizeof(T) + 7) / 8;
-}
-template <int N, int NT, typename T>
-__global__ __launch_bounds__(NT) void k_tg_global(TgSmallArgs A) {
-  using Mh = lds::Mesh<N>;
-  constexpr int P = Mh::P;
-  __shared__ T s_mg[mg_in_scratch<N>() ? 1 : lds::mg_scratch<N, true>() + 1];
-  __shared__ double s_red[6 * (NT / 64)];
-  __shared__ double s_y[kMaxStagedS];
-  double* base = A.scratch + (int64_t)blockIdx.x * tg_global_doubles<N, T>();
-  double* w64 = sizeof(T) < 8 ? base : nullptr;
-  T* g = sizeof(T) < 8 ? reinterpret_cast<T*>(base + 5 * P) : reinterpret_cast<T*>(base);
-  T* vec = g + lds::wblock<true>() * P;
-  lds::PcgArrays<T> a;
-  a.wx = g;
-  a.wy = g + P;
-  a.v = vec;
-  a.t = vec + P;
-  a.r = vec + 2 * P;
-  a.z = vec + 3 * P;
-  a.p = vec + 4 * P;
-  a.q = a.z;
-  a.xtmp = vec + 5 * P;
-  a.mg = mg_in_scratch<N>() ? vec + 6 * P : s_mg;
-  a.red = s_red;
-  lds::zero<NT>(vec, 6 * P);
-  tg_sample<N, NT, true>(A, a, s_y, w64, (int64_t)blockIdx.x);
-}
-
 // The V-cycle below the batched levels: one workgroup per sample reads its
 // padded arrays of the batched layout ((N + 2) N per vector, same indexing)
 // into LDS, runs the cycle (three Chebyshev sweeps per smoothing step),
 // writes the interior of X back.
-template <int N, int NT, typename T>
+template <int N, int NT, typename T, bool kR = false>
 __global__ __launch_bounds__(NT) void k_bottom(const T* __restrict__ w, const T* __restrict__ rhs,
                                                T* __restrict__ X,
                                                const uint8_t* __restrict__ active) {
   using Mh = lds::Mesh<N>;
-  constexpr int P = Mh::P, PG = (N + 2) * N;
+  constexpr int P = Mh::P, PG = (N + 2) * N, WB = lds::wblock<kR>();
   const int64_t b = blockIdx.x;
   if (active && !active[b]) return;
-  __shared__ T s_w[Mh::EW];
+  __shared__ T s_w[WB * P];
   __shared__ T s_b[P], s_x[P];
-  __shared__ T s_mg[lds::mg_scratch<N>() + 1];
-  const T* WX = w + b * 2 * PG;
-  const T* WY = WX + PG;
+  __shared__ T s_mg[lds::mg_scratch<N, kR>() + 1];
+  // the global block holds WB arrays of PG entries; LDS keeps the first P of each
+  const T* wb = w + b * WB * PG;
   const T* rb = rhs + b * PG;
   for (int e = threadIdx.x; e < P; e += NT) {
-    s_w[e] = WX[e];
-    s_w[P + e] = WY[e];
+#pragma unroll
+    for (int a = 0; a < WB; ++a) s_w[a * P + e] = wb[a * PG + e];
     s_b[e] = rb[e];
     s_x[e] = T(0);
   }
   __syncthreads();
-  lds::coarsen_all<NT, N>(s_w, s_w + P, s_mg);
-  lds::vcycle<NT, N, true, T, 3>(s_w, s_w + P, s_b, s_x, s_mg);
+  lds::coarsen_all<NT, N, T, kR>(s_w, s_w + P, s_mg);
+  lds::vcycle<NT, N, true, T, 3, kR>(s_w, s_w + P, s_b, s_x, s_mg);
   LDS_FOR_NODES(NT, N, k) X[b * PG + k] = s_x[k];
 }
 
@@ -473,10 +428,15 @@ hipError_t tg_small_n(const TgSmallArgs& a, hipStream_t st) {
 
 template <int N, typename T>
 hipError_t bottom_n(int64_t B, const T* w, const T* rhs, T* X, const uint8_t* active,
-                    hipStream_t st) {
+                    int reaction, hipStream_t st) {
   constexpr int NT = threads_for<N>();
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_bottom<N, NT, T>), dim3((unsigned)B), dim3(NT), 0, st, w, rhs, X, active);
+  if (reaction)
+    hipLaunchKernelGGL((k_bottom<N, NT, T, true>), dim3((unsigned)B), dim3(NT), 0, st, w, rhs, X,
+                       active);
+  else
+    hipLaunchKernelGGL((k_bottom<N, NT, T, false>), dim3((unsigned)B), dim3(NT), 0, st, w, rhs, X,
+                       active);
   return hipGetLastError();
 }
 
@@ -495,30 +455,6 @@ hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st) {
 }
 
 int64_t rqi_scratch_doubles(int N) { return N == 64 ? global_doubles<64>() : 0; }
-
-int64_t tg_scratch_doubles(int N, int mixed) {
-  if (N == 64) return mixed ? tg_global_doubles<64, float>() : tg_global_doubles<64, double>();
-  if (N == 128)
-    return mixed ? tg_global_doubles<128, float>() : tg_global_doubles<128, double>();
-  return 0;
-}
-
-namespace {
-template <int N>
-hipError_t tg_global_n(const TgSmallArgs& a, hipStream_t st) {
-  // Problem 2: one workgroup per sample, a.n x tg_scratch_doubles(N, mixed)
-  // doubles of scratch
-  if (!a.rphi) return hipErrorInvalidValue;
-  if (a.n <= 0) return hipSuccess;
-  const int64_t per = a.mixed ? tg_global_doubles<N, float>() : tg_global_doubles<N, double>();
-  if (!a.scratch || a.scratch_doubles < a.n * per) return hipErrorInvalidValue;
-  if (a.mixed)
-    hipLaunchKernelGGL((k_tg_global<N, 512, float>), dim3((unsigned)a.n), dim3(512), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_tg_global<N, 512, double>), dim3((unsigned)a.n), dim3(512), 0, st, a);
-  return hipGetLastError();
-}
-}  // namespace
 
 template <int N>
 hipError_t rqi_occupancy(int* per, int mixed, int reaction) {
@@ -563,26 +499,24 @@ hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st) {
     case 8: return tg_small_n<8>(a, st);
     case 16: return tg_small_n<16>(a, st);
     case 32: return tg_small_n<32>(a, st);
-    case 64: return tg_global_n<64>(a, st);
-    case 128: return tg_global_n<128>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
 hipError_t launch_bottom_vcycle(int NB, int64_t B, const T* w, const T* rhs, T* X,
-                                const uint8_t* active, hipStream_t st) {
+                                const uint8_t* active, int reaction, hipStream_t st) {
   switch (NB) {
-    case 4: return bottom_n<4, T>(B, w, rhs, X, active, st);
-    case 8: return bottom_n<8, T>(B, w, rhs, X, active, st);
-    case 16: return bottom_n<16, T>(B, w, rhs, X, active, st);
-    case 32: return bottom_n<32, T>(B, w, rhs, X, active, st);
+    case 4: return bottom_n<4, T>(B, w, rhs, X, active, reaction, st);
+    case 8: return bottom_n<8, T>(B, w, rhs, X, active, reaction, st);
+    case 16: return bottom_n<16, T>(B, w, rhs, X, active, reaction, st);
+    case 32: return bottom_n<32, T>(B, w, rhs, X, active, reaction, st);
     default: return hipErrorInvalidValue;
   }
 }
 template hipError_t launch_bottom_vcycle<double>(int, int64_t, const double*, const double*,
-                                                 double*, const uint8_t*, hipStream_t);
+                                                 double*, const uint8_t*, int, hipStream_t);
 template hipError_t launch_bottom_vcycle<float>(int, int64_t, const float*, const float*, float*,
-                                                const uint8_t*, hipStream_t);
+                                                const uint8_t*, int, hipStream_t);
 
 }  // namespace mlqmc

@@ -188,7 +188,8 @@ __global__ __launch_bounds__(256, 2) void k_expand_mfma(int64_t B, int s, int64_
                                                      const double* __restrict__ phi, double a0,
                                                      double* __restrict__ out,
                                                      float* __restrict__ out32, int nbm,
-                                                     int64_t per_xcd, int64_t ntiles) {
+                                                     int64_t per_xcd, int64_t ntiles,
+                                                     int64_t ldo) {
   __shared__ double sY[2][kXK][kXM + kXPad];
   __shared__ double sP[2][kXK][kXN + kXPad];
   const int64_t L = blockIdx.x;
@@ -274,8 +275,8 @@ __global__ __launch_bounds__(256, 2) void k_expand_mfma(int64_t B, int s, int64_
         const int64_t b = m0 + wm * 64 + i * 16 + 4 * r + fk;
         if (b < B) {
           const double v = a0 + acc[i][j][r];
-          out[b * E + e] = v;
-          if (out32) out32[b * E + e] = (float)v;
+          out[b * ldo + e] = v;
+          if (out32) out32[b * ldo + e] = (float)v;
         }
       }
     }
@@ -459,15 +460,36 @@ hipError_t launch_phi_reaction_padded(int n, int rows, const double* phi_el, dou
 
 hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t ldY,
                          const double* phi, double a0, double* out, float* out32,
-                         hipStream_t st) {
+                         hipStream_t st, int64_t ldo) {
   if (B <= 0 || E <= 0) return hipSuccess;
   if (E & 1) return hipErrorInvalidValue;  // rows of phi are read in aligned pairs
+  if (ldo == 0) ldo = E;
+  if (ldo < E) return hipErrorInvalidValue;
   const int nbm = (int)((B + kXM - 1) / kXM);
   const int64_t nbn = (E + kXN - 1) / kXN;
   const int64_t ntiles = (int64_t)nbm * nbn;
   const int64_t per_xcd = (ntiles + 7) / 8;
   hipLaunchKernelGGL(k_expand_mfma, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, st, B, s, E, Y,
-                     ldY, phi, a0, out, out32, nbm, per_xcd, ntiles);
+                     ldY, phi, a0, out, out32, nbm, per_xcd, ntiles, ldo);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_prepend_one(int64_t B, int s, const double* __restrict__ Y,
+                                                     int64_t ldY, double* __restrict__ Y1) {
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t w = s + 1;
+  if (id >= B * w) return;
+  const int64_t b = id / w;
+  const int j = (int)(id - b * w);
+  Y1[id] = j == 0 ? 1.0 : Y[b * ldY + j - 1];
+}
+
+hipError_t launch_prepend_one(int64_t B, int s, const double* Y, int64_t ldY, double* Y1,
+                              hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  const int64_t tot = B * (s + 1);
+  hipLaunchKernelGGL(k_prepend_one, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, B, s,
+                     Y, ldY, Y1);
   return hipGetLastError();
 }
 

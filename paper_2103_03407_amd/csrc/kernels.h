@@ -43,9 +43,6 @@ struct RqiArgs {
 hipError_t launch_rqi(int N, const RqiArgs& a, hipStream_t st);
 // doubles of global scratch one chain needs on mesh N (0: all in LDS)
 int64_t rqi_scratch_doubles(int N);
-// doubles of global scratch one sample of the two-grid update needs on mesh N
-// (Problem 2 on 1/64; 0: all in LDS)
-int64_t tg_scratch_doubles(int N, int mixed);
 // workgroups of the eigensolve on mesh N resident on the current device at once
 int rqi_chains_in_flight(int N, int mixed, int reaction);
 
@@ -68,19 +65,17 @@ struct TgSmallArgs {
   double* g;            // [n] G of the two-grid eigenvector (integral, normalised), or nullptr
   int* lin_iters;       // [n] added to, or nullptr
   uint8_t* flags;       // [n] OR-ed
-  double* scratch;      // mesh 1/64 (Problem 2): n x tg_scratch_doubles(64, mixed) doubles
-  int64_t scratch_doubles;
 };
-// Two-grid update in LDS (N <= 32), or on 1/64 for Problem 2 in FP64 with the
-// top level in global scratch
+// Two-grid update with every array in LDS, one workgroup per sample (N <= 32)
 hipError_t launch_tg_small(int N, const TgSmallArgs& a, hipStream_t st);
 
 // One V-cycle X = K^{-1} B per active sample on mesh NB <= 32 from padded global
-// arrays (weights [WX | WY], rhs, X; see k_fine.hip), computed in LDS in the
-// storage type T, three Chebyshev-weighted Jacobi sweeps per smoothing step.
+// arrays (weights [WX | WY], or [WX | WY | RX | RY | RD] with the reaction;
+// rhs, X; see k_fine.hip), computed in LDS in the storage type T, three
+// Chebyshev-weighted Jacobi sweeps per smoothing step.
 template <typename T>
 hipError_t launch_bottom_vcycle(int NB, int64_t B, const T* w, const T* rhs, T* X,
-                                const uint8_t* active, hipStream_t st);
+                                const uint8_t* active, int reaction, hipStream_t st);
 
 // ---------------- batched fine-mesh kernels (XCD-aware 1-D grid over samples x blocks) ----------------
 
@@ -107,22 +102,25 @@ hipError_t launch_zero_boundary(int n, int64_t B, void* const* ptrs, int cnt, in
 // interior layout -> interior layout (component entry point)
 hipError_t launch_prolong_interior(int nH, int nh, int64_t B, const double* uH, double* uh,
                                    hipStream_t st);
+// `reaction` (Problem 2): weight blocks [WX | WY | RX | RY | RD] and the
+// operator A + R in every kernel below that takes the flag
 template <typename T>
-hipError_t launch_coarsen(int n, int64_t B, const T* w, T* wc, hipStream_t st);
+hipError_t launch_coarsen(int n, int64_t B, const T* w, T* wc, int reaction, hipStream_t st);
 // The set-up and final kernels take the coarse eigenvectors uH [B x (nH-1)^2]
 // and evaluate v = P u_H (P1 interpolation to mesh n) where they need it.
 hipError_t launch_setup_dots(int n, int64_t B, const double* uH, int nH, const double* w,
-                             double* part, hipStream_t st);
+                             double* part, int reaction, hipStream_t st);
 template <typename T>
 hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const double* w64,
-                            const FineState& S, T* r, T* vn, T* mvn, hipStream_t st);
+                            const FineState& S, T* r, T* vn, T* mvn, int reaction,
+                            hipStream_t st);
 // the new direction pout = z - c2 vn + beta pin and q = (A - mu M) pout (stored
 // only if q != nullptr), with the dot-product partials of the step (M vn is
 // formed from vn in the kernel)
 template <typename T>
 hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
                                 const T* w, T* t, const FineState& S, int first, T* pout, T* q,
-                                double* part, hipStream_t st);
+                                double* part, int reaction, hipStream_t st);
 // fused V-cycle level, pre-smoothing from zero and restriction:
 //   X = Chebyshev-weighted Jacobi sweeps on A X = rhs from X = 0;
 //   rhs_c = P^T (rhs - A X); with p != nullptr (the current direction) the rhs
@@ -131,7 +129,7 @@ hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const
 template <typename T>
 hipError_t launch_pre(int n, int64_t B, const T* w, const T* rhs, T* X, T* rhs_c,
                       const uint8_t* active, const T* p, const T* mvn, const FineState* S,
-                      T* rout, hipStream_t st);
+                      T* rout, int reaction, hipStream_t st);
 // fused V-cycle level, coarse correction and post-smoothing:
 //   Xout = Chebyshev-weighted sweeps from Xin + P Xc; with part != nullptr also
 //   the partials rhs.Xout, mvn.Xout, rhs.vn per strip (level 0 of the projected
@@ -139,7 +137,7 @@ hipError_t launch_pre(int n, int64_t B, const T* w, const T* rhs, T* X, T* rhs_c
 template <typename T>
 hipError_t launch_post(int n, int64_t B, const T* w, const T* rhs, const T* Xin, const T* Xc,
                        T* Xout, const T* vn, const T* mvn, const uint8_t* active, double* part,
-                       hipStream_t st);
+                       int reaction, hipStream_t st);
 // strips per sample of launch_post for a batch of B (its partial-sum count per sample)
 int post_strips(int n, int64_t B);
 // workgroups in flight the batched stencil kernels aim for (<= 0: default);
@@ -150,7 +148,7 @@ int march_blocks(int n, int64_t B);
 template <typename T>
 hipError_t launch_final_dots(int n, int64_t B, const double* uH, int nH, const T* t, const T* p0,
                              const T* p1, const double* w, const FineState& S, double* part,
-                             hipStream_t st);
+                             int reaction, hipStream_t st);
 
 // scalar phases: one wavefront per sample sums that sample's block partials
 enum ScalarPhase { PH_SETUP = 0, PH_FIRST_RZ = 1, PH_ALPHA = 2, PH_BETA = 3, PH_FINAL = 4 };
@@ -194,10 +192,15 @@ hipError_t launch_phi_elements_islands(int n, int rows, const double* c, const i
 // edge arriving at node k from the south-west)
 hipError_t launch_phi_reaction_padded(int n, int rows, const double* phi_el, double* phi_r,
                                       hipStream_t st);
-// out[b][e] = a0 + sum_{j<s} Y[b][j] phi[j][e], e < E
+// out[b * ldo + e] = a0 + sum_{j<s} Y[b][j] phi[j][e], e < E (ldo = 0: E);
+// out32 (optional) the same rounded to FP32
 hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t ldY,
                          const double* phi, double a0, double* out, float* out32,
-                         hipStream_t st);
+                         hipStream_t st, int64_t ldo = 0);
+// Y1[b] = (1, Y[b][0 .. s)): the points with the leading 1 that selects the
+// background row of a Problem 2 table
+hipError_t launch_prepend_one(int64_t B, int s, const double* Y, int64_t ldY, double* Y1,
+                              hipStream_t st);
 // Q[l*R + r] = (1/N) sum_k (lam[r*N + k] - lam_prev[r*N + k]) (fixed-order tree);
 // lam_prev may be nullptr (lambda^{-1} = 0)
 hipError_t launch_level_sums(int64_t N, int R, const double* lam, const double* lam_prev,

@@ -29,7 +29,7 @@ _STORE = os.path.join(_HERE, "lattice")
 # (N, s) pairs the workloads need; gamma_j = j^-2 throughout.
 NEEDED = [(256, 16), (1024, 64), (16384, 16), (8192, 32), (2048, 64),
           (1024, 128), (256, 256), (1024, 512), (64, 8), (128, 16), (512, 32),
-          (16384, 256), (4096, 32), (512, 256)]
+          (16384, 256), (4096, 32), (512, 256), (256, 512)]
 
 
 def _b2(x: np.ndarray) -> np.ndarray:

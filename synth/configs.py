@@ -153,6 +153,13 @@ def _islands_levels5():
     return tuple(lv)
 
 
+def _islands_levels6():
+    """_islands_levels5 plus level 5 on h = 1/256 (s = 512, N = 2^8)."""
+    lv = list(_islands_levels5())
+    lv.append(LevelSpec(256, 512, 8, coarse_trunc(512, 16), 128, 256, 1 << 8))
+    return tuple(lv)
+
+
 def _nested_levels(base):
     """The levels of ``base`` with H_l = h_0 and S_l = s_0 for l >= 1."""
     l0 = base[0]
@@ -194,6 +201,9 @@ CONFIGS = {
     11: Workload("cfg11-problem1-mlqmc-3level", 11, "fp64", 2.0, _islands_levels(), 8,
                  "Problem 1 of the numerical section (decay 2) on workload 8's meshes, "
                  "truncations and N_l", p1_decay=2.0),
+    12: Workload("cfg12-islands-mlqmc-6level", 12, "fp64", 0.0, _islands_levels6(), 8,
+                 "Problem 2 (islands), six-level two-grid MLQMC, h=1/8..1/256, s=16..512, "
+                 "H=1/8, S=16", problem=2, decays=P2_DECAYS),
 }
 
 

@@ -3,8 +3,9 @@ region-wise diffusion a and reaction b), against the FP64 CPU oracle,
 through the C ABI (mlqmc_create_islands).
 
 The family runs on meshes 1/8 .. 1/32, every array of a solve in LDS, and as
-the fine or previous mesh of a two-grid level on 1/64 and 1/128 (top levels in
-global scratch), in FP64 or mixed precision.  Tolerances as for Problem 1: eigenvalues relative 1e-10
+the fine or previous mesh of a two-grid level on 1/64 .. 1/1024 (the batched
+stencil kernels with the reaction term; 1/64, 1/128 and 1/256 here), in FP64
+or mixed precision.  Tolerances as for Problem 1: eigenvalues relative 1e-10
 per sample (mixed 1e-8), G(u) relative 1e-9 (mixed 1e-7), estimator sums from
 the per-sample bound.  Both parameter
 sets of the paper's complexity figure are covered: decays (4/3, 2, 4/3, 2)
@@ -160,15 +161,15 @@ def test_nested_estimate(ctx, fam):
     assert abs(est[0] - ref.Q_ml) <= 4 * LAM_RTOL * scale
 
 
-@pytest.mark.parametrize("lv,prec", [((256, 32, 16, 16, 0, 0), m.MLQMC_FP64),
+@pytest.mark.parametrize("lv,prec", [((2048, 32, 16, 16, 0, 0), m.MLQMC_FP64),
                                      ((4, 4, 0, 0, 0, 0), m.MLQMC_FP64),
-                                     ((32, 16, 8, 8, 256, 16), m.MLQMC_FP64),
+                                     ((128, 16, 64, 8, 0, 0), m.MLQMC_FP64),
                                      ((64, 8, 0, 0, 0, 0), m.MLQMC_FP64),
                                      ((64, 8, 0, 0, 0, 0), m.MLQMC_MIXED),
                                      ((16, 8, 0, 0, 64, 8), m.MLQMC_MIXED)])
 def test_rejected_levels(ctx, lv, prec):
-    # meshes outside 1/8 .. 1/128 and direct levels above 1/32 are refused
-    # on the host
+    # meshes outside 1/8 .. 1/1024, coarse meshes and direct levels above 1/32
+    # are refused on the host
     Y = _points(max(lv[1], 1), 2, 37)
     lam = np.empty(2)
     fl = np.zeros(2, np.uint8)
@@ -323,7 +324,7 @@ def test_mixed_cfg8_sampled(ctx_p2):
             assert abs(Yl[i] - v.Y) <= 2e-8 * v.lam, (l, i)
 
 
-# ---------------- two-grid updates on 1/64 (top level in global scratch) ----------------
+# ---------------- two-grid updates on 1/64 (batched kernels with the reaction) ----------------
 
 @pytest.mark.parametrize("lv", [(64, 32, 8, 8, 0, 0), (64, 64, 16, 16, 32, 32),
                                 (64, 64, 8, 16, 8, 16)])
@@ -359,9 +360,9 @@ def test_functional_64(ctx, fam):
         assert abs(gp[k] - v.G_prev) <= G_RTOL * v.G_prev
 
 
-def test_64_across_scratch_chunks(ctx, fam):
-    # more samples than one scratch chunk (4096): samples on both sides of
-    # the chunk boundary and the last one against the oracle
+def test_64_many_samples(ctx, fam):
+    # a batch of 4100 samples (the first, the last and two in between against
+    # the oracle)
     lv = (64, 16, 8, 8, 0, 0)
     n = 4100
     z = lattice_vector(16384, 16)
@@ -409,7 +410,7 @@ def test_mixed_two_grid_level_64(ctx, fam, lv):
             assert abs(lamp[k] - v.lam_prev) <= 1e-8 * v.lam_prev
 
 
-# ---------------- two-grid updates on 1/128 (V-cycle in global scratch too) ----------------
+# ---------------- two-grid updates on 1/128 and 1/256 ----------------
 
 @pytest.mark.parametrize("prec,tol", [("fp64", LAM_RTOL), ("mixed", 1e-8)])
 @pytest.mark.parametrize("lv", [(128, 64, 8, 8, 0, 0), (128, 64, 16, 16, 64, 32)])
@@ -429,8 +430,8 @@ def test_two_grid_level_128(ctx, fam, lv, prec, tol):
             assert abs(lamp[k] - v.lam_prev) <= tol * v.lam_prev
 
 
-def test_128_across_scratch_chunks(ctx, fam):
-    # 1/128 runs 512 samples per scratch chunk: both sides of the boundary
+def test_128_two_batches(ctx, fam):
+    # batches of 512 samples: both sides of the batch boundary
     lv = (128, 16, 8, 8, 0, 0)
     n = 520
     z = lattice_vector(16384, 16)
@@ -438,12 +439,46 @@ def test_128_across_scratch_chunks(ctx, fam):
     Y = np.ascontiguousarray(qmc.lattice_points(z, 16384, sh, range(n)))
     lam = np.empty(n)
     fl = np.zeros(n, np.uint8)
-    ctx.eig_level(lv, Y, lam, fl)
+    ctx.eig_level(lv, Y, lam, fl, opts=m.default_opts(batch=512))
     assert not fl.any()
     for k in (511, 512, n - 1):
         ref = twogrid.two_grid(128, 16, 8, 8, Y[k], fam)[0]
         assert abs(lam[k] - ref) <= LAM_RTOL * ref, (k, lam[k], ref)
 
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", LAM_RTOL), ("mixed", 1e-8)])
+@pytest.mark.parametrize("lv", [(256, 64, 8, 8, 0, 0), (256, 64, 16, 16, 128, 32)])
+def test_two_grid_level_256(ctx, fam, lv, prec, tol):
+    spec = LevelSpec(*lv, 0)
+    count = 3
+    Y = _points(lv[1], count, 82)
+    lam, lamp = np.empty(count), np.empty(count)
+    fl = np.zeros(count, np.uint8)
+    o = m.default_opts(prec=m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED)
+    ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp if lv[4] else None, opts=o)
+    assert not fl.any(), fl
+    for k in range(count):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= tol * v.lam, (k, lam[k], v.lam)
+        if lv[4]:
+            assert abs(lamp[k] - v.lam_prev) <= tol * v.lam_prev
+
+
+def test_functional_256(ctx, fam):
+    lv = (256, 32, 8, 8, 64, 16)
+    spec = LevelSpec(*lv, 0)
+    count = 2
+    Y = _points(lv[1], count, 83)
+    lam, lamp, g, gp = (np.empty(count) for _ in range(4))
+    fl = np.zeros(count, np.uint8)
+    ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp, g=g, g_prev=gp)
+    assert not fl.any(), fl
+    for k in range(count):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(lam[k] - v.lam) <= LAM_RTOL * v.lam
+        assert abs(g[k] - v.G) <= G_RTOL * v.G, (k, g[k], v.G)
+        assert abs(gp[k] - v.G_prev) <= G_RTOL * v.G_prev
 
 
 def test_no_random_terms_on_64(ctx, fam):
@@ -459,8 +494,8 @@ def test_no_random_terms_on_64(ctx, fam):
 
 
 def test_nested_and_extended_with_a_64_level(ctx, fam):
-    # shared shifts with level 3 on 1/64 (the global-scratch update), grown
-    # in two steps, against the oracle's nested estimate
+    # shared shifts with level 3 on 1/64 (a batched update), grown in two
+    # steps, against the oracle's nested estimate
     N = [8, 4, 4, 2]
     levels = [LevelSpec(8, 4, 0, 0, 0, 0, N[0]), LevelSpec(16, 6, 8, 4, 8, 4, N[1]),
               LevelSpec(32, 8, 8, 4, 16, 6, N[2]), LevelSpec(64, 8, 8, 4, 32, 8, N[3])]
@@ -504,5 +539,37 @@ def test_cfg10_five_levels_sampled(ctx_p2):
                 assert abs(Yl[i] - v.Y) <= 2 * LAM_RTOL * v.lam, (l, i)
             per_r = Yl.reshape(w.R, lv.N).mean(axis=1)
             assert np.max(np.abs(Q[l] - per_r)) <= 2 * LAM_RTOL * np.max(lam)
+    finally:
+        c.close()
+
+
+def test_cfg12_finest_level_sampled(ctx_p2):
+    # the six-level Problem 2 workload's finest level (h = 1/256, s = 512,
+    # previous term on 1/128) at full size: every value unflagged, three
+    # strided ones against the oracle, the estimator's level mean equal to the
+    # mean of the level values
+    w = CONFIGS[12]
+    fam = w.family()
+    l = 5
+    lv = w.levels[l]
+    c = m.Context(fam)
+    try:
+        st, Q, Qh, V, est = c.estimate([_lv6(x) for x in w.levels], [x.N for x in w.levels],
+                                       w.R, [w.z(i) for i in range(6)],
+                                       [w.shifts(i) for i in range(6)])
+        assert st == m.MLQMC_OK
+        Y = _level_points(c, w, l)
+        n = Y.shape[0]
+        lam, lamp = np.empty(n), np.empty(n)
+        fl = np.zeros(n, np.uint8)
+        c.eig_level(_lv6(lv), Y, lam, fl, lam_prev=lamp)
+        assert not fl.any()
+        Yl = lam - lamp
+        for i in (0, n // 2 + 7, n - 1):
+            v = mlqmc.level_value(lv, Y[i], fam)
+            assert abs(lam[i] - v.lam) <= LAM_RTOL * v.lam, (i, lam[i], v.lam)
+            assert abs(Yl[i] - v.Y) <= 2 * LAM_RTOL * v.lam, (i, Yl[i], v.Y)
+        per_r = Yl.reshape(w.R, lv.N).mean(axis=1)
+        assert np.max(np.abs(Q[l] - per_r)) <= 2 * LAM_RTOL * np.max(lam)
     finally:
         c.close()

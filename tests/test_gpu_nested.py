@@ -297,11 +297,14 @@ def test_extend_from_zero_equals_nested(ctx):
     assert np.allclose(sums, ref[1] * np.array(N)[:, None], rtol=1e-15, atol=0)
 
 
-@pytest.mark.parametrize("path", [[[8, 4, 4, 2]], [[16, 4, 4, 1]], [[4, 2, 2, 1], [8, 8, 4, 2]]])
+@pytest.mark.parametrize("path", [[[8, 4, 4, 2]], [[16, 4, 4, 1]], [[4, 2, 2, 1], [8, 8, 4, 2]],
+                                  [[16, 8, 4, 2], [16, 8, 8, 2]]])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
 def test_extend_in_steps(ctx, fam, path, prec, tol):
-    # grow to N in steps (including a level whose block is empty and
-    # uneven starting points): the same estimate as one call and as the
+    # grow to N in steps (including a level whose block is empty, uneven
+    # starting points, and steps that grow only a finer level, where the
+    # coarser levels are evaluated only at the points it needs): the same
+    # estimate as one call and as the
     # oracle at N.  Against the one call the bar is the parity bar, not
     # rounding: other batch sizes change the warm-start chains of level 0 and
     # the strip order of the batched level's dot products
