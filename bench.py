@@ -42,6 +42,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
 PEAK_FP64_MFMA_TFS = 78.6  # MI355X dense FP64 matrix, published
 PEAK_FP64_VALU_TFS = 78.6  # MI355X FP64 vector, published
 PEAK_FP32_VALU_TFS = 157.3  # MI355X FP32 vector, published
+# LDS: 128 bytes per clock per compute unit x 256 units x 2.4 GHz
+PEAK_LDS_TBS = 128 * 256 * 2.4e9 / 1e12
 
 
 def _parse():
@@ -413,12 +415,48 @@ def rqi_sample_flops(n: int, rows: int, rq: int, lin: int, reaction: bool) -> in
             lin * ((op + 38) * D + vcycle))
 
 
-def rqi_step_flops(ctx, m, w, opts):
+def lds_words(n: int, its: int, rq: int, reaction: bool, solve: str) -> int:
+    """LDS traffic of one per-sample solve on mesh 1/n, in array elements read
+    or written (the same operation structure as the flop counts), per
+    interior node:
+
+    * operator A [+ R] x: 5 x reads and 4 weights (with the reaction 7 x reads
+      and 10 weights), 1 write: 10 (18); mass M x: 7 reads + 1 write = 8;
+    * V-cycle, per node of each level: the first sweep (right-hand side,
+      weights, write: 6 (12)), three sweeps (operator reads + rhs + write:
+      11 (19) each), the residual (operator reads + rhs: 10 (18)), the
+      restriction (2) and the prolongation (4): 55 (93);
+    * PCG iteration on the top level: q = (A - mu M) p (12 (18)), the six
+      dots and the t, r updates (13), the three dots after the V-cycle (3),
+      the p update (4): 32 (38), plus one V-cycle;
+    * per solve: staging the weights (2 (5) writes per node), the initial
+      residual (20 (26)) and V-cycle, and two Rayleigh quotients (16 (24)
+      each); an RQ eigensolve adds, per RQ step, a correction set-up and a
+      quotient.
+    solve = "update" (k_tg_small, `its` PCG iterations) or "rqi" (k_rqi,
+    `rq` RQ steps and `its` inner iterations in all)."""
+    D = (n - 1) ** 2
+    levels, c = 0, n
+    while c >= 2:
+        levels += (c - 1) ** 2
+        c //= 2
+    vcyc = (93 if reaction else 55) * levels
+    stage = (5 if reaction else 2) * D
+    init = (26 if reaction else 20) * D + vcyc
+    rq_eval = (24 if reaction else 16) * D
+    it = (38 if reaction else 32) * D + vcyc
+    if solve == "update":
+        return stage + init + 2 * rq_eval + its * it
+    return stage + rq_eval + rq * (init + rq_eval) + its * it
+
+
+def rqi_step_flops(ctx, m, w, opts, with_words=False):
     """Algorithmic flops of every k_rqi launch of one step of a direct-only
     workload, from the RQ-step and inner-iteration counts of the same points
     (an untimed pass)."""
     import numpy as np
     total = 0
+    words = [0]
     reaction = w.problem == 2
     for l, lv in enumerate(w.levels):
         n = w.R * lv.N
@@ -435,10 +473,11 @@ def rqi_step_flops(ctx, m, w, opts):
             rows = sm + 1 if reaction else sm
             for q, k in zip(rq.tolist(), li.tolist()):
                 total += rqi_sample_flops(nm, rows, q, k, reaction)
-    return total
+                words[0] += lds_words(nm, k, q, reaction, "rqi")
+    return (total, words[0]) if with_words else total
 
 
-def lds_step_flops(ctx, m, w, opts):
+def lds_step_flops(ctx, m, w, opts, with_words=False):
     """Algorithmic flops of every k_tg_small launch of one step of workload w,
     from the PCG iteration counts of the same points (an untimed pass; the
     solves are deterministic).  mlqmc_eig_level reports the coarse eigensolve's
@@ -448,6 +487,7 @@ def lds_step_flops(ctx, m, w, opts):
     requested G switches on)."""
     import numpy as np
     total = 0
+    words = 0
     reaction = w.problem == 2
     for l, lv in enumerate(w.levels):
         if not lv.n_coarse:
@@ -478,7 +518,10 @@ def lds_step_flops(ctx, m, w, opts):
             total += n * lds_update_flops(nm, rows, 0, reaction)
             total += int(its.sum()) * (lds_update_flops(nm, rows, 1, reaction) -
                                        lds_update_flops(nm, rows, 0, reaction))
-    return total
+            words += n * lds_words(nm, 0, 0, reaction, "update")
+            words += int(its.sum()) * (lds_words(nm, 1, 0, reaction, "update") -
+                                       lds_words(nm, 0, 0, reaction, "update"))
+    return (total, words) if with_words else total
 
 
 def _traffic(kernel: str, prec: str = "fp64", cfg: int = 2):
@@ -552,10 +595,11 @@ def timed_leg(ctx, m, w, opts, steps: int, warmup: int, kernel_class: str):
         est = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    launches, kms, kbytes = ctx.get_timing()
+    launches, kms, kbytes, kflops = ctx.get_timing(flops=True)
     ctx.set_timing(m.K_NONE)
     return {"value": w.n_samples() * steps / dt, "ms_per_step": 1e3 * dt / steps, "est": est,
-            "launches": launches, "kms": kms, "kbytes": kbytes, "steps": steps}
+            "launches": launches, "kms": kms, "kbytes": kbytes, "kflops": kflops,
+            "steps": steps}
 
 
 def roofline(ctx, m, w, opts, prec: str, kernel_class: str, leg, cfg: int):
@@ -568,34 +612,38 @@ def roofline(ctx, m, w, opts, prec: str, kernel_class: str, leg, cfg: int):
     avg_ms = kms / launches
     if kernel_class in ("rqi", "lds"):
         # LDS-resident solvers: vector arithmetic on data in LDS, against the
-        # vector peak of the precision they compute in
-        fl = (rqi_step_flops if kernel_class == "rqi" else lds_step_flops)(ctx, m, w, opts)
+        # vector peak of the precision they compute in; beside it the LDS
+        # traffic of the same solves against the LDS peak (neither bounds
+        # them: they wait on LDS latency and workgroup barriers)
+        fl, words = (rqi_step_flops if kernel_class == "rqi" else lds_step_flops)(
+            ctx, m, w, opts, with_words=True)
         flops_per_launch = fl * steps / launches
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
         peak = PEAK_FP64_VALU_TFS if prec == "fp64" else PEAK_FP32_VALU_TFS
+        lds_bytes = words * (8 if prec == "fp64" else 4) * steps / launches
+        lds_rate = lds_bytes / (avg_ms * 1e-3) / 1e12
         return {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                 "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
-                "algorithmic_flops_per_launch": flops_per_launch}
+                "algorithmic_flops_per_launch": flops_per_launch,
+                "lds": {"achieved": round(lds_rate, 3), "peak": PEAK_LDS_TBS, "unit": "TB/s",
+                        "frac": round(lds_rate / PEAK_LDS_TBS, 4),
+                        "bytes_per_launch": lds_bytes}}
     if kernel_class == "coeff":
-        # the coefficient product on FP64 MFMA: 2 s E flops per sample
-        # (E = edge weights of the padded mesh) on the batched meshes
-        flops_step = 0.0
-        for lv in w.levels:
-            if not lv.n_coarse:
-                continue
-            meshes = [(lv.n_fine, lv.s_fine)]
-            if lv.n_prev and not w.nested and not (lv.n_prev == lv.n_coarse and
-                                                    lv.s_prev == lv.s_coarse):
-                meshes.append((lv.n_prev, lv.s_prev))
-            for nm, sm in meshes:
-                if nm >= 64:
-                    flops_step += 2.0 * sm * 2 * (nm + 2) * nm * w.R * lv.N
-        flops_per_launch = flops_step * steps / launches
+        # the coefficient expansion: the product the library formed (the dense
+        # Y Phi on FP64 MFMA, 2 s E flops per sample, or the separable one on
+        # the FP64 vector units), flops from the library's model
+        flops_per_launch = leg["kflops"] / launches
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-        return {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 2),
-                "peak": PEAK_FP64_MFMA_TFS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_MFMA_TFS, 4),
+        fam = w.family()
+        dense = w.problem == 2 or not all(
+            4 * int(max(fam["k1"][:lv.s_fine])) < lv.s_fine for lv in w.levels if lv.n_coarse)
+        peak = PEAK_FP64_MFMA_TFS if dense else PEAK_FP64_VALU_TFS
+        if not dense:
+            kname = "k_sep_weights+k_sep_rows+k_sep_alias"
+        return {"bound": "mfma" if dense else "alu", "kernel": kname,
+                "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4),
                 "traffic": _traffic(kname, prec, cfg), "avg_launch_us": round(avg_ms * 1e3, 2),
                 "launches": launches, "algorithmic_flops_per_launch": flops_per_launch,
                 "hbm_GBs": round(kbytes / launches / (avg_ms * 1e-3) / 1e9, 1)}

@@ -412,10 +412,13 @@ enum {
 /* Selects the kernel class whose launches are bracketed by HIP events on the
  * context's stream (MLQMC_K_NONE disables) and clears the totals. */
 mlqmc_status mlqmc_set_timing(mlqmc_ctx* ctx, int32_t kernel_class);
-/* Number of timed launches, their summed duration in ms and the summed
- * algorithmic bytes those launches move (the model in the library's notes). */
+/* Number of timed launches, their summed duration in ms, and the summed
+ * algorithmic bytes and flops of those launches (the library's per-kernel
+ * model: bytes each array is moved once, flops of the arithmetic the kernel
+ * must do; flops are counted for the coefficient expansion only, else 0).
+ * Any output may be NULL. */
 mlqmc_status mlqmc_get_timing(mlqmc_ctx* ctx, int64_t* launches, double* total_ms,
-                              double* model_bytes);
+                              double* model_bytes, double* model_flops);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,7 @@ import os
 import sys
 import time
 
-CANDIDATES = (8192, 16384, 32768, 65536, 131072, 262144)
+CANDIDATES = (2048, 4096, 8192, 16384, 32768, 65536, 131072, 262144)
 
 
 def _levels_on_batched_path(w):
@@ -100,7 +100,11 @@ def main(argv=None):
     arch, entries = tune(a.cfg, reps=a.reps, log=lambda s: print(s, flush=True))
     out = a.out or B.TUNING_PATH
     table = json.load(open(out)) if os.path.exists(out) else {}
-    table[arch] = entries
+    # the measured (mesh, precision) pairs replace theirs; the others stay
+    keep = {(e["n_fine"], e["prec"]): e for e in table.get(arch, [])}
+    for e in entries:
+        keep[(e["n_fine"], e["prec"])] = e
+    table[arch] = [keep[k] for k in sorted(keep)]
     with open(out, "w") as f:
         json.dump(table, f, indent=1)
     print(json.dumps({"arch": arch, "entries": entries}))

@@ -129,7 +129,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                             C.POINTER(I32)]
     lib.mlqmc_set_tuning.argtypes = [P, I32, I32, I64]
     lib.mlqmc_set_timing.argtypes = [P, I32]
-    lib.mlqmc_get_timing.argtypes = [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]
+    lib.mlqmc_get_timing.argtypes = [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D),
+                                     C.POINTER(D)]
     for name in ("mlqmc_create", "mlqmc_create_islands", "mlqmc_lattice_points",
                  "mlqmc_embedded_points", "mlqmc_coefficient", "mlqmc_apply_operator", "mlqmc_prolong",
                  "mlqmc_eig_level", "mlqmc_eig_level_noalloc", "mlqmc_estimate",
@@ -491,11 +492,16 @@ class Context:
     def set_timing(self, kernel_class):
         return self._check(self._lib.mlqmc_set_timing(self._h, int(kernel_class)))
 
-    def get_timing(self):
+    def get_timing(self, flops=False):
+        """(launches, total ms, model bytes[, model flops]) of the timed class."""
         n = C.c_int64()
         ms = C.c_double()
         by = C.c_double()
-        self._check(self._lib.mlqmc_get_timing(self._h, C.byref(n), C.byref(ms), C.byref(by)))
+        fl = C.c_double()
+        self._check(self._lib.mlqmc_get_timing(self._h, C.byref(n), C.byref(ms), C.byref(by),
+                                               C.byref(fl)))
+        if flops:
+            return int(n.value), float(ms.value), float(by.value), float(fl.value)
         return int(n.value), float(ms.value), float(by.value)
 
 

@@ -126,6 +126,17 @@ struct mlqmc_ctx {
   int* d_region = nullptr;
   std::map<std::string, DevBuf> bufs;
   std::map<int, Table> tables;
+  // Problem 1 family on the host (the separable expansion's term boxes)
+  std::vector<int> h_k1, h_k2;
+  // separable expansion per (mesh, truncation): the term box kx x ky, its
+  // cells in CSR, the sines on the grid of thirds
+  struct SepTable {
+    int kx = 0, ky = 0;
+    int* cell_start = nullptr;
+    int* cell_term = nullptr;
+    double* S = nullptr;
+  };
+  std::map<std::pair<int, int>, SepTable> seps;
   // No-allocation mode (mlqmc_eig_level_noalloc): named buffers and tables
   // are carved in order from this device's copy of `scratch` and live for one
   // call; nothing is allocated and nothing is cached past the call.
@@ -136,6 +147,52 @@ struct mlqmc_ctx {
   std::map<int, Table> arena_tables;
   int64_t bytes_alloc = 0;
   int64_t mem_cap = 0;
+
+  // The separable table for (n, s), or nullptr when the dense product is
+  // cheaper: the separable form costs 8 kx per padded node and sample (two
+  // weights, two elements, kx multiply-adds each) on the vector units
+  // against 4 s on the matrix cores, so it is taken when 2 kx < s / 2.
+  mlqmc_status sep_table(int n, int s, SepTable** out) {
+    *out = nullptr;
+    if (islands || n < 64 || (n % 64) || s < 1 || (int)h_k1.size() < s) return MLQMC_OK;
+    int kx = 0, ky = 0;
+    for (int j = 0; j < s; ++j) {
+      kx = std::max(kx, h_k1[j]);
+      ky = std::max(ky, h_k2[j]);
+    }
+    if (kx > 64 || kx * ky > 1024 || !(4 * kx < s)) return MLQMC_OK;
+    SepTable& t = seps[{n, s}];
+    if (!t.S) {
+      const int kmax = std::max(kx, ky), cells = kx * ky;
+      std::vector<int> start(cells + 1, 0), term(s);
+      for (int j = 0; j < s; ++j) ++start[(h_k1[j] - 1) * ky + (h_k2[j] - 1) + 1];
+      for (int c = 0; c < cells; ++c) start[c + 1] += start[c];
+      std::vector<int> fill(start.begin(), start.end() - 1);
+      for (int j = 0; j < s; ++j) term[fill[(h_k1[j] - 1) * ky + (h_k2[j] - 1)]++] = j;
+      const size_t bs = (size_t)kmax * (3 * n + 2) * sizeof(double);
+      const size_t bc = (cells + 1) * sizeof(int), bt = (size_t)s * sizeof(int);
+      if (mem_cap > 0 && bytes_alloc + (int64_t)(bs + bc + bt) > mem_cap)
+        return fail(MLQMC_ENOMEM, "separable table for n=%d exceeds the device memory cap", n);
+      hipError_t e = hipMalloc(&t.S, bs);
+      if (e == hipSuccess) e = hipMalloc(&t.cell_start, bc);
+      if (e == hipSuccess) e = hipMalloc(&t.cell_term, bt);
+      if (e == hipSuccess)
+        e = hipMemcpy(t.cell_start, start.data(), bc, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(t.cell_term, term.data(), bt, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = launch_sep_sin(n, kmax, t.S, stream);
+      if (e != hipSuccess) {
+        for (void* q : {(void*)t.S, (void*)t.cell_start, (void*)t.cell_term})
+          if (q) (void)hipFree(q);
+        seps.erase({n, s});
+        return fail(MLQMC_ENOMEM, "separable table: %s", hipGetErrorString(e));
+      }
+      bytes_alloc += (int64_t)(bs + bc + bt);
+      t.kx = kx;
+      t.ky = ky;
+    }
+    *out = &t;
+    return MLQMC_OK;
+  }
   std::string err;
   // timing
   int timing_class = MLQMC_K_NONE;
@@ -144,6 +201,7 @@ struct mlqmc_ctx {
   int64_t t_launches = 0;
   double t_ms = 0.0;
   double t_bytes = 0.0;
+  double t_flops = 0.0;
 
   mlqmc_status fail(mlqmc_status code, const char* fmt, ...) {
     char buf[512];
@@ -165,6 +223,31 @@ struct mlqmc_ctx {
                   name, arena_used, arena_size);
     *out = arena + arena_used;
     arena_used += b;
+    return MLQMC_OK;
+  }
+
+  // streams of the levels that run beside the context's stream (default
+  // priority, non-blocking) and the fork / join events, created on first use
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> sync_ev;
+  mlqmc_status side_stream(int k, hipStream_t* out) {
+    while ((int)side.size() <= k) {
+      hipStream_t s = nullptr;
+      const hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "side stream");
+      side.push_back(s);
+    }
+    *out = side[k];
+    return MLQMC_OK;
+  }
+  mlqmc_status event(int k, hipEvent_t* out) {
+    while ((int)sync_ev.size() <= k) {
+      hipEvent_t ev = nullptr;
+      const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "event");
+      sync_ev.push_back(ev);
+    }
+    *out = sync_ev[k];
     return MLQMC_OK;
   }
 
@@ -325,7 +408,7 @@ struct mlqmc_ctx {
     }
     if (hipEventRecord(ev_pool[ev_used].first, stream) != hipSuccess) timing_class = MLQMC_K_NONE;
   }
-  void t_end(int cls, double bytes) {
+  void t_end(int cls, double bytes, double flops = 0.0) {
     if (!timed(cls)) return;
     if (hipEventRecord(ev_pool[ev_used].second, stream) != hipSuccess) {
       timing_class = MLQMC_K_NONE;
@@ -334,6 +417,7 @@ struct mlqmc_ctx {
     ++ev_used;
     ++t_launches;
     t_bytes += bytes;
+    t_flops += flops;
   }
   void t_collect() {
     for (size_t k = 0; k < ev_used; ++k) {
@@ -578,6 +662,9 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   for (size_t k = 1; k < nL; ++k) per_sample += sz * (EW(lv[k]) + 3 * P(lv[k]));
   per_sample += sz * (EW(nb) + 2 * P(nb));
   if (rx) per_sample += 8 * (s + 1);  // the points with their leading 1
+  mlqmc_ctx::SepTable* sep = nullptr;  // the separable expansion, when cheaper
+  CS(ctx->sep_table(nh, s, &sep));
+  if (sep) per_sample += 8 * (3 * nh + 2) * sep->kx;  // its row sums U
   // default batch: up to 48 GB of working arrays (HBM holds 288 GB), in
   // multiples of the 128-sample tile of the coefficient product when larger
   int64_t batch = o->batch;
@@ -591,10 +678,11 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
 
   std::string p = tag;
   auto nm = [&](const char* x) { return p + x; };
-  double *w64, *part, *Y1 = nullptr;
+  double *w64, *part, *Y1 = nullptr, *sepU = nullptr;
   T *wT, *vn, *mvn, *t, *r, *r2, *z, *zb, *pp[2];
   CS(ctx->getT(nm("w64").c_str(), batch * EW(nh), &w64));
   if (rx) CS(ctx->getT(nm("Y1").c_str(), batch * (s + 1), &Y1));
+  if (sep) CS(ctx->getT(nm("sepU").c_str(), batch * (3 * nh + 2) * sep->kx, &sepU));
   if constexpr (kMixed) {
     CS(ctx->getT(nm("w32").c_str(), batch * EW(nh), &wT));
   } else {
@@ -697,14 +785,28 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
       CK(launch_expand(Bn, s + 1, 3 * P(nh), Y1, s + 1, tb->rpad, 0.0, w64 + 2 * P(nh),
                        w32 ? w32 + 2 * P(nh) : nullptr, st, EW(nh)),
          "expand");
+    } else if (sep) {
+      CK(launch_expand_separable(Bn, nh, s, sep->kx, sep->ky, Y + b0 * ldY, ldY, ctx->d_c,
+                                 sep->cell_start, sep->cell_term, sep->S, sepU, ctx->a0, w64, w32,
+                                 EW(nh), st),
+         "expand (separable)");
     } else {
       CK(launch_expand(Bn, s, EW(nh), Y + b0 * ldY, ldY, tb->pad, ctx->a0, w64, w32, st),
          "expand");
     }
-    // Y and phi in, the weights out (FP64, plus the FP32 copy in mixed precision)
+    // the weights out (FP64, plus the FP32 copy in mixed precision); in: Y and
+    // the table (dense), or Y and the row sums U (separable: written and read
+    // once); flops of the product actually formed
     const int rows = rx ? s + 1 : s;
-    ctx->t_end(MLQMC_K_COEFF, 8.0 * ((double)Bn * rows + (double)rows * EW(nh)) +
-                                  (8.0 + (kMixed ? 4.0 : 0.0)) * (double)Bn * EW(nh));
+    const double wout = (8.0 + (kMixed ? 4.0 : 0.0)) * (double)Bn * EW(nh);
+    if (sep) {
+      const double M3 = 3.0 * nh + 2.0;
+      ctx->t_end(MLQMC_K_COEFF, 8.0 * (double)Bn * s + 16.0 * (double)Bn * M3 * sep->kx + wout,
+                 (double)Bn * (8.0 * sep->kx * P(nh) + 2.0 * M3 * sep->kx * sep->ky));
+    } else {
+      ctx->t_end(MLQMC_K_COEFF, 8.0 * ((double)Bn * rows + (double)rows * EW(nh)) + wout,
+                 2.0 * rows * (double)EW(nh) * Bn);
+    }
     for (size_t k = 0; k < nL; ++k)
       CK(launch_coarsen<T>(lv[k], Bn, W[k], W[k + 1], rx, st), "coarsen");
 
@@ -922,7 +1024,11 @@ int shift_chain(mlqmc_ctx* ctx, int64_t N, int R, const mlqmc_opts* o, int mesh)
 mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* o, int64_t n,
                         const double* Y, int64_t ldY, int warm, double* lam, double* lam_prev,
                         double* lam_coarse, int* rq_iters, int* lin_iters, uint8_t* flags,
-                        double* g = nullptr, double* g_prev = nullptr) {
+                        double* g = nullptr, double* g_prev = nullptr,
+                        const std::string& pfx = std::string()) {
+  // named scratch of this call (a prefix keeps levels that run at the same
+  // time on different streams apart)
+  auto nm = [&](const char* x) { return pfx + x; };
   hipStream_t st = ctx->stream;
   if (n == 0) return MLQMC_OK;
   CK(hipMemsetAsync(flags, 0, n, st), "memset");
@@ -944,7 +1050,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
     auto scratch_for = [&](int mesh, RqiArgs& ra) -> mlqmc_status {
       if (const int64_t per = rqi_scratch_doubles(mesh)) {
         ra.scratch_doubles = per * ((n + chain - 1) / chain);
-        CS(ctx->getT("rqi_scratch", ra.scratch_doubles, &ra.scratch));
+        CS(ctx->getT(nm("rqi_scratch").c_str(), ra.scratch_doubles, &ra.scratch));
       }
       return MLQMC_OK;
     };
@@ -961,8 +1067,8 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
     if (L->n_prev && lam_prev) {
       uint8_t* f2 = nullptr;
       int* i2 = nullptr;
-      CS(ctx->getT("flags_prev", n, &f2));
-      CS(ctx->getT("rq_prev", n, &i2));
+      CS(ctx->getT(nm("flags_prev").c_str(), n, &f2));
+      CS(ctx->getT(nm("rq_prev").c_str(), n, &i2));
       CS(ctx->table(L->n_prev, L->s_prev, &tb));
       RqiArgs b = a;
       b.S = L->s_prev;
@@ -979,14 +1085,9 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
       ctx->t_begin(MLQMC_K_COARSE);
       CK(launch_rqi(L->n_prev, b, st), "eigensolve (LDS)");
       ctx->t_end(MLQMC_K_COARSE, 0.0);
-      // merge the flags of the previous-level eigensolve on the host
-      std::vector<uint8_t> h1(n), h2(n);
-      CK(hipMemcpyAsync(h1.data(), flags, n, hipMemcpyDeviceToHost, st), "flags");
-      CK(hipMemcpyAsync(h2.data(), f2, n, hipMemcpyDeviceToHost, st), "flags");
-      CS(ctx->sync("flags"));
-      for (int64_t k = 0; k < n; ++k) h1[k] |= h2[k];
-      CK(hipMemcpyAsync(flags, h1.data(), n, hipMemcpyHostToDevice, st), "flags");
-      CS(ctx->sync("flags"));
+      // the previous-level eigensolve's flags join the level's (on the device:
+      // no host round trip)
+      CK(launch_or_flags(n, flags, f2, st), "flags");
     }
     return MLQMC_OK;
   }
@@ -995,8 +1096,8 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   CS(ctx->table(L->n_coarse, L->s_coarse, &tb));
   const int64_t DH = (int64_t)(L->n_coarse - 1) * (L->n_coarse - 1);
   double *uH = nullptr, *lamH = lam_coarse;
-  CS(ctx->getT("uH", n * DH, &uH));
-  if (!lamH) CS(ctx->getT("lamH", n, &lamH));
+  CS(ctx->getT(nm("uH").c_str(), n * DH, &uH));
+  if (!lamH) CS(ctx->getT(nm("lamH").c_str(), n, &lamH));
   a.S = L->s_coarse;
   a.phi = tb->pad;
   a.rphi = tb->rpad;
@@ -1014,7 +1115,7 @@ mlqmc_status level_core(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_opts* 
   a.refine = (ctx->islands || g || (L->n_prev && g_prev)) ? 1 : 0;
   if (const int64_t per = rqi_scratch_doubles(L->n_coarse)) {
     a.scratch_doubles = per * ((n + chain - 1) / chain);
-    CS(ctx->getT("rqi_scratch", a.scratch_doubles, &a.scratch));
+    CS(ctx->getT(nm("rqi_scratch").c_str(), a.scratch_doubles, &a.scratch));
   }
   ctx->t_begin(MLQMC_K_COARSE);
   CK(launch_rqi(L->n_coarse, a, st), "coarse eigensolve (LDS)");
@@ -1122,6 +1223,8 @@ mlqmc_status mlqmc_create(mlqmc_ctx** out, const mlqmc_coeff* cf, int device, vo
     k1[j] = cf->k1[j];
     k2[j] = cf->k2[j];
   }
+  ctx->h_k1.assign(k1.begin(), k1.begin() + cf->s_max);
+  ctx->h_k2.assign(k2.begin(), k2.begin() + cf->s_max);
   e = hipMalloc(&ctx->d_c, sm * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&ctx->d_k1, sm * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&ctx->d_k2, sm * sizeof(int));
@@ -1235,6 +1338,9 @@ void mlqmc_destroy(mlqmc_ctx* ctx) {
   for (auto& kv : ctx->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto& kv : ctx->tables) kv.second.release();
+  for (auto& kv : ctx->seps)
+    for (void* q : {(void*)kv.second.S, (void*)kv.second.cell_start, (void*)kv.second.cell_term})
+      if (q) (void)hipFree(q);
   for (auto& ev : ctx->ev_pool) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
@@ -1242,6 +1348,9 @@ void mlqmc_destroy(mlqmc_ctx* ctx) {
   for (auto& kv : ctx->graphs)
     if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  for (hipStream_t ss : ctx->side) (void)hipStreamSynchronize(ss);
+  for (hipStream_t ss : ctx->side) (void)hipStreamDestroy(ss);
+  for (hipEvent_t ev : ctx->sync_ev) (void)hipEventDestroy(ev);
   if (ctx->d_c) (void)hipFree(ctx->d_c);
   if (ctx->d_k1) (void)hipFree(ctx->d_k1);
   if (ctx->d_k2) (void)hipFree(ctx->d_k2);
@@ -1533,43 +1642,109 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
   const size_t gsz = (size_t)nl * R + 2 * (size_t)nl + 2;
   double* dG = nullptr;
   if (g_stats) CS(out_buf(ctx, "e_G", g_stats, gsz, dev, &dG));
-  bool flagged = false;
+  // The levels are independent (Algorithm 2).  Those whose every solve runs
+  // per sample in LDS (meshes up to 1/32) need no host round trip: they are
+  // enqueued first, each on a stream of its own, and run beside the batched
+  // levels, which follow on the context's stream (their PCG reads back which
+  // samples are still active).  Every level has its own buffers; the
+  // coefficient tables are built before the fork, with the largest truncation
+  // each mesh needs, so no table is rebuilt while a level reads it.
+  auto lds_only = [](const mlqmc_level& L) {
+    return L.n_fine <= 32 && L.n_coarse <= 32 && L.n_prev <= 32;
+  };
+  {
+    std::map<int, int> smax;
+    auto need = [&](int m, int sv) {
+      if (m > 0) smax[m] = std::max(smax[m], sv);
+    };
+    for (int l = 0; l < nl; ++l) {
+      need(lv[l].n_fine, lv[l].s_fine);
+      need(lv[l].n_coarse, lv[l].s_coarse);
+      need(lv[l].n_prev, lv[l].s_prev);
+    }
+    for (const auto& kv : smax) {
+      Table* tb = nullptr;
+      CS(ctx->table(kv.first, kv.second, &tb));
+    }
+  }
+  std::vector<int64_t> zo(nl), so(nl);
   zoff = soff = 0;
   for (int l = 0; l < nl; ++l) {
+    zo[l] = zoff;
+    so[l] = soff;
+    zoff += lv[l].s_fine;
+    soff += (int64_t)R * lv[l].s_fine;
+  }
+  std::vector<uint8_t*> lflags(nl, nullptr);
+  // one level on the context's current stream, buffers named by level
+  auto run_level = [&](int l) -> mlqmc_status {
     const mlqmc_level& L = lv[l];
     const int s = L.s_fine;
     const int64_t n = (int64_t)R * N[l];
-    const int64_t *dz;
+    const std::string p = "e" + std::to_string(l) + "_";
+    auto nm = [&](const char* x) { return p + x; };
+    hipStream_t ls = ctx->stream;
+    const int64_t* dz;
     const double* dsh;
-    CS(stage_in(ctx, "e_z", z + zoff, s, 0, &dz));
-    CS(stage_in(ctx, "e_sh", shifts + soff, (size_t)R * s, 0, &dsh));
+    CS(stage_in(ctx, nm("z").c_str(), z + zo[l], s, 0, &dz));
+    CS(stage_in(ctx, nm("sh").c_str(), shifts + so[l], (size_t)R * s, 0, &dsh));
     double *Y, *lam, *lamp = nullptr;
     int *rqi, *lini;
     uint8_t* fl;
-    CS(ctx->getT("e_Y", (size_t)(n * std::max(s, 1)), &Y));
-    CS(ctx->getT("e_lam", n, &lam));
-    if (L.n_prev) CS(ctx->getT("e_lamp", n, &lamp));
-    CS(ctx->getT("e_rq", n, &rqi));
-    CS(ctx->getT("e_li", n, &lini));
-    CS(ctx->getT("e_fl", n, &fl));
-    CK(launch_lattice_multi(N[l], s, R, dz, dsh, N[l], Y, std::max(s, 1), st), "lattice");
+    CS(ctx->getT(nm("Y").c_str(), (size_t)(n * std::max(s, 1)), &Y));
+    CS(ctx->getT(nm("lam").c_str(), n, &lam));
+    if (L.n_prev) CS(ctx->getT(nm("lamp").c_str(), n, &lamp));
+    CS(ctx->getT(nm("rq").c_str(), n, &rqi));
+    CS(ctx->getT(nm("li").c_str(), n, &lini));
+    CS(ctx->getT(nm("fl").c_str(), n, &fl));
+    lflags[l] = fl;
+    CK(launch_lattice_multi(N[l], s, R, dz, dsh, N[l], Y, std::max(s, 1), ls), "lattice");
     mlqmc_opts oo = *o;
     oo.chain_len = shift_chain(ctx, N[l], R, o, L.n_coarse ? L.n_coarse : L.n_fine);
     double *gv = nullptr, *gp = nullptr;
     if (dG) {
-      CS(ctx->getT("e_g", n, &gv));
-      if (L.n_prev) CS(ctx->getT("e_gp", n, &gp));
+      CS(ctx->getT(nm("g").c_str(), n, &gv));
+      if (L.n_prev) CS(ctx->getT(nm("gp").c_str(), n, &gp));
     }
     CS(level_core(ctx, &L, &oo, n, Y, std::max(s, 1), 1, lam, lamp, nullptr, rqi, lini, fl, gv,
-                  gp));
-    CK(launch_level_sums(N[l], R, lam, lamp, dQ + (int64_t)l * R, st), "level sums");
-    if (dG) CK(launch_level_sums(N[l], R, gv, gp, dG + (int64_t)l * R, st), "level sums");
-    bool any = false;
-    CS(any_flag(ctx, fl, n, &any));
-    flagged |= any;
-    zoff += s;
-    soff += (int64_t)R * s;
+                  gp, p));
+    CK(launch_level_sums(N[l], R, lam, lamp, dQ + (int64_t)l * R, ls), "level sums");
+    if (dG) CK(launch_level_sums(N[l], R, gv, gp, dG + (int64_t)l * R, ls), "level sums");
+    return MLQMC_OK;
+  };
+  // fork: the side streams start after everything enqueued so far
+  std::vector<hipEvent_t> joins;
+  int side = 0;
+  for (int l = 0; l < nl; ++l)
+    if (lds_only(lv[l])) ++side;
+  if (side > 1 || (side == 1 && side < nl)) {
+    hipEvent_t fork = nullptr;
+    CS(ctx->event(0, &fork));
+    CK(hipEventRecord(fork, st), "fork");
+    int k = 0;
+    for (int l = 0; l < nl; ++l) {
+      if (!lds_only(lv[l])) continue;
+      hipStream_t ss = nullptr;
+      CS(ctx->side_stream(k, &ss));
+      CK(hipStreamWaitEvent(ss, fork, 0), "fork");
+      const hipStream_t keep = ctx->stream;
+      ctx->stream = ss;
+      const mlqmc_status r = run_level(l);
+      ctx->stream = keep;
+      CS(r);
+      hipEvent_t j = nullptr;
+      CS(ctx->event(1 + k, &j));
+      CK(hipEventRecord(j, ss), "join");
+      joins.push_back(j);
+      ++k;
+    }
+    for (int l = 0; l < nl; ++l)
+      if (!lds_only(lv[l])) CS(run_level(l));
+    for (hipEvent_t j : joins) CK(hipStreamWaitEvent(st, j, 0), "join");
+  } else {
+    for (int l = 0; l < nl; ++l) CS(run_level(l));
   }
+  bool flagged = false;
   CK(launch_estimator_final(nl, R, dQ, dQh, dV, dest, 0, st), "estimator");
   if (dG) {
     double* q = dG + (size_t)nl * R;
@@ -1581,6 +1756,11 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
   CS(stage_out(ctx, est, dest, 2, dev));
   if (dG) CS(stage_out(ctx, g_stats, dG, gsz, dev));
   CS(ctx->sync("estimate"));
+  for (int l = 0; l < nl; ++l) {
+    bool any = false;
+    CS(any_flag(ctx, lflags[l], (int64_t)R * N[l], &any));
+    flagged |= any;
+  }
   return flagged ? ctx->fail(MLQMC_ENOCONV, "at least one sample is flagged") : MLQMC_OK;
 }
 
@@ -2032,18 +2212,20 @@ mlqmc_status mlqmc_set_timing(mlqmc_ctx* ctx, int32_t cls) {
   ctx->t_launches = 0;
   ctx->t_ms = 0.0;
   ctx->t_bytes = 0.0;
+  ctx->t_flops = 0.0;
   ctx->ev_used = 0;
   return MLQMC_OK;
 }
 
 mlqmc_status mlqmc_get_timing(mlqmc_ctx* ctx, int64_t* launches, double* total_ms,
-                              double* model_bytes) {
+                              double* model_bytes, double* model_flops) {
   if (!ctx) return MLQMC_EINVAL;
   CK(hipSetDevice(ctx->device), "set device");
   CS(ctx->sync("timing"));
   if (launches) *launches = ctx->t_launches;
   if (total_ms) *total_ms = ctx->t_ms;
   if (model_bytes) *model_bytes = ctx->t_bytes;
+  if (model_flops) *model_flops = ctx->t_flops;
   return MLQMC_OK;
 }
 

@@ -282,6 +282,154 @@ __global__ __launch_bounds__(256, 2) void k_expand_mfma(int64_t B, int s, int64_
     }
 }
 
+// ---------------------------------------------------------------- separable expansion
+//
+// For a family whose terms are products sin(pi k1 x1) sin(pi k2 x2) the sum
+// over j collects into C(y)[p][q] = sum of y_j c_j over the terms with
+// (k1, k2) = (p + 1, q + 1), and at a point with coordinates (x1, x2)
+//   sum_j y_j a_j = sum_p sin(pi (p+1) x1) U_p(x2),  U_p(x2) = sum_q C[p][q] sin(pi (q+1) x2).
+// Every element centroid lies on the grid of thirds of the mesh, x = m h / 3,
+// so with S[p][m] = sin(pi (p+1) m / (3 n)) and U[m][p] the row sums at
+// x2 = m h / 3, an edge weight (the mean over its two elements) is
+//   WX(i, j) = a0 + (S[.][3i-2] . U[3j-1] + S[.][3i-1] . U[3j+1]) / 2
+//     (the upper element of square (i-1, j-1), centroid (i - 2/3, j - 1/3) h,
+//      and the lower one of square (i-1, j), (i - 1/3, j + 1/3) h),
+//   WY(i, j) = a0 + (S[.][3i-1] . U[3j-2] + S[.][3i+1] . U[3j-1]) / 2
+//     (the lower element of square (i-1, j-1), (i - 1/3, j - 2/3) h, and the
+//      upper one of square (i, j-1), (i + 1/3, j - 1/3) h):
+// 2 kx multiply-adds per weight instead of 2 s (kx = the largest k1).
+
+// S[p][m] = sin(pi (p + 1) m / (3 n)), p < kmax, m < 3 n + 2
+__global__ __launch_bounds__(256) void k_sep_sin(int n, int kmax, double* __restrict__ S) {
+  const int M = 3 * n + 2;
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (id >= (int64_t)kmax * M) return;
+  const int p = (int)(id / M), m = (int)(id - (int64_t)p * M);
+  S[id] = sinpi((double)((p + 1) * m) / (3.0 * n));
+}
+
+// U[b][m][p] for m in [m0, m0 + 64) of sample b (grid: m tiles x samples):
+// C_b from the terms of each (k1, k2) cell in term order, then the row sums
+constexpr int kSepMaxCells = 1024;
+__global__ __launch_bounds__(256) void k_sep_rows(int n, int s, int kx, int ky,
+                                                  const double* __restrict__ Y, int64_t ldY,
+                                                  const double* __restrict__ c,
+                                                  const int* __restrict__ cell_start,
+                                                  const int* __restrict__ cell_term,
+                                                  const double* __restrict__ S,
+                                                  double* __restrict__ U) {
+  __shared__ double sC[kSepMaxCells];
+  const int64_t b = blockIdx.y;
+  const int M = 3 * n + 2;
+  const int m0 = blockIdx.x * 64;
+  for (int cell = threadIdx.x; cell < kx * ky; cell += 256) {
+    double v = 0.0;
+    for (int t = cell_start[cell]; t < cell_start[cell + 1]; ++t) {
+      const int j = cell_term[t];
+      v += Y[b * ldY + j] * c[j];
+    }
+    sC[cell] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * kx; e += 256) {
+    const int m = m0 + e / kx, p = e % kx;
+    if (m >= M) continue;
+    double u = 0.0;
+    for (int q = 0; q < ky; ++q) u += sC[p * ky + q] * S[(int64_t)q * M + m];
+    U[(b * M + m) * kx + p] = u;
+  }
+}
+
+// Padded [WX | WY] of B samples from U (tiles of 64 columns x 16 rows; wave w
+// of a block owns rows r0 + 4w .. r0 + 4w + 3, lane = column).  Positions
+// that are not edges of interior nodes get a0, as in the table product; the
+// right-boundary aliases of WX (column 0, rows 2..n) come from k_sep_alias.
+constexpr int kSepMaxK = 64;
+__global__ __launch_bounds__(256) void k_sep_weights(int64_t B, int n, int kx, int tiles,
+                                                     const double* __restrict__ U,
+                                                     const double* __restrict__ S, double a0,
+                                                     double* __restrict__ out,
+                                                     float* __restrict__ out32, int64_t ldo) {
+  // XCD-aware: the tiles of one sample run on one XCD (block L on XCD L mod 8)
+  const int64_t L = blockIdx.x;
+  const int64_t q = L >> 3;
+  const int64_t b = ((q / tiles) << 3) + (L & 7);
+  if (b >= B) return;
+  const int tile = (int)(q % tiles);
+  const int ct = n / 64;
+  const int c0 = (tile % ct) * 64, r0 = (tile / ct) * 16;
+  const int M = 3 * n + 2, P = (n + 2) * n;
+  // dynamic LDS: S at 3i-2, 3i-1, 3i+1 for the tile's columns [3][kx][64],
+  // then U at m = 3 r0 - 3 .. 3 r0 + 48 [52][kx]
+  extern __shared__ double sm_sep[];
+  double* sS = sm_sep;
+  double* sU = sm_sep + 3 * kx * 64;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int e = t; e < 3 * kx * 64; e += 256) {
+    const int o = e / (kx * 64), rem = e - o * kx * 64, p = rem / 64, cc = rem % 64;
+    const int m = 3 * (c0 + cc) + (o == 0 ? -2 : (o == 1 ? -1 : 1));
+    sS[e] = (m >= 0 && m < M) ? S[(int64_t)p * M + m] : 0.0;
+  }
+  const int mb = 3 * r0 - 3;
+  const double* Ub = U + b * (int64_t)M * kx;
+  for (int e = t; e < 52 * kx; e += 256) {
+    const int m = mb + e / kx, p = e % kx;
+    sU[e] = (m >= 0 && m < M) ? Ub[(int64_t)m * kx + p] : 0.0;
+  }
+  __syncthreads();
+  double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
+  const int jr = r0 + 4 * w;  // first of this wave's four rows
+  for (int p = 0; p < kx; ++p) {
+    const double sa = sS[p * 64 + lane], sb = sS[(kx + p) * 64 + lane],
+                 sc = sS[(2 * kx + p) * 64 + lane];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = jr + r, u0 = 3 * j - mb;  // U row of m = 3j lives at u0
+      const double um2 = sU[(u0 - 2) * kx + p], um1 = sU[(u0 - 1) * kx + p],
+                   up1 = sU[(u0 + 1) * kx + p];
+      ax[r] += sa * um1 + sb * up1;
+      ay[r] += sb * um2 + sc * um1;
+    }
+  }
+  const int i = c0 + lane;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int j = jr + r;
+    if (j > n + 1) continue;
+    const double vx = (i >= 1 && j >= 1 && j <= n - 1) ? a0 + 0.5 * ax[r] : a0;
+    const double vy = (i >= 1 && j >= 1 && j <= n) ? a0 + 0.5 * ay[r] : a0;
+    const int64_t o = b * ldo + (int64_t)j * n + i;
+    out[o] = vx;
+    out[o + P] = vy;
+    if (out32) {
+      out32[o] = (float)vx;
+      out32[o + P] = (float)vy;
+    }
+  }
+}
+
+// WX at column 0 of rows 2..n: the edge (n-1, j-1)-(n, j-1) into the right
+// boundary, at x = (n - 2/3) h and (n - 1/3) h (grid: samples; thread = row)
+__global__ __launch_bounds__(256) void k_sep_alias(int64_t B, int n, int kx,
+                                                   const double* __restrict__ U,
+                                                   const double* __restrict__ S, double a0,
+                                                   double* __restrict__ out,
+                                                   float* __restrict__ out32, int64_t ldo) {
+  const int64_t b = blockIdx.y;
+  const int j = 2 + blockIdx.x * 256 + threadIdx.x;
+  if (b >= B || j > n) return;
+  const int M = 3 * n + 2, je = j - 1;
+  const double* Ub = U + b * (int64_t)M * kx;
+  double acc = 0.0;
+  for (int p = 0; p < kx; ++p)
+    acc += S[(int64_t)p * M + 3 * n - 2] * Ub[(int64_t)(3 * je - 1) * kx + p] +
+           S[(int64_t)p * M + 3 * n - 1] * Ub[(int64_t)(3 * je + 1) * kx + p];
+  const double v = a0 + 0.5 * acc;
+  const int64_t o = b * ldo + (int64_t)j * n;
+  out[o] = v;
+  if (out32) out32[o] = (float)v;
+}
+
 __global__ __launch_bounds__(256) void k_level_sums(int64_t N, const double* __restrict__ lam,
                                                     const double* __restrict__ lam_prev,
                                                     double* __restrict__ Q) {
@@ -490,6 +638,45 @@ hipError_t launch_prepend_one(int64_t B, int s, const double* Y, int64_t ldY, do
   const int64_t tot = B * (s + 1);
   hipLaunchKernelGGL(k_prepend_one, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, B, s,
                      Y, ldY, Y1);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_or_flags(int64_t n, uint8_t* __restrict__ dst,
+                                                  const uint8_t* __restrict__ src) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] |= src[i];
+}
+
+hipError_t launch_or_flags(int64_t n, uint8_t* dst, const uint8_t* src, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_or_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, dst, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_sin(int n, int kmax, double* S, hipStream_t st) {
+  const int64_t tot = (int64_t)kmax * (3 * n + 2);
+  hipLaunchKernelGGL(k_sep_sin, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, kmax, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_separable(int64_t B, int n, int s, int kx, int ky, const double* Y,
+                                   int64_t ldY, const double* c, const int* cell_start,
+                                   const int* cell_term, const double* S, double* U, double a0,
+                                   double* out, float* out32, int64_t ldo, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  if (n < 64 || (n & 63) || kx < 1 || ky < 1 || kx > kSepMaxK || kx * ky > kSepMaxCells ||
+      ldo < 2 * (int64_t)(n + 2) * n)
+    return hipErrorInvalidValue;
+  const int M = 3 * n + 2;
+  hipLaunchKernelGGL(k_sep_rows, dim3((unsigned)((M + 63) / 64), (unsigned)B), dim3(256), 0, st, n,
+                     s, kx, ky, Y, ldY, c, cell_start, cell_term, S, U);
+  const int tiles = (n / 64) * ((n + 2 + 15) / 16);
+  const int64_t Bp = (B + 7) / 8 * 8;
+  const size_t lds = (size_t)(3 * 64 + 52) * kx * sizeof(double);
+  hipLaunchKernelGGL(k_sep_weights, dim3((unsigned)(Bp * tiles)), dim3(256), lds, st, B, n, kx,
+                     tiles, U, S, a0, out, out32, ldo);
+  hipLaunchKernelGGL(k_sep_alias, dim3((unsigned)((n - 1 + 255) / 256), (unsigned)B), dim3(256), 0,
+                     st, B, n, kx, U, S, a0, out, out32, ldo);
   return hipGetLastError();
 }
 

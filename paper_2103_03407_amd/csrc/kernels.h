@@ -197,6 +197,20 @@ hipError_t launch_phi_reaction_padded(int n, int rows, const double* phi_el, dou
 hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t ldY,
                          const double* phi, double a0, double* out, float* out32,
                          hipStream_t st, int64_t ldo = 0);
+// The separable expansion of a Problem 1 table (terms c_j sin(pi k1_j x1)
+// sin(pi k2_j x2)): S [kmax x (3n+2)] the sines on the grid of thirds
+// (launch_sep_sin once per mesh); cells of the kx x ky box of (k1, k2) in CSR
+// (cell_start [kx ky + 1], cell_term: the term indices of each cell, in order);
+// U scratch [B x (3n+2) x kx].  Writes the padded [WX | WY] of B samples at
+// out[b * ldo ...] (and out32), equal to launch_expand with the padded edge
+// table up to rounding.  n a multiple of 64, kx <= 64, kx ky <= 1024.
+hipError_t launch_sep_sin(int n, int kmax, double* S, hipStream_t st);
+// dst[i] |= src[i], i < n
+hipError_t launch_or_flags(int64_t n, uint8_t* dst, const uint8_t* src, hipStream_t st);
+hipError_t launch_expand_separable(int64_t B, int n, int s, int kx, int ky, const double* Y,
+                                   int64_t ldY, const double* c, const int* cell_start,
+                                   const int* cell_term, const double* S, double* U, double a0,
+                                   double* out, float* out32, int64_t ldo, hipStream_t st);
 // Y1[b] = (1, Y[b][0 .. s)): the points with the leading 1 that selects the
 // background row of a Problem 2 table
 hipError_t launch_prepend_one(int64_t B, int s, const double* Y, int64_t ldY, double* Y1,
