@@ -113,7 +113,14 @@ void mlqmc_default_opts(mlqmc_opts* opt);
 
 /* Creates a context on HIP device `device`, enqueueing on `hip_stream`
  * (a hipStream_t; NULL = the device's null stream).  Validates and copies
- * the coefficient family. */
+ * the coefficient family.  MLQMC_EDEVICE if the device does not exist.
+ *
+ * device = MLQMC_HOST_ONLY makes a host-only context: nothing touches a
+ * device, and every call on it checks its arguments as on a device context,
+ * returning MLQMC_EINVAL for invalid ones and MLQMC_EDEVICE (nothing written)
+ * for valid ones.  It never computes; it exists so that argument checking can
+ * be exercised on a machine without a GPU. */
+#define MLQMC_HOST_ONLY (-1)
 mlqmc_status mlqmc_create(mlqmc_ctx** out, const mlqmc_coeff* coeff, int device,
                           void* hip_stream);
 /* Problem 2 of the numerical section (the domain with four interior islands

@@ -6,7 +6,7 @@ behind the C ABI of ``include/mlqmc.h``); this package is its ctypes binding.
 
 from .binding import (  # noqa: F401
     Context, Level, Opts, Islands, MlqmcError, default_opts, load, EXPORTS,
-    MLQMC_OK, MLQMC_EINVAL, MLQMC_ENOMEM, MLQMC_EDEVICE, MLQMC_ENOCONV,
+    MLQMC_OK, MLQMC_EINVAL, MLQMC_ENOMEM, MLQMC_EDEVICE, MLQMC_ENOCONV, MLQMC_HOST_ONLY,
     MLQMC_FP64, MLQMC_MIXED,
     FLAG_RQ_NOCONV, FLAG_LIN_NOCONV, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_WRONG_PAIR,
     K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE, K_PRE, K_TG_LDS,

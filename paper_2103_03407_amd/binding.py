@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmlqmc.so")
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
 MLQMC_OK, MLQMC_EINVAL, MLQMC_ENOMEM, MLQMC_EDEVICE, MLQMC_ENOCONV = 0, -1, -2, -3, -4
+MLQMC_HOST_ONLY = -1  # device id of a host-only context (argument checks, no compute)
 MLQMC_FP64, MLQMC_MIXED = 0, 1
 FLAG_RQ_NOCONV, FLAG_LIN_NOCONV, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_WRONG_PAIR = 1, 2, 4, 8, 16
 K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE, K_PRE, K_TG_LDS = 0, 1, 2, 3, 4, 5, 6
@@ -215,7 +216,7 @@ class Context:
             c = np.ascontiguousarray(family["c"], dtype=np.float64)
             cf = Coeff(int(c.size), float(family["a0"]), c.ctypes.data_as(dp),
                        k1.ctypes.data_as(ip), k2.ctypes.data_as(ip))
-        if stream is None:
+        if stream is None and device != MLQMC_HOST_ONLY:
             try:
                 import torch
                 if torch.cuda.is_available():

@@ -96,6 +96,7 @@ hipError_t scratch_address(int device, void** out) {
 
 struct mlqmc_ctx {
   int device = 0;
+  bool host_only = false;  // created with MLQMC_HOST_ONLY: validates, never computes
   hipStream_t stream = nullptr;
   // captured PCG iterations (graph replay): one entry per fine-solve tag,
   // valid while every argument baked into it (the key) is unchanged
@@ -214,6 +215,13 @@ struct mlqmc_ctx {
   }
   mlqmc_status hip_fail(hipError_t e, const char* what) {
     return fail(MLQMC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  }
+  // makes the context's device current for a call whose arguments passed
+  mlqmc_status bind() {
+    if (host_only)
+      return fail(MLQMC_EDEVICE, "host-only context: the arguments are valid; no device to run on");
+    hipError_t e = hipSetDevice(device);
+    return e == hipSuccess ? MLQMC_OK : hip_fail(e, "set device");
   }
 
   mlqmc_status carve(const char* name, size_t bytes, void** out) {
@@ -1151,6 +1159,25 @@ bool finite_host(const double* x, size_t n) {
 
 }  // namespace
 
+namespace {
+// checks that `device` exists and makes it current (context creation)
+mlqmc_status bind_new_device(int device) {
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || device < 0 || device >= ndev) {
+    g_create_error = std::string("no HIP device ") + std::to_string(device) +
+                     (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
+    return MLQMC_EDEVICE;
+  }
+  e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+    return MLQMC_EDEVICE;
+  }
+  return MLQMC_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void mlqmc_default_opts(mlqmc_opts* o) {
@@ -1196,23 +1223,14 @@ mlqmc_status mlqmc_create(mlqmc_ctx** out, const mlqmc_coeff* cf, int device, vo
     g_create_error = "a0 - 0.5 sum |c_j| <= 0: the coefficient is not uniformly positive";
     return MLQMC_EINVAL;
   }
-  int ndev = 0;
-  hipError_t e = hipGetDeviceCount(&ndev);
-  if (e != hipSuccess || device < 0 || device >= ndev) {
-    g_create_error = std::string("no HIP device ") + std::to_string(device) +
-                     (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
-    return MLQMC_EDEVICE;
-  }
-  e = hipSetDevice(device);
-  if (e != hipSuccess) {
-    g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
-    return MLQMC_EDEVICE;
-  }
+  const bool host_only = device == MLQMC_HOST_ONLY;
+  if (!host_only) CS(bind_new_device(device));
   mlqmc_ctx* ctx = new mlqmc_ctx();
   ctx->device = device;
+  ctx->host_only = host_only;
   ctx->stream = static_cast<hipStream_t>(stream);
   // the no-allocation entry point's scratch on this device (device current)
-  ctx->scratch_err = scratch_address(device, &ctx->scratch_base);
+  if (!host_only) ctx->scratch_err = scratch_address(device, &ctx->scratch_base);
   ctx->s_max = cf->s_max;
   ctx->a0 = cf->a0;
   const int sm = std::max(cf->s_max, 1);
@@ -1225,7 +1243,11 @@ mlqmc_status mlqmc_create(mlqmc_ctx** out, const mlqmc_coeff* cf, int device, vo
   }
   ctx->h_k1.assign(k1.begin(), k1.begin() + cf->s_max);
   ctx->h_k2.assign(k2.begin(), k2.begin() + cf->s_max);
-  e = hipMalloc(&ctx->d_c, sm * sizeof(double));
+  if (host_only) {
+    *out = ctx;
+    return MLQMC_OK;
+  }
+  hipError_t e = hipMalloc(&ctx->d_c, sm * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&ctx->d_k1, sm * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&ctx->d_k2, sm * sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(ctx->d_c, c.data(), sm * sizeof(double), hipMemcpyHostToDevice);
@@ -1277,23 +1299,14 @@ mlqmc_status mlqmc_create_islands(mlqmc_ctx** out, const mlqmc_islands* cf, int 
     g_create_error = "the reaction coefficient can be negative on a region";
     return MLQMC_EINVAL;
   }
-  int ndev = 0;
-  hipError_t e = hipGetDeviceCount(&ndev);
-  if (e != hipSuccess || device < 0 || device >= ndev) {
-    g_create_error = std::string("no HIP device ") + std::to_string(device) +
-                     (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
-    return MLQMC_EDEVICE;
-  }
-  e = hipSetDevice(device);
-  if (e != hipSuccess) {
-    g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
-    return MLQMC_EDEVICE;
-  }
+  const bool host_only = device == MLQMC_HOST_ONLY;
+  if (!host_only) CS(bind_new_device(device));
   mlqmc_ctx* ctx = new mlqmc_ctx();
   ctx->device = device;
+  ctx->host_only = host_only;
   ctx->stream = static_cast<hipStream_t>(stream);
   // the no-allocation entry point's scratch on this device (device current)
-  ctx->scratch_err = scratch_address(device, &ctx->scratch_base);
+  if (!host_only) ctx->scratch_err = scratch_address(device, &ctx->scratch_base);
   ctx->s_max = cf->s_max;
   ctx->islands = true;
   ctx->a_in = cf->a0_in;
@@ -1311,7 +1324,11 @@ mlqmc_status mlqmc_create_islands(mlqmc_ctx** out, const mlqmc_islands* cf, int 
     rg[j] = cf->region[j];
   }
   const size_t bd = sm * sizeof(double), bi = sm * sizeof(int);
-  e = hipMalloc(&ctx->d_c, bd);
+  if (host_only) {
+    *out = ctx;
+    return MLQMC_OK;
+  }
+  hipError_t e = hipMalloc(&ctx->d_c, bd);
   if (e == hipSuccess) e = hipMalloc(&ctx->d_cb, bd);
   if (e == hipSuccess) e = hipMalloc(&ctx->d_k1, bi);
   if (e == hipSuccess) e = hipMalloc(&ctx->d_k2, bi);
@@ -1332,6 +1349,10 @@ mlqmc_status mlqmc_create_islands(mlqmc_ctx** out, const mlqmc_islands* cf, int 
 
 void mlqmc_destroy(mlqmc_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->host_only) {  // holds host memory only
+    delete ctx;
+    return;
+  }
   // teardown: errors here have nowhere to go, and every release is attempted
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
@@ -1378,7 +1399,7 @@ mlqmc_status lattice_entry(mlqmc_ctx* ctx, int64_t N, int32_t s, const int64_t* 
     if (!(shift[j] >= 0.0 && shift[j] < 1.0))
       return ctx->fail(MLQMC_EINVAL, "shift[%d] outside [0, 1)", j);
   }
-  CK(hipSetDevice(ctx->device), "set device");
+  CS(ctx->bind());
   const int64_t* dz;
   const double* dsh;
   double* dY;
@@ -1415,7 +1436,7 @@ mlqmc_status mlqmc_coefficient(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B, 
   if (B < 0 || (B > 0 && (!aK || (s > 0 && !Y)))) return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
   if (!on_dev && B * s > 0 && !finite_host(Y, (size_t)(B * s)))
     return ctx->fail(MLQMC_EINVAL, "Y has non-finite entries");
-  CK(hipSetDevice(ctx->device), "set device");
+  CS(ctx->bind());
   Table* tb = nullptr;
   CS(ctx->table(n, s, &tb));
   const double* dY;
@@ -1437,7 +1458,7 @@ mlqmc_status mlqmc_apply_operator(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t 
   if (ctx->islands) return ctx->fail(MLQMC_EINVAL, "mlqmc_apply_operator covers Problem 1 only");
   if (B < 0 || (B > 0 && (!sigma || !x || !out || (s > 0 && !Y))))
     return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
-  CK(hipSetDevice(ctx->device), "set device");
+  CS(ctx->bind());
   Table* tb = nullptr;
   CS(ctx->table(n, s, &tb));
   const int64_t D = (int64_t)(n - 1) * (n - 1), EW = 2LL * (n - 1) * n;
@@ -1460,7 +1481,7 @@ mlqmc_status mlqmc_prolong(mlqmc_ctx* ctx, int32_t nH, int32_t nh, int64_t B, co
   if (!is_pow2(nH) || !is_pow2(nh) || nH < 2 || nh < nH || nh > 4096)
     return ctx->fail(MLQMC_EINVAL, "need powers of two 2 <= nH <= nh <= 4096");
   if (B < 0 || (B > 0 && (!uH || !uh))) return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
-  CK(hipSetDevice(ctx->device), "set device");
+  CS(ctx->bind());
   const int64_t DH = (int64_t)(nH - 1) * (nH - 1), Dh = (int64_t)(nh - 1) * (nh - 1);
   const double* du;
   double* dv;
@@ -1487,7 +1508,7 @@ mlqmc_status mlqmc_eig_level(mlqmc_ctx* ctx, const mlqmc_level* L, const mlqmc_o
   if (!dev && n * s > 0 && !finite_host(Y, (size_t)(n * s)))
     return ctx->fail(MLQMC_EINVAL, "Y has non-finite entries");
   ctx->mem_cap = o->device_mem_cap;
-  CK(hipSetDevice(ctx->device), "set device");
+  CS(ctx->bind());
   if (n == 0) return MLQMC_OK;
   const double* dY;
   double *dl, *dlp = nullptr, *dlc = nullptr;
@@ -1576,10 +1597,10 @@ mlqmc_status mlqmc_eig_level_noalloc(mlqmc_ctx* ctx, const mlqmc_level* L, const
     return ctx->fail(MLQMC_EINVAL, "this call needs %zu bytes of scratch; the maximum is %zu "
                                    "(MLQMC_NOALLOC_SCRATCH_BYTES)",
                      need, (size_t)MLQMC_NOALLOC_SCRATCH_BYTES);
+  CS(ctx->bind());
   if (!ctx->scratch_base)
     return ctx->hip_fail(ctx->scratch_err != hipSuccess ? ctx->scratch_err : hipErrorInvalidValue,
                          "address of the no-allocation scratch");
-  CK(hipSetDevice(ctx->device), "set device");
   if (n == 0) return MLQMC_OK;
   // every named buffer and table of this call comes from the scratch
   struct Arena {
@@ -1630,7 +1651,7 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
     soff += (int64_t)R * s;
   }
   ctx->mem_cap = o->device_mem_cap;
-  CK(hipSetDevice(ctx->device), "set device");
+  CS(ctx->bind());
   hipStream_t st = ctx->stream;
   const int dev = o->io_on_device;
   double *dQ, *dQh, *dV, *dest;
@@ -1764,23 +1785,12 @@ mlqmc_status mlqmc_estimate(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, c
   return flagged ? ctx->fail(MLQMC_ENOCONV, "at least one sample is flagged") : MLQMC_OK;
 }
 
-namespace {
-// The nested estimator over the points [Nd[l], N[l]) of each level (Nd =
-// nullptr: none done), added to running per-(level, shift) sums of Y_l on the
-// device (dsum [nl x R]; dgsum the same for G, when g_stats is requested).
-// The embedded rule makes the points independent of N (point k is the lattice
-// point phi_2(k) z + shift for every rule size above k), so an estimate over
-// N points continues to any larger N.  Level l is evaluated on [e_l, N[l]),
-// e_l = min(Nd[l], Nd[l+1]): its own new points and those where level l+1
-// needs lambda^l; level 0 provides the coarse pairs on [min_l Nd[l], N[0]).
-mlqmc_status nested_core(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, const int64_t* Nd,
-                         const int64_t* N, int32_t R, const int64_t* z, const double* shifts,
-                         const mlqmc_opts* o, double* dsum, double* dgsum, double* Q_lr,
-                         double* Qhat, double* V, double* est, double* lam_out,
-                         double* g_stats) {
+// The levels, sizes and inputs of a nested estimate (host arrays): level 0
+// direct, every coarse pair level 0's, each previous term the level below's
+// value, N non-increasing and powers of two, 0 <= N_done <= N.
+mlqmc_status check_nested(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, const int64_t* Nd,
+                          const int64_t* N, int32_t R, const int64_t* z, const double* shifts) {
   int s_max = 0;
-  int64_t total = 0;
-  std::vector<int64_t> a(nl), e(nl);
   for (int l = 0; l < nl; ++l) {
     CS(check_level(ctx, &lv[l]));
     CS(check_islands_level(ctx, &lv[l]));
@@ -1789,11 +1799,9 @@ mlqmc_status nested_core(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, cons
     if (l > 0 && N[l] > N[l - 1])
       return ctx->fail(MLQMC_EINVAL, "N must not increase with the level (N[%d] > N[%d])", l,
                        l - 1);
-    a[l] = Nd ? Nd[l] : 0;
-    if (a[l] < 0 || a[l] > N[l])
-      return ctx->fail(MLQMC_EINVAL, "N_done[%d] outside [0, N[%d]]", l, l);
+    const int64_t d = Nd ? Nd[l] : 0;
+    if (d < 0 || d > N[l]) return ctx->fail(MLQMC_EINVAL, "N_done[%d] outside [0, N[%d]]", l, l);
     s_max = std::max(s_max, (int)lv[l].s_fine);
-    total += (int64_t)R * N[l];
   }
   const mlqmc_level& L0 = lv[0];
   if (L0.n_coarse != 0 || L0.n_prev != 0)
@@ -1813,6 +1821,34 @@ mlqmc_status nested_core(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, cons
   for (int64_t k = 0; k < (int64_t)R * s_max; ++k)
     if (!(shifts[k] >= 0.0 && shifts[k] < 1.0))
       return ctx->fail(MLQMC_EINVAL, "shift entry %lld outside [0, 1)", (long long)k);
+  return MLQMC_OK;
+}
+
+
+namespace {
+// The nested estimator over the points [Nd[l], N[l]) of each level (Nd =
+// nullptr: none done), added to running per-(level, shift) sums of Y_l on the
+// device (dsum [nl x R]; dgsum the same for G, when g_stats is requested).
+// The embedded rule makes the points independent of N (point k is the lattice
+// point phi_2(k) z + shift for every rule size above k), so an estimate over
+// N points continues to any larger N.  Level l is evaluated on [e_l, N[l]),
+// e_l = min(Nd[l], Nd[l+1]): its own new points and those where level l+1
+// needs lambda^l; level 0 provides the coarse pairs on [min_l Nd[l], N[0]).
+mlqmc_status nested_core(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level* lv, const int64_t* Nd,
+                         const int64_t* N, int32_t R, const int64_t* z, const double* shifts,
+                         const mlqmc_opts* o, double* dsum, double* dgsum, double* Q_lr,
+                         double* Qhat, double* V, double* est, double* lam_out,
+                         double* g_stats) {
+  CS(check_nested(ctx, nl, lv, Nd, N, R, z, shifts));
+  const mlqmc_level& L0 = lv[0];
+  int s_max = 0;
+  int64_t total = 0;
+  std::vector<int64_t> a(nl), e(nl);
+  for (int l = 0; l < nl; ++l) {
+    a[l] = Nd ? Nd[l] : 0;
+    s_max = std::max(s_max, (int)lv[l].s_fine);
+    total += (int64_t)R * N[l];
+  }
   // Level l is evaluated on [e_l, f_l): its own new points [a_l, N_l) and the
   // points [a_{l+1}, N_{l+1}) where level l+1 needs lambda^l; level 0 on the
   // union of the non-empty ranges (it supplies every level's coarse pairs).
@@ -1997,8 +2033,9 @@ mlqmc_status mlqmc_estimate_nested(mlqmc_ctx* ctx, int32_t nl, const mlqmc_level
   if (nl < 1 || !lv || !N || !z || !shifts || R < 1)
     return ctx->fail(MLQMC_EINVAL, "need n_levels >= 1, R >= 1 and non-NULL inputs");
   if (!Q_lr || !Qhat || !V || !est) return ctx->fail(MLQMC_EINVAL, "NULL output");
+  CS(check_nested(ctx, nl, lv, nullptr, N, R, z, shifts));
   ctx->mem_cap = o->device_mem_cap;
-  CK(hipSetDevice(ctx->device), "set device");
+  CS(ctx->bind());
   double *dsum = nullptr, *dgsum = nullptr;
   CS(ctx->getT("e_sum", (size_t)nl * R, &dsum));
   CK(hipMemsetAsync(dsum, 0, (size_t)nl * R * sizeof(double), ctx->stream), "memset");
@@ -2023,8 +2060,9 @@ mlqmc_status mlqmc_estimate_nested_extend(mlqmc_ctx* ctx, int32_t nl, const mlqm
   if (!Q_lr || !Qhat || !V || !est) return ctx->fail(MLQMC_EINVAL, "NULL output");
   if ((g_sums == nullptr) != (g_stats == nullptr))
     return ctx->fail(MLQMC_EINVAL, "g_sums and g_stats go together");
+  CS(check_nested(ctx, nl, lv, N_done, N, R, z, shifts));
   ctx->mem_cap = o->device_mem_cap;
-  CK(hipSetDevice(ctx->device), "set device");
+  CS(ctx->bind());
   const int dev = o->io_on_device;
   const size_t n = (size_t)nl * R;
   const hipMemcpyKind in = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -2126,7 +2164,12 @@ mlqmc_status mlqmc_estimate_adaptive(mlqmc_ctx* ctx, int32_t max_levels, const m
       for (int j = 0; j < s_l; ++j) sh_l[(size_t)r * s_l + j] = shifts[(size_t)r * s_all + j];
     return sh_l.data();
   };
-  CK(hipSetDevice(ctx->device), "set device");
+  {
+    // every hierarchy the rule may reach is a prefix of a valid nested level list
+    const std::vector<int64_t> Nchk(max_levels, ao->N_init);
+    CS(check_nested(ctx, max_levels, lv, nullptr, Nchk.data(), R, z, shifts));
+  }
+  CS(ctx->bind());
   ctx->mem_cap = o->device_mem_cap;
   double* dsum = nullptr;
   CS(ctx->getT("a_sum", (size_t)max_levels * R, &dsum));
@@ -2220,7 +2263,7 @@ mlqmc_status mlqmc_set_timing(mlqmc_ctx* ctx, int32_t cls) {
 mlqmc_status mlqmc_get_timing(mlqmc_ctx* ctx, int64_t* launches, double* total_ms,
                               double* model_bytes, double* model_flops) {
   if (!ctx) return MLQMC_EINVAL;
-  CK(hipSetDevice(ctx->device), "set device");
+  CS(ctx->bind());
   CS(ctx->sync("timing"));
   if (launches) *launches = ctx->t_launches;
   if (total_ms) *total_ms = ctx->t_ms;
