@@ -631,17 +631,18 @@ def roofline(ctx, m, w, opts, prec: str, kernel_class: str, leg, cfg: int):
                         "bytes_per_launch": lds_bytes}}
     if kernel_class == "coeff":
         # the coefficient expansion: the product the library formed (the dense
-        # Y Phi on FP64 MFMA, 2 s E flops per sample, or the separable one on
-        # the FP64 vector units), flops from the library's model
+        # Y Phi, 2 s E flops per sample, or the separable one, 8 kx per
+        # weight pair plus the row sums), both on FP64 MFMA; flops from the
+        # library's model
         flops_per_launch = leg["kflops"] / launches
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
         fam = w.family()
         dense = w.problem == 2 or not all(
             4 * int(max(fam["k1"][:lv.s_fine])) < lv.s_fine for lv in w.levels if lv.n_coarse)
-        peak = PEAK_FP64_MFMA_TFS if dense else PEAK_FP64_VALU_TFS
+        peak = PEAK_FP64_MFMA_TFS
         if not dense:
-            kname = "k_sep_weights+k_sep_rows+k_sep_alias"
-        return {"bound": "mfma" if dense else "alu", "kernel": kname,
+            kname = "k_sep_mfma+k_sep_rows+k_sep_alias"
+        return {"bound": "mfma", "kernel": kname,
                 "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4),
                 "traffic": _traffic(kname, prec, cfg), "avg_launch_us": round(avg_ms * 1e3, 2),

@@ -152,8 +152,8 @@ typedef struct {
  * [WX | WY | RX | RY | RD] from two coefficient products), in either
  * precision; meshes are multiples of 1/8 so that the islands' edges are mesh
  * lines.  The level and estimator calls return MLQMC_EINVAL for other meshes,
- * and mlqmc_coefficient / mlqmc_apply_operator for any call (they cover
- * Problem 1). */
+ * and mlqmc_coefficient / mlqmc_apply_operator / mlqmc_edge_weights for any
+ * call (they cover Problem 1). */
 mlqmc_status mlqmc_create_islands(mlqmc_ctx** out, const mlqmc_islands* cf, int device,
                                   void* hip_stream);
 /* Frees everything the context allocated.  NULL-safe. */
@@ -195,6 +195,23 @@ mlqmc_status mlqmc_coefficient(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B,
 mlqmc_status mlqmc_apply_operator(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B,
                                   const double* Y, const double* sigma, const double* x,
                                   double* out, int32_t io_on_device);
+
+/* Edge weights of the fine-mesh solves (eq. coeff at the element centroids,
+ * the quadrature of section 4.2; on these right-isosceles elements a
+ * horizontal or vertical edge couples its two nodes in the stiffness matrix
+ * of section 2.3 with the mean of a over the two elements sharing it, and
+ * hypotenuses do not couple).  For B points Y [B x s] (row stride s), out
+ * [B x 2 (n+2) n] receives the padded [WX | WY] blocks the batched kernels
+ * read: WX[j n + i] the edge arriving at node (i, j) from the west
+ * (i, j = 1..n-1), column 0 of row j + 1 the edge from node (n-1, j) into the
+ * right boundary (j = 1..n-1), WY[j n + i] the edge arriving from the south
+ * (i = 1..n-1, j = 1..n), every other entry a0.  Formed as those solves form
+ * them for this family and truncation: the separable product (sums over k1
+ * and k2 of the sine pairs) when it is cheaper, else the table product.
+ * Problem 1 only; n a power of two in [64, 1024]; host or device memory as
+ * on_dev.  MLQMC_EINVAL for other arguments (nothing written). */
+mlqmc_status mlqmc_edge_weights(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B,
+                                const double* Y, double* out, int32_t on_dev);
 
 /* P1 interpolation from mesh 1/nH to mesh 1/nh (nh a multiple of nH; section 3):
  * uh[b] = values at the fine interior nodes of the coarse P1 function uH[b]. */

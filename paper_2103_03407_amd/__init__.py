@@ -11,7 +11,8 @@ from .binding import (  # noqa: F401
     FLAG_RQ_NOCONV, FLAG_LIN_NOCONV, FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_WRONG_PAIR,
     K_NONE, K_COEFF, K_APPLY, K_SMOOTH, K_COARSE, K_PRE, K_TG_LDS,
     mlqmc_create, mlqmc_create_islands, mlqmc_destroy, mlqmc_last_error, mlqmc_default_opts,
-    mlqmc_lattice_points, mlqmc_coefficient, mlqmc_apply_operator, mlqmc_prolong,
+    mlqmc_lattice_points, mlqmc_coefficient, mlqmc_apply_operator, mlqmc_edge_weights,
+    mlqmc_prolong,
     mlqmc_eig_level, mlqmc_eig_level_noalloc, mlqmc_estimate, mlqmc_set_tuning, mlqmc_set_timing, mlqmc_get_timing,
     mlqmc_embedded_points, mlqmc_estimate_nested, mlqmc_estimate_nested_extend,
     mlqmc_adaptive_decide, mlqmc_estimate_adaptive, AdaptiveOpts,

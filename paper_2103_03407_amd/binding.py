@@ -29,8 +29,8 @@ EXPORTS = [
     "mlqmc_default_opts", "mlqmc_create", "mlqmc_create_islands", "mlqmc_destroy",
     "mlqmc_last_error",
     "mlqmc_lattice_points", "mlqmc_embedded_points", "mlqmc_coefficient",
-    "mlqmc_apply_operator", "mlqmc_prolong", "mlqmc_eig_level", "mlqmc_eig_level_noalloc",
-    "mlqmc_estimate",
+    "mlqmc_apply_operator", "mlqmc_edge_weights", "mlqmc_prolong", "mlqmc_eig_level",
+    "mlqmc_eig_level_noalloc", "mlqmc_estimate",
     "mlqmc_estimate_nested", "mlqmc_estimate_nested_extend", "mlqmc_adaptive_decide",
     "mlqmc_estimate_adaptive", "mlqmc_set_tuning",
     "mlqmc_set_timing", "mlqmc_get_timing",
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlqmc_embedded_points.argtypes = [P, I64, I32, P, P, I64, I64, P, I32]
     lib.mlqmc_coefficient.argtypes = [P, I32, I32, I64, P, P, I32]
     lib.mlqmc_apply_operator.argtypes = [P, I32, I32, I64, P, P, P, P, I32]
+    lib.mlqmc_edge_weights.argtypes = [P, I32, I32, I64, P, P, I32]
     lib.mlqmc_prolong.argtypes = [P, I32, I32, I64, P, P, I32]
     lib.mlqmc_eig_level.argtypes = [P, C.POINTER(Level), C.POINTER(Opts), I64, P, I32, P, P, P,
                                     P, P, P, P, P]
@@ -133,7 +134,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlqmc_get_timing.argtypes = [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D),
                                      C.POINTER(D)]
     for name in ("mlqmc_create", "mlqmc_create_islands", "mlqmc_lattice_points",
-                 "mlqmc_embedded_points", "mlqmc_coefficient", "mlqmc_apply_operator", "mlqmc_prolong",
+                 "mlqmc_embedded_points", "mlqmc_coefficient", "mlqmc_apply_operator",
+                 "mlqmc_edge_weights", "mlqmc_prolong",
                  "mlqmc_eig_level", "mlqmc_eig_level_noalloc", "mlqmc_estimate",
                  "mlqmc_estimate_nested",
                  "mlqmc_estimate_nested_extend", "mlqmc_estimate_adaptive",
@@ -306,6 +308,13 @@ class Context:
         B = x.shape[0]
         return self._check(self._lib.mlqmc_apply_operator(
             self._h, int(n), int(s), int(B), py, ps, px, po, _one_side(dy, ds, dx, do)))
+
+    def edge_weights(self, n, s, Y, out):
+        """Padded [WX | WY] edge weights, out [B, 2 (n+2) n] (mlqmc_edge_weights)."""
+        py, dy = _ptr(Y, np.float64)
+        po, do = _ptr(out, np.float64)
+        return self._check(self._lib.mlqmc_edge_weights(self._h, int(n), int(s), int(out.shape[0]),
+                                                        py, po, _one_side(dy, do)))
 
     def prolong(self, nH, nh, uH, uh):
         pu, du = _ptr(uH, np.float64)
@@ -552,6 +561,10 @@ def mlqmc_coefficient(ctx, *a, **k):
 
 def mlqmc_apply_operator(ctx, *a, **k):
     return ctx.apply_operator(*a, **k)
+
+
+def mlqmc_edge_weights(ctx, *a, **k):
+    return ctx.edge_weights(*a, **k)
 
 
 def mlqmc_prolong(ctx, *a, **k):

@@ -1475,6 +1475,41 @@ mlqmc_status mlqmc_apply_operator(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t 
   return ctx->sync("apply");
 }
 
+mlqmc_status mlqmc_edge_weights(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B,
+                                const double* Y, double* w, int32_t on_dev) {
+  if (!ctx) return MLQMC_EINVAL;
+  if (!is_pow2(n) || n < 64 || n > 1024)
+    return ctx->fail(MLQMC_EINVAL, "n must be a power of two in [64, 1024]");
+  if (s < 0 || s > ctx->s_max) return ctx->fail(MLQMC_EINVAL, "s outside [0, s_max]");
+  if (ctx->islands) return ctx->fail(MLQMC_EINVAL, "mlqmc_edge_weights covers Problem 1 only");
+  if (B < 0 || (B > 0 && (!w || (s > 0 && !Y)))) return ctx->fail(MLQMC_EINVAL, "bad batch/buffers");
+  if (!on_dev && B * s > 0 && !finite_host(Y, (size_t)(B * s)))
+    return ctx->fail(MLQMC_EINVAL, "Y has non-finite entries");
+  CS(ctx->bind());
+  if (B == 0) return MLQMC_OK;
+  const int64_t EW = 2 * padded_size(n);
+  const double* dY = nullptr;
+  double* dw;
+  if (s > 0) CS(stage_in(ctx, "in_Y", Y, (size_t)(B * s), on_dev, &dY));
+  CS(out_buf(ctx, "out_w", w, (size_t)(B * EW), on_dev, &dw));
+  // the choice the fine-mesh solves make for this mesh and truncation
+  mlqmc_ctx::SepTable* sep = nullptr;
+  CS(ctx->sep_table(n, s, &sep));
+  if (sep) {
+    double* U;
+    CS(ctx->getT("ew_U", (size_t)B * (3 * n + 2) * sep->kx, &U));
+    CK(launch_expand_separable(B, n, s, sep->kx, sep->ky, dY, s, ctx->d_c, sep->cell_start,
+                               sep->cell_term, sep->S, U, ctx->a0, dw, nullptr, EW, ctx->stream),
+       "expand (separable)");
+  } else {
+    Table* tb = nullptr;
+    CS(ctx->table(n, s, &tb));
+    CK(launch_expand(B, s, EW, dY, s, tb->pad, ctx->a0, dw, nullptr, ctx->stream), "expand");
+  }
+  CS(stage_out(ctx, w, dw, (size_t)(B * EW), on_dev));
+  return ctx->sync("edge weights");
+}
+
 mlqmc_status mlqmc_prolong(mlqmc_ctx* ctx, int32_t nH, int32_t nh, int64_t B, const double* uH,
                            double* uh, int32_t on_dev) {
   if (!ctx) return MLQMC_EINVAL;

@@ -340,70 +340,96 @@ __global__ __launch_bounds__(256) void k_sep_rows(int n, int s, int kx, int ky,
   }
 }
 
-// Padded [WX | WY] of B samples from U (tiles of 64 columns x 16 rows; wave w
-// of a block owns rows r0 + 4w .. r0 + 4w + 3, lane = column).  Positions
-// that are not edges of interior nodes get a0, as in the table product; the
+// Padded [WX | WY] of B samples from U, as a batched matrix product on FP64
+// MFMA (v_mfma_f64_16x16x4f64): with rows j and columns i,
+//   WX = a0 + (U_{3j-1} S_{3i-2} + U_{3j+1} S_{3i-1}) / 2,
+//   WY = a0 + (U_{3j-2} S_{3i-1} + U_{3j-1} S_{3i+1}) / 2,
+// each a [rows x kx] x [kx x columns] product per sample.  A block (8 waves)
+// owns a 64 x 64 tile of both outputs of one sample: wave w the rows
+// j0 + 16 (w & 3) .. + 15 and columns i0 + 32 (w >> 2) .. + 31 (two 16 x 16
+// MFMA tiles of WX and two of WY).  K runs in chunks of kSmK terms staged in
+// LDS as [offset][p][row or column] (rows padded by 16 doubles so that the
+// four 16-lane groups of a fragment read fall on different banks); terms
+// p >= kx and rows m outside [0, 3n + 2) are zero.  Positions that are not
+// edges of interior nodes get a0, as in the table product; the
 // right-boundary aliases of WX (column 0, rows 2..n) come from k_sep_alias.
 constexpr int kSepMaxK = 64;
-__global__ __launch_bounds__(256) void k_sep_weights(int64_t B, int n, int kx, int tiles,
-                                                     const double* __restrict__ U,
-                                                     const double* __restrict__ S, double a0,
-                                                     double* __restrict__ out,
-                                                     float* __restrict__ out32, int64_t ldo) {
+constexpr int kSmT = 64, kSmK = 8, kSmLd = kSmT + 16;
+__global__ __launch_bounds__(512) void k_sep_mfma(int64_t B, int n, int kx, int tiles_i,
+                                                  int tiles, const double* __restrict__ U,
+                                                  const double* __restrict__ S, double a0,
+                                                  double* __restrict__ out,
+                                                  float* __restrict__ out32, int64_t ldo) {
+  __shared__ double sS[3][kSmK][kSmLd];
+  __shared__ double sU[3][kSmK][kSmLd];
   // XCD-aware: the tiles of one sample run on one XCD (block L on XCD L mod 8)
   const int64_t L = blockIdx.x;
   const int64_t q = L >> 3;
   const int64_t b = ((q / tiles) << 3) + (L & 7);
   if (b >= B) return;
   const int tile = (int)(q % tiles);
-  const int ct = n / 64;
-  const int c0 = (tile % ct) * 64, r0 = (tile / ct) * 16;
+  const int i0 = (tile % tiles_i) * kSmT, j0 = (tile / tiles_i) * kSmT;
   const int M = 3 * n + 2, P = (n + 2) * n;
-  // dynamic LDS: S at 3i-2, 3i-1, 3i+1 for the tile's columns [3][kx][64],
-  // then U at m = 3 r0 - 3 .. 3 r0 + 48 [52][kx]
-  extern __shared__ double sm_sep[];
-  double* sS = sm_sep;
-  double* sU = sm_sep + 3 * kx * 64;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int e = t; e < 3 * kx * 64; e += 256) {
-    const int o = e / (kx * 64), rem = e - o * kx * 64, p = rem / 64, cc = rem % 64;
-    const int m = 3 * (c0 + cc) + (o == 0 ? -2 : (o == 1 ? -1 : 1));
-    sS[e] = (m >= 0 && m < M) ? S[(int64_t)p * M + m] : 0.0;
-  }
-  const int mb = 3 * r0 - 3;
   const double* Ub = U + b * (int64_t)M * kx;
-  for (int e = t; e < 52 * kx; e += 256) {
-    const int m = mb + e / kx, p = e % kx;
-    sU[e] = (m >= 0 && m < M) ? Ub[(int64_t)m * kx + p] : 0.0;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  const int rw = (w & 3) * 16, cw = (w >> 2) * 32;
+  v4d ax[2], ay[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) ax[c] = ay[c] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int p0 = 0; p0 < kx; p0 += kSmK) {
+    // stage: S at m = 3i - 2, 3i - 1, 3i + 1 of the tile's columns; U rows
+    // m = 3j - 2, 3j - 1, 3j + 1 of its rows (p fastest in global memory)
+    for (int e = t; e < 3 * kSmK * kSmT; e += 512) {
+      const int o = e / (kSmK * kSmT), rem = e - o * (kSmK * kSmT);
+      const int off = o == 0 ? -2 : (o == 1 ? -1 : 1);
+      {
+        const int pp = rem / kSmT, c = rem - pp * kSmT, p = p0 + pp;
+        const int m = 3 * (i0 + c) + off;
+        sS[o][pp][c] = (p < kx && m >= 0 && m < M) ? S[(int64_t)p * M + m] : 0.0;
+      }
+      {
+        const int r = rem / kSmK, pp = rem - r * kSmK, p = p0 + pp;
+        const int m = 3 * (j0 + r) + off;
+        sU[o][pp][r] = (p < kx && m >= 0 && m < M) ? Ub[(int64_t)m * kx + p] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kSmK; kk += 4) {
+      // A[row][k] in lane row + 16 k; B[k][col] in lane col + 16 k
+      const double um2 = sU[0][kk + fk][rw + fr], um1 = sU[1][kk + fk][rw + fr],
+                   up1 = sU[2][kk + fk][rw + fr];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int col = cw + 16 * c + fr;
+        const double sa = sS[0][kk + fk][col], sb = sS[1][kk + fk][col],
+                     sc = sS[2][kk + fk][col];
+        ax[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(um1, sa, ax[c], 0, 0, 0);
+        ax[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(up1, sb, ax[c], 0, 0, 0);
+        ay[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(um2, sb, ay[c], 0, 0, 0);
+        ay[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(um1, sc, ay[c], 0, 0, 0);
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
-  const int jr = r0 + 4 * w;  // first of this wave's four rows
-  for (int p = 0; p < kx; ++p) {
-    const double sa = sS[p * 64 + lane], sb = sS[(kx + p) * 64 + lane],
-                 sc = sS[(2 * kx + p) * 64 + lane];
+  // D[row][col]: lane holds col = lane & 15 and, in its r-th value, row 4 r + (lane >> 4)
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int i = i0 + cw + 16 * c + fr;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int j = jr + r, u0 = 3 * j - mb;  // U row of m = 3j lives at u0
-      const double um2 = sU[(u0 - 2) * kx + p], um1 = sU[(u0 - 1) * kx + p],
-                   up1 = sU[(u0 + 1) * kx + p];
-      ax[r] += sa * um1 + sb * up1;
-      ay[r] += sb * um2 + sc * um1;
-    }
-  }
-  const int i = c0 + lane;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int j = jr + r;
-    if (j > n + 1) continue;
-    const double vx = (i >= 1 && j >= 1 && j <= n - 1) ? a0 + 0.5 * ax[r] : a0;
-    const double vy = (i >= 1 && j >= 1 && j <= n) ? a0 + 0.5 * ay[r] : a0;
-    const int64_t o = b * ldo + (int64_t)j * n + i;
-    out[o] = vx;
-    out[o + P] = vy;
-    if (out32) {
-      out32[o] = (float)vx;
-      out32[o + P] = (float)vy;
+      const int j = j0 + rw + 4 * r + fk;
+      if (j > n + 1) continue;
+      const double vx = (i >= 1 && j >= 1 && j <= n - 1) ? a0 + 0.5 * ax[c][r] : a0;
+      const double vy = (i >= 1 && j >= 1 && j <= n) ? a0 + 0.5 * ay[c][r] : a0;
+      const int64_t o = b * ldo + (int64_t)j * n + i;
+      out[o] = vx;
+      out[o + P] = vy;
+      if (out32) {
+        out32[o] = (float)vx;
+        out32[o + P] = (float)vy;
+      }
     }
   }
 }
@@ -670,11 +696,10 @@ hipError_t launch_expand_separable(int64_t B, int n, int s, int kx, int ky, cons
   const int M = 3 * n + 2;
   hipLaunchKernelGGL(k_sep_rows, dim3((unsigned)((M + 63) / 64), (unsigned)B), dim3(256), 0, st, n,
                      s, kx, ky, Y, ldY, c, cell_start, cell_term, S, U);
-  const int tiles = (n / 64) * ((n + 2 + 15) / 16);
+  const int tiles_i = n / kSmT, tiles = tiles_i * ((n + 2 + kSmT - 1) / kSmT);
   const int64_t Bp = (B + 7) / 8 * 8;
-  const size_t lds = (size_t)(3 * 64 + 52) * kx * sizeof(double);
-  hipLaunchKernelGGL(k_sep_weights, dim3((unsigned)(Bp * tiles)), dim3(256), lds, st, B, n, kx,
-                     tiles, U, S, a0, out, out32, ldo);
+  hipLaunchKernelGGL(k_sep_mfma, dim3((unsigned)(Bp * tiles)), dim3(512), 0, st, B, n, kx,
+                     tiles_i, tiles, U, S, a0, out, out32, ldo);
   hipLaunchKernelGGL(k_sep_alias, dim3((unsigned)((n - 1 + 255) / 256), (unsigned)B), dim3(256), 0,
                      st, B, n, kx, U, S, a0, out, out32, ldo);
   return hipGetLastError();

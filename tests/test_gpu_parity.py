@@ -80,6 +80,38 @@ def test_coefficient(ctx, fam, n, s, B):
         assert np.max(np.abs(a[b] - ref)) <= 1e-14 * np.max(np.abs(ref))
 
 
+# Edge weights of the batched fine-mesh solves, against the oracle's
+# assembled stiffness matrix with the boundary nodes kept: a horizontal or
+# vertical edge couples its nodes with minus its weight.  Both products the
+# library forms are covered: the separable one (4 kx < s) and the table one.
+@pytest.mark.parametrize("n,s,B", [(128, 16, 2), (64, 64, 3), (256, 256, 2), (1024, 512, 2)])
+def test_edge_weights(ctx, fam, n, s, B):
+    rng = np.random.default_rng(7 * n + s)
+    Y = rng.random((B, s)) - 0.5
+    P = (n + 2) * n
+    w = np.empty((B, 2 * P))
+    ctx.edge_weights(n, s, Y, w)
+    node = lambda i, j: j * (n + 1) + i  # noqa: E731
+    ii, jj = np.meshgrid(np.arange(1, n), np.arange(1, n), indexing="xy")
+    ii, jj = ii.ravel(), jj.ravel()
+    jy, iy = np.meshgrid(np.arange(1, n + 1), np.arange(1, n), indexing="ij")
+    jy, iy = jy.ravel(), iy.ravel()
+    jb = np.arange(1, n)
+    for b in range(B):
+        A = fem.stiffness(n, coeff.coefficient(n, Y[b], fam), full=True).tocsr()
+        ref = np.full(2 * P, float(fam["a0"]))
+        ref[jj * n + ii] = -np.asarray(A[node(ii - 1, jj), node(ii, jj)]).ravel()
+        ref[(jb + 1) * n] = -np.asarray(A[node(n - 1, jb), node(n, jb)]).ravel()
+        ref[P + jy * n + iy] = -np.asarray(A[node(iy, jy - 1), node(iy, jy)]).ravel()
+        assert np.max(np.abs(w[b] - ref)) <= 1e-13 * np.max(np.abs(ref)), b
+
+
+def test_edge_weights_cover_both_products(fam):
+    k1 = np.asarray(fam["k1"])
+    sep = [4 * int(k1[:s].max()) < s for s in (16, 64, 256, 512)]
+    assert sep == [False, True, True, True]
+
+
 # ---------------- a3: operator ----------------
 
 @pytest.mark.parametrize("n,s,B", [(2, 4, 2), (8, 16, 3), (64, 64, 4), (128, 8, 2)])
