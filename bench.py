@@ -640,12 +640,13 @@ def roofline(ctx, m, w, opts, prec: str, kernel_class: str, leg, cfg: int):
         dense = w.problem == 2 or not all(
             4 * int(max(fam["k1"][:lv.s_fine])) < lv.s_fine for lv in w.levels if lv.n_coarse)
         peak = PEAK_FP64_MFMA_TFS
+        tkey = kname
         if not dense:
-            kname = "k_sep_mfma+k_sep_rows+k_sep_alias"
+            kname, tkey = "k_sep_mfma+k_sep_rows+k_sep_alias", "k_sep"
         return {"bound": "mfma", "kernel": kname,
                 "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4),
-                "traffic": _traffic(kname, prec, cfg), "avg_launch_us": round(avg_ms * 1e3, 2),
+                "traffic": _traffic(tkey, prec, cfg), "avg_launch_us": round(avg_ms * 1e3, 2),
                 "launches": launches, "algorithmic_flops_per_launch": flops_per_launch,
                 "hbm_GBs": round(kbytes / launches / (avg_ms * 1e-3) / 1e9, 1)}
     bytes_per_launch = kbytes / launches
