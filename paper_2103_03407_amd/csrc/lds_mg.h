@@ -58,6 +58,21 @@ struct Mesh {
   for (int k = (n) + (int)threadIdx.x; k < (n) * (n); k += (NT)) \
     if ((k & ((n) - 1)) != 0)
 
+// Synchronisation between the steps of a V-cycle level: the workgroup, or
+// (kW) only the one wave that runs the coarsest levels by itself.  A wave's
+// LDS accesses complete in order, so there the fences only keep the compiler
+// from moving them across.
+template <bool kW>
+MLQMC_DEV void level_sync() {
+  if constexpr (kW) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // weight arrays per level: [WX | WY], or [WX | WY | RX | RY | RD] with reaction
 template <bool kR>
 constexpr int wblock() {
@@ -180,14 +195,14 @@ MLQMC_DEV void coarsen_all(const T* wx, const T* wy, T* nxt) {
 }
 
 // X = omega * B / diag  (first sweep from a zero start)
-template <int NT, int n, typename T, bool kR = false>
+template <int NT, int n, typename T, bool kR = false, bool kW = false>
 MLQMC_DEV void jacobi_first(const T* wx, const T* wy, const T* B, T* X, double om) {
   LDS_FOR_NODES(NT, n, k) X[k] = T(om) * B[k] / pdiag<n, T, kR>(wx, wy, k);
-  __syncthreads();
+  level_sync<kW>();
 }
 
 // X <- X + omega (B - A X) / diag, new values staged in registers
-template <int NT, int n, typename T, bool kR = false>
+template <int NT, int n, typename T, bool kR = false, bool kW = false>
 MLQMC_DEV void jacobi_sweep(const T* wx, const T* wy, const T* B, T* X, double om) {
   constexpr int PT = (n * n - n + NT - 1) / NT;
   T nv[PT];
@@ -200,13 +215,13 @@ MLQMC_DEV void jacobi_sweep(const T* wx, const T* wy, const T* B, T* X, double o
       nv[q] = X[k] + T(om) * (B[k] - ax) / d;
     }
   }
-  __syncthreads();
+  level_sync<kW>();
 #pragma unroll
   for (int q = 0; q < PT; ++q) {
     const int k = n + (int)threadIdx.x + q * NT;
     if (k < n * n && (k & (n - 1)) != 0) X[k] = nv[q];
   }
-  __syncthreads();
+  level_sync<kW>();
 }
 
 // Xout = Xin + omega (B - A Xin) / diag (two distinct arrays; for top levels
@@ -225,7 +240,7 @@ MLQMC_DEV void jacobi_to(const T* wx, const T* wy, const T* B, const T* Xin, T* 
 // Bc = P^T (B - A X): the residual at the seven fine nodes each coarse node's
 // hat function covers (weight 1 at the node, 1/2 at E, W, N, S, NE, SW, all
 // interior), formed on the fly, so no residual array is stored.
-template <int NT, int n, typename T, bool kR = false>
+template <int NT, int n, typename T, bool kR = false, bool kW = false>
 MLQMC_DEV void restrict_residual(const T* wx, const T* wy, const T* B, const T* X, T* Bc) {
   constexpr int nc = n / 2;
   auto res = [&](int k) {
@@ -238,32 +253,36 @@ MLQMC_DEV void restrict_residual(const T* wx, const T* wy, const T* B, const T* 
     Bc[kc] = res(f) + T(0.5) * (res(f - 1) + res(f + 1) + res(f - n) + res(f + n) +
                                 res(f + n + 1) + res(f - n - 1));
   }
-  __syncthreads();
+  level_sync<kW>();
 }
 
 // X += P Xc (2:1 P1 interpolation: the mean of the coarse values at
 // (i>>1, j>>1) and ((i+1)>>1, (j+1)>>1))
-template <int NT, int n, typename T>
+template <int NT, int n, typename T, bool kW = false>
 MLQMC_DEV void prolong_add(const T* Xc, T* X) {
   constexpr int nc = n / 2;
   LDS_FOR_NODES(NT, n, k) {
     const int i = k & (n - 1), j = k >> Mesh<n>::lg;
     X[k] += T(0.5) * (Xc[(j >> 1) * nc + (i >> 1)] + Xc[((j + 1) >> 1) * nc + ((i + 1) >> 1)]);
   }
-  __syncthreads();
+  level_sync<kW>();
 }
 
 // One V-cycle X = K^{-1} B on mesh n; `nxt` holds the coarser levels (weights
 // built by coarsen_all).  kStage: register-staged sweeps (false: the sweeps
 // alternate between X and Xtmp, for top levels in global scratch).  kSw: 2 or
 // 3 Jacobi sweeps per smoothing step with the Chebyshev weights of that
-// degree (3 needs kStage).
-template <int NT, int n, bool kStage = true, typename T, int kSw = 2, bool kR = false>
+// degree (3 needs kStage).  The levels of 1/8 and coarser (49 nodes or
+// fewer) run in the first wave alone (kW), with no workgroup barrier inside
+// them; the other waves wait at one barrier for their result.
+template <int NT, int n, bool kStage = true, typename T, int kSw = 2, bool kR = false,
+          bool kW = false>
 MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtmp = nullptr) {
   static_assert(kSw == 2 || (kSw == 3 && kStage), "3 sweeps need register staging");
+  static_assert(!kW || NT == 64, "a wave-local level runs on 64 threads");
   if constexpr (n == 2) {
     if (threadIdx.x == 0) X[3] = B[3] / pdiag<2, T, kR>(wx, wy, 3);
-    __syncthreads();
+    level_sync<kW>();
   } else {
     constexpr int nc = n / 2, Pc = Mesh<nc>::P;
     const T* wxc = nxt;
@@ -273,26 +292,31 @@ MLQMC_DEV void vcycle(const T* wx, const T* wy, const T* B, T* X, T* nxt, T* Xtm
     T* X2c = level_vectors(nc) == 3 ? Xc + Pc : nullptr;
     T* nxtc = Xc + (level_vectors(nc) - 1) * Pc;
     if constexpr (kSw == 3) {
-      jacobi_first<NT, n, T, kR>(wx, wy, B, X, kCheb3[0]);
-      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[1]);
-      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[2]);
+      jacobi_first<NT, n, T, kR, kW>(wx, wy, B, X, kCheb3[0]);
+      jacobi_sweep<NT, n, T, kR, kW>(wx, wy, B, X, kCheb3[1]);
+      jacobi_sweep<NT, n, T, kR, kW>(wx, wy, B, X, kCheb3[2]);
     } else if constexpr (kStage) {
-      jacobi_first<NT, n, T, kR>(wx, wy, B, X, kOmega1);
-      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kOmega2);
+      jacobi_first<NT, n, T, kR, kW>(wx, wy, B, X, kOmega1);
+      jacobi_sweep<NT, n, T, kR, kW>(wx, wy, B, X, kOmega2);
     } else {
       jacobi_first<NT, n, T, kR>(wx, wy, B, Xtmp, kOmega1);
       jacobi_to<NT, n, T, kR>(wx, wy, B, Xtmp, X, kOmega2);
     }
-    restrict_residual<NT, n, T, kR>(wx, wy, B, X, Bc);
-    vcycle<NT, nc, (nc <= 32), T, kSw, kR>(wxc, wyc, Bc, Xc, nxtc, X2c);
-    prolong_add<NT, n>(Xc, X);
+    restrict_residual<NT, n, T, kR, kW>(wx, wy, B, X, Bc);
+    if constexpr (!kW && NT > 64 && nc <= 8) {
+      if (threadIdx.x < 64) vcycle<64, nc, true, T, kSw, kR, true>(wxc, wyc, Bc, Xc, nxtc, X2c);
+      __syncthreads();
+    } else {
+      vcycle<NT, nc, (nc <= 32), T, kSw, kR, kW>(wxc, wyc, Bc, Xc, nxtc, X2c);
+    }
+    prolong_add<NT, n, T, kW>(Xc, X);
     if constexpr (kSw == 3) {
-      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[0]);
-      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[1]);
-      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kCheb3[2]);
+      jacobi_sweep<NT, n, T, kR, kW>(wx, wy, B, X, kCheb3[0]);
+      jacobi_sweep<NT, n, T, kR, kW>(wx, wy, B, X, kCheb3[1]);
+      jacobi_sweep<NT, n, T, kR, kW>(wx, wy, B, X, kCheb3[2]);
     } else if constexpr (kStage) {
-      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kOmega1);
-      jacobi_sweep<NT, n, T, kR>(wx, wy, B, X, kOmega2);
+      jacobi_sweep<NT, n, T, kR, kW>(wx, wy, B, X, kOmega1);
+      jacobi_sweep<NT, n, T, kR, kW>(wx, wy, B, X, kOmega2);
     } else {
       jacobi_to<NT, n, T, kR>(wx, wy, B, X, Xtmp, kOmega1);
       jacobi_to<NT, n, T, kR>(wx, wy, B, Xtmp, X, kOmega2);
