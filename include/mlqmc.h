@@ -96,7 +96,8 @@ typedef struct {
                                 value (default 1e-2) costs fewer inner steps in total */
   int32_t max_lin_iter;      /* cap on PCG iterations per linear solve */
   int32_t chain_len;         /* samples per warm-start chain (<=0: library default) */
-  int32_t batch;             /* samples per fine-solve batch (<=0: library default) */
+  int32_t batch;             /* samples per fine-solve batch (<=0: library default, up to
+                                96 GB of working arrays, split evenly) */
   int32_t pcg_graph;         /* 1: replay the batched PCG iterations from a captured HIP graph
                                 (cached per layout); 0: launch them one by one */
   int32_t io_on_device;      /* 1: device pointers, 0: host pointers */

@@ -644,6 +644,45 @@ __device__ __forceinline__ void fetch_row_inputs(T* dst, const T* rb, const T* w
     dst[10] = hm * rd[k + n + 1];
   }
 }
+// The same for the row after the one whose inputs are prev (which may be
+// dst itself), in the marching direction dir: the vertical edge the two rows
+// share (WY, and RY with the reaction) comes from prev instead of a second
+// read, which would come one row step later, after the rows of every
+// workgroup in flight on the XCD have passed through its L2.
+template <typename T, bool kR>
+__device__ __forceinline__ void fetch_row_inputs_next(T* dst, const T* prev, int dir,
+                                                      const T* rb, const T* wx, const T* wy,
+                                                      int k, int n, int P, T hm) {
+  const T shared = dir > 0 ? prev[4] : prev[3];
+  T rshared = T(0);
+  if constexpr (kR) rshared = dir > 0 ? prev[8] : prev[7];
+  dst[0] = rb[k];
+  dst[1] = wx[k];
+  dst[2] = wx[k + 1];
+  if (dir > 0) {
+    dst[3] = shared;
+    dst[4] = wy[k + n];
+  } else {
+    dst[3] = wy[k];
+    dst[4] = shared;
+  }
+  if constexpr (kR) {
+    const T* rx = wx + 2 * P;
+    const T* ry = wx + 3 * P;
+    const T* rd = wx + 4 * P;
+    dst[5] = hm * rx[k];
+    dst[6] = hm * rx[k + 1];
+    if (dir > 0) {
+      dst[7] = rshared;
+      dst[8] = hm * ry[k + n];
+    } else {
+      dst[7] = hm * ry[k];
+      dst[8] = rshared;
+    }
+    dst[9] = hm * rd[k];
+    dst[10] = hm * rd[k + n + 1];
+  }
+}
 // the diagonal of A [+ R] at a node from its row inputs
 template <typename T, bool kR>
 __device__ __forceinline__ T row_diag(const T* in) {
@@ -928,13 +967,27 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
       }
     }
   };
+  // With one column per thread the vertical edge a row shares with the
+  // previous one is carried over (in[1] after the shift holds that row's
+  // inputs); measured 7 % faster on 1/128, while with 2 or 4 columns per
+  // thread (1/512, 1/1024) the carry made the kernel 10 % slower.
+  bool have = false;
   auto fetch_in = [&](int j) {
-    if (!(j >= max(f0 - NS + 1, 1) && j <= min(f1 + NS - 2, n - 1))) return;
+    if (!(j >= max(f0 - NS + 1, 1) && j <= min(f1 + NS - 2, n - 1))) {
+      have = false;
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int c = t + q * NTC, k = j * n + c;
-      if (c >= 1) fetch_row_inputs<T, kR>(in[0][q], rb, wx, wy, k, n, g.P, hm);
+      if (c >= 1) {
+        if (CPT == 1 && have)
+          fetch_row_inputs_next<T, kR>(in[0][q], in[1][q], dir, rb, wx, wy, k, n, g.P, hm);
+        else
+          fetch_row_inputs<T, kR>(in[0][q], rb, wx, wy, k, n, g.P, hm);
+      }
     }
+    have = true;
   };
   const int jfirst = dir > 0 ? f0 - NS : f1 + NS - 1;
   const int last = f1 - f0 + 2 * NS - 1;
