@@ -967,10 +967,11 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
       }
     }
   };
-  // With one column per thread the vertical edge a row shares with the
-  // previous one is carried over (in[1] after the shift holds that row's
-  // inputs); measured 7 % faster on 1/128, while with 2 or 4 columns per
-  // thread (1/512, 1/1024) the carry made the kernel 10 % slower.
+  // With one column per thread and no reaction the vertical edge a row
+  // shares with the previous one is carried over (in[1] after the shift
+  // holds that row's inputs): measured 7 % faster on 1/128, while with 2 or 4
+  // columns per thread (1/512, 1/1024) the carry made the kernel 10 % slower,
+  // and with the reaction arrays 8 % (FP64) to 27 % (FP32) slower.
   bool have = false;
   auto fetch_in = [&](int j) {
     if (!(j >= max(f0 - NS + 1, 1) && j <= min(f1 + NS - 2, n - 1))) {
@@ -981,7 +982,7 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
     for (int q = 0; q < CPT; ++q) {
       const int c = t + q * NTC, k = j * n + c;
       if (c >= 1) {
-        if (CPT == 1 && have)
+        if (CPT == 1 && !kR && have)
           fetch_row_inputs_next<T, kR>(in[0][q], in[1][q], dir, rb, wx, wy, k, n, g.P, hm);
         else
           fetch_row_inputs<T, kR>(in[0][q], rb, wx, wy, k, n, g.P, hm);
