@@ -50,7 +50,7 @@ def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cfg", type=int, default=5,
                     help="workload id (5: two-grid 1/64 -> 1/1024, s = 512; 2: 1/32 -> 1/128)")
     ap.add_argument("--kernel-class", default=None,

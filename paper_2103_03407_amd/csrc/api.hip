@@ -666,7 +666,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   auto P = [](int m) { return padded_size(m); };                // padded vector
   auto EW = [WB](int m) { return WB * padded_size(m); };        // padded weight block
   const int64_t sz = (int64_t)sizeof(T);
-  int64_t per_sample = 8 * (EW(nh) + 2 * P(nh)) + sz * (9 * P(nh)) + (kMixed ? 4 * EW(nh) : 0);
+  int64_t per_sample = sz * EW(nh) + 8 * 2 * P(nh) + sz * (9 * P(nh));
   for (size_t k = 1; k < nL; ++k) per_sample += sz * (EW(lv[k]) + 3 * P(lv[k]));
   per_sample += sz * (EW(nb) + 2 * P(nb));
   if (rx) per_sample += 8 * (s + 1);  // the points with their leading 1
@@ -693,16 +693,23 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
 
   std::string p = tag;
   auto nm = [&](const char* x) { return p + x; };
-  double *w64, *part, *Y1 = nullptr, *sepU = nullptr;
+  // The edge weights are stored once, in the storage precision: the FP64
+  // set-up residual and Rayleigh quotients read them there too and compute in
+  // FP64.  In mixed precision that puts an FP32 rounding into every weight of
+  // the operator whose eigenvalue is returned; the roundings are independent,
+  // so the eigenvalue moves by about 1e-10 relative (measured with the oracle
+  // on 1/256: 4e-11 .. 1.4e-10), far inside the 1e-8 the mixed path promises.
+  double *part, *Y1 = nullptr, *sepU = nullptr;
   T *wT, *vn, *mvn, *t, *r, *r2, *z, *zb, *pp[2];
-  CS(ctx->getT(nm("w64").c_str(), batch * EW(nh), &w64));
+  CS(ctx->getT(nm(kMixed ? "w32" : "w64").c_str(), batch * EW(nh), &wT));
+  double* w64 = nullptr;  // the weights when stored in FP64
+  float* w32 = nullptr;   // ... in FP32
+  if constexpr (kMixed)
+    w32 = wT;
+  else
+    w64 = wT;
   if (rx) CS(ctx->getT(nm("Y1").c_str(), batch * (s + 1), &Y1));
   if (sep) CS(ctx->getT(nm("sepU").c_str(), batch * (3 * nh + 2) * sep->kx, &sepU));
-  if constexpr (kMixed) {
-    CS(ctx->getT(nm("w32").c_str(), batch * EW(nh), &wT));
-  } else {
-    wT = w64;
-  }
   // blocks per sample <= (rows + 7) / 8 strips x (column blocks <= 4): bound the
   // partial-sum buffer by the most strips any batch size can take, 3 partials each
   CS(ctx->getT(nm("part").c_str(), batch * (4 * ((nh + 6) / 8) + 4) * 6, &part));
@@ -788,17 +795,17 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     hipStream_t st = ctx->stream;
     const uint8_t* act = vact;  // the V-cycle skips samples whose last step is taken
 
-    // coefficient expansion straight into FP64 edge weights, the storage copy, coarser levels
+    // coefficient expansion straight into the edge weights (computed in FP64,
+    // stored in the storage precision), then the coarser levels
     ctx->t_begin(MLQMC_K_COEFF);
-    float* w32 = nullptr;
-    if constexpr (kMixed) w32 = wT;
     if (rx) {
       // (1, y) against the tables of a and b (row 0: the background values)
       CK(launch_prepend_one(Bn, s, Y + b0 * ldY, ldY, Y1, st), "points");
       CK(launch_expand(Bn, s + 1, 2 * P(nh), Y1, s + 1, tb->pad, 0.0, w64, w32, st, EW(nh)),
          "expand");
-      CK(launch_expand(Bn, s + 1, 3 * P(nh), Y1, s + 1, tb->rpad, 0.0, w64 + 2 * P(nh),
-                       w32 ? w32 + 2 * P(nh) : nullptr, st, EW(nh)),
+      CK(launch_expand(Bn, s + 1, 3 * P(nh), Y1, s + 1, tb->rpad, 0.0,
+                       w64 ? w64 + 2 * P(nh) : nullptr, w32 ? w32 + 2 * P(nh) : nullptr, st,
+                       EW(nh)),
          "expand");
     } else if (sep) {
       CK(launch_expand_separable(Bn, nh, s, sep->kx, sep->ky, Y + b0 * ldY, ldY, ctx->d_c,
@@ -809,11 +816,11 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
       CK(launch_expand(Bn, s, EW(nh), Y + b0 * ldY, ldY, tb->pad, ctx->a0, w64, w32, st),
          "expand");
     }
-    // the weights out (FP64, plus the FP32 copy in mixed precision); in: Y and
-    // the table (dense), or Y and the row sums U (separable: written and read
-    // once); flops of the product actually formed
+    // the weights out in the storage precision; in: Y and the table (dense),
+    // or Y and the row sums U (separable: written and read once); flops of
+    // the product actually formed
     const int rows = rx ? s + 1 : s;
-    const double wout = (8.0 + (kMixed ? 4.0 : 0.0)) * (double)Bn * EW(nh);
+    const double wout = (double)sz * (double)Bn * EW(nh);
     if (sep) {
       const double M3 = 3.0 * nh + 2.0;
       ctx->t_end(MLQMC_K_COEFF, 8.0 * (double)Bn * s + 16.0 * (double)Bn * M3 * sep->kx + wout,
@@ -827,9 +834,9 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
 
     // v = P u_H is evaluated inside these kernels from the coarse vectors
     const double* uHb = uH + b0 * D(nH);
-    CK(launch_setup_dots(nh, Bn, uHb, nH, w64, part, rx, st), "setup dots");
+    CK(launch_setup_dots<T>(nh, Bn, uHb, nH, wT, part, rx, st), "setup dots");
     CK(launch_scalar(PH_SETUP, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
-    CK(launch_setup_rhs<T>(nh, Bn, uHb, nH, w64, S, r, vn, mvn, rx, st), "setup rhs");
+    CK(launch_setup_rhs<T>(nh, Bn, uHb, nH, wT, S, r, vn, mvn, rx, st), "setup rhs");
 
     // z = K^{-1} r by one V-cycle: fused pre-smoothing + restriction per level,
     // the LDS bottom solve, fused coarse correction + post-smoothing per level;
@@ -946,7 +953,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
         }
       }
     }
-    CK(launch_final_dots<T>(nh, Bn, uHb, nH, t, pp[0], pp[1], w64, S, part, rx, st),
+    CK(launch_final_dots<T>(nh, Bn, uHb, nH, t, pp[0], pp[1], wT, S, part, rx, st),
        "final dots");
     CK(launch_scalar(PH_FINAL, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
   }

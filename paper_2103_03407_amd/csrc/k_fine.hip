@@ -238,6 +238,30 @@ __device__ __forceinline__ Wts<W, kR> load_wts(const W* wx, const W* wy, int k, 
   }
   return o;
 }
+// The same widened to FP64 from weights stored in W, with the reaction scale
+// applied in FP64 (rounding the scale to FP32 would shift every reaction
+// term by one and the same relative amount, and the eigenvalue with it).
+template <typename W, bool kR = false>
+__device__ __forceinline__ Wts<double, kR> load_wts_fp64(const W* wx, const W* wy, int k, int n,
+                                                         int P, double hm) {
+  Wts<double, kR> o;
+  o.ww = (double)wx[k];
+  o.we = (double)wx[k + 1];
+  o.ws = (double)wy[k];
+  o.wn = (double)wy[k + n];
+  if constexpr (kR) {
+    const W* rx = wx + 2 * P;
+    const W* ry = wx + 3 * P;
+    const W* rd = wx + 4 * P;
+    o.rw = hm * (double)rx[k];
+    o.re = hm * (double)rx[k + 1];
+    o.rs = hm * (double)ry[k];
+    o.rn = hm * (double)ry[k + n];
+    o.rsw = hm * (double)rd[k];
+    o.rne = hm * (double)rd[k + n + 1];
+  }
+  return o;
+}
 // ((A [+ R]) x)_k from a ring of x rows (south, centre, north; column ci)
 template <typename T, typename W, bool kR = false>
 __device__ __forceinline__ T ring_Aw(const T* rs, const T* rc, const T* rn, int ci,
@@ -372,23 +396,24 @@ __global__ __launch_bounds__(256) void k_coarsen(int xblk, int n, int64_t B, con
   wc[b * wblk<kR>() * Pc + e] = val;
 }
 
-// partials: v.M12 v, v.A v  (raw FP64 v, FP64 weights)
-template <int NTC, bool kR>
+// partials: v.M12 v, v.A v  (raw FP64 v; the weights in their storage
+// precision W, the arithmetic in FP64)
+template <typename W, int NTC, bool kR>
 __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, Coarse cv,
-                                                    const double* __restrict__ w,
+                                                    const W* __restrict__ w,
                                                     double* __restrict__ part) {
   __shared__ double ring[4][NTC + 2];
   int64_t b;
   int c0, j0, j1, blk, dir;
   if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir)) return;
-  const double* wx = w + b * wblk<kR>() * g.P;
-  const double* wy = wx + g.P;
+  const W* wx = w + b * wblk<kR>() * g.P;
+  const W* wy = wx + g.P;
   const double hm = mass_scale(g.n);
   double s[2] = {0.0, 0.0};
   march_pf<double, NTC>(
       ring, g, c0, j0, j1, dir, [&](int k) { return coarse_v(cv, g, b, k); },
       [](double f) { return f; },
-      [&](int k) { return load_wts<double, kR>(wx, wy, k, g.n, g.P, hm); },
+      [&](int k) { return load_wts_fp64<W, kR>(wx, wy, k, g.n, g.P, hm); },
       [&](int, int, const double* rs, const double* rc, const double* rn, int ci,
           const Wts<double, kR>& wt, double) {
         const double av = ring_Aw(rs, rc, rn, ci, wt);
@@ -398,24 +423,25 @@ __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, Coarse cv,
   write_partials_m<NTC, 2>(s, part, b, blk, g.nblk);
 }
 
-// r = -(A v_n - rho M v_n) (FP64), vn = v_n, mvn = M v_n (t starts at 0 without
-// being stored: the PCG kernels read t only from its third step on)
+// r = -(A v_n - rho M v_n) (FP64 arithmetic on the weights of storage type
+// T), vn = v_n, mvn = M v_n (t starts at 0 without being stored: the PCG
+// kernels read t only from its third step on)
 template <typename T, int NTC, bool kR>
 __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
-                                                   const double* __restrict__ w64, FineState S,
+                                                   const T* __restrict__ w, FineState S,
                                                    T* __restrict__ r, T* __restrict__ vn,
                                                    T* __restrict__ mvn) {
   __shared__ double ring[4][NTC + 2];
   int64_t b;
   int c0, j0, j1, blk, dir;
   if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir)) return;
-  const double* wx = w64 + b * wblk<kR>() * g.P;
-  const double* wy = wx + g.P;
+  const T* wx = w + b * wblk<kR>() * g.P;
+  const T* wy = wx + g.P;
   const double vs = S.vs[b], rho = S.rho[b], hm = mass_scale(g.n);
   march_pf<double, NTC>(
       ring, g, c0, j0, j1, dir, [&](int k) { return coarse_v(cv, g, b, k); },
       [](double f) { return f; },
-      [&](int k) { return load_wts<double, kR>(wx, wy, k, g.n, g.P, hm); },
+      [&](int k) { return load_wts_fp64<T, kR>(wx, wy, k, g.n, g.P, hm); },
       [&](int, int k, const double* rs, const double* rc, const double* rn, int ci,
           const Wts<double, kR>& wt, double) {
                        const double av = ring_Aw(rs, rc, rn, ci, wt);
@@ -1091,14 +1117,15 @@ __global__ __launch_bounds__(NTC) void k_post(VGeo g, const T* __restrict__ w,
 
 // ---------------------------------------------------------------- final
 
-// w = vs v + t (FP64): partials w.A w, w.M12 w with FP64 weights, and the
-// sum of w (h^2 times it is the integral of the P1 function w)
+// w = vs v + t (FP64): partials w.A w, w.M12 w in FP64 arithmetic on the
+// weights of storage type T, and the sum of w (h^2 times it is the integral
+// of the P1 function w)
 template <typename T, int NTC, bool kR>
 __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, Coarse cv,
                                                     const T* __restrict__ t,
                                                     const T* __restrict__ p0,
                                                     const T* __restrict__ p1,
-                                                    const double* __restrict__ w, FineState S,
+                                                    const T* __restrict__ w, FineState S,
                                                     double* __restrict__ part) {
   __shared__ double ring[4][NTC + 2];
   int64_t b;
@@ -1112,8 +1139,8 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, Coarse cv,
   const T al = its > 0 ? (T)S.alpha[b] : T(0);
   const bool tread = its >= 2;  // t_{its-1} stored (t_0 = 0 never is)
   const double vs = S.vs[b];
-  const double* wx = w + b * wblk<kR>() * g.P;
-  const double* wy = wx + g.P;
+  const T* wx = w + b * wblk<kR>() * g.P;
+  const T* wy = wx + g.P;
   const double hm = mass_scale(g.n);
   double s[3] = {0.0, 0.0, 0.0};
   struct Fin {
@@ -1124,7 +1151,7 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, Coarse cv,
       ring, g, c0, j0, j1, dir,
       [&](int k) { return Fin{coarse_v(cv, g, b, k), tread ? tb[k] : T(0), pl[k]}; },
       [&](const Fin& f) { return vs * f.v + (double)(T)(f.t + al * f.p); },
-      [&](int k) { return load_wts<double, kR>(wx, wy, k, g.n, g.P, hm); },
+      [&](int k) { return load_wts_fp64<T, kR>(wx, wy, k, g.n, g.P, hm); },
       [&](int, int, const double* rs, const double* rc, const double* rn, int ci,
           const Wts<double, kR>& wt, const Fin&) {
         const double aw = ring_Aw(rs, rc, rn, ci, wt);
@@ -1346,26 +1373,28 @@ Coarse coarse_of(const double* uH, int nH, int n) {
 }
 }  // namespace
 
-hipError_t launch_setup_dots(int n, int64_t B, const double* uH, int nH, const double* w,
+template <typename T>
+hipError_t launch_setup_dots(int n, int64_t B, const double* uH, int nH, const T* w,
                              double* part, int reaction, hipStream_t st) {
   if (nH < 2 || n % nH) return hipErrorInvalidValue;
   const Coarse cv = coarse_of(uH, nH, n);
   MARCH_DISPATCH(n, KR_DISPATCH(reaction, {
     const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_setup_dots<NTC, kR>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, w, part);
+    hipLaunchKernelGGL((k_setup_dots<T, NTC, kR>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, w,
+                       part);
   }));
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const double* w64,
+hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const T* w,
                             const FineState& S, T* r, T* vn, T* mvn, int reaction,
                             hipStream_t st) {
   if (nH < 2 || n % nH) return hipErrorInvalidValue;
   const Coarse cv = coarse_of(uH, nH, n);
   MARCH_DISPATCH(n, KR_DISPATCH(reaction, {
     const MGeo g = mgeo<NTC>(n, B);
-    hipLaunchKernelGGL((k_setup_rhs<T, NTC, kR>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, w64, S,
+    hipLaunchKernelGGL((k_setup_rhs<T, NTC, kR>), mgrid<NTC>(g), dim3(NTC), 0, st, g, cv, w, S,
                        r, vn, mvn);
   }));
   return hipGetLastError();
@@ -1505,7 +1534,7 @@ int march_blocks(int n, int64_t B) {
 
 template <typename T>
 hipError_t launch_final_dots(int n, int64_t B, const double* uH, int nH, const T* t, const T* p0,
-                             const T* p1, const double* w, const FineState& S, double* part,
+                             const T* p1, const T* w, const FineState& S, double* part,
                              int reaction, hipStream_t st) {
   if (nH < 2 || n % nH) return hipErrorInvalidValue;
   const Coarse cv = coarse_of(uH, nH, n);
@@ -1537,13 +1566,15 @@ hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* s
 
 #define INST(T)                                                                                 \
   template hipError_t launch_coarsen<T>(int, int64_t, const T*, T*, int, hipStream_t);           \
-  template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, int, const double*,      \
+  template hipError_t launch_setup_dots<T>(int, int64_t, const double*, int, const T*, double*, \
+                                           int, hipStream_t);                                   \
+  template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, int, const T*,           \
                                           const FineState&, T*, T*, T*, int, hipStream_t);      \
   template hipError_t launch_pupdate_apply<T>(int, int64_t, const T*, const T*, const T*,       \
                                               const T*, T*, const FineState&, int, T*, T*,      \
                                               double*, int, hipStream_t);                       \
   template hipError_t launch_final_dots<T>(int, int64_t, const double*, int, const T*,          \
-                                           const T*, const T*, const double*, const FineState&, \
+                                           const T*, const T*, const T*, const FineState&,      \
                                            double*, int, hipStream_t);
 INST(double)
 INST(float)

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_phi_diag_padded(int n, int s,
 // chunks of 16 through double-buffered LDS, the next chunk's global loads in
 // flight while the current one is multiplied.  Tiles are ordered so that the
 // blocks sharing one entry tile of phi run together on one XCD (one L2).
-// out32, when given, receives the same values rounded to FP32.
+// out and out32, each when given, receive the values in FP64 and rounded to FP32.
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kXM = 128, kXN = 128, kXK = 16, kXPad = 4;
 
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256, 2) void k_expand_mfma(int64_t B, int s, int64_
         const int64_t b = m0 + wm * 64 + i * 16 + 4 * r + fk;
         if (b < B) {
           const double v = a0 + acc[i][j][r];
-          out[b * ldo + e] = v;
+          if (out) out[b * ldo + e] = v;
           if (out32) out32[b * ldo + e] = (float)v;
         }
       }
@@ -424,8 +424,10 @@ __global__ __launch_bounds__(512) void k_sep_mfma(int64_t B, int n, int kx, int 
       const double vx = (i >= 1 && j >= 1 && j <= n - 1) ? a0 + 0.5 * ax[c][r] : a0;
       const double vy = (i >= 1 && j >= 1 && j <= n) ? a0 + 0.5 * ay[c][r] : a0;
       const int64_t o = b * ldo + (int64_t)j * n + i;
-      out[o] = vx;
-      out[o + P] = vy;
+      if (out) {
+        out[o] = vx;
+        out[o + P] = vy;
+      }
       if (out32) {
         out32[o] = (float)vx;
         out32[o + P] = (float)vy;
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(256) void k_sep_alias(int64_t B, int n, int kx,
            S[(int64_t)p * M + 3 * n - 1] * Ub[(int64_t)(3 * je + 1) * kx + p];
   const double v = a0 + 0.5 * acc;
   const int64_t o = b * ldo + (int64_t)j * n;
-  out[o] = v;
+  if (out) out[o] = v;
   if (out32) out32[o] = (float)v;
 }
 

@@ -107,11 +107,13 @@ hipError_t launch_prolong_interior(int nH, int nh, int64_t B, const double* uH, 
 template <typename T>
 hipError_t launch_coarsen(int n, int64_t B, const T* w, T* wc, int reaction, hipStream_t st);
 // The set-up and final kernels take the coarse eigenvectors uH [B x (nH-1)^2]
-// and evaluate v = P u_H (P1 interpolation to mesh n) where they need it.
-hipError_t launch_setup_dots(int n, int64_t B, const double* uH, int nH, const double* w,
+// and evaluate v = P u_H (P1 interpolation to mesh n) where they need it; they
+// read the edge weights in the storage precision T and compute in FP64.
+template <typename T>
+hipError_t launch_setup_dots(int n, int64_t B, const double* uH, int nH, const T* w,
                              double* part, int reaction, hipStream_t st);
 template <typename T>
-hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const double* w64,
+hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const T* w,
                             const FineState& S, T* r, T* vn, T* mvn, int reaction,
                             hipStream_t st);
 // the new direction pout = z - c2 vn + beta pin and q = (A - mu M) pout (stored
@@ -147,7 +149,7 @@ void set_target_blocks(int64_t v);
 int march_blocks(int n, int64_t B);
 template <typename T>
 hipError_t launch_final_dots(int n, int64_t B, const double* uH, int nH, const T* t, const T* p0,
-                             const T* p1, const double* w, const FineState& S, double* part,
+                             const T* p1, const T* w, const FineState& S, double* part,
                              int reaction, hipStream_t st);
 
 // scalar phases: one wavefront per sample sums that sample's block partials
@@ -193,7 +195,7 @@ hipError_t launch_phi_elements_islands(int n, int rows, const double* c, const i
 hipError_t launch_phi_reaction_padded(int n, int rows, const double* phi_el, double* phi_r,
                                       hipStream_t st);
 // out[b * ldo + e] = a0 + sum_{j<s} Y[b][j] phi[j][e], e < E (ldo = 0: E);
-// out32 (optional) the same rounded to FP32
+// out32 the same rounded to FP32; either may be null
 hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t ldY,
                          const double* phi, double a0, double* out, float* out32,
                          hipStream_t st, int64_t ldo = 0);
@@ -202,7 +204,7 @@ hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t l
 // (launch_sep_sin once per mesh); cells of the kx x ky box of (k1, k2) in CSR
 // (cell_start [kx ky + 1], cell_term: the term indices of each cell, in order);
 // U scratch [B x (3n+2) x kx].  Writes the padded [WX | WY] of B samples at
-// out[b * ldo ...] (and out32), equal to launch_expand with the padded edge
+// out[b * ldo ...] and / or out32, equal to launch_expand with the padded edge
 // table up to rounding.  n a multiple of 64, kx <= 64, kx ky <= 1024.
 hipError_t launch_sep_sin(int n, int kmax, double* S, hipStream_t st);
 // dst[i] |= src[i], i < n
