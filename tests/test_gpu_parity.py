@@ -663,3 +663,30 @@ def test_direct_level_64(ctx, fam, lv, chain):
         if lv[4]:
             assert abs(lamp[k] - v.lam_prev) <= LAM_RTOL * v.lam_prev
             assert abs(gp[k] - v.G_prev) <= 1e-9 * v.G_prev
+
+
+# ---------------- ragged batches of the batched path ----------------
+
+@pytest.mark.parametrize("prec,tol", [("fp64", LAM_RTOL), ("mixed", 1e-8)])
+def test_ragged_batches_match_one_batch(ctx, fam, prec, tol):
+    # 300 samples in batches of 128, 128 and 44 against one batch of 300, and
+    # against the oracle at the first and last sample of every batch
+    lv = (64, 32, 16, 8, 32, 16)
+    cnt = 300
+    Y = np.ascontiguousarray(_points(1024, 32, 2, 0, 3, range(7, 7 + cnt)))
+    p = m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED
+    out = {}
+    for batch in (0, 128):
+        lam, lamp = np.empty(cnt), np.empty(cnt)
+        fl = np.zeros(cnt, np.uint8)
+        ctx.eig_level(lv, Y, lam, fl, lam_prev=lamp, opts=m.default_opts(prec=p, batch=batch))
+        assert not fl.any(), fl
+        out[batch] = (lam, lamp)
+    # a batch changes only the strip layout and with it the summation order
+    assert np.max(np.abs(out[0][0] - out[128][0]) / out[0][0]) <= tol
+    assert np.max(np.abs(out[0][1] - out[128][1]) / out[0][1]) <= tol
+    spec = LevelSpec(*lv, 0)
+    for k in (0, 127, 128, 255, 256, 299):
+        v = mlqmc.level_value(spec, Y[k], fam)
+        assert abs(out[128][0][k] - v.lam) <= tol * v.lam, (k, out[128][0][k], v.lam)
+        assert abs(out[128][1][k] - v.lam_prev) <= tol * v.lam_prev
