@@ -103,6 +103,7 @@ struct mlqmc_ctx {
   struct PcgGraph {
     std::vector<uint64_t> key;
     hipGraphExec_t exec = nullptr;
+    int pairs = 0;  // replays the batch needed the last time it ran (0: not known)
   };
   std::map<std::string, PcgGraph> graphs;
   hipStream_t cap_stream = nullptr;  // private stream for capturing (default priority)
@@ -766,6 +767,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
   CS(ctx->getT(nm("active").c_str(), batch, &active));
   CS(ctx->getT(nm("vact").c_str(), batch, &vact));
   std::vector<uint8_t> h_active(batch);
+  std::vector<int> h_its(batch);
 
   set_target_blocks(ctx->target_for(nh, kMixed ? MLQMC_MIXED : MLQMC_FP64));
   for (int64_t b0 = 0; b0 < n; b0 += batch) {
@@ -911,11 +913,20 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
          "scalar");
       return MLQMC_OK;
     };
-    auto any_active = [&](bool* any) -> mlqmc_status {
+    // any sample still active; with `steps` also the most PCG steps any
+    // sample has taken
+    auto any_active = [&](bool* any, int* steps = nullptr) -> mlqmc_status {
       CK(hipMemcpyAsync(h_active.data(), active, Bn, hipMemcpyDeviceToHost, st), "active");
+      if (steps)
+        CK(hipMemcpyAsync(h_its.data(), its, Bn * sizeof(int), hipMemcpyDeviceToHost, st),
+           "steps");
       CS(ctx->sync("pcg"));
       *any = false;
       for (int64_t k = 0; k < Bn; ++k) *any |= h_active[k] != 0;
+      if (steps) {
+        *steps = 0;
+        for (int64_t k = 0; k < Bn; ++k) *steps = std::max(*steps, h_its[k]);
+      }
       return MLQMC_OK;
     };
     CS(iteration(0));
@@ -935,12 +946,23 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
         return r;
       }, graph_key<T>(nh, Bn, o, S, {zc, zo, rc, ro, pp[0], pp[1], vn, mvn, wT, t, part, act,
                                      active}, W, X, Xb, Bv, nblk0, nblk_post), &exec));
+      // Replays before the first read-back of the activity: as many as this
+      // batch needed the last time it ran (converged samples exit at once, so
+      // a replay too many costs only its empty launches), then one at a time.
+      mlqmc_ctx::PcgGraph& pg = ctx->graphs[gtag];
+      const int ahead = std::max(1, pg.pairs);
+      int pairs = 0;
       while (done_its < o->max_lin_iter) {
         CK(hipGraphLaunch(exec, st), "graph launch");
         done_its += 2;
+        if (++pairs < ahead && done_its < o->max_lin_iter) continue;
         bool any = false;
-        CS(any_active(&any));
-        if (!any) break;
+        int steps = 0;
+        CS(any_active(&any, &steps));
+        if (!any) {
+          pg.pairs = steps / 2;  // steps 1 .. steps - 1 in replays of two
+          break;
+        }
       }
     } else {
       for (int it = 1; it < o->max_lin_iter; ++it) {

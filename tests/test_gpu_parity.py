@@ -564,6 +564,33 @@ def test_pcg_graph_replays_match_eager(ctx, prec):
                       opts=m.default_opts(prec=pr, pcg_graph=rep % 2))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pcg_graph_replays_ahead_match_eager(ctx, prec):
+    # a batch launches as many replays before its first read-back as it
+    # needed the last time; replays past convergence must change nothing:
+    # a run to a tight tolerance (many steps) followed by one to the default
+    # (fewer steps, so some replays find every sample converged) gives the
+    # eager launches' results bit for bit
+    pr = m.MLQMC_FP64 if prec == "fp64" else m.MLQMC_MIXED
+    Y = np.ascontiguousarray(_points(1024, 64, 2, 0, 11, range(20)))
+    lv = (128, 64, 32, 8, 0, 0)
+    ref, li_ref = np.empty(20), np.zeros(20, np.int32)
+    ctx.eig_level(lv, Y, ref, np.zeros(20, np.uint8), lin_iters=li_ref,
+                  opts=m.default_opts(prec=pr, pcg_graph=0))
+    # unreachable tolerances: every sample runs to the step cap
+    tight = m.default_opts(prec=pr, pcg_graph=1, lam_rtol=1e-30, lin_rtol=1e-30,
+                           max_lin_iter=20)
+    li_t = np.zeros(20, np.int32)
+    ctx.eig_level(lv, Y, np.empty(20), np.zeros(20, np.uint8), lin_iters=li_t, opts=tight)
+    assert li_t.max() >= li_ref.max() + 4
+    got, li = np.empty(20), np.zeros(20, np.int32)
+    fl = np.zeros(20, np.uint8)
+    ctx.eig_level(lv, Y, got, fl, lin_iters=li, opts=m.default_opts(prec=pr, pcg_graph=1))
+    assert not fl.any()
+    assert np.array_equal(got, ref)
+    assert np.array_equal(li, li_ref)
+
+
 def test_tuning_changes_speed_not_results(ctx, tmp_path):
     Y = np.ascontiguousarray(_points(1024, 64, 2, 0, 10, range(40)))
     lv = (128, 64, 32, 8, 0, 0)
