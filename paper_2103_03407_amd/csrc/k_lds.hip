@@ -197,9 +197,16 @@ __device__ void rqi_chain(const RqiArgs& A, const lds::PcgArrays<T>& a, double* 
 // quotients then use FP64 weights recomputed from the edge table.
 // With kR (Problem 2) the weight block also holds the reaction arrays; with
 // FP32 storage an FP64 copy of it serves the Rayleigh quotients.
+// Minimum waves per SIMD (the second launch bound), measured per mesh and
+// precision: four where the registers allow (more waves beat the spills
+// they cause), two for the FP64 1/32 kernels, three for the reaction's 1/8
+// and 1/16 kernels (in FP64 5-8 % faster on 1/8 and 1/16 levels and 1.7x on
+// a direct 1/16 level than leaving the choice to the compiler, which took
+// 180-256 registers and one or two waves; four spilled more and ran 30 %
+// slower), one for its 1/32 kernels (110 KB of LDS each).
 template <int N, int NT, bool kR>
 constexpr int lds_blocks_per_cu(int tsize) {
-  return kR ? 1 : ((N >= 32 && tsize == 8) ? 2 : 4);
+  return kR ? (N <= 16 ? 3 : 1) : ((N >= 32 && tsize == 8) ? 2 : 4);
 }
 template <int N, int NT, typename T, bool kR = false>
 __global__ __launch_bounds__(NT, (lds_blocks_per_cu<N, NT, kR>(sizeof(T)))) void k_rqi(RqiArgs A) {
