@@ -318,27 +318,6 @@ __global__ __launch_bounds__(256) void k_zero_boundary(int n, int64_t B, int per
   }
 }
 
-// interior-layout coarse field (mesh nH) -> padded fine field (mesh n), P1 interpolation
-// P1 interpolation from the interior-layout coarse field at fine node (i, j)
-// for a power-of-two ratio 2^lr: barycentric on the coarse "/" triangle
-// holding the node (the same arithmetic as interp_coarse; 1/r is exact)
-__device__ __forceinline__ double interp_pow2(const double* __restrict__ uH, int nH, int lr,
-                                              double inv_r, int i, int j) {
-  const int mH = nH - 1, r = 1 << lr;
-  const int I = i >> lr, J = j >> lr, li = i & (r - 1), lj = j & (r - 1);
-  auto U = [&](int a, int b) -> double {
-    return (a >= 1 && a <= mH && b >= 1 && b <= mH) ? uH[(b - 1) * mH + (a - 1)] : 0.0;
-  };
-  const double xi = li * inv_r, eta = lj * inv_r;
-  const double u00 = U(I, J), u11 = U(I + 1, J + 1);
-  if (lj <= li) {  // lower triangle (I,J),(I+1,J),(I+1,J+1)
-    const double u10 = U(I + 1, J);
-    return u00 + xi * (u10 - u00) + eta * (u11 - u10);
-  }
-  const double u01 = U(I, J + 1);  // upper triangle (I,J),(I+1,J+1),(I,J+1)
-  return u00 + eta * (u01 - u00) + xi * (u11 - u01);
-}
-
 // The prolongated coarse eigenvector v = P u_H, evaluated where it is needed
 // instead of being stored: node k of mesh n (padded layout) of sample b.
 // Padding positions (column 0, rows 0 and n) come out as 0.
@@ -347,10 +326,38 @@ struct Coarse {
   int nH, lr;        // coarse mesh, log2(n / nH)
   double inv_r;      // 2^-lr
 };
-__device__ __forceinline__ double coarse_v(const Coarse& cv, const MGeo& g, int64_t b, int k) {
-  const int mH = cv.nH - 1;
-  return interp_pow2(cv.uH + b * (int64_t)(mH * mH), cv.nH, cv.lr, cv.inv_r, k & (g.n - 1),
-                     k >> g.lg);
+// In two parts, so that a row-marching kernel can request the loads a row
+// step before it needs the value: coarse_src loads the three vertices of the
+// coarse triangle holding the node (u00, u11 and the third, (I+1, J) below
+// the diagonal or (I, J+1) above it) and keeps the node's offsets in the
+// coarse square; coarse_val interpolates, barycentric on that triangle (the
+// arithmetic of interp_coarse, with the power-of-two ratio 2^lr: 1/r is
+// exact).
+struct CoarseSrc {
+  double u00, u11, ux;
+  int li, lj;
+};
+__device__ __forceinline__ CoarseSrc coarse_src(const Coarse& cv, const MGeo& g, int64_t b,
+                                                int k) {
+  const int mH = cv.nH - 1, i = k & (g.n - 1), j = k >> g.lg, r = 1 << cv.lr;
+  const double* uH = cv.uH + b * (int64_t)(mH * mH);
+  const int I = i >> cv.lr, J = j >> cv.lr;
+  CoarseSrc s;
+  s.li = i & (r - 1);
+  s.lj = j & (r - 1);
+  auto U = [&](int a, int c) -> double {
+    return (a >= 1 && a <= mH && c >= 1 && c <= mH) ? uH[(c - 1) * mH + (a - 1)] : 0.0;
+  };
+  const bool lower = s.lj <= s.li;
+  s.u00 = U(I, J);
+  s.u11 = U(I + 1, J + 1);
+  s.ux = U(lower ? I + 1 : I, lower ? J : J + 1);
+  return s;
+}
+__device__ __forceinline__ double coarse_val(const Coarse& cv, const CoarseSrc& s) {
+  const double xi = s.li * cv.inv_r, eta = s.lj * cv.inv_r;
+  if (s.lj <= s.li) return s.u00 + xi * (s.ux - s.u00) + eta * (s.u11 - s.ux);
+  return s.u00 + eta * (s.ux - s.u00) + xi * (s.u11 - s.ux);
 }
 
 // interior-layout prolongation for the component entry point
@@ -411,11 +418,11 @@ __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, Coarse cv,
   const double hm = mass_scale(g.n);
   double s[2] = {0.0, 0.0};
   march_pf<double, NTC>(
-      ring, g, c0, j0, j1, dir, [&](int k) { return coarse_v(cv, g, b, k); },
-      [](double f) { return f; },
+      ring, g, c0, j0, j1, dir, [&](int k) { return coarse_src(cv, g, b, k); },
+      [&](const CoarseSrc& f) { return coarse_val(cv, f); },
       [&](int k) { return load_wts_fp64<W, kR>(wx, wy, k, g.n, g.P, hm); },
       [&](int, int, const double* rs, const double* rc, const double* rn, int ci,
-          const Wts<double, kR>& wt, double) {
+          const Wts<double, kR>& wt, const CoarseSrc&) {
         const double av = ring_Aw(rs, rc, rn, ci, wt);
         s[0] += rc[ci] * ring_M12(rs, rc, rn, ci);
         s[1] += rc[ci] * av;
@@ -439,11 +446,11 @@ __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
   const T* wy = wx + g.P;
   const double vs = S.vs[b], rho = S.rho[b], hm = mass_scale(g.n);
   march_pf<double, NTC>(
-      ring, g, c0, j0, j1, dir, [&](int k) { return coarse_v(cv, g, b, k); },
-      [](double f) { return f; },
+      ring, g, c0, j0, j1, dir, [&](int k) { return coarse_src(cv, g, b, k); },
+      [&](const CoarseSrc& f) { return coarse_val(cv, f); },
       [&](int k) { return load_wts_fp64<T, kR>(wx, wy, k, g.n, g.P, hm); },
       [&](int, int k, const double* rs, const double* rc, const double* rn, int ci,
-          const Wts<double, kR>& wt, double) {
+          const Wts<double, kR>& wt, const CoarseSrc&) {
                        const double av = ring_Aw(rs, rc, rn, ci, wt);
                        const double mv = hm * ring_M12(rs, rc, rn, ci);
                        const double rv = -vs * (av - rho * mv);
@@ -1151,13 +1158,13 @@ __global__ __launch_bounds__(NTC) void k_final_dots(MGeo g, Coarse cv,
   const double hm = mass_scale(g.n);
   double s[3] = {0.0, 0.0, 0.0};
   struct Fin {
-    double v;
+    CoarseSrc v;
     T t, p;
   };
   march_pf<double, NTC>(
       ring, g, c0, j0, j1, dir,
-      [&](int k) { return Fin{coarse_v(cv, g, b, k), tread ? tb[k] : T(0), pl[k]}; },
-      [&](const Fin& f) { return vs * f.v + (double)(T)(f.t + al * f.p); },
+      [&](int k) { return Fin{coarse_src(cv, g, b, k), tread ? tb[k] : T(0), pl[k]}; },
+      [&](const Fin& f) { return vs * coarse_val(cv, f.v) + (double)(T)(f.t + al * f.p); },
       [&](int k) { return load_wts_fp64<T, kR>(wx, wy, k, g.n, g.P, hm); },
       [&](int, int, const double* rs, const double* rc, const double* rn, int ci,
           const Wts<double, kR>& wt, const Fin&) {
