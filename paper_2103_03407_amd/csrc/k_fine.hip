@@ -456,9 +456,9 @@ __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
                        const double rv = -vs * (av - rho * mv);
                        const T rT = (T)rv;
                        const int64_t o = b * g.P + k;
-                       r[o] = rT;
-                       vn[o] = (T)(vs * rc[ci]);
-                       mvn[o] = (T)(vs * mv);
+                       __builtin_nontemporal_store(rT, &r[o]);
+                       __builtin_nontemporal_store((T)(vs * rc[ci]), &vn[o]);
+                       __builtin_nontemporal_store((T)(vs * mv), &mvn[o]);
                      });
 }
 
@@ -939,7 +939,7 @@ __global__ __launch_bounds__(NTC) void k_pre(VGeo g, const T* __restrict__ w,
 }
 
 // The stencil kernels write their full-size outputs (Xout, X, the updated
-// residual, p, t) with non-temporal stores: they are read again only a kernel
+// residual, p, t, and the set-up's r, vn, M vn) with non-temporal stores: they are read again only a kernel
 // or more later, long after they would have left the L2, and kept out of it
 // they leave room for the rows the neighbouring strips share (measured 2-8 %
 // faster k_post, k_pupdate_apply and k_pre launches).
