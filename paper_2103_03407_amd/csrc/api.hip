@@ -137,6 +137,9 @@ struct mlqmc_ctx {
     int* cell_start = nullptr;
     int* cell_term = nullptr;
     double* S = nullptr;
+    // per coarse mesh nH: the interval sums of S behind the coarse-side set-up
+    // products (launch_sep_tri)
+    std::map<int, double*> tri;
   };
   std::map<std::pair<int, int>, SepTable> seps;
   // No-allocation mode (mlqmc_eig_level_noalloc): named buffers and tables
@@ -193,6 +196,32 @@ struct mlqmc_ctx {
       t.ky = ky;
     }
     *out = &t;
+    return MLQMC_OK;
+  }
+  // The interval sums of the separable table t for fine mesh n over coarse
+  // mesh nH, or nullptr where the coarse-side set-up products do not apply
+  // (nH > 64, n not a multiple of nH)
+  mlqmc_status sep_tri(SepTable* t, int n, int nH, double** out) {
+    *out = nullptr;
+    if (!t || nH < 2 || nH > 64 || n % nH) return MLQMC_OK;
+    auto it = t->tri.find(nH);
+    if (it != t->tri.end()) {
+      *out = it->second;
+      return MLQMC_OK;
+    }
+    const size_t bytes = (size_t)3 * (n / nH) * t->kx * 2 * nH * sizeof(double);
+    if (mem_cap > 0 && bytes_alloc + (int64_t)bytes > mem_cap)
+      return fail(MLQMC_ENOMEM, "set-up table for n=%d exceeds the device memory cap", n);
+    double* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipSuccess) e = launch_sep_tri(n, nH, t->kx, t->S, p, stream);
+    if (e != hipSuccess) {
+      if (p) (void)hipFree(p);
+      return fail(MLQMC_ENOMEM, "set-up table: %s", hipGetErrorString(e));
+    }
+    bytes_alloc += (int64_t)bytes;
+    t->tri[nH] = p;
+    *out = p;
     return MLQMC_OK;
   }
   std::string err;
@@ -711,6 +740,8 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     w64 = wT;
   if (rx) CS(ctx->getT(nm("Y1").c_str(), batch * (s + 1), &Y1));
   if (sep) CS(ctx->getT(nm("sepU").c_str(), batch * (3 * nh + 2) * sep->kx, &sepU));
+  double* sep_tri_t = nullptr;  // interval sums for the coarse-side set-up products
+  if (sep) CS(ctx->sep_tri(sep, nh, nH, &sep_tri_t));
   // blocks per sample <= (rows + 7) / 8 strips x (column blocks <= 4): bound the
   // partial-sum buffer by the most strips any batch size can take, 3 partials each
   CS(ctx->getT(nm("part").c_str(), batch * (4 * ((nh + 6) / 8) + 4) * 6, &part));
@@ -834,10 +865,20 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     for (size_t k = 0; k < nL; ++k)
       CK(launch_coarsen<T>(lv[k], Bn, W[k], W[k + 1], rx, st), "coarsen");
 
-    // v = P u_H is evaluated inside these kernels from the coarse vectors
+    // v = P u_H is evaluated inside these kernels from the coarse vectors.
+    // With the separable expansion v^T M v and v^T A v come from coarse
+    // quantities and the expansion's row sums instead of a pass over the fine
+    // edge weights (the coefficient at the fine centroids, summed per coarse
+    // triangle).
     const double* uHb = uH + b0 * D(nH);
-    CK(launch_setup_dots<T>(nh, Bn, uHb, nH, wT, part, rx, st), "setup dots");
-    CK(launch_scalar(PH_SETUP, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
+    if (sep_tri_t) {
+      CK(launch_sep_setup_dots(Bn, nh, nH, sep->kx, sepU, sep_tri_t, uHb, ctx->a0, part, st),
+         "setup dots (separable)");
+      CK(launch_scalar(PH_SETUP, nh, Bn, 1, part, S, 0.0, 0, st), "scalar");
+    } else {
+      CK(launch_setup_dots<T>(nh, Bn, uHb, nH, wT, part, rx, st), "setup dots");
+      CK(launch_scalar(PH_SETUP, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
+    }
     CK(launch_setup_rhs<T>(nh, Bn, uHb, nH, wT, S, r, vn, mvn, rx, st), "setup rhs");
 
     // z = K^{-1} r by one V-cycle: fused pre-smoothing + restriction per level,
@@ -1395,9 +1436,12 @@ void mlqmc_destroy(mlqmc_ctx* ctx) {
   for (auto& kv : ctx->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto& kv : ctx->tables) kv.second.release();
-  for (auto& kv : ctx->seps)
+  for (auto& kv : ctx->seps) {
     for (void* q : {(void*)kv.second.S, (void*)kv.second.cell_start, (void*)kv.second.cell_term})
       if (q) (void)hipFree(q);
+    for (auto& tv : kv.second.tri)
+      if (tv.second) (void)hipFree(tv.second);
+  }
   for (auto& ev : ctx->ev_pool) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);

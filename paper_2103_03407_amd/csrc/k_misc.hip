@@ -458,6 +458,133 @@ __global__ __launch_bounds__(256) void k_sep_alias(int64_t B, int n, int kx,
   if (out32) out32[o] = (float)v;
 }
 
+// ---------------------------------------------------------------- separable set-up products
+//
+// The set-up of a two-grid update needs v^T M_h v and v^T A_h v for the
+// prolongated coarse eigenvector v = P u_H.  On nested meshes both follow from
+// coarse quantities.  The P1 mass matrices integrate exactly, so
+// v^T M_h v = u_H^T M_H u_H.  The gradient of v is constant on each coarse
+// triangle T and the fine elements K tile T, so
+//   v^T A_h v = sum_K a_K |K| |grad v|_K^2 = sum_T |grad u_H|_T^2 (h^2 / 2) sum_{K in T} a_K,
+// with a_K the coefficient at the centroid of K.  In the separable form
+// a_K = a0 + S[.][x_K] . U[y_K] (grid of thirds: the lower element of fine
+// square (a, b) has its centroid at x = 3a + 2, y = 3b + 1, the upper one at
+// 3a + 1, 3b + 2), so with r = n / nH the sum over T is r^2 a0 plus, over the
+// fine rows b = r B + beta of coarse row B, U rows 3b + 1 and 3b + 2 against
+// sums of S over the fine squares of that row that lie in T (a = r A + alpha;
+// below the coarse diagonal alpha > beta, above alpha < beta, and on it the
+// lower element goes to the lower triangle and the upper one to the upper).
+// Those interval sums do not depend on the sample: Tp [K x 2 nH], K = 3 r kx,
+// row (3 beta + e) kx + p for U row 3 (r B + beta) + e (e = 0 holds no
+// centroid: zero), column A for the lower and nH + A for the upper triangle
+// of coarse square (A, B).
+
+// Tp (grid: K x 2 nH entries)
+__global__ __launch_bounds__(256) void k_sep_tri(int n, int nH, int kx,
+                                                 const double* __restrict__ S,
+                                                 double* __restrict__ Tp) {
+  const int r = n / nH, K = 3 * r * kx, NC = 2 * nH, M = 3 * n + 2;
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (id >= (int64_t)K * NC) return;
+  const int k = (int)(id / NC), col = (int)(id - (int64_t)k * NC);
+  const int beta = k / (3 * kx), e = (k / kx) % 3, p = k % kx;
+  const int A = col % nH, upper = col / nH;
+  int lo = 0, hi = 0, off = 0;  // alpha in [lo, hi), x index 3 (r A + alpha) + off
+  if (e == 1) {                 // lower fine elements
+    off = 2;
+    lo = upper ? 0 : beta;
+    hi = upper ? beta : r;
+  } else if (e == 2) {          // upper fine elements
+    off = 1;
+    lo = upper ? 0 : beta + 1;
+    hi = upper ? beta + 1 : r;
+  }
+  double acc = 0.0;
+  for (int alpha = lo; alpha < hi; ++alpha) acc += S[(int64_t)p * M + 3 * (r * A + alpha) + off];
+  Tp[id] = acc;
+}
+
+// part[2 b] = sum over fine nodes of v (M12 v), part[2 b + 1] = v^T A_h v, the
+// partial sums the set-up kernel k_setup_dots forms on the fine mesh (one
+// block per sample).  One workgroup per sample; wave w takes the 16-row
+// strips w, w + 4, ... of the [nH x 2 nH] product U_b Tp on FP64 MFMA and
+// weights each entry with |grad u_H|^2 of its triangle.
+constexpr int kSepTriMaxCT = 8;  // column tiles: nH <= 64
+__global__ __launch_bounds__(256) void k_sep_setup_dots(int64_t B, int n, int nH, int kx,
+                                                        const double* __restrict__ U,
+                                                        const double* __restrict__ Tp,
+                                                        const double* __restrict__ uH, double a0,
+                                                        double* __restrict__ part) {
+  __shared__ double red[2 * 4];
+  const int64_t b = blockIdx.x;
+  if (b >= B) return;
+  const int r = n / nH, K = 3 * r * kx, NC = 2 * nH, M = 3 * n + 2, mH = nH - 1;
+  const int CT = (NC + 15) / 16, RS = (nH + 15) / 16;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  const double* ub = uH + b * (int64_t)mH * mH;
+  auto u = [&](int a, int c) -> double {
+    return (a >= 1 && a <= mH && c >= 1 && c <= mH) ? ub[(c - 1) * mH + (a - 1)] : 0.0;
+  };
+  const double r2a0 = (double)r * r * a0;
+  double s[2] = {0.0, 0.0};
+  for (int strip = w; strip < RS; strip += 4) {
+    v4d acc[kSepTriMaxCT];
+#pragma unroll
+    for (int c = 0; c < kSepTriMaxCT; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int brow = strip * 16 + fr;
+    const double* ur = U + ((int64_t)b * M + (int64_t)3 * r * brow) * kx;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      // A[row][k] in lane row + 16 k; B[k][col] in lane col + 16 k
+      const int k = k0 + fk;
+      const double a = (brow < nH && k < K) ? ur[k] : 0.0;
+#pragma unroll
+      for (int c = 0; c < kSepTriMaxCT; ++c) {
+        if (c < CT) {
+          const int col = 16 * c + fr;
+          const double bv = (col < NC && k < K) ? Tp[(int64_t)k * NC + col] : 0.0;
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[c], 0, 0, 0);
+        }
+      }
+    }
+    // D[row][col]: lane holds col = lane & 15 and, in its q-th value, row 4 q + (lane >> 4)
+#pragma unroll
+    for (int c = 0; c < kSepTriMaxCT; ++c) {
+      if (c >= CT) continue;
+      const int col = 16 * c + fr;
+      if (col >= NC) continue;
+      const int A = col % nH, upper = col / nH;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int Bc = strip * 16 + 4 * q + fk;
+        if (Bc >= nH) continue;
+        double dx, dy;
+        if (upper) {  // (A, B), (A + 1, B + 1), (A, B + 1)
+          dx = u(A + 1, Bc + 1) - u(A, Bc + 1);
+          dy = u(A, Bc + 1) - u(A, Bc);
+        } else {      // (A, B), (A + 1, B), (A + 1, B + 1)
+          dx = u(A + 1, Bc) - u(A, Bc);
+          dy = u(A + 1, Bc + 1) - u(A + 1, Bc);
+        }
+        s[1] += (dx * dx + dy * dy) * (r2a0 + acc[c][q]);
+      }
+    }
+  }
+  // u_H^T M12_H u_H over the coarse interior nodes
+  for (int k = t; k < mH * mH; k += 256) {
+    const int a = k % mH + 1, c = k / mH + 1;
+    const double x = u(a, c);
+    s[0] += x * (6.0 * x + u(a - 1, c) + u(a + 1, c) + u(a, c - 1) + u(a, c + 1) +
+                 u(a + 1, c + 1) + u(a - 1, c - 1));
+  }
+  block_sums<256, 2>(s, red);
+  if (t == 0) {
+    // fine-mesh scaling: M_h / M_H = (h / H)^2, and |K| |grad|^2 = (diff)^2 / (2 r^2)
+    part[2 * b] = s[0] * r * r;
+    part[2 * b + 1] = s[1] / (2.0 * r * r);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_level_sums(int64_t N, const double* __restrict__ lam,
                                                     const double* __restrict__ lam_prev,
                                                     double* __restrict__ Q) {
@@ -704,6 +831,25 @@ hipError_t launch_expand_separable(int64_t B, int n, int s, int kx, int ky, cons
                      tiles_i, tiles, U, S, a0, out, out32, ldo);
   hipLaunchKernelGGL(k_sep_alias, dim3((unsigned)((n - 1 + 255) / 256), (unsigned)B), dim3(256), 0,
                      st, B, n, kx, U, S, a0, out, out32, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_tri(int n, int nH, int kx, const double* S, double* Tp, hipStream_t st) {
+  if (nH < 2 || n % nH || kx < 1 || kx > kSepMaxK) return hipErrorInvalidValue;
+  const int64_t tot = (int64_t)3 * (n / nH) * kx * 2 * nH;
+  hipLaunchKernelGGL(k_sep_tri, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nH, kx,
+                     S, Tp);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_setup_dots(int64_t B, int n, int nH, int kx, const double* U,
+                                 const double* Tp, const double* uH, double a0, double* part,
+                                 hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  if (nH < 2 || nH > 16 * kSepTriMaxCT / 2 || n % nH || kx < 1 || kx > kSepMaxK)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sep_setup_dots, dim3((unsigned)B), dim3(256), 0, st, B, n, nH, kx, U, Tp,
+                     uH, a0, part);
   return hipGetLastError();
 }
 

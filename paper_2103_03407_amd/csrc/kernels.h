@@ -207,6 +207,16 @@ hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t l
 // out[b * ldo ...] and / or out32, equal to launch_expand with the padded edge
 // table up to rounding.  n a multiple of 64, kx <= 64, kx ky <= 1024.
 hipError_t launch_sep_sin(int n, int kmax, double* S, hipStream_t st);
+// The set-up products v^T M v and v^T A v of v = P u_H (mesh n from mesh nH)
+// from coarse quantities, for the separable expansion: Tp [3 (n/nH) kx x 2 nH]
+// the sample-independent interval sums of S (launch_sep_tri once per mesh
+// pair), U the row sums the expansion of the same batch left in its scratch.
+// Writes part[2 b], part[2 b + 1] as the set-up kernel's partial sums with one
+// block per sample (v.M12 v without the mass scale, v.A v).  nH <= 64.
+hipError_t launch_sep_tri(int n, int nH, int kx, const double* S, double* Tp, hipStream_t st);
+hipError_t launch_sep_setup_dots(int64_t B, int n, int nH, int kx, const double* U,
+                                 const double* Tp, const double* uH, double a0, double* part,
+                                 hipStream_t st);
 // dst[i] |= src[i], i < n
 hipError_t launch_or_flags(int64_t n, uint8_t* dst, const uint8_t* src, hipStream_t st);
 hipError_t launch_expand_separable(int64_t B, int n, int s, int kx, int ky, const double* Y,
