@@ -506,15 +506,18 @@ __global__ __launch_bounds__(256) void k_sep_tri(int n, int nH, int kx,
 
 // part[2 b] = sum over fine nodes of v (M12 v), part[2 b + 1] = v^T A_h v, the
 // partial sums the set-up kernel k_setup_dots forms on the fine mesh (one
-// block per sample).  One workgroup per sample; wave w takes the 16-row
-// strips w, w + 4, ... of the [nH x 2 nH] product U_b Tp on FP64 MFMA and
-// weights each entry with |grad u_H|^2 of its triangle.
+// block per sample).  One workgroup per sample; wave w takes the 16-row strip
+// w of the [nH x 2 nH] product U_b Tp on FP64 MFMA (nH <= 64: four strips at
+// most), with Tp staged through LDS in chunks of kSepTriKC rows shared by the
+// four waves, and weights each entry with |grad u_H|^2 of its triangle.
 constexpr int kSepTriMaxCT = 8;  // column tiles: nH <= 64
+constexpr int kSepTriKC = 16, kSepTriLd = 16 * kSepTriMaxCT + 16;
 __global__ __launch_bounds__(256) void k_sep_setup_dots(int64_t B, int n, int nH, int kx,
                                                         const double* __restrict__ U,
                                                         const double* __restrict__ Tp,
                                                         const double* __restrict__ uH, double a0,
                                                         double* __restrict__ part) {
+  __shared__ double sT[kSepTriKC][kSepTriLd];
   __shared__ double red[2 * 4];
   const int64_t b = blockIdx.x;
   if (b >= B) return;
@@ -528,26 +531,34 @@ __global__ __launch_bounds__(256) void k_sep_setup_dots(int64_t B, int n, int nH
   };
   const double r2a0 = (double)r * r * a0;
   double s[2] = {0.0, 0.0};
-  for (int strip = w; strip < RS; strip += 4) {
-    v4d acc[kSepTriMaxCT];
+  v4d acc[kSepTriMaxCT];
 #pragma unroll
-    for (int c = 0; c < kSepTriMaxCT; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
-    const int brow = strip * 16 + fr;
-    const double* ur = U + ((int64_t)b * M + (int64_t)3 * r * brow) * kx;
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      // A[row][k] in lane row + 16 k; B[k][col] in lane col + 16 k
-      const int k = k0 + fk;
-      const double a = (brow < nH && k < K) ? ur[k] : 0.0;
+  for (int c = 0; c < kSepTriMaxCT; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int brow = w * 16 + fr;
+  const double* ur = U + ((int64_t)b * M + (int64_t)3 * r * brow) * kx;
+  for (int k0 = 0; k0 < K; k0 += kSepTriKC) {
+    for (int e = t; e < kSepTriKC * 16 * CT; e += 256) {
+      const int kk = e / (16 * CT), col = e - kk * 16 * CT, k = k0 + kk;
+      sT[kk][col] = (k < K && col < NC) ? Tp[(int64_t)k * NC + col] : 0.0;
+    }
+    __syncthreads();
+    if (w < RS) {
 #pragma unroll
-      for (int c = 0; c < kSepTriMaxCT; ++c) {
-        if (c < CT) {
-          const int col = 16 * c + fr;
-          const double bv = (col < NC && k < K) ? Tp[(int64_t)k * NC + col] : 0.0;
-          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[c], 0, 0, 0);
-        }
+      for (int kk = 0; kk < kSepTriKC; kk += 4) {
+        // A[row][k] in lane row + 16 k; B[k][col] in lane col + 16 k
+        const int k = k0 + kk + fk;
+        const double a = (brow < nH && k < K) ? ur[k] : 0.0;
+#pragma unroll
+        for (int c = 0; c < kSepTriMaxCT; ++c)
+          if (c < CT)
+            acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sT[kk + fk][16 * c + fr], acc[c], 0,
+                                                          0, 0);
       }
     }
-    // D[row][col]: lane holds col = lane & 15 and, in its q-th value, row 4 q + (lane >> 4)
+    __syncthreads();
+  }
+  // D[row][col]: lane holds col = lane & 15 and, in its q-th value, row 4 q + (lane >> 4)
+  if (w < RS) {
 #pragma unroll
     for (int c = 0; c < kSepTriMaxCT; ++c) {
       if (c >= CT) continue;
@@ -556,7 +567,7 @@ __global__ __launch_bounds__(256) void k_sep_setup_dots(int64_t B, int n, int nH
       const int A = col % nH, upper = col / nH;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int Bc = strip * 16 + 4 * q + fk;
+        const int Bc = w * 16 + 4 * q + fk;
         if (Bc >= nH) continue;
         double dx, dy;
         if (upper) {  // (A, B), (A + 1, B + 1), (A, B + 1)
