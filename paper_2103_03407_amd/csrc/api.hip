@@ -1016,9 +1016,20 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
         }
       }
     }
-    CK(launch_final_dots<T>(nh, Bn, uHb, nH, t, pp[0], pp[1], wT, S, part, rx, st),
-       "final dots");
-    CK(launch_scalar(PH_FINAL, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
+    // The Rayleigh quotient of w = v_n + t.  The PCG tracks it step by step,
+    // mu + f / m with f = w^T (A - mu M) w and m = w^T M w updated from the
+    // step's own FP64 dot products; with FP64 storage that is the quotient of
+    // the returned w up to the rounding of a few dot products, so no pass over
+    // the fine vectors is needed.  In FP32 storage the tracked products carry
+    // FP32 errors, and G needs the sum of w: there the final kernel forms
+    // w^T A w and w^T M w in FP64 from the stored vectors.
+    if (!kMixed && !g) {
+      CK(launch_scalar(PH_FINAL_TRACKED, nh, Bn, 0, part, S, 0.0, 0, st), "scalar");
+    } else {
+      CK(launch_final_dots<T>(nh, Bn, uHb, nH, t, pp[0], pp[1], wT, S, part, rx, st),
+         "final dots");
+      CK(launch_scalar(PH_FINAL, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
+    }
   }
   return MLQMC_OK;
 }

@@ -1285,6 +1285,13 @@ __global__ __launch_bounds__(256) void k_scalar(int phase, int n, int64_t B, int
       if (!isfinite(lam)) S.flags[b] |= MLQMC_FLAG_NONFINITE;
       break;
     }
+    case PH_FINAL_TRACKED: {  // mu + f/m of the last step's w (FP64 storage only)
+      const double lam = S.mu[b] + S.f[b] / S.m[b];
+      S.lam[b] = lam;
+      if (S.lin_acc) S.lin_acc[b] += S.its[b];
+      if (!isfinite(lam)) S.flags[b] |= MLQMC_FLAG_NONFINITE;
+      break;
+    }
   }
 }
 

@@ -153,7 +153,14 @@ hipError_t launch_final_dots(int n, int64_t B, const double* uH, int nH, const T
                              int reaction, hipStream_t st);
 
 // scalar phases: one wavefront per sample sums that sample's block partials
-enum ScalarPhase { PH_SETUP = 0, PH_FIRST_RZ = 1, PH_ALPHA = 2, PH_BETA = 3, PH_FINAL = 4 };
+enum ScalarPhase {
+  PH_SETUP = 0,
+  PH_FIRST_RZ = 1,
+  PH_ALPHA = 2,
+  PH_BETA = 3,
+  PH_FINAL = 4,
+  PH_FINAL_TRACKED = 5  // the eigenvalue from the tracked quotient (no partial sums)
+};
 hipError_t launch_scalar(int phase, int n, int64_t B, int nblk, const double* part,
                          const FineState& S, double rtol, int max_it, hipStream_t st);
 
