@@ -591,6 +591,21 @@ def test_pcg_graph_replays_ahead_match_eager(ctx, prec):
     assert np.array_equal(li, li_ref)
 
 
+def test_pcg_graph_follows_the_coarse_mesh(ctx):
+    # the replayed PCG steps interpolate vn from the coarse vectors: a graph
+    # captured for one coarse mesh must not be replayed for another (same
+    # fine mesh, batch and buffers), nor after the coarse vectors moved
+    Y = np.ascontiguousarray(_points(1024, 64, 2, 0, 12, range(16)))
+    for nH in (32, 16, 32, 8):
+        lv = (128, 64, nH, 8, 0, 0)
+        ref = np.empty(16)
+        ctx.eig_level(lv, Y, ref, np.zeros(16, np.uint8), opts=m.default_opts(pcg_graph=0))
+        got, fl = np.empty(16), np.zeros(16, np.uint8)
+        ctx.eig_level(lv, Y, got, fl, opts=m.default_opts(pcg_graph=1))
+        assert not fl.any(), nH
+        assert np.array_equal(got, ref), nH
+
+
 def test_tuning_changes_speed_not_results(ctx, tmp_path):
     Y = np.ascontiguousarray(_points(1024, 64, 2, 0, 10, range(40)))
     lv = (128, 64, 32, 8, 0, 0)
