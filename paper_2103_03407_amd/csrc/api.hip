@@ -879,11 +879,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
       CK(launch_setup_dots<T>(nh, Bn, uHb, nH, wT, part, rx, st), "setup dots");
       CK(launch_scalar(PH_SETUP, nh, Bn, nblk0, part, S, 0.0, 0, st), "scalar");
     }
-    // With FP64 storage vn is not stored: the apply kernel interpolates it
-    // from the coarse vectors as this kernel does (FP32 storage keeps it: the
-    // post-smoothing reads it for the product r.vn)
-    T* const vn_st = kMixed ? vn : nullptr;
-    CK(launch_setup_rhs<T>(nh, Bn, uHb, nH, wT, S, r, vn_st, mvn, rx, st), "setup rhs");
+    CK(launch_setup_rhs<T>(nh, Bn, uHb, nH, wT, S, r, vn, mvn, rx, st), "setup rhs");
 
     // z = K^{-1} r by one V-cycle: fused pre-smoothing + restriction per level,
     // the LDS bottom solve, fused coarse correction + post-smoothing per level;
@@ -939,16 +935,15 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     all_active = false;
     const int nblk_post = post_strips(nh, Bn);
     CK(launch_scalar(PH_FIRST_RZ, nh, Bn, nblk_post, part, S, 0.0, 0, st), "scalar");
-    // first apply: z, vn (FP32 storage; interpolated from the coarse vectors
-    // in FP64), 2 weights per node in (M vn is formed from vn; no previous p;
-    // t = 0 not read); p out (q feeds only the partial sums)
-    const double ab = (double)sz * Bn * (((kMixed ? 5 : 4) + 3 * rx) * D(nh));
+    // first apply: z, vn, 2 weights per node in (M vn is formed from vn; no
+    // previous p; t = 0 not read); p out (q feeds only the partial sums)
+    const double ab = (double)sz * Bn * ((5 + 3 * rx) * D(nh));
     // one PCG iteration: apply (with the previous step's t update), alpha and
     // the eigenvalue test, the V-cycle (with the residual update), beta
     auto iteration = [&](int it) -> mlqmc_status {
       if (it == 0) ctx->t_begin(MLQMC_K_APPLY);
-      CK(launch_pupdate_apply<T>(nh, Bn, zc, vn_st, uHb, nH, pp[cur], wT, t, S, it == 0,
-                                 pp[1 - cur], nullptr, part, rx, st),
+      CK(launch_pupdate_apply<T>(nh, Bn, zc, vn, pp[cur], wT, t, S, it == 0, pp[1 - cur],
+                                 nullptr, part, rx, st),
          "apply");
       if (it == 0) ctx->t_end(MLQMC_K_APPLY, ab);
       cur = 1 - cur;
@@ -991,7 +986,7 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
         st = keep;
         return r;
       }, graph_key<T>(nh, Bn, o, S, {zc, zo, rc, ro, pp[0], pp[1], vn, mvn, wT, t, part, act,
-                                     active, vn_st, uHb, (const void*)(uintptr_t)nH},
+                                     active, uHb, (const void*)(uintptr_t)nH},
                       W, X, Xb, Bv, nblk0, nblk_post), &exec));
       // Replays before the first read-back of the activity: as many as this
       // batch needed the last time it ran (converged samples exit at once, so

@@ -431,9 +431,8 @@ __global__ __launch_bounds__(NTC) void k_setup_dots(MGeo g, Coarse cv,
 }
 
 // r = -(A v_n - rho M v_n) (FP64 arithmetic on the weights of storage type
-// T), vn = v_n (unless vn is null: the PCG kernels then interpolate it),
-// mvn = M v_n (t starts at 0 without being stored: the PCG kernels read t only
-// from its third step on)
+// T), vn = v_n, mvn = M v_n (t starts at 0 without being stored: the PCG
+// kernels read t only from its third step on)
 template <typename T, int NTC, bool kR>
 __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
                                                    const T* __restrict__ w, FineState S,
@@ -458,7 +457,7 @@ __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
                        const T rT = (T)rv;
                        const int64_t o = b * g.P + k;
                        __builtin_nontemporal_store(rT, &r[o]);
-                       if (vn) __builtin_nontemporal_store((T)(vs * rc[ci]), &vn[o]);
+                       __builtin_nontemporal_store((T)(vs * rc[ci]), &vn[o]);
                        __builtin_nontemporal_store((T)(vs * mv), &mvn[o]);
                      });
 }
@@ -467,9 +466,8 @@ __global__ __launch_bounds__(NTC) void k_setup_rhs(MGeo g, Coarse cv,
 
 // p = z - c2 vn + beta p_in (first: beta = 0), q = (A - mu M) p;
 // partials p.q, vn.q, p.M vn
-template <typename T, int NTC, bool kR, bool kVc>
-__global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, Coarse cv,
-                                                       const T* __restrict__ z,
+template <typename T, int NTC, bool kR>
+__global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, const T* __restrict__ z,
                                                        const T* __restrict__ vn,
                                                        const T* __restrict__ pin,
                                                        const T* __restrict__ w,
@@ -479,18 +477,14 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, Coarse cv,
                                                        double* __restrict__ part) {
   // M vn is recomputed from a ring of vn rows (vn is read anyway) instead of
   // being read; in FP32 storage it then differs from the stored M vn the
-  // other kernels read by rounding only.  With kVc (FP64 storage) vn itself
-  // is not read either: vn = vs P u_H is interpolated from the coarse vector
-  // with the set-up kernel's arithmetic, so it equals the vector the set-up
-  // formed, and the set-up does not store it.
+  // other kernels read by rounding only
   __shared__ T ring[4][NTC + 2];
   __shared__ T ringv[4][NTC + 2];
   int64_t b;
   int c0, j0, j1, blk, dir;
   if (!map_march<NTC>(g, b, c0, j0, j1, blk, dir) || !S.active[b]) return;
   const T* zz = z + b * g.P;
-  const T* vb = kVc ? nullptr : vn + b * g.P;
-  const double vsc = kVc ? S.vs[b] : 0.0;
+  const T* vb = vn + b * g.P;
   const T* pb = pin + b * g.P;
   const T* wx = w + b * wblk<kR>() * g.P;
   const T* wy = wx + g.P;
@@ -513,7 +507,6 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, Coarse cv,
   // its ring fill for its stencil step.
   struct Src {
     T z, v, p, zh, vh, ph;
-    CoarseSrc cs, csh;  // with kVc: the coarse sources of v and vh
   };
   struct Row {
     Wts<T, kR> w;
@@ -522,31 +515,17 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, Coarse cv,
   auto fetch_src = [&](int j, Src& f) {
     const bool rowok = (j >= 1 && j <= n - 1);
     f.z = f.v = f.p = f.zh = f.vh = f.ph = T(0);
-    if constexpr (kVc) f.cs = f.csh = CoarseSrc{0.0, 0.0, 0.0, 0, 0};
     if (rowok && c >= 1) {
       const int k = j * n + c;
       f.z = zz[k];
-      if constexpr (kVc)
-        f.cs = coarse_src(cv, g, b, k);
-      else
-        f.v = vb[k];
+      f.v = vb[k];
       if (!first) f.p = pb[k];
     }
     if (rowok && hok) {
       const int k = j * n + ch;
       f.zh = zz[k];
-      if constexpr (kVc)
-        f.csh = coarse_src(cv, g, b, k);
-      else
-        f.vh = vb[k];
+      f.vh = vb[k];
       if (!first) f.ph = pb[k];
-    }
-  };
-  // vn and its halo value from the sources (interpolated at ring-store time)
-  auto vfill = [&](Src& f) {
-    if constexpr (kVc) {
-      f.v = (T)(vsc * coarse_val(cv, f.cs));
-      f.vh = (T)(vsc * coarse_val(cv, f.csh));
     }
   };
   auto store = [&](int j, const Src& f) {
@@ -571,10 +550,8 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, Coarse cv,
   const int count = j1 - j0;
   Src f, fn;
   fetch_src(jf - dir, f);
-  vfill(f);
   store(jf - dir, f);
   fetch_src(jf, f);
-  vfill(f);
   store(jf, f);
   T sv = f.v, sp = f.p;  // vn and p_prev of the row the next stencil step handles
   fetch_src(jf + dir, fn);
@@ -582,7 +559,6 @@ __global__ __launch_bounds__(NTC) void k_pupdate_apply(MGeo g, Coarse cv,
   fetch_row(jf, rw);
   for (int i = 0; i < count; ++i) {
     const int j = jf + i * dir;
-    vfill(fn);
     store(j + dir, fn);
     const T nv = fn.v, np = fn.p;
     const Row rc = rw;
@@ -1446,26 +1422,13 @@ hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const T*
 }
 
 template <typename T>
-hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const double* uH,
-                                int nH, const T* pin, const T* w, T* t, const FineState& S,
-                                int first, T* pout, T* q, double* part, int reaction,
-                                hipStream_t st) {
-  const bool vc = vn == nullptr;  // vn from the coarse vectors (FP64 storage)
-  if (vc && (sizeof(T) != 8 || !uH || nH < 2 || n % nH)) return hipErrorInvalidValue;
-  const Coarse cv = vc ? coarse_of(uH, nH, n) : Coarse{nullptr, 0, 0, 0.0};
+hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
+                                const T* w, T* t, const FineState& S, int first, T* pout, T* q,
+                                double* part, int reaction, hipStream_t st) {
   MARCH_DISPATCH(n, KR_DISPATCH(reaction, {
     const MGeo g = mgeo<NTC>(n, B);
-    bool done = false;
-    if constexpr (sizeof(T) == 8) {
-      if (vc) {
-        hipLaunchKernelGGL((k_pupdate_apply<T, NTC, kR, true>), mgrid<NTC>(g), dim3(NTC), 0, st,
-                           g, cv, z, vn, pin, w, t, S, first, pout, q, part);
-        done = true;
-      }
-    }
-    if (!done)
-      hipLaunchKernelGGL((k_pupdate_apply<T, NTC, kR, false>), mgrid<NTC>(g), dim3(NTC), 0, st,
-                         g, cv, z, vn, pin, w, t, S, first, pout, q, part);
+    hipLaunchKernelGGL((k_pupdate_apply<T, NTC, kR>), mgrid<NTC>(g), dim3(NTC), 0, st, g, z, vn,
+                       pin, w, t, S, first, pout, q, part);
   }));
   return hipGetLastError();
 }
@@ -1628,9 +1591,9 @@ hipError_t launch_apply_plain(int n, int64_t B, const double* w, const double* s
                                            int, hipStream_t);                                   \
   template hipError_t launch_setup_rhs<T>(int, int64_t, const double*, int, const T*,           \
                                           const FineState&, T*, T*, T*, int, hipStream_t);      \
-  template hipError_t launch_pupdate_apply<T>(int, int64_t, const T*, const T*, const double*, \
-                                              int, const T*, const T*, T*, const FineState&,    \
-                                              int, T*, T*, double*, int, hipStream_t);          \
+  template hipError_t launch_pupdate_apply<T>(int, int64_t, const T*, const T*, const T*,       \
+                                              const T*, T*, const FineState&, int, T*, T*,      \
+                                              double*, int, hipStream_t);                       \
   template hipError_t launch_final_dots<T>(int, int64_t, const double*, int, const T*,          \
                                            const T*, const T*, const T*, const FineState&,      \
                                            double*, int, hipStream_t);

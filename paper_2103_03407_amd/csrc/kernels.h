@@ -118,13 +118,11 @@ hipError_t launch_setup_rhs(int n, int64_t B, const double* uH, int nH, const T*
                             hipStream_t st);
 // the new direction pout = z - c2 vn + beta pin and q = (A - mu M) pout (stored
 // only if q != nullptr), with the dot-product partials of the step (M vn is
-// formed from vn in the kernel).  vn null (T = double): vn = vs P u_H is
-// interpolated from the coarse vectors uH (mesh nH), as the set-up formed it
+// formed from vn in the kernel)
 template <typename T>
-hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const double* uH,
-                                int nH, const T* pin, const T* w, T* t, const FineState& S,
-                                int first, T* pout, T* q, double* part, int reaction,
-                                hipStream_t st);
+hipError_t launch_pupdate_apply(int n, int64_t B, const T* z, const T* vn, const T* pin,
+                                const T* w, T* t, const FineState& S, int first, T* pout, T* q,
+                                double* part, int reaction, hipStream_t st);
 // fused V-cycle level, pre-smoothing from zero and restriction:
 //   X = Chebyshev-weighted Jacobi sweeps on A X = rhs from X = 0;
 //   rhs_c = P^T (rhs - A X); with p != nullptr (the current direction) the rhs
