@@ -631,18 +631,22 @@ def roofline(ctx, m, w, opts, prec: str, kernel_class: str, leg, cfg: int):
                         "bytes_per_launch": lds_bytes}}
     if kernel_class == "coeff":
         # the coefficient expansion: the product the library formed (the dense
-        # Y Phi, 2 s E flops per sample, or the separable one, 8 kx per
-        # weight pair plus the row sums), both on FP64 MFMA; flops from the
-        # library's model
+        # Y Phi, 2 s E flops per sample, or the separable one, two element
+        # products of kx terms per node plus the row sums), both on FP64 MFMA;
+        # flops from the library's model
         flops_per_launch = leg["kflops"] / launches
         achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
         fam = w.family()
-        dense = w.problem == 2 or not all(
-            4 * int(max(fam["k1"][:lv.s_fine])) < lv.s_fine for lv in w.levels if lv.n_coarse)
+
+        def separable(s):
+            kx, ky = int(max(fam["k1"][:s])), int(max(fam["k2"][:s]))
+            return 4 * kx < s and kx <= 32 and kx * ky <= 1024
+
+        dense = w.problem == 2 or not all(separable(lv.s_fine) for lv in w.levels if lv.n_coarse)
         peak = PEAK_FP64_MFMA_TFS
         tkey = kname
         if not dense:
-            kname, tkey = "k_sep_mfma+k_sep_rows+k_sep_alias", "k_sep"
+            kname, tkey = "k_sep_march+k_sep_rows", "k_sep"
         return {"bound": "mfma", "kernel": kname,
                 "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4),

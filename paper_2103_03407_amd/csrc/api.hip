@@ -154,9 +154,10 @@ struct mlqmc_ctx {
   int64_t mem_cap = 0;
 
   // The separable table for (n, s), or nullptr when the dense product is
-  // cheaper: the separable form costs 8 kx per padded node and sample (two
-  // weights, two elements, kx multiply-adds each) on the vector units
-  // against 4 s on the matrix cores, so it is taken when 2 kx < s / 2.
+  // taken: the separable form costs 4 kx flops per padded node and sample (two
+  // element products of kx terms) against 4 s for the table product, both on
+  // the matrix cores, plus the row sums U and their traffic; it is taken for
+  // kx <= 32 and 4 kx < s, which leaves the row sums a wide margin.
   mlqmc_status sep_table(int n, int s, SepTable** out) {
     *out = nullptr;
     if (islands || n < 64 || (n % 64) || s < 1 || (int)h_k1.size() < s) return MLQMC_OK;
@@ -165,7 +166,7 @@ struct mlqmc_ctx {
       kx = std::max(kx, h_k1[j]);
       ky = std::max(ky, h_k2[j]);
     }
-    if (kx > 64 || kx * ky > 1024 || !(4 * kx < s)) return MLQMC_OK;
+    if (kx > 32 || kx * ky > 1024 || !(4 * kx < s)) return MLQMC_OK;
     SepTable& t = seps[{n, s}];
     if (!t.S) {
       const int kmax = std::max(kx, ky), cells = kx * ky;
@@ -855,9 +856,10 @@ mlqmc_status fine_batched(mlqmc_ctx* ctx, const mlqmc_opts* o, int nh, int s, co
     const int rows = rx ? s + 1 : s;
     const double wout = (double)sz * (double)Bn * EW(nh);
     if (sep) {
-      const double M3 = 3.0 * nh + 2.0;
+      // U: 3 n + 2 rows stored, 2 n + 1 of them (the element centroids) formed
+      const double M3 = 3.0 * nh + 2.0, Mc = 2.0 * nh + 1.0;
       ctx->t_end(MLQMC_K_COEFF, 8.0 * (double)Bn * s + 16.0 * (double)Bn * M3 * sep->kx + wout,
-                 (double)Bn * (8.0 * sep->kx * P(nh) + 2.0 * M3 * sep->kx * sep->ky));
+                 (double)Bn * (4.0 * sep->kx * P(nh) + 2.0 * Mc * sep->kx * sep->ky));
     } else {
       ctx->t_end(MLQMC_K_COEFF, 8.0 * ((double)Bn * rows + (double)rows * EW(nh)) + wout,
                  2.0 * rows * (double)EW(nh) * Bn);

@@ -309,8 +309,13 @@ __global__ __launch_bounds__(256) void k_sep_sin(int n, int kmax, double* __rest
 }
 
 // U[b][m][p] for m in [m0, m0 + 64) of sample b (grid: m tiles x samples):
-// C_b from the terms of each (k1, k2) cell in term order, then the row sums
-constexpr int kSepMaxCells = 1024;
+// C_b from the terms of each (k1, k2) cell in term order, then the row sums,
+// with the S values of the tile's rows staged in LDS kSepRowsQC terms q at a
+// time.  Rows m = 3 t hold no element centroid and are never used as
+// factors: they are stored as zeros (the set-up products multiply them by
+// zero interval sums).
+constexpr int kSepMaxK = 32, kSepMaxCells = 1024;
+constexpr int kSepRowsQC = 32;
 __global__ __launch_bounds__(256) void k_sep_rows(int n, int s, int kx, int ky,
                                                   const double* __restrict__ Y, int64_t ldY,
                                                   const double* __restrict__ c,
@@ -319,143 +324,200 @@ __global__ __launch_bounds__(256) void k_sep_rows(int n, int s, int kx, int ky,
                                                   const double* __restrict__ S,
                                                   double* __restrict__ U) {
   __shared__ double sC[kSepMaxCells];
+  __shared__ double sS[kSepRowsQC][64];
   const int64_t b = blockIdx.y;
   const int M = 3 * n + 2;
-  const int m0 = blockIdx.x * 64;
-  for (int cell = threadIdx.x; cell < kx * ky; cell += 256) {
+  const int m0 = blockIdx.x * 64, t = threadIdx.x;
+  for (int cell = t; cell < kx * ky; cell += 256) {
     double v = 0.0;
-    for (int t = cell_start[cell]; t < cell_start[cell + 1]; ++t) {
-      const int j = cell_term[t];
+    for (int k = cell_start[cell]; k < cell_start[cell + 1]; ++k) {
+      const int j = cell_term[k];
       v += Y[b * ldY + j] * c[j];
     }
     sC[cell] = v;
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < 64 * kx; e += 256) {
-    const int m = m0 + e / kx, p = e % kx;
-    if (m >= M) continue;
-    double u = 0.0;
-    for (int q = 0; q < ky; ++q) u += sC[p * ky + q] * S[(int64_t)q * M + m];
-    U[(b * M + m) * kx + p] = u;
+  // thread t owns the outputs e = t + 256 u (row m0 + e / kx, term e % kx);
+  // 64 kx <= 256 kSepMaxK / 4
+  constexpr int kPer = kSepMaxK / 4;
+  double acc[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) acc[u] = 0.0;
+  for (int q0 = 0; q0 < ky; q0 += kSepRowsQC) {
+    __syncthreads();
+    for (int e = t; e < kSepRowsQC * 64; e += 256) {
+      const int qq = e >> 6, r = e & 63, q = q0 + qq, m = m0 + r;
+      sS[qq][r] = (q < ky && m < M) ? S[(int64_t)q * M + m] : 0.0;
+    }
+    __syncthreads();
+    const int qn = min(kSepRowsQC, ky - q0);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = t + 256 * u;
+      if (e >= 64 * kx) break;
+      const int r = e / kx, p = e - r * kx;
+      if ((m0 + r) % 3 == 0) continue;
+      const double* cp = sC + p * ky + q0;
+      double v = acc[u];
+      for (int qq = 0; qq < qn; ++qq) v += cp[qq] * sS[qq][r];
+      acc[u] = v;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = t + 256 * u;
+    if (e >= 64 * kx) break;
+    const int r = e / kx, p = e - r * kx, m = m0 + r;
+    if (m < M) U[(b * M + m) * kx + p] = acc[u];
   }
 }
 
-// Padded [WX | WY] of B samples from U, as a batched matrix product on FP64
-// MFMA (v_mfma_f64_16x16x4f64): with rows j and columns i,
-//   WX = a0 + (U_{3j-1} S_{3i-2} + U_{3j+1} S_{3i-1}) / 2,
-//   WY = a0 + (U_{3j-2} S_{3i-1} + U_{3j-1} S_{3i+1}) / 2,
-// each a [rows x kx] x [kx x columns] product per sample.  A block (8 waves)
-// owns a 64 x 64 tile of both outputs of one sample: wave w the rows
-// j0 + 16 (w & 3) .. + 15 and columns i0 + 32 (w >> 2) .. + 31 (two 16 x 16
-// MFMA tiles of WX and two of WY).  K runs in chunks of kSmK terms staged in
-// LDS as [offset][p][row or column] (rows padded by 16 doubles so that the
-// four 16-lane groups of a fragment read fall on different banks); terms
-// p >= kx and rows m outside [0, 3n + 2) are zero.  Positions that are not
-// edges of interior nodes get a0, as in the table product; the
-// right-boundary aliases of WX (column 0, rows 2..n) come from k_sep_alias.
-constexpr int kSepMaxK = 64;
-constexpr int kSmT = 64, kSmK = 8, kSmLd = kSmT + 16;
-__global__ __launch_bounds__(512) void k_sep_mfma(int64_t B, int n, int kx, int tiles_i,
-                                                  int tiles, const double* __restrict__ U,
-                                                  const double* __restrict__ S, double a0,
-                                                  double* __restrict__ out,
-                                                  float* __restrict__ out32, int64_t ldo) {
-  __shared__ double sS[3][kSmK][kSmLd];
-  __shared__ double sU[3][kSmK][kSmLd];
-  // XCD-aware: the tiles of one sample run on one XCD (block L on XCD L mod 8)
-  const int64_t L = blockIdx.x;
-  const int64_t q = L >> 3;
-  const int64_t b = ((q / tiles) << 3) + (L & 7);
-  if (b >= B) return;
-  const int tile = (int)(q % tiles);
-  const int i0 = (tile % tiles_i) * kSmT, j0 = (tile / tiles_i) * kSmT;
-  const int M = 3 * n + 2, P = (n + 2) * n;
-  const double* Ub = U + b * (int64_t)M * kx;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int fr = lane & 15, fk = lane >> 4;
-  const int rw = (w & 3) * 16, cw = (w >> 2) * 32;
-  v4d ax[2], ay[2];
-#pragma unroll
-  for (int c = 0; c < 2; ++c) ax[c] = ay[c] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int p0 = 0; p0 < kx; p0 += kSmK) {
-    // stage: S at m = 3i - 2, 3i - 1, 3i + 1 of the tile's columns; U rows
-    // m = 3j - 2, 3j - 1, 3j + 1 of its rows (p fastest in global memory)
-    for (int e = t; e < 3 * kSmK * kSmT; e += 512) {
-      const int o = e / (kSmK * kSmT), rem = e - o * (kSmK * kSmT);
-      const int off = o == 0 ? -2 : (o == 1 ? -1 : 1);
-      {
-        const int pp = rem / kSmT, c = rem - pp * kSmT, p = p0 + pp;
-        const int m = 3 * (i0 + c) + off;
-        sS[o][pp][c] = (p < kx && m >= 0 && m < M) ? S[(int64_t)p * M + m] : 0.0;
-      }
-      {
-        const int r = rem / kSmK, pp = rem - r * kSmK, p = p0 + pp;
-        const int m = 3 * (j0 + r) + off;
-        sU[o][pp][r] = (p < kx && m >= 0 && m < M) ? Ub[(int64_t)m * kx + p] : 0.0;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kSmK; kk += 4) {
-      // A[row][k] in lane row + 16 k; B[k][col] in lane col + 16 k
-      const double um2 = sU[0][kk + fk][rw + fr], um1 = sU[1][kk + fk][rw + fr],
-                   up1 = sU[2][kk + fk][rw + fr];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int col = cw + 16 * c + fr;
-        const double sa = sS[0][kk + fk][col], sb = sS[1][kk + fk][col],
-                     sc = sS[2][kk + fk][col];
-        ax[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(um1, sa, ax[c], 0, 0, 0);
-        ax[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(up1, sb, ax[c], 0, 0, 0);
-        ay[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(um2, sb, ay[c], 0, 0, 0);
-        ay[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(um1, sc, ay[c], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-  // D[row][col]: lane holds col = lane & 15 and, in its r-th value, row 4 r + (lane >> 4)
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int i = i0 + cw + 16 * c + fr;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int j = j0 + rw + 4 * r + fk;
-      if (j > n + 1) continue;
-      const double vx = (i >= 1 && j >= 1 && j <= n - 1) ? a0 + 0.5 * ax[c][r] : a0;
-      const double vy = (i >= 1 && j >= 1 && j <= n) ? a0 + 0.5 * ay[c][r] : a0;
-      const int64_t o = b * ldo + (int64_t)j * n + i;
-      if (out) {
-        out[o] = vx;
-        out[o + P] = vy;
-      }
-      if (out32) {
-        out32[o] = (float)vx;
-        out32[o + P] = (float)vy;
-      }
-    }
-  }
-}
-
-// WX at column 0 of rows 2..n: the edge (n-1, j-1)-(n, j-1) into the right
-// boundary, at x = (n - 2/3) h and (n - 1/3) h (grid: samples; thread = row)
-__global__ __launch_bounds__(256) void k_sep_alias(int64_t B, int n, int kx,
+// Padded [WX | WY] of B samples from U on FP64 MFMA (v_mfma_f64_16x16x4f64),
+// with no LDS: a wave owns 32 columns of one sample and marches down all
+// n + 2 rows in steps of 16 (the row index of the MFMA tiles), forming per node
+// two element products of kx terms, each used by two edges:
+//   Lo(i, j)  = U_{3j+1} . S_{3i-1}  (lower element of square (i-1, j)),
+//   Up'(i, j) = U_{3j-1} . S_{3i+1}  (upper element of square (i, j-1)),
+//   WX(i, j) = a0 + (Up'(i-1, j) + Lo(i, j)) / 2,
+//   WY(i, j) = a0 + (Lo(i, j-1) + Up'(i, j)) / 2,
+// the shifts by one column and one row being lane shuffles of the MFMA
+// results (the row above the tile is carried from the previous step; the
+// column left of the wave is a short dot product on the vector units).  The
+// S fragments of the wave's columns stay in registers for every term (they
+// depend on neither the sample nor the row); the two U rows of a step come
+// from global memory (L2: the waves of one sample run on one XCD).  Two waves
+// per SIMD; no barriers; K is padded to a multiple of 4 only.  NK = ceil(kx / 4).
+// Positions that are not edges of interior nodes get a0, as in the table
+// product.  Measured alternatives, all slower: the two edge products of each
+// weight formed directly (four per node, 1.1 times as long), 64 x 64 tiles
+// staged through LDS (1.7 times), 16 columns per wave (three waves per SIMD,
+// 1.2 times), and the next step's U rows loaded before this step's stores
+// (one wave per SIMD at 32 columns, 1.4 times in mixed precision).
+constexpr int kSepMarchMaxNK = kSepMaxK / 4;
+template <int NK>
+__global__ __launch_bounds__(256) void k_sep_march(int64_t B, int n, int kx, int cw_per,
+                                                   int64_t per_xcd,
                                                    const double* __restrict__ U,
                                                    const double* __restrict__ S, double a0,
                                                    double* __restrict__ out,
                                                    float* __restrict__ out32, int64_t ldo) {
-  const int64_t b = blockIdx.y;
-  const int j = 2 + blockIdx.x * 256 + threadIdx.x;
-  if (b >= B || j > n) return;
-  const int M = 3 * n + 2, je = j - 1;
+  constexpr int C = 2;  // 16-column MFMA tiles per wave
+  // XCD-aware: block L runs on XCD L mod 8 and takes logical block
+  // (L mod 8) per_xcd + L / 8, so consecutive logical blocks (the column waves
+  // of one sample) share an XCD and its L2
+  const int64_t L = blockIdx.x;
+  const int64_t lb = (L & 7) * per_xcd + (L >> 3);
+  const int lane = threadIdx.x & 63;
+  const int64_t W = lb * 4 + (threadIdx.x >> 6);
+  const int64_t b = W / cw_per;
+  if (b >= B) return;
+  const int ic = (int)(W - b * cw_per) * 16 * C;
+  const int M = 3 * n + 2, P = (n + 2) * n;
+  const int fr = lane & 15, fk = lane >> 4;
   const double* Ub = U + b * (int64_t)M * kx;
-  double acc = 0.0;
-  for (int p = 0; p < kx; ++p)
-    acc += S[(int64_t)p * M + 3 * n - 2] * Ub[(int64_t)(3 * je - 1) * kx + p] +
-           S[(int64_t)p * M + 3 * n - 1] * Ub[(int64_t)(3 * je + 1) * kx + p];
-  const double v = a0 + 0.5 * acc;
-  const int64_t o = b * ldo + (int64_t)j * n;
-  if (out) out[o] = v;
-  if (out32) out32[o] = (float)v;
+  // B[k][col] in lane col + 16 k: column i = ic + 16 c + fr, term p = 4 kk + fk.
+  // Column 0 holds no WX edge of its own: its Lo takes the S values of column
+  // n, and the column left of it is column n - 1, so that its WX is the edge
+  // into the right boundary, which the padded layout stores at column 0 of the
+  // next row (its WY is a0).
+  double sl[C][NK], su[C][NK], sh[NK];
+  const int ih = ic == 0 ? n - 1 : ic - 1;  // the halo column of Up'
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk) {
+    const int p = 4 * kk + fk;
+    const bool ok = p < kx;
+    const double* Sp = S + (int64_t)p * M;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int i = ic + 16 * c + fr, ia = i == 0 ? n : i;
+      sl[c][kk] = ok ? Sp[3 * ia - 1] : 0.0;
+      su[c][kk] = ok ? Sp[3 * i + 1] : 0.0;
+    }
+    sh[kk] = ok ? Sp[3 * ih + 1] : 0.0;
+  }
+  const int src_col = (lane & 48) | ((fr + 15) & 15);  // column i - 1 of the same 16
+  const int src_row = (lane + 48) & 63;                // row 4 r + fk - 1 (fk > 0)
+  // A[row][k] in lane row + 16 k: U rows 3 j + 1 (squares j in [0, n)) and
+  // 3 j - 1 (squares j - 1) of row j = jt + fr; zero elsewhere
+  auto load_u = [&](int jt, double (&ul)[NK], double (&uu)[NK]) {
+    const int j = jt + fr;
+    const bool okl = j <= n - 1, oku = j >= 1 && j <= n;
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const int p = 4 * kk + fk;
+      const bool ok = p < kx;
+      ul[kk] = (ok && okl) ? Ub[(int64_t)(3 * j + 1) * kx + p] : 0.0;
+      uu[kk] = (ok && oku) ? Ub[(int64_t)(3 * j - 1) * kx + p] : 0.0;
+    }
+  };
+  double carry[C];  // Lo of the row above the tile, in lanes fk = 0
+#pragma unroll
+  for (int c = 0; c < C; ++c) carry[c] = 0.0;
+  for (int jt = 0; jt < n + 2; jt += 16) {
+    double ul[NK], uu[NK];
+    load_u(jt, ul, uu);
+    v4d lo[C], up[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) lo[c] = up[c] = v4d{0.0, 0.0, 0.0, 0.0};
+    double hd = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        lo[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ul[kk], sl[c][kk], lo[c], 0, 0, 0);
+        up[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(uu[kk], su[c][kk], up[c], 0, 0, 0);
+      }
+      hd += uu[kk] * sh[kk];
+    }
+    // Up' of the halo column for row jt + fr: the four term groups summed
+    hd += __shfl_xor(hd, 16);
+    hd += __shfl_xor(hd, 32);
+    // D[row][col]: lane holds col = lane & 15 and, in its r-th value, row 4 r + (lane >> 4)
+    double upl[C][4], lou[C][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double h = __shfl(hd, 4 * r + fk);
+      double t[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) t[c] = __shfl(up[c][r], src_col);
+#pragma unroll
+      for (int c = 0; c < C; ++c) upl[c][r] = fr == 0 ? (c == 0 ? h : t[c - 1]) : t[c];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      double t[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) t[r] = __shfl(lo[c][r], src_row);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) lou[c][r] = fk > 0 ? t[r] : (r > 0 ? t[r - 1] : carry[c]);
+      carry[c] = t[3];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int i = ic + 16 * c + fr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = jt + 4 * r + fk;
+        if (j > n + 1) continue;
+        const double vx = (j >= 1 && j <= n - 1) ? a0 + 0.5 * (upl[c][r] + lo[c][r]) : a0;
+        const double vy = (i >= 1 && j >= 1 && j <= n) ? a0 + 0.5 * (lou[c][r] + up[c][r]) : a0;
+        const int64_t o = b * ldo + (int64_t)j * n + i;
+        // column 0: WX of row j goes to row j + 1 (rows 1 .. n + 1), and row 0 gets a0
+        const bool al = i == 0;
+        const bool wx = !al || j <= n;
+        const int64_t ox = al ? o + n : o;
+        if (out) {
+          if (wx) out[ox] = vx;
+          if (al && j == 0) out[o] = a0;
+          out[o + P] = vy;
+        }
+        if (out32) {
+          if (wx) out32[ox] = (float)vx;
+          if (al && j == 0) out32[o] = (float)a0;
+          out32[o + P] = (float)vy;
+        }
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------- separable set-up products
@@ -836,12 +898,27 @@ hipError_t launch_expand_separable(int64_t B, int n, int s, int kx, int ky, cons
   const int M = 3 * n + 2;
   hipLaunchKernelGGL(k_sep_rows, dim3((unsigned)((M + 63) / 64), (unsigned)B), dim3(256), 0, st, n,
                      s, kx, ky, Y, ldY, c, cell_start, cell_term, S, U);
-  const int tiles_i = n / kSmT, tiles = tiles_i * ((n + 2 + kSmT - 1) / kSmT);
-  const int64_t Bp = (B + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_sep_mfma, dim3((unsigned)(Bp * tiles)), dim3(512), 0, st, B, n, kx,
-                     tiles_i, tiles, U, S, a0, out, out32, ldo);
-  hipLaunchKernelGGL(k_sep_alias, dim3((unsigned)((n - 1 + 255) / 256), (unsigned)B), dim3(256), 0,
-                     st, B, n, kx, U, S, a0, out, out32, ldo);
+  // four column waves of 32 columns per block; the block count is a multiple of 8
+  const int cw_per = n / 32;
+  const int64_t blocks = (B * cw_per + 3) / 4, per_xcd = (blocks + 7) / 8;
+  const dim3 grid((unsigned)(8 * per_xcd));
+#define MLQMC_SEP_MARCH(K)                                                                   \
+  case K:                                                                                    \
+    hipLaunchKernelGGL(k_sep_march<K>, grid, dim3(256), 0, st, B, n, kx, cw_per, per_xcd, U, \
+                       S, a0, out, out32, ldo);                                              \
+    break;
+  switch ((kx + 3) / 4) {
+    MLQMC_SEP_MARCH(1)
+    MLQMC_SEP_MARCH(2)
+    MLQMC_SEP_MARCH(3)
+    MLQMC_SEP_MARCH(4)
+    MLQMC_SEP_MARCH(5)
+    MLQMC_SEP_MARCH(6)
+    MLQMC_SEP_MARCH(7)
+    MLQMC_SEP_MARCH(8)
+  }
+#undef MLQMC_SEP_MARCH
+  static_assert(kSepMarchMaxNK == 8, "one case per NK");
   return hipGetLastError();
 }
 
