@@ -84,25 +84,55 @@ def test_coefficient(ctx, fam, n, s, B):
 # assembled stiffness matrix with the boundary nodes kept: a horizontal or
 # vertical edge couples its nodes with minus its weight.  Both products the
 # library forms are covered: the separable one (4 kx < s) and the table one.
-@pytest.mark.parametrize("n,s,B", [(128, 16, 2), (64, 64, 3), (256, 256, 2), (1024, 512, 2)])
-def test_edge_weights(ctx, fam, n, s, B):
-    rng = np.random.default_rng(7 * n + s)
-    Y = rng.random((B, s)) - 0.5
+def _edge_ref(n, y, fam):
+    """Padded [WX | WY] from the oracle's stiffness matrix (boundary nodes kept)."""
     P = (n + 2) * n
-    w = np.empty((B, 2 * P))
-    ctx.edge_weights(n, s, Y, w)
     node = lambda i, j: j * (n + 1) + i  # noqa: E731
     ii, jj = np.meshgrid(np.arange(1, n), np.arange(1, n), indexing="xy")
     ii, jj = ii.ravel(), jj.ravel()
     jy, iy = np.meshgrid(np.arange(1, n + 1), np.arange(1, n), indexing="ij")
     jy, iy = jy.ravel(), iy.ravel()
     jb = np.arange(1, n)
+    A = fem.stiffness(n, coeff.coefficient(n, y, fam), full=True).tocsr()
+    ref = np.full(2 * P, float(fam["a0"]))
+    ref[jj * n + ii] = -np.asarray(A[node(ii - 1, jj), node(ii, jj)]).ravel()
+    ref[(jb + 1) * n] = -np.asarray(A[node(n - 1, jb), node(n, jb)]).ravel()
+    ref[P + jy * n + iy] = -np.asarray(A[node(iy, jy - 1), node(iy, jy)]).ravel()
+    return ref
+
+
+@pytest.mark.parametrize("n,s,B", [(128, 16, 2), (64, 64, 3), (256, 256, 2), (1024, 512, 2)])
+def test_edge_weights(ctx, fam, n, s, B):
+    rng = np.random.default_rng(7 * n + s)
+    Y = rng.random((B, s)) - 0.5
+    w = np.empty((B, 2 * (n + 2) * n))
+    ctx.edge_weights(n, s, Y, w)
     for b in range(B):
-        A = fem.stiffness(n, coeff.coefficient(n, Y[b], fam), full=True).tocsr()
-        ref = np.full(2 * P, float(fam["a0"]))
-        ref[jj * n + ii] = -np.asarray(A[node(ii - 1, jj), node(ii, jj)]).ravel()
-        ref[(jb + 1) * n] = -np.asarray(A[node(n - 1, jb), node(n, jb)]).ravel()
-        ref[P + jy * n + iy] = -np.asarray(A[node(iy, jy - 1), node(iy, jy)]).ravel()
+        ref = _edge_ref(n, Y[b], fam)
+        assert np.max(np.abs(w[b] - ref)) <= 1e-13 * np.max(np.abs(ref)), b
+
+
+# The separable product at every width of its term box it takes (kx = 1 ..
+# 32: one kernel instance per ceil(kx / 4)), and just past it (kx = 33, the
+# table product), on sine-product families whose largest k1 is kx.
+@pytest.mark.parametrize("kx", [1, 4, 5, 8, 11, 16, 21, 24, 29, 32, 33])
+def test_edge_weights_separable_widths(kx):
+    s = 4 * kx + 3
+    j = np.arange(s)
+    ky = min(8, 1024 // kx)
+    fam_k = {"a0": 1.0, "c": 0.5 * (j + 1.0) ** -2.0, "k1": (1 + j % kx).astype(np.int32),
+             "k2": (1 + (7 * j) % ky).astype(np.int32)}
+    n, B = 128, 2
+    rng = np.random.default_rng(kx)
+    Y = rng.random((B, s)) - 0.5
+    w = np.empty((B, 2 * (n + 2) * n))
+    c = m.Context(fam_k)
+    try:
+        c.edge_weights(n, s, Y, w)
+    finally:
+        c.close()
+    for b in range(B):
+        ref = _edge_ref(n, Y[b], fam_k)
         assert np.max(np.abs(w[b] - ref)) <= 1e-13 * np.max(np.abs(ref)), b
 
 
