@@ -208,7 +208,9 @@ mlqmc_status mlqmc_apply_operator(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t 
  * right boundary (j = 1..n-1), WY[j n + i] the edge arriving from the south
  * (i = 1..n-1, j = 1..n), every other entry a0.  Formed as those solves form
  * them for this family and truncation: the separable product (sums over k1
- * and k2 of the sine pairs) when it is cheaper, else the table product.
+ * and k2 of the sine pairs) when the largest k1 among the s terms, kx, has
+ * kx <= 32, 4 kx < s and kx times the largest k2 <= 1024, else the table
+ * product.
  * Problem 1 only; n a power of two in [64, 1024]; host or device memory as
  * on_dev.  MLQMC_EINVAL for other arguments (nothing written). */
 mlqmc_status mlqmc_edge_weights(mlqmc_ctx* ctx, int32_t n, int32_t s, int64_t B,

@@ -212,7 +212,7 @@ hipError_t launch_expand(int64_t B, int s, int64_t E, const double* Y, int64_t l
 // (cell_start [kx ky + 1], cell_term: the term indices of each cell, in order);
 // U scratch [B x (3n+2) x kx].  Writes the padded [WX | WY] of B samples at
 // out[b * ldo ...] and / or out32, equal to launch_expand with the padded edge
-// table up to rounding.  n a multiple of 64, kx <= 64, kx ky <= 1024.
+// table up to rounding.  n a multiple of 64, kx <= 32, kx ky <= 1024.
 hipError_t launch_sep_sin(int n, int kmax, double* S, hipStream_t st);
 // The set-up products v^T M v and v^T A v of v = P u_H (mesh n from mesh nH)
 // from coarse quantities, for the separable expansion: Tp [3 (n/nH) kx x 2 nH]
