@@ -391,10 +391,7 @@ __global__ __launch_bounds__(256) void k_sep_rows(int n, int s, int kx, int ky,
 // weight formed directly (four per node, 1.1 times as long), 64 x 64 tiles
 // staged through LDS (1.7 times), 16 columns per wave (three waves per SIMD,
 // 1.2 times), and the next step's U rows loaded before this step's stores
-// (one wave per SIMD at 32 columns, 1.4 times in mixed precision); a second
-// copy of U in fragment order, so that every load of a step is one
-// contiguous 512-byte read, ran alike in FP64 and 6 % slower in mixed
-// precision (the copy's writes).
+// (one wave per SIMD at 32 columns, 1.4 times in mixed precision).
 constexpr int kSepMarchMaxNK = kSepMaxK / 4;
 template <int NK>
 __global__ __launch_bounds__(256) void k_sep_march(int64_t B, int n, int kx, int cw_per,
